@@ -1,0 +1,9 @@
+"""paper_1109_2348_amd: batched bzip2 compression stages (BWT, MTF,
+RUNA/RUNB, Huffman, bit-packing) as HIP kernels for the MI355X, behind the C
+ABI in include/bzgpu.h.
+
+    from paper_1109_2348_amd import compress, bwt, mtf, huffman
+"""
+
+from .native import (BzgError, Compressor, Context, bwt, compress, compress_bound, context, huffman,  # noqa: F401
+                     mtf, uniform_offsets)

@@ -1,0 +1,690 @@
+// Block BWT as a prefix-doubling sort of cyclic rotations (Sec. 3.1: the BWT
+// is the sort of the rotations; Sec. 2.1: GPU sorting and lexicographic
+// naming by prefix sums).
+//
+// All blocks of a batch share one array of SA rows (row k of block b lives at
+// blk_off[b] + local row).  A rotation's rank is the row of the first member
+// of its group ("head"), so ranks of different blocks never collide and rank
+// order is rotation order.
+//
+//  init   SA = rows in descending start order; key = 4 cyclic bytes,
+//         big-endian; stable LSD radix per block; name groups.
+//  round  for every unresolved group (a "segment"), key2 = rank of the
+//         rotation h positions on; stable sort of the segment by key2; a new
+//         group starts where key2 changes; rank = row of its head.  Groups of
+//         one row are done; groups whose block length is <= the next h hold
+//         equal rotations and are done too.  h doubles.
+//
+// Stable sorts from a descending start order leave equal rotations in
+// descending start order.  Segments of at most SMALL_MAX rows are packed into
+// tiles and sorted in LDS; larger ones go through global LSD radix passes in
+// which each segment keeps its own histogram column (a segmented sort).  The
+// gather of key2 runs as its own kernel so that no rank is read after it has
+// been refined in the same round.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bzg {
+
+constexpr int RI = RADIX_TILE / NT;  // 16 items per thread
+constexpr int NW = NT / BZG_WAVE;    // 4 waves
+
+__device__ __forceinline__ uint32_t find_block(const uint32_t* off, uint32_t nb, uint32_t k) {
+  uint32_t lo = 0, hi = nb - 1;  // last b with off[b] <= k
+  while (lo < hi) {
+    uint32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t lowest_lane(uint64_t m) { return (uint32_t)(__ffsll((long long)m) - 1); }
+
+// ------------------------------------------------------------------ init
+
+__global__ __launch_bounds__(NT) void k_sa_init(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
+                                                uint32_t nb, uint32_t N, uint32_t* __restrict__ SA,
+                                                uint32_t* __restrict__ key) {
+  uint32_t k = blockIdx.x * NT + threadIdx.x;
+  if (k >= N) return;
+  uint32_t b = find_block(off, nb, k);
+  uint32_t o = off[b], n = off[b + 1] - o;
+  uint32_t i = n - 1 - (k - o);  // descending start order
+  SA[k] = o + i;
+  uint32_t v = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    uint32_t q = i + j;
+    while (q >= n) q -= n;
+    v = (v << 8) | text[o + q];
+  }
+  key[k] = v;
+}
+
+// -------------------------------------------------- segment radix passes
+
+struct BigTile {
+  SegRec r;
+  uint32_t t, nt, lo, hi;
+};
+
+__device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, const uint32_t* owner) {
+  BigTile g;
+  g.r = segs[owner[j]];
+  g.nt = (g.r.len + RADIX_TILE - 1) / RADIX_TILE;
+  g.t = j - g.r.base;
+  g.lo = g.r.start + g.t * RADIX_TILE;
+  g.hi = min(g.lo + RADIX_TILE, g.r.start + g.r.len);
+  return g;
+}
+
+__global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                                   const uint32_t* __restrict__ kin, int shift,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t cnt[NW][256];
+  const uint32_t w = threadIdx.x / BZG_WAVE;
+  for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
+  __syncthreads();
+  BigTile g = big_tile(blockIdx.x, segs, owner);
+  const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
+  for (int i = 0; i < RI; i++) {
+    uint32_t k = wbase + i * BZG_WAVE + lane();
+    bool ok = k < g.hi;
+    uint64_t valid = __ballot(ok);
+    if (!valid) break;
+    uint32_t d = ok ? (kin[k] >> shift) & 255u : 0u;
+    uint64_t peers = match_digit8(d, valid);
+    if (ok && lowest_lane(peers) == lane()) cnt[w][d] += __popcll(peers);
+  }
+  __syncthreads();
+  uint32_t d = threadIdx.x;
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < NW; q++) s += cnt[q][d];
+  hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
+                                                      const uint32_t* __restrict__ owner,
+                                                      const uint32_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout, int shift,
+                                                      const uint32_t* __restrict__ hscan) {
+  __shared__ uint32_t cnt[NW][256];
+  const uint32_t w = threadIdx.x / BZG_WAVE;
+  for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
+  __syncthreads();
+  BigTile g = big_tile(blockIdx.x, segs, owner);
+  const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
+  uint32_t key[RI], val[RI], rk[RI];
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    uint32_t k = wbase + i * BZG_WAVE + lane();
+    bool ok = k < g.hi;
+    uint64_t valid = __ballot(ok);
+    key[i] = ok ? kin[k] : 0u;
+    val[i] = ok ? vin[k] : 0u;
+    rk[i] = 0xFFFFFFFFu;
+    if (valid) {
+      uint32_t d = (key[i] >> shift) & 255u;
+      uint64_t peers = match_digit8(d, valid);
+      uint32_t before = cnt[w][d];
+      if (ok) rk[i] = before + __popcll(peers & lanemask_lt());
+      if (ok && lowest_lane(peers) == lane()) cnt[w][d] = before + __popcll(peers);
+    }
+  }
+  __syncthreads();
+  {
+    uint32_t d = threadIdx.x;
+    const size_t col0 = (size_t)g.r.base * 256;
+    uint32_t run = g.r.start + hscan[col0 + (size_t)d * g.nt + g.t] - hscan[col0];
+#pragma unroll
+    for (int q = 0; q < NW; q++) {
+      uint32_t c = cnt[q][d];
+      cnt[q][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    if (rk[i] != 0xFFFFFFFFu) {
+      uint32_t d = (key[i] >> shift) & 255u;
+      uint32_t pos = cnt[w][d] + rk[i];
+      kout[pos] = key[i];
+      vout[pos] = val[i];
+    }
+  }
+}
+
+// --------------------------------------------------------- new segments
+
+struct AppendCtx {
+  SegRec* segs;
+  uint32_t* head;   // packed offset -> segment index + 1
+  uint32_t* owner;  // tile -> segment index
+  RoundCounters* cnt;
+};
+
+// Workgroup-aggregated append of up to `m` groups held by this thread
+// (group g = (start[g], len[g], blk)).  All threads must call it.
+template <int M>
+__device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint32_t* gl, int m, uint32_t blk_of_thread,
+                              const uint32_t* gblk, uint32_t* sh32, uint32_t* wg_base /*LDS[4]*/) {
+  uint32_t nseg = (uint32_t)m, nsmall = 0, ntiles = 0, nact = 0;
+  for (int g = 0; g < m; g++) {
+    nact += gl[g];
+    if (gl[g] <= SMALL_MAX) nsmall += gl[g];
+    else ntiles += (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
+  }
+  uint32_t t_seg, t_small, t_tiles, t_act;
+  uint32_t e_seg = block_excl_sum<uint32_t, NT>(nseg, sh32, &t_seg);
+  uint32_t e_small = block_excl_sum<uint32_t, NT>(nsmall, sh32, &t_small);
+  uint32_t e_tiles = block_excl_sum<uint32_t, NT>(ntiles, sh32, &t_tiles);
+  (void)block_excl_sum<uint32_t, NT>(nact, sh32, &t_act);
+  if (threadIdx.x == 0) {
+    wg_base[0] = t_seg ? atomicAdd(&a.cnt->n_segs, t_seg) : 0u;
+    wg_base[1] = t_small ? atomicAdd(&a.cnt->small_total, t_small) : 0u;
+    wg_base[2] = t_tiles ? atomicAdd(&a.cnt->big_tiles, t_tiles) : 0u;
+    if (t_act) atomicAdd(&a.cnt->active, t_act);
+  }
+  __syncthreads();
+  uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
+  for (int g = 0; g < m; g++) {
+    SegRec r;
+    r.start = gs[g];
+    r.len = gl[g];
+    r.blk = gblk ? gblk[g] : blk_of_thread;
+    if (gl[g] <= SMALL_MAX) {
+      r.base = so;
+      a.head[so] = si + 1;
+      so += gl[g];
+    } else {
+      uint32_t nt = (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
+      r.base = st;
+      for (uint32_t q = 0; q < nt; q++) a.owner[st + q] = si;
+      st += nt;
+    }
+    a.segs[si] = r;
+    si++;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------ naming, large
+
+// Per tile: the last group head (row + 1, 0 = none) among sorted keys.
+__global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                                 const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg) {
+  __shared__ uint32_t sh[NW + 1];
+  BigTile g = big_tile(blockIdx.x, segs, owner);
+  uint32_t best = 0;
+  for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
+    if (k == g.r.start || kin[k] != kin[k - 1]) best = max(best, k + 1);
+  }
+  best = wave_max(best);
+  if (lane() == 0) sh[threadIdx.x / BZG_WAVE] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int q = 0; q < NW; q++) m = max(m, sh[q]);
+    agg[blockIdx.x] = m;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                                 const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                 const uint32_t* __restrict__ agg, const uint32_t* __restrict__ blk_off,
+                                                 uint32_t* __restrict__ SA, uint32_t* __restrict__ rank,
+                                                 uint32_t h_next, AppendCtx app) {
+  __shared__ uint32_t sh[NW + 1];
+  __shared__ uint32_t sx[NT];
+  __shared__ uint32_t s_carry;
+  __shared__ uint32_t wg_base[4];
+  BigTile g = big_tile(blockIdx.x, segs, owner);
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (uint32_t j = blockIdx.x; j > blockIdx.x - g.t; j--) {
+      c = agg[j - 1];
+      if (c) break;
+    }
+    s_carry = c;
+  }
+  const uint32_t nblk = blk_off[g.r.blk + 1] - blk_off[g.r.blk];
+  const bool keep_blk = h_next < nblk;
+  const uint32_t segend = g.r.start + g.r.len;
+  const uint32_t k0 = g.lo + threadIdx.x * RI;  // blocked: RI consecutive rows per thread
+  uint32_t kk[RI];
+  uint32_t lastb = 0;
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    uint32_t k = k0 + i;
+    kk[i] = k < g.hi ? kin[k] : 0u;
+    if (k < g.hi && (k == g.r.start || kk[i] != (i ? kk[i - 1] : kin[k - 1]))) lastb = k + 1;
+  }
+  __syncthreads();
+  uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
+  sx[threadIdx.x] = incl;
+  __syncthreads();
+  uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+  hp = max(hp, s_carry);
+  uint32_t gs[RI / 2 + 1], gl[RI / 2 + 1];
+  int m = 0;
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    uint32_t k = k0 + i;
+    if (k < g.hi) {
+      if (k == g.r.start || kk[i] != (i ? kk[i - 1] : kin[k - 1])) hp = k + 1;
+      uint32_t v = vin[k];
+      SA[k] = v;
+      rank[v] = hp - 1;
+      bool end = (k + 1 == segend) || ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : kin[k + 1] != kk[i]);
+      if (end) {
+        uint32_t len = k + 1 - (hp - 1);
+        if (len >= 2 && keep_blk && m < RI / 2 + 1) {
+          gs[m] = hp - 1;
+          gl[m] = len;
+          m++;
+        }
+      }
+    }
+  }
+  append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, nullptr, sh, wg_base);
+}
+
+// ------------------------------------------------------------ gather key2
+
+constexpr uint16_t NO_SEG = 0xFFFFu;
+
+// Loads a small tile's segment map: mark[p] = segment index + 1 at each
+// segment's first position, segp[p] = first position of p's segment.
+__device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head, const SegRec* __restrict__ segs,
+                                   uint32_t small_total, uint32_t* mark, uint16_t* segp, uint32_t* sh,
+                                   uint32_t* s_n) {
+  for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) mark[p] = 0;
+  if (threadIdx.x == 0) *s_n = 0;
+  __syncthreads();
+  const uint32_t lo = t * SMALL_T;
+  for (uint32_t i = threadIdx.x; i < SMALL_T; i += NT) {
+    uint32_t o = lo + i;
+    if (o < small_total) {
+      uint32_t hd = head[o];
+      if (hd) {
+        mark[i] = hd;
+        atomicMax(s_n, i + segs[hd - 1].len);
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int PER = SMALL_CAP / NT;  // 16 positions per thread, blocked
+  const uint32_t p0 = threadIdx.x * PER;
+  uint32_t last = 0;
+  for (int i = 0; i < PER; i++)
+    if (mark[p0 + i]) last = p0 + i + 1;
+  uint32_t incl = block_incl_max<uint32_t, NT>(last, sh, 0u);
+  // exclusive carry via a shuffle of the inclusive value of the previous thread
+  __shared__ uint32_t sx[NT];
+  sx[threadIdx.x] = incl;
+  __syncthreads();
+  uint32_t cur = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+  for (int i = 0; i < PER; i++) {
+    if (mark[p0 + i]) cur = p0 + i + 1;
+    // positions before the tile's first segment belong to a segment of the
+    // previous tile
+    segp[p0 + i] = cur ? (uint16_t)(cur - 1) : NO_SEG;
+  }
+  __syncthreads();
+  return *s_n;
+}
+
+__global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
+                                               const uint32_t* __restrict__ owner, const RoundCounters* cnt,
+                                               uint32_t n_small_tiles, const uint32_t* __restrict__ blk_off,
+                                               const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
+                                               uint32_t h, uint32_t* __restrict__ key2) {
+  __shared__ uint32_t mark[SMALL_CAP];
+  __shared__ uint16_t segp[SMALL_CAP];
+  __shared__ uint32_t sh[NW + 1];
+  __shared__ uint32_t s_n;
+  if (blockIdx.x < n_small_tiles) {
+    uint32_t n = small_tile_map(blockIdx.x, head, segs, cnt->small_total, mark, segp, sh, &s_n);
+    for (uint32_t p = threadIdx.x; p < n; p += NT) {
+      uint32_t sp = segp[p];
+      if (sp == NO_SEG) continue;
+      SegRec r = segs[mark[sp] - 1];
+      uint32_t k = r.start + (p - sp);
+      uint32_t o = blk_off[r.blk], nbk = blk_off[r.blk + 1] - o;
+      uint32_t i = SA[k] - o + h;
+      if (i >= nbk) i -= nbk;
+      key2[k] = rank[o + i] - o;
+    }
+  } else {
+    BigTile g = big_tile(blockIdx.x - n_small_tiles, segs, owner);
+    uint32_t o = blk_off[g.r.blk], nbk = blk_off[g.r.blk + 1] - o;
+    for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
+      uint32_t i = SA[k] - o + h;
+      if (i >= nbk) i -= nbk;
+      key2[k] = rank[o + i] - o;
+    }
+  }
+}
+
+// --------------------------------------------------- small segments, LDS
+
+__global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
+                                                   const RoundCounters* cnt, const uint32_t* __restrict__ blk_off,
+                                                   const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
+                                                   uint32_t* __restrict__ rank, uint32_t h_next, AppendCtx app) {
+  __shared__ uint32_t mark[SMALL_CAP];
+  __shared__ uint16_t segp[SMALL_CAP];
+  __shared__ uint32_t skey[SMALL_CAP];
+  __shared__ uint32_t sval[SMALL_CAP];
+  __shared__ uint32_t scnt[NW][256];
+  __shared__ uint32_t sh[NW + 1];
+  __shared__ uint32_t sx[NT];
+  __shared__ uint32_t s_n;
+  __shared__ uint32_t wg_base[4];
+  const uint32_t small_total = cnt->small_total;
+  const uint32_t n = small_tile_map(blockIdx.x, head, segs, small_total, mark, segp, sh, &s_n);
+  // load (segment start << 21 | key2, SA value).  Positions before the
+  // first segment take key 0 and stay in front (no segment starts at 0 then);
+  // positions past the last take the largest key and stay behind.
+  for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) {
+    uint32_t kv = 0xFFFFFFFFu, vv = 0;
+    if (p < n && segp[p] == NO_SEG) {
+      kv = 0;
+    } else if (p < n) {
+      uint32_t sp = segp[p];
+      SegRec r = segs[mark[sp] - 1];
+      uint32_t k = r.start + (p - sp);
+      kv = (sp << 21) | key2[k];
+      vv = SA[k];
+    }
+    skey[p] = kv;
+    sval[p] = vv;
+  }
+  // clear the head entries of this tile for reuse two rounds later
+  const uint32_t lo = blockIdx.x * SMALL_T;
+  for (uint32_t i = threadIdx.x; i < SMALL_T; i += NT)
+    if (lo + i < small_total) head[lo + i] = 0;
+  __syncthreads();
+  // stable LSD radix sort of the tile in LDS; wave w owns positions
+  // [w*1024, (w+1)*1024), item i of lane l is position w*1024 + i*64 + l
+  const uint32_t w = threadIdx.x / BZG_WAVE;
+  constexpr int PI = SMALL_CAP / NT;  // 16
+  for (int shift = 0; shift < 32; shift += 8) {
+    for (int d = threadIdx.x; d < NW * 256; d += NT) (&scnt[0][0])[d] = 0;
+    __syncthreads();
+    uint32_t key[PI], val[PI], rk[PI];
+#pragma unroll
+    for (int i = 0; i < PI; i++) {
+      uint32_t p = w * (PI * BZG_WAVE) + i * BZG_WAVE + lane();
+      key[i] = skey[p];
+      val[i] = sval[p];
+      uint32_t d = (key[i] >> shift) & 255u;
+      uint64_t peers = match_digit8(d, ~0ull);
+      uint32_t before = scnt[w][d];
+      rk[i] = before + __popcll(peers & lanemask_lt());
+      if (lowest_lane(peers) == lane()) scnt[w][d] = before + __popcll(peers);
+    }
+    __syncthreads();
+    {
+      uint32_t d = threadIdx.x;
+      uint32_t tot = 0;
+#pragma unroll
+      for (int q = 0; q < NW; q++) tot += scnt[q][d];
+      uint32_t all;
+      uint32_t run = block_excl_sum<uint32_t, NT>(tot, sh, &all);
+#pragma unroll
+      for (int q = 0; q < NW; q++) {
+        uint32_t c = scnt[q][d];
+        scnt[q][d] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PI; i++) {
+      uint32_t d = (key[i] >> shift) & 255u;
+      uint32_t pos = scnt[w][d] + rk[i];
+      skey[pos] = key[i];
+      sval[pos] = val[i];
+    }
+    __syncthreads();
+  }
+  // naming: blocked, PI consecutive positions per thread
+  const uint32_t p0 = threadIdx.x * PI;
+  uint32_t lastb = 0;
+  for (int i = 0; i < PI; i++) {
+    uint32_t p = p0 + i;
+    if (p < n && segp[p] != NO_SEG && (p == segp[p] || skey[p] != skey[p - 1])) lastb = p + 1;
+  }
+  uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
+  sx[threadIdx.x] = incl;
+  __syncthreads();
+  uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+  uint32_t gs[PI / 2 + 1], gl[PI / 2 + 1], gb[PI / 2 + 1];
+  int m = 0;
+  for (int i = 0; i < PI; i++) {
+    uint32_t p = p0 + i;
+    if (p >= n) break;
+    uint32_t sp = segp[p];
+    if (sp == NO_SEG) continue;
+    SegRec r = segs[mark[sp] - 1];
+    if (p == sp || skey[p] != skey[p - 1]) hp = p + 1;
+    uint32_t k = r.start + (p - sp);
+    uint32_t headk = r.start + (hp - 1 - sp);
+    uint32_t v = sval[p];
+    SA[k] = v;
+    rank[v] = headk;
+    bool end = (p + 1 == sp + r.len) || skey[p + 1] != skey[p];
+    if (end) {
+      uint32_t len = p + 1 - (hp - 1);
+      uint32_t nbk = blk_off[r.blk + 1] - blk_off[r.blk];
+      if (len >= 2 && h_next < nbk) {
+        gs[m] = headk;
+        gl[m] = len;
+        gb[m] = r.blk;
+        m++;
+      }
+    }
+  }
+  append_groups<PI / 2 + 1>(app, gs, gl, m, 0, gb, sh, wg_base);
+}
+
+// ------------------------------------------------------------- final BWT
+
+// L[k] = byte before rotation SA[k]; primary[b] = row of rotation 0; the
+// optional local SA.
+__global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
+                                                uint32_t nb, uint32_t N, const uint32_t* __restrict__ SA,
+                                                uint8_t* __restrict__ L, uint32_t* __restrict__ primary,
+                                                uint32_t* __restrict__ sa_local) {
+  uint32_t k = blockIdx.x * NT + threadIdx.x;
+  if (k >= N) return;
+  uint32_t b = find_block(off, nb, k);
+  uint32_t o = off[b], n = off[b + 1] - o;
+  uint32_t p = SA[k];
+  L[k] = text[p == o ? o + n - 1 : p - 1];
+  if (p == o) primary[b] = k - o;
+  if (sa_local) sa_local[k] = p - o;
+}
+
+// ------------------------------------------------------------- host side
+
+struct BwtWork {
+  uint32_t *SA, *rank, *key, *tmpK, *tmpV, *hist, *scan_tmp, *agg;
+  SegRec* segs[2];
+  uint32_t* head[2];
+  uint32_t* owner[2];
+  RoundCounters* cnt;    // device [2]
+  RoundCounters* h_cnt;  // pinned host [2]
+  uint32_t* d_off;       // device block offsets (nb+1)
+};
+
+struct BwtSizes {
+  size_t seg_cap, head_cap, owner_cap, hist_cap, scan_tmp_cap;
+};
+
+static BwtSizes bwt_sizes(uint32_t N, uint32_t nb) {
+  BwtSizes z;
+  z.seg_cap = (size_t)N / 2 + nb + 16;
+  z.head_cap = (size_t)N + SMALL_T + 16;
+  z.owner_cap = (size_t)N / RADIX_TILE + (size_t)N / (SMALL_MAX + 1) + nb + 16;
+  z.hist_cap = z.owner_cap * 256 + 16;
+  z.scan_tmp_cap = scan_tmp_elems(z.hist_cap) + 16;
+  return z;
+}
+
+size_t bwt_workspace_bytes(uint32_t N, uint32_t nb) {
+  BwtSizes z = bwt_sizes(N, nb);
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
+  for (int i = 0; i < 5; i++) add((size_t)N * 4 + 64);  // SA rank key tmpK tmpV
+  add(z.hist_cap * 4);
+  add(z.scan_tmp_cap * 4);
+  add(z.owner_cap * 4);  // agg
+  for (int i = 0; i < 2; i++) {
+    add(z.seg_cap * sizeof(SegRec));
+    add(z.head_cap * 4);
+    add(z.owner_cap * 4);
+  }
+  add(2 * sizeof(RoundCounters));
+  add(((size_t)nb + 1) * 4);
+  return b + 4096;
+}
+
+static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, int passes,
+                               uint32_t** kin, uint32_t** vin, hipStream_t st) {
+  uint32_t *ka = w.key, *va = w.SA, *kb = w.tmpK, *vb = w.tmpV;
+  for (int p = 0; p < passes; p++) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist);
+    hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
+                       w.hist);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  *kin = ka;
+  *vin = va;
+  return hipGetLastError();
+}
+
+// Sorts the rotations of every block of `text` (blocks at h_off[b]..h_off[b+1],
+// all lengths in 1..MAX_BLOCK, total N).  Leaves SA rows in w.SA.
+hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, void* ws, size_t ws_bytes,
+                    RoundCounters* h_pinned, hipStream_t st, uint32_t** SA_out, uint32_t** off_out, int* rounds,
+                    std::string& err) {
+  const uint32_t nb = (uint32_t)h_off.size() - 1;
+  const uint32_t N = h_off[nb];
+  BwtSizes z = bwt_sizes(N, nb);
+  Bump bump;
+  bump.base = (char*)ws;
+  bump.cap = ws_bytes;
+  BwtWork w;
+  w.SA = bump.take<uint32_t>(N + 16);
+  w.rank = bump.take<uint32_t>(N + 16);
+  w.key = bump.take<uint32_t>(N + 16);
+  w.tmpK = bump.take<uint32_t>(N + 16);
+  w.tmpV = bump.take<uint32_t>(N + 16);
+  w.hist = bump.take<uint32_t>(z.hist_cap);
+  w.scan_tmp = bump.take<uint32_t>(z.scan_tmp_cap);
+  w.agg = bump.take<uint32_t>(z.owner_cap);
+  for (int i = 0; i < 2; i++) {
+    w.segs[i] = bump.take<SegRec>(z.seg_cap);
+    w.head[i] = bump.take<uint32_t>(z.head_cap);
+    w.owner[i] = bump.take<uint32_t>(z.owner_cap);
+  }
+  w.cnt = bump.take<RoundCounters>(2);
+  w.d_off = bump.take<uint32_t>(nb + 1);
+  if (bump.used > ws_bytes) {
+    err = "bwt workspace too small";
+    return hipErrorInvalidValue;
+  }
+  w.h_cnt = h_pinned;
+  *SA_out = w.SA;
+  *off_out = w.d_off;
+  hipError_t e;
+#define BZG_TRY(x)                  \
+  do {                              \
+    e = (x);                        \
+    if (e != hipSuccess) return e;  \
+  } while (0)
+  BZG_TRY(hipMemcpyAsync(w.d_off, h_off.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
+  BZG_TRY(hipMemsetAsync(w.head[0], 0, z.head_cap * 4, st));
+  BZG_TRY(hipMemsetAsync(w.head[1], 0, z.head_cap * 4, st));
+  BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
+  uint32_t max_n = 0;
+  for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
+  hipLaunchKernelGGL(k_sa_init, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, w.d_off, nb, N, w.SA, w.key);
+  // initial segments: every block of two or more rows, as a large segment
+  std::vector<SegRec> segs0;
+  std::vector<uint32_t> owner0;
+  for (uint32_t b = 0; b < nb; b++) {
+    uint32_t n = h_off[b + 1] - h_off[b];
+    if (n < 2) continue;
+    SegRec r{h_off[b], n, b, (uint32_t)owner0.size()};
+    for (uint32_t t = 0; t < (n + RADIX_TILE - 1) / RADIX_TILE; t++) owner0.push_back((uint32_t)segs0.size());
+    segs0.push_back(r);
+  }
+  int nround = 0;
+  if (!segs0.empty()) {
+    BZG_TRY(hipMemcpyAsync(w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec), hipMemcpyHostToDevice, st));
+    BZG_TRY(hipMemcpyAsync(w.owner[0], owner0.data(), owner0.size() * 4, hipMemcpyHostToDevice, st));
+    uint32_t big_tiles = (uint32_t)owner0.size();
+    uint32_t *kin, *vin;
+    BZG_TRY(radix_passes(w, big_tiles, w.segs[0], w.owner[0], 4, &kin, &vin, st));
+    AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1]};
+    hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, w.agg);
+    hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, vin, w.agg, w.d_off,
+                       w.SA, w.rank, 4u, app);
+    BZG_TRY(hipGetLastError());
+    int cur = 1;
+    uint32_t h = 4;
+    int bits = 1;
+    while ((1u << bits) < max_n) bits++;
+    const int passes = (bits + 7) / 8;
+    for (;;) {
+      BZG_TRY(hipMemcpyAsync(&w.h_cnt[cur], &w.cnt[cur], sizeof(RoundCounters), hipMemcpyDeviceToHost, st));
+      BZG_TRY(hipStreamSynchronize(st));
+      RoundCounters c = w.h_cnt[cur];
+      if (c.n_segs == 0) break;
+      if (c.n_segs > z.seg_cap || c.big_tiles > z.owner_cap || c.small_total > N) {
+        err = "bwt: segment capacity exceeded";
+        return hipErrorInvalidValue;
+      }
+      nround++;
+      const int nxt = cur ^ 1;
+      BZG_TRY(hipMemsetAsync(&w.cnt[nxt], 0, sizeof(RoundCounters), st));
+      const uint32_t nsmall = (c.small_total + SMALL_T - 1) / SMALL_T;
+      hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.head[cur],
+                         w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank, h, w.key);
+      AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[nxt]};
+      if (nsmall)
+        hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
+                           w.d_off, w.key, w.SA, w.rank, 2 * h, app2);
+      if (c.big_tiles) {
+        BZG_TRY(radix_passes(w, c.big_tiles, w.segs[cur], w.owner[cur], passes, &kin, &vin, st));
+        hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
+        hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
+                           w.agg, w.d_off, w.SA, w.rank, 2 * h, app2);
+      }
+      BZG_TRY(hipGetLastError());
+      cur = nxt;
+      h *= 2;
+    }
+  }
+  if (rounds) *rounds = nround;
+  return hipGetLastError();
+#undef BZG_TRY
+}
+
+hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, uint32_t N, const uint32_t* SA,
+                      uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
+  if (N) hipLaunchKernelGGL(k_bwt_out, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, d_off, nb, N, SA, L, primary,
+                            sa_local);
+  return hipGetLastError();
+}
+
+}  // namespace bzg

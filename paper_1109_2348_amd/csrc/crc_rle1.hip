@@ -1,0 +1,316 @@
+// Block CRC and RLE1 (bzip2's first run-length stage), data-parallel.
+//
+// RLE1 follows the four-step pattern of Figure 1 (Sec. 3.2): run boundaries
+// are flagged, a max-scan gives every byte the start of its run, a prefix sum
+// of per-byte output counts gives output positions, and bytes are scattered.
+// Inside a run, byte t (0-based) sits at u = t mod 255 of a piece of at most
+// 255 bytes; it writes its own byte when u < 4, the byte at u = 3 also owns
+// the slot of the piece's count byte, and the last byte of a piece writes the
+// count u - 3 into that slot.  So every byte's output count depends only on
+// u, never on the run's length, and long runs stay load-balanced.
+//
+// Tiles of RLE_TILE bytes never cross a block.  Pass A reduces each tile to
+// (last run start, bytes before the first run start, output count of the
+// bytes after it, CRC share); pass B scans tiles per block; pass C emits.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bzg {
+
+constexpr int RITEMS = RLE_TILE / NT;  // 16 bytes per thread
+
+struct RleTile {
+  uint32_t last_bnd;  // last run start in the tile, +1 (0 = none)
+  uint32_t lead;      // bytes before the tile's first run start
+  uint32_t inner;     // output bytes of the bytes from the first run start on
+  uint32_t crc;       // CRC share, already shifted to the end of the block
+};
+
+__device__ __forceinline__ uint32_t rle_emit_count(uint32_t t) {
+  uint32_t u = t % 255u;
+  return u < 3 ? 1u : (u == 3 ? 2u : 0u);
+}
+// output bytes of the first x bytes of a run
+__device__ __forceinline__ uint32_t rle_prefix(uint32_t x) {
+  uint32_t r = x % 255u;
+  return 5u * (x / 255u) + (r <= 3 ? r : 5u);
+}
+
+struct TileGeom {
+  uint32_t b;       // block
+  uint64_t base;    // block start in the input
+  uint32_t n;       // block length
+  uint32_t lo, hi;  // tile range inside the block
+};
+
+__device__ __forceinline__ TileGeom tile_geom(uint32_t t, const uint32_t* tile_blk, const uint32_t* blk_tile0,
+                                              const uint64_t* blk_off) {
+  TileGeom g;
+  g.b = tile_blk[t];
+  g.base = blk_off[g.b];
+  g.n = (uint32_t)(blk_off[g.b + 1] - g.base);
+  g.lo = (t - blk_tile0[g.b]) * RLE_TILE;
+  g.hi = min(g.lo + RLE_TILE, g.n);
+  return g;
+}
+
+// Loads this thread's RITEMS bytes and the byte before them.
+__device__ __forceinline__ void load_run(const uint8_t* s, const TileGeom& g, uint32_t p0, uint8_t* v,
+                                         int& cnt, uint32_t& prev) {
+  cnt = 0;
+  prev = 0x100u;  // never equal to a byte
+  if (p0 < g.hi) cnt = (int)min((uint32_t)RITEMS, g.hi - p0);
+  if (p0 > 0 && p0 < g.hi) prev = s[g.base + p0 - 1];
+#pragma unroll
+  for (int i = 0; i < RITEMS; i++) v[i] = i < cnt ? s[g.base + p0 + i] : 0;
+}
+
+__global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* tile_blk,
+                                                   const uint32_t* blk_tile0, const uint64_t* blk_off,
+                                                   const uint32_t* __restrict__ crc_tab, const uint32_t* crc_pow,
+                                                   RleTile* tiles) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  __shared__ uint32_t tab[256];
+  tab[threadIdx.x] = crc_tab[threadIdx.x];
+  const uint32_t t = blockIdx.x;
+  TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
+  const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
+  uint8_t v[RITEMS];
+  int cnt;
+  uint32_t prev;
+  load_run(s, g, p0, v, cnt, prev);
+  __syncthreads();
+  // CRC of this thread's bytes from a zero register, shifted to the block end
+  uint32_t reg = 0;
+  for (int i = 0; i < cnt; i++) reg = (reg << 8) ^ tab[(reg >> 24) ^ v[i]];
+  uint32_t share = cnt ? gf2_mulmod(reg, gf2_xpow8((uint64_t)(g.n - (p0 + cnt)), crc_pow)) : 0u;
+  // run starts
+  uint32_t lastb = 0;
+  uint32_t pv = prev;
+  for (int i = 0; i < cnt; i++) {
+    if (p0 + i == 0 || v[i] != pv) lastb = p0 + i + 1;
+    pv = v[i];
+  }
+  uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
+  sx[threadIdx.x] = incl;
+  __syncthreads();
+  const uint32_t carry = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+  const uint32_t tile_last = sx[NT - 1];
+  uint32_t lead = 0, inner = 0, rs = carry;
+  pv = prev;
+  for (int i = 0; i < cnt; i++) {
+    uint32_t p = p0 + i;
+    if (p == 0 || v[i] != pv) rs = p + 1;
+    pv = v[i];
+    if (rs == 0) lead++;
+    else inner += rle_emit_count(p - (rs - 1));
+  }
+  lead = block_sum<uint32_t, NT>(lead, sh);
+  inner = block_sum<uint32_t, NT>(inner, sh);
+  share = wave_xor(share);
+  uint32_t w = threadIdx.x / BZG_WAVE;
+  if (lane() == 0) sx[w] = share;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (int i = 0; i < NT / BZG_WAVE; i++) c ^= sx[i];
+    RleTile r;
+    r.last_bnd = tile_last;
+    r.lead = lead;
+    r.inner = inner;
+    r.crc = c;
+    tiles[t] = r;
+  }
+}
+
+// One workgroup per block: scan its tiles.  Writes each tile's carried run
+// start (+1) and output offset, the block's RLE1 length and CRC.
+__global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, const uint64_t* blk_off,
+                                                    const uint32_t* crc_pow, RleTile* tiles,
+                                                    uint32_t* tile_out, uint32_t* rle_n, uint32_t* crc_out) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  const uint32_t b = blockIdx.x;
+  const uint32_t t0 = blk_tile0[b], t1 = blk_tile0[b + 1];
+  const uint32_t n = (uint32_t)(blk_off[b + 1] - blk_off[b]);
+  uint32_t carry_rs = 0, carry_out = 0, x = 0;
+  for (uint32_t c = t0; c < t1; c += NT) {
+    uint32_t t = c + threadIdx.x;
+    RleTile r = {0, 0, 0, 0};
+    if (t < t1) r = tiles[t];
+    uint32_t incl = block_incl_max<uint32_t, NT>(r.last_bnd, sh, 0u);
+    sx[threadIdx.x] = incl;
+    __syncthreads();
+    uint32_t rs = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+    rs = rs > carry_rs ? rs : carry_rs;
+    uint32_t lo = (t - t0) * RLE_TILE;
+    uint32_t e = 0;
+    if (t < t1) {
+      e = r.inner;
+      if (r.lead) {  // the tile opens inside a run that started at rs-1
+        uint32_t off = lo - (rs - 1);
+        e += rle_prefix(off + r.lead) - rle_prefix(off);
+      }
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_sum<uint32_t, NT>(e, sh, &tot);
+    if (t < t1) {
+      tile_out[t] = carry_out + ex;
+      tiles[t].last_bnd = rs;  // reused: run start carried into the tile (+1)
+    }
+    x ^= (t < t1) ? r.crc : 0u;
+    carry_out += tot;
+    carry_rs = sx[NT - 1] > carry_rs ? sx[NT - 1] : carry_rs;
+    __syncthreads();
+  }
+  uint32_t xa = wave_xor(x);
+  if (lane() == 0) sx[threadIdx.x / BZG_WAVE] = xa;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (int i = 0; i < NT / BZG_WAVE; i++) c ^= sx[i];
+    uint32_t init = gf2_mulmod(0xFFFFFFFFu, gf2_xpow8((uint64_t)n, crc_pow));
+    crc_out[b] = ~(init ^ c);
+    rle_n[b] = carry_out;
+  }
+}
+
+// Walks one tile with the carried run start: computes each byte's output
+// position.  mode 0 writes RLE1 output at out + out_base[b]; mode 1 counts the
+// bytes whose output ends at or before `limit` (the block is cut there).
+template <int MODE>
+__device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, uint32_t tile_off,
+                          uint8_t* out, uint64_t obase, uint32_t limit, uint32_t* sh, uint32_t* sx,
+                          uint32_t* count_out) {
+  const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
+  uint8_t v[RITEMS];
+  int cnt;
+  uint32_t prev;
+  load_run(s, g, p0, v, cnt, prev);
+  uint8_t next = 0;
+  bool has_next = false;
+  if (cnt > 0 && p0 + cnt < g.n) {
+    next = s[g.base + p0 + cnt];
+    has_next = true;
+  }
+  uint32_t lastb = 0, pv = prev, e = 0;
+  for (int i = 0; i < cnt; i++) {
+    if (p0 + i == 0 || v[i] != pv) lastb = p0 + i + 1;
+    pv = v[i];
+  }
+  uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
+  sx[threadIdx.x] = incl;
+  __syncthreads();
+  uint32_t rs = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+  rs = rs > carry ? rs : carry;
+  uint32_t rs0 = rs;
+  pv = prev;
+  for (int i = 0; i < cnt; i++) {
+    uint32_t p = p0 + i;
+    if (p == 0 || v[i] != pv) rs = p + 1;
+    pv = v[i];
+    e += rle_emit_count(p - (rs - 1));
+  }
+  uint32_t tot;
+  uint32_t o = block_excl_sum<uint32_t, NT>(e, sh, &tot) + tile_off;
+  rs = rs0;
+  pv = prev;
+  uint32_t below = 0;
+  for (int i = 0; i < cnt; i++) {
+    uint32_t p = p0 + i;
+    if (p == 0 || v[i] != pv) rs = p + 1;
+    pv = v[i];
+    uint32_t tt = p - (rs - 1);
+    uint32_t u = tt % 255u;
+    uint32_t ec = rle_emit_count(tt);
+    if (MODE == 0) {
+      if (u <= 3) out[obase + o] = v[i];
+      bool last_of_piece = (u == 254) || (i + 1 < cnt ? v[i + 1] != v[i] : (!has_next || next != v[i]));
+      if (last_of_piece && u >= 3) out[obase + (u == 3 ? o + 1 : o - 1)] = (uint8_t)(u - 3);
+    } else {
+      if (o + ec <= limit) below++;
+    }
+    o += ec;
+  }
+  if (MODE == 1) {
+    below = block_sum<uint32_t, NT>(below, sh);
+    if (threadIdx.x == 0) *count_out = g.lo + below;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rle1_emit(const uint8_t* __restrict__ s, const uint32_t* tile_blk,
+                                                  const uint32_t* blk_tile0, const uint64_t* blk_off,
+                                                  const RleTile* tiles, const uint32_t* tile_out,
+                                                  const uint64_t* out_base, uint8_t* __restrict__ out) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  const uint32_t t = blockIdx.x;
+  TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
+  rle1_walk<0>(s, g, tiles[t].last_bnd, tile_out[t], out, out_base[g.b], 0, sh, sx, nullptr);
+}
+
+// One workgroup per oversized block: the length of the longest input prefix
+// whose RLE1 output fits in `limit` bytes.
+__global__ __launch_bounds__(NT) void k_rle1_cut(const uint8_t* __restrict__ s, const uint32_t* blk_ids,
+                                                 const uint32_t* blk_tile0, const uint64_t* blk_off,
+                                                 const RleTile* tiles, const uint32_t* tile_out,
+                                                 uint32_t limit, uint32_t* cut) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  __shared__ uint32_t tsel;
+  const uint32_t b = blk_ids[blockIdx.x];
+  const uint32_t t0 = blk_tile0[b], t1 = blk_tile0[b + 1];
+  if (threadIdx.x == 0) {  // last tile whose output starts at or below the limit
+    uint32_t lo = t0, hi = t1 - 1;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi + 1) / 2;
+      if (tile_out[mid] <= limit) lo = mid; else hi = mid - 1;
+    }
+    tsel = lo;
+  }
+  __syncthreads();
+  const uint32_t t = tsel;
+  TileGeom g;
+  g.b = b;
+  g.base = blk_off[b];
+  g.n = (uint32_t)(blk_off[b + 1] - g.base);
+  g.lo = (t - t0) * RLE_TILE;
+  g.hi = min(g.lo + RLE_TILE, g.n);
+  rle1_walk<1>(s, g, tiles[t].last_bnd, tile_out[t], nullptr, 0, limit, sh, sx, &cut[blockIdx.x]);
+}
+
+hipError_t rle1_tiles(const uint8_t* s, uint32_t ntiles, const uint32_t* tile_blk, const uint32_t* blk_tile0,
+                      const uint64_t* blk_off, const uint32_t* crc_tab, const uint32_t* crc_pow, void* tiles,
+                      hipStream_t st) {
+  if (ntiles) hipLaunchKernelGGL(k_rle1_tiles, dim3(ntiles), dim3(NT), 0, st, s, tile_blk, blk_tile0, blk_off,
+                                 crc_tab, crc_pow, (RleTile*)tiles);
+  return hipGetLastError();
+}
+
+hipError_t rle1_blocks(uint32_t nb, const uint32_t* blk_tile0, const uint64_t* blk_off, const uint32_t* crc_pow,
+                       void* tiles, uint32_t* tile_out, uint32_t* rle_n, uint32_t* crc, hipStream_t st) {
+  if (nb) hipLaunchKernelGGL(k_rle1_blocks, dim3(nb), dim3(NT), 0, st, blk_tile0, blk_off, crc_pow,
+                             (RleTile*)tiles, tile_out, rle_n, crc);
+  return hipGetLastError();
+}
+
+hipError_t rle1_emit(const uint8_t* s, uint32_t ntiles, const uint32_t* tile_blk, const uint32_t* blk_tile0,
+                     const uint64_t* blk_off, const void* tiles, const uint32_t* tile_out, const uint64_t* out_base,
+                     uint8_t* out, hipStream_t st) {
+  if (ntiles) hipLaunchKernelGGL(k_rle1_emit, dim3(ntiles), dim3(NT), 0, st, s, tile_blk, blk_tile0, blk_off,
+                                 (const RleTile*)tiles, tile_out, out_base, out);
+  return hipGetLastError();
+}
+
+hipError_t rle1_cut(const uint8_t* s, uint32_t ncut, const uint32_t* blk_ids, const uint32_t* blk_tile0,
+                    const uint64_t* blk_off, const void* tiles, const uint32_t* tile_out, uint32_t limit,
+                    uint32_t* cut, hipStream_t st) {
+  if (ncut) hipLaunchKernelGGL(k_rle1_cut, dim3(ncut), dim3(NT), 0, st, s, blk_ids, blk_tile0, blk_off,
+                               (const RleTile*)tiles, tile_out, limit, cut);
+  return hipGetLastError();
+}
+
+size_t rle_tile_bytes() { return sizeof(RleTile); }
+
+}  // namespace bzg

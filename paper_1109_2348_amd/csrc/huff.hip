@@ -1,0 +1,298 @@
+// Huffman code tables per block (Sec. 3.4: Huffman coding; Sec. 4: tables
+// chosen by analysing the data).  The paper gives no GPU tree construction
+// and deems one unlikely; here each block gets one workgroup:
+//
+//  * table count G from the symbol count, an equal-frequency partition of the
+//    alphabet as the starting tables (cost 0 inside a table's range, 15
+//    outside);
+//  * four refinement passes: every 50-symbol group picks the table with the
+//    least total code length (lowest index on ties), the groups' symbols are
+//    counted per table, and each table is rebuilt from its counts;
+//  * a table build is textbook Huffman on (weight, id) keys with weights
+//    floored at 1: one wave ranks the leaves, one lane runs the two-queue
+//    merge (leaves in key order, internal nodes in creation order -- their
+//    weights never decrease, so each queue head is its queue's minimum),
+//    every lane walks its leaves to the root; lengths over 17 halve the
+//    weights (w -> 1 + w/2) and rebuild;
+//  * canonical codes in (length, symbol) order; the selectors' MTF indices
+//    (list 0..G-1) from a prefix-max of each table's last use; header and
+//    per-group data bit counts for the packer.
+#include <climits>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bzg {
+
+struct BlockTables {
+  uint32_t G, nsel, hdr_bits, alpha;
+  uint64_t data_bits;
+  uint8_t len[MAXG][MAXA];
+  uint32_t code[MAXG][MAXA];
+};
+
+struct HuffScratch {
+  uint32_t w[MAXA];
+  uint32_t lw[MAXA];  // leaf weights in key order
+  uint16_t order[MAXA];
+  uint32_t wn[MAXA];  // internal node weights
+  uint16_t parent[2 * MAXA];
+};
+
+// One wave: code lengths for frequencies f[0..a).  All 64 lanes call it.
+__device__ void huff_lengths_wave(const uint32_t* f, int a, uint8_t* len, HuffScratch* hs) {
+  const int l = (int)lane();
+  for (int i = l; i < a; i += 64) hs->w[i] = f[i] ? f[i] : 1u;
+  for (;;) {
+    __builtin_amdgcn_wave_barrier();
+    for (int i = l; i < a; i += 64) {
+      uint32_t wi = hs->w[i];
+      int r = 0;
+      for (int j = 0; j < a; j++) {
+        uint32_t wj = hs->w[j];
+        r += (wj < wi || (wj == wi && j < i)) ? 1 : 0;
+      }
+      hs->order[r] = (uint16_t)i;
+      hs->lw[r] = wi;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (l == 0) {
+      int li = 0, ni = 0, nn = 0;
+      for (int step = 0; step < a - 1; step++) {
+        uint32_t wsum = 0;
+        uint32_t ids[2];
+        for (int pick = 0; pick < 2; pick++) {
+          bool leaf = li < a && (ni >= nn || hs->lw[li] <= hs->wn[ni]);  // leaf ids sort below internal ids
+          if (leaf) {
+            ids[pick] = hs->order[li];
+            wsum += hs->lw[li];
+            li++;
+          } else {
+            ids[pick] = (uint32_t)(a + ni);
+            wsum += hs->wn[ni];
+            ni++;
+          }
+        }
+        hs->wn[nn] = wsum;
+        hs->parent[ids[0]] = (uint16_t)(a + nn);
+        hs->parent[ids[1]] = (uint16_t)(a + nn);
+        nn++;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int root = 2 * a - 2;
+    int maxd = 0;
+    for (int i = l; i < a; i += 64) {
+      int d = 0, v = i;
+      while (v != root && d < 2 * MAXA) {  // parents have larger ids: at most 2a steps
+        v = hs->parent[v];
+        d++;
+      }
+      len[i] = (uint8_t)d;
+      maxd = d > maxd ? d : maxd;
+    }
+    maxd = wave_max(maxd);
+    if (maxd <= MAXLEN) break;
+    for (int i = l; i < a; i += 64) hs->w[i] = 1u + hs->w[i] / 2u;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int n_tables(uint32_t ns, int a) {
+  int g = ns < 200 ? 2 : ns < 600 ? 3 : ns < 1200 ? 4 : ns < 2400 ? 5 : 6;
+  return g < a ? g : a;
+}
+
+__global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, const uint64_t* __restrict__ sym_base,
+                                             const uint32_t* __restrict__ nsyms, const uint32_t* __restrict__ freq,
+                                             const uint32_t* __restrict__ inuse, const uint64_t* __restrict__ sel_base,
+                                             uint8_t* __restrict__ sel, uint8_t* __restrict__ selmtf,
+                                             uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs) {
+  __shared__ uint32_t tf[MAXG][MAXA];
+  __shared__ uint8_t lens[MAXG][MAXA];
+  __shared__ uint64_t cost[MAXA];
+  __shared__ HuffScratch hs[NT / BZG_WAVE];
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ int shi[NT / BZG_WAVE + 1];
+  __shared__ int sx[NT];
+  __shared__ uint32_t s_first[MAXG][MAXLEN + 2];
+  const uint32_t b = blockIdx.x;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t w = tid / BZG_WAVE;
+  uint32_t nu = 0;
+  for (int j = 0; j < 8; j++) nu += __popc(inuse[b * 8 + j]);
+  const int a = (int)nu + 2;
+  const uint32_t ns = nsyms[b];
+  const uint32_t nsel = (ns + GROUP - 1) / GROUP;
+  const int G = n_tables(ns, a);
+  const uint16_t* S = syms + sym_base[b];
+  const uint64_t sb = sel_base[b];
+  // starting tables: equal-frequency partition of the alphabet
+  if (tid == 0) {
+    uint64_t rem = ns;
+    int gs = 0;
+    for (int t = 0; t < G; t++) {
+      int left = G - t, ge;
+      if (left == 1) ge = a - 1;
+      else {
+        ge = gs;
+        uint64_t acc = freq[(size_t)b * MAXA + gs];
+        while (ge + 1 <= a - left && acc * (uint64_t)left < rem) {
+          ge++;
+          acc += freq[(size_t)b * MAXA + ge];
+        }
+      }
+      uint64_t part = 0;
+      for (int v = 0; v < a; v++) {
+        bool in = v >= gs && v <= ge;
+        lens[t][v] = in ? 0 : 15;
+        if (in) part += freq[(size_t)b * MAXA + v];
+      }
+      rem -= part;
+      gs = ge + 1;
+    }
+  }
+  __syncthreads();
+  for (int it = 0; it < 4; it++) {
+    for (int v = tid; v < a; v += NT) {
+      uint64_t c = 0;
+      for (int t = 0; t < G; t++) c |= (uint64_t)lens[t][v] << (10 * t);
+      cost[v] = c;
+    }
+    for (int i = tid; i < MAXG * MAXA; i += NT) (&tf[0][0])[i] = 0;
+    __syncthreads();
+    for (uint32_t g = tid; g < nsel; g += NT) {
+      uint32_t lo = g * GROUP, hi = min(lo + GROUP, ns);
+      uint64_t acc = 0;
+      for (uint32_t i = lo; i < hi; i++) acc += cost[S[i]];
+      uint32_t best = 0, bc = (uint32_t)(acc & 1023u);
+      for (int t = 1; t < G; t++) {
+        uint32_t c = (uint32_t)((acc >> (10 * t)) & 1023u);
+        if (c < bc) {
+          bc = c;
+          best = (uint32_t)t;
+        }
+      }
+      sel[sb + g] = (uint8_t)best;
+      for (uint32_t i = lo; i < hi; i++) atomicAdd(&tf[best][S[i]], 1u);
+    }
+    __syncthreads();
+    for (int t = (int)w; t < G; t += NT / BZG_WAVE) huff_lengths_wave(tf[t], a, lens[t], &hs[w]);
+    __syncthreads();
+  }
+  // canonical codes
+  if (tid < (uint32_t)G) {
+    uint32_t cnt[MAXLEN + 2];
+    for (int q = 0; q <= MAXLEN + 1; q++) cnt[q] = 0;
+    for (int v = 0; v < a; v++) cnt[lens[tid][v]]++;
+    uint32_t code = 0;
+    for (int q = 1; q <= MAXLEN; q++) {
+      s_first[tid][q] = code;
+      code = (code + cnt[q]) << 1;
+    }
+  }
+  __syncthreads();
+  BlockTables* T = &tabs[b];
+  for (int i = tid; i < G * MAXA; i += NT) {
+    int t = i / MAXA, v = i % MAXA;
+    if (v < a) {
+      uint8_t L = lens[t][v];
+      uint32_t r = 0;
+      for (int u = 0; u < v; u++) r += (lens[t][u] == L) ? 1u : 0u;
+      T->len[t][v] = L;
+      T->code[t][v] = s_first[t][L] + r;
+    }
+  }
+  // data bits per group under the final tables
+  uint64_t dbits = 0;
+  for (uint32_t g = tid; g < nsel; g += NT) {
+    uint32_t lo = g * GROUP, hi = min(lo + GROUP, ns);
+    uint32_t t = sel[sb + g];
+    uint32_t acc = 0;
+    for (uint32_t i = lo; i < hi; i++) acc += lens[t][S[i]];
+    gbits[sb + g] = acc;
+    dbits += acc;
+  }
+  // selector MTF indices: thread-contiguous ranges, prefix-max of last use
+  const uint32_t per = (nsel + NT - 1) / NT;
+  const uint32_t g0 = min(tid * per, nsel), g1 = min(g0 + per, nsel);
+  int lastv[MAXG];
+  for (int v = 0; v < MAXG; v++) lastv[v] = -1 - v;  // initial list 0..G-1, 0 most recent
+  int loc[MAXG];
+  for (int v = 0; v < MAXG; v++) loc[v] = INT_MIN;
+  for (uint32_t g = g0; g < g1; g++) loc[sel[sb + g]] = (int)g;
+  for (int v = 0; v < MAXG; v++) {
+    int incl = block_incl_max<int, NT>(loc[v], shi, INT_MIN);
+    sx[tid] = incl;
+    __syncthreads();
+    int ex = tid ? sx[tid - 1] : INT_MIN;
+    if (ex > lastv[v]) lastv[v] = ex;
+    __syncthreads();
+  }
+  uint32_t sbits = 0;
+  for (uint32_t g = g0; g < g1; g++) {
+    int x = sel[sb + g];
+    uint32_t idx = 0;
+    for (int v = 0; v < G; v++) idx += (v != x && lastv[v] > lastv[x]) ? 1u : 0u;
+    selmtf[sb + g] = (uint8_t)idx;
+    lastv[x] = (int)g;
+    sbits += idx + 1;
+  }
+  uint64_t dtot = block_sum<uint64_t, NT>(dbits, (uint64_t*)cost);
+  uint32_t stot = block_sum<uint32_t, NT>(sbits, sh);
+  if (tid == 0) {
+    uint32_t ranges = 0;
+    for (int j = 0; j < 8; j++) {
+      uint32_t x = inuse[b * 8 + j];
+      ranges += ((x & 0xFFFFu) ? 1u : 0u) + ((x >> 16) ? 1u : 0u);
+    }
+    uint32_t hb = 16 + 16 * ranges + 3 + 15 + stot;
+    for (int t = 0; t < G; t++) {
+      hb += 5;
+      int cur = lens[t][0];
+      for (int v = 0; v < a; v++) {
+        int d = (int)lens[t][v] - cur;
+        hb += 2 * (uint32_t)(d < 0 ? -d : d) + 1;
+        cur = lens[t][v];
+      }
+    }
+    T->G = (uint32_t)G;
+    T->nsel = nsel;
+    T->hdr_bits = hb;
+    T->alpha = (uint32_t)a;
+    T->data_bits = dtot;
+  }
+}
+
+// Per-block symbol histogram (for callers that pass symbols directly).
+__global__ __launch_bounds__(NT) void k_freq(const uint16_t* __restrict__ syms, const uint64_t* __restrict__ sym_base,
+                                             const uint32_t* __restrict__ nsyms, uint32_t* __restrict__ freq,
+                                             uint32_t* __restrict__ err) {
+  __shared__ uint32_t h[MAXA];
+  const uint32_t b = blockIdx.x;
+  for (int i = threadIdx.x; i < MAXA; i += NT) h[i] = 0;
+  __syncthreads();
+  const uint16_t* S = syms + sym_base[b];
+  const uint32_t ns = nsyms[b];
+  for (uint32_t i = threadIdx.x; i < ns; i += NT) {
+    uint32_t v = S[i];
+    if (v < MAXA) atomicAdd(&h[v], 1u);
+    else atomicOr(err, 2u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < MAXA; i += NT) freq[(size_t)b * MAXA + i] = h[i];
+}
+
+size_t block_tables_bytes() { return sizeof(BlockTables); }
+
+hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
+                    uint32_t* freq, bool count_freq, const uint32_t* inuse, const uint64_t* sel_base, uint8_t* sel,
+                    uint8_t* selmtf, uint64_t* gbits, void* tabs, uint32_t* err, hipStream_t st) {
+  if (!nb) return hipSuccess;
+  if (count_freq) hipLaunchKernelGGL(k_freq, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, err);
+  hipLaunchKernelGGL(k_huff, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, inuse, sel_base, sel, selmtf,
+                     gbits, (BlockTables*)tabs);
+  return hipGetLastError();
+}
+
+}  // namespace bzg

@@ -1,0 +1,60 @@
+// Host-side declarations shared by the kernel translation units and the C
+// ABI layer.  Not part of the public interface (that is include/bzgpu.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace bzg {
+
+// Tuning constants (fixed; every choice gives identical output).
+constexpr int NT = 256;                // threads per workgroup
+constexpr uint32_t RADIX_TILE = 4096;  // elements per tile of a segment radix pass
+constexpr uint32_t SMALL_T = 2048;     // packed elements per small-segment tile
+constexpr uint32_t SMALL_MAX = 2048;   // segments up to this size are sorted in LDS
+constexpr uint32_t SMALL_CAP = SMALL_T + SMALL_MAX;  // LDS capacity of a small tile
+constexpr uint32_t RLE_TILE = 4096;    // input bytes per RLE1/CRC tile
+constexpr uint32_t MTF_CHUNK = 8192;   // symbols per move-to-front chunk
+constexpr uint32_t MAX_BLOCK = 1u << 21;  // largest block the sort accepts (ranks fit 21 bits)
+constexpr int GROUP = 50;              // symbols per Huffman selector group
+constexpr int MAXG = 6, MAXA = 258, MAXLEN = 17;
+constexpr uint32_t PACK_GROUPS = 64;   // selector groups per bit-packing tile
+
+// A run of equal-prefix rotations still to be ordered: SA rows
+// [start, start+len) of block blk.  `base` is the segment's packed element
+// offset (small segments) or first tile index (large segments).
+struct SegRec {
+  uint32_t start, len, blk, base;
+};
+
+// Device counters written by a sorting round and read back by the host.
+struct RoundCounters {
+  uint32_t n_segs;       // segments for the next round
+  uint32_t small_total;  // packed elements of small segments
+  uint32_t big_tiles;    // radix tiles of large segments
+  uint32_t active;       // elements in all segments
+  uint32_t overflow;     // nonzero if a capacity was exceeded
+  uint32_t pad[3];
+};
+
+struct Bump {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  template <typename T>
+  T* take(size_t n) {
+    size_t a = (used + 255) & ~size_t(255);
+    used = a + n * sizeof(T);
+    return reinterpret_cast<T*>(base + a);
+  }
+};
+
+// ---- launchers (defined in the kernel translation units) ----
+
+// Device-wide exclusive scan; in == out allowed.  tmp needs scan_tmp_elems(n).
+size_t scan_tmp_elems(size_t n);
+hipError_t scan_excl_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp, hipStream_t s);
+hipError_t scan_excl_u64(const uint64_t* in, uint64_t* out, size_t n, uint64_t* tmp, hipStream_t s);
+
+}  // namespace bzg

@@ -1,0 +1,417 @@
+// Move-to-front (Sec. 3.3) with RUNA/RUNB zero-run coding, chunked.
+//
+// The paper parallelises one MTF step over the recency stack: every
+// processor checks one stack slot and the match is unique.  Here a wave64
+// holds the 256-slot stack, four slots per lane, and one ballot per slot
+// column finds the symbol.  That alone is serial over the block, so blocks
+// are cut into chunks and the stack is carried between them: after a chunk X
+// the stack is D_X followed by the incoming stack with D_X removed, where D_X
+// lists X's distinct symbols by last occurrence, latest first.  That map
+// composes associatively, so chunk summaries are computed in parallel, a
+// per-block scan yields each chunk's incoming stack, and all chunks re-run
+// MTF in parallel.
+//
+// MTF index 0 at row j means L[j] == L[j-1] (at the block's first row: L[0]
+// is the smallest in-use byte), so zero runs -- and the RUNA/RUNB symbol
+// counts -- are known from L alone.  A chunk's zero-run summary
+// (leading zeros, trailing zeros, all-zero flag, digits of runs closed
+// inside, nonzero count) forms a monoid; the scan turns it into every
+// chunk's output offset.  A run is coded where it ends.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bzg {
+
+constexpr int MITEMS = MTF_CHUNK / NT;  // 32 rows per thread
+
+struct ZSum {
+  uint32_t lz, tz, inner, nnz, len, all;
+};
+
+__device__ __forceinline__ uint32_t run_digits(uint32_t r) { return 31u - __clz(r + 1u); }
+
+__device__ __forceinline__ ZSum zcombine(const ZSum& a, const ZSum& b) {
+  ZSum r;
+  r.len = a.len + b.len;
+  if (a.all && b.all) {
+    r = a;
+    r.len = a.len + b.len;
+    r.lz = r.tz = r.len;
+    return r;
+  }
+  r.all = 0;
+  if (a.all) {
+    r.lz = a.len + b.lz;
+    r.tz = b.tz;
+    r.inner = b.inner;
+    r.nnz = b.nnz;
+  } else if (b.all) {
+    r.lz = a.lz;
+    r.tz = a.tz + b.len;
+    r.inner = a.inner;
+    r.nnz = a.nnz;
+  } else {
+    r.lz = a.lz;
+    r.tz = b.tz;
+    r.inner = a.inner + b.inner + run_digits(a.tz + b.lz);
+    r.nnz = a.nnz + b.nnz;
+  }
+  return r;
+}
+
+struct ChunkGeom {
+  uint32_t b, lo, hi, blo, bhi;  // block, chunk rows [lo,hi), block rows [blo,bhi)
+  bool last;
+};
+
+__device__ __forceinline__ ChunkGeom chunk_geom(uint32_t c, const uint32_t* chunk_blk, const uint32_t* blk_chunk0,
+                                                const uint32_t* off) {
+  ChunkGeom g;
+  g.b = chunk_blk[c];
+  g.blo = off[g.b];
+  g.bhi = off[g.b + 1];
+  g.lo = g.blo + (c - blk_chunk0[g.b]) * MTF_CHUNK;
+  g.hi = min(g.lo + MTF_CHUNK, g.bhi);
+  g.last = (c + 1 == blk_chunk0[g.b + 1]);
+  return g;
+}
+
+// In-use bitmap per block (8 words; the caller zeroes it).
+__global__ __launch_bounds__(NT) void k_inuse(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                              const uint32_t* blk_chunk0, const uint32_t* off,
+                                              uint32_t* __restrict__ inuse) {
+  ChunkGeom g = chunk_geom(blockIdx.x, chunk_blk, blk_chunk0, off);
+  uint32_t bm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
+    uint32_t v = L[k];
+#pragma unroll
+    for (int j = 0; j < 8; j++) bm[j] |= ((v >> 5) == (uint32_t)j) ? (1u << (v & 31)) : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    uint32_t x = bm[j];
+    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d, BZG_WAVE);
+    if (lane() == 0 && x) atomicOr(&inuse[g.b * 8 + j], x);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                                  const uint32_t* blk_chunk0, const uint32_t* off,
+                                                  const uint32_t* __restrict__ inuse, uint8_t* __restrict__ chunk_D,
+                                                  uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
+  __shared__ uint32_t last[256];
+  __shared__ ZSum wsum[NT];
+  __shared__ uint32_t s_nd;
+  const uint32_t c = blockIdx.x;
+  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
+  last[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_nd = 0;
+  uint32_t minb = 0;
+  for (int j = 0; j < 8; j++) {
+    uint32_t x = inuse[g.b * 8 + j];
+    if (x) {
+      minb = j * 32 + (__ffs(x) - 1);
+      break;
+    }
+  }
+  __syncthreads();
+  // rows [lo + t*32, +32): last occurrences and the zero-run summary
+  const uint32_t r0 = g.lo + threadIdx.x * MITEMS;
+  uint8_t v[MITEMS];
+  uint32_t prev = 0x100u;
+  if (r0 < g.hi) prev = (r0 == g.blo) ? minb : L[r0 - 1];
+  ZSum s = {0, 0, 0, 0, 0, 1};
+#pragma unroll
+  for (int i = 0; i < MITEMS; i++) {
+    uint32_t k = r0 + i;
+    if (k < g.hi) {
+      v[i] = L[k];
+      ZSum e;
+      if (v[i] == prev) e = {1, 1, 0, 0, 1, 1};
+      else e = {0, 0, 0, 1, 1, 0};
+      s = zcombine(s, e);
+      prev = v[i];
+    }
+  }
+  // last occurrence: scan own rows backwards, report each byte once
+  {
+    uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = MITEMS - 1; i >= 0; i--) {
+      uint32_t k = r0 + i;
+      if (k >= g.hi) continue;
+      uint32_t x = v[i];
+      uint32_t bit = 1u << (x & 31);
+      uint32_t word = 0;
+#pragma unroll
+      for (int j = 0; j < 8; j++) word |= ((x >> 5) == (uint32_t)j) ? seen[j] : 0u;
+      if (!(word & bit)) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) seen[j] |= ((x >> 5) == (uint32_t)j) ? bit : 0u;
+        atomicMax(&last[x], k - g.lo + 1);
+      }
+    }
+  }
+  wsum[threadIdx.x] = s;
+  __syncthreads();
+  // D_X: present bytes by last occurrence, latest first
+  {
+    uint32_t x = threadIdx.x;
+    uint32_t lx = last[x];
+    if (lx) {
+      uint32_t r = 0;
+      for (int u = 0; u < 256; u++) r += (last[u] > lx) ? 1u : 0u;
+      chunk_D[(size_t)c * 256 + r] = (uint8_t)x;
+      atomicAdd(&s_nd, 1u);
+    }
+  }
+  if (threadIdx.x == 0) {
+    ZSum t = wsum[0];
+    for (int i = 1; i < NT; i++) t = zcombine(t, wsum[i]);
+    chunk_sum[c] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_nD[c] = s_nd;
+}
+
+// One wave per block: serial over its chunks.  Writes every chunk's incoming
+// stack, carried zero count and output offset, and the block's symbol count.
+__global__ __launch_bounds__(BZG_WAVE) void k_mtf_scan(const uint32_t* blk_chunk0, const uint32_t* __restrict__ inuse,
+                                                       const uint8_t* __restrict__ chunk_D,
+                                                       const uint32_t* __restrict__ chunk_nD,
+                                                       const ZSum* __restrict__ chunk_sum,
+                                                       uint8_t* __restrict__ chunk_list, uint32_t* __restrict__ chunk_carry,
+                                                       uint32_t* __restrict__ chunk_out, uint32_t* __restrict__ nsyms) {
+  __shared__ uint32_t tmp[256];
+  __shared__ uint16_t f[256];
+  const uint32_t b = blockIdx.x;
+  const uint32_t l = lane();
+  uint32_t bm[8];
+  uint32_t nu = 0;
+  for (int j = 0; j < 8; j++) {
+    bm[j] = inuse[b * 8 + j];
+    nu += __popc(bm[j]);
+  }
+  for (int j = 0; j < 4; j++) tmp[j * 64 + l] = 0x100u;
+  f[l] = 0;
+  f[l + 64] = 0;
+  f[l + 128] = 0;
+  f[l + 192] = 0;
+  __syncthreads();
+  for (int j = 0; j < 4; j++) {
+    uint32_t v = j * 64 + l;
+    if ((bm[v >> 5] >> (v & 31)) & 1u) {
+      uint32_t pos = 0;
+      for (int q = 0; q < (int)(v >> 5); q++) pos += __popc(bm[q]);
+      pos += __popc(bm[v >> 5] & ((1u << (v & 31)) - 1u));
+      tmp[pos] = v;
+    }
+  }
+  __syncthreads();
+  uint32_t e[4];
+  for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
+  __syncthreads();
+  const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1];
+  uint32_t carry = 0, out = 0;
+  for (uint32_t c = c0; c < c1; c++) {
+    for (int j = 0; j < 4; j++) chunk_list[(size_t)c * 256 + j * 64 + l] = (uint8_t)(e[j] & 255u);
+    const uint32_t nd = chunk_nD[c];
+    for (uint32_t i = l; i < nd; i += 64) f[chunk_D[(size_t)c * 256 + i]] = (uint16_t)(i + 1);
+    __syncthreads();
+    uint32_t isd[4];
+    uint64_t nd_mask[4];
+    for (int j = 0; j < 4; j++) {
+      isd[j] = e[j] < 256u ? f[e[j]] : 0u;
+      nd_mask[j] = __ballot(isd[j] == 0);
+    }
+    uint32_t before = 0;
+    for (int j = 0; j < 4; j++) {
+      uint32_t np = isd[j] ? isd[j] - 1 : nd + before + __popcll(nd_mask[j] & lanemask_lt());
+      before += __popcll(nd_mask[j]);
+      tmp[np] = e[j];
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
+    for (uint32_t i = l; i < nd; i += 64) f[chunk_D[(size_t)c * 256 + i]] = 0;
+    __syncthreads();
+    ZSum s = chunk_sum[c];
+    uint32_t cnt;
+    if (l == 0) chunk_carry[c] = carry;
+    if (s.all) {
+      cnt = 0;
+      carry += s.len;
+    } else {
+      cnt = s.nnz + s.inner + run_digits(carry + s.lz);
+      carry = s.tz;
+    }
+    if (c + 1 == c1) cnt += run_digits(carry) + 1;  // flush and end of block
+    if (l == 0) chunk_out[c] = out;
+    out += cnt;
+  }
+  if (l == 0) nsyms[b] = out;
+  (void)nu;
+}
+
+// One wave per chunk: MTF from the chunk's incoming stack, RUNA/RUNB,
+// symbols staged in LDS and stored 256 at a time.
+__global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                                       const uint32_t* blk_chunk0, const uint32_t* off,
+                                                       const uint32_t* __restrict__ inuse,
+                                                       const uint8_t* __restrict__ chunk_list,
+                                                       const uint32_t* __restrict__ chunk_carry,
+                                                       const uint32_t* __restrict__ chunk_out,
+                                                       const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
+                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err) {
+  __shared__ uint16_t buf[512];
+  __shared__ uint32_t fq[MAXA];
+  const uint32_t c = blockIdx.x;
+  const uint32_t l = lane();
+  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
+  uint32_t nu = 0;
+  for (int j = 0; j < 8; j++) nu += __popc(inuse[g.b * 8 + j]);
+  for (uint32_t i = l; i < MAXA; i += 64) fq[i] = 0;
+  uint32_t e[4];
+  for (int j = 0; j < 4; j++) {
+    uint32_t p = j * 64 + l;
+    e[j] = p < nu ? chunk_list[(size_t)c * 256 + p] : 0x100u;
+  }
+  const int ncol = (int)((nu + 63) / 64);
+  uint32_t zrun = chunk_carry[c];
+  const uint64_t obase = sym_base[g.b] + chunk_out[c];
+  uint32_t wc = 0;  // symbols emitted by this chunk
+  __syncthreads();
+  auto flush_half = [&](uint32_t upto) {
+    // store the 256-symbol half that ends at `upto` (a multiple of 256)
+    uint32_t h = ((upto - 1) >> 8) & 1u;
+    __syncthreads();
+    for (int q = 0; q < 4; q++) {
+      uint32_t i = q * 64 + l;
+      syms[obase + upto - 256 + i] = buf[h * 256 + i];
+    }
+    __syncthreads();
+  };
+  auto emit = [&](uint32_t sym) {
+    if (l == 0) {
+      buf[wc & 511u] = (uint16_t)sym;
+      fq[sym]++;
+    }
+    wc++;
+    if ((wc & 255u) == 0) flush_half(wc);
+  };
+  auto emit_run = [&](uint32_t r) {
+    while (r) {
+      if (r & 1u) {
+        emit(0);
+        r = (r - 1) >> 1;
+      } else {
+        emit(1);
+        r = (r - 2) >> 1;
+      }
+    }
+  };
+  for (uint32_t base = g.lo; base < g.hi; base += 64) {
+    uint32_t cnt = min(64u, g.hi - base);
+    uint32_t mine = (base + l < g.hi) ? L[base + l] : 0u;
+    {
+      for (uint32_t i = 0; i < cnt; i++) {
+        uint32_t x = __shfl(mine, (int)i, BZG_WAVE);
+        uint32_t pos = 0xFFFFFFFFu;
+        for (int j = 0; j < ncol; j++) {
+          uint64_t m = __ballot(e[j] == x);
+          if (m) {
+            pos = j * 64 + (uint32_t)(__ffsll((long long)m) - 1);
+            break;
+          }
+        }
+        if (pos == 0) {
+          zrun++;
+          continue;
+        }
+        if (pos == 0xFFFFFFFFu) {  // symbol not in the stack: corrupt input
+          if (l == 0) atomicOr(err, 1u);
+          pos = 1;
+        }
+        emit_run(zrun);
+        zrun = 0;
+        emit(pos + 1);
+        // rows 1..pos take the row above them, row 0 takes x
+        uint32_t into = x;  // old value entering column j at lane 0
+        for (int j = 0; j < ncol; j++) {
+          if ((uint32_t)j * 64 > pos) break;
+          uint32_t old = e[j];
+          uint32_t up = __shfl_up(old, 1, BZG_WAVE);
+          if (l == 0) up = into;
+          into = __shfl(old, 63, BZG_WAVE);
+          if ((uint32_t)j * 64 + l <= pos) e[j] = up;
+        }
+      }
+    }
+  }
+  if (g.last) {
+    emit_run(zrun);
+    emit(nu + 1);
+  }
+  __syncthreads();
+  uint32_t rem = wc & 255u;
+  if (rem) {
+    uint32_t h = (wc >> 8) & 1u;
+    for (uint32_t i = l; i < rem; i += 64) syms[obase + (wc - rem) + i] = buf[h * 256 + i];
+  }
+  for (uint32_t i = l; i < nu + 2; i += 64)
+    if (fq[i]) atomicAdd(&freq[(size_t)g.b * MAXA + i], fq[i]);
+}
+
+// ------------------------------------------------------------- host side
+
+hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<uint32_t>& h_off, void* ws,
+                   size_t ws_bytes, uint16_t* syms, const uint64_t* d_sym_base, uint32_t* nsyms, uint32_t* inuse,
+                   uint32_t* freq, uint32_t* err, hipStream_t st, std::string& emsg) {
+  const uint32_t nb = (uint32_t)h_off.size() - 1;
+  std::vector<uint32_t> chunk_blk, blk_chunk0(nb + 1);
+  for (uint32_t b = 0; b < nb; b++) {
+    blk_chunk0[b] = (uint32_t)chunk_blk.size();
+    uint32_t n = h_off[b + 1] - h_off[b];
+    uint32_t nc = (n + MTF_CHUNK - 1) / MTF_CHUNK;
+    for (uint32_t q = 0; q < nc; q++) chunk_blk.push_back(b);
+  }
+  blk_chunk0[nb] = (uint32_t)chunk_blk.size();
+  const uint32_t nc = (uint32_t)chunk_blk.size();
+  Bump bump;
+  bump.base = (char*)ws;
+  bump.cap = ws_bytes;
+  uint32_t* d_chunk_blk = bump.take<uint32_t>(nc + 1);
+  uint32_t* d_blk_chunk0 = bump.take<uint32_t>(nb + 1);
+  uint8_t* d_D = bump.take<uint8_t>((size_t)nc * 256);
+  uint32_t* d_nD = bump.take<uint32_t>(nc + 1);
+  ZSum* d_sum = bump.take<ZSum>(nc + 1);
+  uint8_t* d_list = bump.take<uint8_t>((size_t)nc * 256);
+  uint32_t* d_carry = bump.take<uint32_t>(nc + 1);
+  uint32_t* d_out = bump.take<uint32_t>(nc + 1);
+  if (bump.used > ws_bytes) {
+    emsg = "mtf workspace too small";
+    return hipErrorInvalidValue;
+  }
+  hipError_t e;
+  if (nc == 0) return hipSuccess;
+  if ((e = hipMemcpyAsync(d_chunk_blk, chunk_blk.data(), nc * 4, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return e;
+  if ((e = hipMemsetAsync(inuse, 0, (size_t)nb * 32, st)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(freq, 0, (size_t)nb * MAXA * 4, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_inuse, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse);
+  hipLaunchKernelGGL(k_mtf_state, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_D, d_nD,
+                     d_sum);
+  hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d_blk_chunk0, inuse, d_D, d_nD, d_sum, d_list,
+                     d_carry, d_out, nsyms);
+  hipLaunchKernelGGL(k_mtf_emit, dim3(nc), dim3(BZG_WAVE), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_list,
+                     d_carry, d_out, d_sym_base, syms, freq, err);
+  return hipGetLastError();
+}
+
+size_t mtf_workspace_bytes(const std::vector<uint32_t>& h_off) {
+  const uint32_t nb = (uint32_t)h_off.size() - 1;
+  size_t nc = 0;
+  for (uint32_t b = 0; b < nb; b++) nc += (h_off[b + 1] - h_off[b] + MTF_CHUNK - 1) / MTF_CHUNK;
+  return 8 * 256 + (nc + 1) * (4 + 256 + 4 + sizeof(ZSum) + 256 + 4 + 4) + (nb + 1) * 4 + 4096;
+}
+
+}  // namespace bzg

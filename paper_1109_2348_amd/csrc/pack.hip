@@ -1,0 +1,322 @@
+// Variable-length packing and stream assembly (Sec. 3.4, Figure 3: look up
+// every symbol's code and length, take the prefix sum of the lengths as bit
+// offsets, write every code at its offset).
+//
+// Bits are written MSB-first straight into their final place in the output
+// stream, so blocks need no later bit-shifting copy: block bit offsets are a
+// prefix sum of block sizes, group offsets a prefix sum of group sizes, symbol
+// offsets a prefix sum inside a tile.  A tile assembles its words in LDS;
+// words wholly inside the tile are stored, the two edge words are OR-ed in
+// atomically (the buffer is zeroed first).  Words hold stream bits in
+// big-endian order and are byte-swapped on store.
+#include <climits>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bzg {
+
+struct BlockTables {  // mirror of the layout in huff.hip
+  uint32_t G, nsel, hdr_bits, alpha;
+  uint64_t data_bits;
+  uint8_t len[MAXG][MAXA];
+  uint32_t code[MAXG][MAXA];
+};
+
+__device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
+
+// OR the low n (<= 32) bits of v into the stream at bit position pos.
+__device__ __forceinline__ void put_bits(uint32_t* words, uint64_t pos, uint32_t v, uint32_t n) {
+  if (n == 0) return;
+  v &= (n == 32) ? 0xFFFFFFFFu : ((1u << n) - 1u);
+  uint64_t wi = pos >> 5;
+  uint32_t o = (uint32_t)(pos & 31);
+  if (o + n <= 32) {
+    atomicOr(&words[wi], bswap32(v << (32 - o - n)));
+  } else {
+    uint32_t spill = o + n - 32;
+    atomicOr(&words[wi], bswap32(v >> spill));
+    atomicOr(&words[wi + 1], bswap32(v << (32 - spill)));
+  }
+}
+
+__device__ __forceinline__ void put_bits64(uint32_t* words, uint64_t pos, uint64_t v, uint32_t n) {
+  if (n > 32) {
+    put_bits(words, pos, (uint32_t)(v >> 32), n - 32);
+    put_bits(words, pos + (n - 32), (uint32_t)v, 32);
+  } else {
+    put_bits(words, pos, (uint32_t)v, n);
+  }
+}
+
+// Block layout: bit offset of every block and the stream end.  One
+// workgroup.  mode 0: one stream (blocks follow a 32-bit stream header, each
+// block carries the 105-bit block header); mode 1: bodies only, block b at
+// body_byte[b] * 8.
+__global__ __launch_bounds__(NT) void k_layout(uint32_t nb, const BlockTables* __restrict__ tabs, int mode,
+                                               const uint64_t* __restrict__ body_byte, uint64_t* __restrict__ blk_bit,
+                                               const uint32_t* __restrict__ crc, uint64_t* __restrict__ info) {
+  __shared__ uint64_t sh[NT / BZG_WAVE + 1];
+  uint64_t carry = 32;
+  for (uint32_t c = 0; c < nb; c += NT) {
+    uint32_t b = c + threadIdx.x;
+    uint64_t sz = 0;
+    if (b < nb) sz = (mode == 0 ? 105u : 0u) + tabs[b].hdr_bits + tabs[b].data_bits;
+    uint64_t tot;
+    uint64_t ex = block_excl_sum<uint64_t, NT>(sz, sh, &tot);
+    if (b < nb) blk_bit[b] = mode == 0 ? carry + ex : body_byte[b] * 8;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    uint32_t comb = 0;
+    if (mode == 0)
+      for (uint32_t b = 0; b < nb; b++) comb = ((comb << 1) | (comb >> 31)) ^ crc[b];
+    info[0] = carry + 80;  // stream bits incl. end-of-stream marker and CRC
+    info[1] = comb;
+  }
+}
+
+// Block header and body head: [magic, CRC, rand bit, origPtr,] symbol map,
+// table count, selector count, unary MTF'd selectors, delta-coded lengths.
+__global__ __launch_bounds__(NT) void k_pack_header(const BlockTables* __restrict__ tabs, int mode,
+                                                    const uint64_t* __restrict__ blk_bit,
+                                                    const uint32_t* __restrict__ crc,
+                                                    const uint32_t* __restrict__ primary,
+                                                    const uint32_t* __restrict__ inuse,
+                                                    const uint64_t* __restrict__ sel_base,
+                                                    const uint8_t* __restrict__ selmtf, uint32_t* __restrict__ words) {
+  __shared__ uint64_t sh[NT / BZG_WAVE + 1];
+  const uint32_t b = blockIdx.x;
+  const BlockTables* T = &tabs[b];
+  const uint32_t G = T->G, nsel = T->nsel, a = T->alpha;
+  uint64_t pos = blk_bit[b];
+  if (mode == 0) {
+    if (threadIdx.x == 0) {
+      put_bits64(words, pos, 0x314159265359ull, 48);
+      put_bits(words, pos + 48, crc[b], 32);
+      put_bits(words, pos + 81, primary[b], 24);  // bit 80 is the (zero) randomised flag
+    }
+    pos += 105;
+  }
+  uint32_t bm[8];
+  uint32_t ranges = 0, nr = 0;
+  for (int j = 0; j < 8; j++) {
+    bm[j] = inuse[b * 8 + j];
+    for (int hlf = 0; hlf < 2; hlf++) {
+      uint32_t r = 2 * j + hlf;
+      if ((bm[j] >> (16 * hlf)) & 0xFFFFu) {
+        ranges |= 1u << (15 - r);
+        nr++;
+      }
+    }
+  }
+  if (threadIdx.x == 0) put_bits(words, pos, ranges, 16);
+  pos += 16;
+  if (threadIdx.x < 16 && ((ranges >> (15 - threadIdx.x)) & 1u)) {
+    uint32_t r = threadIdx.x;
+    uint32_t k = __popc(ranges >> (16 - r)) ;  // used ranges before r
+    if (r == 0) k = 0;
+    uint32_t half = (bm[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+    uint32_t v = 0;  // bit j (MSB first) = byte 16r + j in use
+    for (int j = 0; j < 16; j++) v |= ((half >> j) & 1u) << (15 - j);
+    put_bits(words, pos + 16 * k, v, 16);
+  }
+  pos += 16 * nr;
+  if (threadIdx.x == 0) {
+    put_bits(words, pos, G, 3);
+    put_bits(words, pos + 3, nsel, 15);
+  }
+  pos += 18;
+  // selectors: thread-contiguous ranges
+  const uint32_t per = (nsel + NT - 1) / NT;
+  const uint32_t g0 = min(threadIdx.x * per, nsel), g1 = min(g0 + per, nsel);
+  const uint8_t* M = selmtf + sel_base[b];
+  uint64_t mine = 0;
+  for (uint32_t g = g0; g < g1; g++) mine += M[g] + 1u;
+  uint64_t tot;
+  uint64_t p = pos + block_excl_sum<uint64_t, NT>(mine, sh, &tot);
+  for (uint32_t g = g0; g < g1; g++) {
+    uint32_t n = M[g] + 1u;
+    put_bits(words, p, (1u << n) - 2u, n);
+    p += n;
+  }
+  pos += tot;
+  // code lengths, one table after another
+  for (uint32_t t = 0; t < G; t++) {
+    if (threadIdx.x == 0) put_bits(words, pos, T->len[t][0], 5);
+    pos += 5;
+    for (uint32_t c = 0; c < a; c += NT) {
+      uint32_t v = c + threadIdx.x;
+      uint32_t n = 0;
+      int d = 0;
+      if (v < a) {
+        int prev = v ? T->len[t][v - 1] : T->len[t][0];
+        d = (int)T->len[t][v] - prev;
+        n = 2u * (uint32_t)(d < 0 ? -d : d) + 1u;
+      }
+      uint64_t tt;
+      uint64_t q = pos + block_excl_sum<uint64_t, NT>((uint64_t)n, sh, &tt);
+      if (v < a) {
+        uint64_t code = 0;
+        uint32_t step = d < 0 ? 3u : 2u;
+        for (int i = 0; i < (d < 0 ? -d : d); i++) code = (code << 2) | step;
+        code <<= 1;
+        put_bits64(words, q, code, n);
+      }
+      pos += tt;
+    }
+  }
+}
+
+// Data codes: tile = PACK_GROUPS selector groups of one block.
+__global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict__ tabs, int mode,
+                                                  const uint32_t* __restrict__ tile_blk,
+                                                  const uint32_t* __restrict__ blk_tile0,
+                                                  const uint64_t* __restrict__ blk_bit,
+                                                  const uint16_t* __restrict__ syms,
+                                                  const uint64_t* __restrict__ sym_base,
+                                                  const uint32_t* __restrict__ nsyms,
+                                                  const uint64_t* __restrict__ sel_base,
+                                                  const uint8_t* __restrict__ sel,
+                                                  const uint64_t* __restrict__ gofs, uint32_t* __restrict__ words) {
+  constexpr uint32_t MAXSYM = PACK_GROUPS * GROUP;               // 3200
+  constexpr uint32_t PER = (MAXSYM + NT - 1) / NT;               // 13
+  constexpr uint32_t WCAP = (MAXSYM * MAXLEN) / 32 + 4;          // staging words
+  __shared__ uint32_t stage[WCAP];
+  __shared__ uint8_t slen[MAXG][MAXA];
+  __shared__ uint32_t scode[MAXG][MAXA];
+  __shared__ uint64_t sh[NT / BZG_WAVE + 1];
+  const uint32_t j = blockIdx.x;
+  const uint32_t b = tile_blk[j];
+  const BlockTables* T = &tabs[b];
+  const uint32_t nsel = T->nsel, G = T->G, a = T->alpha;
+  const uint32_t g0 = (j - blk_tile0[b]) * PACK_GROUPS;
+  if (g0 >= nsel) return;
+  const uint32_t g1 = min(g0 + PACK_GROUPS, nsel);
+  const uint32_t ns = nsyms[b];
+  const uint32_t s0 = g0 * GROUP, s1 = min(g1 * GROUP, ns);
+  for (uint32_t i = threadIdx.x; i < G * MAXA; i += NT) {
+    uint32_t t = i / MAXA, v = i % MAXA;
+    if (v < a) {
+      slen[t][v] = T->len[t][v];
+      scode[t][v] = T->code[t][v];
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < WCAP; i += NT) stage[i] = 0;
+  __syncthreads();
+  const uint64_t sb = sel_base[b];
+  const uint64_t data0 = blk_bit[b] + (mode == 0 ? 105u : 0u) + T->hdr_bits;
+  const uint64_t B0 = data0 + (gofs[sb + g0] - gofs[sb]);
+  const uint16_t* S = syms + sym_base[b];
+  // blocked: PER consecutive symbols per thread
+  const uint32_t i0 = s0 + threadIdx.x * PER;
+  uint32_t mine = 0;
+  for (uint32_t q = 0; q < PER; q++) {
+    uint32_t i = i0 + q;
+    if (i < s1) mine += slen[sel[sb + i / GROUP]][S[i]];
+  }
+  uint64_t tot;
+  uint64_t p = (B0 & 31) + block_excl_sum<uint64_t, NT>((uint64_t)mine, sh, &tot);
+  for (uint32_t q = 0; q < PER; q++) {
+    uint32_t i = i0 + q;
+    if (i >= s1) break;
+    uint32_t t = sel[sb + i / GROUP];
+    uint32_t s = S[i];
+    uint32_t n = slen[t][s], v = scode[t][s];
+    uint32_t wi = (uint32_t)(p >> 5), o = (uint32_t)(p & 31);
+    if (o + n <= 32) {
+      atomicOr(&stage[wi], v << (32 - o - n));
+    } else {
+      uint32_t spill = o + n - 32;
+      atomicOr(&stage[wi], v >> spill);
+      atomicOr(&stage[wi + 1], v << (32 - spill));
+    }
+    p += n;
+  }
+  __syncthreads();
+  const uint64_t endbit = (B0 & 31) + tot;  // local bit end
+  const uint32_t nw = (uint32_t)((endbit + 31) >> 5);
+  const uint64_t W0 = B0 >> 5;
+  for (uint32_t i = threadIdx.x; i < nw; i += NT) {
+    uint32_t v = stage[i];
+    if (i == 0 || i + 1 == nw) {
+      if (v) atomicOr(&words[W0 + i], bswap32(v));
+    } else {
+      words[W0 + i] = bswap32(v);
+    }
+  }
+}
+
+__global__ void k_stream_ends(int level, const uint64_t* __restrict__ info, uint32_t* __restrict__ words) {
+  if (threadIdx.x != 0) return;
+  uint64_t end = info[0];
+  uint32_t hdr = ((uint32_t)'B' << 24) | ((uint32_t)'Z' << 16) | ((uint32_t)'h' << 8) | (uint32_t)('0' + level);
+  atomicOr(&words[0], bswap32(hdr));
+  put_bits64(words, end - 80, 0x177245385090ull, 48);
+  put_bits(words, end - 32, (uint32_t)info[1], 32);
+}
+
+// Per block: byte 0 = table count, bytes 16 + 258*t + v = code lengths.
+__global__ __launch_bounds__(NT) void k_tables_export(const BlockTables* __restrict__ tabs, uint8_t* __restrict__ out) {
+  constexpr uint32_t STRIDE = 1568;
+  const uint32_t b = blockIdx.x;
+  const BlockTables* T = &tabs[b];
+  for (uint32_t i = threadIdx.x; i < STRIDE; i += NT) {
+    uint8_t v = 0;
+    if (i == 0) {
+      v = (uint8_t)T->G;
+    } else if (i >= 16 && i < 16 + MAXG * MAXA) {
+      uint32_t t = (i - 16) / MAXA, s = (i - 16) % MAXA;
+      if (t < T->G && s < T->alpha) v = T->len[t][s];
+    }
+    out[(size_t)b * STRIDE + i] = v;
+  }
+}
+
+// Body bits per block, and a capacity flag (bit 2 of err).
+__global__ __launch_bounds__(NT) void k_body_sizes(uint32_t nb, const BlockTables* __restrict__ tabs,
+                                                   const uint64_t* __restrict__ obyte, uint64_t* __restrict__ nbits,
+                                                   uint32_t* __restrict__ err) {
+  uint32_t b = blockIdx.x * NT + threadIdx.x;
+  if (b >= nb) return;
+  uint64_t bits = (uint64_t)tabs[b].hdr_bits + tabs[b].data_bits;
+  nbits[b] = bits;
+  if (bits > (obyte[b + 1] - obyte[b]) * 8) atomicOr(err, 4u);
+}
+
+hipError_t tables_export(uint32_t nb, const void* tabs, uint8_t* out, hipStream_t st) {
+  if (nb) hipLaunchKernelGGL(k_tables_export, dim3(nb), dim3(NT), 0, st, (const BlockTables*)tabs, out);
+  return hipGetLastError();
+}
+
+hipError_t body_sizes(uint32_t nb, const void* tabs, const uint64_t* obyte, uint64_t* nbits, uint32_t* err,
+                      hipStream_t st) {
+  if (nb) hipLaunchKernelGGL(k_body_sizes, dim3((nb + NT - 1) / NT), dim3(NT), 0, st, nb, (const BlockTables*)tabs,
+                             obyte, nbits, err);
+  return hipGetLastError();
+}
+
+hipError_t pack_layout(uint32_t nb, const void* tabs, int mode, const uint64_t* body_byte, uint64_t* blk_bit,
+                       const uint32_t* crc, uint64_t* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(NT), 0, st, nb, (const BlockTables*)tabs, mode, body_byte, blk_bit, crc,
+                     info);
+  return hipGetLastError();
+}
+
+hipError_t pack_run(uint32_t nb, const void* tabs, int mode, const uint64_t* blk_bit, const uint32_t* crc,
+                    const uint32_t* primary, const uint32_t* inuse, const uint64_t* sel_base, const uint8_t* sel,
+                    const uint8_t* selmtf, const uint64_t* gofs, uint32_t ntiles, const uint32_t* tile_blk,
+                    const uint32_t* blk_tile0, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
+                    int level, const uint64_t* info, uint32_t* words, hipStream_t st) {
+  if (nb) {
+    hipLaunchKernelGGL(k_pack_header, dim3(nb), dim3(NT), 0, st, (const BlockTables*)tabs, mode, blk_bit, crc, primary,
+                       inuse, sel_base, selmtf, words);
+    if (ntiles)
+      hipLaunchKernelGGL(k_pack_data, dim3(ntiles), dim3(NT), 0, st, (const BlockTables*)tabs, mode, tile_blk,
+                         blk_tile0, blk_bit, syms, sym_base, nsyms, sel_base, sel, gofs, words);
+  }
+  if (mode == 0) hipLaunchKernelGGL(k_stream_ends, dim3(1), dim3(64), 0, st, level, info, words);
+  return hipGetLastError();
+}
+
+}  // namespace bzg

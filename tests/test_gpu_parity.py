@@ -1,0 +1,269 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: every
+output is integer and must match bit for bit."""
+
+import bz2
+import itertools
+import random
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cref
+from paper_1109_2348_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bz():
+    import torch
+    import paper_1109_2348_amd as bz
+    assert torch.cuda.is_available()
+    return bz
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).cuda()
+
+
+def _concat(blocks):
+    offs = np.zeros(len(blocks) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(b) for b in blocks])
+    data = np.concatenate([np.frombuffer(bytes(b), np.uint8) if not isinstance(b, np.ndarray) else b
+                           for b in blocks]) if blocks else np.zeros(0, np.uint8)
+    return data.astype(np.uint8), offs
+
+
+def _check_bwt(bz, blocks, name, full_oracle=True):
+    data, offs = _concat(blocks)
+    _say(f"bwt {name}: {len(blocks)} blocks, {data.size} bytes")
+    L, prim, sa = bz.bwt(_dev(data), offs, want_sa=True)
+    L = L.cpu().numpy()
+    prim = prim.cpu().numpy()
+    sa = sa.cpu().numpy().view(np.uint32)
+    for k, blk in enumerate(blocks):
+        a, b = int(offs[k]), int(offs[k + 1])
+        if full_oracle:
+            rsa, rL, ro = cref.bwt(blk)
+            assert np.array_equal(sa[a:b], rsa), f"{name} block {k}: SA differs"
+            assert np.array_equal(L[a:b], rL), f"{name} block {k}: L differs"
+            assert int(prim[k]) == ro, f"{name} block {k}: primary {prim[k]} != {ro}"
+        else:
+            blk = np.asarray(blk, np.uint8)
+            assert cref.check_sa(blk, sa[a:b]) == -1, f"{name} block {k}: SA not sorted"
+            n = b - a
+            assert np.array_equal(L[a:b], blk[(sa[a:b].astype(np.int64) - 1) % n])
+            assert int(sa[a + int(prim[k])]) == 0
+
+
+def test_bwt_brute_force_families(bz):
+    blocks = []
+    for n in range(1, 9):
+        blocks += [bytes(t) for t in itertools.product(b"ab", repeat=n)]
+    for n in range(1, 6):
+        blocks += [bytes(t) for t in itertools.product(b"abc", repeat=n)]
+    _check_bwt(bz, blocks, "all strings over {a,b} <= 8 and {a,b,c} <= 5")
+
+
+def test_bwt_random_sizes(bz):
+    rnd = random.Random(1)
+    blocks = []
+    for n in [1, 2, 3, 4, 5, 63, 64, 65, 4095, 4096, 4097, 2047, 2048, 2049, 10000, 33333]:
+        alpha = rnd.choice([b"ab", b"abcd", bytes(range(256))])
+        blocks.append(bytes(rnd.choice(alpha) for _ in range(n)))
+    _check_bwt(bz, blocks, "random sizes across tile edges")
+
+
+def test_bwt_periodic_and_same(bz):
+    blocks = [b"a" * 5000, b"ab" * 3000, b"abc" * 2000 + b"ab", b"xyzxa" * 1400, b"\x00" * 70000,
+              (b"q" * 300 + b"r") * 40]
+    c = W.config3(nb=6, n_same=2, block=20000, seed=31)
+    blocks += [c.block(k) for k in range(c.n_blocks)]
+    _check_bwt(bz, blocks, "periodic / all-same / flipped-periodic")
+
+
+def test_bwt_text_blocks(bz):
+    b = W.config2(total=3 * 150000, block=150000, seed=7)
+    _check_bwt(bz, [b.block(k) for k in range(b.n_blocks)], "uniform/text/sparse 150000-byte blocks")
+
+
+def test_bwt_max_block(bz):
+    g = np.random.default_rng(3)
+    blk = g.integers(0, 4, size=1 << 21, dtype=np.uint8)
+    _check_bwt(bz, [blk], "one block of 2^21 bytes", full_oracle=False)
+
+
+def test_bwt_rejects_bad_blocks(bz):
+    x = _dev(np.zeros(10, np.uint8))
+    with pytest.raises(bz.BzgError):
+        bz.bwt(x, [0, 5, 5, 10])  # empty block
+    with pytest.raises(bz.BzgError):
+        bz.bwt(_dev(np.zeros((1 << 21) + 1, np.uint8)), [0, (1 << 21) + 1])
+
+
+def _check_mtf(bz, Ls, name):
+    data, offs = _concat(Ls)
+    _say(f"mtf {name}: {len(Ls)} blocks, {data.size} bytes")
+    syms, nsyms, inuse = bz.mtf(_dev(data), offs)
+    syms = syms.cpu().numpy().view(np.uint16)
+    nsyms = nsyms.cpu().numpy()
+    inuse = inuse.cpu().numpy()
+    for k, Lk in enumerate(Ls):
+        rs, used, nu, _ = cref.mtf_zrle(Lk)
+        base = int(offs[k]) + k
+        assert int(nsyms[k]) == rs.size, f"{name} block {k}: nsyms {nsyms[k]} != {rs.size}"
+        assert np.array_equal(syms[base:base + rs.size], rs), f"{name} block {k}: symbols differ"
+        bits = np.unpackbits(inuse[32 * k:32 * k + 32], bitorder="little")
+        assert np.array_equal(bits, used), f"{name} block {k}: in-use map differs"
+
+
+def test_mtf_random(bz):
+    rnd = random.Random(2)
+    Ls = []
+    for n in [1, 2, 3, 64, 100, 8191, 8192, 8193, 20000, 50001]:
+        alpha = rnd.choice([b"a", b"ab", b"abc", bytes(range(256)), bytes(range(0, 256, 3))])
+        p0 = rnd.random()
+        s = bytearray()
+        for _ in range(n):
+            s.append(s[-1] if s and rnd.random() < p0 else rnd.choice(alpha))
+        Ls.append(bytes(s))
+    _check_mtf(bz, Ls, "random blocks with runs")
+
+
+def test_mtf_bwt_columns(bz):
+    b = W.config2(total=4 * 100000, block=100000, seed=11)
+    Ls = []
+    for k in range(b.n_blocks):
+        _, L, _ = cref.bwt(cref.rle1(b.block(k)))
+        Ls.append(L)
+    Ls.append(np.zeros(30000, np.uint8))  # one long zero run across chunks
+    _check_mtf(bz, Ls, "BWT columns of uniform/text/sparse")
+
+
+def _check_huff(bz, sym_lists, used_list, name):
+    import torch
+    _say(f"huffman {name}: {len(sym_lists)} blocks")
+    nb = len(sym_lists)
+    so = np.zeros(nb + 1, np.uint64)
+    so[1:] = np.cumsum([s.size for s in sym_lists])
+    syms = torch.from_numpy(np.concatenate(sym_lists).astype(np.uint16).view(np.int16)).cuda()
+    nsyms = torch.tensor([s.size for s in sym_lists], dtype=torch.int32).cuda()
+    inuse = torch.from_numpy(np.concatenate([np.packbits(u.astype(np.uint8), bitorder="little")
+                                             for u in used_list])).cuda()
+    out, oo, nbits, tabs = bz.huffman(syms, nsyms, inuse, so, want_tables=True)
+    out = out.cpu().numpy()
+    nbits = nbits.cpu().numpy()
+    tabs = tabs.cpu().numpy()
+    for k in range(nb):
+        ref, rbits, rlens, rsel = cref.body(sym_lists[k], used_list[k])
+        assert int(nbits[k]) == rbits, f"{name} block {k}: {nbits[k]} bits != {rbits}"
+        g = int(tabs[1568 * k])
+        assert g == rlens.shape[0]
+        a = rlens.shape[1]
+        for t in range(g):
+            got = tabs[1568 * k + 16 + 258 * t:1568 * k + 16 + 258 * t + a]
+            assert np.array_equal(got, rlens[t]), f"{name} block {k}: table {t} lengths differ"
+        body = out[int(oo[k]):int(oo[k]) + (rbits + 7) // 8].tobytes()
+        assert body == ref, f"{name} block {k}: body bits differ"
+
+
+def test_huffman_from_oracle_symbols(bz):
+    b = W.config2(total=6 * 60000, block=60000, seed=13)
+    sl, ul = [], []
+    for k in range(b.n_blocks):
+        _, L, _ = cref.bwt(cref.rle1(b.block(k)))
+        s, used, _, _ = cref.mtf_zrle(L)
+        sl.append(s)
+        ul.append(used)
+    for n in [1, 2, 3, 49, 50, 51, 199, 200, 599, 600, 1199, 2399, 2400]:  # table-count edges
+        rnd = np.random.default_rng(n)
+        nu = int(rnd.integers(1, 40))
+        s = rnd.integers(0, nu + 1, size=n - 1).astype(np.uint16)
+        sl.append(np.concatenate([s, [nu + 1]]).astype(np.uint16))
+        used = np.zeros(256, np.uint8)
+        used[rnd.choice(256, size=nu, replace=False)] = 1
+        ul.append(used)
+    _check_huff(bz, sl, ul, "oracle symbol streams + table-count edges")
+
+
+def _check_compress(bz, data, offs, level, name):
+    _say(f"compress {name}: {data.size} bytes, level {level}")
+    z = bz.compress(_dev(data), offs, level=level).cpu().numpy().tobytes()
+    ref = cref.compress(data, offs, level=level, threads=16)
+    if z != ref:
+        n = min(len(z), len(ref))
+        first = next((i for i in range(n) if z[i] != ref[i]), n)
+        raise AssertionError(f"{name}: stream differs at byte {first} (gpu {len(z)} B, oracle {len(ref)} B)")
+    return z
+
+
+def test_compress_small_cases(bz):
+    rnd = random.Random(5)
+    cases = [b"", b"a", b"ab", b"banana", b"aaaa", b"aaaaa", b"a" * 300, b"abab" * 100,
+             bytes(range(256)) * 5, bytes(rnd.randrange(256) for _ in range(5000))]
+    for i, x in enumerate(cases):
+        data = np.frombuffer(x, np.uint8)
+        offs = [0, len(x)] if x else [0]
+        z = _check_compress(bz, data, offs, 9, f"small case {i}")
+        assert bz2.decompress(z) == x
+
+
+def test_compress_config1(bz):
+    b = W.config1()
+    z = _check_compress(bz, b.data, b.offsets, 1, "single 100000-byte block, order-2 Markov")
+    assert bz2.decompress(z) == b.data.tobytes()
+
+
+def test_compress_mixed_blocks(bz):
+    b = W.config2(total=9 * 100000 + 12345, block=100000, seed=17)
+    z = _check_compress(bz, b.data, b.offsets, 1, "10 blocks uniform/text/sparse, level 1 (cuts)")
+    assert bz2.decompress(z) == b.data.tobytes()
+
+
+def test_compress_uneven_blocks(bz):
+    b = W.config4(nb=40, lo=10, hi=150000, seed=19)
+    z = _check_compress(bz, b.data, b.offsets, 2, "40 uneven blocks")
+    assert bz2.decompress(z) == b.data.tobytes()
+
+
+def test_compress_rejects_bad_args(bz):
+    x = _dev(np.zeros(10, np.uint8))
+    with pytest.raises(bz.BzgError):
+        bz.compress(x, [0, 10], level=0)
+    with pytest.raises(bz.BzgError):
+        bz.compress(x, [0, 7, 3, 10], level=9)
+
+
+@pytest.mark.slow
+def test_compress_config2_full(bz):
+    b = W.config2()
+    z = _check_compress(bz, b.data, b.offsets, 9, "64 MiB in 900000-byte blocks")
+    assert bz2.decompress(z) == b.data.tobytes()
+
+
+@pytest.mark.slow
+def test_bwt_config3_sampled(bz):
+    b = W.config3()
+    _say("bwt 256 x 900000 periodic / all-same (sampled property check)")
+    L, prim, sa = bz.bwt(_dev(b.data), b.offsets, want_sa=True)
+    sa = sa.cpu().numpy().view(np.uint32)
+    L = L.cpu().numpy()
+    prim = prim.cpu().numpy()
+    rnd = random.Random(3)
+    picks = sorted(rnd.sample(range(b.n_blocks), 4)) + [b.kinds.index("same")]
+    for k in picks:
+        a, e = int(b.offsets[k]), int(b.offsets[k + 1])
+        blk = b.block(k)
+        assert cref.check_sa(blk, sa[a:e]) == -1, f"block {k} ({b.kinds[k]}): SA not sorted"
+        assert np.array_equal(L[a:e], blk[(sa[a:e].astype(np.int64) - 1) % (e - a)])
+        assert int(sa[a + int(prim[k])]) == 0
+    for k in range(b.n_blocks):  # every block: permutation and primary
+        a, e = int(b.offsets[k]), int(b.offsets[k + 1])
+        assert int(sa[a + int(prim[k])]) == 0
