@@ -1,0 +1,152 @@
+"""Benchmark: whole-pipeline bzip2 compression (CRC, RLE1, BWT, MTF,
+RUNA/RUNB, Huffman, packing) of 64 MiB cut into 900,000-byte blocks on one
+MI355X, input resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "input MB/s (BWT+MTF+Huffman), batched vs per-block on 1 MI355X; p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, sample_blocks, threads):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    from oracle import cref
+    idx = []
+    for kind in ("uniform", "text", "sparse"):
+        idx += [k for k in range(batch.n_blocks) if batch.kinds[k] == kind][:sample_blocks // 3]
+    idx.sort()
+    blocks = [batch.block(k) for k in idx]
+    data = np.concatenate(blocks)
+    offs = np.zeros(len(blocks) + 1, np.uint64)
+    offs[1:] = np.cumsum([b.size for b in blocks])
+    t0 = time.perf_counter()
+    z = cref.compress(data, offs, level=9, threads=threads)
+    dt = time.perf_counter() - t0
+    return data, offs, z, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--per-block-passes", type=int, default=1)
+    ap.add_argument("--cpu-sample-blocks", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--total", type=int, default=64 << 20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1109_2348_amd as bz
+    from paper_1109_2348_amd import native
+    from paper_1109_2348_amd import workloads as W
+
+    log("generating workload")
+    batch = W.config2(total=args.total)
+    n_in = int(batch.data.size)
+    x = torch.from_numpy(batch.data).cuda()
+    comp = bz.Compressor()
+    stream = torch.cuda.current_stream()
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        comp(x, batch.offsets, level=9)
+    torch.cuda.synchronize()
+
+    prof = native.Profile()
+    prof.enable(comp.ctx)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        z = comp(x, batch.offsets, level=9)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof.disable(comp.ctx)
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    out_bytes = int(z.numel())
+    value = args.steps * n_in / wall / 1e6
+    kern = prof.read(comp.ctx)
+
+    # per-block form: the same kernels, one call per block, one stream
+    log("per-block form")
+    nb = batch.n_blocks
+    pb_times = []
+    for _ in range(args.per_block_passes):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(nb):
+            a, e = int(batch.offsets[k]), int(batch.offsets[k + 1])
+            comp(x[a:e], [0, e - a], level=9)
+        torch.cuda.synchronize()
+        pb_times.append(time.perf_counter() - t1)
+    pb_value = n_in / min(pb_times) / 1e6
+
+    # dominant kernel and its roofline
+    roof = None
+    if kern:
+        name, rec = max(kern.items(), key=lambda kv: kv[1]["ms"])
+        avg_ms = rec["ms"] / max(rec["launches"], 1)
+        bytes_per_launch = rec["bytes"] / max(rec["launches"], 1)
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": rec["launches"] / args.steps,
+                "share_of_step": round(rec["ms"] / step_ms.sum(), 3)}
+
+    cpu = None
+    if not args.no_cpu:
+        threads = len(os.sched_getaffinity(0))
+        log(f"cpu baseline on {threads} threads")
+        data, offs, zref, dt = cpu_baseline(batch, args.cpu_sample_blocks, threads)
+        xs = torch.from_numpy(data).cuda()
+        zg = bz.compress(xs, offs, level=9).cpu().numpy().tobytes()
+        if zg != zref:
+            log("ERROR: GPU stream differs from the oracle on the CPU-baseline sample")
+            sys.exit(1)
+        cpu = {"value": round(data.size / dt / 1e6, 3), "unit": "MB/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(offs) - 1} of the {nb} blocks ({data.size} B, equal thirds uniform/text/sparse), "
+                         f"oracle compress with one thread per block; GPU stream on the sample bit-identical"}
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": batch.name, "input_bytes": n_in, "blocks": nb, "level": 9,
+                   "output_bytes": out_bytes, "ratio": round(out_bytes / n_in, 4)},
+        "p50_ms": round(float(np.percentile(step_ms, 50)), 3), "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
+        "per_block": {"value": round(pb_value, 2), "unit": "MB/s", "calls": nb},
+        "roofline": roof, "cpu_baseline": cpu,
+        "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches": v["launches"] // args.steps}
+                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

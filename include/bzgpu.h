@@ -137,6 +137,19 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
 int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level,
                     uint8_t* d_out, uint64_t out_cap, uint64_t* h_out_bytes, uint32_t* h_n_blocks, void* stream);
 
+/*
+ * Diagnostics: per-kernel timing.  While enabled, every instrumented launch
+ * is bracketed by HIP events on its stream; after each call the elapsed times
+ * are added up per kernel together with the launch's algorithmic bytes (the
+ * array traffic the method needs, not what the hardware moved).
+ * bzg_profile(ctx, 1) clears the totals and enables, bzg_profile(ctx, 0)
+ * disables.  bzg_profile_read writes one line per kernel,
+ * "name launches total_ms total_bytes", NUL-terminated, into buf (cap bytes);
+ * BZG_ECAPACITY if it does not fit.
+ */
+int bzg_profile(bzg_ctx* ctx, int enable);
+int bzg_profile_read(bzg_ctx* ctx, char* buf, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -187,6 +187,7 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
     wg_base[1] = t_small ? atomicAdd(&a.cnt->small_total, t_small) : 0u;
     wg_base[2] = t_tiles ? atomicAdd(&a.cnt->big_tiles, t_tiles) : 0u;
     if (t_act) atomicAdd(&a.cnt->active, t_act);
+    if (t_act > t_small) atomicAdd(&a.cnt->big_active, t_act - t_small);
   }
   __syncthreads();
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
@@ -555,12 +556,19 @@ size_t bwt_workspace_bytes(uint32_t N, uint32_t nb) {
 }
 
 static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, int passes,
-                               uint32_t** kin, uint32_t** vin, hipStream_t st) {
+                               double elems, uint32_t** kin, uint32_t** vin, hipStream_t st) {
   uint32_t *ka = w.key, *va = w.SA, *kb = w.tmpK, *vb = w.tmpV;
   for (int p = 0; p < passes; p++) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist);
-    hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
-    if (e != hipSuccess) return e;
+    {
+      ProfScope ps("radix_hist", st, 4.0 * elems);  // read the key
+      hipLaunchKernelGGL(k_radix_hist, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist);
+    }
+    {
+      ProfScope ps("scan", st, 8.0 * big_tiles * 256);
+      hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
+      if (e != hipSuccess) return e;
+    }
+    ProfScope ps("radix_scatter", st, 16.0 * elems);  // read and write key and value
     hipLaunchKernelGGL(k_radix_scatter, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
                        w.hist);
     std::swap(ka, kb);
@@ -617,13 +625,18 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
   uint32_t max_n = 0;
   for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
-  hipLaunchKernelGGL(k_sa_init, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, w.d_off, nb, N, w.SA, w.key);
+  {
+    ProfScope ps("sa_init", st, 9.0 * N);  // read the text, write row and key
+    hipLaunchKernelGGL(k_sa_init, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, w.d_off, nb, N, w.SA, w.key);
+  }
   // initial segments: every block of two or more rows, as a large segment
   std::vector<SegRec> segs0;
   std::vector<uint32_t> owner0;
+  double init_elems = 0;
   for (uint32_t b = 0; b < nb; b++) {
     uint32_t n = h_off[b + 1] - h_off[b];
     if (n < 2) continue;
+    init_elems += n;
     SegRec r{h_off[b], n, b, (uint32_t)owner0.size()};
     for (uint32_t t = 0; t < (n + RADIX_TILE - 1) / RADIX_TILE; t++) owner0.push_back((uint32_t)segs0.size());
     segs0.push_back(r);
@@ -634,11 +647,17 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     BZG_TRY(hipMemcpyAsync(w.owner[0], owner0.data(), owner0.size() * 4, hipMemcpyHostToDevice, st));
     uint32_t big_tiles = (uint32_t)owner0.size();
     uint32_t *kin, *vin;
-    BZG_TRY(radix_passes(w, big_tiles, w.segs[0], w.owner[0], 4, &kin, &vin, st));
+    BZG_TRY(radix_passes(w, big_tiles, w.segs[0], w.owner[0], 4, init_elems, &kin, &vin, st));
     AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1]};
-    hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, w.agg);
-    hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, vin, w.agg, w.d_off,
-                       w.SA, w.rank, 4u, app);
+    {
+      ProfScope ps("rename_a", st, 4.0 * init_elems);
+      hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, w.agg);
+    }
+    {
+      ProfScope ps("rename_b", st, 16.0 * init_elems);
+      hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, vin, w.agg,
+                         w.d_off, w.SA, w.rank, 4u, app);
+    }
     BZG_TRY(hipGetLastError());
     int cur = 1;
     uint32_t h = 4;
@@ -658,15 +677,25 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       const int nxt = cur ^ 1;
       BZG_TRY(hipMemsetAsync(&w.cnt[nxt], 0, sizeof(RoundCounters), st));
       const uint32_t nsmall = (c.small_total + SMALL_T - 1) / SMALL_T;
-      hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.head[cur],
-                         w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank, h, w.key);
+      {
+        ProfScope ps("gather", st, 12.0 * c.active);  // row, partner rank, key2
+        hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.head[cur],
+                           w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank, h, w.key);
+      }
       AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[nxt]};
-      if (nsmall)
+      if (nsmall) {
+        ProfScope ps("small_sort", st, 16.0 * c.small_total);  // key2 and row in, row and rank out
         hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
                            w.d_off, w.key, w.SA, w.rank, 2 * h, app2);
+      }
       if (c.big_tiles) {
-        BZG_TRY(radix_passes(w, c.big_tiles, w.segs[cur], w.owner[cur], passes, &kin, &vin, st));
-        hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
+        const double be = c.big_active;
+        BZG_TRY(radix_passes(w, c.big_tiles, w.segs[cur], w.owner[cur], passes, be, &kin, &vin, st));
+        {
+          ProfScope ps("rename_a", st, 4.0 * be);
+          hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
+        }
+        ProfScope ps("rename_b", st, 16.0 * be);
         hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
                            w.agg, w.d_off, w.SA, w.rank, 2 * h, app2);
       }
@@ -682,6 +711,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
 
 hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, uint32_t N, const uint32_t* SA,
                       uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
+  ProfScope ps("bwt_out", st, 6.0 * N);  // row in, byte gathered, byte out
   if (N) hipLaunchKernelGGL(k_bwt_out, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, d_off, nb, N, SA, L, primary,
                             sa_local);
   return hipGetLastError();

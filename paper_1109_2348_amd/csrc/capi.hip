@@ -41,10 +41,46 @@ hipError_t tables_export(uint32_t, const void*, uint8_t*, hipStream_t);
 hipError_t body_sizes(uint32_t, const void*, const uint64_t*, uint64_t*, uint32_t*, hipStream_t);
 }  // namespace bzg
 
+namespace bzg {
+
+thread_local Profiler* g_prof = nullptr;
+
+ProfScope::ProfScope(const char* name, hipStream_t s, double bytes) : st(s) {
+  if (g_prof && g_prof->on) {
+    Profiler::Pending p{name, nullptr, nullptr, bytes};
+    if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return;
+    (void)hipEventRecord(p.a, s);
+    g_prof->pending.push_back(p);
+    live = true;
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (live) (void)hipEventRecord(g_prof->pending.back().b, st);
+}
+
+void Profiler::collect() {
+  for (auto& p : pending) {
+    float ms = 0;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ProfRec& r = acc[p.name];
+      r.ms += ms;
+      r.bytes += p.bytes;
+      r.launches++;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  pending.clear();
+}
+
+}  // namespace bzg
+
 using namespace bzg;
 
 struct bzg_ctx {
   int device = 0;
+  Profiler prof;
   std::string err;
   void* ws[2] = {nullptr, nullptr};
   size_t ws_cap[2] = {0, 0};
@@ -152,6 +188,16 @@ size_t sz(size_t n) {
   return ((n * sizeof(T)) + 255) & ~size_t(255);
 }
 
+// Routes instrumented launches of one API call to the context's profiler.
+struct ProfGuard {
+  bzg_ctx* c;
+  explicit ProfGuard(bzg_ctx* x) : c(x) { g_prof = &c->prof; }
+  ~ProfGuard() {
+    if (c->prof.on) c->prof.collect();
+    g_prof = nullptr;
+  }
+};
+
 bool offsets_ok(const uint64_t* h, uint32_t nb) {
   for (uint32_t k = 0; k < nb; k++)
     if (h[k + 1] < h[k]) return false;
@@ -196,6 +242,27 @@ void bzg_destroy(bzg_ctx* ctx) {
 
 const char* bzg_last_error(const bzg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int bzg_profile(bzg_ctx* ctx, int enable) {
+  if (!ctx) return BZG_EINVAL;
+  if (enable) ctx->prof.acc.clear();
+  ctx->prof.on = enable != 0;
+  return 0;
+}
+
+int bzg_profile_read(bzg_ctx* ctx, char* buf, size_t cap) {
+  if (!ctx || !buf || cap == 0) return BZG_EINVAL;
+  std::string s;
+  char line[256];
+  for (auto& kv : ctx->prof.acc) {
+    snprintf(line, sizeof(line), "%s %llu %.6f %.1f\n", kv.first.c_str(), (unsigned long long)kv.second.launches,
+             kv.second.ms, kv.second.bytes);
+    s += line;
+  }
+  if (s.size() + 1 > cap) return fail(ctx, BZG_ECAPACITY, "profile text needs " + std::to_string(s.size() + 1));
+  memcpy(buf, s.c_str(), s.size() + 1);
+  return 0;
+}
+
 uint64_t bzg_compress_bound(uint64_t n_bytes, uint32_t n_blocks) {
   // every RLE1 byte becomes at most one 17-bit code (plus RUNA/RUNB digits,
   // which only replace zeros); generous per-block header allowance
@@ -209,6 +276,7 @@ int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offse
                       uint8_t* d_bwt, uint32_t* d_primary, uint32_t* d_sa, void* stream) {
   if (!ctx) return BZG_EINVAL;
   ctx->err.clear();
+  ProfGuard pg(ctx);
   if (!h_offsets || !d_bwt || !d_primary || (n_blocks && !d_in)) return fail(ctx, BZG_EINVAL, "null pointer");
   if (n_blocks == 0) return 0;
   if (!offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
@@ -242,6 +310,7 @@ int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* h_offse
                      uint16_t* d_syms, uint32_t* d_nsyms, uint8_t* d_inuse, void* stream) {
   if (!ctx) return BZG_EINVAL;
   ctx->err.clear();
+  ProfGuard pg(ctx);
   if (!h_offsets || !d_syms || !d_nsyms || !d_inuse || (n_blocks && !d_bwt)) return fail(ctx, BZG_EINVAL, "null pointer");
   if (n_blocks == 0) return 0;
   if (!offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
@@ -287,6 +356,7 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
                          const uint64_t* h_out_offsets, uint64_t* d_nbits, uint8_t* d_tables, void* stream) {
   if (!ctx) return BZG_EINVAL;
   ctx->err.clear();
+  ProfGuard pg(ctx);
   if (!h_sym_offsets || !h_out_offsets || !d_nbits || (n_blocks && (!d_syms || !d_nsyms || !d_inuse || !d_out)))
     return fail(ctx, BZG_EINVAL, "null pointer");
   if (n_blocks == 0) return 0;
@@ -369,6 +439,7 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
                     uint8_t* d_out, uint64_t out_cap, uint64_t* h_out_bytes, uint32_t* h_n_blocks, void* stream) {
   if (!ctx) return BZG_EINVAL;
   ctx->err.clear();
+  ProfGuard pg(ctx);
   if (!h_offsets || !d_out || !h_out_bytes || (n_blocks && !d_in)) return fail(ctx, BZG_EINVAL, "null pointer");
   if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
   if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
@@ -435,7 +506,10 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
     HIPX(hipMemcpyAsync(d_boff, boff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(d_tile_blk, tile_blk.data(), ntiles * 4, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(d_blk_tile0, blk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
-    HIPX(rle1_tiles(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + 256, d_rtiles, st));
+    {
+      ProfScope ps("rle1_tiles", st, (double)(boff[nb] - boff[0]));
+      HIPX(rle1_tiles(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + 256, d_rtiles, st));
+    }
     HIPX(rle1_blocks(nb, d_blk_tile0, d_boff, ctx->crc_tab + 256, d_rtiles, d_tile_out, d_rle_n, d_crc, st));
     uint32_t* h_rle = (uint32_t*)pin;
     HIPX(hipMemcpyAsync(h_rle, d_rle_n, nb * 4, hipMemcpyDeviceToHost, st));
@@ -521,7 +595,10 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
   void* d_stage = c0.take<char>(0);
   size_t stage_bytes = ctx->ws_cap[0] - c0.used;
   HIPX(hipMemcpyAsync(d_rbase, rbase.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
-  HIPX(rle1_emit(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, d_rtiles, d_tile_out, d_rbase, d_text, st));
+  {
+    ProfScope ps("rle1_emit", st, (double)total + N);
+    HIPX(rle1_emit(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, d_rtiles, d_tile_out, d_rbase, d_text, st));
+  }
   // ---- BWT
   uint32_t *SA, *d_off;
   int rounds = 0;
@@ -557,8 +634,11 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
   HIPX(hipMemsetAsync(d_out, 0, words * 4, st));
   if (nptiles) HIPX(hipMemcpyAsync(d_ptile_blk, ptile_blk.data(), nptiles * 4, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
-  HIPX(pack_run(nb, d_tabs, 0, d_blkbit, d_crc, d_primary, d_inuse, d_selb, d_sel, d_selmtf, d_gofs, nptiles,
-                d_ptile_blk, d_pblk_tile0, d_syms, d_sbase, d_nsyms, level, d_info, (uint32_t*)d_out, st));
+  {
+    ProfScope ps("pack", st, 2.0 * N + (double)bytes);  // symbols in, stream out
+    HIPX(pack_run(nb, d_tabs, 0, d_blkbit, d_crc, d_primary, d_inuse, d_selb, d_sel, d_selmtf, d_gofs, nptiles,
+                  d_ptile_blk, d_pblk_tile0, d_syms, d_sbase, d_nsyms, level, d_info, (uint32_t*)d_out, st));
+  }
   HIPX(hipStreamSynchronize(st));
   return 0;
 }

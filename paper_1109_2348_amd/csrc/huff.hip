@@ -290,6 +290,7 @@ hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base,
                     uint8_t* selmtf, uint64_t* gbits, void* tabs, uint32_t* err, hipStream_t st) {
   if (!nb) return hipSuccess;
   if (count_freq) hipLaunchKernelGGL(k_freq, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, err);
+  ProfScope ps("huffman", st, 0.0);  // symbol count is known on the device only
   hipLaunchKernelGGL(k_huff, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, inuse, sel_base, sel, selmtf,
                      gbits, (BlockTables*)tabs);
   return hipGetLastError();

@@ -4,10 +4,39 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
 namespace bzg {
+
+// Optional per-kernel timing: HIP events recorded on the launch stream around
+// each instrumented launch, with the launch's algorithmic bytes (the bytes the
+// method must move, not what the hardware moved).  Collected after the call's
+// final synchronisation.
+struct ProfRec {
+  double ms = 0, bytes = 0;
+  uint64_t launches = 0;
+};
+struct Profiler {
+  bool on = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Pending> pending;
+  std::map<std::string, ProfRec> acc;
+  void collect();
+};
+extern thread_local Profiler* g_prof;
+
+struct ProfScope {
+  hipStream_t st;
+  bool live = false;
+  ProfScope(const char* name, hipStream_t s, double bytes);
+  ~ProfScope();
+};
 
 // Tuning constants (fixed; every choice gives identical output).
 constexpr int NT = 256;                // threads per workgroup
@@ -36,7 +65,8 @@ struct RoundCounters {
   uint32_t big_tiles;    // radix tiles of large segments
   uint32_t active;       // elements in all segments
   uint32_t overflow;     // nonzero if a capacity was exceeded
-  uint32_t pad[3];
+  uint32_t big_active;   // elements in large segments
+  uint32_t pad[2];
 };
 
 struct Bump {

@@ -397,13 +397,26 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
     return e;
   if ((e = hipMemsetAsync(inuse, 0, (size_t)nb * 32, st)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(freq, 0, (size_t)nb * MAXA * 4, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_inuse, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse);
-  hipLaunchKernelGGL(k_mtf_state, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_D, d_nD,
-                     d_sum);
-  hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d_blk_chunk0, inuse, d_D, d_nD, d_sum, d_list,
-                     d_carry, d_out, nsyms);
-  hipLaunchKernelGGL(k_mtf_emit, dim3(nc), dim3(BZG_WAVE), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_list,
-                     d_carry, d_out, d_sym_base, syms, freq, err);
+  const double n = h_off[nb];
+  {
+    ProfScope ps("inuse", st, n);
+    hipLaunchKernelGGL(k_inuse, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse);
+  }
+  {
+    ProfScope ps("mtf_state", st, n + 256.0 * nc);
+    hipLaunchKernelGGL(k_mtf_state, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_D,
+                       d_nD, d_sum);
+  }
+  {
+    ProfScope ps("mtf_scan", st, 512.0 * nc);
+    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d_blk_chunk0, inuse, d_D, d_nD, d_sum, d_list,
+                       d_carry, d_out, nsyms);
+  }
+  {
+    ProfScope ps("mtf_emit", st, 3.0 * n);  // read L, write at most one 2-byte symbol per row
+    hipLaunchKernelGGL(k_mtf_emit, dim3(nc), dim3(BZG_WAVE), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse,
+                       d_list, d_carry, d_out, d_sym_base, syms, freq, err);
+  }
   return hipGetLastError();
 }
 

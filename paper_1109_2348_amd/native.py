@@ -52,12 +52,35 @@ def lib() -> C.CDLL:
         L.huffman_encode_batch.argtypes = [vp, vp, vp, vp, u64p, C.c_uint32, vp, u64p, vp, vp, vp]
         L.compress_blocks.restype = C.c_int
         L.compress_blocks.argtypes = [vp, vp, u64p, C.c_uint32, C.c_int, vp, C.c_uint64, u64p, u32p, vp]
+        L.bzg_profile.restype = C.c_int
+        L.bzg_profile.argtypes = [vp, C.c_int]
+        L.bzg_profile_read.restype = C.c_int
+        L.bzg_profile_read.argtypes = [vp, C.c_char_p, C.c_size_t]
         _lib = L
     return _lib
 
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_compress_bound", "bwt_forward_batch",
-           "mtf_encode_batch", "huffman_encode_batch", "compress_blocks")
+           "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "bzg_profile", "bzg_profile_read")
+
+
+class Profile:
+    """Per-kernel HIP-event timing inside the library (diagnostics)."""
+
+    def enable(self, ctx: "Context"):
+        ctx.check(lib().bzg_profile(ctx.h, 1))
+
+    def disable(self, ctx: "Context"):
+        ctx.check(lib().bzg_profile(ctx.h, 0))
+
+    def read(self, ctx: "Context") -> dict:
+        buf = C.create_string_buffer(1 << 16)
+        ctx.check(lib().bzg_profile_read(ctx.h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, launches, ms, nbytes = line.split()
+            out[name] = {"launches": int(launches), "ms": float(ms), "bytes": float(nbytes)}
+        return out
 
 
 class Context:
