@@ -105,7 +105,7 @@ def main():
             comp(x[a:e], [0, e - a], level=9)
         torch.cuda.synchronize()
         pb_times.append(time.perf_counter() - t1)
-    pb_value = n_in / min(pb_times) / 1e6
+    pb_value = n_in / min(pb_times) / 1e6 if pb_times else None
 
     # dominant kernel and its roofline
     roof = None
@@ -140,7 +140,7 @@ def main():
         "config": {"workload": batch.name, "input_bytes": n_in, "blocks": nb, "level": 9,
                    "output_bytes": out_bytes, "ratio": round(out_bytes / n_in, 4)},
         "p50_ms": round(float(np.percentile(step_ms, 50)), 3), "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
-        "per_block": {"value": round(pb_value, 2), "unit": "MB/s", "calls": nb},
+        "per_block": {"value": round(pb_value, 2) if pb_value else None, "unit": "MB/s", "calls": nb},
         "roofline": roof, "cpu_baseline": cpu,
         "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches": v["launches"] // args.steps}
                     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},

@@ -30,7 +30,10 @@ hipError_t mtf_run(const uint8_t*, const uint32_t*, const std::vector<uint32_t>&
                    const uint64_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*, hipStream_t, std::string&);
 size_t block_tables_bytes();
 hipError_t huff_run(uint32_t, const uint16_t*, const uint64_t*, const uint32_t*, uint32_t*, bool, const uint32_t*,
-                    const uint64_t*, uint8_t*, uint8_t*, uint64_t*, void*, uint32_t*, hipStream_t);
+                    const uint64_t*, uint8_t*, uint8_t*, uint64_t*, void*, uint32_t*, uint32_t, const uint32_t*,
+                    const uint32_t*, void*, hipStream_t);
+size_t huff_workspace_bytes(uint32_t nb);
+uint32_t huff_assign_groups();
 hipError_t pack_layout(uint32_t, const void*, int, const uint64_t*, uint64_t*, const uint32_t*, uint64_t*,
                        hipStream_t);
 hipError_t pack_run(uint32_t, const void*, int, const uint64_t*, const uint32_t*, const uint32_t*, const uint32_t*,
@@ -197,6 +200,20 @@ struct ProfGuard {
     g_prof = nullptr;
   }
 };
+
+// Tiles of `per` selector groups per block, from the per-block group
+// capacities selb[b+1]-selb[b].
+void group_tiles(const std::vector<uint64_t>& selb, uint32_t nb, uint32_t per, std::vector<uint32_t>& tile_blk,
+                 std::vector<uint32_t>& blk_tile0) {
+  tile_blk.clear();
+  blk_tile0.assign(nb + 1, 0);
+  for (uint32_t b = 0; b < nb; b++) {
+    blk_tile0[b] = (uint32_t)tile_blk.size();
+    uint64_t g = selb[b + 1] - selb[b];
+    for (uint64_t q = 0; q < (g + per - 1) / per; q++) tile_blk.push_back(b);
+  }
+  blk_tile0[nb] = (uint32_t)tile_blk.size();
+}
 
 bool offsets_ok(const uint64_t* h, uint32_t nb) {
   for (uint32_t k = 0; k < nb; k++)
@@ -377,18 +394,15 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   }
   selb[n_blocks] = ng;
   for (uint32_t k = 0; k <= n_blocks; k++) obyte[k] = h_out_offsets[k];
-  std::vector<uint32_t> tile_blk, blk_tile0(n_blocks + 1);
-  for (uint32_t k = 0; k < n_blocks; k++) {
-    blk_tile0[k] = (uint32_t)tile_blk.size();
-    uint64_t g = selb[k + 1] - selb[k];
-    for (uint64_t q = 0; q < (g + PACK_GROUPS - 1) / PACK_GROUPS; q++) tile_blk.push_back(k);
-  }
-  blk_tile0[n_blocks] = (uint32_t)tile_blk.size();
-  const uint32_t ntiles = (uint32_t)tile_blk.size();
+  std::vector<uint32_t> tile_blk, blk_tile0, atile_blk, ablk_tile0;
+  group_tiles(selb, n_blocks, PACK_GROUPS, tile_blk, blk_tile0);
+  group_tiles(selb, n_blocks, huff_assign_groups(), atile_blk, ablk_tile0);
+  const uint32_t ntiles = (uint32_t)tile_blk.size(), natiles = (uint32_t)atile_blk.size();
   size_t need = sz<uint64_t>(n_blocks) * 2 + sz<uint64_t>(n_blocks + 1) * 2 + sz<uint32_t>((size_t)n_blocks * MAXA) +
                 sz<uint8_t>(ng + 1) * 2 + sz<uint64_t>(ng + 1) * 2 + sz<uint64_t>(scan_tmp_elems(ng + 1)) +
-                block_tables_bytes() * n_blocks + 256 + sz<uint32_t>(ntiles + 1) + sz<uint32_t>(n_blocks + 1) +
-                sz<uint64_t>(4) + sz<uint32_t>(4) + 8192;
+                block_tables_bytes() * n_blocks + 256 + sz<uint32_t>(ntiles + 1) + sz<uint32_t>(natiles + 1) +
+                2 * sz<uint32_t>(n_blocks + 1) + sz<uint64_t>(4) + sz<uint32_t>(4) + huff_workspace_bytes(n_blocks) +
+                8192;
   void* ws;
   int rc = ensure_ws(ctx, 1, need, &ws);
   if (rc) return rc;
@@ -408,17 +422,22 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   void* d_tabs = cv.take<char>(block_tables_bytes() * n_blocks);
   uint32_t* d_tile_blk = cv.take<uint32_t>(ntiles + 1);
   uint32_t* d_blk_tile0 = cv.take<uint32_t>(n_blocks + 1);
+  uint32_t* d_atile_blk = cv.take<uint32_t>(natiles + 1);
+  uint32_t* d_ablk_tile0 = cv.take<uint32_t>(n_blocks + 1);
   uint64_t* d_info = cv.take<uint64_t>(4);
   uint32_t* d_err = cv.take<uint32_t>(4);
+  void* d_hws = cv.take<char>(huff_workspace_bytes(n_blocks));
   HIPX(hipMemcpyAsync(d_sbase, sbase.data(), n_blocks * 8, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_selb, selb.data(), (n_blocks + 1) * 8, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_obyte, obyte.data(), (n_blocks + 1) * 8, hipMemcpyHostToDevice, st));
   if (ntiles) HIPX(hipMemcpyAsync(d_tile_blk, tile_blk.data(), ntiles * 4, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4, hipMemcpyHostToDevice, st));
+  if (natiles) HIPX(hipMemcpyAsync(d_atile_blk, atile_blk.data(), natiles * 4, hipMemcpyHostToDevice, st));
+  HIPX(hipMemcpyAsync(d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4, hipMemcpyHostToDevice, st));
   HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
   HIPX(huff_run(n_blocks, d_syms, d_sbase, d_nsyms, d_freq, true, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
-                d_gbits, d_tabs, d_err, st));
+                d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
   HIPX(body_sizes(n_blocks, d_tabs, d_obyte, d_nbits, d_err, st));
   HIPX(pack_layout(n_blocks, d_tabs, 1, d_obyte, d_blkbit, nullptr, d_info, st));
@@ -553,20 +572,17 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
     ng += ((uint64_t)rle_n[b] + 1 + GROUP - 1) / GROUP;
   }
   selb[nb] = ng;
-  std::vector<uint32_t> ptile_blk, pblk_tile0(nb + 1);
-  for (uint32_t b = 0; b < nb; b++) {
-    pblk_tile0[b] = (uint32_t)ptile_blk.size();
-    uint64_t g = selb[b + 1] - selb[b];
-    for (uint64_t q = 0; q < (g + PACK_GROUPS - 1) / PACK_GROUPS; q++) ptile_blk.push_back(b);
-  }
-  pblk_tile0[nb] = (uint32_t)ptile_blk.size();
-  const uint32_t nptiles = (uint32_t)ptile_blk.size();
+  std::vector<uint32_t> ptile_blk, pblk_tile0, atile_blk, ablk_tile0;
+  group_tiles(selb, nb, PACK_GROUPS, ptile_blk, pblk_tile0);
+  group_tiles(selb, nb, huff_assign_groups(), atile_blk, ablk_tile0);
+  const uint32_t nptiles = (uint32_t)ptile_blk.size(), natiles = (uint32_t)atile_blk.size();
   size_t bwt_ws = bwt_workspace_bytes(N, nb);
   size_t need0 = sz<uint8_t>(N + 64) * 2 + sz<uint32_t>(nb) + sz<uint16_t>((size_t)N + nb + 64) + sz<uint64_t>(nb) +
                  sz<uint32_t>(nb) + sz<uint32_t>((size_t)nb * 8) + sz<uint32_t>((size_t)nb * MAXA) + sz<uint32_t>(4) +
                  sz<uint64_t>(nb + 1) + sz<uint8_t>(ng + 1) * 2 + sz<uint64_t>(ng + 1) * 2 +
                  sz<uint64_t>(scan_tmp_elems(ng + 1)) + block_tables_bytes() * nb + 256 + sz<uint64_t>(nb) +
                  sz<uint32_t>(nptiles + 1) + sz<uint32_t>(nb + 1) + sz<uint64_t>(4) + sz<uint32_t>(nb + 1) +
+                 sz<uint32_t>(natiles + 1) + sz<uint32_t>(nb + 1) + huff_workspace_bytes(nb) +
                  std::max(bwt_ws, mtf_workspace_bytes(roff)) + 16384;
   void* ws0;
   if ((rc = ensure_ws(ctx, 0, need0, &ws0))) return rc;
@@ -592,6 +608,9 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
   uint32_t* d_pblk_tile0 = c0.take<uint32_t>(nb + 1);
   uint64_t* d_info = c0.take<uint64_t>(4);
   uint32_t* d_roff = c0.take<uint32_t>(nb + 1);
+  uint32_t* d_atile_blk = c0.take<uint32_t>(natiles + 1);
+  uint32_t* d_ablk_tile0 = c0.take<uint32_t>(nb + 1);
+  void* d_hws = c0.take<char>(huff_workspace_bytes(nb));
   void* d_stage = c0.take<char>(0);
   size_t stage_bytes = ctx->ws_cap[0] - c0.used;
   HIPX(hipMemcpyAsync(d_rbase, rbase.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
@@ -614,8 +633,10 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
   // ---- Huffman tables, layout
   HIPX(hipMemcpyAsync(d_selb, selb.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
   HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
+  if (natiles) HIPX(hipMemcpyAsync(d_atile_blk, atile_blk.data(), natiles * 4, hipMemcpyHostToDevice, st));
+  HIPX(hipMemcpyAsync(d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
   HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,
-                st));
+                natiles, d_atile_blk, d_ablk_tile0, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
   HIPX(pack_layout(nb, d_tabs, 0, nullptr, d_blkbit, d_crc, d_info, st));
   uint64_t* h_info = (uint64_t*)pin;

@@ -1,22 +1,24 @@
 // Huffman code tables per block (Sec. 3.4: Huffman coding; Sec. 4: tables
 // chosen by analysing the data).  The paper gives no GPU tree construction
-// and deems one unlikely; here each block gets one workgroup:
+// and deems one unlikely; the table choice is spread over kernels instead:
 //
-//  * table count G from the symbol count, an equal-frequency partition of the
-//    alphabet as the starting tables (cost 0 inside a table's range, 15
-//    outside);
-//  * four refinement passes: every 50-symbol group picks the table with the
-//    least total code length (lowest index on ties), the groups' symbols are
-//    counted per table, and each table is rebuilt from its counts;
-//  * a table build is textbook Huffman on (weight, id) keys with weights
-//    floored at 1: one wave ranks the leaves, one lane runs the two-queue
-//    merge (leaves in key order, internal nodes in creation order -- their
-//    weights never decrease, so each queue head is its queue's minimum),
-//    every lane walks its leaves to the root; lengths over 17 halve the
-//    weights (w -> 1 + w/2) and rebuild;
-//  * canonical codes in (length, symbol) order; the selectors' MTF indices
-//    (list 0..G-1) from a prefix-max of each table's last use; header and
-//    per-group data bit counts for the packer.
+//  setup   table count G from the symbol count; an equal-frequency partition
+//          of the alphabet gives the starting tables (cost 0 inside a table's
+//          range, 15 outside).
+//  assign  (tile-parallel, many workgroups per block) every 50-symbol group
+//          picks the table with the least total code length, lowest index on
+//          ties, and its symbols are counted for that table.  Costs come from
+//          one 64-bit word per symbol holding six 10-bit lengths, so a group's
+//          six costs are one sum of 50 words.
+//  build   (one wave per table) textbook Huffman on (weight, id) keys with
+//          weights floored at 1: the wave ranks the leaves, one lane runs the
+//          two-queue merge (leaves in key order, internal nodes in creation
+//          order -- their weights never decrease, so each queue head is its
+//          queue's minimum), every lane walks its leaves to the root; lengths
+//          over 17 halve the weights (w -> 1 + w/2) and rebuild.
+//  assign and build run four times; then per-group data bits under the final
+//  tables, canonical codes in (length, symbol) order, and the selectors' MTF
+//  indices (list 0..G-1) from a prefix-max of each table's last use.
 #include <climits>
 
 #include "common.hpp"
@@ -30,6 +32,10 @@ struct BlockTables {
   uint8_t len[MAXG][MAXA];
   uint32_t code[MAXG][MAXA];
 };
+
+constexpr uint32_t ASSIGN_GROUPS = 512;      // selector groups per assign tile
+constexpr uint32_t ASSIGN_SUB = NT;          // groups staged in LDS at a time
+constexpr uint32_t ASSIGN_SYMS = ASSIGN_SUB * GROUP;
 
 struct HuffScratch {
   uint32_t w[MAXA];
@@ -103,32 +109,28 @@ __device__ __forceinline__ int n_tables(uint32_t ns, int a) {
   return g < a ? g : a;
 }
 
-__global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, const uint64_t* __restrict__ sym_base,
-                                             const uint32_t* __restrict__ nsyms, const uint32_t* __restrict__ freq,
-                                             const uint32_t* __restrict__ inuse, const uint64_t* __restrict__ sel_base,
-                                             uint8_t* __restrict__ sel, uint8_t* __restrict__ selmtf,
-                                             uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs) {
-  __shared__ uint32_t tf[MAXG][MAXA];
-  __shared__ uint8_t lens[MAXG][MAXA];
-  __shared__ uint64_t cost[MAXA];
-  __shared__ HuffScratch hs[NT / BZG_WAVE];
-  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  __shared__ int shi[NT / BZG_WAVE + 1];
-  __shared__ int sx[NT];
-  __shared__ uint32_t s_first[MAXG][MAXLEN + 2];
+__device__ __forceinline__ uint64_t pack_costs(const BlockTables* T, int G, int v) {
+  uint64_t c = 0;
+  for (int t = 0; t < G; t++) c |= (uint64_t)T->len[t][v] << (10 * t);
+  return c;
+}
+
+// Per block: sizes, the starting tables, cleared counters.
+__global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ nsyms, const uint32_t* __restrict__ freq,
+                                                   const uint32_t* __restrict__ inuse, BlockTables* __restrict__ tabs,
+                                                   uint64_t* __restrict__ cost, uint32_t* __restrict__ tf) {
   const uint32_t b = blockIdx.x;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t w = tid / BZG_WAVE;
+  BlockTables* T = &tabs[b];
   uint32_t nu = 0;
   for (int j = 0; j < 8; j++) nu += __popc(inuse[b * 8 + j]);
   const int a = (int)nu + 2;
   const uint32_t ns = nsyms[b];
-  const uint32_t nsel = (ns + GROUP - 1) / GROUP;
   const int G = n_tables(ns, a);
-  const uint16_t* S = syms + sym_base[b];
-  const uint64_t sb = sel_base[b];
-  // starting tables: equal-frequency partition of the alphabet
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
+    T->G = (uint32_t)G;
+    T->nsel = (ns + GROUP - 1) / GROUP;
+    T->alpha = (uint32_t)a;
+    T->data_bits = 0;
     uint64_t rem = ns;
     int gs = 0;
     for (int t = 0; t < G; t++) {
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, 
       uint64_t part = 0;
       for (int v = 0; v < a; v++) {
         bool in = v >= gs && v <= ge;
-        lens[t][v] = in ? 0 : 15;
+        T->len[t][v] = in ? 0 : 15;
         if (in) part += freq[(size_t)b * MAXA + v];
       }
       rem -= part;
@@ -153,34 +155,140 @@ __global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, 
     }
   }
   __syncthreads();
-  for (int it = 0; it < 4; it++) {
-    for (int v = tid; v < a; v += NT) {
-      uint64_t c = 0;
-      for (int t = 0; t < G; t++) c |= (uint64_t)lens[t][v] << (10 * t);
-      cost[v] = c;
+  for (int v = threadIdx.x; v < a; v += NT) cost[(size_t)b * MAXA + v] = pack_costs(T, G, v);
+  for (int i = threadIdx.x; i < MAXG * MAXA; i += NT) tf[(size_t)b * MAXG * MAXA + i] = 0;
+}
+
+// Tile of ASSIGN_GROUPS groups of one block.  mode 0: choose tables and count
+// symbols per table; mode 1: data bits of every group under the final tables.
+__global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __restrict__ tile_blk,
+                                                    const uint32_t* __restrict__ blk_tile0,
+                                                    const uint16_t* __restrict__ syms,
+                                                    const uint64_t* __restrict__ sym_base,
+                                                    const uint32_t* __restrict__ nsyms,
+                                                    const uint64_t* __restrict__ sel_base, uint8_t* __restrict__ sel,
+                                                    const uint64_t* __restrict__ cost, uint32_t* __restrict__ tf,
+                                                    uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs) {
+  __shared__ uint16_t st[ASSIGN_SYMS];
+  __shared__ uint64_t sc[MAXA];
+  __shared__ uint32_t stf[MAXG][MAXA];
+  __shared__ uint8_t slen[MAXG][MAXA];
+  __shared__ uint64_t sh[NT / BZG_WAVE + 1];
+  const uint32_t j = blockIdx.x;
+  const uint32_t b = tile_blk[j];
+  BlockTables* T = &tabs[b];
+  const uint32_t nsel = T->nsel, G = T->G, a = T->alpha;
+  const uint32_t g0 = (j - blk_tile0[b]) * ASSIGN_GROUPS;
+  if (g0 >= nsel) return;
+  const uint32_t g1 = min(g0 + ASSIGN_GROUPS, nsel);
+  const uint32_t ns = nsyms[b];
+  const uint16_t* S = syms + sym_base[b];
+  const uint64_t sb = sel_base[b];
+  if (mode == 0) {
+    for (uint32_t v = threadIdx.x; v < a; v += NT) sc[v] = cost[(size_t)b * MAXA + v];
+    for (uint32_t i = threadIdx.x; i < MAXG * MAXA; i += NT) (&stf[0][0])[i] = 0;
+  } else {
+    for (uint32_t i = threadIdx.x; i < G * MAXA; i += NT) {
+      uint32_t t = i / MAXA, v = i % MAXA;
+      if (v < a) slen[t][v] = T->len[t][v];
     }
-    for (int i = tid; i < MAXG * MAXA; i += NT) (&tf[0][0])[i] = 0;
-    __syncthreads();
-    for (uint32_t g = tid; g < nsel; g += NT) {
-      uint32_t lo = g * GROUP, hi = min(lo + GROUP, ns);
-      uint64_t acc = 0;
-      for (uint32_t i = lo; i < hi; i++) acc += cost[S[i]];
-      uint32_t best = 0, bc = (uint32_t)(acc & 1023u);
-      for (int t = 1; t < G; t++) {
-        uint32_t c = (uint32_t)((acc >> (10 * t)) & 1023u);
-        if (c < bc) {
-          bc = c;
-          best = (uint32_t)t;
-        }
-      }
-      sel[sb + g] = (uint8_t)best;
-      for (uint32_t i = lo; i < hi; i++) atomicAdd(&tf[best][S[i]], 1u);
-    }
-    __syncthreads();
-    for (int t = (int)w; t < G; t += NT / BZG_WAVE) huff_lengths_wave(tf[t], a, lens[t], &hs[w]);
-    __syncthreads();
   }
-  // canonical codes
+  uint64_t bits = 0;
+  for (uint32_t gs = g0; gs < g1; gs += ASSIGN_SUB) {
+    const uint32_t ge = min(gs + ASSIGN_SUB, g1);
+    const uint32_t s0 = gs * GROUP, s1 = min(ge * GROUP, ns);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < s1 - s0; i += NT) st[i] = S[s0 + i];
+    __syncthreads();
+    const uint32_t g = gs + threadIdx.x;
+    if (g < ge) {
+      const uint32_t lo = g * GROUP - s0, hi = min(g * GROUP + GROUP, ns) - s0;
+      if (mode == 0) {
+        uint64_t acc = 0;
+        for (uint32_t i = lo; i < hi; i++) acc += sc[st[i]];
+        uint32_t best = 0, bc = (uint32_t)(acc & 1023u);
+        for (uint32_t t = 1; t < G; t++) {
+          uint32_t c = (uint32_t)((acc >> (10 * t)) & 1023u);
+          if (c < bc) {
+            bc = c;
+            best = t;
+          }
+        }
+        sel[sb + g] = (uint8_t)best;
+        for (uint32_t i = lo; i < hi; i++) atomicAdd(&stf[best][st[i]], 1u);
+      } else {
+        const uint32_t t = sel[sb + g];
+        uint32_t acc = 0;
+        for (uint32_t i = lo; i < hi; i++) acc += slen[t][st[i]];
+        gbits[sb + g] = acc;
+        bits += acc;
+      }
+    }
+  }
+  __syncthreads();
+  if (mode == 0) {
+    for (uint32_t i = threadIdx.x; i < G * MAXA; i += NT) {
+      uint32_t t = i / MAXA, v = i % MAXA;
+      if (v < a && stf[t][v]) atomicAdd(&tf[((size_t)b * MAXG + t) * MAXA + v], stf[t][v]);
+    }
+  } else {
+    uint64_t tot = block_sum<uint64_t, NT>(bits, sh);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&T->data_bits, (unsigned long long)tot);
+  }
+}
+
+// Per block, one wave per table: new lengths from the counts; packed costs;
+// counters cleared for the next pass.
+constexpr int BUILD_NT = MAXG * BZG_WAVE;
+
+__global__ __launch_bounds__(BUILD_NT) void k_huff_build(BlockTables* __restrict__ tabs, uint64_t* __restrict__ cost,
+                                                         uint32_t* __restrict__ tf) {
+  __shared__ uint32_t sf[MAXG][MAXA];
+  __shared__ uint8_t sl[MAXG][MAXA];
+  __shared__ HuffScratch hs[MAXG];
+  const uint32_t b = blockIdx.x;
+  BlockTables* T = &tabs[b];
+  const int G = (int)T->G, a = (int)T->alpha;
+  uint32_t* F = tf + (size_t)b * MAXG * MAXA;
+  for (int i = threadIdx.x; i < MAXG * MAXA; i += BUILD_NT) {
+    (&sf[0][0])[i] = F[i];
+    F[i] = 0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x / BZG_WAVE;
+  if (w < G) {
+    huff_lengths_wave(sf[w], a, sl[w], &hs[w]);
+    for (int v = lane(); v < a; v += BZG_WAVE) T->len[w][v] = sl[w][v];
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < a; v += BUILD_NT) {
+    uint64_t c = 0;
+    for (int t = 0; t < G; t++) c |= (uint64_t)sl[t][v] << (10 * t);
+    cost[(size_t)b * MAXA + v] = c;
+  }
+}
+
+// Per block: canonical codes, selector MTF indices and header bit count.
+__global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__ inuse,
+                                                    const uint64_t* __restrict__ sel_base,
+                                                    const uint8_t* __restrict__ sel, uint8_t* __restrict__ selmtf,
+                                                    BlockTables* __restrict__ tabs) {
+  __shared__ uint8_t lens[MAXG][MAXA];
+  __shared__ uint32_t s_first[MAXG][MAXLEN + 2];
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ int shi[NT / BZG_WAVE + 1];
+  __shared__ int sx[NT];
+  const uint32_t b = blockIdx.x;
+  const uint32_t tid = threadIdx.x;
+  BlockTables* T = &tabs[b];
+  const int G = (int)T->G, a = (int)T->alpha;
+  const uint32_t nsel = T->nsel;
+  const uint64_t sb = sel_base[b];
+  for (int i = tid; i < G * MAXA; i += NT) {
+    int t = i / MAXA, v = i % MAXA;
+    if (v < a) lens[t][v] = T->len[t][v];
+  }
+  __syncthreads();
   if (tid < (uint32_t)G) {
     uint32_t cnt[MAXLEN + 2];
     for (int q = 0; q <= MAXLEN + 1; q++) cnt[q] = 0;
@@ -192,26 +300,14 @@ __global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, 
     }
   }
   __syncthreads();
-  BlockTables* T = &tabs[b];
   for (int i = tid; i < G * MAXA; i += NT) {
     int t = i / MAXA, v = i % MAXA;
     if (v < a) {
       uint8_t L = lens[t][v];
       uint32_t r = 0;
       for (int u = 0; u < v; u++) r += (lens[t][u] == L) ? 1u : 0u;
-      T->len[t][v] = L;
       T->code[t][v] = s_first[t][L] + r;
     }
-  }
-  // data bits per group under the final tables
-  uint64_t dbits = 0;
-  for (uint32_t g = tid; g < nsel; g += NT) {
-    uint32_t lo = g * GROUP, hi = min(lo + GROUP, ns);
-    uint32_t t = sel[sb + g];
-    uint32_t acc = 0;
-    for (uint32_t i = lo; i < hi; i++) acc += lens[t][S[i]];
-    gbits[sb + g] = acc;
-    dbits += acc;
   }
   // selector MTF indices: thread-contiguous ranges, prefix-max of last use
   const uint32_t per = (nsel + NT - 1) / NT;
@@ -238,7 +334,6 @@ __global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, 
     lastv[x] = (int)g;
     sbits += idx + 1;
   }
-  uint64_t dtot = block_sum<uint64_t, NT>(dbits, (uint64_t*)cost);
   uint32_t stot = block_sum<uint32_t, NT>(sbits, sh);
   if (tid == 0) {
     uint32_t ranges = 0;
@@ -256,11 +351,7 @@ __global__ __launch_bounds__(NT) void k_huff(const uint16_t* __restrict__ syms, 
         cur = lens[t][v];
       }
     }
-    T->G = (uint32_t)G;
-    T->nsel = nsel;
     T->hdr_bits = hb;
-    T->alpha = (uint32_t)a;
-    T->data_bits = dtot;
   }
 }
 
@@ -285,15 +376,37 @@ __global__ __launch_bounds__(NT) void k_freq(const uint16_t* __restrict__ syms, 
 
 size_t block_tables_bytes() { return sizeof(BlockTables); }
 
+// Scratch for huff_run: packed costs and per-table counts.
+size_t huff_workspace_bytes(uint32_t nb) {
+  return ((size_t)nb * MAXA * 8 + 255) / 256 * 256 + ((size_t)nb * MAXG * MAXA * 4 + 255) / 256 * 256 + 512;
+}
+
+// sel_base[b] holds ceil(capacity/50) groups per block; the assign tiles are
+// laid out from those capacities on the host.
 hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
                     uint32_t* freq, bool count_freq, const uint32_t* inuse, const uint64_t* sel_base, uint8_t* sel,
-                    uint8_t* selmtf, uint64_t* gbits, void* tabs, uint32_t* err, hipStream_t st) {
+                    uint8_t* selmtf, uint64_t* gbits, void* tabs_v, uint32_t* err, uint32_t ntiles,
+                    const uint32_t* tile_blk, const uint32_t* blk_tile0, void* ws, hipStream_t st) {
   if (!nb) return hipSuccess;
+  BlockTables* tabs = (BlockTables*)tabs_v;
+  uint64_t* cost = (uint64_t*)ws;
+  uint32_t* tf = (uint32_t*)((char*)ws + ((size_t)nb * MAXA * 8 + 255) / 256 * 256);
   if (count_freq) hipLaunchKernelGGL(k_freq, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, err);
   ProfScope ps("huffman", st, 0.0);  // symbol count is known on the device only
-  hipLaunchKernelGGL(k_huff, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, inuse, sel_base, sel, selmtf,
-                     gbits, (BlockTables*)tabs);
+  hipLaunchKernelGGL(k_huff_setup, dim3(nb), dim3(NT), 0, st, nsyms, freq, inuse, tabs, cost, tf);
+  for (int it = 0; it < 4; it++) {
+    if (ntiles)
+      hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 0, tile_blk, blk_tile0, syms, sym_base, nsyms,
+                         sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
+    hipLaunchKernelGGL(k_huff_build, dim3(nb), dim3(BUILD_NT), 0, st, tabs, cost, tf);
+  }
+  if (ntiles)
+    hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 1, tile_blk, blk_tile0, syms, sym_base, nsyms,
+                       sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
+  hipLaunchKernelGGL(k_huff_finish, dim3(nb), dim3(NT), 0, st, inuse, sel_base, (const uint8_t*)sel, selmtf, tabs);
   return hipGetLastError();
 }
+
+uint32_t huff_assign_groups() { return ASSIGN_GROUPS; }
 
 }  // namespace bzg

@@ -251,8 +251,16 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_scan(const uint32_t* blk_chunk
   (void)nu;
 }
 
+// Stack column j of the wave: slot j*64 + lane.  A DPP wave_shr:1 moves every
+// lane's value one lane up; lane 0 keeps `into`.
+__device__ __forceinline__ uint32_t wave_shift_in(uint32_t into, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)into, (int)v, 0x138, 0xF, 0xF, false);
+}
+
 // One wave per chunk: MTF from the chunk's incoming stack, RUNA/RUNB,
-// symbols staged in LDS and stored 256 at a time.
+// symbols staged in LDS and stored 256 at a time.  Rows whose MTF index is 0
+// (the byte repeats the previous one) are found 64 at a time by one ballot
+// and only counted; the stack is searched and shifted for the other rows.
 __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
                                                        const uint32_t* blk_chunk0, const uint32_t* off,
                                                        const uint32_t* __restrict__ inuse,
@@ -269,33 +277,31 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
   uint32_t nu = 0;
   for (int j = 0; j < 8; j++) nu += __popc(inuse[g.b * 8 + j]);
   for (uint32_t i = l; i < MAXA; i += 64) fq[i] = 0;
-  uint32_t e[4];
-  for (int j = 0; j < 4; j++) {
-    uint32_t p = j * 64 + l;
-    e[j] = p < nu ? chunk_list[(size_t)c * 256 + p] : 0x100u;
-  }
-  const int ncol = (int)((nu + 63) / 64);
+  const uint8_t* lst = chunk_list + (size_t)c * 256;
+  uint32_t e0 = l < nu ? lst[l] : 0x100u;
+  uint32_t e1 = 64 + l < nu ? lst[64 + l] : 0x100u;
+  uint32_t e2 = 128 + l < nu ? lst[128 + l] : 0x100u;
+  uint32_t e3 = 192 + l < nu ? lst[192 + l] : 0x100u;
   uint32_t zrun = chunk_carry[c];
   const uint64_t obase = sym_base[g.b] + chunk_out[c];
   uint32_t wc = 0;  // symbols emitted by this chunk
+  // the byte before the chunk is the front of its incoming stack (at the
+  // block start: the smallest in-use byte, which MTF index 0 refers to)
+  uint32_t prev = (uint32_t)__builtin_amdgcn_readlane((int)e0, 0);
   __syncthreads();
-  auto flush_half = [&](uint32_t upto) {
-    // store the 256-symbol half that ends at `upto` (a multiple of 256)
-    uint32_t h = ((upto - 1) >> 8) & 1u;
-    __syncthreads();
-    for (int q = 0; q < 4; q++) {
-      uint32_t i = q * 64 + l;
-      syms[obase + upto - 256 + i] = buf[h * 256 + i];
-    }
-    __syncthreads();
-  };
   auto emit = [&](uint32_t sym) {
     if (l == 0) {
       buf[wc & 511u] = (uint16_t)sym;
-      fq[sym]++;
+      atomicAdd(&fq[sym], 1u);
     }
     wc++;
-    if ((wc & 255u) == 0) flush_half(wc);
+    if ((wc & 255u) == 0) {
+      uint32_t h = ((wc - 1) >> 8) & 1u;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; q++) syms[obase + wc - 256 + q * 64 + l] = buf[h * 256 + q * 64 + l];
+      __syncthreads();
+    }
   };
   auto emit_run = [&](uint32_t r) {
     while (r) {
@@ -309,42 +315,52 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
     }
   };
   for (uint32_t base = g.lo; base < g.hi; base += 64) {
-    uint32_t cnt = min(64u, g.hi - base);
-    uint32_t mine = (base + l < g.hi) ? L[base + l] : 0u;
-    {
-      for (uint32_t i = 0; i < cnt; i++) {
-        uint32_t x = __shfl(mine, (int)i, BZG_WAVE);
-        uint32_t pos = 0xFFFFFFFFu;
-        for (int j = 0; j < ncol; j++) {
-          uint64_t m = __ballot(e[j] == x);
-          if (m) {
-            pos = j * 64 + (uint32_t)(__ffsll((long long)m) - 1);
-            break;
+    const uint32_t cnt = min(64u, g.hi - base);
+    const uint32_t mine = l < cnt ? (uint32_t)L[base + l] : 0x1FFu;
+    const uint32_t before = wave_shift_in(prev, mine);
+    uint64_t nz = __ballot(l < cnt && mine != before);
+    int last = -1;
+    while (nz) {
+      const int i = __ffsll((long long)nz) - 1;
+      nz &= nz - 1;
+      zrun += (uint32_t)(i - last - 1);
+      last = i;
+      const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
+      const uint64_t m0 = __ballot(e0 == x), m1 = __ballot(e1 == x), m2 = __ballot(e2 == x), m3 = __ballot(e3 == x);
+      uint32_t pos;
+      if (m0) pos = (uint32_t)(__ffsll((long long)m0) - 1);
+      else if (m1) pos = 64u + (uint32_t)(__ffsll((long long)m1) - 1);
+      else if (m2) pos = 128u + (uint32_t)(__ffsll((long long)m2) - 1);
+      else if (m3) pos = 192u + (uint32_t)(__ffsll((long long)m3) - 1);
+      else {  // byte missing from the stack: inconsistent in-use map
+        if (l == 0) atomicOr(err, 1u);
+        pos = 1;
+      }
+      emit_run(zrun);
+      zrun = 0;
+      emit(pos + 1);
+      // slots 1..pos take the slot above them, slot 0 takes x
+      uint32_t into = x, old;
+      old = e0;
+      e0 = (l <= pos) ? wave_shift_in(into, old) : old;
+      if (pos >= 64) {
+        into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+        old = e1;
+        e1 = (64 + l <= pos) ? wave_shift_in(into, old) : old;
+        if (pos >= 128) {
+          into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+          old = e2;
+          e2 = (128 + l <= pos) ? wave_shift_in(into, old) : old;
+          if (pos >= 192) {
+            into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+            old = e3;
+            e3 = (192 + l <= pos) ? wave_shift_in(into, old) : old;
           }
-        }
-        if (pos == 0) {
-          zrun++;
-          continue;
-        }
-        if (pos == 0xFFFFFFFFu) {  // symbol not in the stack: corrupt input
-          if (l == 0) atomicOr(err, 1u);
-          pos = 1;
-        }
-        emit_run(zrun);
-        zrun = 0;
-        emit(pos + 1);
-        // rows 1..pos take the row above them, row 0 takes x
-        uint32_t into = x;  // old value entering column j at lane 0
-        for (int j = 0; j < ncol; j++) {
-          if ((uint32_t)j * 64 > pos) break;
-          uint32_t old = e[j];
-          uint32_t up = __shfl_up(old, 1, BZG_WAVE);
-          if (l == 0) up = into;
-          into = __shfl(old, 63, BZG_WAVE);
-          if ((uint32_t)j * 64 + l <= pos) e[j] = up;
         }
       }
     }
+    zrun += (uint32_t)((int)cnt - 1 - last);
+    prev = (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)cnt - 1);
   }
   if (g.last) {
     emit_run(zrun);
@@ -356,6 +372,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
     uint32_t h = (wc >> 8) & 1u;
     for (uint32_t i = l; i < rem; i += 64) syms[obase + (wc - rem) + i] = buf[h * 256 + i];
   }
+  __syncthreads();
   for (uint32_t i = l; i < nu + 2; i += 64)
     if (fq[i]) atomicAdd(&freq[(size_t)g.b * MAXA + i], fq[i]);
 }
