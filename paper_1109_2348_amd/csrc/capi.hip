@@ -89,7 +89,7 @@ struct bzg_ctx {
   size_t ws_cap[2] = {0, 0};
   void* pin = nullptr;
   size_t pin_cap = 0;
-  uint32_t* crc_tab = nullptr;  // device: 256 byte-step entries, then 64 powers x^(8*2^j) mod P
+  uint32_t* crc_tab = nullptr;  // device: 256 byte steps, 64 powers x^(8*2^j), 256 tile shifts (mod P)
 };
 
 namespace {
@@ -173,6 +173,14 @@ void crc_tables(uint32_t* tab, uint32_t* pw) {
   uint32_t x8 = 0x100u;  // x^8
   pw[0] = x8;
   for (int j = 1; j < 64; j++) pw[j] = mul(pw[j - 1], pw[j - 1]);
+  // pw[64 + t] = x^(8 * 16 * (255 - t)): shift of thread t's 16 bytes to the
+  // end of a full 4096-byte tile
+  uint32_t x128 = pw[4];  // x^(8*16)
+  uint32_t acc = 1;
+  for (int t = 255; t >= 0; t--) {
+    pw[64 + t] = acc;
+    acc = mul(acc, x128);
+  }
 }
 
 struct Carve {
@@ -232,9 +240,9 @@ int bzg_create(bzg_ctx** out, int hip_device) {
   if (!ctx) return BZG_ENOMEM;
   ctx->device = hip_device;
   hipError_t e = hipSetDevice(hip_device);
-  if (e == hipSuccess) e = hipMalloc(&ctx->crc_tab, 320 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&ctx->crc_tab, 576 * sizeof(uint32_t));
   if (e == hipSuccess) {
-    uint32_t h[320];
+    uint32_t h[576];
     crc_tables(h, h + 256);
     e = hipMemcpy(ctx->crc_tab, h, sizeof(h), hipMemcpyHostToDevice);
   }

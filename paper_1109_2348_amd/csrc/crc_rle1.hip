@@ -23,7 +23,7 @@ struct RleTile {
   uint32_t last_bnd;  // last run start in the tile, +1 (0 = none)
   uint32_t lead;      // bytes before the tile's first run start
   uint32_t inner;     // output bytes of the bytes from the first run start on
-  uint32_t crc;       // CRC share, already shifted to the end of the block
+  uint32_t crc;       // CRC share of the tile from a zero register (at the tile end)
 };
 
 __device__ __forceinline__ uint32_t rle_emit_count(uint32_t t) {
@@ -81,10 +81,16 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
   uint32_t prev;
   load_run(s, g, p0, v, cnt, prev);
   __syncthreads();
-  // CRC of this thread's bytes from a zero register, shifted to the block end
+  // CRC of this thread's bytes from a zero register, shifted to the tile end
+  // (by a per-thread constant in full tiles)
   uint32_t reg = 0;
   for (int i = 0; i < cnt; i++) reg = (reg << 8) ^ tab[(reg >> 24) ^ v[i]];
-  uint32_t share = cnt ? gf2_mulmod(reg, gf2_xpow8((uint64_t)(g.n - (p0 + cnt)), crc_pow)) : 0u;
+  uint32_t share = 0;
+  if (cnt) {
+    const uint32_t after = g.hi - (p0 + cnt);
+    const uint32_t sft = (g.hi - g.lo == RLE_TILE) ? crc_pow[64 + threadIdx.x] : gf2_xpow8(after, crc_pow);
+    share = gf2_mulmod(reg, sft);
+  }
   // run starts
   uint32_t lastb = 0;
   uint32_t pv = prev;
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, c
       tile_out[t] = carry_out + ex;
       tiles[t].last_bnd = rs;  // reused: run start carried into the tile (+1)
     }
-    x ^= (t < t1) ? r.crc : 0u;
+    if (t < t1) x ^= gf2_mulmod(r.crc, gf2_xpow8((uint64_t)(n - min(lo + RLE_TILE, n)), crc_pow));
     carry_out += tot;
     carry_rs = sx[NT - 1] > carry_rs ? sx[NT - 1] : carry_rs;
     __syncthreads();

@@ -257,50 +257,34 @@ __device__ __forceinline__ uint32_t wave_shift_in(uint32_t into, uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)into, (int)v, 0x138, 0xF, 0xF, false);
 }
 
-// One wave per chunk: MTF from the chunk's incoming stack, RUNA/RUNB,
-// symbols staged in LDS and stored 256 at a time.  Rows whose MTF index is 0
-// (the byte repeats the previous one) are found 64 at a time by one ballot
-// and only counted; the stack is searched and shifted for the other rows.
-__global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
-                                                       const uint32_t* blk_chunk0, const uint32_t* off,
-                                                       const uint32_t* __restrict__ inuse,
-                                                       const uint8_t* __restrict__ chunk_list,
-                                                       const uint32_t* __restrict__ chunk_carry,
-                                                       const uint32_t* __restrict__ chunk_out,
-                                                       const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
-                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err) {
-  __shared__ uint16_t buf[512];
-  __shared__ uint32_t fq[MAXA];
-  const uint32_t c = blockIdx.x;
+__device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)(__ffsll((long long)m) - 1); }
+
+// One wave per chunk: MTF from the chunk's incoming stack, RUNA/RUNB.
+// Rows whose MTF index is 0 (the byte repeats the previous one) are found 64
+// at a time by one ballot and only counted; the stack is searched (only the
+// columns that can hold in-use bytes) and shifted for the other rows.
+// Emitted symbols collect in one register across the wave (v_writelane) and
+// are stored 64 at a time; the symbol histogram is updated per store.
+template <int NCOL>
+__device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g, uint32_t nu, const uint8_t* lst,
+                               uint32_t zrun, uint64_t obase, uint16_t* __restrict__ syms, uint32_t* fq,
+                               uint32_t* __restrict__ err) {
   const uint32_t l = lane();
-  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
-  uint32_t nu = 0;
-  for (int j = 0; j < 8; j++) nu += __popc(inuse[g.b * 8 + j]);
-  for (uint32_t i = l; i < MAXA; i += 64) fq[i] = 0;
-  const uint8_t* lst = chunk_list + (size_t)c * 256;
   uint32_t e0 = l < nu ? lst[l] : 0x100u;
-  uint32_t e1 = 64 + l < nu ? lst[64 + l] : 0x100u;
-  uint32_t e2 = 128 + l < nu ? lst[128 + l] : 0x100u;
-  uint32_t e3 = 192 + l < nu ? lst[192 + l] : 0x100u;
-  uint32_t zrun = chunk_carry[c];
-  const uint64_t obase = sym_base[g.b] + chunk_out[c];
-  uint32_t wc = 0;  // symbols emitted by this chunk
+  uint32_t e1 = (NCOL > 1 && 64 + l < nu) ? lst[64 + l] : 0x100u;
+  uint32_t e2 = (NCOL > 2 && 128 + l < nu) ? lst[128 + l] : 0x100u;
+  uint32_t e3 = (NCOL > 3 && 192 + l < nu) ? lst[192 + l] : 0x100u;
+  uint32_t wc = 0;     // symbols emitted so far by this chunk
+  uint32_t outv = 0;   // pending symbols: lane i holds symbol (wc & ~63) + i
   // the byte before the chunk is the front of its incoming stack (at the
   // block start: the smallest in-use byte, which MTF index 0 refers to)
   uint32_t prev = (uint32_t)__builtin_amdgcn_readlane((int)e0, 0);
-  __syncthreads();
   auto emit = [&](uint32_t sym) {
-    if (l == 0) {
-      buf[wc & 511u] = (uint16_t)sym;
-      atomicAdd(&fq[sym], 1u);
-    }
+    outv = (l == (wc & 63u)) ? sym : outv;
     wc++;
-    if ((wc & 255u) == 0) {
-      uint32_t h = ((wc - 1) >> 8) & 1u;
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; q++) syms[obase + wc - 256 + q * 64 + l] = buf[h * 256 + q * 64 + l];
-      __syncthreads();
+    if ((wc & 63u) == 0) {
+      syms[obase + wc - 64 + l] = (uint16_t)outv;
+      atomicAdd(&fq[outv], 1u);
     }
   };
   auto emit_run = [&](uint32_t r) {
@@ -314,47 +298,65 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
       }
     }
   };
+  uint32_t nxt = (g.lo + l < g.hi) ? (uint32_t)L[g.lo + l] : 0x1FFu;
   for (uint32_t base = g.lo; base < g.hi; base += 64) {
     const uint32_t cnt = min(64u, g.hi - base);
-    const uint32_t mine = l < cnt ? (uint32_t)L[base + l] : 0x1FFu;
+    const uint32_t mine = l < cnt ? nxt : 0x1FFu;
+    nxt = (base + 64 + l < g.hi) ? (uint32_t)L[base + 64 + l] : 0x1FFu;  // prefetch the next batch
     const uint32_t before = wave_shift_in(prev, mine);
     uint64_t nz = __ballot(l < cnt && mine != before);
     int last = -1;
     while (nz) {
-      const int i = __ffsll((long long)nz) - 1;
+      const int i = (int)first_lane(nz);
       nz &= nz - 1;
       zrun += (uint32_t)(i - last - 1);
       last = i;
       const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
-      const uint64_t m0 = __ballot(e0 == x), m1 = __ballot(e1 == x), m2 = __ballot(e2 == x), m3 = __ballot(e3 == x);
       uint32_t pos;
-      if (m0) pos = (uint32_t)(__ffsll((long long)m0) - 1);
-      else if (m1) pos = 64u + (uint32_t)(__ffsll((long long)m1) - 1);
-      else if (m2) pos = 128u + (uint32_t)(__ffsll((long long)m2) - 1);
-      else if (m3) pos = 192u + (uint32_t)(__ffsll((long long)m3) - 1);
-      else {  // byte missing from the stack: inconsistent in-use map
-        if (l == 0) atomicOr(err, 1u);
-        pos = 1;
+      const uint64_t m0 = __ballot(e0 == x);
+      if (m0) {
+        pos = first_lane(m0);
+      } else {
+        const uint64_t m1 = NCOL > 1 ? __ballot(e1 == x) : 0ull;
+        if (m1) {
+          pos = 64u + first_lane(m1);
+        } else {
+          const uint64_t m2 = NCOL > 2 ? __ballot(e2 == x) : 0ull;
+          if (m2) {
+            pos = 128u + first_lane(m2);
+          } else {
+            const uint64_t m3 = NCOL > 3 ? __ballot(e3 == x) : 0ull;
+            if (m3) {
+              pos = 192u + first_lane(m3);
+            } else {  // byte missing from the stack: inconsistent in-use map
+              if (l == 0) atomicOr(err, 1u);
+              pos = 1;
+            }
+          }
+        }
       }
       emit_run(zrun);
       zrun = 0;
       emit(pos + 1);
       // slots 1..pos take the slot above them, slot 0 takes x
-      uint32_t into = x, old;
-      old = e0;
-      e0 = (l <= pos) ? wave_shift_in(into, old) : old;
-      if (pos >= 64) {
-        into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+      uint32_t old = e0;
+      uint32_t sh = wave_shift_in(x, old);
+      e0 = (l <= pos) ? sh : old;
+      if (NCOL > 1 && pos >= 64) {
+        uint32_t into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
         old = e1;
-        e1 = (64 + l <= pos) ? wave_shift_in(into, old) : old;
-        if (pos >= 128) {
+        sh = wave_shift_in(into, old);
+        e1 = (64 + l <= pos) ? sh : old;
+        if (NCOL > 2 && pos >= 128) {
           into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
           old = e2;
-          e2 = (128 + l <= pos) ? wave_shift_in(into, old) : old;
-          if (pos >= 192) {
+          sh = wave_shift_in(into, old);
+          e2 = (128 + l <= pos) ? sh : old;
+          if (NCOL > 3 && pos >= 192) {
             into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
             old = e3;
-            e3 = (192 + l <= pos) ? wave_shift_in(into, old) : old;
+            sh = wave_shift_in(into, old);
+            e3 = (192 + l <= pos) ? sh : old;
           }
         }
       }
@@ -366,12 +368,36 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
     emit_run(zrun);
     emit(nu + 1);
   }
-  __syncthreads();
-  uint32_t rem = wc & 255u;
-  if (rem) {
-    uint32_t h = (wc >> 8) & 1u;
-    for (uint32_t i = l; i < rem; i += 64) syms[obase + (wc - rem) + i] = buf[h * 256 + i];
+  const uint32_t rem = wc & 63u;
+  if (rem && l < rem) {
+    syms[obase + (wc - rem) + l] = (uint16_t)outv;
+    atomicAdd(&fq[outv], 1u);
   }
+}
+
+__global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                                       const uint32_t* blk_chunk0, const uint32_t* off,
+                                                       const uint32_t* __restrict__ inuse,
+                                                       const uint8_t* __restrict__ chunk_list,
+                                                       const uint32_t* __restrict__ chunk_carry,
+                                                       const uint32_t* __restrict__ chunk_out,
+                                                       const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
+                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err) {
+  __shared__ uint32_t fq[MAXA];
+  const uint32_t c = blockIdx.x;
+  const uint32_t l = lane();
+  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
+  uint32_t nu = 0;
+  for (int j = 0; j < 8; j++) nu += __popc(inuse[g.b * 8 + j]);
+  for (uint32_t i = l; i < MAXA; i += 64) fq[i] = 0;
+  __syncthreads();
+  const uint8_t* lst = chunk_list + (size_t)c * 256;
+  const uint32_t zrun = chunk_carry[c];
+  const uint64_t obase = sym_base[g.b] + chunk_out[c];
+  if (nu <= 64) mtf_emit_chunk<1>(L, g, nu, lst, zrun, obase, syms, fq, err);
+  else if (nu <= 128) mtf_emit_chunk<2>(L, g, nu, lst, zrun, obase, syms, fq, err);
+  else if (nu <= 192) mtf_emit_chunk<3>(L, g, nu, lst, zrun, obase, syms, fq, err);
+  else mtf_emit_chunk<4>(L, g, nu, lst, zrun, obase, syms, fq, err);
   __syncthreads();
   for (uint32_t i = l; i < nu + 2; i += 64)
     if (fq[i]) atomicAdd(&freq[(size_t)g.b * MAXA + i], fq[i]);
