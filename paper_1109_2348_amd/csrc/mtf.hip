@@ -260,32 +260,52 @@ __device__ __forceinline__ uint32_t wave_shift_in(uint32_t into, uint32_t v) {
 __device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)(__ffsll((long long)m) - 1); }
 
 // One wave per chunk: MTF from the chunk's incoming stack, RUNA/RUNB.
+//
 // Rows whose MTF index is 0 (the byte repeats the previous one) are found 64
-// at a time by one ballot and only counted; the stack is searched (only the
-// columns that can hold in-use bytes) and shifted for the other rows.
-// Emitted symbols collect in one register across the wave (v_writelane) and
-// are stored 64 at a time; the symbol histogram is updated per store.
+// at a time by one ballot.  A batch of 64 rows with few nonzero indices runs
+// the serial step for those rows only: search the stack columns that can hold
+// in-use bytes, shift.  A batch with many runs the batched step, which has
+// no serial chain: for row l holding byte x,
+//   * if x occurred earlier in the batch (last at lane p), its index is the
+//     number of distinct bytes in lanes p+1..l-1 = lanes k < l whose next
+//     occurrence is at or after l, i.e. lanes below l minus the "previous
+//     occurrence" lanes of rows below l (an exclusive prefix-OR);
+//   * else its index is D + R(x) - #{first-occurrence lanes k < l with
+//     R(x_k) < R(x)}, with R the position in the stack before the batch and D
+//     the number of distinct bytes in lanes below l;
+// and the stack becomes [the batch's bytes by last occurrence, latest first]
+// followed by the rest in their old order.  Emitted symbols of the serial
+// path collect in one register (stored 64 at a time); the batched path
+// stores its symbols directly at their prefix-sum offsets.
 template <int NCOL>
 __device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g, uint32_t nu, const uint8_t* lst,
                                uint32_t zrun, uint64_t obase, uint16_t* __restrict__ syms, uint32_t* fq,
-                               uint32_t* __restrict__ err) {
+                               uint32_t* posof, uint32_t* nstk, uint32_t* inb, uint32_t* __restrict__ err) {
+  constexpr int BATCHED_MIN = 16;  // nonzero rows from which a batch takes the batched step
   const uint32_t l = lane();
+  const uint64_t lt = lanemask_lt();
   uint32_t e0 = l < nu ? lst[l] : 0x100u;
   uint32_t e1 = (NCOL > 1 && 64 + l < nu) ? lst[64 + l] : 0x100u;
   uint32_t e2 = (NCOL > 2 && 128 + l < nu) ? lst[128 + l] : 0x100u;
   uint32_t e3 = (NCOL > 3 && 192 + l < nu) ? lst[192 + l] : 0x100u;
-  uint32_t wc = 0;     // symbols emitted so far by this chunk
-  uint32_t outv = 0;   // pending symbols: lane i holds symbol (wc & ~63) + i
+  uint32_t wc = 0;    // symbols emitted so far by this chunk
+  uint32_t ob = 0;    // symbols [ob, wc) are pending in outv (lane i = symbol ob + i)
+  uint32_t outv = 0;
   // the byte before the chunk is the front of its incoming stack (at the
   // block start: the smallest in-use byte, which MTF index 0 refers to)
   uint32_t prev = (uint32_t)__builtin_amdgcn_readlane((int)e0, 0);
-  auto emit = [&](uint32_t sym) {
-    outv = (l == (wc & 63u)) ? sym : outv;
-    wc++;
-    if ((wc & 63u) == 0) {
-      syms[obase + wc - 64 + l] = (uint16_t)outv;
+  auto flush = [&]() {
+    const uint32_t n = wc - ob;
+    if (n && l < n) {
+      syms[obase + ob + l] = (uint16_t)outv;
       atomicAdd(&fq[outv], 1u);
     }
+    ob = wc;
+  };
+  auto emit = [&](uint32_t sym) {
+    outv = (l == wc - ob) ? sym : outv;
+    wc++;
+    if (wc - ob == 64) flush();
   };
   auto emit_run = [&](uint32_t r) {
     while (r) {
@@ -301,78 +321,175 @@ __device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g
   uint32_t nxt = (g.lo + l < g.hi) ? (uint32_t)L[g.lo + l] : 0x1FFu;
   for (uint32_t base = g.lo; base < g.hi; base += 64) {
     const uint32_t cnt = min(64u, g.hi - base);
-    const uint32_t mine = l < cnt ? nxt : 0x1FFu;
+    const bool valid = l < cnt;
+    const uint32_t mine = valid ? nxt : 0x1FFu;
     nxt = (base + 64 + l < g.hi) ? (uint32_t)L[base + 64 + l] : 0x1FFu;  // prefetch the next batch
     const uint32_t before = wave_shift_in(prev, mine);
-    uint64_t nz = __ballot(l < cnt && mine != before);
-    int last = -1;
-    while (nz) {
-      const int i = (int)first_lane(nz);
-      nz &= nz - 1;
-      zrun += (uint32_t)(i - last - 1);
-      last = i;
-      const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
-      uint32_t pos;
-      const uint64_t m0 = __ballot(e0 == x);
-      if (m0) {
-        pos = first_lane(m0);
-      } else {
-        const uint64_t m1 = NCOL > 1 ? __ballot(e1 == x) : 0ull;
-        if (m1) {
-          pos = 64u + first_lane(m1);
+    uint64_t nz = __ballot(valid && mine != before);
+    if (__popcll(nz) < BATCHED_MIN) {
+      // ---------------- serial step for the few nonzero rows
+      int last = -1;
+      while (nz) {
+        const int i = (int)first_lane(nz);
+        nz &= nz - 1;
+        zrun += (uint32_t)(i - last - 1);
+        last = i;
+        const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
+        uint32_t pos;
+        const uint64_t m0 = __ballot(e0 == x);
+        if (m0) {
+          pos = first_lane(m0);
         } else {
-          const uint64_t m2 = NCOL > 2 ? __ballot(e2 == x) : 0ull;
-          if (m2) {
-            pos = 128u + first_lane(m2);
+          const uint64_t m1 = NCOL > 1 ? __ballot(e1 == x) : 0ull;
+          if (m1) {
+            pos = 64u + first_lane(m1);
           } else {
-            const uint64_t m3 = NCOL > 3 ? __ballot(e3 == x) : 0ull;
-            if (m3) {
-              pos = 192u + first_lane(m3);
-            } else {  // byte missing from the stack: inconsistent in-use map
-              if (l == 0) atomicOr(err, 1u);
-              pos = 1;
+            const uint64_t m2 = NCOL > 2 ? __ballot(e2 == x) : 0ull;
+            if (m2) {
+              pos = 128u + first_lane(m2);
+            } else {
+              const uint64_t m3 = NCOL > 3 ? __ballot(e3 == x) : 0ull;
+              if (m3) {
+                pos = 192u + first_lane(m3);
+              } else {  // byte missing from the stack: inconsistent in-use map
+                if (l == 0) atomicOr(err, 1u);
+                pos = 1;
+              }
+            }
+          }
+        }
+        emit_run(zrun);
+        zrun = 0;
+        emit(pos + 1);
+        // slots 1..pos take the slot above them, slot 0 takes x
+        uint32_t old = e0;
+        uint32_t sh = wave_shift_in(x, old);
+        e0 = (l <= pos) ? sh : old;
+        if (NCOL > 1 && pos >= 64) {
+          uint32_t into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+          old = e1;
+          sh = wave_shift_in(into, old);
+          e1 = (64 + l <= pos) ? sh : old;
+          if (NCOL > 2 && pos >= 128) {
+            into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+            old = e2;
+            sh = wave_shift_in(into, old);
+            e2 = (128 + l <= pos) ? sh : old;
+            if (NCOL > 3 && pos >= 192) {
+              into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
+              old = e3;
+              sh = wave_shift_in(into, old);
+              e3 = (192 + l <= pos) ? sh : old;
             }
           }
         }
       }
-      emit_run(zrun);
-      zrun = 0;
-      emit(pos + 1);
-      // slots 1..pos take the slot above them, slot 0 takes x
-      uint32_t old = e0;
-      uint32_t sh = wave_shift_in(x, old);
-      e0 = (l <= pos) ? sh : old;
-      if (NCOL > 1 && pos >= 64) {
-        uint32_t into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
-        old = e1;
-        sh = wave_shift_in(into, old);
-        e1 = (64 + l <= pos) ? sh : old;
-        if (NCOL > 2 && pos >= 128) {
-          into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
-          old = e2;
-          sh = wave_shift_in(into, old);
-          e2 = (128 + l <= pos) ? sh : old;
-          if (NCOL > 3 && pos >= 192) {
-            into = (uint32_t)__builtin_amdgcn_readlane((int)old, 63);
-            old = e3;
-            sh = wave_shift_in(into, old);
-            e3 = (192 + l <= pos) ? sh : old;
+      zrun += (uint32_t)((int)cnt - 1 - last);
+    } else {
+      // ---------------- batched step
+      flush();
+      if (e0 < 256u) posof[e0] = l;
+      if (NCOL > 1 && e1 < 256u) posof[e1] = 64u + l;
+      if (NCOL > 2 && e2 < 256u) posof[e2] = 128u + l;
+      if (NCOL > 3 && e3 < 256u) posof[e3] = 192u + l;
+      __syncthreads();
+      const uint64_t vmask = __ballot(valid);
+      const uint32_t R = valid ? posof[mine] : 0x3FFu;
+      const uint64_t peers = match_digit8(mine & 255u, vmask);
+      const uint64_t pm = peers & lt;
+      const int p = pm ? 63 - (int)__clzll((long long)pm) : -1;          // previous occurrence
+      const uint64_t nm = peers & ~lt & ~(1ull << l);
+      const bool is_last = valid && nm == 0;                              // no later occurrence
+      const uint64_t first_m = __ballot(valid && p < 0);
+      const uint64_t last_m = __ballot(is_last);
+      // N = lanes k that are the previous occurrence of some lane m < l
+      uint64_t incl = (valid && p >= 0) ? (1ull << p) : 0ull;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        uint64_t u = __shfl_up(incl, d, BZG_WAVE);
+        if ((int)l >= d) incl |= u;
+      }
+      uint64_t N = __shfl_up(incl, 1, BZG_WAVE);
+      if (l == 0) N = 0;
+      uint32_t idx;
+      if (p >= 0) {
+        const uint64_t upto_p = (p >= 63) ? ~0ull : ((2ull << p) - 1ull);
+        idx = (uint32_t)__popcll(lt & ~N & ~upto_p);
+      } else {
+        uint32_t below = 0;
+        uint64_t fm = first_m & ((1ull << 63) - 1ull);
+        while (fm) {
+          const int k = (int)first_lane(fm);
+          fm &= fm - 1;
+          const uint32_t rk = (uint32_t)__builtin_amdgcn_readlane((int)R, k);
+          below += ((int)l > k && rk < R) ? 1u : 0u;
+        }
+        idx = (uint32_t)__popcll(first_m & lt) + R - below;
+      }
+      if (!valid) idx = 0;
+      // RUNA/RUNB: a nonzero row emits the digits of the zero run before it
+      const uint64_t nzm = __ballot(valid && idx != 0);
+      const uint64_t pz = nzm & lt;
+      const int pnz = pz ? 63 - (int)__clzll((long long)pz) : -1;
+      const bool isnz = (nzm >> l) & 1ull;
+      uint32_t r = (uint32_t)((int)l - pnz - 1) + (pnz < 0 ? zrun : 0u);
+      const uint32_t ndig = isnz ? run_digits(r) : 0u;
+      const uint32_t cnt_e = isnz ? ndig + 1u : 0u;
+      const uint32_t inc = wave_incl_sum(cnt_e);
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+      if (isnz) {
+        uint64_t o = obase + wc + inc - cnt_e;
+        while (r) {
+          if (r & 1u) {
+            syms[o++] = 0;
+            atomicAdd(&fq[0], 1u);
+            r = (r - 1) >> 1;
+          } else {
+            syms[o++] = 1;
+            atomicAdd(&fq[1], 1u);
+            r = (r - 2) >> 1;
           }
         }
+        syms[o] = (uint16_t)(idx + 1);
+        atomicAdd(&fq[idx + 1], 1u);
       }
+      wc += total;
+      ob = wc;
+      const int lnz = nzm ? 63 - (int)__clzll((long long)nzm) : -1;
+      zrun = (lnz < 0) ? zrun + cnt : (uint32_t)((int)cnt - 1 - lnz);
+      // new stack: batch bytes by last occurrence, then the rest in order
+      const uint32_t nd = (uint32_t)__popcll(first_m);
+      if (valid && p < 0) inb[mine] = 1u;
+      __syncthreads();
+      if (is_last) nstk[__popcll(last_m & ~(lt | (1ull << l)))] = mine;
+      uint32_t seen = 0;
+#define BZG_RESTACK(ej, J)                                                     \
+  {                                                                            \
+    const bool in_b = (ej) < 256u && inb[(ej)];                                \
+    const uint64_t cm = __ballot(in_b);                                        \
+    if (!in_b) nstk[nd + (J) * 64u + l - (seen + (uint32_t)__popcll(cm & lt))] = (ej); \
+    seen += (uint32_t)__popcll(cm);                                            \
+  }
+      BZG_RESTACK(e0, 0)
+      if (NCOL > 1) BZG_RESTACK(e1, 1)
+      if (NCOL > 2) BZG_RESTACK(e2, 2)
+      if (NCOL > 3) BZG_RESTACK(e3, 3)
+#undef BZG_RESTACK
+      __syncthreads();
+      e0 = nstk[l];
+      if (NCOL > 1) e1 = nstk[64 + l];
+      if (NCOL > 2) e2 = nstk[128 + l];
+      if (NCOL > 3) e3 = nstk[192 + l];
+      if (valid && p < 0) inb[mine] = 0u;
+      __syncthreads();
     }
-    zrun += (uint32_t)((int)cnt - 1 - last);
     prev = (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)cnt - 1);
   }
   if (g.last) {
     emit_run(zrun);
     emit(nu + 1);
   }
-  const uint32_t rem = wc & 63u;
-  if (rem && l < rem) {
-    syms[obase + (wc - rem) + l] = (uint16_t)outv;
-    atomicAdd(&fq[outv], 1u);
-  }
+  flush();
 }
 
 __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
@@ -384,20 +501,22 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
                                                        const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
                                                        uint32_t* __restrict__ freq, uint32_t* __restrict__ err) {
   __shared__ uint32_t fq[MAXA];
+  __shared__ uint32_t posof[256], nstk[256], inb[256];
   const uint32_t c = blockIdx.x;
   const uint32_t l = lane();
   ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
   uint32_t nu = 0;
   for (int j = 0; j < 8; j++) nu += __popc(inuse[g.b * 8 + j]);
   for (uint32_t i = l; i < MAXA; i += 64) fq[i] = 0;
+  for (uint32_t i = l; i < 256; i += 64) inb[i] = 0;
   __syncthreads();
   const uint8_t* lst = chunk_list + (size_t)c * 256;
   const uint32_t zrun = chunk_carry[c];
   const uint64_t obase = sym_base[g.b] + chunk_out[c];
-  if (nu <= 64) mtf_emit_chunk<1>(L, g, nu, lst, zrun, obase, syms, fq, err);
-  else if (nu <= 128) mtf_emit_chunk<2>(L, g, nu, lst, zrun, obase, syms, fq, err);
-  else if (nu <= 192) mtf_emit_chunk<3>(L, g, nu, lst, zrun, obase, syms, fq, err);
-  else mtf_emit_chunk<4>(L, g, nu, lst, zrun, obase, syms, fq, err);
+  if (nu <= 64) mtf_emit_chunk<1>(L, g, nu, lst, zrun, obase, syms, fq, posof, nstk, inb, err);
+  else if (nu <= 128) mtf_emit_chunk<2>(L, g, nu, lst, zrun, obase, syms, fq, posof, nstk, inb, err);
+  else if (nu <= 192) mtf_emit_chunk<3>(L, g, nu, lst, zrun, obase, syms, fq, posof, nstk, inb, err);
+  else mtf_emit_chunk<4>(L, g, nu, lst, zrun, obase, syms, fq, posof, nstk, inb, err);
   __syncthreads();
   for (uint32_t i = l; i < nu + 2; i += 64)
     if (fq[i]) atomicAdd(&freq[(size_t)g.b * MAXA + i], fq[i]);
