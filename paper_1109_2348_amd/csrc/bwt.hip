@@ -21,6 +21,9 @@
 // which each segment keeps its own histogram column (a segmented sort).  The
 // gather of key2 runs as its own kernel so that no rank is read after it has
 // been refined in the same round.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -45,7 +48,7 @@ __device__ __forceinline__ uint32_t lowest_lane(uint64_t m) { return (uint32_t)(
 __global__ __launch_bounds__(NT) void k_sa_init(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
                                                 uint32_t nb, uint32_t N, uint32_t* __restrict__ SA,
                                                 uint32_t* __restrict__ key) {
-  uint32_t k = blockIdx.x * NT + threadIdx.x;
+  uint32_t k = xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   if (k >= N) return;
   uint32_t b = find_block(off, nb, k);
   uint32_t o = off[b], n = off[b + 1] - o;
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
-  BigTile g = big_tile(blockIdx.x, segs, owner);
+  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
   for (int i = 0; i < RI; i++) {
     uint32_t k = wbase + i * BZG_WAVE + lane();
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
-  BigTile g = big_tile(blockIdx.x, segs, owner);
+  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
   uint32_t key[RI], val[RI], rk[RI];
 #pragma unroll
@@ -218,7 +221,7 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
 __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                  const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg) {
   __shared__ uint32_t sh[NW + 1];
-  BigTile g = big_tile(blockIdx.x, segs, owner);
+  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
   uint32_t best = 0;
   for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
     if (k == g.r.start || kin[k] != kin[k - 1]) best = max(best, k + 1);
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs
   if (threadIdx.x == 0) {
     uint32_t m = 0;
     for (int q = 0; q < NW; q++) m = max(m, sh[q]);
-    agg[blockIdx.x] = m;
+    agg[xcd_tile(blockIdx.x, gridDim.x)] = m;
   }
 }
 
@@ -242,10 +245,11 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t s_carry;
   __shared__ uint32_t wg_base[4];
-  BigTile g = big_tile(blockIdx.x, segs, owner);
+  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
   if (threadIdx.x == 0) {
     uint32_t c = 0;
-    for (uint32_t j = blockIdx.x; j > blockIdx.x - g.t; j--) {
+    const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
+    for (uint32_t j = jt; j > jt - g.t; j--) {
       c = agg[j - 1];
       if (c) break;
     }
@@ -347,8 +351,9 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t s_n;
-  if (blockIdx.x < n_small_tiles) {
-    uint32_t n = small_tile_map(blockIdx.x, head, segs, cnt->small_total, mark, segp, sh, &s_n);
+  const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
+  if (jt < n_small_tiles) {
+    uint32_t n = small_tile_map(jt, head, segs, cnt->small_total, mark, segp, sh, &s_n);
     for (uint32_t p = threadIdx.x; p < n; p += NT) {
       uint32_t sp = segp[p];
       if (sp == NO_SEG) continue;
@@ -360,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
       key2[k] = rank[o + i] - o;
     }
   } else {
-    BigTile g = big_tile(blockIdx.x - n_small_tiles, segs, owner);
+    BigTile g = big_tile(jt - n_small_tiles, segs, owner);
     uint32_t o = blk_off[g.r.blk], nbk = blk_off[g.r.blk + 1] - o;
     for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
       uint32_t i = SA[k] - o + h;
@@ -386,7 +391,8 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   __shared__ uint32_t s_n;
   __shared__ uint32_t wg_base[4];
   const uint32_t small_total = cnt->small_total;
-  const uint32_t n = small_tile_map(blockIdx.x, head, segs, small_total, mark, segp, sh, &s_n);
+  const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n);
   // load (segment start << 21 | key2, SA value).  Positions before the
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     sval[p] = vv;
   }
   // clear the head entries of this tile for reuse two rounds later
-  const uint32_t lo = blockIdx.x * SMALL_T;
+  const uint32_t lo = jt * SMALL_T;
   for (uint32_t i = threadIdx.x; i < SMALL_T; i += NT)
     if (lo + i < small_total) head[lo + i] = 0;
   __syncthreads();
@@ -501,7 +507,7 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
                                                 uint32_t nb, uint32_t N, const uint32_t* __restrict__ SA,
                                                 uint8_t* __restrict__ L, uint32_t* __restrict__ primary,
                                                 uint32_t* __restrict__ sa_local) {
-  uint32_t k = blockIdx.x * NT + threadIdx.x;
+  uint32_t k = xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   if (k >= N) return;
   uint32_t b = find_block(off, nb, k);
   uint32_t o = off[b], n = off[b + 1] - o;
@@ -642,6 +648,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     segs0.push_back(r);
   }
   int nround = 0;
+  const bool log_rounds = getenv("BZG_LOG") != nullptr;
   if (!segs0.empty()) {
     BZG_TRY(hipMemcpyAsync(w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec), hipMemcpyHostToDevice, st));
     BZG_TRY(hipMemcpyAsync(w.owner[0], owner0.data(), owner0.size() * 4, hipMemcpyHostToDevice, st));
@@ -668,6 +675,9 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       BZG_TRY(hipMemcpyAsync(&w.h_cnt[cur], &w.cnt[cur], sizeof(RoundCounters), hipMemcpyDeviceToHost, st));
       BZG_TRY(hipStreamSynchronize(st));
       RoundCounters c = w.h_cnt[cur];
+      if (log_rounds)
+        fprintf(stderr, "[bzg] sort round %d h=%u segments=%u small_rows=%u large_rows=%u large_tiles=%u\n", nround,
+                h, c.n_segs, c.small_total, c.big_active, c.big_tiles);
       if (c.n_segs == 0) break;
       if (c.n_segs > z.seg_cap || c.big_tiles > z.owner_cap || c.small_total > N) {
         err = "bwt: segment capacity exceeded";

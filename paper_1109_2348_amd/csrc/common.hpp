@@ -126,6 +126,16 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t valid) {
   return m;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by workgroup id.  This
+// maps workgroup id -> logical tile so that every XCD runs one contiguous
+// range of tiles: neighbouring tiles (the same block's rows, ranks and text)
+// then share that XCD's L2.  A bijection on [0, n).
+constexpr uint32_t NXCD = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t wg, uint32_t n) {
+  const uint32_t x = wg % NXCD, i = wg / NXCD, q = n / NXCD, r = n % NXCD;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ---------------------------------------------------------------- CRC-32
 // The bzip2 block CRC is non-reflected (MSB first) with polynomial
 // 0x04C11DB7; in GF(2)[x] the register after data B (from zero) is
