@@ -240,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
                                                  const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                  const uint32_t* __restrict__ agg, const uint32_t* __restrict__ blk_off,
                                                  uint32_t* __restrict__ SA, uint32_t* __restrict__ rank,
-                                                 uint32_t h_next, AppendCtx app) {
+                                                 uint32_t h_next, int key_is_rank, AppendCtx app) {
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t s_carry;
@@ -286,7 +286,10 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
       bool end = (k + 1 == segend) || ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : kin[k + 1] != kk[i]);
       if (end) {
         uint32_t len = k + 1 - (hp - 1);
-        if (len >= 2 && keep_blk && m < RI / 2 + 1) {
+        // closed group: the segment did not split and every partner lies in
+        // it, so its rotations are all equal (already in final order)
+        const bool closed = key_is_rank && len == g.r.len && kk[i] == g.r.start - blk_off[g.r.blk];
+        if (len >= 2 && keep_blk && !closed && m < RI / 2 + 1) {
           gs[m] = hp - 1;
           gl[m] = len;
           m++;
@@ -488,7 +491,9 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     if (end) {
       uint32_t len = p + 1 - (hp - 1);
       uint32_t nbk = blk_off[r.blk + 1] - blk_off[r.blk];
-      if (len >= 2 && h_next < nbk) {
+      // closed group (see k_rename_b): equal rotations, final
+      const bool closed = len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - blk_off[r.blk];
+      if (len >= 2 && h_next < nbk && !closed) {
         gs[m] = headk;
         gl[m] = len;
         gb[m] = r.blk;
@@ -663,7 +668,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     {
       ProfScope ps("rename_b", st, 16.0 * init_elems);
       hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, vin, w.agg,
-                         w.d_off, w.SA, w.rank, 4u, app);
+                         w.d_off, w.SA, w.rank, 4u, 0, app);
     }
     BZG_TRY(hipGetLastError());
     int cur = 1;
@@ -707,7 +712,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
         }
         ProfScope ps("rename_b", st, 16.0 * be);
         hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
-                           w.agg, w.d_off, w.SA, w.rank, 2 * h, app2);
+                           w.agg, w.d_off, w.SA, w.rank, 2 * h, 1, app2);
       }
       BZG_TRY(hipGetLastError());
       cur = nxt;

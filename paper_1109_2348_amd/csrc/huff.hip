@@ -41,11 +41,21 @@ struct HuffScratch {
   uint32_t w[MAXA];
   uint32_t lw[MAXA];  // leaf weights in key order
   uint16_t order[MAXA];
-  uint32_t wn[MAXA];  // internal node weights
   uint16_t parent[2 * MAXA];
 };
 
+// Column c (uniform, < 5) of a 5-register wave array, lane i (uniform).
+__device__ __forceinline__ uint32_t col_read(uint32_t c, uint32_t i, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                             uint32_t v4) {
+  uint32_t v = c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : c == 3 ? v3 : v4;
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
+}
+
 // One wave: code lengths for frequencies f[0..a).  All 64 lanes call it.
+// Sorted leaf weights, leaf ids and internal node weights/depths live in
+// registers across the wave (5 columns of 64), so the serial merge reads them
+// with readlane instead of LDS round trips; the deepest leaf is tracked during
+// the merge and parents are only walked for the accepted pass.
 __device__ void huff_lengths_wave(const uint32_t* f, int a, uint8_t* len, HuffScratch* hs) {
   const int l = (int)lane();
   for (int i = l; i < a; i += 64) hs->w[i] = f[i] ? f[i] : 1u;
@@ -62,44 +72,65 @@ __device__ void huff_lengths_wave(const uint32_t* f, int a, uint8_t* len, HuffSc
       hs->lw[r] = wi;
     }
     __builtin_amdgcn_wave_barrier();
-    if (l == 0) {
-      int li = 0, ni = 0, nn = 0;
-      for (int step = 0; step < a - 1; step++) {
-        uint32_t wsum = 0;
-        uint32_t ids[2];
-        for (int pick = 0; pick < 2; pick++) {
-          bool leaf = li < a && (ni >= nn || hs->lw[li] <= hs->wn[ni]);  // leaf ids sort below internal ids
-          if (leaf) {
-            ids[pick] = hs->order[li];
-            wsum += hs->lw[li];
-            li++;
-          } else {
-            ids[pick] = (uint32_t)(a + ni);
-            wsum += hs->wn[ni];
-            ni++;
-          }
+    uint32_t LW0, LW1, LW2, LW3, LW4, OR0, OR1, OR2, OR3, OR4;
+#define BZG_LD(q) \
+  LW##q = (q * 64 + l < a) ? hs->lw[q * 64 + l] : 0u; \
+  OR##q = (q * 64 + l < a) ? hs->order[q * 64 + l] : 0u;
+    BZG_LD(0) BZG_LD(1) BZG_LD(2) BZG_LD(3) BZG_LD(4)
+#undef BZG_LD
+    uint32_t WN0 = 0, WN1 = 0, WN2 = 0, WN3 = 0, WN4 = 0;  // internal node weights
+    uint32_t DN0 = 0, DN1 = 0, DN2 = 0, DN3 = 0, DN4 = 0;  // internal node depths
+    uint32_t li = 0, ni = 0, nn = 0, dmax = 0;
+    uint32_t lw_head = col_read(0, 0, LW0, LW1, LW2, LW3, LW4);
+    uint32_t wn_head = 0;
+    for (int step = 0; step < a - 1; step++) {
+      uint32_t wsum = 0, dnew = 0, ids[2];
+      for (int pick = 0; pick < 2; pick++) {
+        const bool leaf = li < (uint32_t)a && (ni >= nn || lw_head <= wn_head);  // leaf ids sort first
+        if (leaf) {
+          ids[pick] = col_read(li >> 6, li & 63, OR0, OR1, OR2, OR3, OR4);
+          wsum += lw_head;
+          li++;
+          lw_head = li < (uint32_t)a ? col_read(li >> 6, li & 63, LW0, LW1, LW2, LW3, LW4) : 0u;
+        } else {
+          ids[pick] = (uint32_t)a + ni;
+          wsum += wn_head;
+          const uint32_t d = col_read(ni >> 6, ni & 63, DN0, DN1, DN2, DN3, DN4);
+          dnew = d > dnew ? d : dnew;
+          ni++;
+          wn_head = ni < nn ? col_read(ni >> 6, ni & 63, WN0, WN1, WN2, WN3, WN4) : 0u;
         }
-        hs->wn[nn] = wsum;
+      }
+      dnew += 1;
+      dmax = dnew;
+      const uint32_t c = nn >> 6;
+      const bool me = (uint32_t)l == (nn & 63);
+#define BZG_PUT(q)                  \
+  if (c == q && me) {               \
+    WN##q = wsum;                   \
+    DN##q = dnew;                   \
+  }
+      BZG_PUT(0) BZG_PUT(1) BZG_PUT(2) BZG_PUT(3) BZG_PUT(4)
+#undef BZG_PUT
+      if (l == 0) {
         hs->parent[ids[0]] = (uint16_t)(a + nn);
         hs->parent[ids[1]] = (uint16_t)(a + nn);
-        nn++;
       }
+      if (ni == nn) wn_head = wsum;  // the new node heads an empty internal queue
+      nn++;
     }
-    __builtin_amdgcn_wave_barrier();
-    const int root = 2 * a - 2;
-    int maxd = 0;
-    for (int i = l; i < a; i += 64) {
-      int d = 0, v = i;
-      while (v != root && d < 2 * MAXA) {  // parents have larger ids: at most 2a steps
-        v = hs->parent[v];
-        d++;
-      }
-      len[i] = (uint8_t)d;
-      maxd = d > maxd ? d : maxd;
-    }
-    maxd = wave_max(maxd);
-    if (maxd <= MAXLEN) break;
+    if (dmax <= MAXLEN) break;
     for (int i = l; i < a; i += 64) hs->w[i] = 1u + hs->w[i] / 2u;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int root = 2 * a - 2;
+  for (int i = l; i < a; i += 64) {
+    int d = 0, v = i;
+    while (v != root && d < 2 * MAXA) {  // parents have larger ids: at most 2a steps
+      v = hs->parent[v];
+      d++;
+    }
+    len[i] = (uint8_t)d;
   }
   __builtin_amdgcn_wave_barrier();
 }
