@@ -174,23 +174,32 @@ struct AppendCtx {
 template <int M>
 __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint32_t* gl, int m, uint32_t blk_of_thread,
                               const uint32_t* gblk, uint32_t* sh32, uint32_t* wg_base /*LDS[4]*/) {
-  uint32_t nseg = (uint32_t)m, nsmall = 0, ntiles = 0, nact = 0;
+  uint32_t nseg = (uint32_t)m, nsmall = 0, ntiles = 0, nbig = 0;
   for (int g = 0; g < m; g++) {
-    nact += gl[g];
     if (gl[g] <= SMALL_MAX) nsmall += gl[g];
-    else ntiles += (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
+    else {
+      ntiles += (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
+      nbig += gl[g];
+    }
   }
-  uint32_t t_seg, t_small, t_tiles, t_act;
-  uint32_t e_seg = block_excl_sum<uint32_t, NT>(nseg, sh32, &t_seg);
-  uint32_t e_small = block_excl_sum<uint32_t, NT>(nsmall, sh32, &t_small);
-  uint32_t e_tiles = block_excl_sum<uint32_t, NT>(ntiles, sh32, &t_tiles);
-  (void)block_excl_sum<uint32_t, NT>(nact, sh32, &t_act);
+  // one scan of four packed counts.  Groups appended by a workgroup end in
+  // its (at most 4096) rows: segments <= 2048+1, small rows <= 4096+1024,
+  // tiles <= 2^21/4096+4 (13 bits each); large rows <= 2^21+4096 (22 bits).
+  __shared__ uint64_t sh64[NT / BZG_WAVE + 1];
+  (void)sh32;
+  const uint64_t packed = (uint64_t)nseg | ((uint64_t)nsmall << 13) | ((uint64_t)ntiles << 26) | ((uint64_t)nbig << 39);
+  uint64_t tot;
+  const uint64_t ex = block_excl_sum<uint64_t, NT>(packed, sh64, &tot);
+  const uint32_t M13 = (1u << 13) - 1u;
+  const uint32_t t_seg = (uint32_t)tot & M13, t_small = (uint32_t)(tot >> 13) & M13;
+  const uint32_t t_tiles = (uint32_t)(tot >> 26) & M13, t_big = (uint32_t)(tot >> 39) & ((1u << 22) - 1u);
+  const uint32_t e_seg = (uint32_t)ex & M13, e_small = (uint32_t)(ex >> 13) & M13, e_tiles = (uint32_t)(ex >> 26) & M13;
   if (threadIdx.x == 0) {
     wg_base[0] = t_seg ? atomicAdd(&a.cnt->n_segs, t_seg) : 0u;
     wg_base[1] = t_small ? atomicAdd(&a.cnt->small_total, t_small) : 0u;
     wg_base[2] = t_tiles ? atomicAdd(&a.cnt->big_tiles, t_tiles) : 0u;
-    if (t_act) atomicAdd(&a.cnt->active, t_act);
-    if (t_act > t_small) atomicAdd(&a.cnt->big_active, t_act - t_small);
+    if (t_small + t_big) atomicAdd(&a.cnt->active, t_small + t_big);
+    if (t_big) atomicAdd(&a.cnt->big_active, t_big);
   }
   __syncthreads();
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;

@@ -150,6 +150,8 @@ __device__ __forceinline__ uint64_t pack_costs(const BlockTables* T, int G, int 
 __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ nsyms, const uint32_t* __restrict__ freq,
                                                    const uint32_t* __restrict__ inuse, BlockTables* __restrict__ tabs,
                                                    uint64_t* __restrict__ cost, uint32_t* __restrict__ tf) {
+  __shared__ uint32_t sf[MAXA];
+  __shared__ int rng[MAXG][2];
   const uint32_t b = blockIdx.x;
   BlockTables* T = &tabs[b];
   uint32_t nu = 0;
@@ -157,6 +159,8 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
   const int a = (int)nu + 2;
   const uint32_t ns = nsyms[b];
   const int G = n_tables(ns, a);
+  for (int v = threadIdx.x; v < a; v += NT) sf[v] = freq[(size_t)b * MAXA + v];
+  __syncthreads();
   if (threadIdx.x == 0) {
     T->G = (uint32_t)G;
     T->nsel = (ns + GROUP - 1) / GROUP;
@@ -166,27 +170,34 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
     int gs = 0;
     for (int t = 0; t < G; t++) {
       int left = G - t, ge;
-      if (left == 1) ge = a - 1;
-      else {
+      uint64_t acc;
+      if (left == 1) {
+        ge = a - 1;
+        acc = rem;
+      } else {
         ge = gs;
-        uint64_t acc = freq[(size_t)b * MAXA + gs];
+        acc = sf[gs];
         while (ge + 1 <= a - left && acc * (uint64_t)left < rem) {
           ge++;
-          acc += freq[(size_t)b * MAXA + ge];
+          acc += sf[ge];
         }
       }
-      uint64_t part = 0;
-      for (int v = 0; v < a; v++) {
-        bool in = v >= gs && v <= ge;
-        T->len[t][v] = in ? 0 : 15;
-        if (in) part += freq[(size_t)b * MAXA + v];
-      }
-      rem -= part;
+      rng[t][0] = gs;
+      rng[t][1] = ge;
+      rem -= acc;
       gs = ge + 1;
     }
   }
   __syncthreads();
-  for (int v = threadIdx.x; v < a; v += NT) cost[(size_t)b * MAXA + v] = pack_costs(T, G, v);
+  for (int i = threadIdx.x; i < G * MAXA; i += NT) {
+    const int t = i / MAXA, v = i % MAXA;
+    if (v < a) T->len[t][v] = (v >= rng[t][0] && v <= rng[t][1]) ? 0 : 15;
+  }
+  for (int v = threadIdx.x; v < a; v += NT) {
+    uint64_t c = 0;
+    for (int t = 0; t < G; t++) c |= (uint64_t)((v >= rng[t][0] && v <= rng[t][1]) ? 0 : 15) << (10 * t);
+    cost[(size_t)b * MAXA + v] = c;
+  }
   for (int i = threadIdx.x; i < MAXG * MAXA; i += NT) tf[(size_t)b * MAXG * MAXA + i] = 0;
 }
 
@@ -365,6 +376,14 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
     lastv[x] = (int)g;
     sbits += idx + 1;
   }
+  // delta-coded lengths: 2|d| + 1 bits per symbol, 5 per table
+  for (int i = tid; i < G * MAXA; i += NT) {
+    const int t = i / MAXA, v = i % MAXA;
+    if (v < a) {
+      const int d = (int)lens[t][v] - (int)lens[t][v ? v - 1 : 0];
+      sbits += 2u * (uint32_t)(d < 0 ? -d : d) + 1u;
+    }
+  }
   uint32_t stot = block_sum<uint32_t, NT>(sbits, sh);
   if (tid == 0) {
     uint32_t ranges = 0;
@@ -372,17 +391,7 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
       uint32_t x = inuse[b * 8 + j];
       ranges += ((x & 0xFFFFu) ? 1u : 0u) + ((x >> 16) ? 1u : 0u);
     }
-    uint32_t hb = 16 + 16 * ranges + 3 + 15 + stot;
-    for (int t = 0; t < G; t++) {
-      hb += 5;
-      int cur = lens[t][0];
-      for (int v = 0; v < a; v++) {
-        int d = (int)lens[t][v] - cur;
-        hb += 2 * (uint32_t)(d < 0 ? -d : d) + 1;
-        cur = lens[t][v];
-      }
-    }
-    T->hdr_bits = hb;
+    T->hdr_bits = 16 + 16 * ranges + 3 + 15 + stot + 5u * (uint32_t)G;
   }
 }
 
@@ -423,17 +432,26 @@ hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base,
   uint64_t* cost = (uint64_t*)ws;
   uint32_t* tf = (uint32_t*)((char*)ws + ((size_t)nb * MAXA * 8 + 255) / 256 * 256);
   if (count_freq) hipLaunchKernelGGL(k_freq, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, err);
-  ProfScope ps("huffman", st, 0.0);  // symbol count is known on the device only
-  hipLaunchKernelGGL(k_huff_setup, dim3(nb), dim3(NT), 0, st, nsyms, freq, inuse, tabs, cost, tf);
+  // symbol counts are known on the device only: no algorithmic bytes recorded
+  {
+    ProfScope ps("huff_setup", st, 0.0);
+    hipLaunchKernelGGL(k_huff_setup, dim3(nb), dim3(NT), 0, st, nsyms, freq, inuse, tabs, cost, tf);
+  }
   for (int it = 0; it < 4; it++) {
-    if (ntiles)
+    if (ntiles) {
+      ProfScope ps("huff_assign", st, 0.0);
       hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 0, tile_blk, blk_tile0, syms, sym_base, nsyms,
                          sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
+    }
+    ProfScope ps("huff_build", st, 0.0);
     hipLaunchKernelGGL(k_huff_build, dim3(nb), dim3(BUILD_NT), 0, st, tabs, cost, tf);
   }
-  if (ntiles)
+  if (ntiles) {
+    ProfScope ps("huff_assign", st, 0.0);
     hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 1, tile_blk, blk_tile0, syms, sym_base, nsyms,
                        sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
+  }
+  ProfScope ps("huff_finish", st, 0.0);
   hipLaunchKernelGGL(k_huff_finish, dim3(nb), dim3(NT), 0, st, inuse, sel_base, (const uint8_t*)sel, selmtf, tabs);
   return hipGetLastError();
 }

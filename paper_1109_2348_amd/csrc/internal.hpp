@@ -41,8 +41,8 @@ struct ProfScope {
 // Tuning constants (fixed; every choice gives identical output).
 constexpr int NT = 256;                // threads per workgroup
 constexpr uint32_t RADIX_TILE = 4096;  // elements per tile of a segment radix pass
-constexpr uint32_t SMALL_T = 2048;     // packed elements per small-segment tile
-constexpr uint32_t SMALL_MAX = 2048;   // segments up to this size are sorted in LDS
+constexpr uint32_t SMALL_T = 1024;     // packed elements per small-segment tile
+constexpr uint32_t SMALL_MAX = 1024;   // segments up to this size are sorted in LDS
 constexpr uint32_t SMALL_CAP = SMALL_T + SMALL_MAX;  // LDS capacity of a small tile
 constexpr uint32_t RLE_TILE = 4096;    // input bytes per RLE1/CRC tile
 constexpr uint32_t MTF_CHUNK = 8192;   // symbols per move-to-front chunk
