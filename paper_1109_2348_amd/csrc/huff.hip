@@ -51,80 +51,80 @@ __device__ __forceinline__ uint32_t col_read(uint32_t c, uint32_t i, uint32_t v0
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
 }
 
-// One wave: code lengths for frequencies f[0..a).  All 64 lanes call it.
-// Sorted leaf weights, leaf ids and internal node weights/depths live in
-// registers across the wave (5 columns of 64), so the serial merge reads them
-// with readlane instead of LDS round trips; the deepest leaf is tracked during
-// the merge and parents are only walked for the accepted pass.
-__device__ void huff_lengths_wave(const uint32_t* f, int a, uint8_t* len, HuffScratch* hs) {
+// One wave, one Huffman pass over the weights hs->w[0..a): ranks the leaves
+// by (weight, id), runs the two-queue merge and returns the depth of the
+// deepest leaf; parents are left in hs->parent.  Sorted leaf weights, leaf ids
+// and internal node weights/depths live in registers across the wave (5
+// columns of 64) and are read with readlane.  All 64 lanes call it.
+__device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
   const int l = (int)lane();
-  for (int i = l; i < a; i += 64) hs->w[i] = f[i] ? f[i] : 1u;
-  for (;;) {
-    __builtin_amdgcn_wave_barrier();
-    for (int i = l; i < a; i += 64) {
-      uint32_t wi = hs->w[i];
-      int r = 0;
-      for (int j = 0; j < a; j++) {
-        uint32_t wj = hs->w[j];
-        r += (wj < wi || (wj == wi && j < i)) ? 1 : 0;
-      }
-      hs->order[r] = (uint16_t)i;
-      hs->lw[r] = wi;
+  __builtin_amdgcn_wave_barrier();
+  for (int i = l; i < a; i += 64) {
+    uint32_t wi = hs->w[i];
+    int r = 0;
+    for (int j = 0; j < a; j++) {
+      uint32_t wj = hs->w[j];
+      r += (wj < wi || (wj == wi && j < i)) ? 1 : 0;
     }
-    __builtin_amdgcn_wave_barrier();
-    uint32_t LW0, LW1, LW2, LW3, LW4, OR0, OR1, OR2, OR3, OR4;
+    hs->order[r] = (uint16_t)i;
+    hs->lw[r] = wi;
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint32_t LW0, LW1, LW2, LW3, LW4, OR0, OR1, OR2, OR3, OR4;
 #define BZG_LD(q) \
   LW##q = (q * 64 + l < a) ? hs->lw[q * 64 + l] : 0u; \
   OR##q = (q * 64 + l < a) ? hs->order[q * 64 + l] : 0u;
-    BZG_LD(0) BZG_LD(1) BZG_LD(2) BZG_LD(3) BZG_LD(4)
+  BZG_LD(0) BZG_LD(1) BZG_LD(2) BZG_LD(3) BZG_LD(4)
 #undef BZG_LD
-    uint32_t WN0 = 0, WN1 = 0, WN2 = 0, WN3 = 0, WN4 = 0;  // internal node weights
-    uint32_t DN0 = 0, DN1 = 0, DN2 = 0, DN3 = 0, DN4 = 0;  // internal node depths
-    uint32_t li = 0, ni = 0, nn = 0, dmax = 0;
-    uint32_t lw_head = col_read(0, 0, LW0, LW1, LW2, LW3, LW4);
-    uint32_t wn_head = 0;
-    for (int step = 0; step < a - 1; step++) {
-      uint32_t wsum = 0, dnew = 0, ids[2];
-      for (int pick = 0; pick < 2; pick++) {
-        const bool leaf = li < (uint32_t)a && (ni >= nn || lw_head <= wn_head);  // leaf ids sort first
-        if (leaf) {
-          ids[pick] = col_read(li >> 6, li & 63, OR0, OR1, OR2, OR3, OR4);
-          wsum += lw_head;
-          li++;
-          lw_head = li < (uint32_t)a ? col_read(li >> 6, li & 63, LW0, LW1, LW2, LW3, LW4) : 0u;
-        } else {
-          ids[pick] = (uint32_t)a + ni;
-          wsum += wn_head;
-          const uint32_t d = col_read(ni >> 6, ni & 63, DN0, DN1, DN2, DN3, DN4);
-          dnew = d > dnew ? d : dnew;
-          ni++;
-          wn_head = ni < nn ? col_read(ni >> 6, ni & 63, WN0, WN1, WN2, WN3, WN4) : 0u;
-        }
+  uint32_t WN0 = 0, WN1 = 0, WN2 = 0, WN3 = 0, WN4 = 0;  // internal node weights
+  uint32_t DN0 = 0, DN1 = 0, DN2 = 0, DN3 = 0, DN4 = 0;  // internal node depths
+  uint32_t li = 0, ni = 0, nn = 0, dmax = 0;
+  uint32_t lw_head = col_read(0, 0, LW0, LW1, LW2, LW3, LW4);
+  uint32_t wn_head = 0;
+  for (int step = 0; step < a - 1; step++) {
+    uint32_t wsum = 0, dnew = 0, ids[2];
+    for (int pick = 0; pick < 2; pick++) {
+      const bool leaf = li < (uint32_t)a && (ni >= nn || lw_head <= wn_head);  // leaf ids sort first
+      if (leaf) {
+        ids[pick] = col_read(li >> 6, li & 63, OR0, OR1, OR2, OR3, OR4);
+        wsum += lw_head;
+        li++;
+        lw_head = li < (uint32_t)a ? col_read(li >> 6, li & 63, LW0, LW1, LW2, LW3, LW4) : 0u;
+      } else {
+        ids[pick] = (uint32_t)a + ni;
+        wsum += wn_head;
+        const uint32_t d = col_read(ni >> 6, ni & 63, DN0, DN1, DN2, DN3, DN4);
+        dnew = d > dnew ? d : dnew;
+        ni++;
+        wn_head = ni < nn ? col_read(ni >> 6, ni & 63, WN0, WN1, WN2, WN3, WN4) : 0u;
       }
-      dnew += 1;
-      dmax = dnew;
-      const uint32_t c = nn >> 6;
-      const bool me = (uint32_t)l == (nn & 63);
-#define BZG_PUT(q)                  \
-  if (c == q && me) {               \
-    WN##q = wsum;                   \
-    DN##q = dnew;                   \
-  }
-      BZG_PUT(0) BZG_PUT(1) BZG_PUT(2) BZG_PUT(3) BZG_PUT(4)
-#undef BZG_PUT
-      if (l == 0) {
-        hs->parent[ids[0]] = (uint16_t)(a + nn);
-        hs->parent[ids[1]] = (uint16_t)(a + nn);
-      }
-      if (ni == nn) wn_head = wsum;  // the new node heads an empty internal queue
-      nn++;
     }
-    if (dmax <= MAXLEN) break;
-    for (int i = l; i < a; i += 64) hs->w[i] = 1u + hs->w[i] / 2u;
+    dnew += 1;
+    dmax = dnew;
+    const uint32_t c = nn >> 6;
+    const bool me = (uint32_t)l == (nn & 63);
+#define BZG_PUT(q)    \
+  if (c == q && me) { \
+    WN##q = wsum;     \
+    DN##q = dnew;     \
+  }
+    BZG_PUT(0) BZG_PUT(1) BZG_PUT(2) BZG_PUT(3) BZG_PUT(4)
+#undef BZG_PUT
+    if (l == 0) {
+      hs->parent[ids[0]] = (uint16_t)(a + nn);
+      hs->parent[ids[1]] = (uint16_t)(a + nn);
+    }
+    if (ni == nn) wn_head = wsum;  // the new node heads an empty internal queue
+    nn++;
   }
   __builtin_amdgcn_wave_barrier();
+  return dmax;
+}
+
+// One wave: leaf depths from the parents of the last pass.
+__device__ void huff_walk_wave(int a, const HuffScratch* hs, uint8_t* len) {
   const int root = 2 * a - 2;
-  for (int i = l; i < a; i += 64) {
+  for (int i = (int)lane(); i < a; i += 64) {
     int d = 0, v = i;
     while (v != root && d < 2 * MAXA) {  // parents have larger ids: at most 2a steps
       v = hs->parent[v];
@@ -132,7 +132,6 @@ __device__ void huff_lengths_wave(const uint32_t* f, int a, uint8_t* len, HuffSc
     }
     len[i] = (uint8_t)d;
   }
-  __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ int n_tables(uint32_t ns, int a) {
@@ -227,7 +226,11 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
   const uint16_t* S = syms + sym_base[b];
   const uint64_t sb = sel_base[b];
   if (mode == 0) {
-    for (uint32_t v = threadIdx.x; v < a; v += NT) sc[v] = cost[(size_t)b * MAXA + v];
+    for (uint32_t v = threadIdx.x; v < a; v += NT) {
+      uint64_t c = 0;
+      for (uint32_t t = 0; t < G; t++) c |= (uint64_t)T->len[t][v] << (10 * t);
+      sc[v] = c;
+    }
     for (uint32_t i = threadIdx.x; i < MAXG * MAXA; i += NT) (&stf[0][0])[i] = 0;
   } else {
     for (uint32_t i = threadIdx.x; i < G * MAXA; i += NT) {
@@ -279,34 +282,47 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
   }
 }
 
-// Per block, one wave per table: new lengths from the counts; packed costs;
-// counters cleared for the next pass.
-constexpr int BUILD_NT = MAXG * BZG_WAVE;
+// One workgroup per (block, table): new code lengths from the counts.  The
+// oracle halves the weights (w -> 1 + w/2) and rebuilds until no length
+// exceeds 17; here BUILD_WAVES waves try k = base .. base+7 halvings at once
+// and the smallest k that fits wins -- the same k the sequential loop stops
+// at.  The counts are cleared for the next pass.
+constexpr int BUILD_WAVES = 8;
+constexpr int BUILD_NT = BUILD_WAVES * BZG_WAVE;
 
-__global__ __launch_bounds__(BUILD_NT) void k_huff_build(BlockTables* __restrict__ tabs, uint64_t* __restrict__ cost,
-                                                         uint32_t* __restrict__ tf) {
-  __shared__ uint32_t sf[MAXG][MAXA];
-  __shared__ uint8_t sl[MAXG][MAXA];
-  __shared__ HuffScratch hs[MAXG];
-  const uint32_t b = blockIdx.x;
+__global__ __launch_bounds__(BUILD_NT) void k_huff_build(BlockTables* __restrict__ tabs, uint32_t* __restrict__ tf) {
+  __shared__ uint32_t sf[MAXA];
+  __shared__ HuffScratch hs[BUILD_WAVES];
+  __shared__ uint32_t ok[BUILD_WAVES];
+  const uint32_t b = blockIdx.x, t = blockIdx.y;
   BlockTables* T = &tabs[b];
   const int G = (int)T->G, a = (int)T->alpha;
-  uint32_t* F = tf + (size_t)b * MAXG * MAXA;
-  for (int i = threadIdx.x; i < MAXG * MAXA; i += BUILD_NT) {
-    (&sf[0][0])[i] = F[i];
+  if ((int)t >= G) return;
+  uint32_t* F = tf + ((size_t)b * MAXG + t) * MAXA;
+  for (int i = threadIdx.x; i < a; i += BUILD_NT) {
+    sf[i] = F[i];
     F[i] = 0;
   }
   __syncthreads();
   const int w = threadIdx.x / BZG_WAVE;
-  if (w < G) {
-    huff_lengths_wave(sf[w], a, sl[w], &hs[w]);
-    for (int v = lane(); v < a; v += BZG_WAVE) T->len[w][v] = sl[w][v];
-  }
-  __syncthreads();
-  for (int v = threadIdx.x; v < a; v += BUILD_NT) {
-    uint64_t c = 0;
-    for (int t = 0; t < G; t++) c |= (uint64_t)sl[t][v] << (10 * t);
-    cost[(size_t)b * MAXA + v] = c;
+  for (int base = 0;; base += BUILD_WAVES) {
+    const int k = base + w;
+    for (int i = lane(); i < a; i += BZG_WAVE) {
+      uint32_t x = sf[i] ? sf[i] : 1u;
+      for (int r = 0; r < k && x > 2u; r++) x = 1u + x / 2u;  // 1 and 2 are fixed points
+      hs[w].w[i] = x;
+    }
+    const uint32_t dmax = huff_pass_wave(a, &hs[w]);
+    if (lane() == 0) ok[w] = dmax <= (uint32_t)MAXLEN ? 1u : 0u;
+    __syncthreads();
+    int first = BUILD_WAVES;
+    for (int q = BUILD_WAVES - 1; q >= 0; q--)
+      if (ok[q]) first = q;
+    if (first < BUILD_WAVES) {
+      if (w == first) huff_walk_wave(a, &hs[w], &T->len[t][0]);
+      break;
+    }
+    __syncthreads();
   }
 }
 
@@ -444,7 +460,7 @@ hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base,
                          sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
     }
     ProfScope ps("huff_build", st, 0.0);
-    hipLaunchKernelGGL(k_huff_build, dim3(nb), dim3(BUILD_NT), 0, st, tabs, cost, tf);
+    hipLaunchKernelGGL(k_huff_build, dim3(nb, MAXG), dim3(BUILD_NT), 0, st, tabs, tf);
   }
   if (ntiles) {
     ProfScope ps("huff_assign", st, 0.0);
