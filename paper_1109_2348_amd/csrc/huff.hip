@@ -39,7 +39,8 @@ constexpr uint32_t ASSIGN_SYMS = ASSIGN_SUB * GROUP;
 
 struct HuffScratch {
   uint32_t w[MAXA];
-  uint32_t lw[MAXA];  // leaf weights in key order
+  uint32_t key[MAXA];  // (weight << 9) | id
+  uint32_t lw[MAXA];   // leaf weights in key order
   uint16_t order[MAXA];
   uint16_t parent[2 * MAXA];
 };
@@ -58,16 +59,35 @@ __device__ __forceinline__ uint32_t col_read(uint32_t c, uint32_t i, uint32_t v0
 // columns of 64) and are read with readlane.  All 64 lanes call it.
 __device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
   const int l = (int)lane();
+  // (weight, id) as one unique key: weights are symbol counts < 2^22
+  for (int i = l; i < a; i += 64) hs->key[i] = (hs->w[i] << 9) | (uint32_t)i;
   __builtin_amdgcn_wave_barrier();
-  for (int i = l; i < a; i += 64) {
-    uint32_t wi = hs->w[i];
-    int r = 0;
-    for (int j = 0; j < a; j++) {
-      uint32_t wj = hs->w[j];
-      r += (wj < wi || (wj == wi && j < i)) ? 1 : 0;
+  {
+    uint32_t k[5], r[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+      k[q] = (q * 64 + l < a) ? hs->key[q * 64 + l] : 0xFFFFFFFFu;
+      r[q] = 0;
     }
-    hs->order[r] = (uint16_t)i;
-    hs->lw[r] = wi;
+    int j = 0;
+    for (; j + 4 <= a; j += 4) {
+      const uint32_t k0 = hs->key[j], k1 = hs->key[j + 1], k2 = hs->key[j + 2], k3 = hs->key[j + 3];
+#pragma unroll
+      for (int q = 0; q < 5; q++)
+        r[q] += (uint32_t)(k0 < k[q]) + (uint32_t)(k1 < k[q]) + (uint32_t)(k2 < k[q]) + (uint32_t)(k3 < k[q]);
+    }
+    for (; j < a; j++) {
+      const uint32_t kj = hs->key[j];
+#pragma unroll
+      for (int q = 0; q < 5; q++) r[q] += (uint32_t)(kj < k[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+      if (q * 64 + l < a) {
+        hs->order[r[q]] = (uint16_t)(q * 64 + l);
+        hs->lw[r[q]] = k[q] >> 9;
+      }
+    }
   }
   __builtin_amdgcn_wave_barrier();
   uint32_t LW0, LW1, LW2, LW3, LW4, OR0, OR1, OR2, OR3, OR4;
@@ -287,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
 // exceeds 17; here BUILD_WAVES waves try k = base .. base+7 halvings at once
 // and the smallest k that fits wins -- the same k the sequential loop stops
 // at.  The counts are cleared for the next pass.
-constexpr int BUILD_WAVES = 8;
+constexpr int BUILD_WAVES = 1;
 constexpr int BUILD_NT = BUILD_WAVES * BZG_WAVE;
 
 __global__ __launch_bounds__(BUILD_NT) void k_huff_build(BlockTables* __restrict__ tabs, uint32_t* __restrict__ tf) {
