@@ -23,9 +23,12 @@
  *    and per planning step); outputs are complete when the call returns 0.
  *  - Return values: 0 on success, a negative BZG_E* code otherwise, with a
  *    message in bzg_last_error().  No exception crosses the ABI.
- *  - A context may be used by one host thread at a time.  Scratch memory is
- *    owned by the context and grows on demand (hipMalloc); it is released by
- *    bzg_destroy().
+ *  - Calls on one context run one at a time (the context holds a lock for
+ *    the whole call); to overlap work from several host threads give each
+ *    thread its own context and stream.  Scratch memory is owned by the
+ *    context and grows on demand (hipMalloc); it is released by
+ *    bzg_destroy().  bzg_last_error() gives the message of the latest
+ *    call on the context.
  *  - Everything is integer arithmetic; outputs are bit-exact functions of the
  *    inputs (independent of launch sizes and scheduling).
  */
@@ -128,14 +131,40 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
  * becoming the next block, so every stream respects the decoder limit of its
  * header digit.  Empty blocks are skipped; no blocks gives the 14-byte empty
  * stream.
- *   d_in        uint8 input; blocks at h_offsets (any length; total < 2^31).
+ *   d_in        uint8 input; blocks at h_offsets (any length; total < 2^31);
+ *               may be NULL when every block is empty.
  *   d_out       output stream; out_cap bytes, 4-byte aligned.
- *   h_out_bytes host uint64 output: stream length in bytes (also set, to the
- *               required capacity, when BZG_ECAPACITY is returned).
+ *   h_out_bytes host uint64 output: stream length in bytes (also set when
+ *               BZG_ECAPACITY is returned; the capacity needed is that
+ *               rounded up to a multiple of 4).
  *   h_n_blocks  optional host uint32 output: blocks in the stream.
  */
 int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level,
                     uint8_t* d_out, uint64_t out_cap, uint64_t* h_out_bytes, uint32_t* h_n_blocks, void* stream);
+
+/*
+ * Many independent streams in one pass (Sec. 4: the stages are data-parallel
+ * over blocks, so the blocks of several requests are processed together):
+ * request r is input blocks [h_req_blocks[r], h_req_blocks[r+1]) and becomes
+ * one bzip2 stream of its own, identical to what compress_blocks gives for
+ * those blocks alone.  One level for all requests.
+ *   d_in, h_offsets, n_blocks  as for compress_blocks (all requests' blocks,
+ *                  in request order).
+ *   h_req_blocks   n_req+1 host block indices; [0] = 0, [n_req] = n_blocks,
+ *                  non-decreasing.  A request with no bytes gets the 14-byte
+ *                  empty stream.  n_req <= 65535.
+ *   d_out          output, 4-byte aligned; stream r is written from byte
+ *                  h_out_offsets[r] and must end by h_out_offsets[r+1].
+ *   h_out_offsets  n_req+1 host byte offsets, multiples of 4, non-decreasing.
+ *                  Bytes of a range past its stream's rounded-up last word
+ *                  are left untouched.
+ *   h_out_bytes    host uint64[n_req] output: each stream's length in bytes.
+ * Returns BZG_ECAPACITY (h_out_bytes still filled; nothing packed) when a
+ * stream, rounded up to 4 bytes, does not fit its range.
+ */
+int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
+                   const uint32_t* h_req_blocks, uint32_t n_req, int level, uint8_t* d_out,
+                   const uint64_t* h_out_offsets, uint64_t* h_out_bytes, void* stream);
 
 /*
  * Diagnostics: per-kernel timing.  While enabled, every instrumented launch

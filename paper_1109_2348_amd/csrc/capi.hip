@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,12 +35,13 @@ hipError_t huff_run(uint32_t, const uint16_t*, const uint64_t*, const uint32_t*,
                     const uint32_t*, void*, hipStream_t);
 size_t huff_workspace_bytes(uint32_t nb);
 uint32_t huff_assign_groups();
-hipError_t pack_layout(uint32_t, const void*, int, const uint64_t*, uint64_t*, const uint32_t*, uint64_t*,
-                       hipStream_t);
+hipError_t pack_layout(uint32_t, uint32_t, const uint32_t*, const uint64_t*, const void*, int, const uint64_t*,
+                       uint64_t*, const uint32_t*, uint64_t*, hipStream_t);
+hipError_t zero_streams(uint32_t, uint64_t, const uint64_t*, const uint64_t*, uint32_t*, hipStream_t);
 hipError_t pack_run(uint32_t, const void*, int, const uint64_t*, const uint32_t*, const uint32_t*, const uint32_t*,
                     const uint64_t*, const uint8_t*, const uint8_t*, const uint64_t*, uint32_t, const uint32_t*,
-                    const uint32_t*, const uint16_t*, const uint64_t*, const uint32_t*, int, const uint64_t*,
-                    uint32_t*, hipStream_t);
+                    const uint32_t*, const uint16_t*, const uint64_t*, const uint32_t*, int, uint32_t,
+                    const uint64_t*, const uint64_t*, uint32_t*, hipStream_t);
 hipError_t tables_export(uint32_t, const void*, uint8_t*, hipStream_t);
 hipError_t body_sizes(uint32_t, const void*, const uint64_t*, uint64_t*, uint32_t*, hipStream_t);
 }  // namespace bzg
@@ -82,6 +84,7 @@ void Profiler::collect() {
 using namespace bzg;
 
 struct bzg_ctx {
+  std::mutex mu;  // calls on one context run one at a time
   int device = 0;
   Profiler prof;
   std::string err;
@@ -269,6 +272,7 @@ const char* bzg_last_error(const bzg_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int bzg_profile(bzg_ctx* ctx, int enable) {
   if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   if (enable) ctx->prof.acc.clear();
   ctx->prof.on = enable != 0;
   return 0;
@@ -276,6 +280,7 @@ int bzg_profile(bzg_ctx* ctx, int enable) {
 
 int bzg_profile_read(bzg_ctx* ctx, char* buf, size_t cap) {
   if (!ctx || !buf || cap == 0) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   std::string s;
   char line[256];
   for (auto& kv : ctx->prof.acc) {
@@ -300,6 +305,7 @@ uint64_t bzg_compress_bound(uint64_t n_bytes, uint32_t n_blocks) {
 int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
                       uint8_t* d_bwt, uint32_t* d_primary, uint32_t* d_sa, void* stream) {
   if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
   if (!h_offsets || !d_bwt || !d_primary || (n_blocks && !d_in)) return fail(ctx, BZG_EINVAL, "null pointer");
@@ -334,6 +340,7 @@ int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offse
 int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* h_offsets, uint32_t n_blocks,
                      uint16_t* d_syms, uint32_t* d_nsyms, uint8_t* d_inuse, void* stream) {
   if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
   if (!h_offsets || !d_syms || !d_nsyms || !d_inuse || (n_blocks && !d_bwt)) return fail(ctx, BZG_EINVAL, "null pointer");
@@ -380,6 +387,7 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
                          const uint64_t* h_sym_offsets, uint32_t n_blocks, uint8_t* d_out,
                          const uint64_t* h_out_offsets, uint64_t* d_nbits, uint8_t* d_tables, void* stream) {
   if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
   if (!h_sym_offsets || !h_out_offsets || !d_nbits || (n_blocks && (!d_syms || !d_nsyms || !d_inuse || !d_out)))
@@ -448,7 +456,7 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
                 d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
   HIPX(body_sizes(n_blocks, d_tabs, d_obyte, d_nbits, d_err, st));
-  HIPX(pack_layout(n_blocks, d_tabs, 1, d_obyte, d_blkbit, nullptr, d_info, st));
+  HIPX(pack_layout(n_blocks, 1, nullptr, nullptr, d_tabs, 1, d_obyte, d_blkbit, nullptr, d_info, st));
   HIPX(hipMemcpyAsync(pin, d_err, 4, hipMemcpyDeviceToHost, st));
   HIPX(hipStreamSynchronize(st));
   uint32_t ef = *(uint32_t*)pin;
@@ -456,43 +464,55 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   if (ef & 4u) return fail(ctx, BZG_ECAPACITY, "huffman: a block body does not fit its output range");
   HIPX(hipMemsetAsync(d_out + h_out_offsets[0], 0, h_out_offsets[n_blocks] - h_out_offsets[0], st));
   HIPX(pack_run(n_blocks, d_tabs, 1, d_blkbit, nullptr, nullptr, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
-                d_gofs, ntiles, d_tile_blk, d_blk_tile0, d_syms, d_sbase, d_nsyms, 9, d_info, (uint32_t*)d_out, st));
+                d_gofs, ntiles, d_tile_blk, d_blk_tile0, d_syms, d_sbase, d_nsyms, 9, 0, nullptr, d_info,
+                (uint32_t*)d_out, st));
   if (d_tables) HIPX(tables_export(n_blocks, d_tabs, d_tables, st));
   HIPX(hipStreamSynchronize(st));
   return 0;
 }
 
-int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level,
-                    uint8_t* d_out, uint64_t out_cap, uint64_t* h_out_bytes, uint32_t* h_n_blocks, void* stream) {
-  if (!ctx) return BZG_EINVAL;
-  ctx->err.clear();
-  ProfGuard pg(ctx);
-  if (!h_offsets || !d_out || !h_out_bytes || (n_blocks && !d_in)) return fail(ctx, BZG_EINVAL, "null pointer");
-  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
-  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
-  if ((uintptr_t)d_out & 3) return fail(ctx, BZG_EINVAL, "d_out must be 4-byte aligned");
-  hipStream_t st = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// One bzip2 stream per request: request r is input blocks
+// [req_blocks[r], req_blocks[r+1]) and its stream goes to d_out + out_off[r],
+// at most out_off[r+1] - out_off[r] bytes.  All requests' blocks go through
+// every stage together.
+int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
+                  const uint32_t* req_blocks, uint32_t n_req, int level, uint8_t* d_out, const uint64_t* out_off,
+                  uint64_t* h_out_bytes, uint32_t* h_n_blocks, hipStream_t st) {
   HIPX(hipSetDevice(ctx->device));
   const uint64_t in0 = n_blocks ? h_offsets[0] : 0;
   const uint64_t total = n_blocks ? h_offsets[n_blocks] - in0 : 0;
   if (total >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "input too large for one call (2^31 bytes)");
   const uint8_t* in = d_in ? d_in + in0 : nullptr;
-  // input blocks (relative to in), empty ones dropped
+  // input blocks (relative to in), empty ones dropped; breq = owning request
   std::vector<uint64_t> boff{0};
-  for (uint32_t k = 0; k < n_blocks; k++)
-    if (h_offsets[k + 1] > h_offsets[k]) boff.push_back(h_offsets[k + 1] - in0);
+  std::vector<uint32_t> breq;
+  for (uint32_t r = 0; r < n_req; r++)
+    for (uint32_t k = req_blocks[r]; k < req_blocks[r + 1]; k++)
+      if (h_offsets[k + 1] > h_offsets[k]) {
+        boff.push_back(h_offsets[k + 1] - in0);
+        breq.push_back(r);
+      }
   void* pin;
-  int rc = ensure_pin(ctx, 64 * 1024 + 16 * (boff.size() + total / 100000 + 16), &pin);
+  int rc = ensure_pin(ctx, 64 * 1024 + 16 * (boff.size() + total / 100000 + 16) + 16 * (size_t)n_req, &pin);
   if (rc) return rc;
   uint32_t nb = (uint32_t)boff.size() - 1;
-  if (nb == 0) {
+  if (h_n_blocks) *h_n_blocks = 0;
+  if (nb == 0) {  // every stream is the 14-byte empty stream
     uint8_t* p = (uint8_t*)pin;
     const uint8_t empty[14] = {'B', 'Z', 'h', (uint8_t)('0' + level), 0x17, 0x72, 0x45, 0x38, 0x50, 0x90, 0, 0, 0, 0};
-    *h_out_bytes = 14;
-    if (h_n_blocks) *h_n_blocks = 0;
-    if (out_cap < 14) return fail(ctx, BZG_ECAPACITY, "output needs 14 bytes");
     memcpy(p, empty, 14);
-    HIPX(hipMemcpyAsync(d_out, p, 14, hipMemcpyHostToDevice, st));
+    bool short_cap = false;
+    for (uint32_t r = 0; r < n_req; r++) {
+      h_out_bytes[r] = 14;
+      short_cap |= out_off[r + 1] - out_off[r] < 14;
+    }
+    if (short_cap) return fail(ctx, BZG_ECAPACITY, "an empty stream needs 14 bytes");
+    for (uint32_t r = 0; r < n_req; r++)
+      HIPX(hipMemcpyAsync(d_out + out_off[r], p, 14, hipMemcpyHostToDevice, st));
     HIPX(hipStreamSynchronize(st));
     return 0;
   }
@@ -553,17 +573,25 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
     HIPX(hipMemcpyAsync(h_cut, d_cuts, over.size() * 4, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
     std::vector<uint64_t> nboff{0};
+    std::vector<uint32_t> nbreq;
     size_t oi = 0;
     for (uint32_t b = 0; b < nb; b++) {
       if (oi < over.size() && over[oi] == b) {
         uint64_t cut = h_cut[oi++];
         if (cut == 0 || cut >= boff[b + 1] - boff[b]) return fail(ctx, BZG_EINVAL, "internal: bad block cut");
         nboff.push_back(boff[b] + cut);
+        nbreq.push_back(breq[b]);
       }
       nboff.push_back(boff[b + 1]);
+      nbreq.push_back(breq[b]);
     }
     boff.swap(nboff);
+    breq.swap(nbreq);
   }
+  // ---- streams: block range of every request (blocks are in request order)
+  std::vector<uint32_t> rb(n_req + 1, nb);
+  for (uint32_t b = nb; b-- > 0;) rb[breq[b]] = b;
+  for (uint32_t r = n_req; r-- > 0;) rb[r] = std::min(rb[r], rb[r + 1]);
   // ---- RLE1 output layout
   std::vector<uint32_t> roff(nb + 1, 0);
   std::vector<uint64_t> rbase(nb + 1, 0);
@@ -589,7 +617,8 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
                  sz<uint32_t>(nb) + sz<uint32_t>((size_t)nb * 8) + sz<uint32_t>((size_t)nb * MAXA) + sz<uint32_t>(4) +
                  sz<uint64_t>(nb + 1) + sz<uint8_t>(ng + 1) * 2 + sz<uint64_t>(ng + 1) * 2 +
                  sz<uint64_t>(scan_tmp_elems(ng + 1)) + block_tables_bytes() * nb + 256 + sz<uint64_t>(nb) +
-                 sz<uint32_t>(nptiles + 1) + sz<uint32_t>(nb + 1) + sz<uint64_t>(4) + sz<uint32_t>(nb + 1) +
+                 sz<uint32_t>(nptiles + 1) + sz<uint32_t>(nb + 1) + sz<uint64_t>(2 * (size_t)n_req + 2) +
+                 sz<uint32_t>(n_req + 1) + sz<uint64_t>(n_req) + sz<uint32_t>(nb + 1) +
                  sz<uint32_t>(natiles + 1) + sz<uint32_t>(nb + 1) + huff_workspace_bytes(nb) +
                  std::max(bwt_ws, mtf_workspace_bytes(roff)) + 16384;
   void* ws0;
@@ -614,7 +643,9 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
   uint64_t* d_blkbit = c0.take<uint64_t>(nb);
   uint32_t* d_ptile_blk = c0.take<uint32_t>(nptiles + 1);
   uint32_t* d_pblk_tile0 = c0.take<uint32_t>(nb + 1);
-  uint64_t* d_info = c0.take<uint64_t>(4);
+  uint64_t* d_info = c0.take<uint64_t>(2 * (size_t)n_req + 2);
+  uint32_t* d_rb = c0.take<uint32_t>(n_req + 1);
+  uint64_t* d_rout = c0.take<uint64_t>(n_req);
   uint32_t* d_roff = c0.take<uint32_t>(nb + 1);
   uint32_t* d_atile_blk = c0.take<uint32_t>(natiles + 1);
   uint32_t* d_ablk_tile0 = c0.take<uint32_t>(nb + 1);
@@ -646,30 +677,89 @@ int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets
   HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,
                 natiles, d_atile_blk, d_ablk_tile0, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
-  HIPX(pack_layout(nb, d_tabs, 0, nullptr, d_blkbit, d_crc, d_info, st));
+  HIPX(hipMemcpyAsync(d_rb, rb.data(), (n_req + 1) * 4, hipMemcpyHostToDevice, st));
+  HIPX(hipMemcpyAsync(d_rout, out_off, n_req * 8, hipMemcpyHostToDevice, st));
+  HIPX(pack_layout(nb, n_req, d_rb, d_rout, d_tabs, 0, nullptr, d_blkbit, d_crc, d_info, st));
   uint64_t* h_info = (uint64_t*)pin;
-  HIPX(hipMemcpyAsync(h_info, d_info, 16, hipMemcpyDeviceToHost, st));
-  HIPX(hipMemcpyAsync(h_info + 2, d_err, 4, hipMemcpyDeviceToHost, st));
+  HIPX(hipMemcpyAsync(h_info, d_info, 16 * (size_t)n_req, hipMemcpyDeviceToHost, st));
+  HIPX(hipMemcpyAsync(h_info + 2 * (size_t)n_req, d_err, 4, hipMemcpyDeviceToHost, st));
   HIPX(hipStreamSynchronize(st));
-  const uint64_t bits = h_info[0];
-  const uint32_t ef = (uint32_t)h_info[2];
+  const uint32_t ef = (uint32_t)h_info[2 * (size_t)n_req];
   if (ef) return fail(ctx, BZG_EDATA, "internal: inconsistent symbol stream");
-  const uint64_t bytes = (bits + 7) / 8, words = (bits + 31) / 32;
-  *h_out_bytes = bytes;
+  uint64_t max_words = 0, out_total = 0;
+  int short_r = -1;
+  for (uint32_t r = 0; r < n_req; r++) {
+    const uint64_t bits = h_info[2 * r], words = (bits + 31) / 32;
+    h_out_bytes[r] = (bits + 7) / 8;
+    out_total += h_out_bytes[r];
+    max_words = std::max(max_words, words);
+    if (words * 4 > out_off[r + 1] - out_off[r] && short_r < 0) short_r = (int)r;
+  }
   if (h_n_blocks) *h_n_blocks = nb;
-  if (words * 4 > out_cap)
-    return fail(ctx, BZG_ECAPACITY, "output needs " + std::to_string(words * 4) + " bytes (4-byte rounded)");
+  if (short_r >= 0)
+    return fail(ctx, BZG_ECAPACITY,
+                "stream " + std::to_string(short_r) + " needs " +
+                    std::to_string((h_info[2 * short_r] + 31) / 32 * 4) + " bytes (4-byte rounded)");
   // ---- pack
-  HIPX(hipMemsetAsync(d_out, 0, words * 4, st));
   if (nptiles) HIPX(hipMemcpyAsync(d_ptile_blk, ptile_blk.data(), nptiles * 4, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
   {
-    ProfScope ps("pack", st, 2.0 * N + (double)bytes);  // symbols in, stream out
+    ProfScope ps("pack", st, 2.0 * N + (double)out_total);  // symbols in, streams out
+    HIPX(zero_streams(n_req, max_words, d_rout, d_info, (uint32_t*)d_out, st));
     HIPX(pack_run(nb, d_tabs, 0, d_blkbit, d_crc, d_primary, d_inuse, d_selb, d_sel, d_selmtf, d_gofs, nptiles,
-                  d_ptile_blk, d_pblk_tile0, d_syms, d_sbase, d_nsyms, level, d_info, (uint32_t*)d_out, st));
+                  d_ptile_blk, d_pblk_tile0, d_syms, d_sbase, d_nsyms, level, n_req, d_rout, d_info,
+                  (uint32_t*)d_out, st));
   }
   HIPX(hipStreamSynchronize(st));
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level,
+                    uint8_t* d_out, uint64_t out_cap, uint64_t* h_out_bytes, uint32_t* h_n_blocks, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  ProfGuard pg(ctx);
+  if (!h_offsets || !d_out || !h_out_bytes) return fail(ctx, BZG_EINVAL, "null pointer");
+  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
+  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
+  if (n_blocks && h_offsets[n_blocks] > h_offsets[0] && !d_in) return fail(ctx, BZG_EINVAL, "null input");
+  if ((uintptr_t)d_out & 3) return fail(ctx, BZG_EINVAL, "d_out must be 4-byte aligned");
+  const uint32_t rq[2] = {0, n_blocks};
+  const uint64_t oo[2] = {0, out_cap & ~3ull};
+  return compress_impl(ctx, d_in, h_offsets, n_blocks, rq, 1, level, d_out, oo, h_out_bytes, h_n_blocks,
+                       (hipStream_t)stream);
+}
+
+int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
+                   const uint32_t* h_req_blocks, uint32_t n_req, int level, uint8_t* d_out,
+                   const uint64_t* h_out_offsets, uint64_t* h_out_bytes, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  ProfGuard pg(ctx);
+  if (!h_offsets || !h_req_blocks || !h_out_offsets || !h_out_bytes || (n_req && !d_out))
+    return fail(ctx, BZG_EINVAL, "null pointer");
+  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
+  if (n_req > 65535) return fail(ctx, BZG_EINVAL, "at most 65535 requests per call");
+  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
+  if (n_blocks && h_offsets[n_blocks] > h_offsets[0] && !d_in) return fail(ctx, BZG_EINVAL, "null input");
+  if (h_req_blocks[0] != 0 || h_req_blocks[n_req] != n_blocks)
+    return fail(ctx, BZG_EINVAL, "request block ranges must start at 0 and end at n_blocks");
+  for (uint32_t r = 0; r < n_req; r++) {
+    if (h_req_blocks[r + 1] < h_req_blocks[r]) return fail(ctx, BZG_EINVAL, "request block ranges decrease");
+    if (h_out_offsets[r + 1] < h_out_offsets[r]) return fail(ctx, BZG_EINVAL, "output offsets decrease");
+  }
+  for (uint32_t r = 0; r <= n_req; r++)
+    if (h_out_offsets[r] & 3) return fail(ctx, BZG_EINVAL, "output offsets must be multiples of 4");
+  if ((uintptr_t)d_out & 3) return fail(ctx, BZG_EINVAL, "d_out must be 4-byte aligned");
+  if (n_req == 0) return 0;
+  return compress_impl(ctx, d_in, h_offsets, n_blocks, h_req_blocks, n_req, level, d_out, h_out_offsets,
+                       h_out_bytes, nullptr, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -49,31 +49,57 @@ __device__ __forceinline__ void put_bits64(uint32_t* words, uint64_t pos, uint64
   }
 }
 
-// Block layout: bit offset of every block and the stream end.  One
-// workgroup.  mode 0: one stream (blocks follow a 32-bit stream header, each
-// block carries the 105-bit block header); mode 1: bodies only, block b at
-// body_byte[b] * 8.
+// Block layout: bit offset of every block and each stream's end.  One
+// workgroup per stream.  mode 0: one bzip2 stream per request r, made of
+// blocks [rb[r], rb[r+1]) and written from byte rout[r] of the output; blocks
+// follow the 32-bit stream header and carry the 105-bit block header.
+// info[2r] = the stream's length in bits (with the end-of-stream marker and
+// combined CRC), info[2r+1] = the combined CRC.  mode 1: bodies only, block b
+// at body_byte[b] * 8 (rb, rout unused, one workgroup).
 __global__ __launch_bounds__(NT) void k_layout(uint32_t nb, const BlockTables* __restrict__ tabs, int mode,
+                                               const uint32_t* __restrict__ rb, const uint64_t* __restrict__ rout,
                                                const uint64_t* __restrict__ body_byte, uint64_t* __restrict__ blk_bit,
                                                const uint32_t* __restrict__ crc, uint64_t* __restrict__ info) {
   __shared__ uint64_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t shx[NT / BZG_WAVE];
+  const uint32_t r = blockIdx.x;
+  const uint32_t b0 = mode == 0 ? rb[r] : 0u, b1 = mode == 0 ? rb[r + 1] : nb;
+  const uint64_t base = mode == 0 ? rout[r] * 8 : 0;
   uint64_t carry = 32;
-  for (uint32_t c = 0; c < nb; c += NT) {
+  uint32_t comb = 0;
+  for (uint32_t c = b0; c < b1; c += NT) {
     uint32_t b = c + threadIdx.x;
     uint64_t sz = 0;
-    if (b < nb) sz = (mode == 0 ? 105u : 0u) + tabs[b].hdr_bits + tabs[b].data_bits;
+    if (b < b1) sz = (mode == 0 ? 105u : 0u) + tabs[b].hdr_bits + tabs[b].data_bits;
     uint64_t tot;
     uint64_t ex = block_excl_sum<uint64_t, NT>(sz, sh, &tot);
-    if (b < nb) blk_bit[b] = mode == 0 ? carry + ex : body_byte[b] * 8;
+    if (b < b1) {
+      blk_bit[b] = mode == 0 ? base + carry + ex : body_byte[b] * 8;
+      // combined CRC: each block CRC rotated left once per later block
+      if (mode == 0) {
+        uint32_t k = (b1 - 1 - b) & 31u, v = crc[b];
+        comb ^= k ? (v << k) | (v >> (32 - k)) : v;
+      }
+    }
     carry += tot;
   }
+  comb = wave_xor(comb);
+  if (lane() == 0) shx[threadIdx.x / BZG_WAVE] = comb;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t comb = 0;
-    if (mode == 0)
-      for (uint32_t b = 0; b < nb; b++) comb = ((comb << 1) | (comb >> 31)) ^ crc[b];
-    info[0] = carry + 80;  // stream bits incl. end-of-stream marker and CRC
-    info[1] = comb;
+    for (int w = 1; w < NT / BZG_WAVE; w++) comb ^= shx[w];
+    info[2 * r] = carry + 80;  // stream bits incl. end-of-stream marker and CRC
+    info[2 * r + 1] = comb;
   }
+}
+
+// Zero the words each stream will occupy (bits are OR-ed in afterwards).
+// Grid (x, streams); a plain fill kernel, so the call stays capturable.
+__global__ __launch_bounds__(NT) void k_zero_streams(const uint64_t* __restrict__ rout,
+                                                     const uint64_t* __restrict__ info, uint32_t* __restrict__ words) {
+  const uint32_t r = blockIdx.y;
+  const uint64_t w0 = rout[r] / 4, nw = (info[2 * r] + 31) / 32;
+  for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * NT) words[w0 + i] = 0;
 }
 
 // Block header and body head: [magic, CRC, rand bit, origPtr,] symbol map,
@@ -247,13 +273,17 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
   }
 }
 
-__global__ void k_stream_ends(int level, const uint64_t* __restrict__ info, uint32_t* __restrict__ words) {
+// Stream header "BZh<level>", end-of-stream marker and combined CRC of
+// stream r (one workgroup per stream).
+__global__ void k_stream_ends(int level, const uint64_t* __restrict__ rout, const uint64_t* __restrict__ info,
+                              uint32_t* __restrict__ words) {
   if (threadIdx.x != 0) return;
-  uint64_t end = info[0];
+  const uint32_t r = blockIdx.x;
+  const uint64_t start = rout[r] * 8, end = start + info[2 * r];
   uint32_t hdr = ((uint32_t)'B' << 24) | ((uint32_t)'Z' << 16) | ((uint32_t)'h' << 8) | (uint32_t)('0' + level);
-  atomicOr(&words[0], bswap32(hdr));
+  atomicOr(&words[start / 32], bswap32(hdr));
   put_bits64(words, end - 80, 0x177245385090ull, 48);
-  put_bits(words, end - 32, (uint32_t)info[1], 32);
+  put_bits(words, end - 32, (uint32_t)info[2 * r + 1], 32);
 }
 
 // Per block: byte 0 = table count, bytes 16 + 258*t + v = code lengths.
@@ -296,10 +326,19 @@ hipError_t body_sizes(uint32_t nb, const void* tabs, const uint64_t* obyte, uint
   return hipGetLastError();
 }
 
-hipError_t pack_layout(uint32_t nb, const void* tabs, int mode, const uint64_t* body_byte, uint64_t* blk_bit,
-                       const uint32_t* crc, uint64_t* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(NT), 0, st, nb, (const BlockTables*)tabs, mode, body_byte, blk_bit, crc,
-                     info);
+hipError_t pack_layout(uint32_t nb, uint32_t n_req, const uint32_t* rb, const uint64_t* rout, const void* tabs,
+                       int mode, const uint64_t* body_byte, uint64_t* blk_bit, const uint32_t* crc, uint64_t* info,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_layout, dim3(mode == 0 ? n_req : 1u), dim3(NT), 0, st, nb, (const BlockTables*)tabs, mode, rb,
+                     rout, body_byte, blk_bit, crc, info);
+  return hipGetLastError();
+}
+
+hipError_t zero_streams(uint32_t n_req, uint64_t max_words, const uint64_t* rout, const uint64_t* info,
+                        uint32_t* words, hipStream_t st) {
+  uint64_t gx = (max_words + NT * 8 - 1) / (NT * 8);
+  gx = gx < 1 ? 1 : (gx > 1024 ? 1024 : gx);
+  if (n_req) hipLaunchKernelGGL(k_zero_streams, dim3((uint32_t)gx, n_req), dim3(NT), 0, st, rout, info, words);
   return hipGetLastError();
 }
 
@@ -307,7 +346,8 @@ hipError_t pack_run(uint32_t nb, const void* tabs, int mode, const uint64_t* blk
                     const uint32_t* primary, const uint32_t* inuse, const uint64_t* sel_base, const uint8_t* sel,
                     const uint8_t* selmtf, const uint64_t* gofs, uint32_t ntiles, const uint32_t* tile_blk,
                     const uint32_t* blk_tile0, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
-                    int level, const uint64_t* info, uint32_t* words, hipStream_t st) {
+                    int level, uint32_t n_req, const uint64_t* rout, const uint64_t* info, uint32_t* words,
+                    hipStream_t st) {
   if (nb) {
     hipLaunchKernelGGL(k_pack_header, dim3(nb), dim3(NT), 0, st, (const BlockTables*)tabs, mode, blk_bit, crc, primary,
                        inuse, sel_base, selmtf, words);
@@ -315,7 +355,7 @@ hipError_t pack_run(uint32_t nb, const void* tabs, int mode, const uint64_t* blk
       hipLaunchKernelGGL(k_pack_data, dim3(ntiles), dim3(NT), 0, st, (const BlockTables*)tabs, mode, tile_blk,
                          blk_tile0, blk_bit, syms, sym_base, nsyms, sel_base, sel, gofs, words);
   }
-  if (mode == 0) hipLaunchKernelGGL(k_stream_ends, dim3(1), dim3(64), 0, st, level, info, words);
+  if (mode == 0 && n_req) hipLaunchKernelGGL(k_stream_ends, dim3(n_req), dim3(64), 0, st, level, rout, info, words);
   return hipGetLastError();
 }
 

@@ -52,6 +52,8 @@ def lib() -> C.CDLL:
         L.huffman_encode_batch.argtypes = [vp, vp, vp, vp, u64p, C.c_uint32, vp, u64p, vp, vp, vp]
         L.compress_blocks.restype = C.c_int
         L.compress_blocks.argtypes = [vp, vp, u64p, C.c_uint32, C.c_int, vp, C.c_uint64, u64p, u32p, vp]
+        L.compress_batch.restype = C.c_int
+        L.compress_batch.argtypes = [vp, vp, u64p, C.c_uint32, u32p, C.c_uint32, C.c_int, vp, u64p, u64p, vp]
         L.bzg_profile.restype = C.c_int
         L.bzg_profile.argtypes = [vp, C.c_int]
         L.bzg_profile_read.restype = C.c_int
@@ -61,7 +63,8 @@ def lib() -> C.CDLL:
 
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_compress_bound", "bwt_forward_batch",
-           "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "bzg_profile", "bzg_profile_read")
+           "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch", "bzg_profile",
+           "bzg_profile_read")
 
 
 class Profile:
@@ -217,10 +220,12 @@ def compress_bound(n_bytes: int, n_blocks: int) -> int:
 
 
 class Compressor:
-    """Reusable compress_blocks caller: keeps the output buffer between calls."""
+    """Reusable compress_blocks caller: keeps the output buffer between calls.
+    ctx: the library context (default: the device's shared one; give each
+    host thread that should overlap with others a Context of its own)."""
 
-    def __init__(self, device: Optional[int] = None):
-        self.ctx = context(device)
+    def __init__(self, device: Optional[int] = None, ctx: Optional[Context] = None):
+        self.ctx = ctx or context(device)
         self.out = None
         self.out_bytes = C.c_uint64(0)
         self.n_blocks = C.c_uint32(0)
@@ -245,3 +250,46 @@ def compress(x: torch.Tensor, offsets=None, level: int = 9, block_bytes: Optiona
     """Whole-pipeline compression of the blocks of x into one bzip2 stream
     (a uint8 tensor on x's device)."""
     return Compressor(x.device.index)(x, offsets, level, block_bytes).clone()
+
+
+class BatchCompressor:
+    """Reusable compress_batch caller: many requests, one stream each, all
+    blocks through every stage together.  Keeps its output buffer.  ctx as
+    for Compressor."""
+
+    def __init__(self, device: Optional[int] = None, ctx: Optional[Context] = None):
+        self.ctx = ctx or context(device)
+        self.out = None
+
+    def __call__(self, x: torch.Tensor, offsets, req_blocks, level: int = 9):
+        """x: all requests' bytes on the GPU; offsets: block boundaries in x;
+        req_blocks: n_req+1 block indices (request r = blocks
+        [req_blocks[r], req_blocks[r+1])).  Returns one uint8 tensor view per
+        request (valid until the next call)."""
+        x = _dev_u8(x)
+        o = _offs(offsets)
+        rq = np.ascontiguousarray(np.asarray(req_blocks, dtype=np.uint32))
+        nb, nr = o.size - 1, rq.size - 1
+        if nr < 0:
+            raise ValueError("req_blocks needs at least one entry")
+        ok = rq.size and int(rq[0]) == 0 and int(rq[-1]) == nb and bool(np.all(np.diff(rq.astype(np.int64)) >= 0))
+        ok = ok and bool(np.all(np.diff(o.astype(np.int64)) >= 0))
+        # ranges the library will reject get no output space
+        caps = [(compress_bound(int(o[rq[r + 1]]) - int(o[rq[r]]), int(rq[r + 1]) - int(rq[r])) + 3) & ~3
+                if ok else 0 for r in range(nr)]
+        oo = np.zeros(nr + 1, np.uint64)
+        oo[1:] = np.cumsum(caps, dtype=np.uint64)
+        need = max(int(oo[-1]), 4)
+        if self.out is None or self.out.numel() < need or self.out.device != x.device:
+            self.out = torch.empty(need, dtype=torch.uint8, device=x.device)
+        ob = np.zeros(max(nr, 1), np.uint64)
+        rc = lib().compress_batch(self.ctx.h, C.c_void_p(x.data_ptr()), _u64p(o), nb,
+                                  rq.ctypes.data_as(C.POINTER(C.c_uint32)), nr, level,
+                                  C.c_void_p(self.out.data_ptr()), _u64p(oo), _u64p(ob), _stream(x.device))
+        self.ctx.check(rc)
+        return [self.out[int(oo[r]): int(oo[r]) + int(ob[r])] for r in range(nr)]
+
+
+def compress_batch(x: torch.Tensor, offsets, req_blocks, level: int = 9):
+    """One bzip2 stream per request (list of uint8 tensors on x's device)."""
+    return [z.clone() for z in BatchCompressor(x.device.index)(x, offsets, req_blocks, level)]

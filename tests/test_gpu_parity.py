@@ -241,6 +241,102 @@ def test_compress_rejects_bad_args(bz):
         bz.compress(x, [0, 7, 3, 10], level=9)
 
 
+def _batch_inputs(reqs, block):
+    """All requests' bytes, block offsets (each request cut into `block`-byte
+    blocks) and the request -> block ranges."""
+    datas, offs, rq = [], [0], [0]
+    pos = 0
+    for r in reqs:
+        n = len(r)
+        for a in range(0, n, block):
+            offs.append(pos + min(a + block, n))
+        pos += n
+        datas.append(np.frombuffer(bytes(r), np.uint8) if not isinstance(r, np.ndarray) else r)
+        rq.append(len(offs) - 1)
+    data = np.concatenate(datas) if datas else np.zeros(0, np.uint8)
+    return data, np.array(offs, np.uint64), np.array(rq, np.uint32)
+
+
+def _check_batch(bz, reqs, level, block, name):
+    from paper_1109_2348_amd import native
+    data, offs, rq = _batch_inputs(reqs, block)
+    _say(f"compress_batch {name}: {len(reqs)} requests, {data.size} bytes, {offs.size - 1} blocks, level {level}")
+    zs = native.compress_batch(_dev(data), offs, rq, level=level)
+    assert len(zs) == len(reqs)
+    for i, r in enumerate(reqs):
+        a, e = int(rq[i]), int(rq[i + 1])
+        ro = offs[a:e + 1] - offs[a]
+        rd = data[int(offs[a]):int(offs[e])]
+        z = zs[i].cpu().numpy().tobytes()
+        ref = cref.compress(rd, ro if e > a else [0], level=level, threads=16)
+        assert z == ref, f"{name}: request {i} ({rd.size} B) differs from the oracle run on it alone"
+        assert bz2.decompress(z) == rd.tobytes()
+    return zs
+
+
+def test_compress_batch_each_stream_alone(bz):
+    rnd = random.Random(23)
+    b = W.config4(nb=12, lo=1, hi=120000, seed=29)
+    reqs = [b"", b"banana", b.block(0), b"", bytes(rnd.randrange(4) for _ in range(70000))]
+    reqs += [b.block(k) for k in range(1, 12)] + [b"a" * 250000, b""]
+    _check_batch(bz, reqs, 1, 100000, "mixed sizes, empty requests, level-1 cuts")
+
+
+def test_compress_batch_same_as_compress_blocks(bz):
+    b = W.config2(total=3 * 900000 + 4321, block=900000, seed=31)
+    data, offs, rq = _batch_inputs([b.data[: 2 * 900000], b.data[2 * 900000:]], 900000)
+    from paper_1109_2348_amd import native
+    _say("compress_batch vs compress_blocks: 2 requests of 900000-byte blocks")
+    zs = native.compress_batch(_dev(data), offs, rq, level=9)
+    for i in range(2):
+        a, e = int(rq[i]), int(rq[i + 1])
+        alone = bz.compress(_dev(data[int(offs[a]):int(offs[e])]), offs[a:e + 1] - offs[a], level=9)
+        assert zs[i].cpu().numpy().tobytes() == alone.cpu().numpy().tobytes()
+
+
+def test_compress_batch_all_empty_and_capacity(bz):
+    import ctypes as C
+    import torch
+    from paper_1109_2348_amd import native
+    _say("compress_batch: all-empty requests; one range too small")
+    zs = native.compress_batch(_dev(np.zeros(0, np.uint8)), [0, 0, 0], [0, 0, 1, 2], level=3)
+    for z in zs:
+        assert bz2.decompress(z.cpu().numpy().tobytes()) == b""
+    data, offs, rq = _batch_inputs([bytes(range(256)) * 40, b"xyz" * 999], 100000)
+    x = _dev(data)
+    out = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    oo = np.array([0, 64, 1 << 16], np.uint64)  # request 0 gets 64 bytes: too few
+    ob = np.zeros(2, np.uint64)
+    ctx = native.context()
+    L = native.lib()
+    rc = L.compress_batch(ctx.h, C.c_void_p(x.data_ptr()), native._u64p(offs), offs.size - 1,
+                          rq.ctypes.data_as(C.POINTER(C.c_uint32)), 2, 9, C.c_void_p(out.data_ptr()),
+                          native._u64p(oo), native._u64p(ob), native._stream(x.device))
+    assert rc == native.BZG_ECAPACITY
+    assert ob[0] > 64 and ob[1] > 0
+    oo = np.array([0, 4 * ((int(ob[0]) + 3) // 4), 1 << 16], np.uint64)  # exactly enough
+    rc = L.compress_batch(ctx.h, C.c_void_p(x.data_ptr()), native._u64p(offs), offs.size - 1,
+                          rq.ctypes.data_as(C.POINTER(C.c_uint32)), 2, 9, C.c_void_p(out.data_ptr()),
+                          native._u64p(oo), native._u64p(ob), native._stream(x.device))
+    assert rc == 0
+    o = out.cpu().numpy()
+    for i in range(2):
+        z = o[int(oo[i]): int(oo[i]) + int(ob[i])].tobytes()
+        a, e = int(rq[i]), int(rq[i + 1])
+        assert bz2.decompress(z) == data[int(offs[a]):int(offs[e])].tobytes()
+
+
+def test_compress_batch_rejects_bad_args(bz):
+    from paper_1109_2348_amd import native
+    x = _dev(np.zeros(10, np.uint8))
+    with pytest.raises(bz.BzgError):
+        native.compress_batch(x, [0, 5, 10], [0, 1], level=9)  # ranges end before n_blocks
+    with pytest.raises(bz.BzgError):
+        native.compress_batch(x, [0, 5, 10], [0, 2, 1, 2], level=9)  # ranges decrease
+    with pytest.raises(bz.BzgError):
+        native.compress_batch(x, [0, 5, 10], [0, 2], level=10)
+
+
 @pytest.mark.slow
 def test_compress_config2_full(bz):
     b = W.config2()
