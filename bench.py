@@ -1,8 +1,19 @@
-"""Benchmark: whole-pipeline bzip2 compression (CRC, RLE1, BWT, MTF,
-RUNA/RUNB, Huffman, packing) of 64 MiB cut into 900,000-byte blocks on one
-MI355X, input resident in HBM.  Prints one JSON line.
+"""Benchmark of the bzip2 compression stages on one MI355X.  Prints one JSON
+line.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--config 2]
+
+--config 2 (default): whole-pipeline compression (CRC, RLE1, BWT, MTF,
+    RUNA/RUNB, Huffman, packing) of 64 MiB in 900,000-byte blocks, input
+    resident in HBM, batched (one call for all blocks) and per-block (one
+    call per block).
+--config 1: one 100,000-byte block at level 1 (launch-latency point).
+--config 3: the sort alone (bwt_forward_batch) on 256 x 900,000-byte
+    periodic / all-same blocks (up to 18 doubling rounds).
+--config 4: 8192 blocks of log-uniform size 1,000..900,000 bytes, batched
+    vs per-block.
+--config 5: the serving loop: Poisson arrivals of 4 KB..64 MB requests at
+    fractions of the saturated rate; MB/s with p50/p99 latency.
 """
 
 from __future__ import annotations
@@ -12,6 +23,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -26,21 +38,250 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, sample_blocks, threads):
-    """The oracle as it stands, on a bounded sample of the same workload."""
-    from oracle import cref
+def _sample_idx(batch, per_kind, kinds=("uniform", "text", "sparse")):
     idx = []
-    for kind in ("uniform", "text", "sparse"):
-        idx += [k for k in range(batch.n_blocks) if batch.kinds[k] == kind][:sample_blocks // 3]
-    idx.sort()
+    for kind in kinds:
+        idx += [k for k in range(batch.n_blocks) if batch.kinds[k] == kind][:per_kind]
+    return sorted(idx)
+
+
+def _sub_batch(batch, idx):
     blocks = [batch.block(k) for k in idx]
     data = np.concatenate(blocks)
     offs = np.zeros(len(blocks) + 1, np.uint64)
     offs[1:] = np.cumsum([b.size for b in blocks])
+    return data, offs
+
+
+def _roofline(kern, steps, step_ms_total):
+    """Dominant kernel: algorithmic bytes per launch over its average launch
+    time (HIP events on the launch stream)."""
+    if not kern:
+        return None
+    name, rec = max(kern.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = rec["ms"] / max(rec["launches"], 1)
+    bytes_per_launch = rec["bytes"] / max(rec["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "avg_launch_ms": round(avg_ms, 4), "launches_per_step": rec["launches"] / steps,
+            "share_of_step": round(rec["ms"] / step_ms_total, 3) if step_ms_total > 0 else None}
+
+
+def _kernels(kern, steps):
+    return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches": v["launches"] // steps}
+            for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+
+
+def _timed(fn, ctx, steps, warmup, stream):
+    """W untimed steps, then K timed steps bracketed by device syncs (HIP
+    events per step), then K more steps with the library's per-kernel
+    profile on (its events cost time, so they stay out of the timed steps)."""
+    import torch
+    from paper_1109_2348_amd import native
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    z = cref.compress(data, offs, level=9, threads=threads)
-    dt = time.perf_counter() - t0
-    return data, offs, z, dt
+    out = None
+    for i in range(steps):
+        ev[i][0].record(stream)
+        out = fn()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    prof = native.Profile()
+    prof.enable(ctx)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof.disable(ctx)
+    return out, wall, step_ms, prof.read(ctx)
+
+
+def _per_block(fn_block, nb, passes):
+    import torch
+    times = []
+    for _ in range(passes):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(nb):
+            fn_block(k)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+    return min(times) if times else None
+
+
+def _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extra=None):
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": config,
+        "p50_ms": round(float(np.percentile(step_ms, 50)), 3), "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
+        "per_block": per_block, "roofline": _roofline(kern, args.steps, float(step_ms.sum())), "cpu_baseline": cpu,
+        "profiled_steps": args.steps,
+        "kernels": _kernels(kern, args.steps),
+    }
+    if extra:
+        res.update(extra)
+    return res
+
+
+# ---------------------------------------------------------------- configs 1, 2, 4
+def bench_compress(args, batch, level):
+    import torch
+    import paper_1109_2348_amd as bz
+    n_in = int(batch.data.size)
+    x = torch.from_numpy(batch.data).cuda()
+    comp = bz.Compressor()
+    stream = torch.cuda.current_stream()
+    # one plain device copy of the input (known size): the calibration point
+    # for hardware byte counters collected around this run
+    torch.empty_like(x).copy_(x)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup}, timing {args.steps} steps over {batch.n_blocks} blocks")
+    z, wall, step_ms, kern = _timed(lambda: comp(x, batch.offsets, level=level), comp.ctx, args.steps,
+                                    args.warmup, stream)
+    out_bytes = int(z.numel())
+    value = args.steps * n_in / wall / 1e6
+
+    log("per-block form")
+    offs = batch.offsets
+
+    def one(k):
+        a, e = int(offs[k]), int(offs[k + 1])
+        comp(x[a:e], [0, e - a], level=level)
+    pb = _per_block(one, batch.n_blocks, args.per_block_passes)
+    per_block = {"value": round(n_in / pb / 1e6, 2) if pb else None, "unit": "MB/s", "calls": batch.n_blocks}
+
+    cpu = None
+    if not args.no_cpu:
+        threads = len(os.sched_getaffinity(0))
+        idx = list(range(batch.n_blocks)) if batch.n_blocks <= 3 else _sample_idx(batch, args.cpu_sample_blocks // 3)
+        data, so = _sub_batch(batch, idx)
+        log(f"cpu baseline on {threads} threads, {len(idx)} blocks")
+        from oracle import cref
+        t0 = time.perf_counter()
+        zref = cref.compress(data, so, level=level, threads=threads)
+        dt = time.perf_counter() - t0
+        zg = bz.compress(torch.from_numpy(data).cuda(), so, level=level).cpu().numpy().tobytes()
+        if zg != zref:
+            log("ERROR: GPU stream differs from the oracle on the CPU-baseline sample")
+            sys.exit(1)
+        cpu = {"value": round(data.size / dt / 1e6, 3), "unit": "MB/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(idx)} of the {batch.n_blocks} blocks ({data.size} B"
+                         + (", equal thirds uniform/text/sparse" if len(idx) > 3 else "")
+                         + "), oracle compress with one thread per block; GPU stream on the sample bit-identical"}
+    config = {"workload": batch.name, "input_bytes": n_in, "blocks": batch.n_blocks, "level": level,
+              "output_bytes": out_bytes, "ratio": round(out_bytes / n_in, 4)}
+    return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block)
+
+
+# ---------------------------------------------------------------- config 3
+def bench_sort(args):
+    import torch
+    from paper_1109_2348_amd import native
+    from paper_1109_2348_amd import workloads as W
+    batch = W.config3()
+    n_in = int(batch.data.size)
+    x = torch.from_numpy(batch.data).cuda()
+    ctx = native.context()
+    stream = torch.cuda.current_stream()
+    nb = batch.n_blocks
+    L = torch.empty_like(x)
+    prim = torch.empty(nb, dtype=torch.int32, device=x.device)
+    o = np.ascontiguousarray(batch.offsets, dtype=np.uint64)
+    import ctypes as C
+
+    def run(lo=0, hi=nb):
+        sub = o[lo:hi + 1]
+        rc = native.lib().bwt_forward_batch(ctx.h, C.c_void_p(x.data_ptr()), native._u64p(sub), hi - lo,
+                                            C.c_void_p(L.data_ptr()), C.c_void_p(prim.data_ptr() + 4 * lo), None,
+                                            native._stream(x.device))
+        ctx.check(rc)
+    log(f"warmup {args.warmup}, timing {args.steps} steps of bwt_forward_batch over {nb} blocks")
+    _, wall, step_ms, kern = _timed(run, ctx, args.steps, args.warmup, stream)
+    value = args.steps * n_in / wall / 1e6
+    log("per-block form")
+    pb = _per_block(lambda k: run(k, k + 1), nb, args.per_block_passes)
+    per_block = {"value": round(n_in / pb / 1e6, 2) if pb else None, "unit": "MB/s", "calls": nb}
+    run()
+    torch.cuda.synchronize()
+    Lh, ph = L.cpu().numpy(), prim.cpu().numpy()
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cref
+        threads = len(os.sched_getaffinity(0))
+        idx = sorted([k for k in range(nb) if batch.kinds[k] == "periodic"][:args.cpu_sample_blocks]
+                     + [k for k in range(nb) if batch.kinds[k] == "same"][:2])
+        log(f"cpu baseline: oracle BWT of {len(idx)} blocks on {threads} threads")
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            refs = list(ex.map(lambda k: cref.bwt(batch.block(k)), idx))
+        dt = time.perf_counter() - t0
+        for k, (sa, last, optr) in zip(idx, refs):
+            a, e = int(o[k]), int(o[k + 1])
+            if not (np.array_equal(Lh[a:e], last) and int(ph[k]) == optr):
+                log(f"ERROR: GPU BWT differs from the oracle on block {k}")
+                sys.exit(1)
+        nbytes = sum(int(o[k + 1] - o[k]) for k in idx)
+        cpu = {"value": round(nbytes / dt / 1e6, 3), "unit": "MB/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(idx)} of the {nb} blocks ({nbytes} B), oracle BWT (comparison sort of rotations) "
+                         f"one thread per block; GPU L and primary index on the sample identical"}
+    config = {"workload": batch.name, "input_bytes": n_in, "blocks": nb, "stage": "bwt_forward_batch"}
+    return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block)
+
+
+# ---------------------------------------------------------------- config 5
+def bench_serving(args):
+    from paper_1109_2348_amd import serving as S
+    from paper_1109_2348_amd import workloads as W
+    import torch
+    pool_np = [r.data for r in W.requests(args.pool, 1.0, 4000, 64_000_000, 5)]
+    mean_mb = float(np.mean([p.size for p in pool_np])) / 1e6
+    # requests arrive in pinned host buffers (DMA straight into the arena),
+    # or as plain host arrays staged through the server's pinned buffers
+    pool = pool_np if args.host_arrays else [torch.from_numpy(p).pin_memory() for p in pool_np]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.5)
+    points = []
+    with S.Server(hbm_budget=budget, max_pass=args.max_pass_mib << 20, workers=args.workers) as srv:
+        S.poisson_run(srv, pool[:4], [0.0] * 4)
+        # saturation: every request offered at once
+        srv.stats = S.ServerStats()
+        n_sat = min(args.requests, 3 * len(pool))
+        S.poisson_run(srv, [pool[i % len(pool)] for i in range(n_sat)], [0.0] * n_sat)
+        sat = srv.stats.summary()
+        qps_sat = sat["MB_per_s"] / mean_mb
+        log(f"saturation {sat['MB_per_s']} MB/s = {qps_sat:.1f} req/s of mean {mean_mb:.2f} MB")
+        for frac in args.fractions:
+            qps = frac * qps_sat
+            g = W.rng(5, 77, int(frac * 1000))
+            arr = np.cumsum(g.exponential(1.0 / qps, size=args.requests))
+            srv.stats = S.ServerStats()
+            _, wall = S.poisson_run(srv, [pool[i % len(pool)] for i in range(args.requests)], arr)
+            s = srv.stats.summary()
+            s.update({"load": frac, "qps": round(qps, 2), "wall_s": round(wall, 3)})
+            log(json.dumps(s))
+            points.append(s)
+        arena = srv.arena_bytes
+    at = min(points, key=lambda p: abs(p["load"] - 0.9)) if points else sat
+    return {
+        "metric": METRIC, "value": sat["MB_per_s"], "unit": "MB/s", "n_gpus": 1, "steps": args.requests,
+        "warmup": 4, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals, requests log-uniform 4000..64e6 B "
+                               f"({len(pool)} distinct payloads reused), 900000 B blocks, level 9",
+                   "workers": args.workers, "max_pass_bytes": args.max_pass_mib << 20, "hbm_budget": budget,
+                   "arena_bytes": arena, "mean_request_MB": round(mean_mb, 3)},
+        "p50_ms": at["p50_ms"], "p99_ms": at["p99_ms"], "p_at_load": at.get("load"),
+        "saturation": sat, "sweep": points, "roofline": None, "cpu_baseline": None,
+        "note": "host-to-device upload of each request and the copy of its stream back to the host are inside "
+                "the latency and the MB/s; requests arrive in "
+                + ("plain host arrays" if args.host_arrays else "pinned host buffers"),
+    }
 
 
 def main():
@@ -48,107 +289,35 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--per-block-passes", type=int, default=1)
     ap.add_argument("--cpu-sample-blocks", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--total", type=int, default=64 << 20)
+    ap.add_argument("--total", type=int, default=64 << 20, help="config 2 input bytes")
+    ap.add_argument("--requests", type=int, default=400, help="config 5 requests per load point")
+    ap.add_argument("--pool", type=int, default=48, help="config 5 distinct payloads")
+    ap.add_argument("--fractions", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.2])
+    ap.add_argument("--workers", type=int, default=2)
+    ap.add_argument("--max-pass-mib", type=int, default=256)
+    ap.add_argument("--host-arrays", action="store_true", help="config 5 requests as pageable host arrays")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import paper_1109_2348_amd as bz
-    from paper_1109_2348_amd import native
     from paper_1109_2348_amd import workloads as W
-
-    log("generating workload")
-    batch = W.config2(total=args.total)
-    n_in = int(batch.data.size)
-    x = torch.from_numpy(batch.data).cuda()
-    comp = bz.Compressor()
-    stream = torch.cuda.current_stream()
-
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        comp(x, batch.offsets, level=9)
-    torch.cuda.synchronize()
-    # one plain device copy of the input (known size): the calibration point
-    # for hardware byte counters collected around this run
-    torch.empty_like(x).copy_(x)
-    torch.cuda.synchronize()
-
-    prof = native.Profile()
-    prof.enable(comp.ctx)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        z = comp(x, batch.offsets, level=9)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof.disable(comp.ctx)
-    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    out_bytes = int(z.numel())
-    value = args.steps * n_in / wall / 1e6
-    kern = prof.read(comp.ctx)
-
-    # per-block form: the same kernels, one call per block, one stream
-    log("per-block form")
-    nb = batch.n_blocks
-    pb_times = []
-    for _ in range(args.per_block_passes):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for k in range(nb):
-            a, e = int(batch.offsets[k]), int(batch.offsets[k + 1])
-            comp(x[a:e], [0, e - a], level=9)
-        torch.cuda.synchronize()
-        pb_times.append(time.perf_counter() - t1)
-    pb_value = n_in / min(pb_times) / 1e6 if pb_times else None
-
-    # dominant kernel and its roofline
-    roof = None
-    if kern:
-        name, rec = max(kern.items(), key=lambda kv: kv[1]["ms"])
-        avg_ms = rec["ms"] / max(rec["launches"], 1)
-        bytes_per_launch = rec["bytes"] / max(rec["launches"], 1)
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
-                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": rec["launches"] / args.steps,
-                "share_of_step": round(rec["ms"] / step_ms.sum(), 3)}
-
-    cpu = None
-    if not args.no_cpu:
-        threads = len(os.sched_getaffinity(0))
-        log(f"cpu baseline on {threads} threads")
-        data, offs, zref, dt = cpu_baseline(batch, args.cpu_sample_blocks, threads)
-        xs = torch.from_numpy(data).cuda()
-        zg = bz.compress(xs, offs, level=9).cpu().numpy().tobytes()
-        if zg != zref:
-            log("ERROR: GPU stream differs from the oracle on the CPU-baseline sample")
-            sys.exit(1)
-        cpu = {"value": round(data.size / dt / 1e6, 3), "unit": "MB/s", "cores": threads, "kind": "oracle",
-               "sample": f"{len(offs) - 1} of the {nb} blocks ({data.size} B, equal thirds uniform/text/sparse), "
-                         f"oracle compress with one thread per block; GPU stream on the sample bit-identical"}
-
-    res = {
-        "metric": METRIC, "value": round(value, 2), "unit": "MB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": batch.name, "input_bytes": n_in, "blocks": nb, "level": 9,
-                   "output_bytes": out_bytes, "ratio": round(out_bytes / n_in, 4)},
-        "p50_ms": round(float(np.percentile(step_ms, 50)), 3), "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
-        "per_block": {"value": round(pb_value, 2) if pb_value else None, "unit": "MB/s", "calls": nb},
-        "roofline": roof, "cpu_baseline": cpu,
-        "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches": v["launches"] // args.steps}
-                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
-    }
+    log(f"config {args.config}: generating workload")
+    if args.config == 1:
+        res = bench_compress(args, W.config1(), level=1)
+    elif args.config == 2:
+        res = bench_compress(args, W.config2(total=args.total), level=9)
+    elif args.config == 3:
+        res = bench_sort(args)
+    elif args.config == 4:
+        res = bench_compress(args, W.config4(), level=9)
+    else:
+        res = bench_serving(args)
     print(json.dumps(res), flush=True)
 
 

@@ -189,8 +189,9 @@ class Server:
 
     # ---- client side
     def submit(self, data, arrival: Optional[float] = None) -> Future:
-        """Queue one request (host uint8 array/bytes or device uint8 tensor);
-        the future resolves to its bzip2 stream (bytes)."""
+        """Queue one request (host uint8 array or bytes, host or device uint8
+        tensor); the future resolves to its bzip2 stream, a bytes-like object
+        (a uint8 array from the GPU backend)."""
         if isinstance(data, (bytes, bytearray, memoryview)):
             data = np.frombuffer(bytes(data), np.uint8)
         n = int(data.numel() if hasattr(data, "numel") else data.size)
@@ -323,7 +324,14 @@ class Server:
 
 class GpuBackend:
     """Arena in HBM; uploads on a stream of their own; one library context and
-    stream per worker."""
+    stream per worker.
+
+    Host arrays are uploaded through two pinned staging buffers (the copy
+    into one overlaps the DMA out of the other); pinned host tensors and
+    device tensors are copied directly.  A pass's streams come back in one
+    pinned buffer and are returned as uint8 array views of it."""
+
+    STAGE = 32 << 20
 
     def __init__(self, device: int = 0):
         import torch
@@ -332,6 +340,8 @@ class GpuBackend:
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.up_stream = torch.cuda.Stream(self.device)
+        self.stage = [torch.empty(self.STAGE, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        self.stage_ev = [None, None]
         self.workers = []
 
     def arena(self, nbytes: int):
@@ -340,9 +350,21 @@ class GpuBackend:
     def upload(self, arena, pos: int, data):
         torch = self.torch
         with torch.cuda.stream(self.up_stream):
-            src = data if torch.is_tensor(data) else torch.from_numpy(np.ascontiguousarray(data, dtype=np.uint8))
-            n = int(src.numel())
-            arena[pos:pos + n].copy_(src.reshape(-1))
+            if torch.is_tensor(data):
+                src = data.reshape(-1)
+                arena[pos:pos + src.numel()].copy_(src, non_blocking=True)
+            else:
+                a = np.ascontiguousarray(data, dtype=np.uint8).reshape(-1)
+                for i, c in enumerate(range(0, a.size, self.STAGE)):
+                    k = i % 2
+                    if self.stage_ev[k] is not None:
+                        self.stage_ev[k].synchronize()  # its previous DMA is done
+                    m = min(self.STAGE, a.size - c)
+                    self.stage[k][:m].numpy()[:] = a[c:c + m]
+                    arena[pos + c:pos + c + m].copy_(self.stage[k][:m], non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(self.up_stream)
+                    self.stage_ev[k] = ev
         self.up_stream.synchronize()
 
     def worker(self, i: int):
@@ -361,15 +383,20 @@ class _GpuWorker:
         self.stream = torch.cuda.Stream(device)
         self.comp = BatchCompressor(device.index, ctx=Context(device.index))
 
-    def __call__(self, arena, offsets, req_blocks, level) -> List[bytes]:
+    def __call__(self, arena, offsets, req_blocks, level) -> List[np.ndarray]:
         torch = self.torch
         with torch.cuda.stream(self.stream):
             zs = self.comp(arena, offsets, req_blocks, level)
             lens = [int(z.numel()) for z in zs]
-            host = torch.cat(zs).cpu().numpy() if zs else np.zeros(0, np.uint8)
+            total = sum(lens)
+            host = torch.empty(max(total, 1), dtype=torch.uint8, pin_memory=True)
+            if total:
+                host[:total].copy_(torch.cat(zs), non_blocking=True)
+            self.stream.synchronize()
+        arr = host.numpy()
         out, p = [], 0
         for n in lens:
-            out.append(host[p:p + n].tobytes())
+            out.append(arr[p:p + n])
             p += n
         return out
 
@@ -387,39 +414,3 @@ def poisson_run(server: Server, payloads: Sequence, arrivals: Sequence[float], t
         futs.append(server.submit(data, arrival=t0 + t))
     server.drain(futs, timeout)
     return futs, server.clock() - t0
-
-
-def main(argv=None):
-    """QPS sweep of the serving loop on synthetic requests (Poisson arrivals,
-    log-uniform sizes); one JSON line per QPS point."""
-    import argparse
-    import json
-    from . import workloads as W
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--qps", type=float, nargs="+", default=[5.0, 20.0, 80.0])
-    ap.add_argument("--requests", type=int, default=200)
-    ap.add_argument("--pool", type=int, default=48, help="distinct payloads, reused cyclically")
-    ap.add_argument("--lo", type=int, default=4000)
-    ap.add_argument("--hi", type=int, default=64_000_000)
-    ap.add_argument("--workers", type=int, default=2)
-    ap.add_argument("--budget-gib", type=float, default=48.0)
-    ap.add_argument("--max-pass-mib", type=int, default=256)
-    ap.add_argument("--seed", type=int, default=5)
-    a = ap.parse_args(argv)
-    pool = [r.data for r in W.requests(a.pool, 1.0, a.lo, a.hi, a.seed)]
-    for qps in a.qps:
-        g = W.rng(a.seed, 77, int(qps * 1000))
-        arr = np.cumsum(g.exponential(1.0 / qps, size=a.requests))
-        payloads = [pool[i % len(pool)] for i in range(a.requests)]
-        with Server(hbm_budget=int(a.budget_gib * (1 << 30)), max_pass=a.max_pass_mib << 20,
-                    workers=a.workers) as srv:
-            poisson_run(srv, payloads[:4], [0.0] * 4)  # warm the contexts
-            srv.stats = ServerStats()
-            _, wall = poisson_run(srv, payloads, arr)
-            s = srv.stats.summary()
-        s.update({"qps": qps, "workers": a.workers, "wall_s": round(wall, 3)})
-        print(json.dumps(s), flush=True)
-
-
-if __name__ == "__main__":
-    main()

@@ -215,7 +215,7 @@ def test_gpu_serving_alone_equals_in_mix():
         hs = {w.comp.ctx.h.value for w in backend.workers}
         assert len(hs) == 2, "workers must not share a library context"
         futs, wall = S.poisson_run(srv, payloads, arrivals, timeout=120)
-        outs = [f.result(1) for f in futs]
+        outs = [bytes(f.result(1)) for f in futs]
         summ = srv.stats.summary()
     print(f"[case] serving summary {summ}", flush=True)
     assert summ["requests"] == len(payloads) and summ["failed"] == 0
