@@ -53,7 +53,30 @@ def _sub_batch(batch, idx):
     return data, offs
 
 
-def _roofline(kern, steps, step_ms_total):
+TRAFFIC_FILE = {2: "profiles/compress_64MiB_900k_blocks_hbm_traffic.md"}
+
+
+def _traffic(config, kernel):
+    """Hardware-counted bytes per launch of `kernel` on this workload, from
+    the committed counter summary, or None when there is none or the
+    kernel's sources changed since it was taken."""
+    import hashlib
+    path = TRAFFIC_FILE.get(config)
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    for line in open(os.path.join(ROOT, path)):
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == "k_" + kernel:
+            kv = dict(x.split("=", 1) for x in f[2:])
+            h = hashlib.sha256()
+            for n in (kv["source"], "common.hpp", "internal.hpp"):
+                with open(os.path.join(ROOT, "paper_1109_2348_amd", "csrc", n), "rb") as fh:
+                    h.update(fh.read())
+            return int(kv["bytes_per_launch"]) if h.hexdigest() == kv["sha256"] else None
+    return None
+
+
+def _roofline(kern, steps, step_ms_total, config=None):
     """Dominant kernel: algorithmic bytes per launch over its average launch
     time (HIP events on the launch stream)."""
     if not kern:
@@ -63,7 +86,8 @@ def _roofline(kern, steps, step_ms_total):
     bytes_per_launch = rec["bytes"] / max(rec["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(config, name), "kernel": name,
+            "algorithmic_bytes_per_launch": round(bytes_per_launch),
             "avg_launch_ms": round(avg_ms, 4), "launches_per_step": rec["launches"] / steps,
             "share_of_step": round(rec["ms"] / step_ms_total, 3) if step_ms_total > 0 else None}
 
@@ -120,7 +144,8 @@ def _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extr
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": config,
         "p50_ms": round(float(np.percentile(step_ms, 50)), 3), "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
-        "per_block": per_block, "roofline": _roofline(kern, args.steps, float(step_ms.sum())), "cpu_baseline": cpu,
+        "per_block": per_block, "roofline": _roofline(kern, args.steps, float(step_ms.sum()), args.config),
+        "cpu_baseline": cpu,
         "profiled_steps": args.steps,
         "kernels": _kernels(kern, args.steps),
     }
