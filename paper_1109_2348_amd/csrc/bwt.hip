@@ -7,8 +7,11 @@
 // of its group ("head"), so ranks of different blocks never collide and rank
 // order is rotation order.
 //
-//  init   SA = rows in descending start order; key = 4 cyclic bytes,
-//         big-endian; stable LSD radix per block; name groups.
+//  init   rows start in descending start order; stable LSD radix per
+//         block on the first 4 cyclic bytes (big-endian); name groups.  The
+//         passes move rows only: each pass reads its digit byte from the
+//         block's text (which stays in L2) at the row's position, so no key
+//         array is written or read, and the last pass leaves the rows in SA.
 //  round  for every unresolved group (a "segment"), key2 = rank of the
 //         rotation h positions on; stable sort of the segment by key2; a new
 //         group starts where key2 changes; rank = row of its head.  Groups of
@@ -45,24 +48,44 @@ __device__ __forceinline__ uint32_t lowest_lane(uint64_t m) { return (uint32_t)(
 
 // ------------------------------------------------------------------ init
 
-__global__ __launch_bounds__(NT) void k_sa_init(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
-                                                uint32_t nb, uint32_t N, uint32_t* __restrict__ SA,
-                                                uint32_t* __restrict__ key) {
-  uint32_t k = xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-  if (k >= N) return;
-  uint32_t b = find_block(off, nb, k);
-  uint32_t o = off[b], n = off[b + 1] - o;
-  uint32_t i = n - 1 - (k - o);  // descending start order
-  SA[k] = o + i;
+// q mod n for q < 2n + 3 (positions at most 3 past one wrap; blocks shorter
+// than 4 bytes may wrap more than once).
+__device__ __forceinline__ uint32_t cyc(uint32_t q, uint32_t n) {
+  q = q >= n ? q - n : q;
+  return q >= n ? q % n : q;
+}
+
+// Byte 3-p of the 4-byte key of the rotation at local position pos: the
+// digit of LSD pass p.
+__device__ __forceinline__ uint32_t text_digit(const uint8_t* __restrict__ text, uint32_t o, uint32_t n, uint32_t pos,
+                                               int p) {
+  return text[o + cyc(pos + 3u - (uint32_t)p, n)];
+}
+
+// The first 4 bytes of the rotation at local position pos, big-endian.  When
+// they do not wrap around the block end, two aligned dword loads, each
+// holding at least one of the 4 bytes (so neither leaves the allocation's
+// pages), replace four byte loads.
+__device__ __forceinline__ uint32_t text_key(const uint8_t* __restrict__ text, uint32_t o, uint32_t n, uint32_t pos) {
+  if (pos + 3u < n) {
+    const uintptr_t a = (uintptr_t)(text + o + pos);
+    const uint32_t* w = (const uint32_t*)(a & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3u) * 8u;
+    uint32_t v = w[0] >> sh;
+    if (sh) v |= w[1] << (32u - sh);
+    return __builtin_bswap32(v);
+  }
   uint32_t v = 0;
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    uint32_t q = i + j;
-    while (q >= n) q -= n;
-    v = (v << 8) | text[o + q];
-  }
-  key[k] = v;
+  for (uint32_t j = 0; j < 4; j++) v = (v << 8) | text[o + cyc(pos + j, n)];
+  return v;
 }
+
+// Where the init sort reads its keys: the batch text and block offsets.
+struct TextSrc {
+  const uint8_t* text;
+  const uint32_t* blk_off;
+};
 
 // -------------------------------------------------- segment radix passes
 
@@ -81,23 +104,54 @@ __device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, cons
   return g;
 }
 
+// Per-tile digit counts of one LSD pass.  Keyed: digit = (kin >> shift) & 255.
+// TEXT (init sort): kin holds rows (global text positions; pass 0 derives
+// them from the row index instead), digit = byte 3-pass of the row's key.
+template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                    const uint32_t* __restrict__ kin, int shift,
-                                                   uint32_t* __restrict__ hist) {
+                                                   uint32_t* __restrict__ hist, TextSrc ts, int pass) {
   __shared__ uint32_t cnt[NW][256];
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  uint32_t o = 0, n = 0;
+  if (TEXT) {
+    o = ts.blk_off[g.r.blk];
+    n = ts.blk_off[g.r.blk + 1] - o;
+  }
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
-  for (int i = 0; i < RI; i++) {
-    uint32_t k = wbase + i * BZG_WAVE + lane();
-    bool ok = k < g.hi;
-    uint64_t valid = __ballot(ok);
-    if (!valid) break;
-    uint32_t d = ok ? (kin[k] >> shift) & 255u : 0u;
-    uint64_t peers = match_digit8(d, valid);
-    if (ok && lowest_lane(peers) == lane()) cnt[w][d] += __popcll(peers);
+  // loads in groups of 4 (independent, then the dependent digit gathers),
+  // then the in-wave counting of the group
+  constexpr int GRP = 4;
+#pragma unroll
+  for (int c = 0; c < RI; c += GRP) {
+    uint32_t dg[GRP];
+#pragma unroll
+    for (int j = 0; j < GRP; j++) {
+      const uint32_t k = wbase + (c + j) * BZG_WAVE + lane();
+      dg[j] = 0;
+      if (k < g.hi) dg[j] = TEXT ? (pass == 0 ? n - 1u - (k - o) : kin[k] - o) : (kin[k] >> shift) & 255u;
+    }
+    if (TEXT) {
+#pragma unroll
+      for (int j = 0; j < GRP; j++) {
+        const uint32_t k = wbase + (c + j) * BZG_WAVE + lane();
+        if (k < g.hi) dg[j] = text_digit(ts.text, o, n, dg[j], pass);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < GRP; j++) {
+      const uint32_t k = wbase + (c + j) * BZG_WAVE + lane();
+      const bool ok = k < g.hi;
+      const uint64_t valid = __ballot(ok);
+      if (valid) {
+        const uint32_t d = dg[j];
+        const uint64_t peers = match_digit8(d, valid);
+        if (ok && lowest_lane(peers) == lane()) cnt[w][d] += __popcll(peers);
+      }
+    }
   }
   __syncthreads();
   uint32_t d = threadIdx.x;
@@ -107,29 +161,59 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
+// One stable LSD pass.  Keyed: (key, value) pairs move.  TEXT: only rows
+// move (vin is unused in pass 0, where rows come from the row index in
+// descending start order) and the digit comes from the text as in
+// k_radix_hist; the last pass (3, the most significant byte) writes each
+// row's full key too, for the naming that follows.
+template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
                                                       const uint32_t* __restrict__ owner,
                                                       const uint32_t* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int shift,
-                                                      const uint32_t* __restrict__ hscan) {
+                                                      const uint32_t* __restrict__ hscan, TextSrc ts, int pass) {
   __shared__ uint32_t cnt[NW][256];
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  uint32_t o = 0, n = 0;
+  if (TEXT) {
+    o = ts.blk_off[g.r.blk];
+    n = ts.blk_off[g.r.blk + 1] - o;
+  }
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
+  const bool last_text = TEXT && pass == 3;  // the MSB pass also writes the full key
   uint32_t key[RI], val[RI], rk[RI];
 #pragma unroll
   for (int i = 0; i < RI; i++) {
-    uint32_t k = wbase + i * BZG_WAVE + lane();
-    bool ok = k < g.hi;
-    uint64_t valid = __ballot(ok);
-    key[i] = ok ? kin[k] : 0u;
-    val[i] = ok ? vin[k] : 0u;
+    const uint32_t k = wbase + i * BZG_WAVE + lane();
+    const bool ok = k < g.hi;
+    if (TEXT) {
+      val[i] = ok ? (pass == 0 ? o + (n - 1u - (k - o)) : vin[k]) : 0u;
+    } else {
+      key[i] = ok ? kin[k] : 0u;
+      val[i] = ok ? vin[k] : 0u;
+    }
+  }
+  if (TEXT) {  // key[] holds the digit, or on the last pass the key
+#pragma unroll
+    for (int i = 0; i < RI; i++) {
+      const uint32_t k = wbase + i * BZG_WAVE + lane();
+      key[i] = 0;
+      if (k < g.hi)
+        key[i] = last_text ? text_key(ts.text, o, n, val[i] - o) : text_digit(ts.text, o, n, val[i] - o, pass);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    const uint32_t k = wbase + i * BZG_WAVE + lane();
+    const bool ok = k < g.hi;
+    const uint64_t valid = __ballot(ok);
+    const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i]) : (key[i] >> shift) & 255u;
     rk[i] = 0xFFFFFFFFu;
     if (valid) {
-      uint32_t d = (key[i] >> shift) & 255u;
       uint64_t peers = match_digit8(d, valid);
       uint32_t before = cnt[w][d];
       if (ok) rk[i] = before + __popcll(peers & lanemask_lt());
@@ -152,9 +236,9 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     if (rk[i] != 0xFFFFFFFFu) {
-      uint32_t d = (key[i] >> shift) & 255u;
-      uint32_t pos = cnt[w][d] + rk[i];
-      kout[pos] = key[i];
+      const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i]) : (key[i] >> shift) & 255u;
+      const uint32_t pos = cnt[w][d] + rk[i];
+      if (!TEXT || last_text) kout[pos] = key[i];
       vout[pos] = val[i];
     }
   }
@@ -245,10 +329,13 @@ __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs
   }
 }
 
+// Names the groups of sorted large segments: SA rows in place (vin may be
+// SA itself), rank of every row = its group's head row, new segments
+// appended.
 __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
-                                                 const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                 const uint32_t* __restrict__ kin, const uint32_t* vin,
                                                  const uint32_t* __restrict__ agg, const uint32_t* __restrict__ blk_off,
-                                                 uint32_t* __restrict__ SA, uint32_t* __restrict__ rank,
+                                                 uint32_t* SA, uint32_t* __restrict__ rank,
                                                  uint32_t h_next, int key_is_rank, AppendCtx app) {
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
@@ -264,18 +351,23 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
     }
     s_carry = c;
   }
-  const uint32_t nblk = blk_off[g.r.blk + 1] - blk_off[g.r.blk];
+  const uint32_t bo = blk_off[g.r.blk];
+  const uint32_t nblk = blk_off[g.r.blk + 1] - bo;
   const bool keep_blk = h_next < nblk;
   const uint32_t segend = g.r.start + g.r.len;
   const uint32_t k0 = g.lo + threadIdx.x * RI;  // blocked: RI consecutive rows per thread
   uint32_t kk[RI];
   uint32_t lastb = 0;
+  // key of the row before this thread's first row, and after its last
+  const uint32_t kprev = (k0 < g.hi && k0 > g.r.start) ? kin[k0 - 1] : 0u;
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     uint32_t k = k0 + i;
     kk[i] = k < g.hi ? kin[k] : 0u;
-    if (k < g.hi && (k == g.r.start || kk[i] != (i ? kk[i - 1] : kin[k - 1]))) lastb = k + 1;
+    if (k < g.hi && (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev))) lastb = k + 1;
   }
+  const uint32_t klast = k0 + RI - 1;
+  const uint32_t knext = (klast < g.hi && klast + 1 < segend) ? kin[klast + 1] : 0u;
   __syncthreads();
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
@@ -288,16 +380,18 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   for (int i = 0; i < RI; i++) {
     uint32_t k = k0 + i;
     if (k < g.hi) {
-      if (k == g.r.start || kk[i] != (i ? kk[i - 1] : kin[k - 1])) hp = k + 1;
+      if (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev)) hp = k + 1;
       uint32_t v = vin[k];
-      SA[k] = v;
+      if (vin != SA) SA[k] = v;
       rank[v] = hp - 1;
-      bool end = (k + 1 == segend) || ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : kin[k + 1] != kk[i]);
+      bool end = (k + 1 == segend) ||
+                 ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : (i + 1 < RI) ? kin[k + 1] != kk[i]
+                                                                                    : knext != kk[i]);
       if (end) {
         uint32_t len = k + 1 - (hp - 1);
         // closed group: the segment did not split and every partner lies in
         // it, so its rotations are all equal (already in final order)
-        const bool closed = key_is_rank && len == g.r.len && kk[i] == g.r.start - blk_off[g.r.blk];
+        const bool closed = key_is_rank && len == g.r.len && kk[i] == g.r.start - bo;
         if (len >= 2 && keep_blk && !closed && m < RI / 2 + 1) {
           gs[m] = hp - 1;
           gl[m] = len;
@@ -581,7 +675,8 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
   for (int p = 0; p < passes; p++) {
     {
       ProfScope ps("radix_hist", st, 4.0 * elems);  // read the key
-      hipLaunchKernelGGL(k_radix_hist, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist);
+      hipLaunchKernelGGL(k_radix_hist<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
+                         TextSrc{}, p);
     }
     {
       ProfScope ps("scan", st, 8.0 * big_tiles * 256);
@@ -589,13 +684,39 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
       if (e != hipSuccess) return e;
     }
     ProfScope ps("radix_scatter", st, 16.0 * elems);  // read and write key and value
-    hipLaunchKernelGGL(k_radix_scatter, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
-                       w.hist);
+    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
+                       w.hist, TextSrc{}, p);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
   *kin = ka;
   *vin = va;
+  return hipGetLastError();
+}
+
+// The init sort: 4 LSD passes on the first 4 bytes of every rotation, rows
+// only (see k_radix_scatter<true>).  Pass 0 writes tmpV, pass 3 writes SA
+// and the sorted keys into w.key.
+static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, double elems,
+                              TextSrc ts, hipStream_t st) {
+  const uint32_t* vin = nullptr;
+  for (int p = 0; p < 4; p++) {
+    uint32_t* vout = (p & 1) ? w.SA : w.tmpV;
+    {
+      ProfScope ps("radix_hist", st, (p == 0 ? 1.0 : 5.0) * elems);  // rows + digit bytes
+      hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, vin, 0, w.hist, ts, p);
+    }
+    {
+      ProfScope ps("scan", st, 8.0 * big_tiles * 256);
+      hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
+      if (e != hipSuccess) return e;
+    }
+    // rows in and out, digit bytes; the last pass writes keys too
+    ProfScope ps("radix_scatter", st, (p == 0 ? 5.0 : p == 3 ? 13.0 : 9.0) * elems);
+    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, vin, w.key,
+                       vout, 0, w.hist, ts, p);
+    vin = vout;
+  }
   return hipGetLastError();
 }
 
@@ -645,17 +766,15 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
   uint32_t max_n = 0;
   for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
-  {
-    ProfScope ps("sa_init", st, 9.0 * N);  // read the text, write row and key
-    hipLaunchKernelGGL(k_sa_init, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, w.d_off, nb, N, w.SA, w.key);
-  }
-  // initial segments: every block of two or more rows, as a large segment
+  const TextSrc ts{text, w.d_off};
+  // initial segments: every block as a large segment (a one-row block too:
+  // the init passes are what put its row into SA)
   std::vector<SegRec> segs0;
   std::vector<uint32_t> owner0;
   double init_elems = 0;
   for (uint32_t b = 0; b < nb; b++) {
     uint32_t n = h_off[b + 1] - h_off[b];
-    if (n < 2) continue;
+    if (n == 0) continue;
     init_elems += n;
     SegRec r{h_off[b], n, b, (uint32_t)owner0.size()};
     for (uint32_t t = 0; t < (n + RADIX_TILE - 1) / RADIX_TILE; t++) owner0.push_back((uint32_t)segs0.size());
@@ -668,15 +787,15 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     BZG_TRY(hipMemcpyAsync(w.owner[0], owner0.data(), owner0.size() * 4, hipMemcpyHostToDevice, st));
     uint32_t big_tiles = (uint32_t)owner0.size();
     uint32_t *kin, *vin;
-    BZG_TRY(radix_passes(w, big_tiles, w.segs[0], w.owner[0], 4, init_elems, &kin, &vin, st));
+    BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, ts, st));
     AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1]};
     {
       ProfScope ps("rename_a", st, 4.0 * init_elems);
-      hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, w.agg);
+      hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.agg);
     }
     {
-      ProfScope ps("rename_b", st, 16.0 * init_elems);
-      hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], kin, vin, w.agg,
+      ProfScope ps("rename_b", st, 12.0 * init_elems);  // key and row in, rank out
+      hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.SA, w.agg,
                          w.d_off, w.SA, w.rank, 4u, 0, app);
     }
     BZG_TRY(hipGetLastError());
