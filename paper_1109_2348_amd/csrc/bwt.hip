@@ -81,10 +81,15 @@ __device__ __forceinline__ uint32_t text_key(const uint8_t* __restrict__ text, u
   return v;
 }
 
-// Where the init sort reads its keys: the batch text and block offsets.
+// Where the init sort reads its digits: the batch text and block offsets,
+// and the digit bytes of the current pass (din, in row order) and the next
+// (dout), written by the previous scatter so that histograms read a plain
+// byte stream and each pass gathers at most one byte per row.
 struct TextSrc {
   const uint8_t* text;
   const uint32_t* blk_off;
+  const uint8_t* din;
+  uint8_t* dout;
 };
 
 // -------------------------------------------------- segment radix passes
@@ -105,8 +110,9 @@ __device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, cons
 }
 
 // Per-tile digit counts of one LSD pass.  Keyed: digit = (kin >> shift) & 255.
-// TEXT (init sort): kin holds rows (global text positions; pass 0 derives
-// them from the row index instead), digit = byte 3-pass of the row's key.
+// TEXT (init sort): pass 0 reads byte 3 of each row's key from the text (rows
+// are in descending start order, so this is a sequential read); later passes
+// read the digit bytes the previous scatter wrote (ts.din).
 template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                    const uint32_t* __restrict__ kin, int shift,
@@ -122,35 +128,25 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
     n = ts.blk_off[g.r.blk + 1] - o;
   }
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
-  // loads in groups of 4 (independent, then the dependent digit gathers),
-  // then the in-wave counting of the group
-  constexpr int GRP = 4;
+  uint32_t dg[RI];
 #pragma unroll
-  for (int c = 0; c < RI; c += GRP) {
-    uint32_t dg[GRP];
-#pragma unroll
-    for (int j = 0; j < GRP; j++) {
-      const uint32_t k = wbase + (c + j) * BZG_WAVE + lane();
-      dg[j] = 0;
-      if (k < g.hi) dg[j] = TEXT ? (pass == 0 ? n - 1u - (k - o) : kin[k] - o) : (kin[k] >> shift) & 255u;
+  for (int i = 0; i < RI; i++) {
+    const uint32_t k = wbase + i * BZG_WAVE + lane();
+    dg[i] = 0;
+    if (k < g.hi) {
+      if (TEXT) dg[i] = pass == 0 ? ts.text[o + cyc(n - 1u - (k - o) + 3u, n)] : ts.din[k];
+      else dg[i] = (kin[k] >> shift) & 255u;
     }
-    if (TEXT) {
+  }
 #pragma unroll
-      for (int j = 0; j < GRP; j++) {
-        const uint32_t k = wbase + (c + j) * BZG_WAVE + lane();
-        if (k < g.hi) dg[j] = text_digit(ts.text, o, n, dg[j], pass);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < GRP; j++) {
-      const uint32_t k = wbase + (c + j) * BZG_WAVE + lane();
-      const bool ok = k < g.hi;
-      const uint64_t valid = __ballot(ok);
-      if (valid) {
-        const uint32_t d = dg[j];
-        const uint64_t peers = match_digit8(d, valid);
-        if (ok && lowest_lane(peers) == lane()) cnt[w][d] += __popcll(peers);
-      }
+  for (int i = 0; i < RI; i++) {
+    const uint32_t k = wbase + i * BZG_WAVE + lane();
+    const bool ok = k < g.hi;
+    const uint64_t valid = __ballot(ok);
+    if (valid) {
+      const uint32_t d = dg[i];
+      const uint64_t peers = match_digit8(d, valid);
+      if (ok && lowest_lane(peers) == lane()) cnt[w][d] += __popcll(peers);
     }
   }
   __syncthreads();
@@ -161,11 +157,13 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
-// One stable LSD pass.  Keyed: (key, value) pairs move.  TEXT: only rows
-// move (vin is unused in pass 0, where rows come from the row index in
-// descending start order) and the digit comes from the text as in
-// k_radix_hist; the last pass (3, the most significant byte) writes each
-// row's full key too, for the naming that follows.
+// One stable LSD pass.  Keyed: (key, value) pairs move.  TEXT (init sort):
+// rows move with their next pass's digit byte (ts.dout); pass 0 takes rows
+// from the row index (descending start order) and both its digits from a
+// sequential text read, passes 1 and 2 gather the next digit from the text
+// at the row's position, and the last pass (3, the most significant byte)
+// gathers the row's full key instead and writes it to kout for the naming
+// that follows.
 template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
                                                       const uint32_t* __restrict__ owner,
@@ -184,26 +182,40 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     n = ts.blk_off[g.r.blk + 1] - o;
   }
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
-  const bool last_text = TEXT && pass == 3;  // the MSB pass also writes the full key
+  const bool last_text = TEXT && pass == 3;
+  // key[]: keyed mode the key; TEXT passes 0..2 digit | next digit << 8;
+  // TEXT pass 3 the full key (its digit is the top byte)
   uint32_t key[RI], val[RI], rk[RI];
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     const uint32_t k = wbase + i * BZG_WAVE + lane();
     const bool ok = k < g.hi;
-    if (TEXT) {
-      val[i] = ok ? (pass == 0 ? o + (n - 1u - (k - o)) : vin[k]) : 0u;
-    } else {
-      key[i] = ok ? kin[k] : 0u;
-      val[i] = ok ? vin[k] : 0u;
+    key[i] = 0;
+    val[i] = 0;
+    if (ok) {
+      if (TEXT) {
+        if (pass == 0) {
+          const uint32_t pos = n - 1u - (k - o);
+          val[i] = o + pos;
+          key[i] = ts.text[o + cyc(pos + 3u, n)] | ((uint32_t)ts.text[o + cyc(pos + 2u, n)] << 8);
+        } else {
+          val[i] = vin[k];
+          key[i] = ts.din[k];
+        }
+      } else {
+        key[i] = kin[k];
+        val[i] = vin[k];
+      }
     }
   }
-  if (TEXT) {  // key[] holds the digit, or on the last pass the key
+  if (TEXT && pass > 0) {  // the one gather per row
 #pragma unroll
     for (int i = 0; i < RI; i++) {
       const uint32_t k = wbase + i * BZG_WAVE + lane();
-      key[i] = 0;
-      if (k < g.hi)
-        key[i] = last_text ? text_key(ts.text, o, n, val[i] - o) : text_digit(ts.text, o, n, val[i] - o, pass);
+      if (k < g.hi) {
+        const uint32_t pos = val[i] - o;
+        key[i] = last_text ? text_key(ts.text, o, n, pos) : key[i] | (text_digit(ts.text, o, n, pos, pass + 1) << 8);
+      }
     }
   }
 #pragma unroll
@@ -211,7 +223,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     const uint32_t k = wbase + i * BZG_WAVE + lane();
     const bool ok = k < g.hi;
     const uint64_t valid = __ballot(ok);
-    const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i]) : (key[i] >> shift) & 255u;
+    const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i] & 255u) : (key[i] >> shift) & 255u;
     rk[i] = 0xFFFFFFFFu;
     if (valid) {
       uint64_t peers = match_digit8(d, valid);
@@ -221,10 +233,21 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     }
   }
   __syncthreads();
+  // The tile is staged in LDS in digit order, then every digit's run is
+  // written out by consecutive lanes to consecutive addresses.
+  __shared__ uint32_t sval[RADIX_TILE], skey[RADIX_TILE];
+  __shared__ uint32_t gbase[256], lbase[256];
+  __shared__ uint32_t sh[NW + 1];
   {
-    uint32_t d = threadIdx.x;
+    const uint32_t d = threadIdx.x;  // NT == 256: one digit per thread
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < NW; q++) tot += cnt[q][d];
+    uint32_t all;
+    uint32_t run = block_excl_sum<uint32_t, NT>(tot, sh, &all);
     const size_t col0 = (size_t)g.r.base * 256;
-    uint32_t run = g.r.start + hscan[col0 + (size_t)d * g.nt + g.t] - hscan[col0];
+    lbase[d] = run;
+    gbase[d] = g.r.start + hscan[col0 + (size_t)d * g.nt + g.t] - hscan[col0];
 #pragma unroll
     for (int q = 0; q < NW; q++) {
       uint32_t c = cnt[q][d];
@@ -236,10 +259,24 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     if (rk[i] != 0xFFFFFFFFu) {
-      const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i]) : (key[i] >> shift) & 255u;
-      const uint32_t pos = cnt[w][d] + rk[i];
-      if (!TEXT || last_text) kout[pos] = key[i];
-      vout[pos] = val[i];
+      const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i] & 255u) : (key[i] >> shift) & 255u;
+      const uint32_t L = cnt[w][d] + rk[i];
+      sval[L] = val[i];
+      skey[L] = key[i];
+    }
+  }
+  __syncthreads();
+  const uint32_t tn = g.hi - g.lo;
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    const uint32_t L = i * NT + threadIdx.x;
+    if (L < tn) {
+      const uint32_t kd = skey[L];
+      const uint32_t d = TEXT ? (last_text ? kd >> 24 : kd & 255u) : (kd >> shift) & 255u;
+      const uint32_t pos = gbase[d] + (L - lbase[d]);
+      if (!TEXT || last_text) kout[pos] = kd;
+      else ts.dout[pos] = (uint8_t)(kd >> 8);
+      vout[pos] = sval[L];
     }
   }
 }
@@ -700,10 +737,14 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
 static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, double elems,
                               TextSrc ts, hipStream_t st) {
   const uint32_t* vin = nullptr;
+  // digit bytes ping-pong through tmpK and key (key is written only by pass 3)
+  uint8_t* dbuf[2] = {(uint8_t*)w.tmpK, (uint8_t*)w.key};
   for (int p = 0; p < 4; p++) {
     uint32_t* vout = (p & 1) ? w.SA : w.tmpV;
+    ts.din = p ? dbuf[(p - 1) & 1] : nullptr;
+    ts.dout = p < 3 ? dbuf[p & 1] : nullptr;
     {
-      ProfScope ps("radix_hist", st, (p == 0 ? 1.0 : 5.0) * elems);  // rows + digit bytes
+      ProfScope ps("init_hist", st, 1.0 * elems);  // one digit byte per row
       hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, vin, 0, w.hist, ts, p);
     }
     {
@@ -711,8 +752,9 @@ static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs
       hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
       if (e != hipSuccess) return e;
     }
-    // rows in and out, digit bytes; the last pass writes keys too
-    ProfScope ps("radix_scatter", st, (p == 0 ? 5.0 : p == 3 ? 13.0 : 9.0) * elems);
+    // row and digit in (pass 0: two text bytes), row and next digit out
+    // (pass 3: row and key out, plus the gathered key bytes)
+    ProfScope ps("init_scatter", st, (p == 0 ? 7.0 : p == 3 ? 14.0 : 11.0) * elems);
     hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, vin, w.key,
                        vout, 0, w.hist, ts, p);
     vin = vout;
@@ -766,7 +808,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
   uint32_t max_n = 0;
   for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
-  const TextSrc ts{text, w.d_off};
+  const TextSrc ts{text, w.d_off, nullptr, nullptr};
   // initial segments: every block as a large segment (a one-row block too:
   // the init passes are what put its row into SA)
   std::vector<SegRec> segs0;
