@@ -634,9 +634,13 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
       // closed group (see k_rename_b): equal rotations, final
       const bool closed = len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - blk_off[r.blk];
       if (len >= 2 && h_next < nbk && !closed) {
-        gs[m] = headk;
-        gl[m] = len;
-        gb[m] = r.blk;
+#pragma unroll
+        for (int q = 0; q < PI / 2 + 1; q++)  // register-resident append
+          if (q == m) {
+            gs[q] = headk;
+            gl[q] = len;
+            gb[q] = r.blk;
+          }
         m++;
       }
     }

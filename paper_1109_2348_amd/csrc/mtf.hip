@@ -411,19 +411,25 @@ __device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g
       }
       uint64_t N = __shfl_up(incl, 1, BZG_WAVE);
       if (l == 0) N = 0;
+      // below = #{first-occurrence lanes k < l with R_k < R_l}, one ballot
+      // per bit of R from the top: at bit b, lanes that agree with R_l above
+      // b and have a 0 where R_l has a 1 are smaller
+      uint32_t below = 0;
+      {
+        uint64_t eq = first_m & lt;
+#pragma unroll
+        for (int b = 7; b >= 0; b--) {
+          const bool mb = (R >> b) & 1u;
+          const uint64_t B = __ballot(mb);
+          if (mb) below += (uint32_t)__popcll(eq & ~B);
+          eq &= mb ? B : ~B;
+        }
+      }
       uint32_t idx;
       if (p >= 0) {
         const uint64_t upto_p = (p >= 63) ? ~0ull : ((2ull << p) - 1ull);
         idx = (uint32_t)__popcll(lt & ~N & ~upto_p);
       } else {
-        uint32_t below = 0;
-        uint64_t fm = first_m & ((1ull << 63) - 1ull);
-        while (fm) {
-          const int k = (int)first_lane(fm);
-          fm &= fm - 1;
-          const uint32_t rk = (uint32_t)__builtin_amdgcn_readlane((int)R, k);
-          below += ((int)l > k && rk < R) ? 1u : 0u;
-        }
         idx = (uint32_t)__popcll(first_m & lt) + R - below;
       }
       if (!valid) idx = 0;
