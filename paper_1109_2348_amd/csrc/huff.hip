@@ -45,11 +45,10 @@ struct HuffScratch {
   uint16_t parent[2 * MAXA];
 };
 
-// Column c (uniform, < 5) of a 5-register wave array, lane i (uniform).
-__device__ __forceinline__ uint32_t col_read(uint32_t c, uint32_t i, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
-                                             uint32_t v4) {
-  uint32_t v = c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : c == 3 ? v3 : v4;
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
+// Column c (uniform, < 5) of a 5-register wave array.
+__device__ __forceinline__ uint32_t col_read_v(uint32_t c, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                               uint32_t v4) {
+  return c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : c == 3 ? v3 : v4;
 }
 
 // One wave, one Huffman pass over the weights hs->w[0..a): ranks the leaves
@@ -98,43 +97,72 @@ __device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
 #undef BZG_LD
   uint32_t WN0 = 0, WN1 = 0, WN2 = 0, WN3 = 0, WN4 = 0;  // internal node weights
   uint32_t DN0 = 0, DN1 = 0, DN2 = 0, DN3 = 0, DN4 = 0;  // internal node depths
+  // Leaves and internal nodes are consumed in order, so each queue's current
+  // 64-entry column sits in one register and a pick is a readlane of it:
+  //   cLW/cOR  column li>>6 of the leaf weights / ids,
+  //   cRW/cRD  column ni>>6 of the internal weights / depths, when that
+  //            column is complete (ni>>6 < nn>>6),
+  //   cWW/cWD  column nn>>6 being written; flushed to WN/DN when full.
+  // The 5-column arrays are only touched when an index crosses a column.
+  uint32_t cLW = LW0, cOR = OR0, cRW = 0, cRD = 0, cWW = 0, cWD = 0;
   uint32_t li = 0, ni = 0, nn = 0, dmax = 0;
-  uint32_t lw_head = col_read(0, 0, LW0, LW1, LW2, LW3, LW4);
+  uint32_t lw_head = (uint32_t)__builtin_amdgcn_readlane((int)cLW, 0);
   uint32_t wn_head = 0;
   for (int step = 0; step < a - 1; step++) {
     uint32_t wsum = 0, dnew = 0, ids[2];
+#pragma unroll
     for (int pick = 0; pick < 2; pick++) {
       const bool leaf = li < (uint32_t)a && (ni >= nn || lw_head <= wn_head);  // leaf ids sort first
       if (leaf) {
-        ids[pick] = col_read(li >> 6, li & 63, OR0, OR1, OR2, OR3, OR4);
+        ids[pick] = (uint32_t)__builtin_amdgcn_readlane((int)cOR, (int)(li & 63));
         wsum += lw_head;
         li++;
-        lw_head = li < (uint32_t)a ? col_read(li >> 6, li & 63, LW0, LW1, LW2, LW3, LW4) : 0u;
+        if ((li & 63) == 0 && li < (uint32_t)a) {
+          cLW = col_read_v(li >> 6, LW0, LW1, LW2, LW3, LW4);
+          cOR = col_read_v(li >> 6, OR0, OR1, OR2, OR3, OR4);
+        }
+        lw_head = li < (uint32_t)a ? (uint32_t)__builtin_amdgcn_readlane((int)cLW, (int)(li & 63)) : 0u;
       } else {
         ids[pick] = (uint32_t)a + ni;
         wsum += wn_head;
-        const uint32_t d = col_read(ni >> 6, ni & 63, DN0, DN1, DN2, DN3, DN4);
+        const bool wcol = (ni >> 6) == (nn >> 6);
+        const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)(wcol ? cWD : cRD), (int)(ni & 63));
         dnew = d > dnew ? d : dnew;
         ni++;
-        wn_head = ni < nn ? col_read(ni >> 6, ni & 63, WN0, WN1, WN2, WN3, WN4) : 0u;
+        if ((ni & 63) == 0 && (ni >> 6) < (nn >> 6)) {
+          cRW = col_read_v(ni >> 6, WN0, WN1, WN2, WN3, WN4);
+          cRD = col_read_v(ni >> 6, DN0, DN1, DN2, DN3, DN4);
+        }
+        wn_head = ni < nn ? (uint32_t)__builtin_amdgcn_readlane((int)((ni >> 6) == (nn >> 6) ? cWW : cRW),
+                                                                (int)(ni & 63))
+                          : 0u;
       }
     }
     dnew += 1;
     dmax = dnew;
-    const uint32_t c = nn >> 6;
     const bool me = (uint32_t)l == (nn & 63);
-#define BZG_PUT(q)    \
-  if (c == q && me) { \
-    WN##q = wsum;     \
-    DN##q = dnew;     \
-  }
-    BZG_PUT(0) BZG_PUT(1) BZG_PUT(2) BZG_PUT(3) BZG_PUT(4)
-#undef BZG_PUT
+    cWW = me ? wsum : cWW;
+    cWD = me ? dnew : cWD;
     if (l == 0) {
       hs->parent[ids[0]] = (uint16_t)(a + nn);
       hs->parent[ids[1]] = (uint16_t)(a + nn);
     }
     if (ni == nn) wn_head = wsum;  // the new node heads an empty internal queue
+    if ((nn & 63) == 63) {  // the write column is full: flush it
+      const uint32_t c = nn >> 6;
+#define BZG_PUT(q) \
+  if (c == q) {    \
+    WN##q = cWW;   \
+    DN##q = cWD;   \
+  }
+      BZG_PUT(0) BZG_PUT(1) BZG_PUT(2) BZG_PUT(3) BZG_PUT(4)
+#undef BZG_PUT
+      // the reader, if it is in this column, now reads the complete copy
+      if ((ni >> 6) == c) {
+        cRW = cWW;
+        cRD = cWD;
+      }
+    }
     nn++;
   }
   __builtin_amdgcn_wave_barrier();
