@@ -126,6 +126,22 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t valid) {
   return m;
 }
 
+// Up to 16 bytes starting at p (1 <= n <= 16 of them valid) as 4 little-endian
+// words: byte i of the span is byte i%4 of word i/4.  Reads the aligned
+// dwords that hold at least one valid byte (so never a page the span does not
+// touch) and realigns them with v_alignbyte; bytes past n are unspecified.
+__device__ __forceinline__ void load16(const uint8_t* p, uint32_t n, uint32_t out[4]) {
+  const uintptr_t a = (uintptr_t)p;
+  const uint32_t* w = (const uint32_t*)(a & ~(uintptr_t)3);
+  const uint32_t sh = (uint32_t)(a & 3u);
+  const uint32_t nd = (sh + n + 3u) >> 2;  // dwords holding valid bytes (<= 5)
+  uint32_t v[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) v[j] = (uint32_t)j < nd ? w[j] : 0u;
+#pragma unroll
+  for (int j = 0; j < 4; j++) out[j] = __builtin_amdgcn_alignbyte(v[j + 1], v[j], sh);
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin by workgroup id.  This
 // maps workgroup id -> logical tile so that every XCD runs one contiguous
 // range of tiles: neighbouring tiles (the same block's rows, ranks and text)

@@ -54,15 +54,18 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t t, const uint32_t* tile_b
   return g;
 }
 
-// Loads this thread's RITEMS bytes and the byte before them.
+// Loads this thread's RITEMS (16) bytes, as dwords, and the byte before them.
 __device__ __forceinline__ void load_run(const uint8_t* s, const TileGeom& g, uint32_t p0, uint8_t* v,
                                          int& cnt, uint32_t& prev) {
+  static_assert(RITEMS == 16, "one 16-byte span per thread");
   cnt = 0;
   prev = 0x100u;  // never equal to a byte
   if (p0 < g.hi) cnt = (int)min((uint32_t)RITEMS, g.hi - p0);
   if (p0 > 0 && p0 < g.hi) prev = s[g.base + p0 - 1];
+  uint32_t w[4] = {0, 0, 0, 0};
+  if (cnt) load16(s + g.base + p0, (uint32_t)cnt, w);
 #pragma unroll
-  for (int i = 0; i < RITEMS; i++) v[i] = i < cnt ? s[g.base + p0 + i] : 0;
+  for (int i = 0; i < RITEMS; i++) v[i] = i < cnt ? (uint8_t)(w[i >> 2] >> (8 * (i & 3))) : 0;
 }
 
 __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* tile_blk,

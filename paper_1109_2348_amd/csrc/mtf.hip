@@ -76,16 +76,35 @@ __device__ __forceinline__ ChunkGeom chunk_geom(uint32_t c, const uint32_t* chun
   return g;
 }
 
+// This thread's MITEMS (32) consecutive rows from r0 (those below hi) as
+// dwords; returns how many are valid.
+__device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uint32_t r0, uint32_t hi,
+                                              uint32_t w[MITEMS / 4]) {
+  static_assert(MITEMS == 32, "two 16-byte spans per thread");
+  const uint32_t cnt = r0 < hi ? min((uint32_t)MITEMS, hi - r0) : 0u;
+#pragma unroll
+  for (int j = 0; j < MITEMS / 4; j++) w[j] = 0;
+  if (cnt) load16(L + r0, min(cnt, 16u), w);
+  if (cnt > 16) load16(L + r0 + 16, cnt - 16, w + 4);
+  return cnt;
+}
+
 // In-use bitmap per block (8 words; the caller zeroes it).
 __global__ __launch_bounds__(NT) void k_inuse(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
                                               const uint32_t* blk_chunk0, const uint32_t* off,
                                               uint32_t* __restrict__ inuse) {
   ChunkGeom g = chunk_geom(blockIdx.x, chunk_blk, blk_chunk0, off);
   uint32_t bm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
-    uint32_t v = L[k];
+  const uint32_t r0 = g.lo + threadIdx.x * MITEMS;
+  uint32_t w[MITEMS / 4];
+  const uint32_t cnt = load_rows(L, r0, g.hi, w);
 #pragma unroll
-    for (int j = 0; j < 8; j++) bm[j] |= ((v >> 5) == (uint32_t)j) ? (1u << (v & 31)) : 0u;
+  for (int i = 0; i < MITEMS; i++) {
+    if ((uint32_t)i < cnt) {
+      const uint32_t v = (w[i >> 2] >> (8 * (i & 3))) & 255u;
+#pragma unroll
+      for (int j = 0; j < 8; j++) bm[j] |= ((v >> 5) == (uint32_t)j) ? (1u << (v & 31)) : 0u;
+    }
   }
 #pragma unroll
   for (int j = 0; j < 8; j++) {
@@ -120,12 +139,14 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   uint8_t v[MITEMS];
   uint32_t prev = 0x100u;
   if (r0 < g.hi) prev = (r0 == g.blo) ? minb : L[r0 - 1];
+  uint32_t w[MITEMS / 4];
+  load_rows(L, r0, g.hi, w);
   ZSum s = {0, 0, 0, 0, 0, 1};
 #pragma unroll
   for (int i = 0; i < MITEMS; i++) {
     uint32_t k = r0 + i;
     if (k < g.hi) {
-      v[i] = L[k];
+      v[i] = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
       ZSum e;
       if (v[i] == prev) e = {1, 1, 0, 0, 1, 1};
       else e = {0, 0, 0, 1, 1, 0};
