@@ -651,19 +651,44 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
 // ------------------------------------------------------------- final BWT
 
 // L[k] = byte before rotation SA[k]; primary[b] = row of rotation 0; the
-// optional local SA.
+// optional local SA.  Each thread takes OUT_ROWS consecutive rows (one block
+// search, then the block boundary is followed), L is stored a dword at a
+// time.
+constexpr uint32_t OUT_ROWS = 16;
+
 __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
                                                 uint32_t nb, uint32_t N, const uint32_t* __restrict__ SA,
                                                 uint8_t* __restrict__ L, uint32_t* __restrict__ primary,
                                                 uint32_t* __restrict__ sa_local) {
-  uint32_t k = xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-  if (k >= N) return;
-  uint32_t b = find_block(off, nb, k);
-  uint32_t o = off[b], n = off[b + 1] - o;
-  uint32_t p = SA[k];
-  L[k] = text[p == o ? o + n - 1 : p - 1];
-  if (p == o) primary[b] = k - o;
-  if (sa_local) sa_local[k] = p - o;
+  const uint32_t k0 = (xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x) * OUT_ROWS;
+  if (k0 >= N) return;
+  const uint32_t cnt = min(OUT_ROWS, N - k0);
+  uint32_t b = find_block(off, nb, k0);
+  uint32_t o = off[b], e = off[b + 1];
+  uint32_t p[OUT_ROWS];
+#pragma unroll
+  for (uint32_t i = 0; i < OUT_ROWS; i++) p[i] = i < cnt ? SA[k0 + i] : 0u;
+  uint32_t w[OUT_ROWS / 4] = {0, 0, 0, 0};
+#pragma unroll
+  for (uint32_t i = 0; i < OUT_ROWS; i++) {
+    if (i < cnt) {
+      const uint32_t k = k0 + i;
+      while (k >= e) {  // next block (empty blocks do not occur)
+        b++;
+        o = e;
+        e = off[b + 1];
+      }
+      const uint32_t q = p[i];
+      w[i >> 2] |= (uint32_t)text[q == o ? e - 1 : q - 1] << (8 * (i & 3));
+      if (q == o) primary[b] = k - o;
+      if (sa_local) sa_local[k] = q - o;
+    }
+  }
+  if (cnt == OUT_ROWS && ((uintptr_t)(L + k0) & 15u) == 0) {
+    *(uint4*)(L + k0) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else {
+    for (uint32_t i = 0; i < cnt; i++) L[k0 + i] = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
+  }
 }
 
 // ------------------------------------------------------------- host side
@@ -901,8 +926,9 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
 hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, uint32_t N, const uint32_t* SA,
                       uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
   ProfScope ps("bwt_out", st, 6.0 * N);  // row in, byte gathered, byte out
-  if (N) hipLaunchKernelGGL(k_bwt_out, dim3((N + NT - 1) / NT), dim3(NT), 0, st, text, d_off, nb, N, SA, L, primary,
-                            sa_local);
+  const uint32_t threads = (N + OUT_ROWS - 1) / OUT_ROWS;
+  if (N) hipLaunchKernelGGL(k_bwt_out, dim3((threads + NT - 1) / NT), dim3(NT), 0, st, text, d_off, nb, N, SA, L,
+                            primary, sa_local);
   return hipGetLastError();
 }
 

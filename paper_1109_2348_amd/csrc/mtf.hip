@@ -22,7 +22,7 @@
 
 namespace bzg {
 
-constexpr int MITEMS = MTF_CHUNK / NT;  // 32 rows per thread
+constexpr int MITEMS = MTF_CHUNK / NT;  // rows per thread
 
 struct ZSum {
   uint32_t lz, tz, inner, nnz, len, all;
@@ -76,16 +76,17 @@ __device__ __forceinline__ ChunkGeom chunk_geom(uint32_t c, const uint32_t* chun
   return g;
 }
 
-// This thread's MITEMS (32) consecutive rows from r0 (those below hi) as
-// dwords; returns how many are valid.
+// This thread's MITEMS consecutive rows from r0 (those below hi) as dwords;
+// returns how many are valid.
 __device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uint32_t r0, uint32_t hi,
                                               uint32_t w[MITEMS / 4]) {
-  static_assert(MITEMS == 32, "two 16-byte spans per thread");
+  static_assert(MITEMS % 16 == 0, "whole 16-byte spans per thread");
   const uint32_t cnt = r0 < hi ? min((uint32_t)MITEMS, hi - r0) : 0u;
 #pragma unroll
   for (int j = 0; j < MITEMS / 4; j++) w[j] = 0;
-  if (cnt) load16(L + r0, min(cnt, 16u), w);
-  if (cnt > 16) load16(L + r0 + 16, cnt - 16, w + 4);
+#pragma unroll
+  for (uint32_t h = 0; h < (uint32_t)MITEMS; h += 16)
+    if (cnt > h) load16(L + r0 + h, min(cnt - h, 16u), w + h / 4);
   return cnt;
 }
 
