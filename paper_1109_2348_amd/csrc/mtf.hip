@@ -90,34 +90,13 @@ __device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uin
   return cnt;
 }
 
-// In-use bitmap per block (8 words; the caller zeroes it).
-__global__ __launch_bounds__(NT) void k_inuse(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
-                                              const uint32_t* blk_chunk0, const uint32_t* off,
-                                              uint32_t* __restrict__ inuse) {
-  ChunkGeom g = chunk_geom(blockIdx.x, chunk_blk, blk_chunk0, off);
-  uint32_t bm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const uint32_t r0 = g.lo + threadIdx.x * MITEMS;
-  uint32_t w[MITEMS / 4];
-  const uint32_t cnt = load_rows(L, r0, g.hi, w);
-#pragma unroll
-  for (int i = 0; i < MITEMS; i++) {
-    if ((uint32_t)i < cnt) {
-      const uint32_t v = (w[i >> 2] >> (8 * (i & 3))) & 255u;
-#pragma unroll
-      for (int j = 0; j < 8; j++) bm[j] |= ((v >> 5) == (uint32_t)j) ? (1u << (v & 31)) : 0u;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    uint32_t x = bm[j];
-    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d, BZG_WAVE);
-    if (lane() == 0 && x) atomicOr(&inuse[g.b * 8 + j], x);
-  }
-}
-
+// Per chunk: D_X (distinct bytes by last occurrence, latest first), the
+// zero-run summary of its rows -- without the block's first row, whose MTF
+// index depends on the whole block's in-use set and is added by k_mtf_scan --
+// and the block's in-use bitmap (OR-ed in; the caller zeroes it).
 __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
                                                   const uint32_t* blk_chunk0, const uint32_t* off,
-                                                  const uint32_t* __restrict__ inuse, uint8_t* __restrict__ chunk_D,
+                                                  uint32_t* __restrict__ inuse, uint8_t* __restrict__ chunk_D,
                                                   uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
   __shared__ uint32_t last[256];
   __shared__ ZSum wsum[NT];
@@ -126,20 +105,12 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
   last[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_nd = 0;
-  uint32_t minb = 0;
-  for (int j = 0; j < 8; j++) {
-    uint32_t x = inuse[g.b * 8 + j];
-    if (x) {
-      minb = j * 32 + (__ffs(x) - 1);
-      break;
-    }
-  }
   __syncthreads();
   // rows [lo + t*32, +32): last occurrences and the zero-run summary
   const uint32_t r0 = g.lo + threadIdx.x * MITEMS;
   uint8_t v[MITEMS];
   uint32_t prev = 0x100u;
-  if (r0 < g.hi) prev = (r0 == g.blo) ? minb : L[r0 - 1];
+  if (r0 < g.hi && r0 > g.blo) prev = L[r0 - 1];
   uint32_t w[MITEMS / 4];
   load_rows(L, r0, g.hi, w);
   ZSum s = {0, 0, 0, 0, 0, 1};
@@ -148,10 +119,12 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
     uint32_t k = r0 + i;
     if (k < g.hi) {
       v[i] = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
-      ZSum e;
-      if (v[i] == prev) e = {1, 1, 0, 0, 1, 1};
-      else e = {0, 0, 0, 1, 1, 0};
-      s = zcombine(s, e);
+      if (k != g.blo) {
+        ZSum e;
+        if (v[i] == prev) e = {1, 1, 0, 0, 1, 1};
+        else e = {0, 0, 0, 1, 1, 0};
+        s = zcombine(s, e);
+      }
       prev = v[i];
     }
   }
@@ -179,6 +152,12 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   {
     uint32_t x = threadIdx.x;
     uint32_t lx = last[x];
+    const uint64_t present = __ballot(lx != 0);  // bytes 64w .. 64w+63
+    if (lane() == 0 && present) {
+      const uint32_t wv = threadIdx.x / BZG_WAVE;
+      if ((uint32_t)present) atomicOr(&inuse[g.b * 8 + 2 * wv], (uint32_t)present);
+      if ((uint32_t)(present >> 32)) atomicOr(&inuse[g.b * 8 + 2 * wv + 1], (uint32_t)(present >> 32));
+    }
     if (lx) {
       uint32_t r = 0;
       for (int u = 0; u < 256; u++) r += (last[u] > lx) ? 1u : 0u;
@@ -198,6 +177,7 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
 // One wave per block: serial over its chunks.  Writes every chunk's incoming
 // stack, carried zero count and output offset, and the block's symbol count.
 __global__ __launch_bounds__(BZG_WAVE) void k_mtf_scan(const uint32_t* blk_chunk0, const uint32_t* __restrict__ inuse,
+                                                       const uint8_t* __restrict__ L, const uint32_t* __restrict__ off,
                                                        const uint8_t* __restrict__ chunk_D,
                                                        const uint32_t* __restrict__ chunk_nD,
                                                        const ZSum* __restrict__ chunk_sum,
@@ -233,11 +213,38 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_scan(const uint32_t* blk_chunk
   for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
   __syncthreads();
   const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1];
+  // the block's first row: MTF index 0 exactly when it holds the smallest
+  // in-use byte (the front of the initial stack)
+  uint32_t minb = 0;
+  for (int j = 7; j >= 0; j--)
+    if (bm[j]) minb = j * 32 + (__ffs(bm[j]) - 1);
+  const bool row0_zero = c0 < c1 && L[off[b]] == minb;
   uint32_t carry = 0, out = 0;
+  // the next chunk's D_X, its size and summary are loaded one chunk ahead
+  uint32_t nd_n = 0, dx_n[4] = {0, 0, 0, 0};
+  ZSum s_n = {0, 0, 0, 0, 0, 1};
+  if (c0 < c1) {
+    nd_n = chunk_nD[c0];
+    for (int j = 0; j < 4; j++) dx_n[j] = (uint32_t)(j * 64 + l) < nd_n ? chunk_D[(size_t)c0 * 256 + j * 64 + l] : 0u;
+    s_n = chunk_sum[c0];
+  }
   for (uint32_t c = c0; c < c1; c++) {
+    const uint32_t nd = nd_n;
+    uint32_t dx[4] = {dx_n[0], dx_n[1], dx_n[2], dx_n[3]};
+    ZSum s = s_n;
+    if (c + 1 < c1) {
+      nd_n = chunk_nD[c + 1];
+      for (int j = 0; j < 4; j++)
+        dx_n[j] = (uint32_t)(j * 64 + l) < nd_n ? chunk_D[(size_t)(c + 1) * 256 + j * 64 + l] : 0u;
+      s_n = chunk_sum[c + 1];
+    }
+    if (c == c0) {
+      const ZSum e0 = row0_zero ? ZSum{1, 1, 0, 0, 1, 1} : ZSum{0, 0, 0, 1, 1, 0};
+      s = zcombine(e0, s);
+    }
     for (int j = 0; j < 4; j++) chunk_list[(size_t)c * 256 + j * 64 + l] = (uint8_t)(e[j] & 255u);
-    const uint32_t nd = chunk_nD[c];
-    for (uint32_t i = l; i < nd; i += 64) f[chunk_D[(size_t)c * 256 + i]] = (uint16_t)(i + 1);
+    for (int j = 0; j < 4; j++)
+      if ((uint32_t)(j * 64 + l) < nd) f[dx[j]] = (uint16_t)(j * 64 + l + 1);
     __syncthreads();
     uint32_t isd[4];
     uint64_t nd_mask[4];
@@ -253,9 +260,9 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_scan(const uint32_t* blk_chunk
     }
     __syncthreads();
     for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
-    for (uint32_t i = l; i < nd; i += 64) f[chunk_D[(size_t)c * 256 + i]] = 0;
+    for (int j = 0; j < 4; j++)
+      if ((uint32_t)(j * 64 + l) < nd) f[dx[j]] = 0;
     __syncthreads();
-    ZSum s = chunk_sum[c];
     uint32_t cnt;
     if (l == 0) chunk_carry[c] = carry;
     if (s.all) {
@@ -589,18 +596,14 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   if ((e = hipMemsetAsync(freq, 0, (size_t)nb * MAXA * 4, st)) != hipSuccess) return e;
   const double n = h_off[nb];
   {
-    ProfScope ps("inuse", st, n);
-    hipLaunchKernelGGL(k_inuse, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse);
-  }
-  {
     ProfScope ps("mtf_state", st, n + 256.0 * nc);
     hipLaunchKernelGGL(k_mtf_state, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_D,
                        d_nD, d_sum);
   }
   {
     ProfScope ps("mtf_scan", st, 512.0 * nc);
-    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d_blk_chunk0, inuse, d_D, d_nD, d_sum, d_list,
-                       d_carry, d_out, nsyms);
+    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d_blk_chunk0, inuse, L, d_off, d_D, d_nD, d_sum,
+                       d_list, d_carry, d_out, nsyms);
   }
   {
     ProfScope ps("mtf_emit", st, 3.0 * n);  // read L, write at most one 2-byte symbol per row
