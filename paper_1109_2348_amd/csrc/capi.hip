@@ -12,13 +12,14 @@
 
 namespace bzg {
 // launchers from the kernel translation units
-hipError_t rle1_tiles(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const uint32_t*,
-                      const uint32_t*, void*, hipStream_t);
-hipError_t rle1_blocks(uint32_t, const uint32_t*, const uint64_t*, const uint32_t*, void*, uint32_t*, uint32_t*,
-                       uint32_t*, hipStream_t);
-hipError_t rle1_emit(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const void*,
+hipError_t rle1_tiles(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, const uint64_t*,
+                      const uint32_t*, const uint32_t*, void*, hipStream_t);
+hipError_t rle1_tile_copy(uint32_t, const uint32_t*, const void*, void*, hipStream_t);
+hipError_t rle1_blocks(uint32_t, const uint32_t*, const uint64_t*, const uint32_t*, const void*, uint32_t*, uint32_t*,
+                       uint32_t*, uint32_t*, hipStream_t);
+hipError_t rle1_emit(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const uint32_t*,
                      const uint32_t*, const uint64_t*, uint8_t*, hipStream_t);
-hipError_t rle1_cut(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const void*,
+hipError_t rle1_cut(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const uint32_t*,
                     const uint32_t*, uint32_t, uint32_t*, hipStream_t);
 size_t rle_tile_bytes();
 size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
@@ -521,7 +522,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   const size_t max_nb = nb + total / 50000 + 4;
   const size_t max_tiles = total / RLE_TILE + 2 * max_nb + 4;
   size_t need1 = sz<uint64_t>(max_nb + 1) + sz<uint32_t>(max_tiles) + sz<uint32_t>(max_nb + 1) +
-                 rle_tile_bytes() * max_tiles + 256 + sz<uint32_t>(max_tiles) + sz<uint32_t>(max_nb) * 4 +
+                 2 * (rle_tile_bytes() * max_tiles + 256) + sz<uint32_t>(max_tiles) * 4 + sz<uint32_t>(max_nb) * 4 +
                  sz<uint64_t>(max_nb + 1);
   void* ws1;
   if ((rc = ensure_ws(ctx, 1, need1, &ws1))) return rc;
@@ -529,7 +530,10 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   uint64_t* d_boff = c1.take<uint64_t>(max_nb + 1);
   uint32_t* d_tile_blk = c1.take<uint32_t>(max_tiles);
   uint32_t* d_blk_tile0 = c1.take<uint32_t>(max_nb + 1);
-  void* d_rtiles = c1.take<char>(rle_tile_bytes() * max_tiles);
+  void* d_rt[2] = {c1.take<char>(rle_tile_bytes() * max_tiles), c1.take<char>(rle_tile_bytes() * max_tiles)};
+  uint32_t* d_tile_rs = c1.take<uint32_t>(max_tiles);
+  uint32_t* d_tile_from = c1.take<uint32_t>(max_tiles);
+  uint32_t* d_tile_ids = c1.take<uint32_t>(max_tiles);
   uint32_t* d_tile_out = c1.take<uint32_t>(max_tiles);
   uint32_t* d_rle_n = c1.take<uint32_t>(max_nb);
   uint32_t* d_crc = c1.take<uint32_t>(max_nb);
@@ -537,6 +541,13 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   uint32_t* d_cuts = c1.take<uint32_t>(max_nb);
   uint64_t* d_rbase = c1.take<uint64_t>(max_nb + 1);
   std::vector<uint32_t> tile_blk, blk_tile0, rle_n;
+  // after a cut, each block's origin: (block of the previous plan, offset of
+  // its start in it); tiles that start at the same place and end at the same
+  // place as before are copied, the others (a cut block's last tile and its
+  // remainder) recomputed
+  std::vector<uint32_t> org_blk, prev_tile0, tile_from, tile_ids;
+  std::vector<uint64_t> org_delta, prev_boff;
+  int cur = 0;  // tile-record buffer of the current plan
   uint32_t ntiles = 0;
   for (int iter = 0;; iter++) {
     nb = (uint32_t)boff.size() - 1;
@@ -553,11 +564,40 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
     HIPX(hipMemcpyAsync(d_boff, boff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(d_tile_blk, tile_blk.data(), ntiles * 4, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(d_blk_tile0, blk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
-    {
+    if (iter == 0) {
       ProfScope ps("rle1_tiles", st, (double)(boff[nb] - boff[0]));
-      HIPX(rle1_tiles(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + 256, d_rtiles, st));
+      HIPX(rle1_tiles(in, ntiles, nullptr, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + 256,
+                      d_rt[cur], st));
+    } else {
+      tile_from.assign(ntiles, ~0u);
+      tile_ids.clear();
+      double bytes = 0;
+      for (uint32_t b = 0; b < nb; b++) {
+        const uint32_t ob = org_blk[b];
+        const uint64_t n = boff[b + 1] - boff[b], on = prev_boff[ob + 1] - prev_boff[ob];
+        for (uint32_t t = blk_tile0[b]; t < blk_tile0[b + 1]; t++) {
+          const uint64_t lo = (uint64_t)(t - blk_tile0[b]) * RLE_TILE;
+          if (org_delta[b] == 0 && std::min<uint64_t>(lo + RLE_TILE, n) == std::min<uint64_t>(lo + RLE_TILE, on)) {
+            tile_from[t] = prev_tile0[ob] + (t - blk_tile0[b]);
+          } else {
+            tile_ids.push_back(t);
+            bytes += (double)(std::min<uint64_t>(lo + RLE_TILE, n) - lo);
+          }
+        }
+      }
+      const int nxt = cur ^ 1;
+      HIPX(hipMemcpyAsync(d_tile_from, tile_from.data(), ntiles * 4, hipMemcpyHostToDevice, st));
+      HIPX(rle1_tile_copy(ntiles, d_tile_from, d_rt[cur], d_rt[nxt], st));
+      if (!tile_ids.empty()) {
+        HIPX(hipMemcpyAsync(d_tile_ids, tile_ids.data(), tile_ids.size() * 4, hipMemcpyHostToDevice, st));
+        ProfScope ps("rle1_tiles", st, bytes);
+        HIPX(rle1_tiles(in, (uint32_t)tile_ids.size(), d_tile_ids, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab,
+                        ctx->crc_tab + 256, d_rt[nxt], st));
+      }
+      cur = nxt;
     }
-    HIPX(rle1_blocks(nb, d_blk_tile0, d_boff, ctx->crc_tab + 256, d_rtiles, d_tile_out, d_rle_n, d_crc, st));
+    HIPX(rle1_blocks(nb, d_blk_tile0, d_boff, ctx->crc_tab + 256, d_rt[cur], d_tile_rs, d_tile_out, d_rle_n, d_crc,
+                     st));
     uint32_t* h_rle = (uint32_t*)pin;
     HIPX(hipMemcpyAsync(h_rle, d_rle_n, nb * 4, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
@@ -568,23 +608,33 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
     if (over.empty()) break;
     if (iter > 64) return fail(ctx, BZG_EINVAL, "internal: block cutting did not converge");
     HIPX(hipMemcpyAsync(d_cut_ids, over.data(), over.size() * 4, hipMemcpyHostToDevice, st));
-    HIPX(rle1_cut(in, (uint32_t)over.size(), d_cut_ids, d_blk_tile0, d_boff, d_rtiles, d_tile_out, limit, d_cuts, st));
+    HIPX(rle1_cut(in, (uint32_t)over.size(), d_cut_ids, d_blk_tile0, d_boff, d_tile_rs, d_tile_out, limit, d_cuts,
+                  st));
     uint32_t* h_cut = (uint32_t*)pin;
     HIPX(hipMemcpyAsync(h_cut, d_cuts, over.size() * 4, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
     std::vector<uint64_t> nboff{0};
     std::vector<uint32_t> nbreq;
+    org_blk.clear();
+    org_delta.clear();
     size_t oi = 0;
     for (uint32_t b = 0; b < nb; b++) {
+      uint64_t cut = 0;
       if (oi < over.size() && over[oi] == b) {
-        uint64_t cut = h_cut[oi++];
+        cut = h_cut[oi++];
         if (cut == 0 || cut >= boff[b + 1] - boff[b]) return fail(ctx, BZG_EINVAL, "internal: bad block cut");
         nboff.push_back(boff[b] + cut);
         nbreq.push_back(breq[b]);
+        org_blk.push_back(b);
+        org_delta.push_back(0);
       }
       nboff.push_back(boff[b + 1]);
       nbreq.push_back(breq[b]);
+      org_blk.push_back(b);
+      org_delta.push_back(cut);
     }
+    prev_boff.swap(boff);
+    prev_tile0.swap(blk_tile0);
     boff.swap(nboff);
     breq.swap(nbreq);
   }
@@ -655,7 +705,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   HIPX(hipMemcpyAsync(d_rbase, rbase.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
   {
     ProfScope ps("rle1_emit", st, (double)total + N);
-    HIPX(rle1_emit(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, d_rtiles, d_tile_out, d_rbase, d_text, st));
+    HIPX(rle1_emit(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, d_tile_rs, d_tile_out, d_rbase, d_text, st));
   }
   // ---- BWT
   uint32_t *SA, *d_off;

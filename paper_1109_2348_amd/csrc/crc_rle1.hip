@@ -68,15 +68,17 @@ __device__ __forceinline__ void load_run(const uint8_t* s, const TileGeom& g, ui
   for (int i = 0; i < RITEMS; i++) v[i] = i < cnt ? (uint8_t)(w[i >> 2] >> (8 * (i & 3))) : 0;
 }
 
-__global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* tile_blk,
-                                                   const uint32_t* blk_tile0, const uint64_t* blk_off,
-                                                   const uint32_t* __restrict__ crc_tab, const uint32_t* crc_pow,
-                                                   RleTile* tiles) {
+// Pass A.  One workgroup per tile: tile ids[blockIdx.x], or every tile when
+// ids is null.
+__global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* __restrict__ ids,
+                                                   const uint32_t* tile_blk, const uint32_t* blk_tile0,
+                                                   const uint64_t* blk_off, const uint32_t* __restrict__ crc_tab,
+                                                   const uint32_t* crc_pow, RleTile* tiles) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t tab[256];
   tab[threadIdx.x] = crc_tab[threadIdx.x];
-  const uint32_t t = blockIdx.x;
+  const uint32_t t = ids ? ids[blockIdx.x] : blockIdx.x;
   TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
   const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
   uint8_t v[RITEMS];
@@ -134,10 +136,12 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
 }
 
 // One workgroup per block: scan its tiles.  Writes each tile's carried run
-// start (+1) and output offset, the block's RLE1 length and CRC.
+// start (+1, tile_rs) and output offset, the block's RLE1 length and CRC.
+// The tile records are left as pass A wrote them.
 __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, const uint64_t* blk_off,
-                                                    const uint32_t* crc_pow, RleTile* tiles,
-                                                    uint32_t* tile_out, uint32_t* rle_n, uint32_t* crc_out) {
+                                                    const uint32_t* crc_pow, const RleTile* tiles,
+                                                    uint32_t* tile_rs, uint32_t* tile_out, uint32_t* rle_n,
+                                                    uint32_t* crc_out) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
   __shared__ uint32_t sx[NT];
   const uint32_t b = blockIdx.x;
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, c
     uint32_t ex = block_excl_sum<uint32_t, NT>(e, sh, &tot);
     if (t < t1) {
       tile_out[t] = carry_out + ex;
-      tiles[t].last_bnd = rs;  // reused: run start carried into the tile (+1)
+      tile_rs[t] = rs;  // run start carried into the tile (+1)
     }
     if (t < t1) x ^= gf2_mulmod(r.crc, gf2_xpow8((uint64_t)(n - min(lo + RLE_TILE, n)), crc_pow));
     carry_out += tot;
@@ -250,20 +254,28 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
 
 __global__ __launch_bounds__(NT) void k_rle1_emit(const uint8_t* __restrict__ s, const uint32_t* tile_blk,
                                                   const uint32_t* blk_tile0, const uint64_t* blk_off,
-                                                  const RleTile* tiles, const uint32_t* tile_out,
+                                                  const uint32_t* tile_rs, const uint32_t* tile_out,
                                                   const uint64_t* out_base, uint8_t* __restrict__ out) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
   __shared__ uint32_t sx[NT];
   const uint32_t t = blockIdx.x;
   TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
-  rle1_walk<0>(s, g, tiles[t].last_bnd, tile_out[t], out, out_base[g.b], 0, sh, sx, nullptr);
+  rle1_walk<0>(s, g, tile_rs[t], tile_out[t], out, out_base[g.b], 0, sh, sx, nullptr);
+}
+
+// Tile records carried over from the previous plan: dst[t] = src[from[t]]
+// where from[t] is not ~0.
+__global__ __launch_bounds__(NT) void k_tile_copy(uint32_t n, const uint32_t* __restrict__ from,
+                                                  const RleTile* __restrict__ src, RleTile* __restrict__ dst) {
+  const uint32_t t = blockIdx.x * NT + threadIdx.x;
+  if (t < n && from[t] != ~0u) dst[t] = src[from[t]];
 }
 
 // One workgroup per oversized block: the length of the longest input prefix
 // whose RLE1 output fits in `limit` bytes.
 __global__ __launch_bounds__(NT) void k_rle1_cut(const uint8_t* __restrict__ s, const uint32_t* blk_ids,
                                                  const uint32_t* blk_tile0, const uint64_t* blk_off,
-                                                 const RleTile* tiles, const uint32_t* tile_out,
+                                                 const uint32_t* tile_rs, const uint32_t* tile_out,
                                                  uint32_t limit, uint32_t* cut) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
   __shared__ uint32_t sx[NT];
@@ -286,37 +298,44 @@ __global__ __launch_bounds__(NT) void k_rle1_cut(const uint8_t* __restrict__ s, 
   g.n = (uint32_t)(blk_off[b + 1] - g.base);
   g.lo = (t - t0) * RLE_TILE;
   g.hi = min(g.lo + RLE_TILE, g.n);
-  rle1_walk<1>(s, g, tiles[t].last_bnd, tile_out[t], nullptr, 0, limit, sh, sx, &cut[blockIdx.x]);
+  rle1_walk<1>(s, g, tile_rs[t], tile_out[t], nullptr, 0, limit, sh, sx, &cut[blockIdx.x]);
 }
 
-hipError_t rle1_tiles(const uint8_t* s, uint32_t ntiles, const uint32_t* tile_blk, const uint32_t* blk_tile0,
-                      const uint64_t* blk_off, const uint32_t* crc_tab, const uint32_t* crc_pow, void* tiles,
-                      hipStream_t st) {
-  if (ntiles) hipLaunchKernelGGL(k_rle1_tiles, dim3(ntiles), dim3(NT), 0, st, s, tile_blk, blk_tile0, blk_off,
-                                 crc_tab, crc_pow, (RleTile*)tiles);
+hipError_t rle1_tiles(const uint8_t* s, uint32_t nlaunch, const uint32_t* ids, const uint32_t* tile_blk,
+                      const uint32_t* blk_tile0, const uint64_t* blk_off, const uint32_t* crc_tab,
+                      const uint32_t* crc_pow, void* tiles, hipStream_t st) {
+  if (nlaunch) hipLaunchKernelGGL(k_rle1_tiles, dim3(nlaunch), dim3(NT), 0, st, s, ids, tile_blk, blk_tile0, blk_off,
+                                  crc_tab, crc_pow, (RleTile*)tiles);
+  return hipGetLastError();
+}
+
+hipError_t rle1_tile_copy(uint32_t n, const uint32_t* from, const void* src, void* dst, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_tile_copy, dim3((n + NT - 1) / NT), dim3(NT), 0, st, n, from, (const RleTile*)src,
+                            (RleTile*)dst);
   return hipGetLastError();
 }
 
 hipError_t rle1_blocks(uint32_t nb, const uint32_t* blk_tile0, const uint64_t* blk_off, const uint32_t* crc_pow,
-                       void* tiles, uint32_t* tile_out, uint32_t* rle_n, uint32_t* crc, hipStream_t st) {
+                       const void* tiles, uint32_t* tile_rs, uint32_t* tile_out, uint32_t* rle_n, uint32_t* crc,
+                       hipStream_t st) {
   if (nb) hipLaunchKernelGGL(k_rle1_blocks, dim3(nb), dim3(NT), 0, st, blk_tile0, blk_off, crc_pow,
-                             (RleTile*)tiles, tile_out, rle_n, crc);
+                             (const RleTile*)tiles, tile_rs, tile_out, rle_n, crc);
   return hipGetLastError();
 }
 
 hipError_t rle1_emit(const uint8_t* s, uint32_t ntiles, const uint32_t* tile_blk, const uint32_t* blk_tile0,
-                     const uint64_t* blk_off, const void* tiles, const uint32_t* tile_out, const uint64_t* out_base,
-                     uint8_t* out, hipStream_t st) {
-  if (ntiles) hipLaunchKernelGGL(k_rle1_emit, dim3(ntiles), dim3(NT), 0, st, s, tile_blk, blk_tile0, blk_off,
-                                 (const RleTile*)tiles, tile_out, out_base, out);
+                     const uint64_t* blk_off, const uint32_t* tile_rs, const uint32_t* tile_out,
+                     const uint64_t* out_base, uint8_t* out, hipStream_t st) {
+  if (ntiles) hipLaunchKernelGGL(k_rle1_emit, dim3(ntiles), dim3(NT), 0, st, s, tile_blk, blk_tile0, blk_off, tile_rs,
+                                 tile_out, out_base, out);
   return hipGetLastError();
 }
 
 hipError_t rle1_cut(const uint8_t* s, uint32_t ncut, const uint32_t* blk_ids, const uint32_t* blk_tile0,
-                    const uint64_t* blk_off, const void* tiles, const uint32_t* tile_out, uint32_t limit,
+                    const uint64_t* blk_off, const uint32_t* tile_rs, const uint32_t* tile_out, uint32_t limit,
                     uint32_t* cut, hipStream_t st) {
-  if (ncut) hipLaunchKernelGGL(k_rle1_cut, dim3(ncut), dim3(NT), 0, st, s, blk_ids, blk_tile0, blk_off,
-                               (const RleTile*)tiles, tile_out, limit, cut);
+  if (ncut) hipLaunchKernelGGL(k_rle1_cut, dim3(ncut), dim3(NT), 0, st, s, blk_ids, blk_tile0, blk_off, tile_rs,
+                               tile_out, limit, cut);
   return hipGetLastError();
 }
 
