@@ -66,7 +66,7 @@ def _traffic(config, kernel):
         return None
     for line in open(os.path.join(ROOT, path)):
         f = line.split()
-        if len(f) == 5 and f[0] == "traffic" and f[1] == "k_" + kernel:
+        if len(f) >= 5 and f[0] == "traffic" and f[1] == kernel:
             kv = dict(x.split("=", 1) for x in f[2:])
             h = hashlib.sha256()
             for n in (kv["source"], "common.hpp", "internal.hpp"):
@@ -276,7 +276,7 @@ def bench_serving(args):
         S.poisson_run(srv, pool[:4], [0.0] * 4)
         # saturation: every request offered at once
         srv.stats = S.ServerStats()
-        n_sat = min(args.requests, 3 * len(pool))
+        n_sat = args.requests
         S.poisson_run(srv, [pool[i % len(pool)] for i in range(n_sat)], [0.0] * n_sat)
         sat = srv.stats.summary()
         qps_sat = sat["MB_per_s"] / mean_mb
