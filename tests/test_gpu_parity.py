@@ -337,6 +337,35 @@ def test_compress_batch_rejects_bad_args(bz):
         native.compress_batch(x, [0, 5, 10], [0, 2], level=10)
 
 
+def test_compress_batch_many_small_requests(bz):
+    rnd = random.Random(37)
+    reqs = []
+    for i in range(600):
+        k = rnd.choice([0, 0, 1, 2, 3, 4, 5, 17, 64, 255, 256, 1000, 5000])
+        reqs.append(bytes(rnd.randrange(256) for _ in range(k)) if i % 3 else bytes([i & 255]) * k)
+    _check_batch(bz, reqs, 9, 900000, "600 requests of 0..5000 bytes")
+
+
+@pytest.mark.slow
+def test_compress_config4_full(bz):
+    """8192 uneven blocks in one call: the stock decoder recovers the input;
+    sampled blocks, compressed in one launch as separate streams, equal the
+    oracle's streams of those blocks."""
+    from paper_1109_2348_amd import native
+    b = W.config4()
+    _say(f"compress 8192 uneven blocks ({b.data.size} B), level 9")
+    z = bz.compress(_dev(b.data), b.offsets, level=9).cpu().numpy().tobytes()
+    assert bz2.decompress(z) == b.data.tobytes()
+    rnd = random.Random(41)
+    pick = sorted(rnd.sample(range(b.n_blocks), 24))
+    blocks = [b.block(k) for k in pick]
+    data, offs, rq = _batch_inputs(blocks, 900000)
+    _say(f"compress_batch of {len(pick)} sampled blocks vs the oracle")
+    zs = native.compress_batch(_dev(data), offs, rq, level=9)
+    for k, blk, zk in zip(pick, blocks, zs):
+        assert zk.cpu().numpy().tobytes() == cref.compress(blk, [0, blk.size], level=9), f"block {k}"
+
+
 @pytest.mark.slow
 def test_compress_config2_full(bz):
     b = W.config2()
