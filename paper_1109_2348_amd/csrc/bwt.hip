@@ -48,11 +48,12 @@ __device__ __forceinline__ uint32_t lowest_lane(uint64_t m) { return (uint32_t)(
 
 // ------------------------------------------------------------------ init
 
-// q mod n for q < 2n + 3 (positions at most 3 past one wrap; blocks shorter
-// than 4 bytes may wrap more than once).
+// q mod n for q <= n + 2 and n >= 1 (a position at most 3 past the block
+// end): three conditional subtractions cover even one-byte blocks.
 __device__ __forceinline__ uint32_t cyc(uint32_t q, uint32_t n) {
   q = q >= n ? q - n : q;
-  return q >= n ? q % n : q;
+  q = q >= n ? q - n : q;
+  return q >= n ? q - n : q;
 }
 
 // Byte 3-p of the 4-byte key of the rotation at local position pos: the
