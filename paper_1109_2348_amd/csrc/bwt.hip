@@ -17,6 +17,11 @@
 //         group starts where key2 changes; rank = row of its head.  Groups of
 //         one row are done; groups whose block length is <= the next h hold
 //         equal rotations and are done too.  h doubles.
+//  round 0 (h = 4) takes key2 from the text instead: the 4 bytes h
+//         positions on order those rotations exactly as their ranks would,
+//         and they come from the block's L2-resident text.  So the init
+//         naming ranks only the rows already alone in their group, and round
+//         0 ranks the rest.
 //
 // Stable sorts from a descending start order leave equal rotations in
 // descending start order.  Segments of at most SMALL_MAX rows are packed into
@@ -369,12 +374,14 @@ __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs
 
 // Names the groups of sorted large segments: SA rows in place (vin may be
 // SA itself), rank of every row = its group's head row, new segments
-// appended.
+// appended.  With rank_all = 0 only rows alone in their group get a rank:
+// the others are re-sorted next round, which ranks them, and that round
+// compares text rather than ranks (so nothing reads their ranks before).
 __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                  const uint32_t* __restrict__ kin, const uint32_t* vin,
                                                  const uint32_t* __restrict__ agg, const uint32_t* __restrict__ blk_off,
                                                  uint32_t* SA, uint32_t* __restrict__ rank,
-                                                 uint32_t h_next, int key_is_rank, AppendCtx app) {
+                                                 uint32_t h_next, int key_is_rank, int rank_all, AppendCtx app) {
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t s_carry;
@@ -421,10 +428,10 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
       if (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev)) hp = k + 1;
       uint32_t v = vin[k];
       if (vin != SA) SA[k] = v;
-      rank[v] = hp - 1;
       bool end = (k + 1 == segend) ||
                  ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : (i + 1 < RI) ? kin[k + 1] != kk[i]
                                                                                     : knext != kk[i]);
+      if (rank_all || (end && hp == k + 1)) rank[v] = hp - 1;
       if (end) {
         uint32_t len = k + 1 - (hp - 1);
         // closed group: the segment did not split and every partner lies in
@@ -486,11 +493,16 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
   return *s_n;
 }
 
+// key2 of every row of every segment: the rank of the rotation h positions
+// on, relative to the block start; or (text != null, the first round, h = 4)
+// that rotation's first 4 bytes, which order rotations exactly as their
+// ranks after the init sort do.
 __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
                                                const uint32_t* __restrict__ owner, const RoundCounters* cnt,
                                                uint32_t n_small_tiles, const uint32_t* __restrict__ blk_off,
                                                const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
-                                               uint32_t h, uint32_t* __restrict__ key2) {
+                                               const uint8_t* __restrict__ text, uint32_t h,
+                                               uint32_t* __restrict__ key2) {
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t sh[NW + 1];
@@ -504,31 +516,36 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
       SegRec r = segs[mark[sp] - 1];
       uint32_t k = r.start + (p - sp);
       uint32_t o = blk_off[r.blk], nbk = blk_off[r.blk + 1] - o;
-      uint32_t i = SA[k] - o + h;
-      if (i >= nbk) i -= nbk;
-      key2[k] = rank[o + i] - o;
+      const uint32_t i = cyc(SA[k] - o + h, nbk);
+      key2[k] = text ? text_key(text, o, nbk, i) : rank[o + i] - o;
     }
   } else {
     BigTile g = big_tile(jt - n_small_tiles, segs, owner);
     uint32_t o = blk_off[g.r.blk], nbk = blk_off[g.r.blk + 1] - o;
     for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
-      uint32_t i = SA[k] - o + h;
-      if (i >= nbk) i -= nbk;
-      key2[k] = rank[o + i] - o;
+      const uint32_t i = cyc(SA[k] - o + h, nbk);
+      key2[k] = text ? text_key(text, o, nbk, i) : rank[o + i] - o;
     }
   }
 }
 
 // --------------------------------------------------- small segments, LDS
 
+// Sorts packed small segments in LDS, names their groups, ranks their rows
+// and appends the groups that stay unresolved.  Rank rounds sort on
+// (segment position << 21 | key2) in 4 passes; the text round (text_mode,
+// 32-bit keys) sorts on key2 and then the segment position, 6 passes, and
+// leaves equal-rotation groups to the next round.
 __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
                                                    const RoundCounters* cnt, const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
-                                                   uint32_t* __restrict__ rank, uint32_t h_next, AppendCtx app) {
+                                                   uint32_t* __restrict__ rank, uint32_t h_next, int text_mode,
+                                                   AppendCtx app) {
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t skey[SMALL_CAP];
   __shared__ uint32_t sval[SMALL_CAP];
+  __shared__ uint16_t sseg[SMALL_CAP];  // text round: segment position of each key
   __shared__ uint32_t scnt[NW][256];
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
@@ -541,18 +558,21 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
   for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) {
-    uint32_t kv = 0xFFFFFFFFu, vv = 0;
+    uint32_t kv = 0xFFFFFFFFu, vv = 0, sv = 0xFFFFu;
     if (p < n && segp[p] == NO_SEG) {
       kv = 0;
+      sv = 0;
     } else if (p < n) {
       uint32_t sp = segp[p];
       SegRec r = segs[mark[sp] - 1];
       uint32_t k = r.start + (p - sp);
-      kv = (sp << 21) | key2[k];
+      kv = text_mode ? key2[k] : (sp << 21) | key2[k];
+      sv = sp;
       vv = SA[k];
     }
     skey[p] = kv;
     sval[p] = vv;
+    sseg[p] = (uint16_t)sv;
   }
   // clear the head entries of this tile for reuse two rounds later
   const uint32_t lo = jt * SMALL_T;
@@ -562,17 +582,21 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   // stable LSD radix sort of the tile in LDS; wave w owns positions
   // [w*1024, (w+1)*1024), item i of lane l is position w*1024 + i*64 + l
   const uint32_t w = threadIdx.x / BZG_WAVE;
-  constexpr int PI = SMALL_CAP / NT;  // 16
-  for (int shift = 0; shift < 32; shift += 8) {
+  constexpr int PI = SMALL_CAP / NT;  // 8
+  const int npass = text_mode ? 6 : 4;
+  for (int pass = 0; pass < npass; pass++) {
+    const int shift = (pass & 3) * 8;
+    const bool by_seg = pass >= 4;  // text round: the segment position last
     for (int d = threadIdx.x; d < NW * 256; d += NT) (&scnt[0][0])[d] = 0;
     __syncthreads();
-    uint32_t key[PI], val[PI], rk[PI];
+    uint32_t key[PI], val[PI], rk[PI], sg[PI];
 #pragma unroll
     for (int i = 0; i < PI; i++) {
       uint32_t p = w * (PI * BZG_WAVE) + i * BZG_WAVE + lane();
       key[i] = skey[p];
       val[i] = sval[p];
-      uint32_t d = (key[i] >> shift) & 255u;
+      sg[i] = sseg[p];
+      uint32_t d = ((by_seg ? sg[i] : key[i]) >> shift) & 255u;
       uint64_t peers = match_digit8(d, ~0ull);
       uint32_t before = scnt[w][d];
       rk[i] = before + __popcll(peers & lanemask_lt());
@@ -596,10 +620,11 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PI; i++) {
-      uint32_t d = (key[i] >> shift) & 255u;
+      uint32_t d = ((by_seg ? sg[i] : key[i]) >> shift) & 255u;
       uint32_t pos = scnt[w][d] + rk[i];
       skey[pos] = key[i];
       sval[pos] = val[i];
+      sseg[pos] = (uint16_t)sg[i];
     }
     __syncthreads();
   }
@@ -633,7 +658,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
       uint32_t len = p + 1 - (hp - 1);
       uint32_t nbk = blk_off[r.blk + 1] - blk_off[r.blk];
       // closed group (see k_rename_b): equal rotations, final
-      const bool closed = len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - blk_off[r.blk];
+      const bool closed = !text_mode && len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - blk_off[r.blk];
       if (len >= 2 && h_next < nbk && !closed) {
 #pragma unroll
         for (int q = 0; q < PI / 2 + 1; q++)  // register-resident append
@@ -867,8 +892,9 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     }
     {
       ProfScope ps("rename_b", st, 12.0 * init_elems);  // key and row in, rank out
+      // only rows alone in their group are ranked here: round 0 compares text
       hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.SA, w.agg,
-                         w.d_off, w.SA, w.rank, 4u, 0, app);
+                         w.d_off, w.SA, w.rank, 4u, 0, 0, app);
     }
     BZG_TRY(hipGetLastError());
     int cur = 1;
@@ -890,29 +916,33 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       }
       nround++;
       const int nxt = cur ^ 1;
+      // round 0 (h = 4) sorts on the next 4 text bytes instead of ranks
+      const bool text_round = h == 4;
       BZG_TRY(hipMemsetAsync(&w.cnt[nxt], 0, sizeof(RoundCounters), st));
       const uint32_t nsmall = (c.small_total + SMALL_T - 1) / SMALL_T;
       {
         ProfScope ps("gather", st, 12.0 * c.active);  // row, partner rank, key2
         hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.head[cur],
-                           w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank, h, w.key);
+                           w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank,
+                           text_round ? text : nullptr, h, w.key);
       }
       AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[nxt]};
       if (nsmall) {
         ProfScope ps("small_sort", st, 16.0 * c.small_total);  // key2 and row in, row and rank out
         hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
-                           w.d_off, w.key, w.SA, w.rank, 2 * h, app2);
+                           w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? 1 : 0, app2);
       }
       if (c.big_tiles) {
         const double be = c.big_active;
-        BZG_TRY(radix_passes(w, c.big_tiles, w.segs[cur], w.owner[cur], passes, be, &kin, &vin, st));
+        BZG_TRY(radix_passes(w, c.big_tiles, w.segs[cur], w.owner[cur], text_round ? 4 : passes, be, &kin, &vin,
+                             st));
         {
           ProfScope ps("rename_a", st, 4.0 * be);
           hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
         }
         ProfScope ps("rename_b", st, 16.0 * be);
         hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
-                           w.agg, w.d_off, w.SA, w.rank, 2 * h, 1, app2);
+                           w.agg, w.d_off, w.SA, w.rank, 2 * h, text_round ? 0 : 1, 1, app2);
       }
       BZG_TRY(hipGetLastError());
       cur = nxt;
