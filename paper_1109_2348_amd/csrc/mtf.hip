@@ -22,7 +22,10 @@
 
 namespace bzg {
 
-constexpr int MITEMS = MTF_CHUNK / NT;  // rows per thread
+// Chunk length: MTF_CHUNK rows, or MTF_CHUNK_SMALL when a call holds so few
+// chunks that the long per-chunk chains would leave the GPU idle.
+constexpr uint32_t MTF_CHUNK_SMALL = 2048;
+constexpr uint32_t MTF_FEW_CHUNKS = 64;
 
 struct ZSum {
   uint32_t lz, tz, inner, nnz, len, all;
@@ -65,28 +68,36 @@ struct ChunkGeom {
 };
 
 __device__ __forceinline__ ChunkGeom chunk_geom(uint32_t c, const uint32_t* chunk_blk, const uint32_t* blk_chunk0,
-                                                const uint32_t* off) {
+                                                const uint32_t* off, uint32_t ch) {
   ChunkGeom g;
   g.b = chunk_blk[c];
   g.blo = off[g.b];
   g.bhi = off[g.b + 1];
-  g.lo = g.blo + (c - blk_chunk0[g.b]) * MTF_CHUNK;
-  g.hi = min(g.lo + MTF_CHUNK, g.bhi);
+  g.lo = g.blo + (c - blk_chunk0[g.b]) * ch;
+  g.hi = min(g.lo + ch, g.bhi);
   g.last = (c + 1 == blk_chunk0[g.b + 1]);
   return g;
 }
 
-// This thread's MITEMS consecutive rows from r0 (those below hi) as dwords;
+// This thread's MI consecutive rows from r0 (those below hi) as dwords;
 // returns how many are valid.
+template <int MI>
 __device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uint32_t r0, uint32_t hi,
-                                              uint32_t w[MITEMS / 4]) {
-  static_assert(MITEMS % 16 == 0, "whole 16-byte spans per thread");
-  const uint32_t cnt = r0 < hi ? min((uint32_t)MITEMS, hi - r0) : 0u;
+                                              uint32_t w[MI / 4]) {
+  static_assert(MI % 8 == 0, "whole 8-byte spans per thread");
+  const uint32_t cnt = r0 < hi ? min((uint32_t)MI, hi - r0) : 0u;
 #pragma unroll
-  for (int j = 0; j < MITEMS / 4; j++) w[j] = 0;
+  for (int j = 0; j < MI / 4; j++) w[j] = 0;
 #pragma unroll
-  for (uint32_t h = 0; h < (uint32_t)MITEMS; h += 16)
-    if (cnt > h) load16(L + r0 + h, min(cnt - h, 16u), w + h / 4);
+  for (uint32_t h = 0; h < (uint32_t)MI; h += 16) {
+    if (cnt > h) {
+      uint32_t t[4];
+      load16(L + r0 + h, min(cnt - h, (uint32_t)min(MI - (int)h, 16)), t);
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if ((int)(h / 4) + j < MI / 4) w[h / 4 + j] = t[j];
+    }
+  }
   return cnt;
 }
 
@@ -94,15 +105,17 @@ __device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uin
 // zero-run summary of its rows -- without the block's first row, whose MTF
 // index depends on the whole block's in-use set and is added by k_mtf_scan --
 // and the block's in-use bitmap (OR-ed in; the caller zeroes it).
+template <uint32_t CH>
 __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
                                                   const uint32_t* blk_chunk0, const uint32_t* off,
                                                   uint32_t* __restrict__ inuse, uint8_t* __restrict__ chunk_D,
                                                   uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
+  constexpr int MITEMS = CH / NT;  // rows per thread
   __shared__ uint32_t last[256];
   __shared__ ZSum wsum[NT];
   __shared__ uint32_t s_nd;
   const uint32_t c = blockIdx.x;
-  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
+  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off, CH);
   last[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_nd = 0;
   __syncthreads();
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   uint32_t prev = 0x100u;
   if (r0 < g.hi && r0 > g.blo) prev = L[r0 - 1];
   uint32_t w[MITEMS / 4];
-  load_rows(L, r0, g.hi, w);
+  load_rows<MITEMS>(L, r0, g.hi, w);
   ZSum s = {0, 0, 0, 0, 0, 1};
 #pragma unroll
   for (int i = 0; i < MITEMS; i++) {
@@ -534,12 +547,13 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
                                                        const uint32_t* __restrict__ chunk_carry,
                                                        const uint32_t* __restrict__ chunk_out,
                                                        const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
-                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err) {
+                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err,
+                                                       uint32_t ch) {
   __shared__ uint32_t fq[MAXA];
   __shared__ uint32_t posof[256], nstk[256], inb[256];
   const uint32_t c = blockIdx.x;
   const uint32_t l = lane();
-  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off);
+  ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off, ch);
   uint32_t nu = 0;
   for (int j = 0; j < 8; j++) nu += __popc(inuse[g.b * 8 + j]);
   for (uint32_t i = l; i < MAXA; i += 64) fq[i] = 0;
@@ -559,15 +573,26 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
 
 // ------------------------------------------------------------- host side
 
+static uint32_t count_chunks(const std::vector<uint32_t>& h_off, uint32_t ch) {
+  size_t nc = 0;
+  for (size_t b = 0; b + 1 < h_off.size(); b++) nc += (h_off[b + 1] - h_off[b] + ch - 1) / ch;
+  return (uint32_t)nc;
+}
+
+static uint32_t chunk_size(const std::vector<uint32_t>& h_off) {
+  return count_chunks(h_off, MTF_CHUNK) < MTF_FEW_CHUNKS ? MTF_CHUNK_SMALL : MTF_CHUNK;
+}
+
 hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<uint32_t>& h_off, void* ws,
                    size_t ws_bytes, uint16_t* syms, const uint64_t* d_sym_base, uint32_t* nsyms, uint32_t* inuse,
                    uint32_t* freq, uint32_t* err, hipStream_t st, std::string& emsg) {
   const uint32_t nb = (uint32_t)h_off.size() - 1;
+  const uint32_t ch = chunk_size(h_off);
   std::vector<uint32_t> chunk_blk, blk_chunk0(nb + 1);
   for (uint32_t b = 0; b < nb; b++) {
     blk_chunk0[b] = (uint32_t)chunk_blk.size();
     uint32_t n = h_off[b + 1] - h_off[b];
-    uint32_t nc = (n + MTF_CHUNK - 1) / MTF_CHUNK;
+    uint32_t nc = (n + ch - 1) / ch;
     for (uint32_t q = 0; q < nc; q++) chunk_blk.push_back(b);
   }
   blk_chunk0[nb] = (uint32_t)chunk_blk.size();
@@ -597,8 +622,12 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   const double n = h_off[nb];
   {
     ProfScope ps("mtf_state", st, n + 256.0 * nc);
-    hipLaunchKernelGGL(k_mtf_state, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse, d_D,
-                       d_nD, d_sum);
+    if (ch == MTF_CHUNK)
+      hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK>, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off,
+                         inuse, d_D, d_nD, d_sum);
+    else
+      hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK_SMALL>, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0,
+                         d_off, inuse, d_D, d_nD, d_sum);
   }
   {
     ProfScope ps("mtf_scan", st, 512.0 * nc);
@@ -608,15 +637,14 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   {
     ProfScope ps("mtf_emit", st, 3.0 * n);  // read L, write at most one 2-byte symbol per row
     hipLaunchKernelGGL(k_mtf_emit, dim3(nc), dim3(BZG_WAVE), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse,
-                       d_list, d_carry, d_out, d_sym_base, syms, freq, err);
+                       d_list, d_carry, d_out, d_sym_base, syms, freq, err, ch);
   }
   return hipGetLastError();
 }
 
 size_t mtf_workspace_bytes(const std::vector<uint32_t>& h_off) {
   const uint32_t nb = (uint32_t)h_off.size() - 1;
-  size_t nc = 0;
-  for (uint32_t b = 0; b < nb; b++) nc += (h_off[b + 1] - h_off[b] + MTF_CHUNK - 1) / MTF_CHUNK;
+  const size_t nc = count_chunks(h_off, chunk_size(h_off));
   return 8 * 256 + (nc + 1) * (4 + 256 + 4 + sizeof(ZSum) + 256 + 4 + 4) + (nb + 1) * 4 + 4096;
 }
 
