@@ -296,9 +296,15 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
     const uint32_t g = gs + threadIdx.x;
     if (g < ge) {
       const uint32_t lo = g * GROUP - s0, hi = min(g * GROUP + GROUP, ns) - s0;
+      const bool full = hi - lo == (uint32_t)GROUP;  // all but a block's last group
       if (mode == 0) {
         uint64_t acc = 0;
-        for (uint32_t i = lo; i < hi; i++) acc += sc[st[i]];
+        if (full) {  // unrolled: the 50 lookups are independent
+#pragma unroll
+          for (uint32_t i = 0; i < (uint32_t)GROUP; i++) acc += sc[st[lo + i]];
+        } else {
+          for (uint32_t i = lo; i < hi; i++) acc += sc[st[i]];
+        }
         uint32_t best = 0, bc = (uint32_t)(acc & 1023u);
         for (uint32_t t = 1; t < G; t++) {
           uint32_t c = (uint32_t)((acc >> (10 * t)) & 1023u);
@@ -308,11 +314,21 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
           }
         }
         sel[sb + g] = (uint8_t)best;
-        for (uint32_t i = lo; i < hi; i++) atomicAdd(&stf[best][st[i]], 1u);
+        if (full) {
+#pragma unroll
+          for (uint32_t i = 0; i < (uint32_t)GROUP; i++) atomicAdd(&stf[best][st[lo + i]], 1u);
+        } else {
+          for (uint32_t i = lo; i < hi; i++) atomicAdd(&stf[best][st[i]], 1u);
+        }
       } else {
         const uint32_t t = sel[sb + g];
         uint32_t acc = 0;
-        for (uint32_t i = lo; i < hi; i++) acc += slen[t][st[i]];
+        if (full) {
+#pragma unroll
+          for (uint32_t i = 0; i < (uint32_t)GROUP; i++) acc += slen[t][st[lo + i]];
+        } else {
+          for (uint32_t i = lo; i < hi; i++) acc += slen[t][st[i]];
+        }
         gbits[sb + g] = acc;
         bits += acc;
       }
