@@ -461,13 +461,22 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
   if (threadIdx.x == 0) *s_n = 0;
   __syncthreads();
   const uint32_t lo = t * SMALL_T;
-  for (uint32_t i = threadIdx.x; i < SMALL_T; i += NT) {
-    uint32_t o = lo + i;
-    if (o < small_total) {
-      uint32_t hd = head[o];
-      if (hd) {
-        mark[i] = hd;
-        atomicMax(s_n, i + segs[hd - 1].len);
+  {
+    constexpr int PH = SMALL_T / NT;
+    uint32_t hd[PH], ln[PH];
+#pragma unroll
+    for (int j = 0; j < PH; j++) {
+      const uint32_t o = lo + j * NT + threadIdx.x;
+      hd[j] = o < small_total ? head[o] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < PH; j++) ln[j] = hd[j] ? segs[hd[j] - 1].len : 0u;
+#pragma unroll
+    for (int j = 0; j < PH; j++) {
+      const uint32_t i = j * NT + threadIdx.x;
+      if (hd[j]) {
+        mark[i] = hd[j];
+        atomicMax(s_n, i + ln[j]);
       }
     }
   }
@@ -510,14 +519,34 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   if (jt < n_small_tiles) {
     uint32_t n = small_tile_map(jt, head, segs, cnt->small_total, mark, segp, sh, &s_n);
-    for (uint32_t p = threadIdx.x; p < n; p += NT) {
-      uint32_t sp = segp[p];
-      if (sp == NO_SEG) continue;
-      SegRec r = segs[mark[sp] - 1];
-      uint32_t k = r.start + (p - sp);
-      uint32_t o = blk_off[r.blk], nbk = blk_off[r.blk + 1] - o;
-      const uint32_t i = cyc(SA[k] - o + h, nbk);
-      key2[k] = text ? text_key(text, o, nbk, i) : rank[o + i] - o;
+    // segment records, then block bounds and rows, then the gathers: each
+    // stage's loads are issued together
+    constexpr int PL = SMALL_CAP / NT;
+    SegRec rr[PL];
+    uint32_t sa[PL], bo[PL], bn[PL];
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      rr[j] = SegRec{0, 0, 0, 0};
+      if (p < n && segp[p] != NO_SEG) rr[j] = segs[mark[segp[p]] - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      if (rr[j].len) {
+        sa[j] = SA[rr[j].start + (p - segp[p])];
+        bo[j] = blk_off[rr[j].blk];
+        bn[j] = blk_off[rr[j].blk + 1] - bo[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      if (rr[j].len) {
+        const uint32_t k = rr[j].start + (p - segp[p]);
+        const uint32_t i = cyc(sa[j] - bo[j] + h, bn[j]);
+        key2[k] = text ? text_key(text, bo[j], bn[j], i) : rank[bo[j] + i] - bo[j];
+      }
     }
   } else {
     BigTile g = big_tile(jt - n_small_tiles, segs, owner);
@@ -557,22 +586,37 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   // load (segment start << 21 | key2, SA value).  Positions before the
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
-  for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) {
-    uint32_t kv = 0xFFFFFFFFu, vv = 0, sv = 0xFFFFu;
-    if (p < n && segp[p] == NO_SEG) {
-      kv = 0;
-      sv = 0;
-    } else if (p < n) {
-      uint32_t sp = segp[p];
-      SegRec r = segs[mark[sp] - 1];
-      uint32_t k = r.start + (p - sp);
-      kv = text_mode ? key2[k] : (sp << 21) | key2[k];
-      sv = sp;
-      vv = SA[k];
+  {
+    // all segment records first, then the rows' key2 and SA (independent
+    // loads, issued together)
+    constexpr int PL = SMALL_CAP / NT;
+    uint32_t kk[PL];
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      kk[j] = 0xFFFFFFFFu;
+      if (p < n) {
+        const uint32_t sp = segp[p];
+        if (sp != NO_SEG) kk[j] = segs[mark[sp] - 1].start + (p - sp);
+      }
     }
-    skey[p] = kv;
-    sval[p] = vv;
-    sseg[p] = (uint16_t)sv;
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      uint32_t kv = 0xFFFFFFFFu, vv = 0, sv = 0xFFFFu;
+      if (kk[j] != 0xFFFFFFFFu) {
+        const uint32_t sp = segp[p];
+        kv = text_mode ? key2[kk[j]] : (sp << 21) | key2[kk[j]];
+        sv = sp;
+        vv = SA[kk[j]];
+      } else if (p < n) {  // before the tile's first segment
+        kv = 0;
+        sv = 0;
+      }
+      skey[p] = kv;
+      sval[p] = vv;
+      sseg[p] = (uint16_t)sv;
+    }
   }
   // clear the head entries of this tile for reuse two rounds later
   const uint32_t lo = jt * SMALL_T;
@@ -641,12 +685,21 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
   uint32_t gs[PI / 2 + 1], gl[PI / 2 + 1], gb[PI / 2 + 1];
   int m = 0;
+  // the segment records of this thread's positions, loaded together
+  SegRec rr[PI];
+#pragma unroll
+  for (int i = 0; i < PI; i++) {
+    const uint32_t p = p0 + i;
+    rr[i] = SegRec{0, 0, 0, 0};
+    if (p < n && segp[p] != NO_SEG) rr[i] = segs[mark[segp[p]] - 1];
+  }
+#pragma unroll
   for (int i = 0; i < PI; i++) {
     uint32_t p = p0 + i;
     if (p >= n) break;
     uint32_t sp = segp[p];
     if (sp == NO_SEG) continue;
-    SegRec r = segs[mark[sp] - 1];
+    const SegRec r = rr[i];
     if (p == sp || skey[p] != skey[p - 1]) hp = p + 1;
     uint32_t k = r.start + (p - sp);
     uint32_t headk = r.start + (hp - 1 - sp);
