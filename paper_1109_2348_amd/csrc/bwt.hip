@@ -400,19 +400,33 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   const uint32_t nblk = blk_off[g.r.blk + 1] - bo;
   const bool keep_blk = h_next < nblk;
   const uint32_t segend = g.r.start + g.r.len;
+  // the tile's keys (with the neighbours on both sides, where they are in
+  // the segment) and rows, loaded coalesced into LDS and read blocked
+  __shared__ uint32_t tk[RADIX_TILE + 2], tv[RADIX_TILE];
+  const uint32_t tn = g.hi - g.lo;
+  for (uint32_t i = threadIdx.x; i < tn; i += NT) {
+    tk[i + 1] = kin[g.lo + i];
+    tv[i] = vin[g.lo + i];
+  }
+  if (threadIdx.x == 0) {
+    tk[0] = g.lo > g.r.start ? kin[g.lo - 1] : 0u;
+    tk[tn + 1] = g.hi < segend ? kin[g.hi] : 0u;
+  }
+  __syncthreads();
   const uint32_t k0 = g.lo + threadIdx.x * RI;  // blocked: RI consecutive rows per thread
+  const uint32_t i0 = threadIdx.x * RI;         // its first position in tk (minus the halo)
   uint32_t kk[RI];
   uint32_t lastb = 0;
   // key of the row before this thread's first row, and after its last
-  const uint32_t kprev = (k0 < g.hi && k0 > g.r.start) ? kin[k0 - 1] : 0u;
+  const uint32_t kprev = (k0 < g.hi && k0 > g.r.start) ? tk[i0] : 0u;
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     uint32_t k = k0 + i;
-    kk[i] = k < g.hi ? kin[k] : 0u;
+    kk[i] = k < g.hi ? tk[i0 + i + 1] : 0u;
     if (k < g.hi && (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev))) lastb = k + 1;
   }
   const uint32_t klast = k0 + RI - 1;
-  const uint32_t knext = (klast < g.hi && klast + 1 < segend) ? kin[klast + 1] : 0u;
+  const uint32_t knext = (klast < g.hi && klast + 1 < segend) ? tk[i0 + RI + 1] : 0u;
   __syncthreads();
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
@@ -426,10 +440,10 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
     uint32_t k = k0 + i;
     if (k < g.hi) {
       if (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev)) hp = k + 1;
-      uint32_t v = vin[k];
+      uint32_t v = tv[i0 + i];
       if (vin != SA) SA[k] = v;
       bool end = (k + 1 == segend) ||
-                 ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : (i + 1 < RI) ? kin[k + 1] != kk[i]
+                 ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : (i + 1 < RI) ? tk[i0 + i + 2] != kk[i]
                                                                                     : knext != kk[i]);
       if (rank_all || (end && hp == k + 1)) rank[v] = hp - 1;
       if (end) {
@@ -747,9 +761,11 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
   uint32_t p[OUT_ROWS];
 #pragma unroll
   for (uint32_t i = 0; i < OUT_ROWS; i++) p[i] = i < cnt ? SA[k0 + i] : 0u;
-  uint32_t w[OUT_ROWS / 4] = {0, 0, 0, 0};
+  // text index of every row's last-column byte first, then the gathers
+  uint32_t src[OUT_ROWS];
 #pragma unroll
   for (uint32_t i = 0; i < OUT_ROWS; i++) {
+    src[i] = 0;
     if (i < cnt) {
       const uint32_t k = k0 + i;
       while (k >= e) {  // next block (empty blocks do not occur)
@@ -758,11 +774,15 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
         e = off[b + 1];
       }
       const uint32_t q = p[i];
-      w[i >> 2] |= (uint32_t)text[q == o ? e - 1 : q - 1] << (8 * (i & 3));
+      src[i] = q == o ? e - 1 : q - 1;
       if (q == o) primary[b] = k - o;
       if (sa_local) sa_local[k] = q - o;
     }
   }
+  uint32_t w[OUT_ROWS / 4] = {0, 0, 0, 0};
+#pragma unroll
+  for (uint32_t i = 0; i < OUT_ROWS; i++)
+    if (i < cnt) w[i >> 2] |= (uint32_t)text[src[i]] << (8 * (i & 3));
   if (cnt == OUT_ROWS && ((uintptr_t)(L + k0) & 15u) == 0) {
     *(uint4*)(L + k0) = make_uint4(w[0], w[1], w[2], w[3]);
   } else {
