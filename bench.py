@@ -81,7 +81,10 @@ def _roofline(kern, steps, step_ms_total, config=None):
     time (HIP events on the launch stream)."""
     if not kern:
         return None
-    name, rec = max(kern.items(), key=lambda kv: kv[1]["ms"])
+    # the dominant kernel among those that move array bytes (the Huffman tree
+    # build and the tiny scans record none)
+    moving = {k: v for k, v in kern.items() if v["bytes"] > 0} or kern
+    name, rec = max(moving.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = rec["ms"] / max(rec["launches"], 1)
     bytes_per_launch = rec["bytes"] / max(rec["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
