@@ -467,12 +467,16 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
 constexpr uint16_t NO_SEG = 0xFFFFu;
 
 // Loads a small tile's segment map: mark[p] = segment index + 1 at each
-// segment's first position, segp[p] = first position of p's segment.
+// segment's first position, segp[p] = first position of p's segment;
+// *s_maxlen gets the longest segment.
 __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head, const SegRec* __restrict__ segs,
                                    uint32_t small_total, uint32_t* mark, uint16_t* segp, uint32_t* sh,
-                                   uint32_t* s_n) {
+                                   uint32_t* s_n, uint32_t* s_maxlen) {
   for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) mark[p] = 0;
-  if (threadIdx.x == 0) *s_n = 0;
+  if (threadIdx.x == 0) {
+    *s_n = 0;
+    *s_maxlen = 0;
+  }
   __syncthreads();
   const uint32_t lo = t * SMALL_T;
   {
@@ -491,6 +495,7 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
       if (hd[j]) {
         mark[i] = hd[j];
         atomicMax(s_n, i + ln[j]);
+        atomicMax(s_maxlen, ln[j]);
       }
     }
   }
@@ -529,10 +534,10 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t sh[NW + 1];
-  __shared__ uint32_t s_n;
+  __shared__ uint32_t s_n, s_maxlen;
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   if (jt < n_small_tiles) {
-    uint32_t n = small_tile_map(jt, head, segs, cnt->small_total, mark, segp, sh, &s_n);
+    uint32_t n = small_tile_map(jt, head, segs, cnt->small_total, mark, segp, sh, &s_n, &s_maxlen);
     // segment records, then block bounds and rows, then the gathers: each
     // stage's loads are issued together
     constexpr int PL = SMALL_CAP / NT;
@@ -579,6 +584,10 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // (segment position << 21 | key2) in 4 passes; the text round (text_mode,
 // 32-bit keys) sorts on key2 and then the segment position, 6 passes, and
 // leaves equal-rotation groups to the next round.
+// Segments of at most this many rows are ordered by counting instead of the
+// tile's radix passes.
+constexpr uint32_t COUNT_SORT_MAX = 32;
+
 __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
                                                    const RoundCounters* cnt, const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
@@ -592,11 +601,11 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   __shared__ uint32_t scnt[NW][256];
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
-  __shared__ uint32_t s_n;
+  __shared__ uint32_t s_n, s_maxlen;
   __shared__ uint32_t wg_base[4];
   const uint32_t small_total = cnt->small_total;
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n);
+  const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n, &s_maxlen);
   // load (segment start << 21 | key2, SA value).  Positions before the
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
@@ -641,7 +650,39 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   // [w*1024, (w+1)*1024), item i of lane l is position w*1024 + i*64 + l
   const uint32_t w = threadIdx.x / BZG_WAVE;
   constexpr int PI = SMALL_CAP / NT;  // 8
-  const int npass = text_mode ? 6 : 4;
+  // Tiles whose segments are all short are ordered by counting, for every
+  // row, the rows of its segment that precede it (smaller key, or equal key
+  // further up); keys compare equal inside a segment exactly when key2 does.
+  const bool counting = s_maxlen <= COUNT_SORT_MAX;
+  if (counting) {
+    uint32_t dst[PI], kv[PI], vv[PI];
+#pragma unroll
+    for (int j = 0; j < PI; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      dst[j] = 0xFFFFFFFFu;
+      if (p < n && segp[p] != NO_SEG) {
+        const uint32_t sp = segp[p];
+        const uint32_t me = skey[p];
+        uint32_t r = 0;
+        for (uint32_t q = sp; q < n && (q == sp || mark[q] == 0); q++) {
+          const uint32_t o = skey[q];
+          r += (o < me || (o == me && q < p)) ? 1u : 0u;
+        }
+        dst[j] = sp + r;
+        kv[j] = me;
+        vv[j] = sval[p];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PI; j++)
+      if (dst[j] != 0xFFFFFFFFu) {
+        skey[dst[j]] = kv[j];
+        sval[dst[j]] = vv[j];
+      }
+    __syncthreads();
+  }
+  const int npass = counting ? 0 : text_mode ? 6 : 4;
   for (int pass = 0; pass < npass; pass++) {
     const int shift = (pass & 3) * 8;
     const bool by_seg = pass >= 4;  // text round: the segment position last
