@@ -62,6 +62,23 @@ __device__ __forceinline__ ZSum zcombine(const ZSum& a, const ZSum& b) {
   return r;
 }
 
+// zcombine over the wave in lane order; lane 0 gets the result.
+__device__ __forceinline__ ZSum zreduce_wave(ZSum v) {
+  const uint32_t l = lane();
+#pragma unroll
+  for (int d = 1; d < BZG_WAVE; d <<= 1) {
+    ZSum o;
+    o.lz = __shfl_down(v.lz, d, BZG_WAVE);
+    o.tz = __shfl_down(v.tz, d, BZG_WAVE);
+    o.inner = __shfl_down(v.inner, d, BZG_WAVE);
+    o.nnz = __shfl_down(v.nnz, d, BZG_WAVE);
+    o.len = __shfl_down(v.len, d, BZG_WAVE);
+    o.all = __shfl_down(v.all, d, BZG_WAVE);
+    if ((l & (2 * d - 1)) == 0 && l + d < BZG_WAVE) v = zcombine(v, o);
+  }
+  return v;
+}
+
 struct ChunkGeom {
   uint32_t b, lo, hi, blo, bhi;  // block, chunk rows [lo,hi), block rows [blo,bhi)
   bool last;
@@ -112,7 +129,7 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
                                                   uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
   constexpr int MITEMS = CH / NT;  // rows per thread
   __shared__ uint32_t last[256];
-  __shared__ ZSum wsum[NT];
+  __shared__ ZSum wsum[NT / BZG_WAVE];
   __shared__ uint32_t s_nd;
   const uint32_t c = blockIdx.x;
   ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off, CH);
@@ -159,7 +176,6 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
       }
     }
   }
-  wsum[threadIdx.x] = s;
   __syncthreads();
   // D_X: present bytes by last occurrence, latest first
   {
@@ -178,9 +194,14 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
       atomicAdd(&s_nd, 1u);
     }
   }
+  {
+    const ZSum t = zreduce_wave(s);  // this wave's rows, in order
+    if (lane() == 0) wsum[threadIdx.x / BZG_WAVE] = t;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     ZSum t = wsum[0];
-    for (int i = 1; i < NT; i++) t = zcombine(t, wsum[i]);
+    for (int i = 1; i < NT / BZG_WAVE; i++) t = zcombine(t, wsum[i]);
     chunk_sum[c] = t;
   }
   __syncthreads();
