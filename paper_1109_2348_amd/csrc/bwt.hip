@@ -387,14 +387,17 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   __shared__ uint32_t s_carry;
   __shared__ uint32_t wg_base[4];
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
-  if (threadIdx.x == 0) {
-    uint32_t c = 0;
+  {
+    // the group head carried in: the last head in the segment's earlier
+    // tiles, i.e. the largest of their per-tile last heads (heads grow with
+    // the row)
     const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
-    for (uint32_t j = jt; j > jt - g.t; j--) {
-      c = agg[j - 1];
-      if (c) break;
-    }
-    s_carry = c;
+    uint32_t c = 0;
+    for (uint32_t q = threadIdx.x; q < g.t; q += NT) c = max(c, agg[jt - g.t + q]);
+    c = wave_max(c);
+    if (lane() == 0) sx[threadIdx.x / BZG_WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = max(max(sx[0], sx[1]), max(sx[2], sx[3]));
   }
   const uint32_t bo = blk_off[g.r.blk];
   const uint32_t nblk = blk_off[g.r.blk + 1] - bo;
