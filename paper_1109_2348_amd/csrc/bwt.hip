@@ -573,9 +573,20 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   } else {
     BigTile g = big_tile(jt - n_small_tiles, segs, owner);
     uint32_t o = blk_off[g.r.blk], nbk = blk_off[g.r.blk + 1] - o;
-    for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
-      const uint32_t i = cyc(SA[k] - o + h, nbk);
-      key2[k] = text ? text_key(text, o, nbk, i) : rank[o + i] - o;
+    // all rows of the tile first, then the gathers (independent loads)
+    uint32_t sa[RI];
+#pragma unroll
+    for (int q = 0; q < RI; q++) {
+      const uint32_t k = g.lo + q * NT + threadIdx.x;
+      sa[q] = k < g.hi ? SA[k] : o;
+    }
+#pragma unroll
+    for (int q = 0; q < RI; q++) {
+      const uint32_t k = g.lo + q * NT + threadIdx.x;
+      if (k < g.hi) {
+        const uint32_t i = cyc(sa[q] - o + h, nbk);
+        key2[k] = text ? text_key(text, o, nbk, i) : rank[o + i] - o;
+      }
     }
   }
 }
