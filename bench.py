@@ -96,7 +96,8 @@ def _roofline(kern, steps, step_ms_total, config=None):
 
 
 def _kernels(kern, steps):
-    return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches": v["launches"] // steps}
+    return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches": v["launches"] // steps,
+                "algorithmic_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
             for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
 
 

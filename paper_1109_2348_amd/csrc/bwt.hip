@@ -9,9 +9,9 @@
 //
 //  init   rows start in descending start order; stable LSD radix per
 //         block on the first 4 cyclic bytes (big-endian); name groups.  The
-//         passes move rows only: each pass reads its digit byte from the
-//         block's text (which stays in L2) at the row's position, so no key
-//         array is written or read, and the last pass leaves the rows in SA.
+//         first pass builds the (key, row) pairs from a sequential read of
+//         the block's text; the other three move them as plain pairs, so no
+//         pass gathers at random.
 //  round  for every unresolved group (a "segment"), key2 = rank of the
 //         rotation h positions on; stable sort of the segment by key2; a new
 //         group starts where key2 changes; rank = row of its head.  Groups of
@@ -61,13 +61,6 @@ __device__ __forceinline__ uint32_t cyc(uint32_t q, uint32_t n) {
   return q >= n ? q - n : q;
 }
 
-// Byte 3-p of the 4-byte key of the rotation at local position pos: the
-// digit of LSD pass p.
-__device__ __forceinline__ uint32_t text_digit(const uint8_t* __restrict__ text, uint32_t o, uint32_t n, uint32_t pos,
-                                               int p) {
-  return text[o + cyc(pos + 3u - (uint32_t)p, n)];
-}
-
 // The first 4 bytes of the rotation at local position pos, big-endian.  When
 // they do not wrap around the block end, two aligned dword loads, each
 // holding at least one of the 4 bytes (so neither leaves the allocation's
@@ -87,17 +80,6 @@ __device__ __forceinline__ uint32_t text_key(const uint8_t* __restrict__ text, u
   return v;
 }
 
-// Where the init sort reads its digits: the batch text and block offsets,
-// and the digit bytes of the current pass (din, in row order) and the next
-// (dout), written by the previous scatter so that histograms read a plain
-// byte stream and each pass gathers at most one byte per row.
-struct TextSrc {
-  const uint8_t* text;
-  const uint32_t* blk_off;
-  const uint8_t* din;
-  uint8_t* dout;
-};
-
 // -------------------------------------------------- segment radix passes
 
 struct BigTile {
@@ -115,34 +97,27 @@ __device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, cons
   return g;
 }
 
-// Per-tile digit counts of one LSD pass.  Keyed: digit = (kin >> shift) & 255.
-// TEXT (init sort): pass 0 reads byte 3 of each row's key from the text (rows
-// are in descending start order, so this is a sequential read); later passes
-// read the digit bytes the previous scatter wrote (ts.din).
+// Per-tile digit counts of one LSD pass: digit = (kin >> shift) & 255.
+// TEXT (the init sort's first pass, shift 0): the digit is byte 3 of each
+// row's first 4 bytes, read from the text (rows are in descending start
+// order, so the read is sequential).  Init segments are whole blocks.
 template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                    const uint32_t* __restrict__ kin, int shift,
-                                                   uint32_t* __restrict__ hist, TextSrc ts, int pass) {
+                                                   uint32_t* __restrict__ hist, const uint8_t* __restrict__ text) {
   __shared__ uint32_t cnt[NW][256];
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
-  uint32_t o = 0, n = 0;
-  if (TEXT) {
-    o = ts.blk_off[g.r.blk];
-    n = ts.blk_off[g.r.blk + 1] - o;
-  }
+  const uint32_t o = TEXT ? g.r.start : 0u, n = TEXT ? g.r.len : 0u;
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
   uint32_t dg[RI];
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     const uint32_t k = wbase + i * BZG_WAVE + lane();
     dg[i] = 0;
-    if (k < g.hi) {
-      if (TEXT) dg[i] = pass == 0 ? ts.text[o + cyc(n - 1u - (k - o) + 3u, n)] : ts.din[k];
-      else dg[i] = (kin[k] >> shift) & 255u;
-    }
+    if (k < g.hi) dg[i] = TEXT ? text[o + cyc(n - 1u - (k - o) + 3u, n)] : (kin[k] >> shift) & 255u;
   }
 #pragma unroll
   for (int i = 0; i < RI; i++) {
@@ -163,64 +138,42 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
-// One stable LSD pass.  Keyed: (key, value) pairs move.  TEXT (init sort):
-// rows move with their next pass's digit byte (ts.dout); pass 0 takes rows
-// from the row index (descending start order) and both its digits from a
-// sequential text read, passes 1 and 2 gather the next digit from the text
-// at the row's position, and the last pass (3, the most significant byte)
-// gathers the row's full key instead and writes it to kout for the naming
-// that follows.
+// One stable LSD pass: (key, row) pairs move.  TEXT (the init sort's first
+// pass, shift 0): rows come from the row index, in descending start order,
+// and each key is its row's first 4 bytes (big-endian), read sequentially
+// from the text.
 template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
                                                       const uint32_t* __restrict__ owner,
                                                       const uint32_t* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int shift,
-                                                      const uint32_t* __restrict__ hscan, TextSrc ts, int pass) {
+                                                      const uint32_t* __restrict__ hscan,
+                                                      const uint8_t* __restrict__ text) {
   __shared__ uint32_t cnt[NW][256];
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
-  uint32_t o = 0, n = 0;
-  if (TEXT) {
-    o = ts.blk_off[g.r.blk];
-    n = ts.blk_off[g.r.blk + 1] - o;
-  }
+  const uint32_t o = TEXT ? g.r.start : 0u, n = TEXT ? g.r.len : 0u;
+  // this tile's output base for digit threadIdx.x, loaded before the rows
+  const size_t col0 = (size_t)g.r.base * 256;
+  const uint32_t hs_d = hscan[col0 + (size_t)threadIdx.x * g.nt + g.t], hs_0 = hscan[col0];
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
-  const bool last_text = TEXT && pass == 3;
-  // key[]: keyed mode the key; TEXT passes 0..2 digit | next digit << 8;
-  // TEXT pass 3 the full key (its digit is the top byte)
   uint32_t key[RI], val[RI], rk[RI];
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     const uint32_t k = wbase + i * BZG_WAVE + lane();
-    const bool ok = k < g.hi;
     key[i] = 0;
     val[i] = 0;
-    if (ok) {
+    if (k < g.hi) {
       if (TEXT) {
-        if (pass == 0) {
-          const uint32_t pos = n - 1u - (k - o);
-          val[i] = o + pos;
-          key[i] = ts.text[o + cyc(pos + 3u, n)] | ((uint32_t)ts.text[o + cyc(pos + 2u, n)] << 8);
-        } else {
-          val[i] = vin[k];
-          key[i] = ts.din[k];
-        }
+        const uint32_t pos = n - 1u - (k - o);
+        val[i] = o + pos;
+        key[i] = text_key(text, o, n, pos);
       } else {
         key[i] = kin[k];
         val[i] = vin[k];
-      }
-    }
-  }
-  if (TEXT && pass > 0) {  // the one gather per row
-#pragma unroll
-    for (int i = 0; i < RI; i++) {
-      const uint32_t k = wbase + i * BZG_WAVE + lane();
-      if (k < g.hi) {
-        const uint32_t pos = val[i] - o;
-        key[i] = last_text ? text_key(ts.text, o, n, pos) : key[i] | (text_digit(ts.text, o, n, pos, pass + 1) << 8);
       }
     }
   }
@@ -229,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     const uint32_t k = wbase + i * BZG_WAVE + lane();
     const bool ok = k < g.hi;
     const uint64_t valid = __ballot(ok);
-    const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i] & 255u) : (key[i] >> shift) & 255u;
+    const uint32_t d = (key[i] >> shift) & 255u;
     rk[i] = 0xFFFFFFFFu;
     if (valid) {
       uint64_t peers = match_digit8(d, valid);
@@ -251,9 +204,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     for (int q = 0; q < NW; q++) tot += cnt[q][d];
     uint32_t all;
     uint32_t run = block_excl_sum<uint32_t, NT>(tot, sh, &all);
-    const size_t col0 = (size_t)g.r.base * 256;
     lbase[d] = run;
-    gbase[d] = g.r.start + hscan[col0 + (size_t)d * g.nt + g.t] - hscan[col0];
+    gbase[d] = g.r.start + hs_d - hs_0;
 #pragma unroll
     for (int q = 0; q < NW; q++) {
       uint32_t c = cnt[q][d];
@@ -265,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     if (rk[i] != 0xFFFFFFFFu) {
-      const uint32_t d = TEXT ? (last_text ? key[i] >> 24 : key[i] & 255u) : (key[i] >> shift) & 255u;
+      const uint32_t d = (key[i] >> shift) & 255u;
       const uint32_t L = cnt[w][d] + rk[i];
       sval[L] = val[i];
       skey[L] = key[i];
@@ -278,10 +230,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     const uint32_t L = i * NT + threadIdx.x;
     if (L < tn) {
       const uint32_t kd = skey[L];
-      const uint32_t d = TEXT ? (last_text ? kd >> 24 : kd & 255u) : (kd >> shift) & 255u;
-      const uint32_t pos = gbase[d] + (L - lbase[d]);
-      if (!TEXT || last_text) kout[pos] = kd;
-      else ts.dout[pos] = (uint8_t)(kd >> 8);
+      const uint32_t pos = gbase[(kd >> shift) & 255u] + (L - lbase[(kd >> shift) & 255u]);
+      kout[pos] = kd;
       vout[pos] = sval[L];
     }
   }
@@ -896,7 +846,7 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
     {
       ProfScope ps("radix_hist", st, 4.0 * elems);  // read the key
       hipLaunchKernelGGL(k_radix_hist<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
-                         TextSrc{}, p);
+                         nullptr);
     }
     {
       ProfScope ps("scan", st, 8.0 * big_tiles * 256);
@@ -905,7 +855,7 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
     }
     ProfScope ps("radix_scatter", st, 16.0 * elems);  // read and write key and value
     hipLaunchKernelGGL(k_radix_scatter<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
-                       w.hist, TextSrc{}, p);
+                       w.hist, nullptr);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
@@ -914,33 +864,37 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
   return hipGetLastError();
 }
 
-// The init sort: 4 LSD passes on the first 4 bytes of every rotation, rows
-// only (see k_radix_scatter<true>).  Pass 0 writes tmpV, pass 3 writes SA
-// and the sorted keys into w.key.
+// The init sort: 4 LSD passes on the first 4 bytes of every rotation (big-
+// endian).  Pass 0 builds the (key, row) pairs from a sequential read of the
+// text; the sorted keys and rows end in w.key and w.SA.
 static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, double elems,
-                              TextSrc ts, hipStream_t st) {
-  const uint32_t* vin = nullptr;
-  // digit bytes ping-pong through tmpK and key (key is written only by pass 3)
-  uint8_t* dbuf[2] = {(uint8_t*)w.tmpK, (uint8_t*)w.key};
+                              const uint8_t* text, hipStream_t st) {
+  uint32_t* kout[4] = {w.tmpK, w.key, w.tmpK, w.key};
+  uint32_t* vout[4] = {w.tmpV, w.SA, w.tmpV, w.SA};
   for (int p = 0; p < 4; p++) {
-    uint32_t* vout = (p & 1) ? w.SA : w.tmpV;
-    ts.din = p ? dbuf[(p - 1) & 1] : nullptr;
-    ts.dout = p < 3 ? dbuf[p & 1] : nullptr;
+    const uint32_t* ka = p ? kout[p - 1] : nullptr;
+    const uint32_t* va = p ? vout[p - 1] : nullptr;
     {
-      ProfScope ps("init_hist", st, 1.0 * elems);  // one digit byte per row
-      hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, vin, 0, w.hist, ts, p);
+      ProfScope ps("init_hist", st, (p ? 4.0 : 1.0) * elems);  // key in (pass 0: one text byte)
+      if (p == 0)
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, 0, w.hist, text);
+      else
+        hipLaunchKernelGGL(k_radix_hist<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
+                           nullptr);
     }
     {
       ProfScope ps("scan", st, 8.0 * big_tiles * 256);
       hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
       if (e != hipSuccess) return e;
     }
-    // row and digit in (pass 0: two text bytes), row and next digit out
-    // (pass 3: row and key out, plus the gathered key bytes)
-    ProfScope ps("init_scatter", st, (p == 0 ? 7.0 : p == 3 ? 14.0 : 11.0) * elems);
-    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, vin, w.key,
-                       vout, 0, w.hist, ts, p);
-    vin = vout;
+    // key and row in and out (pass 0: one text byte in per row)
+    ProfScope ps("init_scatter", st, (p ? 16.0 : 9.0) * elems);
+    if (p == 0)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, nullptr,
+                         kout[p], vout[p], 0, w.hist, text);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kout[p],
+                         vout[p], 8 * p, w.hist, nullptr);
   }
   return hipGetLastError();
 }
@@ -991,7 +945,6 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
   uint32_t max_n = 0;
   for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
-  const TextSrc ts{text, w.d_off, nullptr, nullptr};
   // initial segments: every block as a large segment (a one-row block too:
   // the init passes are what put its row into SA)
   std::vector<SegRec> segs0;
@@ -1012,7 +965,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     BZG_TRY(hipMemcpyAsync(w.owner[0], owner0.data(), owner0.size() * 4, hipMemcpyHostToDevice, st));
     uint32_t big_tiles = (uint32_t)owner0.size();
     uint32_t *kin, *vin;
-    BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, ts, st));
+    BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, text, st));
     AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1]};
     {
       ProfScope ps("rename_a", st, 4.0 * init_elems);
