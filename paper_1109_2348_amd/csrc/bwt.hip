@@ -61,18 +61,36 @@ __device__ __forceinline__ uint32_t cyc(uint32_t q, uint32_t n) {
   return q >= n ? q - n : q;
 }
 
-// The first 4 bytes of the rotation at local position pos, big-endian.  When
-// they do not wrap around the block end, two aligned dword loads, each
-// holding at least one of the 4 bytes (so neither leaves the allocation's
-// pages), replace four byte loads.
-__device__ __forceinline__ uint32_t text_key(const uint8_t* __restrict__ text, uint32_t o, uint32_t n, uint32_t pos) {
+// The first 4 bytes of the rotation at local position pos, big-endian, in
+// two steps, so that a caller issues the loads of all its rows before it
+// uses any.  text_key_load reads the aligned dwords that hold bytes
+// min(pos, n-4) .. +3 (one dword when that is aligned; each holds a byte of
+// the block, so neither leaves the allocation's pages); text_key_value
+// assembles them, or, for the few rotations that wrap around the block end
+// (and blocks under 4 bytes), reads the 4 bytes one by one.
+struct TextWords {
+  uint32_t lo, hi;
+};
+
+__device__ __forceinline__ uint32_t text_key_addr(uint32_t o, uint32_t n, uint32_t pos) {
+  return o + (n >= 4u ? min(pos, n - 4u) : 0u);
+}
+
+__device__ __forceinline__ TextWords text_key_load(const uint8_t* __restrict__ text, uint32_t o, uint32_t n,
+                                                   uint32_t pos) {
+  const uint32_t a = text_key_addr(o, n, pos);
+  const uint32_t* w = (const uint32_t*)(text + (a & ~3u));
+  TextWords t;
+  t.lo = w[0];
+  t.hi = w[(a & 3u) && n >= 4u ? 1 : 0];
+  return t;
+}
+
+__device__ __forceinline__ uint32_t text_key_value(TextWords t, const uint8_t* __restrict__ text, uint32_t o,
+                                                   uint32_t n, uint32_t pos) {
   if (pos + 3u < n) {
-    const uintptr_t a = (uintptr_t)(text + o + pos);
-    const uint32_t* w = (const uint32_t*)(a & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(a & 3u) * 8u;
-    uint32_t v = w[0] >> sh;
-    if (sh) v |= w[1] << (32u - sh);
-    return __builtin_bswap32(v);
+    const uint32_t sh = (text_key_addr(o, n, pos) & 3u) * 8u;
+    return __builtin_bswap32(sh ? (t.lo >> sh) | (t.hi << (32u - sh)) : t.lo);
   }
   uint32_t v = 0;
 #pragma unroll
@@ -105,36 +123,47 @@ template <bool TEXT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                    const uint32_t* __restrict__ kin, int shift,
                                                    uint32_t* __restrict__ hist, const uint8_t* __restrict__ text) {
-  __shared__ uint32_t cnt[NW][256];
+  // counts only (no ranks), so LDS atomics instead of matching lanes of
+  // equal digit.  Same-address atomics serialize: every wave keeps 4 copies
+  // (by lane mod 4, padded onto different banks), and the digit of each
+  // slot's first lane, often the common one in skewed data, is added once
+  // for all its lanes.
+  constexpr uint32_t NC = NW * 4, CS = 257;
+  __shared__ uint32_t cnt[NC * CS];
   const uint32_t w = threadIdx.x / BZG_WAVE;
-  for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
+  for (uint32_t d = threadIdx.x; d < NC * CS; d += NT) cnt[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
   const uint32_t o = TEXT ? g.r.start : 0u, n = TEXT ? g.r.len : 0u;
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
+  // loads of clamped rows, none under a branch, so all are in flight at once
   uint32_t dg[RI];
 #pragma unroll
   for (int i = 0; i < RI; i++) {
-    const uint32_t k = wbase + i * BZG_WAVE + lane();
-    dg[i] = 0;
-    if (k < g.hi) dg[i] = TEXT ? text[o + cyc(n - 1u - (k - o) + 3u, n)] : (kin[k] >> shift) & 255u;
+    const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
+    dg[i] = TEXT ? text[o + cyc(n - 1u - (k - o) + 3u, n)] : kin[k];
   }
+#pragma unroll
+  for (int i = 0; i < RI; i++) dg[i] = TEXT ? dg[i] : (dg[i] >> shift) & 255u;
+  uint32_t* mine = cnt + (w * 4u + (lane() & 3u)) * CS;
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     const uint32_t k = wbase + i * BZG_WAVE + lane();
     const bool ok = k < g.hi;
     const uint64_t valid = __ballot(ok);
     if (valid) {
-      const uint32_t d = dg[i];
-      const uint64_t peers = match_digit8(d, valid);
-      if (ok && lowest_lane(peers) == lane()) cnt[w][d] += __popcll(peers);
+      const uint32_t fl = lowest_lane(valid);
+      const uint32_t d0 = __builtin_amdgcn_readlane(dg[i], fl);
+      const bool same = dg[i] == d0;
+      const uint64_t m = __ballot(ok && same);
+      if (ok && (!same || lane() == fl)) atomicAdd(&mine[dg[i]], same ? (uint32_t)__popcll(m) : 1u);
     }
   }
   __syncthreads();
   uint32_t d = threadIdx.x;
   uint32_t s = 0;
 #pragma unroll
-  for (int q = 0; q < NW; q++) s += cnt[q][d];
+  for (uint32_t q = 0; q < NC; q++) s += cnt[q * CS + d];
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
@@ -160,21 +189,28 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
   const size_t col0 = (size_t)g.r.base * 256;
   const uint32_t hs_d = hscan[col0 + (size_t)threadIdx.x * g.nt + g.t], hs_0 = hscan[col0];
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
+  // loads of clamped rows, none under a branch, so all are in flight at once
   uint32_t key[RI], val[RI], rk[RI];
+  if (TEXT) {
+    TextWords tw[RI];
 #pragma unroll
-  for (int i = 0; i < RI; i++) {
-    const uint32_t k = wbase + i * BZG_WAVE + lane();
-    key[i] = 0;
-    val[i] = 0;
-    if (k < g.hi) {
-      if (TEXT) {
-        const uint32_t pos = n - 1u - (k - o);
-        val[i] = o + pos;
-        key[i] = text_key(text, o, n, pos);
-      } else {
-        key[i] = kin[k];
-        val[i] = vin[k];
-      }
+    for (int i = 0; i < RI; i++) {
+      const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
+      tw[i] = text_key_load(text, o, n, n - 1u - (k - o));
+    }
+#pragma unroll
+    for (int i = 0; i < RI; i++) {
+      const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
+      const uint32_t pos = n - 1u - (k - o);
+      val[i] = o + pos;
+      key[i] = text_key_value(tw[i], text, o, n, pos);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RI; i++) {
+      const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
+      key[i] = kin[k];
+      val[i] = vin[k];
     }
   }
 #pragma unroll
@@ -478,6 +514,29 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
 // on, relative to the block start; or (text != null, the first round, h = 4)
 // that rotation's first 4 bytes, which order rotations exactly as their
 // ranks after the init sort do.
+// key2 of M rows from their partner positions p[i], local to the block at
+// bo[i] with bn[i] rows (ONE_BLOCK: all in the block bo[0], bn[0]): the
+// partner's rank relative to the block start, or (text != null) its first 4
+// bytes.  Every load is issued before any value is used.
+template <int M, bool ONE_BLOCK>
+__device__ __forceinline__ void gather_keys_impl(uint32_t* p, const uint32_t* bo, const uint32_t* bn,
+                                                 const uint8_t* __restrict__ text,
+                                                 const uint32_t* __restrict__ rank) {
+  if (text) {
+    TextWords tw[M];
+#pragma unroll
+    for (int i = 0; i < M; i++) tw[i] = text_key_load(text, bo[ONE_BLOCK ? 0 : i], bn[ONE_BLOCK ? 0 : i], p[i]);
+#pragma unroll
+    for (int i = 0; i < M; i++)
+      p[i] = text_key_value(tw[i], text, bo[ONE_BLOCK ? 0 : i], bn[ONE_BLOCK ? 0 : i], p[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; i++) p[i] = rank[bo[ONE_BLOCK ? 0 : i] + p[i]];
+#pragma unroll
+    for (int i = 0; i < M; i++) p[i] -= bo[ONE_BLOCK ? 0 : i];
+  }
+}
+
 __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
                                                const uint32_t* __restrict__ owner, const RoundCounters* cnt,
                                                uint32_t n_small_tiles, const uint32_t* __restrict__ blk_off,
@@ -492,50 +551,60 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   if (jt < n_small_tiles) {
     uint32_t n = small_tile_map(jt, head, segs, cnt->small_total, mark, segp, sh, &s_n, &s_maxlen);
     // segment records, then block bounds and rows, then the gathers: each
-    // stage's loads are issued together
-    constexpr int PL = SMALL_CAP / NT;
-    SegRec rr[PL];
-    uint32_t sa[PL], bo[PL], bn[PL];
+    // stage's loads are issued together, for half the tile at a time (which
+    // bounds the registers held across them)
+    constexpr int PL = SMALL_CAP / NT / 2;
+#pragma unroll 1
+    for (int half = 0; half < 2; half++) {
+      SegRec rr[PL];
+      uint32_t sa[PL], bo[PL], bn[PL], ps[PL], kv[PL];
 #pragma unroll
-    for (int j = 0; j < PL; j++) {
-      const uint32_t p = j * NT + threadIdx.x;
-      rr[j] = SegRec{0, 0, 0, 0};
-      if (p < n && segp[p] != NO_SEG) rr[j] = segs[mark[segp[p]] - 1];
-    }
+      for (int j = 0; j < PL; j++) {
+        const uint32_t p = (half * PL + j) * NT + threadIdx.x;
+        rr[j] = SegRec{0, 0, 0, 0};
+        if (p < n && segp[p] != NO_SEG) rr[j] = segs[mark[segp[p]] - 1];
+      }
+      // positions without a row read row 0 of block 0 (loads stay unbranched)
 #pragma unroll
-    for (int j = 0; j < PL; j++) {
-      const uint32_t p = j * NT + threadIdx.x;
-      if (rr[j].len) {
-        sa[j] = SA[rr[j].start + (p - segp[p])];
+      for (int j = 0; j < PL; j++) {
+        const uint32_t p = (half * PL + j) * NT + threadIdx.x;
+        ps[j] = rr[j].len ? p - segp[p] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < PL; j++) {
+        sa[j] = SA[rr[j].start + ps[j]];
         bo[j] = blk_off[rr[j].blk];
-        bn[j] = blk_off[rr[j].blk + 1] - bo[j];
+        bn[j] = blk_off[rr[j].blk + 1];
       }
-    }
 #pragma unroll
-    for (int j = 0; j < PL; j++) {
-      const uint32_t p = j * NT + threadIdx.x;
-      if (rr[j].len) {
-        const uint32_t k = rr[j].start + (p - segp[p]);
-        const uint32_t i = cyc(sa[j] - bo[j] + h, bn[j]);
-        key2[k] = text ? text_key(text, bo[j], bn[j], i) : rank[bo[j] + i] - bo[j];
+      for (int j = 0; j < PL; j++) {
+        bn[j] -= bo[j];
+        if (!rr[j].len) sa[j] = bo[j] = 0, bn[j] = 1;
+        kv[j] = cyc(sa[j] - bo[j] + (rr[j].len ? h : 0u), bn[j]);  // partner position
       }
+      gather_keys_impl<PL, false>(kv, bo, bn, text, rank);
+#pragma unroll
+      for (int j = 0; j < PL; j++)
+        if (rr[j].len) key2[rr[j].start + ps[j]] = kv[j];
     }
   } else {
     BigTile g = big_tile(jt - n_small_tiles, segs, owner);
-    uint32_t o = blk_off[g.r.blk], nbk = blk_off[g.r.blk + 1] - o;
-    // all rows of the tile first, then the gathers (independent loads)
-    uint32_t sa[RI];
+    const uint32_t o = blk_off[g.r.blk], nbk = blk_off[g.r.blk + 1] - o;
+    // all rows of the tile first, then the gathers (independent loads), for
+    // half the tile at a time
+    constexpr int RH = RI / 2;
+#pragma unroll 1
+    for (int half = 0; half < 2; half++) {
+      uint32_t kv[RH];
 #pragma unroll
-    for (int q = 0; q < RI; q++) {
-      const uint32_t k = g.lo + q * NT + threadIdx.x;
-      sa[q] = k < g.hi ? SA[k] : o;
-    }
+      for (int q = 0; q < RH; q++) kv[q] = SA[min(g.lo + (half * RH + q) * NT + threadIdx.x, g.hi - 1u)];
 #pragma unroll
-    for (int q = 0; q < RI; q++) {
-      const uint32_t k = g.lo + q * NT + threadIdx.x;
-      if (k < g.hi) {
-        const uint32_t i = cyc(sa[q] - o + h, nbk);
-        key2[k] = text ? text_key(text, o, nbk, i) : rank[o + i] - o;
+      for (int q = 0; q < RH; q++) kv[q] = cyc(kv[q] - o + h, nbk);
+      gather_keys_impl<RH, true>(kv, &o, &nbk, text, rank);
+#pragma unroll
+      for (int q = 0; q < RH; q++) {
+        const uint32_t k = g.lo + (half * RH + q) * NT + threadIdx.x;
+        if (k < g.hi) key2[k] = kv[q];
       }
     }
   }
@@ -576,32 +645,36 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   {
     // all segment records first, then the rows' key2 and SA (independent
     // loads, issued together)
+    // (positions without a row load from row 0 of segment 0: no load sits
+    // under a branch, so each stage's loads are all in flight together)
     constexpr int PL = SMALL_CAP / NT;
-    uint32_t kk[PL];
+    uint32_t sp[PL], kk[PL], k2[PL], vv[PL];
 #pragma unroll
     for (int j = 0; j < PL; j++) {
       const uint32_t p = j * NT + threadIdx.x;
-      kk[j] = 0xFFFFFFFFu;
-      if (p < n) {
-        const uint32_t sp = segp[p];
-        if (sp != NO_SEG) kk[j] = segs[mark[sp] - 1].start + (p - sp);
-      }
+      sp[j] = p < n ? segp[p] : NO_SEG;
+      kk[j] = segs[sp[j] != NO_SEG ? mark[sp[j]] - 1 : 0u].start;
     }
 #pragma unroll
     for (int j = 0; j < PL; j++) {
       const uint32_t p = j * NT + threadIdx.x;
-      uint32_t kv = 0xFFFFFFFFu, vv = 0, sv = 0xFFFFu;
-      if (kk[j] != 0xFFFFFFFFu) {
-        const uint32_t sp = segp[p];
-        kv = text_mode ? key2[kk[j]] : (sp << 21) | key2[kk[j]];
-        sv = sp;
-        vv = SA[kk[j]];
+      kk[j] = sp[j] != NO_SEG ? kk[j] + (p - sp[j]) : kk[j];
+      k2[j] = key2[kk[j]];
+      vv[j] = SA[kk[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < PL; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      uint32_t kv = 0xFFFFFFFFu, sv = 0xFFFFu;
+      if (sp[j] != NO_SEG) {
+        kv = text_mode ? k2[j] : (sp[j] << 21) | k2[j];
+        sv = sp[j];
       } else if (p < n) {  // before the tile's first segment
         kv = 0;
         sv = 0;
       }
       skey[p] = kv;
-      sval[p] = vv;
+      sval[p] = sp[j] != NO_SEG ? vv[j] : 0u;
       sseg[p] = (uint16_t)sv;
     }
   }
@@ -784,10 +857,13 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
       if (sa_local) sa_local[k] = q - o;
     }
   }
+  // every gather issued before any is used (rows past cnt re-read row 0's)
+  uint32_t t[OUT_ROWS];
+#pragma unroll
+  for (uint32_t i = 0; i < OUT_ROWS; i++) t[i] = text[i < cnt ? src[i] : src[0]];
   uint32_t w[OUT_ROWS / 4] = {0, 0, 0, 0};
 #pragma unroll
-  for (uint32_t i = 0; i < OUT_ROWS; i++)
-    if (i < cnt) w[i >> 2] |= (uint32_t)text[src[i]] << (8 * (i & 3));
+  for (uint32_t i = 0; i < OUT_ROWS; i++) w[i >> 2] |= t[i] << (8 * (i & 3));
   if (cnt == OUT_ROWS && ((uintptr_t)(L + k0) & 15u) == 0) {
     *(uint4*)(L + k0) = make_uint4(w[0], w[1], w[2], w[3]);
   } else {
