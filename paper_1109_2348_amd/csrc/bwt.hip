@@ -308,11 +308,15 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
   const uint32_t t_tiles = (uint32_t)(tot >> 26) & M13, t_big = (uint32_t)(tot >> 39) & ((1u << 22) - 1u);
   const uint32_t e_seg = (uint32_t)ex & M13, e_small = (uint32_t)(ex >> 13) & M13, e_tiles = (uint32_t)(ex >> 26) & M13;
   if (threadIdx.x == 0) {
-    wg_base[0] = t_seg ? atomicAdd(&a.cnt->n_segs, t_seg) : 0u;
-    wg_base[1] = t_small ? atomicAdd(&a.cnt->small_total, t_small) : 0u;
-    wg_base[2] = t_tiles ? atomicAdd(&a.cnt->big_tiles, t_tiles) : 0u;
-    if (t_small + t_big) atomicAdd(&a.cnt->active, t_small + t_big);
-    if (t_big) atomicAdd(&a.cnt->big_active, t_big);
+    // neither half of a word carries into the other: segments, packed
+    // elements, tiles and large-segment elements of a round stay below 2^32
+    const unsigned long long ss =
+        t_seg ? atomicAdd(&a.cnt->segs_small, (unsigned long long)t_seg | ((unsigned long long)t_small << 32)) : 0ull;
+    const unsigned long long tb =
+        t_tiles ? atomicAdd(&a.cnt->tiles_big, (unsigned long long)t_tiles | ((unsigned long long)t_big << 32)) : 0ull;
+    wg_base[0] = (uint32_t)ss;
+    wg_base[1] = (uint32_t)(ss >> 32);
+    wg_base[2] = (uint32_t)tb;
   }
   __syncthreads();
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   __shared__ uint32_t s_n, s_maxlen;
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   if (jt < n_small_tiles) {
-    uint32_t n = small_tile_map(jt, head, segs, cnt->small_total, mark, segp, sh, &s_n, &s_maxlen);
+    uint32_t n = small_tile_map(jt, head, segs, cnt->small_total(), mark, segp, sh, &s_n, &s_maxlen);
     // segment records, then block bounds and rows, then the gathers: each
     // stage's loads are issued together, for half the tile at a time (which
     // bounds the registers held across them)
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t s_n, s_maxlen;
   __shared__ uint32_t wg_base[4];
-  const uint32_t small_total = cnt->small_total;
+  const uint32_t small_total = cnt->small_total();
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n, &s_maxlen);
   // load (segment start << 21 | key2, SA value).  Positions before the
@@ -720,6 +724,9 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     __syncthreads();
   }
   const int npass = counting ? 0 : text_mode ? 6 : 4;
+  // the passes sort positions [0, 4 * 64 * R) only, R items per lane: the
+  // positions from n on hold the largest key and stay behind anyway
+  const int R = (int)((n + NW * BZG_WAVE - 1) / (NW * BZG_WAVE));
   for (int pass = 0; pass < npass; pass++) {
     const int shift = (pass & 3) * 8;
     const bool by_seg = pass >= 4;  // text round: the segment position last
@@ -728,7 +735,8 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     uint32_t key[PI], val[PI], rk[PI], sg[PI];
 #pragma unroll
     for (int i = 0; i < PI; i++) {
-      uint32_t p = w * (PI * BZG_WAVE) + i * BZG_WAVE + lane();
+      if (i >= R) break;
+      uint32_t p = (w * R + i) * BZG_WAVE + lane();
       key[i] = skey[p];
       val[i] = sval[p];
       sg[i] = sseg[p];
@@ -756,6 +764,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PI; i++) {
+      if (i >= R) break;
       uint32_t d = ((by_seg ? sg[i] : key[i]) >> shift) & 255u;
       uint32_t pos = scnt[w][d] + rk[i];
       skey[pos] = key[i];
@@ -1065,9 +1074,9 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       RoundCounters c = w.h_cnt[cur];
       if (log_rounds)
         fprintf(stderr, "[bzg] sort round %d h=%u segments=%u small_rows=%u large_rows=%u large_tiles=%u\n", nround,
-                h, c.n_segs, c.small_total, c.big_active, c.big_tiles);
-      if (c.n_segs == 0) break;
-      if (c.n_segs > z.seg_cap || c.big_tiles > z.owner_cap || c.small_total > N) {
+                h, c.n_segs(), c.small_total(), c.big_active(), c.big_tiles());
+      if (c.n_segs() == 0) break;
+      if (c.n_segs() > z.seg_cap || c.big_tiles() > z.owner_cap || c.small_total() > N) {
         err = "bwt: segment capacity exceeded";
         return hipErrorInvalidValue;
       }
@@ -1076,29 +1085,29 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       // round 0 (h = 4) sorts on the next 4 text bytes instead of ranks
       const bool text_round = h == 4;
       BZG_TRY(hipMemsetAsync(&w.cnt[nxt], 0, sizeof(RoundCounters), st));
-      const uint32_t nsmall = (c.small_total + SMALL_T - 1) / SMALL_T;
+      const uint32_t nsmall = (c.small_total() + SMALL_T - 1) / SMALL_T;
       {
-        ProfScope ps("gather", st, 12.0 * c.active);  // row, partner rank, key2
-        hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.head[cur],
+        ProfScope ps("gather", st, 12.0 * c.active());  // row, partner rank, key2
+        hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.head[cur],
                            w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank,
                            text_round ? text : nullptr, h, w.key);
       }
       AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[nxt]};
       if (nsmall) {
-        ProfScope ps("small_sort", st, 16.0 * c.small_total);  // key2 and row in, row and rank out
+        ProfScope ps("small_sort", st, 16.0 * c.small_total());  // key2 and row in, row and rank out
         hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
                            w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? 1 : 0, app2);
       }
-      if (c.big_tiles) {
-        const double be = c.big_active;
-        BZG_TRY(radix_passes(w, c.big_tiles, w.segs[cur], w.owner[cur], text_round ? 4 : passes, be, &kin, &vin,
+      if (c.big_tiles()) {
+        const double be = c.big_active();
+        BZG_TRY(radix_passes(w, c.big_tiles(), w.segs[cur], w.owner[cur], text_round ? 4 : passes, be, &kin, &vin,
                              st));
         {
           ProfScope ps("rename_a", st, 4.0 * be);
-          hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
+          hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
         }
         ProfScope ps("rename_b", st, 16.0 * be);
-        hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
+        hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
                            w.agg, w.d_off, w.SA, w.rank, 2 * h, text_round ? 0 : 1, 1, app2);
       }
       BZG_TRY(hipGetLastError());

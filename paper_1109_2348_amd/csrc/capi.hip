@@ -93,7 +93,9 @@ struct bzg_ctx {
   size_t ws_cap[2] = {0, 0};
   void* pin = nullptr;
   size_t pin_cap = 0;
-  uint32_t* crc_tab = nullptr;  // device: 256 byte steps, 64 powers x^(8*2^j), 256 tile shifts (mod P)
+  // device: 4 x 256 byte-step tables (slicing by 4), 64 powers x^(8*2^j),
+  // 256 tile shifts (mod P)
+  uint32_t* crc_tab = nullptr;
 };
 
 namespace {
@@ -158,7 +160,9 @@ int ensure_pin(bzg_ctx* ctx, size_t bytes, void** out) {
   return 0;
 }
 
-// CRC helper tables (built on the host from the polynomial).
+// CRC helper tables (built on the host from the polynomial).  tab[k*256 + b]
+// is the register after k + 1 byte steps from b << 24 with zero input: the
+// slicing-by-4 tables (Kounavis and Berry), k = 0 being the one-byte table.
 void crc_tables(uint32_t* tab, uint32_t* pw) {
   const uint32_t P = 0x04C11DB7u;
   for (uint32_t b = 0; b < 256; b++) {
@@ -166,6 +170,11 @@ void crc_tables(uint32_t* tab, uint32_t* pw) {
     for (int i = 0; i < 8; i++) r = (r & 0x80000000u) ? (r << 1) ^ P : (r << 1);
     tab[b] = r;
   }
+  for (int k = 1; k < 4; k++)
+    for (uint32_t b = 0; b < 256; b++) {
+      const uint32_t r = tab[(k - 1) * 256 + b];
+      tab[k * 256 + b] = (r << 8) ^ tab[r >> 24];
+    }
   auto mul = [&](uint32_t a, uint32_t c) {
     uint32_t r = 0;
     for (int i = 31; i >= 0; i--) {
@@ -244,10 +253,10 @@ int bzg_create(bzg_ctx** out, int hip_device) {
   if (!ctx) return BZG_ENOMEM;
   ctx->device = hip_device;
   hipError_t e = hipSetDevice(hip_device);
-  if (e == hipSuccess) e = hipMalloc(&ctx->crc_tab, 576 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&ctx->crc_tab, CRC_TAB_WORDS * sizeof(uint32_t));
   if (e == hipSuccess) {
-    uint32_t h[576];
-    crc_tables(h, h + 256);
+    uint32_t h[CRC_TAB_WORDS];
+    crc_tables(h, h + CRC_POW_AT);
     e = hipMemcpy(ctx->crc_tab, h, sizeof(h), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
@@ -566,7 +575,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
     HIPX(hipMemcpyAsync(d_blk_tile0, blk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
     if (iter == 0) {
       ProfScope ps("rle1_tiles", st, (double)(boff[nb] - boff[0]));
-      HIPX(rle1_tiles(in, ntiles, nullptr, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + 256,
+      HIPX(rle1_tiles(in, ntiles, nullptr, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + CRC_POW_AT,
                       d_rt[cur], st));
     } else {
       tile_from.assign(ntiles, ~0u);
@@ -592,11 +601,11 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
         HIPX(hipMemcpyAsync(d_tile_ids, tile_ids.data(), tile_ids.size() * 4, hipMemcpyHostToDevice, st));
         ProfScope ps("rle1_tiles", st, bytes);
         HIPX(rle1_tiles(in, (uint32_t)tile_ids.size(), d_tile_ids, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab,
-                        ctx->crc_tab + 256, d_rt[nxt], st));
+                        ctx->crc_tab + CRC_POW_AT, d_rt[nxt], st));
       }
       cur = nxt;
     }
-    HIPX(rle1_blocks(nb, d_blk_tile0, d_boff, ctx->crc_tab + 256, d_rt[cur], d_tile_rs, d_tile_out, d_rle_n, d_crc,
+    HIPX(rle1_blocks(nb, d_blk_tile0, d_boff, ctx->crc_tab + CRC_POW_AT, d_rt[cur], d_tile_rs, d_tile_out, d_rle_n, d_crc,
                      st));
     uint32_t* h_rle = (uint32_t*)pin;
     HIPX(hipMemcpyAsync(h_rle, d_rle_n, nb * 4, hipMemcpyDeviceToHost, st));

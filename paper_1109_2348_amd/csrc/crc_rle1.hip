@@ -18,6 +18,9 @@
 namespace bzg {
 
 constexpr int RITEMS = RLE_TILE / NT;  // 16 bytes per thread
+// Most RLE1 output bytes of one tile: every byte emits at most 2 (the 4th
+// of a piece: itself and the count slot).
+constexpr uint32_t RLE_OUT_MAX = 2 * RLE_TILE;
 
 struct RleTile {
   uint32_t last_bnd;  // last run start in the tile, +1 (0 = none)
@@ -76,8 +79,9 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
                                                    const uint32_t* crc_pow, RleTile* tiles) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
   __shared__ uint32_t sx[NT];
-  __shared__ uint32_t tab[256];
-  tab[threadIdx.x] = crc_tab[threadIdx.x];
+  __shared__ uint32_t tab[4][256];  // slicing-by-4 tables (k + 1 byte steps)
+#pragma unroll
+  for (int k = 0; k < 4; k++) tab[k][threadIdx.x] = crc_tab[k * 256 + threadIdx.x];
   const uint32_t t = ids ? ids[blockIdx.x] : blockIdx.x;
   TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
   const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
@@ -89,7 +93,15 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
   // CRC of this thread's bytes from a zero register, shifted to the tile end
   // (by a per-thread constant in full tiles)
   uint32_t reg = 0;
-  for (int i = 0; i < cnt; i++) reg = (reg << 8) ^ tab[(reg >> 24) ^ v[i]];
+  if (cnt == RITEMS) {  // four bytes a step: 4 dependent lookups instead of 16
+#pragma unroll
+    for (int j = 0; j < RITEMS / 4; j++) {
+      reg ^= ((uint32_t)v[4 * j] << 24) | ((uint32_t)v[4 * j + 1] << 16) | ((uint32_t)v[4 * j + 2] << 8) | v[4 * j + 3];
+      reg = tab[3][reg >> 24] ^ tab[2][(reg >> 16) & 255u] ^ tab[1][(reg >> 8) & 255u] ^ tab[0][reg & 255u];
+    }
+  } else {
+    for (int i = 0; i < cnt; i++) reg = (reg << 8) ^ tab[0][(reg >> 24) ^ v[i]];
+  }
   uint32_t share = 0;
   if (cnt) {
     const uint32_t after = g.hi - (p0 + cnt);
@@ -226,7 +238,16 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
     e += rle_emit_count(p - (rs - 1));
   }
   uint32_t tot;
-  uint32_t o = block_excl_sum<uint32_t, NT>(e, sh, &tot) + tile_off;
+  // MODE 0 stages the tile's output in LDS (at the global dword alignment)
+  // and writes it out coalesced.  A piece's count byte sits right after its
+  // 4th byte; when the piece runs on into the next tile, that slot is this
+  // tile's last output byte and the next tile writes it to global directly.
+  __shared__ uint8_t sout[RLE_OUT_MAX + 4];
+  __shared__ uint32_t s_skip;
+  const uint64_t gbase = obase + tile_off;
+  const uint32_t al = (uint32_t)(gbase & 3u);
+  if (MODE == 0 && threadIdx.x == 0) s_skip = 0;
+  uint32_t o = block_excl_sum<uint32_t, NT>(e, sh, &tot);  // local output position
   rs = rs0;
   pv = prev;
   uint32_t below = 0;
@@ -238,13 +259,32 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
     uint32_t u = tt % 255u;
     uint32_t ec = rle_emit_count(tt);
     if (MODE == 0) {
-      if (u <= 3) out[obase + o] = v[i];
+      if (u <= 3) sout[al + o] = v[i];
       bool last_of_piece = (u == 254) || (i + 1 < cnt ? v[i + 1] != v[i] : (!has_next || next != v[i]));
-      if (last_of_piece && u >= 3) out[obase + (u == 3 ? o + 1 : o - 1)] = (uint8_t)(u - 3);
+      if (last_of_piece && u >= 3) {
+        if (u == 3) sout[al + o + 1] = 0;
+        else if (o > 0) sout[al + o - 1] = (uint8_t)(u - 3);
+        else out[gbase - 1] = (uint8_t)(u - 3);  // slot in the previous tile's output
+      }
+      if (p + 1 == g.hi && u >= 3 && !last_of_piece) s_skip = 1;
     } else {
-      if (o + ec <= limit) below++;
+      if (tile_off + o + ec <= limit) below++;
     }
     o += ec;
+  }
+  if (MODE == 0) {
+    __syncthreads();
+    const uint32_t len = tot - s_skip;
+    const uint32_t nd = (al + len + 3) / 4;
+    uint32_t* gw = (uint32_t*)(out + (gbase - al));
+    const uint32_t* lw = (const uint32_t*)sout;
+    for (uint32_t j = threadIdx.x; j < nd; j += NT) {
+      if (4 * j >= al && 4 * j + 4 <= al + len) {
+        gw[j] = lw[j];
+      } else {
+        for (uint32_t q = max(4 * j, al); q < min(4 * j + 4, al + len); q++) out[gbase - al + q] = sout[q];
+      }
+    }
   }
   if (MODE == 1) {
     below = block_sum<uint32_t, NT>(below, sh);

@@ -49,6 +49,8 @@ constexpr uint32_t MTF_CHUNK = 8192;   // symbols per move-to-front chunk
 constexpr uint32_t MAX_BLOCK = 1u << 21;  // largest block the sort accepts (ranks fit 21 bits)
 constexpr int GROUP = 50;              // symbols per Huffman selector group
 constexpr int MAXG = 6, MAXA = 258, MAXLEN = 17;
+constexpr uint32_t CRC_POW_AT = 1024;                  // CRC table layout: 4 x 256 byte steps,
+constexpr uint32_t CRC_TAB_WORDS = CRC_POW_AT + 64 + 256;  // then powers, then tile shifts
 constexpr uint32_t PACK_GROUPS = 64;   // selector groups per bit-packing tile
 
 // A run of equal-prefix rotations still to be ordered: SA rows
@@ -59,14 +61,19 @@ struct SegRec {
 };
 
 // Device counters written by a sorting round and read back by the host.
+// Counts appended to by every workgroup of a round, two per 64-bit word so
+// that a workgroup takes its ranges with one atomic per word; the words sit
+// on different cache lines.
 struct RoundCounters {
-  uint32_t n_segs;       // segments for the next round
-  uint32_t small_total;  // packed elements of small segments
-  uint32_t big_tiles;    // radix tiles of large segments
-  uint32_t active;       // elements in all segments
-  uint32_t overflow;     // nonzero if a capacity was exceeded
-  uint32_t big_active;   // elements in large segments
-  uint32_t pad[2];
+  unsigned long long segs_small;  // segments for the next round | packed elements of small segments << 32
+  uint32_t pad0[30];
+  unsigned long long tiles_big;   // radix tiles of large segments | elements in large segments << 32
+  uint32_t pad1[30];
+  __host__ __device__ uint32_t n_segs() const { return (uint32_t)segs_small; }
+  __host__ __device__ uint32_t small_total() const { return (uint32_t)(segs_small >> 32); }
+  __host__ __device__ uint32_t big_tiles() const { return (uint32_t)tiles_big; }
+  __host__ __device__ uint32_t big_active() const { return (uint32_t)(tiles_big >> 32); }
+  __host__ __device__ uint32_t active() const { return small_total() + big_active(); }
 };
 
 struct Bump {

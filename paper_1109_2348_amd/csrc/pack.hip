@@ -229,25 +229,39 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
     }
   }
   for (uint32_t i = threadIdx.x; i < WCAP; i += NT) stage[i] = 0;
-  __syncthreads();
   const uint64_t sb = sel_base[b];
   const uint64_t data0 = blk_bit[b] + (mode == 0 ? 105u : 0u) + T->hdr_bits;
   const uint64_t B0 = data0 + (gofs[sb + g0] - gofs[sb]);
   const uint16_t* S = syms + sym_base[b];
+  // the tile's symbols and selectors into LDS: coalesced, unbranched loads
+  // (clamped), all in flight together
+  __shared__ uint16_t ssym[MAXSYM];
+  __shared__ uint8_t ssel[PACK_GROUPS];
+  const uint32_t cnt = s1 - s0;
+  {
+    uint32_t tmp[PER];
+#pragma unroll
+    for (uint32_t q = 0; q < PER; q++) tmp[q] = S[s0 + min(q * NT + threadIdx.x, cnt - 1u)];
+#pragma unroll
+    for (uint32_t q = 0; q < PER; q++)
+      if (q * NT + threadIdx.x < cnt) ssym[q * NT + threadIdx.x] = (uint16_t)tmp[q];
+    if (threadIdx.x < g1 - g0) ssel[threadIdx.x] = sel[sb + g0 + threadIdx.x];
+  }
+  __syncthreads();
   // blocked: PER consecutive symbols per thread
-  const uint32_t i0 = s0 + threadIdx.x * PER;
+  const uint32_t l0 = threadIdx.x * PER;
   uint32_t mine = 0;
   for (uint32_t q = 0; q < PER; q++) {
-    uint32_t i = i0 + q;
-    if (i < s1) mine += slen[sel[sb + i / GROUP]][S[i]];
+    const uint32_t l = l0 + q;
+    if (l < cnt) mine += slen[ssel[l / GROUP]][ssym[l]];
   }
   uint64_t tot;
   uint64_t p = (B0 & 31) + block_excl_sum<uint64_t, NT>((uint64_t)mine, sh, &tot);
   for (uint32_t q = 0; q < PER; q++) {
-    uint32_t i = i0 + q;
-    if (i >= s1) break;
-    uint32_t t = sel[sb + i / GROUP];
-    uint32_t s = S[i];
+    const uint32_t l = l0 + q;
+    if (l >= cnt) break;
+    uint32_t t = ssel[l / GROUP];
+    uint32_t s = ssym[l];
     uint32_t n = slen[t][s], v = scode[t][s];
     uint32_t wi = (uint32_t)(p >> 5), o = (uint32_t)(p & 31);
     if (o + n <= 32) {

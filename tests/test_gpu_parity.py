@@ -215,6 +215,24 @@ def test_compress_small_cases(bz):
         assert bz2.decompress(z) == x
 
 
+def test_compress_runs_across_tiles(bz):
+    """RLE1 runs that open, close or cross a piece boundary (every 255 bytes
+    of a run) at the edge of a 4096-byte input tile, including pieces whose
+    count byte belongs to the previous tile's output."""
+    rnd = np.random.default_rng(23)
+    parts, offs = [], [0]
+    for s in list(range(0, 9)) + list(range(249, 262)):
+        for L in (1, 4, 5, 7, 255, 256, 259, 260, 510, 4099):
+            fill = rnd.integers(0, 255, 4096 - s, dtype=np.uint8)  # never 255
+            tail = rnd.integers(0, 255, 97, dtype=np.uint8)
+            blk = np.concatenate([fill, np.full(L, 255, np.uint8), tail])
+            parts.append(blk)
+            offs.append(offs[-1] + blk.size)
+    data = np.concatenate(parts)
+    z = _check_compress(bz, data, offs, 9, f"{len(parts)} blocks with runs at tile edges")
+    assert bz2.decompress(z) == data.tobytes()
+
+
 def test_compress_config1(bz):
     b = W.config1()
     z = _check_compress(bz, b.data, b.offsets, 1, "single 100000-byte block, order-2 Markov")
