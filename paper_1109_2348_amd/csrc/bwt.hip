@@ -348,9 +348,19 @@ __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs
                                                  const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg) {
   __shared__ uint32_t sh[NW + 1];
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  // every key and its predecessor loaded first (clamped rows, unbranched)
+  uint32_t kc[RI], kp[RI];
+#pragma unroll
+  for (int q = 0; q < RI; q++) {
+    const uint32_t k = min(g.lo + q * NT + threadIdx.x, g.hi - 1u);
+    kc[q] = kin[k];
+    kp[q] = kin[k > g.r.start ? k - 1 : k];
+  }
   uint32_t best = 0;
-  for (uint32_t k = g.lo + threadIdx.x; k < g.hi; k += NT) {
-    if (k == g.r.start || kin[k] != kin[k - 1]) best = max(best, k + 1);
+#pragma unroll
+  for (int q = 0; q < RI; q++) {
+    const uint32_t k = g.lo + q * NT + threadIdx.x;
+    if (k < g.hi && (k == g.r.start || kc[q] != kp[q])) best = max(best, k + 1);
   }
   best = wave_max(best);
   if (lane() == 0) sh[threadIdx.x / BZG_WAVE] = best;
@@ -397,9 +407,22 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   // the segment) and rows, loaded coalesced into LDS and read blocked
   __shared__ uint32_t tk[RADIX_TILE + 2], tv[RADIX_TILE];
   const uint32_t tn = g.hi - g.lo;
-  for (uint32_t i = threadIdx.x; i < tn; i += NT) {
-    tk[i + 1] = kin[g.lo + i];
-    tv[i] = vin[g.lo + i];
+  {
+    uint32_t a[RI], b[RI];  // loads first (clamped rows, unbranched), then LDS
+#pragma unroll
+    for (int q = 0; q < RI; q++) {
+      const uint32_t i = min(q * NT + threadIdx.x, tn - 1u);
+      a[q] = kin[g.lo + i];
+      b[q] = vin[g.lo + i];
+    }
+#pragma unroll
+    for (int q = 0; q < RI; q++) {
+      const uint32_t i = q * NT + threadIdx.x;
+      if (i < tn) {
+        tk[i + 1] = a[q];
+        tv[i] = b[q];
+      }
+    }
   }
   if (threadIdx.x == 0) {
     tk[0] = g.lo > g.r.start ? kin[g.lo - 1] : 0u;

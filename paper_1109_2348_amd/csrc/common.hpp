@@ -126,6 +126,23 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t valid) {
   return m;
 }
 
+// Copies n elements from global memory to LDS with NTH threads: BATCH loads
+// per thread in flight at a time (clamped indices, so no load sits under a
+// branch and waits alone).
+template <int NTH, int BATCH, typename T>
+__device__ __forceinline__ void stage_to_lds(T* dst, const T* __restrict__ src, uint32_t n) {
+  for (uint32_t base = 0; base < n; base += NTH * BATCH) {
+    T v[BATCH];
+#pragma unroll
+    for (int j = 0; j < BATCH; j++) v[j] = src[min(base + j * NTH + threadIdx.x, n - 1u)];
+#pragma unroll
+    for (int j = 0; j < BATCH; j++) {
+      const uint32_t i = base + j * NTH + threadIdx.x;
+      if (i < n) dst[i] = v[j];
+    }
+  }
+}
+
 // Up to 16 bytes starting at p (1 <= n <= 16 of them valid) as 4 little-endian
 // words: byte i of the span is byte i%4 of word i/4.  Reads the aligned
 // dwords that hold at least one valid byte (so never a page the span does not

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
     const uint32_t ge = min(gs + ASSIGN_SUB, g1);
     const uint32_t s0 = gs * GROUP, s1 = min(ge * GROUP, ns);
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < s1 - s0; i += NT) st[i] = S[s0 + i];
+    stage_to_lds<NT, 10>(st, S + s0, s1 - s0);
     __syncthreads();
     const uint32_t g = gs + threadIdx.x;
     if (g < ge) {
