@@ -461,7 +461,10 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
       bool end = (k + 1 == segend) ||
                  ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : (i + 1 < RI) ? tk[i0 + i + 2] != kk[i]
                                                                                     : knext != kk[i]);
-      if (rank_all || (end && hp == k + 1)) rank[v] = hp - 1;
+      // rank rounds: rows of the segment's first group keep the rank they
+      // have (the segment's start)
+      const bool same_rank = key_is_rank && hp - 1 == g.r.start;
+      if (!same_rank && (rank_all || (end && hp == k + 1))) rank[v] = hp - 1;
       if (end) {
         uint32_t len = k + 1 - (hp - 1);
         // closed group: the segment did not split and every partner lies in
@@ -505,14 +508,22 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
     }
 #pragma unroll
     for (int j = 0; j < PH; j++) ln[j] = hd[j] ? segs[hd[j] - 1].len : 0u;
+    uint32_t en = 0, ml = 0;
 #pragma unroll
     for (int j = 0; j < PH; j++) {
       const uint32_t i = j * NT + threadIdx.x;
       if (hd[j]) {
         mark[i] = hd[j];
-        atomicMax(s_n, i + ln[j]);
-        atomicMax(s_maxlen, ln[j]);
+        en = max(en, i + ln[j]);
+        ml = max(ml, ln[j]);
       }
+    }
+    // one LDS atomic per wave (same-address atomics serialize)
+    en = wave_max(en);
+    ml = wave_max(ml);
+    if (lane() == 0) {
+      atomicMax(s_n, en);
+      atomicMax(s_maxlen, ml);
     }
   }
   __syncthreads();
@@ -719,6 +730,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   // further up); keys compare equal inside a segment exactly when key2 does.
   const bool counting = s_maxlen <= COUNT_SORT_MAX;
   if (counting) {
+    const uint32_t ml = s_maxlen;
     uint32_t dst[PI], kv[PI], vv[PI];
 #pragma unroll
     for (int j = 0; j < PI; j++) {
@@ -728,9 +740,15 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
         const uint32_t sp = segp[p];
         const uint32_t me = skey[p];
         uint32_t r = 0;
-        for (uint32_t q = sp; q < n && (q == sp || mark[q] == 0); q++) {
-          const uint32_t o = skey[q];
-          r += (o < me || (o == me && q < p)) ? 1u : 0u;
+        // a fixed count of steps (the tile's longest segment), so the LDS
+        // reads do not wait on the end test of the step before
+        bool in = true;
+#pragma unroll 8
+        for (uint32_t i = 0; i < ml; i++) {
+          const uint32_t q = sp + i, qq = min(q, SMALL_CAP - 1u);
+          const uint32_t o = skey[qq], mq = mark[qq];
+          in = in && q < n && (i == 0 || mq == 0);
+          r += (in && (o < me || (o == me && q < p))) ? 1u : 0u;
         }
         dst[j] = sp + r;
         kv[j] = me;
@@ -817,6 +835,13 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     rr[i] = SegRec{0, 0, 0, 0};
     if (p < n && segp[p] != NO_SEG) rr[i] = segs[mark[segp[p]] - 1];
   }
+  // and their blocks' bounds, also loaded together
+  uint32_t bo[PI], be[PI];
+#pragma unroll
+  for (int i = 0; i < PI; i++) {
+    bo[i] = blk_off[rr[i].blk];
+    be[i] = blk_off[rr[i].blk + 1];
+  }
 #pragma unroll
   for (int i = 0; i < PI; i++) {
     uint32_t p = p0 + i;
@@ -829,13 +854,15 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     uint32_t headk = r.start + (hp - 1 - sp);
     uint32_t v = sval[p];
     SA[k] = v;
-    rank[v] = headk;
+    // rank rounds: rows of the segment's first group keep the rank they have
+    // (the segment's start), so only the other groups' rows are written
+    if (text_mode || hp - 1 != sp) rank[v] = headk;
     bool end = (p + 1 == sp + r.len) || skey[p + 1] != skey[p];
     if (end) {
       uint32_t len = p + 1 - (hp - 1);
-      uint32_t nbk = blk_off[r.blk + 1] - blk_off[r.blk];
+      const uint32_t nbk = be[i] - bo[i];
       // closed group (see k_rename_b): equal rotations, final
-      const bool closed = !text_mode && len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - blk_off[r.blk];
+      const bool closed = !text_mode && len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - bo[i];
       if (len >= 2 && h_next < nbk && !closed) {
 #pragma unroll
         for (int q = 0; q < PI / 2 + 1; q++)  // register-resident append

@@ -36,6 +36,7 @@ struct BlockTables {
 constexpr uint32_t ASSIGN_GROUPS = 512;      // selector groups per assign tile
 constexpr uint32_t ASSIGN_SUB = NT;          // groups staged in LDS at a time
 constexpr uint32_t ASSIGN_SYMS = ASSIGN_SUB * GROUP;
+constexpr uint32_t SEL_CHUNK = 18432;        // selectors staged in LDS at a time
 
 struct HuffScratch {
   uint32_t w[MAXA];
@@ -398,27 +399,27 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
   __shared__ uint8_t lens[MAXG][MAXA];
   __shared__ uint32_t s_first[MAXG][MAXLEN + 2];
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  __shared__ int shi[NT / BZG_WAVE + 1];
-  __shared__ int sx[NT];
   const uint32_t b = blockIdx.x;
   const uint32_t tid = threadIdx.x;
   BlockTables* T = &tabs[b];
   const int G = (int)T->G, a = (int)T->alpha;
   const uint32_t nsel = T->nsel;
   const uint64_t sb = sel_base[b];
+  __shared__ uint32_t lcnt[MAXG][MAXLEN + 2];
+  for (uint32_t i = tid; i < MAXG * (MAXLEN + 2); i += NT) (&lcnt[0][0])[i] = 0;
+  stage_to_lds<NT, 8>(&lens[0][0], &T->len[0][0], (uint32_t)(G * MAXA));
+  __syncthreads();
+  // canonical codes: per table, the first code of every length
   for (int i = tid; i < G * MAXA; i += NT) {
-    int t = i / MAXA, v = i % MAXA;
-    if (v < a) lens[t][v] = T->len[t][v];
+    const int t = i / MAXA, v = i % MAXA;
+    if (v < a) atomicAdd(&lcnt[t][lens[t][v]], 1u);
   }
   __syncthreads();
   if (tid < (uint32_t)G) {
-    uint32_t cnt[MAXLEN + 2];
-    for (int q = 0; q <= MAXLEN + 1; q++) cnt[q] = 0;
-    for (int v = 0; v < a; v++) cnt[lens[tid][v]]++;
     uint32_t code = 0;
     for (int q = 1; q <= MAXLEN; q++) {
       s_first[tid][q] = code;
-      code = (code + cnt[q]) << 1;
+      code = (code + lcnt[tid][q]) << 1;
     }
   }
   __syncthreads();
@@ -431,30 +432,68 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
       T->code[t][v] = s_first[t][L] + r;
     }
   }
-  // selector MTF indices: thread-contiguous ranges, prefix-max of last use
-  const uint32_t per = (nsel + NT - 1) / NT;
-  const uint32_t g0 = min(tid * per, nsel), g1 = min(g0 + per, nsel);
-  int lastv[MAXG];
-  for (int v = 0; v < MAXG; v++) lastv[v] = -1 - v;  // initial list 0..G-1, 0 most recent
-  int loc[MAXG];
-  for (int v = 0; v < MAXG; v++) loc[v] = INT_MIN;
-  for (uint32_t g = g0; g < g1; g++) loc[sel[sb + g]] = (int)g;
-  for (int v = 0; v < MAXG; v++) {
-    int incl = block_incl_max<int, NT>(loc[v], shi, INT_MIN);
-    sx[tid] = incl;
-    __syncthreads();
-    int ex = tid ? sx[tid - 1] : INT_MIN;
-    if (ex > lastv[v]) lastv[v] = ex;
-    __syncthreads();
-  }
+  // selector MTF indices, SEL_CHUNK selectors at a time staged in LDS:
+  // thread-contiguous ranges; a table's rank in the list at a selector is the
+  // number of tables used more recently, so each thread starts from the
+  // prefix-max of last uses before its range (carried across chunks).  The
+  // per-table arrays are indexed by unrolled loops only (no lane-varying
+  // register index).
+  __shared__ uint8_t ssel[SEL_CHUNK];
+  __shared__ int swl[NT / BZG_WAVE][MAXG];
+  const int w = (int)(tid / BZG_WAVE);
+  int carry[MAXG];
+#pragma unroll
+  for (int v = 0; v < MAXG; v++) carry[v] = -1 - v;  // initial list 0..G-1, 0 most recent
   uint32_t sbits = 0;
-  for (uint32_t g = g0; g < g1; g++) {
-    int x = sel[sb + g];
-    uint32_t idx = 0;
-    for (int v = 0; v < G; v++) idx += (v != x && lastv[v] > lastv[x]) ? 1u : 0u;
-    selmtf[sb + g] = (uint8_t)idx;
-    lastv[x] = (int)g;
-    sbits += idx + 1;
+  for (uint32_t c0 = 0; c0 < nsel; c0 += SEL_CHUNK) {
+    const uint32_t cn = min(SEL_CHUNK, nsel - c0);
+    __syncthreads();
+    stage_to_lds<NT, 8>(ssel, sel + sb + c0, cn);
+    __syncthreads();
+    const uint32_t per = (cn + NT - 1) / NT;
+    const uint32_t g0 = min(tid * per, cn), g1 = min(g0 + per, cn);
+    int loc[MAXG], lastv[MAXG];
+#pragma unroll
+    for (int v = 0; v < MAXG; v++) loc[v] = INT_MIN;
+    for (uint32_t g = g0; g < g1; g++) {
+      const int x = ssel[g];
+#pragma unroll
+      for (int v = 0; v < MAXG; v++) loc[v] = x == v ? (int)(c0 + g) : loc[v];
+    }
+    // one workgroup prefix-max of all tables' last uses
+#pragma unroll
+    for (int v = 0; v < MAXG; v++) loc[v] = wave_incl_max(loc[v]);
+    if (lane() == BZG_WAVE - 1) {
+#pragma unroll
+      for (int v = 0; v < MAXG; v++) swl[w][v] = loc[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < MAXG; v++) {
+      int before = INT_MIN, all = INT_MIN;
+      for (int q = 0; q < NT / BZG_WAVE; q++) {
+        before = q < w ? max(before, swl[q][v]) : before;
+        all = max(all, swl[q][v]);
+      }
+      const int up = __shfl_up(loc[v], 1, BZG_WAVE);
+      lastv[v] = max(carry[v], max(before, lane() ? up : INT_MIN));
+      carry[v] = max(carry[v], all);
+    }
+    for (uint32_t g = g0; g < g1; g++) {
+      const int x = ssel[g];
+      int lx = 0;
+#pragma unroll
+      for (int v = 0; v < MAXG; v++) lx = x == v ? lastv[v] : lx;
+      uint32_t idx = 0;
+#pragma unroll
+      for (int v = 0; v < MAXG; v++) idx += (v < G && v != x && lastv[v] > lx) ? 1u : 0u;
+      ssel[g] = (uint8_t)idx;  // only this thread reads position g
+#pragma unroll
+      for (int v = 0; v < MAXG; v++) lastv[v] = x == v ? (int)(c0 + g) : lastv[v];
+      sbits += idx + 1;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cn; i += NT) selmtf[sb + c0 + i] = ssel[i];
   }
   // delta-coded lengths: 2|d| + 1 bits per symbol, 5 per table
   for (int i = tid; i < G * MAXA; i += NT) {

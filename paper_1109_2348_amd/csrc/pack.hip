@@ -25,6 +25,9 @@ struct BlockTables {  // mirror of the layout in huff.hip
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
+constexpr uint32_t SEL_CHUNK = 8192;                         // selectors staged in LDS at a time
+constexpr uint32_t SEL_WORDS = (SEL_CHUNK * MAXG + 31) / 32 + 2;  // their unary codes, 32-bit words
+
 // OR the low n (<= 32) bits of v into the stream at bit position pos.
 __device__ __forceinline__ void put_bits(uint32_t* words, uint64_t pos, uint32_t v, uint32_t n) {
   if (n == 0) return;
@@ -153,20 +156,48 @@ __global__ __launch_bounds__(NT) void k_pack_header(const BlockTables* __restric
     put_bits(words, pos + 3, nsel, 15);
   }
   pos += 18;
-  // selectors: thread-contiguous ranges
-  const uint32_t per = (nsel + NT - 1) / NT;
-  const uint32_t g0 = min(threadIdx.x * per, nsel), g1 = min(g0 + per, nsel);
+  // selectors in unary (idx ones, then a zero), SEL_CHUNK at a time: staged
+  // in LDS, coded into LDS words (thread-contiguous ranges), written out
+  // coalesced; only a chunk's first and last words are shared with others
   const uint8_t* M = selmtf + sel_base[b];
-  uint64_t mine = 0;
-  for (uint32_t g = g0; g < g1; g++) mine += M[g] + 1u;
-  uint64_t tot;
-  uint64_t p = pos + block_excl_sum<uint64_t, NT>(mine, sh, &tot);
-  for (uint32_t g = g0; g < g1; g++) {
-    uint32_t n = M[g] + 1u;
-    put_bits(words, p, (1u << n) - 2u, n);
-    p += n;
+  __shared__ uint8_t sM[SEL_CHUNK];
+  __shared__ uint32_t sw[SEL_WORDS];
+  for (uint32_t c0 = 0; c0 < nsel; c0 += SEL_CHUNK) {
+    const uint32_t cn = min(SEL_CHUNK, nsel - c0);
+    __syncthreads();
+    stage_to_lds<NT, 8>(sM, M + c0, cn);
+    for (uint32_t i = threadIdx.x; i < SEL_WORDS; i += NT) sw[i] = 0;
+    __syncthreads();
+    const uint32_t per = (cn + NT - 1) / NT;
+    const uint32_t g0 = min(threadIdx.x * per, cn), g1 = min(g0 + per, cn);
+    uint64_t mine = 0;
+    for (uint32_t g = g0; g < g1; g++) mine += sM[g] + 1u;
+    uint64_t tot;
+    const uint32_t off = (uint32_t)(pos & 31);
+    uint32_t p = off + (uint32_t)block_excl_sum<uint64_t, NT>(mine, sh, &tot);
+    for (uint32_t g = g0; g < g1; g++) {
+      const uint32_t n = sM[g] + 1u, v = (1u << n) - 2u, o = p & 31u;  // n <= MAXG
+      if (o + n <= 32) {
+        atomicOr(&sw[p >> 5], v << (32 - o - n));
+      } else {
+        atomicOr(&sw[p >> 5], v >> (o + n - 32));
+        atomicOr(&sw[(p >> 5) + 1], v << (64 - o - n));
+      }
+      p += n;
+    }
+    __syncthreads();
+    const uint32_t nw = (uint32_t)((off + tot + 31) / 32);
+    const uint64_t W0 = pos >> 5;
+    for (uint32_t i = threadIdx.x; i < nw; i += NT) {
+      const uint32_t v = sw[i];
+      if (i == 0 || i + 1 == nw) {
+        if (v) atomicOr(&words[W0 + i], bswap32(v));
+      } else {
+        words[W0 + i] = bswap32(v);
+      }
+    }
+    pos += tot;
   }
-  pos += tot;
   // code lengths, one table after another
   for (uint32_t t = 0; t < G; t++) {
     if (threadIdx.x == 0) put_bits(words, pos, T->len[t][0], 5);
