@@ -487,10 +487,11 @@ constexpr uint16_t NO_SEG = 0xFFFFu;
 
 // Loads a small tile's segment map: mark[p] = segment index + 1 at each
 // segment's first position, segp[p] = first position of p's segment;
-// *s_maxlen gets the longest segment.
+// *s_maxlen gets the longest segment; send (optional) gets each segment's end
+// at its first position.
 __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head, const SegRec* __restrict__ segs,
                                    uint32_t small_total, uint32_t* mark, uint16_t* segp, uint32_t* sh,
-                                   uint32_t* s_n, uint32_t* s_maxlen) {
+                                   uint32_t* s_n, uint32_t* s_maxlen, uint16_t* send = nullptr) {
   for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) mark[p] = 0;
   if (threadIdx.x == 0) {
     *s_n = 0;
@@ -514,6 +515,7 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
       const uint32_t i = j * NT + threadIdx.x;
       if (hd[j]) {
         mark[i] = hd[j];
+        if (send) send[i] = (uint16_t)(i + ln[j]);  // end of the segment starting at i
         en = max(en, i + ln[j]);
         ml = max(ml, ln[j]);
       }
@@ -676,7 +678,26 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   __shared__ uint32_t wg_base[4];
   const uint32_t small_total = cnt->small_total();
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n, &s_maxlen);
+  const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n, &s_maxlen, sseg);
+  // Tiles whose segments are all short are ordered by counting (below); they
+  // keep the segment ends in sseg, which the radix passes use otherwise.
+  const bool counting = s_maxlen <= COUNT_SORT_MAX;
+  constexpr int PI = SMALL_CAP / NT;  // 8
+  // The naming at the end needs the segment record and block bounds of
+  // each of this thread's positions there (PI consecutive ones): loaded
+  // now, so that their latency passes during the loads and the sort.
+  // (records with the loads' first stage, block bounds after their second)
+  SegRec rr[PI];
+  uint32_t bo[PI], be[PI];
+  {
+    const uint32_t p0 = threadIdx.x * PI;
+#pragma unroll
+    for (int i = 0; i < PI; i++) {
+      const uint32_t p = p0 + i;
+      rr[i] = SegRec{0, 0, 0, 0};
+      if (p < n && segp[p] != NO_SEG) rr[i] = segs[mark[segp[p]] - 1];
+    }
+  }
   // load (segment start << 21 | key2, SA value).  Positions before the
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
@@ -700,20 +721,22 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
       k2[j] = key2[kk[j]];
       vv[j] = SA[kk[j]];
     }
+    __builtin_amdgcn_sched_barrier(0);  // issue order: these loads stay after the rows'
+#pragma unroll
+    for (int i = 0; i < PI; i++) {
+      bo[i] = blk_off[rr[i].blk];
+      be[i] = blk_off[rr[i].blk + 1];
+    }
+    // (selects, not branches: a load used only under a branch would be
+    // moved into it and waited for there)
 #pragma unroll
     for (int j = 0; j < PL; j++) {
       const uint32_t p = j * NT + threadIdx.x;
-      uint32_t kv = 0xFFFFFFFFu, sv = 0xFFFFu;
-      if (sp[j] != NO_SEG) {
-        kv = text_mode ? k2[j] : (sp[j] << 21) | k2[j];
-        sv = sp[j];
-      } else if (p < n) {  // before the tile's first segment
-        kv = 0;
-        sv = 0;
-      }
-      skey[p] = kv;
-      sval[p] = sp[j] != NO_SEG ? vv[j] : 0u;
-      sseg[p] = (uint16_t)sv;
+      const bool has = sp[j] != NO_SEG, front = !has && p < n;  // front: before the tile's first segment
+      const uint32_t kr = text_mode ? k2[j] : (sp[j] << 21) | k2[j];
+      skey[p] = has ? kr : front ? 0u : 0xFFFFFFFFu;
+      sval[p] = has ? vv[j] : 0u;
+      if (!counting) sseg[p] = (uint16_t)(has ? sp[j] : front ? 0u : 0xFFFFu);
     }
   }
   // clear the head entries of this tile for reuse two rounds later
@@ -724,11 +747,9 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   // stable LSD radix sort of the tile in LDS; wave w owns positions
   // [w*1024, (w+1)*1024), item i of lane l is position w*1024 + i*64 + l
   const uint32_t w = threadIdx.x / BZG_WAVE;
-  constexpr int PI = SMALL_CAP / NT;  // 8
-  // Tiles whose segments are all short are ordered by counting, for every
-  // row, the rows of its segment that precede it (smaller key, or equal key
-  // further up); keys compare equal inside a segment exactly when key2 does.
-  const bool counting = s_maxlen <= COUNT_SORT_MAX;
+  // Counting: for every row, the rows of its segment that precede it
+  // (smaller key, or equal key further up); keys compare equal inside a
+  // segment exactly when key2 does.
   if (counting) {
     const uint32_t ml = s_maxlen;
     uint32_t dst[PI], kv[PI], vv[PI];
@@ -739,16 +760,13 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
       if (p < n && segp[p] != NO_SEG) {
         const uint32_t sp = segp[p];
         const uint32_t me = skey[p];
+        const uint32_t len = sseg[sp] - sp, d = p - sp;
         uint32_t r = 0;
-        // a fixed count of steps (the tile's longest segment), so the LDS
-        // reads do not wait on the end test of the step before
-        bool in = true;
+        // a fixed count of steps (the tile's longest segment)
 #pragma unroll 8
         for (uint32_t i = 0; i < ml; i++) {
-          const uint32_t q = sp + i, qq = min(q, SMALL_CAP - 1u);
-          const uint32_t o = skey[qq], mq = mark[qq];
-          in = in && q < n && (i == 0 || mq == 0);
-          r += (in && (o < me || (o == me && q < p))) ? 1u : 0u;
+          const uint32_t o = skey[min(sp + i, SMALL_CAP - 1u)];
+          r += (i < len && (o < me || (o == me && i < d))) ? 1u : 0u;
         }
         dst[j] = sp + r;
         kv[j] = me;
@@ -827,21 +845,6 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
   uint32_t gs[PI / 2 + 1], gl[PI / 2 + 1], gb[PI / 2 + 1];
   int m = 0;
-  // the segment records of this thread's positions, loaded together
-  SegRec rr[PI];
-#pragma unroll
-  for (int i = 0; i < PI; i++) {
-    const uint32_t p = p0 + i;
-    rr[i] = SegRec{0, 0, 0, 0};
-    if (p < n && segp[p] != NO_SEG) rr[i] = segs[mark[segp[p]] - 1];
-  }
-  // and their blocks' bounds, also loaded together
-  uint32_t bo[PI], be[PI];
-#pragma unroll
-  for (int i = 0; i < PI; i++) {
-    bo[i] = blk_off[rr[i].blk];
-    be[i] = blk_off[rr[i].blk + 1];
-  }
 #pragma unroll
   for (int i = 0; i < PI; i++) {
     uint32_t p = p0 + i;
