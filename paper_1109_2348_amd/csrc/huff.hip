@@ -46,17 +46,9 @@ struct HuffScratch {
   uint16_t parent[2 * MAXA];
 };
 
-// Column c (uniform, < 5) of a 5-register wave array.
-__device__ __forceinline__ uint32_t col_read_v(uint32_t c, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
-                                               uint32_t v4) {
-  return c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : c == 3 ? v3 : v4;
-}
-
 // One wave, one Huffman pass over the weights hs->w[0..a): ranks the leaves
 // by (weight, id), runs the two-queue merge and returns the depth of the
-// deepest leaf; parents are left in hs->parent.  Sorted leaf weights, leaf ids
-// and internal node weights/depths live in registers across the wave (5
-// columns of 64) and are read with readlane.  All 64 lanes call it.
+// deepest leaf; parents are left in hs->parent.  All 64 lanes call it.
 __device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
   const int l = (int)lane();
   // (weight, id) as one unique key: weights are symbol counts < 2^22
@@ -90,81 +82,44 @@ __device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
     }
   }
   __builtin_amdgcn_wave_barrier();
-  uint32_t LW0, LW1, LW2, LW3, LW4, OR0, OR1, OR2, OR3, OR4;
-#define BZG_LD(q) \
-  LW##q = (q * 64 + l < a) ? hs->lw[q * 64 + l] : 0u; \
-  OR##q = (q * 64 + l < a) ? hs->order[q * 64 + l] : 0u;
-  BZG_LD(0) BZG_LD(1) BZG_LD(2) BZG_LD(3) BZG_LD(4)
-#undef BZG_LD
-  uint32_t WN0 = 0, WN1 = 0, WN2 = 0, WN3 = 0, WN4 = 0;  // internal node weights
-  uint32_t DN0 = 0, DN1 = 0, DN2 = 0, DN3 = 0, DN4 = 0;  // internal node depths
-  // Leaves and internal nodes are consumed in order, so each queue's current
-  // 64-entry column sits in one register and a pick is a readlane of it:
-  //   cLW/cOR  column li>>6 of the leaf weights / ids,
-  //   cRW/cRD  column ni>>6 of the internal weights / depths, when that
-  //            column is complete (ni>>6 < nn>>6),
-  //   cWW/cWD  column nn>>6 being written; flushed to WN/DN when full.
-  // The 5-column arrays are only touched when an index crosses a column.
-  uint32_t cLW = LW0, cOR = OR0, cRW = 0, cRD = 0, cWW = 0, cWD = 0;
+  // Two-queue merge: leaves by (weight, id) in hs->lw / hs->order, internal
+  // nodes in creation order (their weights never decrease) in hs->w / hs->key
+  // (free after the ranking).  Each step reads both heads of both queues in
+  // one batch of LDS reads (clamped indices, empty queues read as infinite)
+  // and picks the two smallest with selects, leaves first on ties.  Lane 0
+  // writes; all lanes read the same words.
+  uint32_t* const wn = hs->w;
+  uint32_t* const dn = hs->key;
+  const uint32_t A_ = (uint32_t)a, INF = 0xFFFFFFFFu;
   uint32_t li = 0, ni = 0, nn = 0, dmax = 0;
-  uint32_t lw_head = (uint32_t)__builtin_amdgcn_readlane((int)cLW, 0);
-  uint32_t wn_head = 0;
-  for (int step = 0; step < a - 1; step++) {
-    uint32_t wsum = 0, dnew = 0, ids[2];
-#pragma unroll
-    for (int pick = 0; pick < 2; pick++) {
-      const bool leaf = li < (uint32_t)a && (ni >= nn || lw_head <= wn_head);  // leaf ids sort first
-      if (leaf) {
-        ids[pick] = (uint32_t)__builtin_amdgcn_readlane((int)cOR, (int)(li & 63));
-        wsum += lw_head;
-        li++;
-        if ((li & 63) == 0 && li < (uint32_t)a) {
-          cLW = col_read_v(li >> 6, LW0, LW1, LW2, LW3, LW4);
-          cOR = col_read_v(li >> 6, OR0, OR1, OR2, OR3, OR4);
-        }
-        lw_head = li < (uint32_t)a ? (uint32_t)__builtin_amdgcn_readlane((int)cLW, (int)(li & 63)) : 0u;
-      } else {
-        ids[pick] = (uint32_t)a + ni;
-        wsum += wn_head;
-        const bool wcol = (ni >> 6) == (nn >> 6);
-        const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)(wcol ? cWD : cRD), (int)(ni & 63));
-        dnew = d > dnew ? d : dnew;
-        ni++;
-        if ((ni & 63) == 0 && (ni >> 6) < (nn >> 6)) {
-          cRW = col_read_v(ni >> 6, WN0, WN1, WN2, WN3, WN4);
-          cRD = col_read_v(ni >> 6, DN0, DN1, DN2, DN3, DN4);
-        }
-        wn_head = ni < nn ? (uint32_t)__builtin_amdgcn_readlane((int)((ni >> 6) == (nn >> 6) ? cWW : cRW),
-                                                                (int)(ni & 63))
-                          : 0u;
-      }
-    }
-    dnew += 1;
-    dmax = dnew;
-    const bool me = (uint32_t)l == (nn & 63);
-    cWW = me ? wsum : cWW;
-    cWD = me ? dnew : cWD;
+  for (uint32_t step = 0; step + 1 < A_; step++) {
+    const uint32_t l0 = min(li, A_ - 1u), l1 = min(li + 1u, A_ - 1u);
+    const uint32_t n0 = min(ni, A_ - 2u), n1 = min(ni + 1u, A_ - 2u);
+    const uint32_t lwa = hs->lw[l0], lwb = hs->lw[l1];
+    const uint32_t ida = hs->order[l0], idb = hs->order[l1];
+    const uint32_t wna = wn[n0], wnb = wn[n1];
+    const uint32_t dna = dn[n0], dnb = dn[n1];
+    const uint32_t A0 = li < A_ ? lwa : INF, A1 = li + 1u < A_ ? lwb : INF;
+    const uint32_t B0 = ni < nn ? wna : INF, B1 = ni + 1u < nn ? wnb : INF;
+    const bool p1 = A0 <= B0;  // first pick is a leaf
+    const uint32_t C = p1 ? A1 : A0, D = p1 ? B0 : B1;
+    const bool p2 = C <= D;    // second pick is a leaf
+    const uint32_t w1 = p1 ? A0 : B0, w2 = p2 ? C : D;
+    const uint32_t d1 = p1 ? 0u : dna, d2 = p2 ? 0u : (p1 ? dna : dnb);
+    const uint32_t id1 = p1 ? ida : A_ + ni;
+    const uint32_t id2 = p2 ? (p1 ? idb : ida) : (p1 ? A_ + ni : A_ + ni + 1u);
+    const uint32_t dnew = max(d1, d2) + 1u;
     if (l == 0) {
-      hs->parent[ids[0]] = (uint16_t)(a + nn);
-      hs->parent[ids[1]] = (uint16_t)(a + nn);
+      hs->parent[id1] = (uint16_t)(A_ + nn);
+      hs->parent[id2] = (uint16_t)(A_ + nn);
+      wn[nn] = w1 + w2;
+      dn[nn] = dnew;
     }
-    if (ni == nn) wn_head = wsum;  // the new node heads an empty internal queue
-    if ((nn & 63) == 63) {  // the write column is full: flush it
-      const uint32_t c = nn >> 6;
-#define BZG_PUT(q) \
-  if (c == q) {    \
-    WN##q = cWW;   \
-    DN##q = cWD;   \
-  }
-      BZG_PUT(0) BZG_PUT(1) BZG_PUT(2) BZG_PUT(3) BZG_PUT(4)
-#undef BZG_PUT
-      // the reader, if it is in this column, now reads the complete copy
-      if ((ni >> 6) == c) {
-        cRW = cWW;
-        cRD = cWD;
-      }
-    }
+    const uint32_t nl = (p1 ? 1u : 0u) + (p2 ? 1u : 0u);
+    li += nl;
+    ni += 2u - nl;
     nn++;
+    dmax = dnew;
   }
   __builtin_amdgcn_wave_barrier();
   return dmax;
