@@ -412,8 +412,10 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
 #pragma unroll
     for (int q = 0; q < RI; q++) {
       const uint32_t i = min(q * NT + threadIdx.x, tn - 1u);
-      a[q] = kin[g.lo + i];
-      b[q] = vin[g.lo + i];
+      // streamed once: non-temporal, so the L2 keeps the rank lines that
+      // this kernel's scattered writes land in
+      a[q] = __builtin_nontemporal_load(&kin[g.lo + i]);
+      b[q] = __builtin_nontemporal_load(&vin[g.lo + i]);
     }
 #pragma unroll
     for (int q = 0; q < RI; q++) {

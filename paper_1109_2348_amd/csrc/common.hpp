@@ -149,7 +149,10 @@ __device__ __forceinline__ void stage_to_lds(T* dst, const T* __restrict__ src, 
 // touch) and realigns them with v_alignbyte; bytes past n are unspecified.
 __device__ __forceinline__ void load16(const uint8_t* p, uint32_t n, uint32_t out[4]) {
   const uintptr_t a = (uintptr_t)p;
-  const uint32_t* w = (const uint32_t*)(a & ~(uintptr_t)3);
+  // global address space: a pointer rebuilt from an integer would otherwise
+  // be loaded through flat instructions, which also hold up LDS waits
+  typedef const uint32_t __attribute__((address_space(1)))* gword;
+  const gword w = (gword)(a & ~(uintptr_t)3);
   const uint32_t sh = (uint32_t)(a & 3u);
   const uint32_t nd = (sh + n + 3u) >> 2;  // dwords holding valid bytes (<= 5)
   uint32_t v[5];

@@ -120,14 +120,28 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
   __syncthreads();
   const uint32_t carry = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
   const uint32_t tile_last = sx[NT - 1];
-  uint32_t lead = 0, inner = 0, rs = carry;
+  // bytes before the tile's first run start; the others' output counts, all
+  // 1 unless some byte is the 4th or later of its run
+  uint32_t lead = 0, inner = 0, rs = carry, tmax = 0;
   pv = prev;
   for (int i = 0; i < cnt; i++) {
-    uint32_t p = p0 + i;
+    const uint32_t p = p0 + i;
     if (p == 0 || v[i] != pv) rs = p + 1;
     pv = v[i];
     if (rs == 0) lead++;
-    else inner += rle_emit_count(p - (rs - 1));
+    else tmax = max(tmax, p - (rs - 1));
+  }
+  if (tmax < 3) {
+    inner = (uint32_t)cnt - lead;
+  } else {
+    rs = carry;
+    pv = prev;
+    for (int i = 0; i < cnt; i++) {
+      const uint32_t p = p0 + i;
+      if (p == 0 || v[i] != pv) rs = p + 1;
+      pv = v[i];
+      if (rs != 0) inner += rle_emit_count(p - (rs - 1));
+    }
   }
   lead = block_sum<uint32_t, NT>(lead, sh);
   inner = block_sum<uint32_t, NT>(inner, sh);
@@ -230,12 +244,29 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   uint32_t rs = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
   rs = rs > carry ? rs : carry;
   uint32_t rs0 = rs;
+  // Run offsets of this thread's bytes.  When none reaches 3 (no byte is the
+  // 4th or later of a run: the common case outside long runs) every byte
+  // emits itself and nothing else, and the per-byte piece logic is skipped.
+  uint32_t tmax = 0;
   pv = prev;
   for (int i = 0; i < cnt; i++) {
-    uint32_t p = p0 + i;
+    const uint32_t p = p0 + i;
     if (p == 0 || v[i] != pv) rs = p + 1;
     pv = v[i];
-    e += rle_emit_count(p - (rs - 1));
+    tmax = max(tmax, p - (rs - 1));
+  }
+  const bool plain = tmax < 3;
+  if (plain) {
+    e = (uint32_t)cnt;
+  } else {
+    rs = rs0;
+    pv = prev;
+    for (int i = 0; i < cnt; i++) {
+      const uint32_t p = p0 + i;
+      if (p == 0 || v[i] != pv) rs = p + 1;
+      pv = v[i];
+      e += rle_emit_count(p - (rs - 1));
+    }
   }
   uint32_t tot;
   // MODE 0 stages the tile's output in LDS (at the global dword alignment)
@@ -251,7 +282,14 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   rs = rs0;
   pv = prev;
   uint32_t below = 0;
-  for (int i = 0; i < cnt; i++) {
+  if (plain) {
+    if (MODE == 0) {
+      for (int i = 0; i < cnt; i++) sout[al + o + i] = v[i];
+    } else {
+      for (int i = 0; i < cnt; i++) below += (tile_off + o + i + 1 <= limit) ? 1u : 0u;
+    }
+  }
+  for (int i = 0; i < (plain ? 0 : cnt); i++) {
     uint32_t p = p0 + i;
     if (p == 0 || v[i] != pv) rs = p + 1;
     pv = v[i];
