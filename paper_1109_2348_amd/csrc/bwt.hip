@@ -116,10 +116,11 @@ __device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, cons
 }
 
 // Per-tile digit counts of one LSD pass: digit = (kin >> shift) & 255.
-// TEXT (the init sort's first pass, shift 0): the digit is byte 3 of each
-// row's first 4 bytes, read from the text (rows are in descending start
-// order, so the read is sequential).  Init segments are whole blocks.
-template <bool TEXT>
+// INIT instantiates the init sort's passes (a kernel of their own for
+// profiling); its first pass (text != null, shift 0) reads the digit, byte 3
+// of each row's first 4 bytes, from the text instead (rows are in descending
+// start order, so the read is sequential).  Init segments are whole blocks.
+template <bool INIT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                    const uint32_t* __restrict__ kin, int shift,
                                                    uint32_t* __restrict__ hist, const uint8_t* __restrict__ text) {
@@ -134,17 +135,23 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   for (uint32_t d = threadIdx.x; d < NC * CS; d += NT) cnt[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
-  const uint32_t o = TEXT ? g.r.start : 0u, n = TEXT ? g.r.len : 0u;
+  const bool from_text = INIT && text != nullptr;
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
   // loads of clamped rows, none under a branch, so all are in flight at once
   uint32_t dg[RI];
+  if (from_text) {
+    const uint32_t o = g.r.start, n = g.r.len;
 #pragma unroll
-  for (int i = 0; i < RI; i++) {
-    const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
-    dg[i] = TEXT ? text[o + cyc(n - 1u - (k - o) + 3u, n)] : kin[k];
+    for (int i = 0; i < RI; i++) {
+      const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
+      dg[i] = text[o + cyc(n - 1u - (k - o) + 3u, n)];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RI; i++) dg[i] = kin[min(wbase + i * BZG_WAVE + lane(), g.hi - 1u)];
+#pragma unroll
+    for (int i = 0; i < RI; i++) dg[i] = (dg[i] >> shift) & 255u;
   }
-#pragma unroll
-  for (int i = 0; i < RI; i++) dg[i] = TEXT ? dg[i] : (dg[i] >> shift) & 255u;
   uint32_t* mine = cnt + (w * 4u + (lane() & 3u)) * CS;
 #pragma unroll
   for (int i = 0; i < RI; i++) {
@@ -167,11 +174,11 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
-// One stable LSD pass: (key, row) pairs move.  TEXT (the init sort's first
-// pass, shift 0): rows come from the row index, in descending start order,
-// and each key is its row's first 4 bytes (big-endian), read sequentially
-// from the text.
-template <bool TEXT>
+// One stable LSD pass: (key, row) pairs move.  INIT instantiates the init
+// sort's passes; in its first (text != null, shift 0) rows come from the row
+// index, in descending start order, and each key is its row's first 4 bytes
+// (big-endian), read sequentially from the text.
+template <bool INIT>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
                                                       const uint32_t* __restrict__ owner,
                                                       const uint32_t* __restrict__ kin,
@@ -184,14 +191,15 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
   BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
-  const uint32_t o = TEXT ? g.r.start : 0u, n = TEXT ? g.r.len : 0u;
+  const bool from_text = INIT && text != nullptr;
   // this tile's output base for digit threadIdx.x, loaded before the rows
   const size_t col0 = (size_t)g.r.base * 256;
   const uint32_t hs_d = hscan[col0 + (size_t)threadIdx.x * g.nt + g.t], hs_0 = hscan[col0];
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
   // loads of clamped rows, none under a branch, so all are in flight at once
   uint32_t key[RI], val[RI], rk[RI];
-  if (TEXT) {
+  if (from_text) {
+    const uint32_t o = g.r.start, n = g.r.len;
     TextWords tw[RI];
 #pragma unroll
     for (int i = 0; i < RI; i++) {
@@ -1016,11 +1024,8 @@ static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs
     const uint32_t* va = p ? vout[p - 1] : nullptr;
     {
       ProfScope ps("init_hist", st, (p ? 4.0 : 1.0) * elems);  // key in (pass 0: one text byte)
-      if (p == 0)
-        hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, 0, w.hist, text);
-      else
-        hipLaunchKernelGGL(k_radix_hist<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
-                           nullptr);
+      hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
+                         p ? nullptr : text);
     }
     {
       ProfScope ps("scan", st, 8.0 * big_tiles * 256);
@@ -1029,12 +1034,8 @@ static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs
     }
     // key and row in and out (pass 0: one text byte in per row)
     ProfScope ps("init_scatter", st, (p ? 16.0 : 9.0) * elems);
-    if (p == 0)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, nullptr, nullptr,
-                         kout[p], vout[p], 0, w.hist, text);
-    else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kout[p],
-                         vout[p], 8 * p, w.hist, nullptr);
+    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kout[p], vout[p],
+                       8 * p, w.hist, p ? nullptr : text);
   }
   return hipGetLastError();
 }
