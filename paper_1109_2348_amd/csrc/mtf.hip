@@ -208,110 +208,194 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   if (threadIdx.x == 0) chunk_nD[c] = s_nd;
 }
 
-// One wave per block: serial over its chunks.  Writes every chunk's incoming
-// stack, carried zero count and output offset, and the block's symbol count.
-__global__ __launch_bounds__(BZG_WAVE) void k_mtf_scan(const uint32_t* blk_chunk0, const uint32_t* __restrict__ inuse,
-                                                       const uint8_t* __restrict__ L, const uint32_t* __restrict__ off,
-                                                       const uint8_t* __restrict__ chunk_D,
-                                                       const uint32_t* __restrict__ chunk_nD,
-                                                       const ZSum* __restrict__ chunk_sum,
-                                                       uint8_t* __restrict__ chunk_list, uint32_t* __restrict__ chunk_carry,
-                                                       uint32_t* __restrict__ chunk_out, uint32_t* __restrict__ nsyms) {
-  __shared__ uint32_t tmp[256];
-  __shared__ uint16_t f[256];
-  const uint32_t b = blockIdx.x;
+// Chunk summaries compose associatively: after chunk X the stack is D_X
+// followed by the rest of the incoming stack in order, and after X then Y it
+// is D_Y, then D_X minus D_Y, then the rest; zero-run summaries compose by
+// zcombine.  So a block's chunks are scanned by SCAN_WAVES waves in three
+// steps: each wave composes the summaries of one contiguous range of chunks;
+// one wave turns those into every range's incoming stack and prefix
+// summary; each wave then walks its range from there.  The serial depth is
+// about 2 * chunks / SCAN_WAVES + SCAN_WAVES steps instead of chunks.
+constexpr int SCAN_WAVES = 8;
+
+// Between the steps of one wave's serial work in LDS (no workgroup barrier:
+// the waves run independent loops).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The wave's stack e (slot j*64 + lane; 0x100 = empty) becomes D (nd bytes,
+// dx) followed by the bytes of e not in D, in their order, then empty slots.
+// e may be partial (a composed summary) and D may hold bytes e lacks.  mem
+// (256, zero on entry and exit) and tmp (256) are this wave's LDS.
+__device__ __forceinline__ void stack_front(uint32_t e[4], const uint32_t dx[4], uint32_t nd, uint8_t* mem,
+                                            uint32_t* tmp) {
   const uint32_t l = lane();
-  uint32_t bm[8];
-  uint32_t nu = 0;
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+    if ((uint32_t)(j * 64) + l < nd) mem[dx[j]] = 1;
+  wave_sync();
+  bool keep[4];
+  uint64_t km[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    keep[j] = e[j] < 256u && mem[e[j]] == 0;
+    km[j] = __ballot(keep[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; j++) tmp[j * 64 + l] = (uint32_t)(j * 64) + l < nd ? dx[j] : 0x100u;
+  wave_sync();
+  uint32_t before = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    if (keep[j]) tmp[nd + before + (uint32_t)__popcll(km[j] & lt)] = e[j];
+    before += (uint32_t)__popcll(km[j]);
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+    if ((uint32_t)(j * 64) + l < nd) mem[dx[j]] = 0;
+  wave_sync();
+}
+
+__device__ __forceinline__ uint32_t zs_carry(const ZSum& p) { return p.all ? p.len : p.tz; }
+__device__ __forceinline__ uint32_t zs_out(const ZSum& p) {
+  return p.all ? 0u : p.nnz + p.inner + run_digits(p.lz);
+}
+
+// One workgroup of SCAN_WAVES waves per block.  Writes every chunk's incoming
+// stack, carried zero count and output offset, and the block's symbol count.
+__global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
+    const uint32_t* blk_chunk0, const uint32_t* __restrict__ inuse, const uint8_t* __restrict__ L,
+    const uint32_t* __restrict__ off, const uint8_t* __restrict__ chunk_D, const uint32_t* __restrict__ chunk_nD,
+    const ZSum* __restrict__ chunk_sum, uint8_t* __restrict__ chunk_list, uint32_t* __restrict__ chunk_carry,
+    uint32_t* __restrict__ chunk_out, uint32_t* __restrict__ nsyms) {
+  __shared__ uint32_t tmp[SCAN_WAVES][256];
+  __shared__ uint8_t mem[SCAN_WAVES][256];
+  __shared__ uint8_t gD[SCAN_WAVES][256];  // each range's composed D (then incoming stack)
+  __shared__ uint32_t gn[SCAN_WAVES];
+  __shared__ ZSum gz[SCAN_WAVES];
+  const uint32_t b = blockIdx.x;
+  const uint32_t l = lane(), w = threadIdx.x / BZG_WAVE;
+  uint32_t bm[8], nu = 0;
   for (int j = 0; j < 8; j++) {
     bm[j] = inuse[b * 8 + j];
     nu += __popc(bm[j]);
   }
-  for (int j = 0; j < 4; j++) tmp[j * 64 + l] = 0x100u;
-  f[l] = 0;
-  f[l + 64] = 0;
-  f[l + 128] = 0;
-  f[l + 192] = 0;
-  __syncthreads();
-  for (int j = 0; j < 4; j++) {
-    uint32_t v = j * 64 + l;
-    if ((bm[v >> 5] >> (v & 31)) & 1u) {
-      uint32_t pos = 0;
-      for (int q = 0; q < (int)(v >> 5); q++) pos += __popc(bm[q]);
-      pos += __popc(bm[v >> 5] & ((1u << (v & 31)) - 1u));
-      tmp[pos] = v;
-    }
-  }
-  __syncthreads();
-  uint32_t e[4];
-  for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
-  __syncthreads();
-  const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1];
+#pragma unroll
+  for (int j = 0; j < 4; j++) mem[w][j * 64 + l] = 0;
+  const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1], nc = c1 - c0;
   // the block's first row: MTF index 0 exactly when it holds the smallest
   // in-use byte (the front of the initial stack)
   uint32_t minb = 0;
   for (int j = 7; j >= 0; j--)
     if (bm[j]) minb = j * 32 + (__ffs(bm[j]) - 1);
-  const bool row0_zero = c0 < c1 && L[off[b]] == minb;
-  uint32_t carry = 0, out = 0;
-  // the next chunk's D_X, its size and summary are loaded one chunk ahead
-  uint32_t nd_n = 0, dx_n[4] = {0, 0, 0, 0};
-  ZSum s_n = {0, 0, 0, 0, 0, 1};
-  if (c0 < c1) {
-    nd_n = chunk_nD[c0];
-    for (int j = 0; j < 4; j++) dx_n[j] = (uint32_t)(j * 64 + l) < nd_n ? chunk_D[(size_t)c0 * 256 + j * 64 + l] : 0u;
-    s_n = chunk_sum[c0];
+  const bool row0_zero = nc && L[off[b]] == minb;
+  const ZSum e0 = row0_zero ? ZSum{1, 1, 0, 0, 1, 1} : ZSum{0, 0, 0, 1, 1, 0};
+  const ZSum zid = {0, 0, 0, 0, 0, 1};
+  // this wave's chunk range
+  const uint32_t per = (nc + SCAN_WAVES - 1) / SCAN_WAVES;
+  const uint32_t r0 = c0 + min(w * per, nc), r1 = c0 + min(w * per + per, nc);
+  auto load_d = [&](uint32_t c, uint32_t dx[4], uint32_t& nd, ZSum& z) {
+    nd = chunk_nD[c];
+#pragma unroll
+    for (int j = 0; j < 4; j++) dx[j] = (uint32_t)(j * 64) + l < nd ? chunk_D[(size_t)c * 256 + j * 64 + l] : 0u;
+    z = chunk_sum[c];
+    if (c == c0) z = zcombine(e0, z);
+  };
+  // step 1: compose the range's summaries (the next chunk's loaded ahead)
+  {
+    uint32_t e[4] = {0x100u, 0x100u, 0x100u, 0x100u};
+    ZSum zg = zid;
+    uint32_t dn[4] = {0, 0, 0, 0}, ndn = 0;
+    ZSum zn = zid;
+    if (r0 < r1) load_d(r0, dn, ndn, zn);
+    for (uint32_t c = r0; c < r1; c++) {
+      uint32_t dx[4] = {dn[0], dn[1], dn[2], dn[3]};
+      const uint32_t nd = ndn;
+      const ZSum z = zn;
+      if (c + 1 < r1) load_d(c + 1, dn, ndn, zn);
+      stack_front(e, dx, nd, mem[w], tmp[w]);
+      zg = zcombine(zg, z);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) gD[w][j * 64 + l] = (uint8_t)(e[j] & 255u);
+    uint32_t cnt = 0;  // the composed D's length: its non-empty slots
+#pragma unroll
+    for (int j = 0; j < 4; j++) cnt += (uint32_t)__popcll(__ballot(e[j] < 256u));
+    if (l == 0) {
+      gn[w] = cnt;
+      gz[w] = zg;
+    }
   }
-  for (uint32_t c = c0; c < c1; c++) {
-    const uint32_t nd = nd_n;
-    uint32_t dx[4] = {dx_n[0], dx_n[1], dx_n[2], dx_n[3]};
-    ZSum s = s_n;
-    if (c + 1 < c1) {
-      nd_n = chunk_nD[c + 1];
-      for (int j = 0; j < 4; j++)
-        dx_n[j] = (uint32_t)(j * 64 + l) < nd_n ? chunk_D[(size_t)(c + 1) * 256 + j * 64 + l] : 0u;
-      s_n = chunk_sum[c + 1];
-    }
-    if (c == c0) {
-      const ZSum e0 = row0_zero ? ZSum{1, 1, 0, 0, 1, 1} : ZSum{0, 0, 0, 1, 1, 0};
-      s = zcombine(e0, s);
-    }
-    for (int j = 0; j < 4; j++) chunk_list[(size_t)c * 256 + j * 64 + l] = (uint8_t)(e[j] & 255u);
-    for (int j = 0; j < 4; j++)
-      if ((uint32_t)(j * 64 + l) < nd) f[dx[j]] = (uint16_t)(j * 64 + l + 1);
-    __syncthreads();
-    uint32_t isd[4];
-    uint64_t nd_mask[4];
+  __syncthreads();
+  // step 2: wave 0 runs the ranges' summaries from the initial stack (the
+  // in-use bytes ascending); gD[q] becomes range q's incoming stack and gz[q]
+  // its prefix summary
+  if (w == 0) {
+    uint32_t e[4];
+#pragma unroll
     for (int j = 0; j < 4; j++) {
-      isd[j] = e[j] < 256u ? f[e[j]] : 0u;
-      nd_mask[j] = __ballot(isd[j] == 0);
+      const uint32_t v = j * 64 + l;
+      e[j] = 0x100u;
+      if ((bm[v >> 5] >> (v & 31)) & 1u) {
+        uint32_t pos = 0;
+        for (int q = 0; q < (int)(v >> 5); q++) pos += __popc(bm[q]);
+        pos += __popc(bm[v >> 5] & ((1u << (v & 31)) - 1u));
+        tmp[0][pos] = v;
+      }
     }
-    uint32_t before = 0;
-    for (int j = 0; j < 4; j++) {
-      uint32_t np = isd[j] ? isd[j] - 1 : nd + before + __popcll(nd_mask[j] & lanemask_lt());
-      before += __popcll(nd_mask[j]);
-      tmp[np] = e[j];
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 4; j++) e[j] = (uint32_t)(j * 64) + l < nu ? tmp[0][j * 64 + l] : 0x100u;
+    wave_sync();
+    ZSum p = zid;
+    for (int q = 0; q < SCAN_WAVES; q++) {
+      uint32_t dx[4];
+      const uint32_t nd = gn[q];
+#pragma unroll
+      for (int j = 0; j < 4; j++) dx[j] = gD[q][j * 64 + l];
+      const ZSum zq = gz[q];
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < 4; j++) gD[q][j * 64 + l] = (uint8_t)(e[j] & 255u);
+      if (l == 0) gz[q] = p;
+      stack_front(e, dx, nd, mem[0], tmp[0]);
+      p = zcombine(p, zq);
     }
-    __syncthreads();
-    for (int j = 0; j < 4; j++) e[j] = tmp[j * 64 + l];
-    for (int j = 0; j < 4; j++)
-      if ((uint32_t)(j * 64 + l) < nd) f[dx[j]] = 0;
-    __syncthreads();
-    uint32_t cnt;
-    if (l == 0) chunk_carry[c] = carry;
-    if (s.all) {
-      cnt = 0;
-      carry += s.len;
-    } else {
-      cnt = s.nnz + s.inner + run_digits(carry + s.lz);
-      carry = s.tz;
-    }
-    if (c + 1 == c1) cnt += run_digits(carry) + 1;  // flush and end of block
-    if (l == 0) chunk_out[c] = out;
-    out += cnt;
+    // flush of the last zero run, end of block (no symbols for an empty block)
+    if (l == 0) nsyms[b] = nc ? zs_out(p) + run_digits(zs_carry(p)) + 1u : 0u;
   }
-  if (l == 0) nsyms[b] = out;
-  (void)nu;
+  __syncthreads();
+  // step 3: every wave walks its range from its incoming stack and summary
+  {
+    uint32_t e[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) e[j] = (uint32_t)(j * 64) + l < nu ? (uint32_t)gD[w][j * 64 + l] : 0x100u;
+    ZSum p = gz[w];
+    uint32_t dn[4] = {0, 0, 0, 0}, ndn = 0;
+    ZSum zn = zid;
+    if (r0 < r1) load_d(r0, dn, ndn, zn);
+    for (uint32_t c = r0; c < r1; c++) {
+      uint32_t dx[4] = {dn[0], dn[1], dn[2], dn[3]};
+      const uint32_t nd = ndn;
+      const ZSum z = zn;
+      if (c + 1 < r1) load_d(c + 1, dn, ndn, zn);
+#pragma unroll
+      for (int j = 0; j < 4; j++) chunk_list[(size_t)c * 256 + j * 64 + l] = (uint8_t)(e[j] & 255u);
+      if (l == 0) {
+        chunk_carry[c] = zs_carry(p);
+        chunk_out[c] = zs_out(p);
+      }
+      stack_front(e, dx, nd, mem[w], tmp[w]);
+      p = zcombine(p, z);
+    }
+  }
 }
 
 // Stack column j of the wave: slot j*64 + lane.  A DPP wave_shr:1 moves every
@@ -652,7 +736,7 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   }
   {
     ProfScope ps("mtf_scan", st, 512.0 * nc);
-    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d_blk_chunk0, inuse, L, d_off, d_D, d_nD, d_sum,
+    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, d_blk_chunk0, inuse, L, d_off, d_D, d_nD, d_sum,
                        d_list, d_carry, d_out, nsyms);
   }
   {
