@@ -33,9 +33,9 @@ hipError_t mtf_run(const uint8_t*, const uint32_t*, const std::vector<uint32_t>&
 size_t block_tables_bytes();
 hipError_t huff_run(uint32_t, const uint16_t*, const uint64_t*, const uint32_t*, uint32_t*, bool, const uint32_t*,
                     const uint64_t*, uint8_t*, uint8_t*, uint64_t*, void*, uint32_t*, uint32_t, const uint32_t*,
-                    const uint32_t*, void*, hipStream_t);
+                    const uint32_t*, uint32_t, void*, hipStream_t);
 size_t huff_workspace_bytes(uint32_t nb);
-uint32_t huff_assign_groups();
+uint32_t huff_assign_groups(uint64_t ng);
 hipError_t pack_layout(uint32_t, uint32_t, const uint32_t*, const uint64_t*, const void*, int, const uint64_t*,
                        uint64_t*, const uint32_t*, uint64_t*, hipStream_t);
 hipError_t zero_streams(uint32_t, uint64_t, const uint64_t*, const uint64_t*, uint32_t*, hipStream_t);
@@ -422,7 +422,8 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   for (uint32_t k = 0; k <= n_blocks; k++) obyte[k] = h_out_offsets[k];
   std::vector<uint32_t> tile_blk, blk_tile0, atile_blk, ablk_tile0;
   group_tiles(selb, n_blocks, PACK_GROUPS, tile_blk, blk_tile0);
-  group_tiles(selb, n_blocks, huff_assign_groups(), atile_blk, ablk_tile0);
+  const uint32_t atg = huff_assign_groups(ng);
+  group_tiles(selb, n_blocks, atg, atile_blk, ablk_tile0);
   const uint32_t ntiles = (uint32_t)tile_blk.size(), natiles = (uint32_t)atile_blk.size();
   size_t need = sz<uint64_t>(n_blocks) * 2 + sz<uint64_t>(n_blocks + 1) * 2 + sz<uint32_t>((size_t)n_blocks * MAXA) +
                 sz<uint8_t>(ng + 1) * 2 + sz<uint64_t>(ng + 1) * 2 + sz<uint64_t>(scan_tmp_elems(ng + 1)) +
@@ -463,7 +464,7 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
   HIPX(huff_run(n_blocks, d_syms, d_sbase, d_nsyms, d_freq, true, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
-                d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, d_hws, st));
+                d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
   HIPX(body_sizes(n_blocks, d_tabs, d_obyte, d_nbits, d_err, st));
   HIPX(pack_layout(n_blocks, 1, nullptr, nullptr, d_tabs, 1, d_obyte, d_blkbit, nullptr, d_info, st));
@@ -669,7 +670,8 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   selb[nb] = ng;
   std::vector<uint32_t> ptile_blk, pblk_tile0, atile_blk, ablk_tile0;
   group_tiles(selb, nb, PACK_GROUPS, ptile_blk, pblk_tile0);
-  group_tiles(selb, nb, huff_assign_groups(), atile_blk, ablk_tile0);
+  const uint32_t atg = huff_assign_groups(ng);
+  group_tiles(selb, nb, atg, atile_blk, ablk_tile0);
   const uint32_t nptiles = (uint32_t)ptile_blk.size(), natiles = (uint32_t)atile_blk.size();
   size_t bwt_ws = bwt_workspace_bytes(N, nb);
   size_t need0 = sz<uint8_t>(N + 64) * 2 + sz<uint32_t>(nb) + sz<uint16_t>((size_t)N + nb + 64) + sz<uint64_t>(nb) +
@@ -734,7 +736,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   if (natiles) HIPX(hipMemcpyAsync(d_atile_blk, atile_blk.data(), natiles * 4, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
   HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,
-                natiles, d_atile_blk, d_ablk_tile0, d_hws, st));
+                natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
   HIPX(hipMemcpyAsync(d_rb, rb.data(), (n_req + 1) * 4, hipMemcpyHostToDevice, st));
   HIPX(hipMemcpyAsync(d_rout, out_off, n_req * 8, hipMemcpyHostToDevice, st));

@@ -33,7 +33,8 @@ struct BlockTables {
   uint32_t code[MAXG][MAXA];
 };
 
-constexpr uint32_t ASSIGN_GROUPS = 512;      // selector groups per assign tile
+constexpr uint32_t ASSIGN_GROUPS = 512;      // selector groups per assign tile (large calls)
+constexpr uint32_t ASSIGN_GROUPS_SMALL = 128;  // ... for calls that would not fill the GPU with 512
 constexpr uint32_t ASSIGN_SUB = NT;          // groups staged in LDS at a time
 constexpr uint32_t ASSIGN_SYMS = ASSIGN_SUB * GROUP;
 constexpr uint32_t SEL_CHUNK = 18432;        // selectors staged in LDS at a time
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
   for (int i = threadIdx.x; i < MAXG * MAXA; i += NT) tf[(size_t)b * MAXG * MAXA + i] = 0;
 }
 
-// Tile of ASSIGN_GROUPS groups of one block.  mode 0: choose tables and count
+// Tile of tg groups of one block.  mode 0: choose tables and count
 // symbols per table; mode 1: data bits of every group under the final tables.
 __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __restrict__ tile_blk,
                                                     const uint32_t* __restrict__ blk_tile0,
@@ -213,7 +214,8 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
                                                     const uint32_t* __restrict__ nsyms,
                                                     const uint64_t* __restrict__ sel_base, uint8_t* __restrict__ sel,
                                                     const uint64_t* __restrict__ cost, uint32_t* __restrict__ tf,
-                                                    uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs) {
+                                                    uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs,
+                                                    uint32_t tg) {
   __shared__ uint16_t st[ASSIGN_SYMS];
   __shared__ uint64_t sc[MAXA];
   __shared__ uint32_t stf[MAXG][MAXA];
@@ -223,9 +225,9 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
   const uint32_t b = tile_blk[j];
   BlockTables* T = &tabs[b];
   const uint32_t nsel = T->nsel, G = T->G, a = T->alpha;
-  const uint32_t g0 = (j - blk_tile0[b]) * ASSIGN_GROUPS;
+  const uint32_t g0 = (j - blk_tile0[b]) * tg;
   if (g0 >= nsel) return;
-  const uint32_t g1 = min(g0 + ASSIGN_GROUPS, nsel);
+  const uint32_t g1 = min(g0 + tg, nsel);
   const uint32_t ns = nsyms[b];
   const uint16_t* S = syms + sym_base[b];
   const uint64_t sb = sel_base[b];
@@ -500,7 +502,8 @@ size_t huff_workspace_bytes(uint32_t nb) {
 hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
                     uint32_t* freq, bool count_freq, const uint32_t* inuse, const uint64_t* sel_base, uint8_t* sel,
                     uint8_t* selmtf, uint64_t* gbits, void* tabs_v, uint32_t* err, uint32_t ntiles,
-                    const uint32_t* tile_blk, const uint32_t* blk_tile0, void* ws, hipStream_t st) {
+                    const uint32_t* tile_blk, const uint32_t* blk_tile0, uint32_t tile_groups, void* ws,
+                    hipStream_t st) {
   if (!nb) return hipSuccess;
   BlockTables* tabs = (BlockTables*)tabs_v;
   uint64_t* cost = (uint64_t*)ws;
@@ -515,7 +518,7 @@ hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base,
     if (ntiles) {
       ProfScope ps("huff_assign", st, 0.0);
       hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 0, tile_blk, blk_tile0, syms, sym_base, nsyms,
-                         sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
+                         sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs, tile_groups);
     }
     ProfScope ps("huff_build", st, 0.0);
     hipLaunchKernelGGL(k_huff_build, dim3(nb, MAXG), dim3(BUILD_NT), 0, st, tabs, tf);
@@ -523,13 +526,15 @@ hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base,
   if (ntiles) {
     ProfScope ps("huff_assign", st, 0.0);
     hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 1, tile_blk, blk_tile0, syms, sym_base, nsyms,
-                       sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs);
+                       sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs, tile_groups);
   }
   ProfScope ps("huff_finish", st, 0.0);
   hipLaunchKernelGGL(k_huff_finish, dim3(nb), dim3(NT), 0, st, inuse, sel_base, (const uint8_t*)sel, selmtf, tabs);
   return hipGetLastError();
 }
 
-uint32_t huff_assign_groups() { return ASSIGN_GROUPS; }
+// Groups per assign tile for a call with ng groups in all: smaller tiles
+// when the large ones would leave most of the GPU idle.
+uint32_t huff_assign_groups(uint64_t ng) { return ng >= 1024ull * ASSIGN_GROUPS ? ASSIGN_GROUPS : ASSIGN_GROUPS_SMALL; }
 
 }  // namespace bzg
