@@ -674,8 +674,10 @@ constexpr uint32_t COUNT_SORT_MAX = 32;
 __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
                                                    const RoundCounters* cnt, const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
-                                                   uint32_t* __restrict__ rank, uint32_t h_next, int text_mode,
-                                                   AppendCtx app) {
+                                                   uint32_t* __restrict__ rank, uint32_t h_next,
+                                                   const uint8_t* __restrict__ text, AppendCtx app) {
+  const bool text_mode = text != nullptr;
+  const uint32_t h = h_next / 2;
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t skey[SMALL_CAP];
@@ -717,19 +719,37 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     // (positions without a row load from row 0 of segment 0: no load sits
     // under a branch, so each stage's loads are all in flight together)
     constexpr int PL = SMALL_CAP / NT;
-    uint32_t sp[PL], kk[PL], k2[PL], vv[PL];
+    uint32_t sp[PL], kk[PL], k2[PL], vv[PL], kb[PL];
 #pragma unroll
     for (int j = 0; j < PL; j++) {
       const uint32_t p = j * NT + threadIdx.x;
       sp[j] = p < n ? segp[p] : NO_SEG;
-      kk[j] = segs[sp[j] != NO_SEG ? mark[sp[j]] - 1 : 0u].start;
+      const SegRec& r = segs[sp[j] != NO_SEG ? mark[sp[j]] - 1 : 0u];
+      kk[j] = r.start;
+      kb[j] = r.blk;
     }
 #pragma unroll
     for (int j = 0; j < PL; j++) {
       const uint32_t p = j * NT + threadIdx.x;
       kk[j] = sp[j] != NO_SEG ? kk[j] + (p - sp[j]) : kk[j];
-      k2[j] = key2[kk[j]];
+      if (!text) k2[j] = key2[kk[j]];
       vv[j] = SA[kk[j]];
+    }
+    if (text) {
+      // the text round gathers its own keys: the first 4 bytes of the
+      // rotation h positions on (no k_gather pass for small segments)
+      uint32_t o[PL], nbk[PL];
+#pragma unroll
+      for (int j = 0; j < PL; j++) {
+        o[j] = blk_off[kb[j]];
+        nbk[j] = blk_off[kb[j] + 1];
+      }
+#pragma unroll
+      for (int j = 0; j < PL; j++) {
+        nbk[j] -= o[j];
+        k2[j] = cyc(vv[j] - o[j] + h, nbk[j]);
+      }
+      gather_keys_impl<PL, false>(k2, o, nbk, text, nullptr);
     }
     __builtin_amdgcn_sched_barrier(0);  // issue order: these loads stay after the rows'
 #pragma unroll
@@ -1143,16 +1163,19 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       BZG_TRY(hipMemsetAsync(&w.cnt[nxt], 0, sizeof(RoundCounters), st));
       const uint32_t nsmall = (c.small_total() + SMALL_T - 1) / SMALL_T;
       {
-        ProfScope ps("gather", st, 12.0 * c.active());  // row, partner rank, key2
-        hipLaunchKernelGGL(k_gather, dim3(nsmall + c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.head[cur],
-                           w.owner[cur], &w.cnt[cur], nsmall, w.d_off, w.SA, w.rank,
-                           text_round ? text : nullptr, h, w.key);
+        ProfScope ps("gather", st, 12.0 * (text_round ? c.big_active() : c.active()));  // row, partner rank, key2
+        // the text round's small segments gather their keys in k_small_sort
+        const uint32_t gsmall = text_round ? 0u : nsmall;
+        if (gsmall + c.big_tiles())
+          hipLaunchKernelGGL(k_gather, dim3(gsmall + c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.head[cur],
+                             w.owner[cur], &w.cnt[cur], gsmall, w.d_off, w.SA, w.rank,
+                             text_round ? text : nullptr, h, w.key);
       }
       AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[nxt]};
       if (nsmall) {
         ProfScope ps("small_sort", st, 16.0 * c.small_total());  // key2 and row in, row and rank out
         hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
-                           w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? 1 : 0, app2);
+                           w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
       }
       if (c.big_tiles()) {
         const double be = c.big_active();
