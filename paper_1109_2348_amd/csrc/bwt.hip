@@ -495,63 +495,103 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
 
 constexpr uint16_t NO_SEG = 0xFFFFu;
 
+// Exclusive suffix minimum over a workgroup: the minimum of v over the
+// threads after this one (hi if none).  sh needs NT/64 slots.
+template <int NT_>
+__device__ __forceinline__ uint32_t block_excl_suffix_min(uint32_t v, uint32_t* sh, uint32_t hi) {
+  constexpr int NWV = NT_ / BZG_WAVE;
+  const uint32_t l = lane(), w = threadIdx.x / BZG_WAVE;
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < BZG_WAVE; d <<= 1) {
+    const uint32_t u = __shfl_down(inc, d, BZG_WAVE);
+    if (l + d < BZG_WAVE) inc = min(inc, u);
+  }
+  if (l == 0) sh[w] = inc;  // the wave's minimum
+  __syncthreads();
+  uint32_t later = hi;
+#pragma unroll
+  for (int q = 0; q < NWV; q++) later = q > (int)w ? min(later, sh[q]) : later;
+  uint32_t ex = __shfl_down(inc, 1, BZG_WAVE);
+  ex = l + 1 < BZG_WAVE ? ex : hi;
+  __syncthreads();
+  return min(ex, later);
+}
+
 // Loads a small tile's segment map: mark[p] = segment index + 1 at each
 // segment's first position, segp[p] = first position of p's segment;
 // *s_maxlen gets the longest segment; send (optional) gets each segment's end
-// at its first position.
-__device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head, const SegRec* __restrict__ segs,
-                                   uint32_t small_total, uint32_t* mark, uint16_t* segp, uint32_t* sh,
-                                   uint32_t* s_n, uint32_t* s_maxlen, uint16_t* send = nullptr) {
-  for (uint32_t p = threadIdx.x; p < SMALL_CAP; p += NT) mark[p] = 0;
+// at its first position.  Packed small segments follow each other without
+// gaps, so a segment ends where the next one starts (or where the packed rows
+// end): one load of the head entries of the tile and of the SMALL_MAX
+// positions after it gives every length.
+__device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head, uint32_t small_total,
+                                   uint32_t* mark, uint16_t* segp, uint32_t* sh, uint32_t* s_n, uint32_t* s_maxlen,
+                                   uint16_t* send = nullptr) {
   if (threadIdx.x == 0) {
     *s_n = 0;
     *s_maxlen = 0;
   }
-  __syncthreads();
   const uint32_t lo = t * SMALL_T;
+  const uint32_t avail = min(small_total - lo, SMALL_CAP);  // packed rows from lo on, in this tile's reach
   {
-    constexpr int PH = SMALL_T / NT;
-    uint32_t hd[PH], ln[PH];
+    constexpr int PH = SMALL_CAP / NT;
+    uint32_t hd[PH];
 #pragma unroll
-    for (int j = 0; j < PH; j++) {
-      const uint32_t o = lo + j * NT + threadIdx.x;
-      hd[j] = o < small_total ? head[o] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < PH; j++) ln[j] = hd[j] ? segs[hd[j] - 1].len : 0u;
-    uint32_t en = 0, ml = 0;
+    for (int j = 0; j < PH; j++) hd[j] = head[lo + min(j * NT + threadIdx.x, avail - 1u)];
 #pragma unroll
     for (int j = 0; j < PH; j++) {
       const uint32_t i = j * NT + threadIdx.x;
-      if (hd[j]) {
-        mark[i] = hd[j];
-        if (send) send[i] = (uint16_t)(i + ln[j]);  // end of the segment starting at i
-        en = max(en, i + ln[j]);
-        ml = max(ml, ln[j]);
-      }
-    }
-    // one LDS atomic per wave (same-address atomics serialize)
-    en = wave_max(en);
-    ml = wave_max(ml);
-    if (lane() == 0) {
-      atomicMax(s_n, en);
-      atomicMax(s_maxlen, ml);
+      mark[i] = i < avail ? hd[j] : 0u;
     }
   }
   __syncthreads();
-  constexpr int PER = SMALL_CAP / NT;  // 16 positions per thread, blocked
+  constexpr int PER = SMALL_CAP / NT;  // 8 positions per thread, blocked
   const uint32_t p0 = threadIdx.x * PER;
+  uint32_t mk[PER];
+#pragma unroll
+  for (int i = 0; i < PER; i++) mk[i] = mark[p0 + i];
+  uint32_t first = avail;  // this thread's first segment start
+#pragma unroll
+  for (int i = PER - 1; i >= 0; i--) first = mk[i] ? p0 + i : first;
+  uint32_t nx = block_excl_suffix_min<NT>(first, sh, avail);  // the next start after the thread's range
+  uint32_t en = 0, ml = 0;
+#pragma unroll
+  for (int i = PER - 1; i >= 0; i--) {
+    const uint32_t p = p0 + i;
+    if (mk[i]) {
+      if (p < SMALL_T) {  // a segment of this tile: it ends at the next start
+        en = max(en, nx);
+        ml = max(ml, nx - p);
+        if (send) send[p] = (uint16_t)nx;
+      }
+      nx = p;
+    }
+  }
+  // one LDS atomic per wave (same-address atomics serialize)
+  en = wave_max(en);
+  ml = wave_max(ml);
+  if (lane() == 0) {
+    atomicMax(s_n, en);
+    atomicMax(s_maxlen, ml);
+  }
+  // only this tile's segment starts stay marked
   uint32_t last = 0;
-  for (int i = 0; i < PER; i++)
-    if (mark[p0 + i]) last = p0 + i + 1;
+#pragma unroll
+  for (int i = 0; i < PER; i++) {
+    if (p0 + i >= SMALL_T) mk[i] = 0;
+    last = mk[i] ? p0 + i + 1 : last;
+  }
   uint32_t incl = block_incl_max<uint32_t, NT>(last, sh, 0u);
-  // exclusive carry via a shuffle of the inclusive value of the previous thread
+  // exclusive carry via the inclusive value of the previous thread
   __shared__ uint32_t sx[NT];
   sx[threadIdx.x] = incl;
   __syncthreads();
   uint32_t cur = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+#pragma unroll
   for (int i = 0; i < PER; i++) {
-    if (mark[p0 + i]) cur = p0 + i + 1;
+    if (mk[i]) cur = p0 + i + 1;
+    mark[p0 + i] = mk[i];
     // positions before the tile's first segment belong to a segment of the
     // previous tile
     segp[p0 + i] = cur ? (uint16_t)(cur - 1) : NO_SEG;
@@ -599,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   __shared__ uint32_t s_n, s_maxlen;
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   if (jt < n_small_tiles) {
-    uint32_t n = small_tile_map(jt, head, segs, cnt->small_total(), mark, segp, sh, &s_n, &s_maxlen);
+    uint32_t n = small_tile_map(jt, head, cnt->small_total(), mark, segp, sh, &s_n, &s_maxlen);
     // segment records, then block bounds and rows, then the gathers: each
     // stage's loads are issued together, for half the tile at a time (which
     // bounds the registers held across them)
@@ -690,7 +730,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   __shared__ uint32_t wg_base[4];
   const uint32_t small_total = cnt->small_total();
   const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t n = small_tile_map(jt, head, segs, small_total, mark, segp, sh, &s_n, &s_maxlen, sseg);
+  const uint32_t n = small_tile_map(jt, head, small_total, mark, segp, sh, &s_n, &s_maxlen, sseg);
   // Tiles whose segments are all short are ordered by counting (below); they
   // keep the segment ends in sseg, which the radix passes use otherwise.
   const bool counting = s_maxlen <= COUNT_SORT_MAX;
@@ -769,10 +809,6 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
       if (!counting) sseg[p] = (uint16_t)(has ? sp[j] : front ? 0u : 0xFFFFu);
     }
   }
-  // clear the head entries of this tile for reuse two rounds later
-  const uint32_t lo = jt * SMALL_T;
-  for (uint32_t i = threadIdx.x; i < SMALL_T; i += NT)
-    if (lo + i < small_total) head[lo + i] = 0;
   __syncthreads();
   // stable LSD radix sort of the tile in LDS; wave w owns positions
   // [w*1024, (w+1)*1024), item i of lane l is position w*1024 + i*64 + l
@@ -1176,6 +1212,9 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
         ProfScope ps("small_sort", st, 16.0 * c.small_total());  // key2 and row in, row and rank out
         hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
                            w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
+        // every tile reads the head entries of the next one too, so they are
+        // cleared (for reuse two rounds later) only after the whole pass
+        BZG_TRY(hipMemsetAsync(w.head[cur], 0, (size_t)c.small_total() * 4, st));
       }
       if (c.big_tiles()) {
         const double be = c.big_active();
