@@ -239,7 +239,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
   // The tile is staged in LDS in digit order, then every digit's run is
   // written out by consecutive lanes to consecutive addresses.
   __shared__ uint32_t sval[RADIX_TILE], skey[RADIX_TILE];
-  __shared__ uint32_t gbase[256], lbase[256];
+  __shared__ uint32_t gofs[256];  // output row of a digit's run minus its tile position
   __shared__ uint32_t sh[NW + 1];
   {
     const uint32_t d = threadIdx.x;  // NT == 256: one digit per thread
@@ -248,8 +248,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     for (int q = 0; q < NW; q++) tot += cnt[q][d];
     uint32_t all;
     uint32_t run = block_excl_sum<uint32_t, NT>(tot, sh, &all);
-    lbase[d] = run;
-    gbase[d] = g.r.start + hs_d - hs_0;
+    gofs[d] = g.r.start + hs_d - hs_0 - run;
 #pragma unroll
     for (int q = 0; q < NW; q++) {
       uint32_t c = cnt[q][d];
@@ -258,25 +257,39 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
     }
   }
   __syncthreads();
+  // Each stage below reads LDS for all of the thread's items before using
+  // any (clamped or unconditional reads), so the reads are in flight
+  // together instead of one round trip per item.
+  {
+    uint32_t base[RI];
 #pragma unroll
-  for (int i = 0; i < RI; i++) {
-    if (rk[i] != 0xFFFFFFFFu) {
-      const uint32_t d = (key[i] >> shift) & 255u;
-      const uint32_t L = cnt[w][d] + rk[i];
-      sval[L] = val[i];
-      skey[L] = key[i];
+    for (int i = 0; i < RI; i++) base[i] = cnt[w][(key[i] >> shift) & 255u];
+#pragma unroll
+    for (int i = 0; i < RI; i++) {
+      if (rk[i] != 0xFFFFFFFFu) {
+        const uint32_t L = base[i] + rk[i];
+        sval[L] = val[i];
+        skey[L] = key[i];
+      }
     }
   }
   __syncthreads();
   const uint32_t tn = g.hi - g.lo;
+  uint32_t kd[RI], vd[RI], go[RI];
+#pragma unroll
+  for (int i = 0; i < RI; i++) {
+    const uint32_t L = min(i * NT + threadIdx.x, tn - 1u);
+    kd[i] = skey[L];
+    vd[i] = sval[L];
+  }
+#pragma unroll
+  for (int i = 0; i < RI; i++) go[i] = gofs[(kd[i] >> shift) & 255u];
 #pragma unroll
   for (int i = 0; i < RI; i++) {
     const uint32_t L = i * NT + threadIdx.x;
     if (L < tn) {
-      const uint32_t kd = skey[L];
-      const uint32_t pos = gbase[(kd >> shift) & 255u] + (L - lbase[(kd >> shift) & 255u]);
-      kout[pos] = kd;
-      vout[pos] = sval[L];
+      kout[go[i] + L] = kd[i];
+      vout[go[i] + L] = vd[i];
     }
   }
 }
@@ -829,10 +842,13 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
         const uint32_t len = sseg[sp] - sp, d = p - sp;
         uint32_t r = 0;
         // a fixed count of steps (the tile's longest segment)
+        // (bitwise, not short-circuit, tests: a load used only under a
+        // branch would be moved into it and waited for there, one LDS round
+        // trip per step)
 #pragma unroll 8
         for (uint32_t i = 0; i < ml; i++) {
           const uint32_t o = skey[min(sp + i, SMALL_CAP - 1u)];
-          r += (i < len && (o < me || (o == me && i < d))) ? 1u : 0u;
+          r += (uint32_t)(i < len) & ((uint32_t)(o < me) | ((uint32_t)(o == me) & (uint32_t)(i < d)));
         }
         dst[j] = sp + r;
         kv[j] = me;
@@ -898,12 +914,24 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
     }
     __syncthreads();
   }
-  // naming: blocked, PI consecutive positions per thread
+  // naming: blocked, PI consecutive positions per thread.  The thread's
+  // keys (with one neighbour on each side), segment starts and rows are read
+  // from LDS first, all together (clamped positions).
   const uint32_t p0 = threadIdx.x * PI;
-  uint32_t lastb = 0;
+  uint32_t sk[PI + 2], sg[PI], sv[PI];
+#pragma unroll
+  for (int i = 0; i < PI + 2; i++) sk[i] = skey[min(max(p0 + i, 1u) - 1u, SMALL_CAP - 1u)];
+#pragma unroll
   for (int i = 0; i < PI; i++) {
-    uint32_t p = p0 + i;
-    if (p < n && segp[p] != NO_SEG && (p == segp[p] || skey[p] != skey[p - 1])) lastb = p + 1;
+    sg[i] = segp[p0 + i];
+    sv[i] = sval[p0 + i];
+  }
+  uint32_t lastb = 0;
+#pragma unroll
+  for (int i = 0; i < PI; i++) {
+    const uint32_t p = p0 + i;
+    const bool head = (p < n) & (sg[i] != NO_SEG) & ((p == sg[i]) | (sk[i + 1] != sk[i]));
+    lastb = head ? p + 1 : lastb;
   }
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
@@ -915,23 +943,23 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   for (int i = 0; i < PI; i++) {
     uint32_t p = p0 + i;
     if (p >= n) break;
-    uint32_t sp = segp[p];
+    uint32_t sp = sg[i];
     if (sp == NO_SEG) continue;
     const SegRec r = rr[i];
-    if (p == sp || skey[p] != skey[p - 1]) hp = p + 1;
+    if (p == sp || sk[i + 1] != sk[i]) hp = p + 1;
     uint32_t k = r.start + (p - sp);
     uint32_t headk = r.start + (hp - 1 - sp);
-    uint32_t v = sval[p];
+    uint32_t v = sv[i];
     SA[k] = v;
     // rank rounds: rows of the segment's first group keep the rank they have
     // (the segment's start), so only the other groups' rows are written
     if (text_mode || hp - 1 != sp) rank[v] = headk;
-    bool end = (p + 1 == sp + r.len) || skey[p + 1] != skey[p];
+    bool end = (p + 1 == sp + r.len) || sk[i + 2] != sk[i + 1];
     if (end) {
       uint32_t len = p + 1 - (hp - 1);
       const uint32_t nbk = be[i] - bo[i];
       // closed group (see k_rename_b): equal rotations, final
-      const bool closed = !text_mode && len == r.len && (skey[p] & ((1u << 21) - 1u)) == r.start - bo[i];
+      const bool closed = !text_mode && len == r.len && (sk[i + 1] & ((1u << 21) - 1u)) == r.start - bo[i];
       if (len >= 2 && h_next < nbk && !closed) {
 #pragma unroll
         for (int q = 0; q < PI / 2 + 1; q++)  // register-resident append
