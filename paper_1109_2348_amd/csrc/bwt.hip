@@ -454,18 +454,21 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   __syncthreads();
   const uint32_t k0 = g.lo + threadIdx.x * RI;  // blocked: RI consecutive rows per thread
   const uint32_t i0 = threadIdx.x * RI;         // its first position in tk (minus the halo)
-  uint32_t kk[RI];
+  // the thread's keys with one neighbour on each side (t[i + 1] is row
+  // k0 + i's key) and its rows, read from LDS all together; tk holds the
+  // tile's keys at 1.. with the keys before and after the tile around them
+  uint32_t t[RI + 2], vv[RI];
+#pragma unroll
+  for (int i = 0; i < RI + 2; i++) t[i] = tk[i0 + i];
+#pragma unroll
+  for (int i = 0; i < RI; i++) vv[i] = tv[i0 + i];
   uint32_t lastb = 0;
-  // key of the row before this thread's first row, and after its last
-  const uint32_t kprev = (k0 < g.hi && k0 > g.r.start) ? tk[i0] : 0u;
 #pragma unroll
   for (int i = 0; i < RI; i++) {
-    uint32_t k = k0 + i;
-    kk[i] = k < g.hi ? tk[i0 + i + 1] : 0u;
-    if (k < g.hi && (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev))) lastb = k + 1;
+    const uint32_t k = k0 + i;
+    const bool head = (k < g.hi) & ((k == g.r.start) | (t[i + 1] != t[i]));
+    lastb = head ? k + 1 : lastb;
   }
-  const uint32_t klast = k0 + RI - 1;
-  const uint32_t knext = (klast < g.hi && klast + 1 < segend) ? tk[i0 + RI + 1] : 0u;
   __syncthreads();
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
@@ -478,12 +481,10 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
   for (int i = 0; i < RI; i++) {
     uint32_t k = k0 + i;
     if (k < g.hi) {
-      if (k == g.r.start || kk[i] != (i ? kk[i - 1] : kprev)) hp = k + 1;
-      uint32_t v = tv[i0 + i];
+      if (k == g.r.start || t[i + 1] != t[i]) hp = k + 1;
+      const uint32_t v = vv[i];
       if (vin != SA) SA[k] = v;
-      bool end = (k + 1 == segend) ||
-                 ((i + 1 < RI && k + 1 < g.hi) ? kk[i + 1] != kk[i] : (i + 1 < RI) ? tk[i0 + i + 2] != kk[i]
-                                                                                    : knext != kk[i]);
+      const bool end = (k + 1 == segend) || t[i + 2] != t[i + 1];
       // rank rounds: rows of the segment's first group keep the rank they
       // have (the segment's start)
       const bool same_rank = key_is_rank && hp - 1 == g.r.start;
@@ -492,7 +493,7 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
         uint32_t len = k + 1 - (hp - 1);
         // closed group: the segment did not split and every partner lies in
         // it, so its rotations are all equal (already in final order)
-        const bool closed = key_is_rank && len == g.r.len && kk[i] == g.r.start - bo;
+        const bool closed = key_is_rank && len == g.r.len && t[i + 1] == g.r.start - bo;
         if (len >= 2 && keep_blk && !closed && m < RI / 2 + 1) {
           gs[m] = hp - 1;
           gl[m] = len;

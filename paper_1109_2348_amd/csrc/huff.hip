@@ -232,17 +232,20 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
   const uint16_t* S = syms + sym_base[b];
   const uint64_t sb = sel_base[b];
   if (mode == 0) {
+    // every table's length of a symbol packed in 10-bit fields (loads of all
+    // six tables issued together; unused tables masked out)
     for (uint32_t v = threadIdx.x; v < a; v += NT) {
+      uint32_t lv[MAXG];
+#pragma unroll
+      for (int t = 0; t < MAXG; t++) lv[t] = T->len[t][v];
       uint64_t c = 0;
-      for (uint32_t t = 0; t < G; t++) c |= (uint64_t)T->len[t][v] << (10 * t);
+#pragma unroll
+      for (int t = 0; t < MAXG; t++) c |= (uint32_t)t < G ? (uint64_t)lv[t] << (10 * t) : 0ull;
       sc[v] = c;
     }
     for (uint32_t i = threadIdx.x; i < MAXG * MAXA; i += NT) (&stf[0][0])[i] = 0;
   } else {
-    for (uint32_t i = threadIdx.x; i < G * MAXA; i += NT) {
-      uint32_t t = i / MAXA, v = i % MAXA;
-      if (v < a) slen[t][v] = T->len[t][v];
-    }
+    stage_to_lds<NT, 8>(&slen[0][0], &T->len[0][0], G * MAXA);
   }
   uint64_t bits = 0;
   for (uint32_t gs = g0; gs < g1; gs += ASSIGN_SUB) {
@@ -321,9 +324,19 @@ __global__ __launch_bounds__(BUILD_NT) void k_huff_build(BlockTables* __restrict
   const int G = (int)T->G, a = (int)T->alpha;
   if ((int)t >= G) return;
   uint32_t* F = tf + ((size_t)b * MAXG + t) * MAXA;
-  for (int i = threadIdx.x; i < a; i += BUILD_NT) {
-    sf[i] = F[i];
-    F[i] = 0;
+  {
+    constexpr int PF = (MAXA + BUILD_NT - 1) / BUILD_NT;
+    uint32_t fv[PF];  // all loads issued before any is used (clamped index)
+#pragma unroll
+    for (int q = 0; q < PF; q++) fv[q] = F[min(q * BUILD_NT + (int)threadIdx.x, a - 1)];
+#pragma unroll
+    for (int q = 0; q < PF; q++) {
+      const int i = q * BUILD_NT + (int)threadIdx.x;
+      if (i < a) {
+        sf[i] = fv[q];
+        F[i] = 0;
+      }
+    }
   }
   __syncthreads();
   const int w = threadIdx.x / BZG_WAVE;

@@ -279,21 +279,31 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
     if (threadIdx.x < g1 - g0) ssel[threadIdx.x] = sel[sb + g0 + threadIdx.x];
   }
   __syncthreads();
-  // blocked: PER consecutive symbols per thread
+  // blocked: PER consecutive symbols per thread; each LDS stage is read for
+  // all of them before any is used (clamped positions)
   const uint32_t l0 = threadIdx.x * PER;
-  uint32_t mine = 0;
+  uint32_t tq[PER], sq[PER], nq[PER], vq[PER];
+#pragma unroll
   for (uint32_t q = 0; q < PER; q++) {
-    const uint32_t l = l0 + q;
-    if (l < cnt) mine += slen[ssel[l / GROUP]][ssym[l]];
+    const uint32_t l = min(l0 + q, cnt - 1u);
+    tq[q] = ssel[l / GROUP];
+    sq[q] = ssym[l];
   }
+#pragma unroll
+  for (uint32_t q = 0; q < PER; q++) {
+    nq[q] = slen[tq[q]][sq[q]];
+    vq[q] = scode[tq[q]][sq[q]];
+  }
+  uint32_t mine = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < PER; q++) mine += l0 + q < cnt ? nq[q] : 0u;
   uint64_t tot;
   uint64_t p = (B0 & 31) + block_excl_sum<uint64_t, NT>((uint64_t)mine, sh, &tot);
+#pragma unroll
   for (uint32_t q = 0; q < PER; q++) {
     const uint32_t l = l0 + q;
     if (l >= cnt) break;
-    uint32_t t = ssel[l / GROUP];
-    uint32_t s = ssym[l];
-    uint32_t n = slen[t][s], v = scode[t][s];
+    const uint32_t n = nq[q], v = vq[q];
     uint32_t wi = (uint32_t)(p >> 5), o = (uint32_t)(p & 31);
     if (o + n <= 32) {
       atomicOr(&stage[wi], v << (32 - o - n));
