@@ -238,11 +238,14 @@ __device__ __forceinline__ void stack_front(uint32_t e[4], const uint32_t dx[4],
   for (int j = 0; j < 4; j++)
     if ((uint32_t)(j * 64) + l < nd) mem[dx[j]] = 1;
   wave_sync();
+  uint32_t mb[4];  // membership reads first, all together
+#pragma unroll
+  for (int j = 0; j < 4; j++) mb[j] = mem[e[j] & 255u];
   bool keep[4];
   uint64_t km[4];
 #pragma unroll
   for (int j = 0; j < 4; j++) {
-    keep[j] = e[j] < 256u && mem[e[j]] == 0;
+    keep[j] = (e[j] < 256u) & (mb[j] == 0u);
     km[j] = __ballot(keep[j]);
   }
 #pragma unroll
@@ -616,17 +619,23 @@ __device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g
       __syncthreads();
       if (is_last) nstk[__popcll(last_m & ~(lt | (1ull << l)))] = mine;
       uint32_t seen = 0;
-#define BZG_RESTACK(ej, J)                                                     \
+      // the columns' membership reads first, all together (they precede
+      // the nstk writes, which the compiler keeps in order with them)
+      const uint32_t ib0 = inb[e0 & 255u];
+      const uint32_t ib1 = NCOL > 1 ? inb[e1 & 255u] : 0u;
+      const uint32_t ib2 = NCOL > 2 ? inb[e2 & 255u] : 0u;
+      const uint32_t ib3 = NCOL > 3 ? inb[e3 & 255u] : 0u;
+#define BZG_RESTACK(ej, ibj, J)                                                \
   {                                                                            \
-    const bool in_b = (ej) < 256u && inb[(ej)];                                \
+    const bool in_b = ((ej) < 256u) & ((ibj) != 0u);                           \
     const uint64_t cm = __ballot(in_b);                                        \
     if (!in_b) nstk[nd + (J) * 64u + l - (seen + (uint32_t)__popcll(cm & lt))] = (ej); \
     seen += (uint32_t)__popcll(cm);                                            \
   }
-      BZG_RESTACK(e0, 0)
-      if (NCOL > 1) BZG_RESTACK(e1, 1)
-      if (NCOL > 2) BZG_RESTACK(e2, 2)
-      if (NCOL > 3) BZG_RESTACK(e3, 3)
+      BZG_RESTACK(e0, ib0, 0)
+      if (NCOL > 1) BZG_RESTACK(e1, ib1, 1)
+      if (NCOL > 2) BZG_RESTACK(e2, ib2, 2)
+      if (NCOL > 3) BZG_RESTACK(e3, ib3, 3)
 #undef BZG_RESTACK
       __syncthreads();
       e0 = nstk[l];
