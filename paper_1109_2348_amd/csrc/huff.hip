@@ -48,9 +48,9 @@ struct HuffScratch {
 };
 
 // One wave, one Huffman pass over the weights hs->w[0..a): ranks the leaves
-// by (weight, id), runs the two-queue merge and returns the depth of the
-// deepest leaf; parents are left in hs->parent.  All 64 lanes call it.
-__device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
+// by (weight, id) and runs the two-queue merge; parents are left in
+// hs->parent.  All 64 lanes call it.
+__device__ void huff_pass_wave(int a, HuffScratch* hs) {
   const int l = (int)lane();
   // (weight, id) as one unique key: weights are symbol counts < 2^22
   for (int i = l; i < a; i += 64) hs->key[i] = (hs->w[i] << 9) | (uint32_t)i;
@@ -84,59 +84,59 @@ __device__ uint32_t huff_pass_wave(int a, HuffScratch* hs) {
   }
   __builtin_amdgcn_wave_barrier();
   // Two-queue merge: leaves by (weight, id) in hs->lw / hs->order, internal
-  // nodes in creation order (their weights never decrease) in hs->w / hs->key
-  // (free after the ranking).  Each step reads both heads of both queues in
-  // one batch of LDS reads (clamped indices, empty queues read as infinite)
-  // and picks the two smallest with selects, leaves first on ties.  Lane 0
-  // writes; all lanes read the same words.
+  // nodes in creation order (their weights never decrease) in hs->w (free
+  // after the ranking).  Each step reads both heads of both queues in one
+  // batch of LDS reads (clamped indices, empty queues read as infinite) and
+  // picks the two smallest with selects, leaves first on ties.  Lane 0
+  // writes; all lanes read the same words.  Depths are left to the walk.
   uint32_t* const wn = hs->w;
-  uint32_t* const dn = hs->key;
   const uint32_t A_ = (uint32_t)a, INF = 0xFFFFFFFFu;
-  uint32_t li = 0, ni = 0, nn = 0, dmax = 0;
+  uint32_t li = 0, ni = 0, nn = 0;
   for (uint32_t step = 0; step + 1 < A_; step++) {
     const uint32_t l0 = min(li, A_ - 1u), l1 = min(li + 1u, A_ - 1u);
     const uint32_t n0 = min(ni, A_ - 2u), n1 = min(ni + 1u, A_ - 2u);
     const uint32_t lwa = hs->lw[l0], lwb = hs->lw[l1];
     const uint32_t ida = hs->order[l0], idb = hs->order[l1];
     const uint32_t wna = wn[n0], wnb = wn[n1];
-    const uint32_t dna = dn[n0], dnb = dn[n1];
     const uint32_t A0 = li < A_ ? lwa : INF, A1 = li + 1u < A_ ? lwb : INF;
     const uint32_t B0 = ni < nn ? wna : INF, B1 = ni + 1u < nn ? wnb : INF;
     const bool p1 = A0 <= B0;  // first pick is a leaf
     const uint32_t C = p1 ? A1 : A0, D = p1 ? B0 : B1;
     const bool p2 = C <= D;    // second pick is a leaf
     const uint32_t w1 = p1 ? A0 : B0, w2 = p2 ? C : D;
-    const uint32_t d1 = p1 ? 0u : dna, d2 = p2 ? 0u : (p1 ? dna : dnb);
     const uint32_t id1 = p1 ? ida : A_ + ni;
     const uint32_t id2 = p2 ? (p1 ? idb : ida) : (p1 ? A_ + ni : A_ + ni + 1u);
-    const uint32_t dnew = max(d1, d2) + 1u;
     if (l == 0) {
       hs->parent[id1] = (uint16_t)(A_ + nn);
       hs->parent[id2] = (uint16_t)(A_ + nn);
       wn[nn] = w1 + w2;
-      dn[nn] = dnew;
     }
     const uint32_t nl = (p1 ? 1u : 0u) + (p2 ? 1u : 0u);
     li += nl;
     ni += 2u - nl;
     nn++;
-    dmax = dnew;
   }
   __builtin_amdgcn_wave_barrier();
-  return dmax;
 }
 
-// One wave: leaf depths from the parents of the last pass.
-__device__ void huff_walk_wave(int a, const HuffScratch* hs, uint8_t* len) {
+// One wave: leaf depths from the parents of the last pass (leaf 64*q + lane
+// in dep[q]); returns the deepest.
+constexpr int WALK_COLS = (MAXA + 63) / 64;
+__device__ uint32_t huff_walk_wave(int a, const HuffScratch* hs, uint32_t dep[WALK_COLS]) {
   const int root = 2 * a - 2;
-  for (int i = (int)lane(); i < a; i += 64) {
+  uint32_t dmax = 0;
+#pragma unroll
+  for (int q = 0; q < WALK_COLS; q++) {
+    const int i = q * 64 + (int)lane();
     int d = 0, v = i;
-    while (v != root && d < 2 * MAXA) {  // parents have larger ids: at most 2a steps
+    while (i < a && v != root && d < 2 * MAXA) {  // parents have larger ids: at most 2a steps
       v = hs->parent[v];
       d++;
     }
-    len[i] = (uint8_t)d;
+    dep[q] = (uint32_t)d;
+    dmax = max(dmax, (uint32_t)d);
   }
+  return wave_max(dmax);
 }
 
 __device__ __forceinline__ int n_tables(uint32_t ns, int a) {
@@ -347,14 +347,20 @@ __global__ __launch_bounds__(BUILD_NT) void k_huff_build(BlockTables* __restrict
       for (int r = 0; r < k && x > 2u; r++) x = 1u + x / 2u;  // 1 and 2 are fixed points
       hs[w].w[i] = x;
     }
-    const uint32_t dmax = huff_pass_wave(a, &hs[w]);
+    huff_pass_wave(a, &hs[w]);
+    uint32_t dep[WALK_COLS];
+    const uint32_t dmax = huff_walk_wave(a, &hs[w], dep);
     if (lane() == 0) ok[w] = dmax <= (uint32_t)MAXLEN ? 1u : 0u;
     __syncthreads();
     int first = BUILD_WAVES;
     for (int q = BUILD_WAVES - 1; q >= 0; q--)
       if (ok[q]) first = q;
     if (first < BUILD_WAVES) {
-      if (w == first) huff_walk_wave(a, &hs[w], &T->len[t][0]);
+      if (w == first) {
+#pragma unroll
+        for (int q = 0; q < WALK_COLS; q++)
+          if (q * 64 + (int)lane() < a) T->len[t][q * 64 + lane()] = (uint8_t)dep[q];
+      }
       break;
     }
     __syncthreads();
