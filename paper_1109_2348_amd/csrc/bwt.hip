@@ -307,7 +307,7 @@ struct AppendCtx {
 // (group g = (start[g], len[g], blk)).  All threads must call it.
 template <int M>
 __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint32_t* gl, int m, uint32_t blk_of_thread,
-                              const uint32_t* gblk, uint32_t* sh32, uint32_t* wg_base /*LDS[4]*/) {
+                              const uint32_t* gblk, uint32_t* wg_base /*LDS[4]*/) {
   uint32_t nseg = (uint32_t)m, nsmall = 0, ntiles = 0, nbig = 0;
   for (int g = 0; g < m; g++) {
     if (gl[g] <= SMALL_MAX) nsmall += gl[g];
@@ -320,7 +320,6 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
   // its (at most 4096) rows: segments <= 2048+1, small rows <= 4096+1024,
   // tiles <= 2^21/4096+4 (13 bits each); large rows <= 2^21+4096 (22 bits).
   __shared__ uint64_t sh64[NT / BZG_WAVE + 1];
-  (void)sh32;
   const uint64_t packed = (uint64_t)nseg | ((uint64_t)nsmall << 13) | ((uint64_t)ntiles << 26) | ((uint64_t)nbig << 39);
   uint64_t tot;
   const uint64_t ex = block_excl_sum<uint64_t, NT>(packed, sh64, &tot);
@@ -502,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
       }
     }
   }
-  append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, nullptr, sh, wg_base);
+  append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, nullptr, wg_base);
 }
 
 // ------------------------------------------------------------ gather key2
@@ -973,7 +972,7 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
       }
     }
   }
-  append_groups<PI / 2 + 1>(app, gs, gl, m, 0, gb, sh, wg_base);
+  append_groups<PI / 2 + 1>(app, gs, gl, m, 0, gb, wg_base);
 }
 
 // ------------------------------------------------------------- final BWT

@@ -100,8 +100,6 @@ struct bzg_ctx {
 
 namespace {
 
-constexpr size_t TABLE_STRIDE = 1568;
-
 int fail(bzg_ctx* c, int code, const std::string& m) {
   c->err = m;
   return code;
