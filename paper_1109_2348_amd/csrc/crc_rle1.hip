@@ -71,6 +71,20 @@ __device__ __forceinline__ void load_run(const uint8_t* s, const TileGeom& g, ui
   for (int i = 0; i < RITEMS; i++) v[i] = i < cnt ? (uint8_t)(w[i >> 2] >> (8 * (i & 3))) : 0;
 }
 
+// 1 + the position of the last run start among this thread's bytes (0 when
+// none starts here).  Loops run the full RITEMS with a mask so that v[] is
+// indexed by constants and stays in registers.
+__device__ __forceinline__ uint32_t last_run_start(const uint8_t* v, int cnt, uint32_t p0, uint32_t prev) {
+  uint32_t lastb = 0, pv = prev;
+#pragma unroll
+  for (int i = 0; i < RITEMS; i++) {
+    const bool st = (i < cnt) & ((p0 + i == 0) | (v[i] != pv));
+    lastb = st ? p0 + i + 1 : lastb;
+    pv = v[i];
+  }
+  return lastb;
+}
+
 // Pass A.  One workgroup per tile: tile ids[blockIdx.x], or every tile when
 // ids is null.
 __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* __restrict__ ids,
@@ -100,7 +114,9 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
       reg = tab[3][reg >> 24] ^ tab[2][(reg >> 16) & 255u] ^ tab[1][(reg >> 8) & 255u] ^ tab[0][reg & 255u];
     }
   } else {
-    for (int i = 0; i < cnt; i++) reg = (reg << 8) ^ tab[0][(reg >> 24) ^ v[i]];
+#pragma unroll
+    for (int i = 0; i < RITEMS; i++)
+      if (i < cnt) reg = (reg << 8) ^ tab[0][(reg >> 24) ^ v[i]];
   }
   uint32_t share = 0;
   if (cnt) {
@@ -109,12 +125,8 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
     share = gf2_mulmod(reg, sft);
   }
   // run starts
-  uint32_t lastb = 0;
   uint32_t pv = prev;
-  for (int i = 0; i < cnt; i++) {
-    if (p0 + i == 0 || v[i] != pv) lastb = p0 + i + 1;
-    pv = v[i];
-  }
+  const uint32_t lastb = last_run_start(v, cnt, p0, prev);
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
   __syncthreads();
@@ -123,24 +135,27 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
   // bytes before the tile's first run start; the others' output counts, all
   // 1 unless some byte is the 4th or later of its run
   uint32_t lead = 0, inner = 0, rs = carry, tmax = 0;
-  pv = prev;
-  for (int i = 0; i < cnt; i++) {
+#pragma unroll
+  for (int i = 0; i < RITEMS; i++) {
     const uint32_t p = p0 + i;
-    if (p == 0 || v[i] != pv) rs = p + 1;
+    const bool ok = i < cnt;
+    rs = ok & ((p == 0) | (v[i] != pv)) ? p + 1 : rs;
     pv = v[i];
-    if (rs == 0) lead++;
-    else tmax = max(tmax, p - (rs - 1));
+    lead += (ok & (rs == 0)) ? 1u : 0u;
+    tmax = (ok & (rs != 0)) ? max(tmax, p - (rs - 1)) : tmax;
   }
   if (tmax < 3) {
     inner = (uint32_t)cnt - lead;
   } else {
     rs = carry;
     pv = prev;
-    for (int i = 0; i < cnt; i++) {
+#pragma unroll
+    for (int i = 0; i < RITEMS; i++) {
       const uint32_t p = p0 + i;
-      if (p == 0 || v[i] != pv) rs = p + 1;
+      const bool ok = i < cnt;
+      rs = ok & ((p == 0) | (v[i] != pv)) ? p + 1 : rs;
       pv = v[i];
-      if (rs != 0) inner += rle_emit_count(p - (rs - 1));
+      inner += (ok & (rs != 0)) ? rle_emit_count(p - (rs - 1)) : 0u;
     }
   }
   lead = block_sum<uint32_t, NT>(lead, sh);
@@ -223,21 +238,16 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
                           uint8_t* out, uint64_t obase, uint32_t limit, uint32_t* sh, uint32_t* sx,
                           uint32_t* count_out) {
   const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
+  // the byte after this thread's (read with the others; clamped when absent)
+  const uint32_t pe = p0 + min((uint32_t)RITEMS, g.hi > p0 ? g.hi - p0 : 0u);
+  const bool has_next = pe > p0 && pe < g.n;
+  const uint8_t next = s[g.base + (has_next ? pe : 0u)];
   uint8_t v[RITEMS];
   int cnt;
   uint32_t prev;
   load_run(s, g, p0, v, cnt, prev);
-  uint8_t next = 0;
-  bool has_next = false;
-  if (cnt > 0 && p0 + cnt < g.n) {
-    next = s[g.base + p0 + cnt];
-    has_next = true;
-  }
-  uint32_t lastb = 0, pv = prev, e = 0;
-  for (int i = 0; i < cnt; i++) {
-    if (p0 + i == 0 || v[i] != pv) lastb = p0 + i + 1;
-    pv = v[i];
-  }
+  uint32_t pv = prev, e = 0;
+  const uint32_t lastb = last_run_start(v, cnt, p0, prev);
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
   __syncthreads();
@@ -248,12 +258,13 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   // 4th or later of a run: the common case outside long runs) every byte
   // emits itself and nothing else, and the per-byte piece logic is skipped.
   uint32_t tmax = 0;
-  pv = prev;
-  for (int i = 0; i < cnt; i++) {
+#pragma unroll
+  for (int i = 0; i < RITEMS; i++) {
     const uint32_t p = p0 + i;
-    if (p == 0 || v[i] != pv) rs = p + 1;
+    const bool ok = i < cnt;
+    rs = ok & ((p == 0) | (v[i] != pv)) ? p + 1 : rs;
     pv = v[i];
-    tmax = max(tmax, p - (rs - 1));
+    tmax = ok ? max(tmax, p - (rs - 1)) : tmax;
   }
   const bool plain = tmax < 3;
   if (plain) {
@@ -261,11 +272,13 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   } else {
     rs = rs0;
     pv = prev;
-    for (int i = 0; i < cnt; i++) {
+#pragma unroll
+    for (int i = 0; i < RITEMS; i++) {
       const uint32_t p = p0 + i;
-      if (p == 0 || v[i] != pv) rs = p + 1;
+      const bool ok = i < cnt;
+      rs = ok & ((p == 0) | (v[i] != pv)) ? p + 1 : rs;
       pv = v[i];
-      e += rle_emit_count(p - (rs - 1));
+      e += ok ? rle_emit_count(p - (rs - 1)) : 0u;
     }
   }
   uint32_t tot;
@@ -284,31 +297,40 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   uint32_t below = 0;
   if (plain) {
     if (MODE == 0) {
-      for (int i = 0; i < cnt; i++) sout[al + o + i] = v[i];
+#pragma unroll
+      for (int i = 0; i < RITEMS; i++)
+        if (i < cnt) sout[al + o + i] = v[i];
     } else {
-      for (int i = 0; i < cnt; i++) below += (tile_off + o + i + 1 <= limit) ? 1u : 0u;
+#pragma unroll
+      for (int i = 0; i < RITEMS; i++) below += ((i < cnt) & (tile_off + o + i + 1 <= limit)) ? 1u : 0u;
     }
-  }
-  for (int i = 0; i < (plain ? 0 : cnt); i++) {
-    uint32_t p = p0 + i;
-    if (p == 0 || v[i] != pv) rs = p + 1;
-    pv = v[i];
-    uint32_t tt = p - (rs - 1);
-    uint32_t u = tt % 255u;
-    uint32_t ec = rle_emit_count(tt);
-    if (MODE == 0) {
-      if (u <= 3) sout[al + o] = v[i];
-      bool last_of_piece = (u == 254) || (i + 1 < cnt ? v[i + 1] != v[i] : (!has_next || next != v[i]));
-      if (last_of_piece && u >= 3) {
-        if (u == 3) sout[al + o + 1] = 0;
-        else if (o > 0) sout[al + o - 1] = (uint8_t)(u - 3);
-        else out[gbase - 1] = (uint8_t)(u - 3);  // slot in the previous tile's output
+  } else {
+#pragma unroll
+    for (int i = 0; i < RITEMS; i++) {
+      const uint32_t p = p0 + i;
+      const bool ok = i < cnt;
+      rs = ok & ((p == 0) | (v[i] != pv)) ? p + 1 : rs;
+      pv = v[i];
+      const uint32_t tt = p - (rs - 1);
+      const uint32_t u = tt % 255u;
+      const uint32_t ec = ok ? rle_emit_count(tt) : 0u;
+      if (!ok) {
+      } else if (MODE == 0) {
+        if (u <= 3) sout[al + o] = v[i];
+        // the byte after this one: the next of this thread's, else `next`
+        const bool differs = (i + 1 < cnt) ? v[i + 1 < RITEMS ? i + 1 : i] != v[i] : (!has_next || next != v[i]);
+        const bool last_of_piece = (u == 254) || differs;
+        if (last_of_piece && u >= 3) {
+          if (u == 3) sout[al + o + 1] = 0;
+          else if (o > 0) sout[al + o - 1] = (uint8_t)(u - 3);
+          else out[gbase - 1] = (uint8_t)(u - 3);  // slot in the previous tile's output
+        }
+        if (p + 1 == g.hi && u >= 3 && !last_of_piece) s_skip = 1;
+      } else {
+        if (tile_off + o + ec <= limit) below++;
       }
-      if (p + 1 == g.hi && u >= 3 && !last_of_piece) s_skip = 1;
-    } else {
-      if (tile_off + o + ec <= limit) below++;
+      o += ec;
     }
-    o += ec;
   }
   if (MODE == 0) {
     __syncthreads();

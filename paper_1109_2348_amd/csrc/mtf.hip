@@ -161,7 +161,8 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   // last occurrence: scan own rows backwards, report each byte once
   {
     uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = MITEMS - 1; i >= 0; i--) {
+#pragma unroll
+    for (int i = MITEMS - 1; i >= 0; i--) {  // unrolled: v[] indexed by constants
       uint32_t k = r0 + i;
       if (k >= g.hi) continue;
       uint32_t x = v[i];
