@@ -309,12 +309,14 @@ template <int M>
 __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint32_t* gl, int m, uint32_t blk_of_thread,
                               const uint32_t* gblk, uint32_t* wg_base /*LDS[4]*/) {
   uint32_t nseg = (uint32_t)m, nsmall = 0, ntiles = 0, nbig = 0;
-  for (int g = 0; g < m; g++) {
-    if (gl[g] <= SMALL_MAX) nsmall += gl[g];
-    else {
-      ntiles += (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
-      nbig += gl[g];
-    }
+  // loops over the M slots with a mask: gs[] and gl[] stay in registers
+#pragma unroll
+  for (int g = 0; g < M; g++) {
+    const uint32_t len = g < m ? gl[g] : 0u;
+    const bool big = len > SMALL_MAX;
+    nsmall += big ? 0u : len;
+    ntiles += big ? (len + RADIX_TILE - 1) / RADIX_TILE : 0u;
+    nbig += big ? len : 0u;
   }
   // one scan of four packed counts.  Groups appended by a workgroup end in
   // its (at most 4096) rows: segments <= 2048+1, small rows <= 4096+1024,
@@ -340,7 +342,9 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
   }
   __syncthreads();
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
-  for (int g = 0; g < m; g++) {
+#pragma unroll
+  for (int g = 0; g < M; g++) {
+    if (g >= m) break;
     SegRec r;
     r.start = gs[g];
     r.len = gl[g];
@@ -1127,8 +1131,9 @@ static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs
 // Sorts the rotations of every block of `text` (blocks at h_off[b]..h_off[b+1],
 // all lengths in 1..MAX_BLOCK, total N).  Leaves SA rows in w.SA.
 hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, void* ws, size_t ws_bytes,
-                    RoundCounters* h_pinned, hipStream_t st, uint32_t** SA_out, uint32_t** off_out, int* rounds,
+                    RoundCounters* h_pinned, Stager& stg, uint32_t** SA_out, uint32_t** off_out, int* rounds,
                     std::string& err) {
+  hipStream_t st = stg.st;
   const uint32_t nb = (uint32_t)h_off.size() - 1;
   const uint32_t N = h_off[nb];
   BwtSizes z = bwt_sizes(N, nb);
@@ -1164,7 +1169,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     e = (x);                        \
     if (e != hipSuccess) return e;  \
   } while (0)
-  BZG_TRY(hipMemcpyAsync(w.d_off, h_off.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
+  BZG_TRY(stg.put(w.d_off, h_off.data(), (nb + 1) * 4));
   BZG_TRY(hipMemsetAsync(w.head[0], 0, z.head_cap * 4, st));
   BZG_TRY(hipMemsetAsync(w.head[1], 0, z.head_cap * 4, st));
   BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
@@ -1186,8 +1191,8 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   int nround = 0;
   const bool log_rounds = getenv("BZG_LOG") != nullptr;
   if (!segs0.empty()) {
-    BZG_TRY(hipMemcpyAsync(w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec), hipMemcpyHostToDevice, st));
-    BZG_TRY(hipMemcpyAsync(w.owner[0], owner0.data(), owner0.size() * 4, hipMemcpyHostToDevice, st));
+    BZG_TRY(stg.put(w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec)));
+    BZG_TRY(stg.put(w.owner[0], owner0.data(), owner0.size() * 4));
     uint32_t big_tiles = (uint32_t)owner0.size();
     uint32_t *kin, *vin;
     BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, text, st));

@@ -23,13 +23,13 @@ hipError_t rle1_cut(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, 
                     const uint32_t*, uint32_t, uint32_t*, hipStream_t);
 size_t rle_tile_bytes();
 size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
-hipError_t bwt_sort(const uint8_t*, const std::vector<uint32_t>&, void*, size_t, RoundCounters*, hipStream_t,
+hipError_t bwt_sort(const uint8_t*, const std::vector<uint32_t>&, void*, size_t, RoundCounters*, Stager&,
                     uint32_t**, uint32_t**, int*, std::string&);
 hipError_t bwt_output(const uint8_t*, const uint32_t*, uint32_t, uint32_t, const uint32_t*, uint8_t*, uint32_t*,
                       uint32_t*, hipStream_t);
 size_t mtf_workspace_bytes(const std::vector<uint32_t>&);
 hipError_t mtf_run(const uint8_t*, const uint32_t*, const std::vector<uint32_t>&, void*, size_t, uint16_t*,
-                   const uint64_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*, hipStream_t, std::string&);
+                   const uint64_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*, Stager&, std::string&);
 size_t block_tables_bytes();
 hipError_t huff_run(uint32_t, const uint16_t*, const uint64_t*, const uint32_t*, uint32_t*, bool, const uint32_t*,
                     const uint64_t*, uint8_t*, uint8_t*, uint64_t*, void*, uint32_t*, uint32_t, const uint32_t*,
@@ -93,6 +93,8 @@ struct bzg_ctx {
   size_t ws_cap[2] = {0, 0};
   void* pin = nullptr;
   size_t pin_cap = 0;
+  void* stage = nullptr;  // pinned arena for uploads of host arrays
+  size_t stage_cap = 0;
   // device: 4 x 256 byte-step tables (slicing by 4), 64 powers x^(8*2^j),
   // 256 tile shifts (mod P)
   uint32_t* crc_tab = nullptr;
@@ -155,6 +157,30 @@ int ensure_pin(bzg_ctx* ctx, size_t bytes, void** out) {
     ctx->pin_cap = want;
   }
   *out = ctx->pin;
+  return 0;
+}
+
+// The upload arena, at least `bytes` large, bound to stream st.
+int ensure_stage(bzg_ctx* ctx, size_t bytes, hipStream_t st, Stager* out) {
+  if (ctx->stage_cap < bytes) {
+    if (ctx->stage) {
+      HIPX(hipDeviceSynchronize());
+      HIPX(hipHostFree(ctx->stage));
+      ctx->stage = nullptr;
+      ctx->stage_cap = 0;
+    }
+    size_t want = std::max(bytes, size_t(1) << 20);
+    if (hipHostMalloc(&ctx->stage, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->stage = nullptr;
+      return fail(ctx, BZG_ENOMEM, "pinned host allocation failed");
+    }
+    ctx->stage_cap = want;
+  }
+  out->base = (char*)ctx->stage;
+  out->cap = ctx->stage_cap;
+  out->used = ctx->stage_cap;  // full: the first upload drains the stream
+  out->st = st;
   return 0;
 }
 
@@ -272,6 +298,7 @@ void bzg_destroy(bzg_ctx* ctx) {
   for (int i = 0; i < 2; i++)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
   if (ctx->crc_tab) (void)hipFree(ctx->crc_tab);
   delete ctx;
 }
@@ -334,10 +361,12 @@ int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offse
   if (rc) return rc;
   void* pin;
   if ((rc = ensure_pin(ctx, 4096, &pin))) return rc;
+  Stager stg;
+  if ((rc = ensure_stage(ctx, 65536 + 8 * (size_t)n_blocks + N / 256, st, &stg))) return rc;
   const uint8_t* text = d_in + h_offsets[0];
   uint32_t *SA, *d_off;
   int rounds = 0;
-  hipError_t e = bwt_sort(text, off, ws, ctx->ws_cap[0], (RoundCounters*)pin, st, &SA, &d_off, &rounds, ctx->err);
+  hipError_t e = bwt_sort(text, off, ws, ctx->ws_cap[0], (RoundCounters*)pin, stg, &SA, &d_off, &rounds, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "bwt_sort") : BZG_EHIP;
   HIPX(bwt_output(text, d_off, n_blocks, N, SA, d_bwt + h_offsets[0], d_primary, d_sa ? d_sa + h_offsets[0] : nullptr,
                   st));
@@ -379,11 +408,13 @@ int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* h_offse
   uint32_t* d_freq = cv.take<uint32_t>((size_t)n_blocks * MAXA);
   uint32_t* d_err = cv.take<uint32_t>(4);
   void* rest = cv.take<char>(0);
-  HIPX(hipMemcpyAsync(d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_sbase, sbase.data(), sbase.size() * 8, hipMemcpyHostToDevice, st));
+  Stager stg;
+  if ((rc = ensure_stage(ctx, 65536 + 16 * (size_t)n_blocks + off[n_blocks] / 256, st, &stg))) return rc;
+  HIPX(stg.put(d_off, off.data(), off.size() * 4));
+  HIPX(stg.put(d_sbase, sbase.data(), sbase.size() * 8));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
   hipError_t e = mtf_run(d_bwt + h_offsets[0], d_off, off, rest, ctx->ws_cap[1] - cv.used, d_syms, d_sbase, d_nsyms,
-                         (uint32_t*)d_inuse, d_freq, d_err, st, ctx->err);
+                         (uint32_t*)d_inuse, d_freq, d_err, stg, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
   HIPX(hipMemcpyAsync(pin, d_err, 4, hipMemcpyDeviceToHost, st));
   HIPX(hipStreamSynchronize(st));
@@ -452,13 +483,15 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   uint64_t* d_info = cv.take<uint64_t>(4);
   uint32_t* d_err = cv.take<uint32_t>(4);
   void* d_hws = cv.take<char>(huff_workspace_bytes(n_blocks));
-  HIPX(hipMemcpyAsync(d_sbase, sbase.data(), n_blocks * 8, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_selb, selb.data(), (n_blocks + 1) * 8, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_obyte, obyte.data(), (n_blocks + 1) * 8, hipMemcpyHostToDevice, st));
-  if (ntiles) HIPX(hipMemcpyAsync(d_tile_blk, tile_blk.data(), ntiles * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4, hipMemcpyHostToDevice, st));
-  if (natiles) HIPX(hipMemcpyAsync(d_atile_blk, atile_blk.data(), natiles * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4, hipMemcpyHostToDevice, st));
+  Stager stg;
+  if ((rc = ensure_stage(ctx, 65536 + 48 * (size_t)n_blocks + 4 * (size_t)(ntiles + natiles), st, &stg))) return rc;
+  HIPX(stg.put(d_sbase, sbase.data(), n_blocks * 8));
+  HIPX(stg.put(d_selb, selb.data(), (n_blocks + 1) * 8));
+  HIPX(stg.put(d_obyte, obyte.data(), (n_blocks + 1) * 8));
+  HIPX(stg.put(d_tile_blk, tile_blk.data(), ntiles * 4));
+  HIPX(stg.put(d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4));
+  HIPX(stg.put(d_atile_blk, atile_blk.data(), natiles * 4));
+  HIPX(stg.put(d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4));
   HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
   HIPX(huff_run(n_blocks, d_syms, d_sbase, d_nsyms, d_freq, true, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
@@ -508,6 +541,8 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   void* pin;
   int rc = ensure_pin(ctx, 64 * 1024 + 16 * (boff.size() + total / 100000 + 16) + 16 * (size_t)n_req, &pin);
   if (rc) return rc;
+  Stager stg;
+  if ((rc = ensure_stage(ctx, 65536 + 128 * boff.size() + total / 128 + 16 * (size_t)n_req, st, &stg))) return rc;
   uint32_t nb = (uint32_t)boff.size() - 1;
   if (h_n_blocks) *h_n_blocks = 0;
   if (nb == 0) {  // every stream is the 14-byte empty stream
@@ -569,9 +604,9 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
     }
     blk_tile0[nb] = (uint32_t)tile_blk.size();
     ntiles = (uint32_t)tile_blk.size();
-    HIPX(hipMemcpyAsync(d_boff, boff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
-    HIPX(hipMemcpyAsync(d_tile_blk, tile_blk.data(), ntiles * 4, hipMemcpyHostToDevice, st));
-    HIPX(hipMemcpyAsync(d_blk_tile0, blk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
+    HIPX(stg.put(d_boff, boff.data(), (nb + 1) * 8));
+    HIPX(stg.put(d_tile_blk, tile_blk.data(), ntiles * 4));
+    HIPX(stg.put(d_blk_tile0, blk_tile0.data(), (nb + 1) * 4));
     if (iter == 0) {
       ProfScope ps("rle1_tiles", st, (double)(boff[nb] - boff[0]));
       HIPX(rle1_tiles(in, ntiles, nullptr, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + CRC_POW_AT,
@@ -594,10 +629,10 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
         }
       }
       const int nxt = cur ^ 1;
-      HIPX(hipMemcpyAsync(d_tile_from, tile_from.data(), ntiles * 4, hipMemcpyHostToDevice, st));
+      HIPX(stg.put(d_tile_from, tile_from.data(), ntiles * 4));
       HIPX(rle1_tile_copy(ntiles, d_tile_from, d_rt[cur], d_rt[nxt], st));
       if (!tile_ids.empty()) {
-        HIPX(hipMemcpyAsync(d_tile_ids, tile_ids.data(), tile_ids.size() * 4, hipMemcpyHostToDevice, st));
+        HIPX(stg.put(d_tile_ids, tile_ids.data(), tile_ids.size() * 4));
         ProfScope ps("rle1_tiles", st, bytes);
         HIPX(rle1_tiles(in, (uint32_t)tile_ids.size(), d_tile_ids, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab,
                         ctx->crc_tab + CRC_POW_AT, d_rt[nxt], st));
@@ -615,7 +650,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
       if (rle_n[b] > limit) over.push_back(b);
     if (over.empty()) break;
     if (iter > 64) return fail(ctx, BZG_EINVAL, "internal: block cutting did not converge");
-    HIPX(hipMemcpyAsync(d_cut_ids, over.data(), over.size() * 4, hipMemcpyHostToDevice, st));
+    HIPX(stg.put(d_cut_ids, over.data(), over.size() * 4));
     HIPX(rle1_cut(in, (uint32_t)over.size(), d_cut_ids, d_blk_tile0, d_boff, d_tile_rs, d_tile_out, limit, d_cuts,
                   st));
     uint32_t* h_cut = (uint32_t*)pin;
@@ -711,7 +746,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   void* d_hws = c0.take<char>(huff_workspace_bytes(nb));
   void* d_stage = c0.take<char>(0);
   size_t stage_bytes = ctx->ws_cap[0] - c0.used;
-  HIPX(hipMemcpyAsync(d_rbase, rbase.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
+  HIPX(stg.put(d_rbase, rbase.data(), (nb + 1) * 8));
   {
     ProfScope ps("rle1_emit", st, (double)total + N);
     HIPX(rle1_emit(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, d_tile_rs, d_tile_out, d_rbase, d_text, st));
@@ -719,25 +754,25 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   // ---- BWT
   uint32_t *SA, *d_off;
   int rounds = 0;
-  hipError_t e = bwt_sort(d_text, roff, d_stage, stage_bytes, (RoundCounters*)pin, st, &SA, &d_off, &rounds, ctx->err);
+  hipError_t e = bwt_sort(d_text, roff, d_stage, stage_bytes, (RoundCounters*)pin, stg, &SA, &d_off, &rounds, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "bwt_sort") : BZG_EHIP;
   HIPX(bwt_output(d_text, d_off, nb, N, SA, d_L, d_primary, nullptr, st));
   // ---- MTF + RUNA/RUNB (the sort's scratch is free again)
-  HIPX(hipMemcpyAsync(d_roff, roff.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_sbase, sbase.data(), nb * 8, hipMemcpyHostToDevice, st));
+  HIPX(stg.put(d_roff, roff.data(), (nb + 1) * 4));
+  HIPX(stg.put(d_sbase, sbase.data(), nb * 8));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
-  e = mtf_run(d_L, d_roff, roff, d_stage, stage_bytes, d_syms, d_sbase, d_nsyms, d_inuse, d_freq, d_err, st, ctx->err);
+  e = mtf_run(d_L, d_roff, roff, d_stage, stage_bytes, d_syms, d_sbase, d_nsyms, d_inuse, d_freq, d_err, stg, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
   // ---- Huffman tables, layout
-  HIPX(hipMemcpyAsync(d_selb, selb.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st));
+  HIPX(stg.put(d_selb, selb.data(), (nb + 1) * 8));
   HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
-  if (natiles) HIPX(hipMemcpyAsync(d_atile_blk, atile_blk.data(), natiles * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
+  HIPX(stg.put(d_atile_blk, atile_blk.data(), natiles * 4));
+  HIPX(stg.put(d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4));
   HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,
                 natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
-  HIPX(hipMemcpyAsync(d_rb, rb.data(), (n_req + 1) * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_rout, out_off, n_req * 8, hipMemcpyHostToDevice, st));
+  HIPX(stg.put(d_rb, rb.data(), (n_req + 1) * 4));
+  HIPX(stg.put(d_rout, out_off, n_req * 8));
   HIPX(pack_layout(nb, n_req, d_rb, d_rout, d_tabs, 0, nullptr, d_blkbit, d_crc, d_info, st));
   uint64_t* h_info = (uint64_t*)pin;
   HIPX(hipMemcpyAsync(h_info, d_info, 16 * (size_t)n_req, hipMemcpyDeviceToHost, st));
@@ -760,8 +795,8 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
                 "stream " + std::to_string(short_r) + " needs " +
                     std::to_string((h_info[2 * short_r] + 31) / 32 * 4) + " bytes (4-byte rounded)");
   // ---- pack
-  if (nptiles) HIPX(hipMemcpyAsync(d_ptile_blk, ptile_blk.data(), nptiles * 4, hipMemcpyHostToDevice, st));
-  HIPX(hipMemcpyAsync(d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st));
+  HIPX(stg.put(d_ptile_blk, ptile_blk.data(), nptiles * 4));
+  HIPX(stg.put(d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4));
   {
     ProfScope ps("pack", st, 2.0 * N + (double)out_total);  // symbols in, streams out
     HIPX(zero_streams(n_req, max_words, d_rout, d_info, (uint32_t*)d_out, st));

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include <map>
 #include <string>
@@ -84,6 +85,32 @@ struct Bump {
     size_t a = (used + 255) & ~size_t(255);
     used = a + n * sizeof(T);
     return reinterpret_cast<T*>(base + a);
+  }
+};
+
+// Uploads of host arrays through a pinned arena.  A copy from pageable host
+// memory makes the host wait for the stream to reach it, which leaves the
+// GPU idle while the host prepares the next launches; from pinned memory the
+// copy stays asynchronous.  Each upload takes a fresh slice of the arena, so
+// no queued copy sees its source overwritten; when the arena is full the
+// stream is drained first and the arena reused.  It starts out full, so the
+// first upload of a call also waits for work the stream still holds.
+struct Stager {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  hipStream_t st = nullptr;
+  hipError_t put(void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes > cap) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    size_t at = (used + 255) & ~size_t(255);
+    if (at > cap || cap - at < bytes) {
+      const hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      at = 0;
+    }
+    memcpy(base + at, src, bytes);
+    used = at + bytes;
+    return hipMemcpyAsync(dst, base + at, bytes, hipMemcpyHostToDevice, st);
   }
 };
 

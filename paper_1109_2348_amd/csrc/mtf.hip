@@ -700,7 +700,8 @@ static uint32_t chunk_size(const std::vector<uint32_t>& h_off) {
 
 hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<uint32_t>& h_off, void* ws,
                    size_t ws_bytes, uint16_t* syms, const uint64_t* d_sym_base, uint32_t* nsyms, uint32_t* inuse,
-                   uint32_t* freq, uint32_t* err, hipStream_t st, std::string& emsg) {
+                   uint32_t* freq, uint32_t* err, Stager& stg, std::string& emsg) {
+  hipStream_t st = stg.st;
   const uint32_t nb = (uint32_t)h_off.size() - 1;
   const uint32_t ch = chunk_size(h_off);
   std::vector<uint32_t> chunk_blk, blk_chunk0(nb + 1);
@@ -729,9 +730,8 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   }
   hipError_t e;
   if (nc == 0) return hipSuccess;
-  if ((e = hipMemcpyAsync(d_chunk_blk, chunk_blk.data(), nc * 4, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
-    return e;
+  if ((e = stg.put(d_chunk_blk, chunk_blk.data(), nc * 4)) != hipSuccess) return e;
+  if ((e = stg.put(d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(inuse, 0, (size_t)nb * 32, st)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(freq, 0, (size_t)nb * MAXA * 4, st)) != hipSuccess) return e;
   const double n = h_off[nb];
