@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <limits>
+
 #define BZG_WAVE 64
 
 namespace bzg {
@@ -16,96 +18,133 @@ namespace bzg {
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane()) - 1ull; }
 
+// DPP lane moves (GFX9 controls): row_shr:n (0x110 + n) gives lane l of each
+// 16-lane row the value of lane l - n of the same row; row_bcast:15 (0x142)
+// gives a row lane 15 of the row before; row_bcast:31 (0x143) gives lane 31;
+// wave_shr:1 (0x138) gives lane l the value of lane l - 1.  ROW_MASK picks the
+// rows written.  Lanes not written, or without a source lane, get `idle`.
+// These move data through the VALU, with none of the LDS round trip of a
+// ds_bpermute shuffle.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t idle, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)idle, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_move(T idle, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(
+        T, dpp32<CTRL, ROW_MASK>(__builtin_bit_cast(uint32_t, idle), __builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t i = __builtin_bit_cast(uint64_t, idle), x = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = dpp32<CTRL, ROW_MASK>((uint32_t)i, (uint32_t)x);
+    const uint32_t hi = dpp32<CTRL, ROW_MASK>((uint32_t)(i >> 32), (uint32_t)(x >> 32));
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+// The value of lane 63, in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_last(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), BZG_WAVE - 1));
+  } else {
+    const uint64_t x = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, BZG_WAVE - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), BZG_WAVE - 1);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+// Inclusive scan over the wave for an associative op with identity `id`:
+// steps of 1, 2, 4, 8 lanes inside each 16-lane row, then each row takes the
+// total of the rows before it (row 1 from row 0 and row 3 from row 2, then
+// rows 2 and 3 from lane 31).
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_incl_scan(T v, T id, Op op) {
+  v = op(v, dpp_move<0x111, 0xF>(id, v));
+  v = op(v, dpp_move<0x112, 0xF>(id, v));
+  v = op(v, dpp_move<0x114, 0xF>(id, v));
+  v = op(v, dpp_move<0x118, 0xF>(id, v));
+  v = op(v, dpp_move<0x142, 0xA>(id, v));
+  v = op(v, dpp_move<0x143, 0xC>(id, v));
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T v) {
-#pragma unroll
-  for (int d = 1; d < BZG_WAVE; d <<= 1) {
-    T u = __shfl_up(v, d, BZG_WAVE);
-    if ((int)lane() >= d) v += u;
-  }
-  return v;
+  return wave_incl_scan(v, T(0), [](T a, T b) { return a + b; });
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_incl_max(T v) {
-#pragma unroll
-  for (int d = 1; d < BZG_WAVE; d <<= 1) {
-    T u = __shfl_up(v, d, BZG_WAVE);
-    if ((int)lane() >= d) v = u > v ? u : v;
-  }
-  return v;
+  return wave_incl_scan(v, std::numeric_limits<T>::lowest(), [](T a, T b) { return a > b ? a : b; });
+}
+
+__device__ __forceinline__ uint64_t wave_incl_or(uint64_t v) {
+  return wave_incl_scan(v, uint64_t(0), [](uint64_t a, uint64_t b) { return a | b; });
+}
+
+// Lane l gets lane l - 1's value; lane 0 gets `first`.
+template <typename T>
+__device__ __forceinline__ T wave_shr1(T first, T v) {
+  return dpp_move<0x138, 0xF>(first, v);
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, BZG_WAVE);
-  return v;
+  return wave_last(wave_incl_sum(v));
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    T u = __shfl_xor(v, d, BZG_WAVE);
-    v = u > v ? u : v;
-  }
-  return v;
+  return wave_last(wave_incl_max(v));
 }
 
 __device__ __forceinline__ uint32_t wave_xor(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v ^= __shfl_xor(v, d, BZG_WAVE);
-  return v;
+  return wave_last(wave_incl_scan(v, 0u, [](uint32_t a, uint32_t b) { return a ^ b; }));
 }
 
 // Exclusive sum over a workgroup of NT threads.  `sh` needs NT/64 + 1 slots.
-// Every thread must call it.  Returns the exclusive prefix; *total gets the sum.
+// Every thread must call it.  Returns the exclusive prefix; *total gets the
+// sum.  Each thread adds up the wave totals itself (a broadcast LDS read),
+// so no thread walks them alone between two barriers.
 template <typename T, int NT>
 __device__ __forceinline__ T block_excl_sum(T v, T* sh, T* total) {
   constexpr int NW = NT / BZG_WAVE;
-  T inc = wave_incl_sum(v);
+  const T inc = wave_incl_sum(v);
   const int w = threadIdx.x / BZG_WAVE;
   if (lane() == BZG_WAVE - 1) sh[w] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T acc = 0;
-    for (int i = 0; i < NW; i++) {
-      T t = sh[i];
-      sh[i] = acc;
-      acc += t;
-    }
-    sh[NW] = acc;
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < NW; i++) {
+    const T t = sh[i];
+    before += i < w ? t : T(0);
+    all += t;
   }
+  *total = all;
   __syncthreads();
-  T r = inc - v + sh[w];
-  *total = sh[NW];
-  __syncthreads();
-  return r;
+  return inc - v + before;
 }
 
 // Inclusive max over a workgroup (values must be >= `lo`).
 template <typename T, int NT>
 __device__ __forceinline__ T block_incl_max(T v, T* sh, T lo) {
   constexpr int NW = NT / BZG_WAVE;
-  T inc = wave_incl_max(v);
+  const T inc = wave_incl_max(v);
   const int w = threadIdx.x / BZG_WAVE;
   if (lane() == BZG_WAVE - 1) sh[w] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T acc = lo;
-    for (int i = 0; i < NW; i++) {
-      T t = sh[i];
-      sh[i] = acc;
-      acc = t > acc ? t : acc;
-    }
-    sh[NW] = acc;
+  T before = lo;
+#pragma unroll
+  for (int i = 0; i < NW; i++) {
+    const T t = sh[i];
+    before = (i < w && t > before) ? t : before;
   }
   __syncthreads();
-  T c = sh[w];
-  T r = c > inc ? c : inc;
-  __syncthreads();
-  return r;
+  return before > inc ? before : inc;
 }
 
 template <typename T, int NT>

@@ -451,8 +451,8 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
         before = q < w ? max(before, swl[q][v]) : before;
         all = max(all, swl[q][v]);
       }
-      const int up = __shfl_up(loc[v], 1, BZG_WAVE);
-      lastv[v] = max(carry[v], max(before, lane() ? up : INT_MIN));
+      const int up = wave_shr1(INT_MIN, loc[v]);  // lane 0: none before it
+      lastv[v] = max(carry[v], max(before, up));
       carry[v] = max(carry[v], all);
     }
     for (uint32_t g = g0; g < g1; g++) {

@@ -554,14 +554,8 @@ __device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g
       const uint64_t first_m = __ballot(valid && p < 0);
       const uint64_t last_m = __ballot(is_last);
       // N = lanes k that are the previous occurrence of some lane m < l
-      uint64_t incl = (valid && p >= 0) ? (1ull << p) : 0ull;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint64_t u = __shfl_up(incl, d, BZG_WAVE);
-        if ((int)l >= d) incl |= u;
-      }
-      uint64_t N = __shfl_up(incl, 1, BZG_WAVE);
-      if (l == 0) N = 0;
+      const uint64_t incl = wave_incl_or((valid && p >= 0) ? (1ull << p) : 0ull);
+      const uint64_t N = wave_shr1(uint64_t(0), incl);
       // below = #{first-occurrence lanes k < l with R_k < R_l}, one ballot
       // per bit of R from the top: at bit b, lanes that agree with R_l above
       // b and have a 0 where R_l has a 1 are smaller
