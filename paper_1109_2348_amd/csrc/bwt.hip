@@ -301,6 +301,9 @@ struct AppendCtx {
   uint32_t* head;   // packed offset -> segment index + 1
   uint32_t* owner;  // tile -> segment index
   RoundCounters* cnt;
+  // counter record cleared by workgroup 0 (nullable): the one the round
+  // after the next appends to, which nothing reads or writes meanwhile
+  RoundCounters* clr;
 };
 
 // Workgroup-aggregated append of up to `m` groups held by this thread
@@ -341,6 +344,10 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
     wg_base[2] = (uint32_t)tb;
   }
   __syncthreads();
+  if (a.clr && blockIdx.x == 0 && threadIdx.x == 0) {
+    a.clr->segs_small = 0ull;
+    a.clr->tiles_big = 0ull;
+  }
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
 #pragma unroll
   for (int g = 0; g < M; g++) {
@@ -1038,8 +1045,8 @@ struct BwtWork {
   SegRec* segs[2];
   uint32_t* head[2];
   uint32_t* owner[2];
-  RoundCounters* cnt;    // device [2]
-  RoundCounters* h_cnt;  // pinned host [2]
+  RoundCounters* cnt;    // device [3]: read by a round, appended to by it, cleared by it
+  RoundCounters* h_cnt;  // pinned host [3]
   uint32_t* d_off;       // device block offsets (nb+1)
 };
 
@@ -1070,7 +1077,7 @@ size_t bwt_workspace_bytes(uint32_t N, uint32_t nb) {
     add(z.head_cap * 4);
     add(z.owner_cap * 4);
   }
-  add(2 * sizeof(RoundCounters));
+  add(3 * sizeof(RoundCounters));
   add(((size_t)nb + 1) * 4);
   return b + 4096;
 }
@@ -1151,10 +1158,12 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   w.agg = bump.take<uint32_t>(z.owner_cap);
   for (int i = 0; i < 2; i++) {
     w.segs[i] = bump.take<SegRec>(z.seg_cap);
-    w.head[i] = bump.take<uint32_t>(z.head_cap);
     w.owner[i] = bump.take<uint32_t>(z.owner_cap);
   }
-  w.cnt = bump.take<RoundCounters>(2);
+  // both head arrays and the counter records in one range (one fill)
+  w.head[0] = bump.take<uint32_t>(z.head_cap);
+  w.head[1] = bump.take<uint32_t>(z.head_cap);
+  w.cnt = bump.take<RoundCounters>(3);
   w.d_off = bump.take<uint32_t>(nb + 1);
   if (bump.used > ws_bytes) {
     err = "bwt workspace too small";
@@ -1170,9 +1179,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     if (e != hipSuccess) return e;  \
   } while (0)
   BZG_TRY(stg.put(w.d_off, h_off.data(), (nb + 1) * 4));
-  BZG_TRY(hipMemsetAsync(w.head[0], 0, z.head_cap * 4, st));
-  BZG_TRY(hipMemsetAsync(w.head[1], 0, z.head_cap * 4, st));
-  BZG_TRY(hipMemsetAsync(w.cnt, 0, 2 * sizeof(RoundCounters), st));
+  BZG_TRY(hipMemsetAsync(w.head[0], 0, (size_t)((char*)(w.cnt + 3) - (char*)w.head[0]), st));
   uint32_t max_n = 0;
   for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
   // initial segments: every block as a large segment (a one-row block too:
@@ -1196,7 +1203,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
     uint32_t big_tiles = (uint32_t)owner0.size();
     uint32_t *kin, *vin;
     BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, text, st));
-    AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1]};
+    AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1], nullptr};
     {
       ProfScope ps("rename_a", st, 4.0 * init_elems);
       hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.agg);
@@ -1208,15 +1215,16 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
                          w.d_off, w.SA, w.rank, 4u, 0, 0, app);
     }
     BZG_TRY(hipGetLastError());
-    int cur = 1;
+    int cur = 1;  // segment lists and head arrays: double-buffered
+    int cc = 1;   // counter records: three, so a round clears the one it does not touch
     uint32_t h = 4;
     int bits = 1;
     while ((1u << bits) < max_n) bits++;
     const int passes = (bits + 7) / 8;
     for (;;) {
-      BZG_TRY(hipMemcpyAsync(&w.h_cnt[cur], &w.cnt[cur], sizeof(RoundCounters), hipMemcpyDeviceToHost, st));
+      BZG_TRY(hipMemcpyAsync(&w.h_cnt[cc], &w.cnt[cc], sizeof(RoundCounters), hipMemcpyDeviceToHost, st));
       BZG_TRY(hipStreamSynchronize(st));
-      RoundCounters c = w.h_cnt[cur];
+      RoundCounters c = w.h_cnt[cc];
       if (log_rounds)
         fprintf(stderr, "[bzg] sort round %d h=%u segments=%u small_rows=%u large_rows=%u large_tiles=%u\n", nround,
                 h, c.n_segs(), c.small_total(), c.big_active(), c.big_tiles());
@@ -1229,7 +1237,6 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       const int nxt = cur ^ 1;
       // round 0 (h = 4) sorts on the next 4 text bytes instead of ranks
       const bool text_round = h == 4;
-      BZG_TRY(hipMemsetAsync(&w.cnt[nxt], 0, sizeof(RoundCounters), st));
       const uint32_t nsmall = (c.small_total() + SMALL_T - 1) / SMALL_T;
       {
         ProfScope ps("gather", st, 12.0 * (text_round ? c.big_active() : c.active()));  // row, partner rank, key2
@@ -1237,13 +1244,14 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
         const uint32_t gsmall = text_round ? 0u : nsmall;
         if (gsmall + c.big_tiles())
           hipLaunchKernelGGL(k_gather, dim3(gsmall + c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.head[cur],
-                             w.owner[cur], &w.cnt[cur], gsmall, w.d_off, w.SA, w.rank,
+                             w.owner[cur], &w.cnt[cc], gsmall, w.d_off, w.SA, w.rank,
                              text_round ? text : nullptr, h, w.key);
       }
-      AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[nxt]};
+      const int cn = (cc + 1) % 3, cz = (cc + 2) % 3;
+      AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[cn], &w.cnt[cz]};
       if (nsmall) {
         ProfScope ps("small_sort", st, 16.0 * c.small_total());  // key2 and row in, row and rank out
-        hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cur],
+        hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cc],
                            w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
         // every tile reads the head entries of the next one too, so they are
         // cleared (for reuse two rounds later) only after the whole pass
@@ -1263,6 +1271,7 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
       }
       BZG_TRY(hipGetLastError());
       cur = nxt;
+      cc = cn;
       h *= 2;
     }
   }

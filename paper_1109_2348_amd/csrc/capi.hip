@@ -412,7 +412,6 @@ int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* h_offse
   if ((rc = ensure_stage(ctx, 65536 + 16 * (size_t)n_blocks + off[n_blocks] / 256, st, &stg))) return rc;
   HIPX(stg.put(d_off, off.data(), off.size() * 4));
   HIPX(stg.put(d_sbase, sbase.data(), sbase.size() * 8));
-  HIPX(hipMemsetAsync(d_err, 0, 16, st));
   hipError_t e = mtf_run(d_bwt + h_offsets[0], d_off, off, rest, ctx->ws_cap[1] - cv.used, d_syms, d_sbase, d_nsyms,
                          (uint32_t*)d_inuse, d_freq, d_err, stg, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
@@ -492,7 +491,6 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   HIPX(stg.put(d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4));
   HIPX(stg.put(d_atile_blk, atile_blk.data(), natiles * 4));
   HIPX(stg.put(d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4));
-  HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
   HIPX(huff_run(n_blocks, d_syms, d_sbase, d_nsyms, d_freq, true, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
                 d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
@@ -760,12 +758,10 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   // ---- MTF + RUNA/RUNB (the sort's scratch is free again)
   HIPX(stg.put(d_roff, roff.data(), (nb + 1) * 4));
   HIPX(stg.put(d_sbase, sbase.data(), nb * 8));
-  HIPX(hipMemsetAsync(d_err, 0, 16, st));
   e = mtf_run(d_L, d_roff, roff, d_stage, stage_bytes, d_syms, d_sbase, d_nsyms, d_inuse, d_freq, d_err, stg, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
   // ---- Huffman tables, layout
   HIPX(stg.put(d_selb, selb.data(), (nb + 1) * 8));
-  HIPX(hipMemsetAsync(d_gbits, 0, (ng + 1) * 8, st));
   HIPX(stg.put(d_atile_blk, atile_blk.data(), natiles * 4));
   HIPX(stg.put(d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4));
   HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,

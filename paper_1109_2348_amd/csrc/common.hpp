@@ -102,6 +102,10 @@ __device__ __forceinline__ T wave_max(T v) {
   return wave_last(wave_incl_max(v));
 }
 
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  return wave_last(wave_incl_scan(v, 0u, [](uint32_t a, uint32_t b) { return a | b; }));
+}
+
 __device__ __forceinline__ uint32_t wave_xor(uint32_t v) {
   return wave_last(wave_incl_scan(v, 0u, [](uint32_t a, uint32_t b) { return a ^ b; }));
 }

@@ -150,10 +150,13 @@ __device__ __forceinline__ uint64_t pack_costs(const BlockTables* T, int G, int 
   return c;
 }
 
-// Per block: sizes, the starting tables, cleared counters.
+// Per block: sizes, the starting tables, cleared counters, and zero data
+// bits for the block's group slots past its last group (the slots the final
+// assign pass does not write; the last block also clears the end slot).
 __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ nsyms, const uint32_t* __restrict__ freq,
                                                    const uint32_t* __restrict__ inuse, BlockTables* __restrict__ tabs,
-                                                   uint64_t* __restrict__ cost, uint32_t* __restrict__ tf) {
+                                                   uint64_t* __restrict__ cost, uint32_t* __restrict__ tf,
+                                                   const uint64_t* __restrict__ sel_base, uint64_t* __restrict__ gbits) {
   __shared__ uint32_t sf[MAXA];
   __shared__ int rng[MAXG][2];
   const uint32_t b = blockIdx.x;
@@ -163,6 +166,11 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
   const int a = (int)nu + 2;
   const uint32_t ns = nsyms[b];
   const int G = n_tables(ns, a);
+  {
+    const uint64_t gb0 = sel_base[b] + (ns + GROUP - 1) / GROUP, gb1 = sel_base[b + 1];
+    for (uint64_t g = gb0 + threadIdx.x; g < gb1; g += NT) gbits[g] = 0;
+    if (b + 1 == gridDim.x && threadIdx.x == 0) gbits[gb1] = 0;
+  }
   for (int v = threadIdx.x; v < a; v += NT) sf[v] = freq[(size_t)b * MAXA + v];
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -531,7 +539,7 @@ hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base,
   // symbol counts are known on the device only: no algorithmic bytes recorded
   {
     ProfScope ps("huff_setup", st, 0.0);
-    hipLaunchKernelGGL(k_huff_setup, dim3(nb), dim3(NT), 0, st, nsyms, freq, inuse, tabs, cost, tf);
+    hipLaunchKernelGGL(k_huff_setup, dim3(nb), dim3(NT), 0, st, nsyms, freq, inuse, tabs, cost, tf, sel_base, gbits);
   }
   for (int it = 0; it < 4; it++) {
     if (ntiles) {

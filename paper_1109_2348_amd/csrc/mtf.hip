@@ -121,11 +121,11 @@ __device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uin
 // Per chunk: D_X (distinct bytes by last occurrence, latest first), the
 // zero-run summary of its rows -- without the block's first row, whose MTF
 // index depends on the whole block's in-use set and is added by k_mtf_scan --
-// and the block's in-use bitmap (OR-ed in; the caller zeroes it).
+// and the chunk's in-use bitmap (8 words; k_mtf_scan ORs a block's chunks).
 template <uint32_t CH>
 __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
                                                   const uint32_t* blk_chunk0, const uint32_t* off,
-                                                  uint32_t* __restrict__ inuse, uint8_t* __restrict__ chunk_D,
+                                                  uint32_t* __restrict__ chunk_inuse, uint8_t* __restrict__ chunk_D,
                                                   uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
   constexpr int MITEMS = CH / NT;  // rows per thread
   __shared__ uint32_t last[256];
@@ -183,10 +183,11 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
     uint32_t x = threadIdx.x;
     uint32_t lx = last[x];
     const uint64_t present = __ballot(lx != 0);  // bytes 64w .. 64w+63
-    if (lane() == 0 && present) {
+    static_assert(NT == 4 * BZG_WAVE, "four waves cover the 256 bytes");
+    if (lane() == 0) {
       const uint32_t wv = threadIdx.x / BZG_WAVE;
-      if ((uint32_t)present) atomicOr(&inuse[g.b * 8 + 2 * wv], (uint32_t)present);
-      if ((uint32_t)(present >> 32)) atomicOr(&inuse[g.b * 8 + 2 * wv + 1], (uint32_t)(present >> 32));
+      chunk_inuse[(size_t)c * 8 + 2 * wv] = (uint32_t)present;
+      chunk_inuse[(size_t)c * 8 + 2 * wv + 1] = (uint32_t)(present >> 32);
     }
     if (lx) {
       uint32_t r = 0;
@@ -275,7 +276,8 @@ __device__ __forceinline__ uint32_t zs_out(const ZSum& p) {
 // One workgroup of SCAN_WAVES waves per block.  Writes every chunk's incoming
 // stack, carried zero count and output offset, and the block's symbol count.
 __global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
-    const uint32_t* blk_chunk0, const uint32_t* __restrict__ inuse, const uint8_t* __restrict__ L,
+    const uint32_t* blk_chunk0, const uint32_t* __restrict__ chunk_inuse, uint32_t* __restrict__ inuse,
+    uint32_t* __restrict__ freq, uint32_t* __restrict__ err, const uint8_t* __restrict__ L,
     const uint32_t* __restrict__ off, const uint8_t* __restrict__ chunk_D, const uint32_t* __restrict__ chunk_nD,
     const ZSum* __restrict__ chunk_sum, uint8_t* __restrict__ chunk_list, uint32_t* __restrict__ chunk_carry,
     uint32_t* __restrict__ chunk_out, uint32_t* __restrict__ nsyms) {
@@ -286,14 +288,31 @@ __global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
   __shared__ ZSum gz[SCAN_WAVES];
   const uint32_t b = blockIdx.x;
   const uint32_t l = lane(), w = threadIdx.x / BZG_WAVE;
+  __shared__ uint32_t sbm[8];
+  const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1], nc = c1 - c0;
+  // the block's in-use bitmap: wave w ORs word w over the block's chunks
+  // (and publishes it); the block's symbol counts start from zero
+  static_assert(SCAN_WAVES == 8, "one wave per bitmap word");
+  {
+    uint32_t x = 0;
+#pragma unroll 4
+    for (uint32_t c = c0 + l; c < c1; c += BZG_WAVE) x |= chunk_inuse[(size_t)c * 8 + w];
+    x = wave_or(x);
+    if (l == 0) {
+      sbm[w] = x;
+      inuse[b * 8 + w] = x;
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < (uint32_t)MAXA; i += SCAN_WAVES * BZG_WAVE) freq[(size_t)b * MAXA + i] = 0;
+  if (b == 0 && threadIdx.x < 4) err[threadIdx.x] = 0;  // the call's error flags (k_mtf_emit sets them)
+  __syncthreads();
   uint32_t bm[8], nu = 0;
   for (int j = 0; j < 8; j++) {
-    bm[j] = inuse[b * 8 + j];
+    bm[j] = sbm[j];
     nu += __popc(bm[j]);
   }
 #pragma unroll
   for (int j = 0; j < 4; j++) mem[w][j * 64 + l] = 0;
-  const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1], nc = c1 - c0;
   // the block's first row: MTF index 0 exactly when it holds the smallest
   // in-use byte (the front of the initial stack)
   uint32_t minb = 0;
@@ -718,6 +737,7 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   uint8_t* d_list = bump.take<uint8_t>((size_t)nc * 256);
   uint32_t* d_carry = bump.take<uint32_t>(nc + 1);
   uint32_t* d_out = bump.take<uint32_t>(nc + 1);
+  uint32_t* d_cin = bump.take<uint32_t>((size_t)nc * 8 + 8);
   if (bump.used > ws_bytes) {
     emsg = "mtf workspace too small";
     return hipErrorInvalidValue;
@@ -726,21 +746,20 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   if (nc == 0) return hipSuccess;
   if ((e = stg.put(d_chunk_blk, chunk_blk.data(), nc * 4)) != hipSuccess) return e;
   if ((e = stg.put(d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(inuse, 0, (size_t)nb * 32, st)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(freq, 0, (size_t)nb * MAXA * 4, st)) != hipSuccess) return e;
   const double n = h_off[nb];
   {
     ProfScope ps("mtf_state", st, n + 256.0 * nc);
     if (ch == MTF_CHUNK)
       hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK>, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off,
-                         inuse, d_D, d_nD, d_sum);
+                         d_cin, d_D, d_nD, d_sum);
     else
       hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK_SMALL>, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0,
-                         d_off, inuse, d_D, d_nD, d_sum);
+                         d_off, d_cin, d_D, d_nD, d_sum);
   }
   {
     ProfScope ps("mtf_scan", st, 512.0 * nc);
-    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, d_blk_chunk0, inuse, L, d_off, d_D, d_nD, d_sum,
+    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, d_blk_chunk0, d_cin, inuse, freq, err, L,
+                       d_off, d_D, d_nD, d_sum,
                        d_list, d_carry, d_out, nsyms);
   }
   {
@@ -754,7 +773,7 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
 size_t mtf_workspace_bytes(const std::vector<uint32_t>& h_off) {
   const uint32_t nb = (uint32_t)h_off.size() - 1;
   const size_t nc = count_chunks(h_off, chunk_size(h_off));
-  return 8 * 256 + (nc + 1) * (4 + 256 + 4 + sizeof(ZSum) + 256 + 4 + 4) + (nb + 1) * 4 + 4096;
+  return 9 * 256 + (nc + 1) * (4 + 256 + 4 + sizeof(ZSum) + 256 + 4 + 4 + 32) + (nb + 1) * 4 + 4096;
 }
 
 }  // namespace bzg
