@@ -1198,8 +1198,8 @@ hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, voi
   int nround = 0;
   const bool log_rounds = getenv("BZG_LOG") != nullptr;
   if (!segs0.empty()) {
-    BZG_TRY(stg.put(w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec)));
-    BZG_TRY(stg.put(w.owner[0], owner0.data(), owner0.size() * 4));
+    BZG_TRY(stg.put_span({{w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec)},
+                          {w.owner[0], owner0.data(), owner0.size() * 4}}));  // adjacent in the carve
     uint32_t big_tiles = (uint32_t)owner0.size();
     uint32_t *kin, *vin;
     BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, text, st));

@@ -410,8 +410,7 @@ int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* h_offse
   void* rest = cv.take<char>(0);
   Stager stg;
   if ((rc = ensure_stage(ctx, 65536 + 16 * (size_t)n_blocks + off[n_blocks] / 256, st, &stg))) return rc;
-  HIPX(stg.put(d_off, off.data(), off.size() * 4));
-  HIPX(stg.put(d_sbase, sbase.data(), sbase.size() * 8));
+  HIPX(stg.put_span({{d_off, off.data(), off.size() * 4}, {d_sbase, sbase.data(), sbase.size() * 8}}));
   hipError_t e = mtf_run(d_bwt + h_offsets[0], d_off, off, rest, ctx->ws_cap[1] - cv.used, d_syms, d_sbase, d_nsyms,
                          (uint32_t*)d_inuse, d_freq, d_err, stg, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
@@ -484,13 +483,14 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   void* d_hws = cv.take<char>(huff_workspace_bytes(n_blocks));
   Stager stg;
   if ((rc = ensure_stage(ctx, 65536 + 48 * (size_t)n_blocks + 4 * (size_t)(ntiles + natiles), st, &stg))) return rc;
-  HIPX(stg.put(d_sbase, sbase.data(), n_blocks * 8));
-  HIPX(stg.put(d_selb, selb.data(), (n_blocks + 1) * 8));
-  HIPX(stg.put(d_obyte, obyte.data(), (n_blocks + 1) * 8));
-  HIPX(stg.put(d_tile_blk, tile_blk.data(), ntiles * 4));
-  HIPX(stg.put(d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4));
-  HIPX(stg.put(d_atile_blk, atile_blk.data(), natiles * 4));
-  HIPX(stg.put(d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4));
+  // (the first three, and the four tile maps, are adjacent in the carve)
+  HIPX(stg.put_span({{d_sbase, sbase.data(), n_blocks * 8},
+                     {d_selb, selb.data(), (n_blocks + 1) * 8},
+                     {d_obyte, obyte.data(), (n_blocks + 1) * 8}}));
+  HIPX(stg.put_span({{d_tile_blk, tile_blk.data(), ntiles * 4},
+                     {d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4},
+                     {d_atile_blk, atile_blk.data(), natiles * 4},
+                     {d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4}}));
   HIPX(hipMemsetAsync(d_err, 0, 16, st));
   HIPX(huff_run(n_blocks, d_syms, d_sbase, d_nsyms, d_freq, true, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
                 d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
@@ -602,9 +602,9 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
     }
     blk_tile0[nb] = (uint32_t)tile_blk.size();
     ntiles = (uint32_t)tile_blk.size();
-    HIPX(stg.put(d_boff, boff.data(), (nb + 1) * 8));
-    HIPX(stg.put(d_tile_blk, tile_blk.data(), ntiles * 4));
-    HIPX(stg.put(d_blk_tile0, blk_tile0.data(), (nb + 1) * 4));
+    HIPX(stg.put_span({{d_boff, boff.data(), (nb + 1) * 8},
+                       {d_tile_blk, tile_blk.data(), ntiles * 4},
+                       {d_blk_tile0, blk_tile0.data(), (nb + 1) * 4}}));
     if (iter == 0) {
       ProfScope ps("rle1_tiles", st, (double)(boff[nb] - boff[0]));
       HIPX(rle1_tiles(in, ntiles, nullptr, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + CRC_POW_AT,
@@ -720,12 +720,16 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   uint8_t* d_L = c0.take<uint8_t>(N + 64);
   uint32_t* d_primary = c0.take<uint32_t>(nb);
   uint16_t* d_syms = c0.take<uint16_t>((size_t)N + nb + 64);
+  // arrays uploaded together are carved next to each other (one copy each group)
   uint64_t* d_sbase = c0.take<uint64_t>(nb);
+  uint32_t* d_roff = c0.take<uint32_t>(nb + 1);
   uint32_t* d_nsyms = c0.take<uint32_t>(nb);
   uint32_t* d_inuse = c0.take<uint32_t>((size_t)nb * 8);
   uint32_t* d_freq = c0.take<uint32_t>((size_t)nb * MAXA);
   uint32_t* d_err = c0.take<uint32_t>(4);
   uint64_t* d_selb = c0.take<uint64_t>(nb + 1);
+  uint32_t* d_atile_blk = c0.take<uint32_t>(natiles + 1);
+  uint32_t* d_ablk_tile0 = c0.take<uint32_t>(nb + 1);
   uint8_t* d_sel = c0.take<uint8_t>(ng + 1);
   uint8_t* d_selmtf = c0.take<uint8_t>(ng + 1);
   uint64_t* d_gbits = c0.take<uint64_t>(ng + 1);
@@ -738,9 +742,6 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   uint64_t* d_info = c0.take<uint64_t>(2 * (size_t)n_req + 2);
   uint32_t* d_rb = c0.take<uint32_t>(n_req + 1);
   uint64_t* d_rout = c0.take<uint64_t>(n_req);
-  uint32_t* d_roff = c0.take<uint32_t>(nb + 1);
-  uint32_t* d_atile_blk = c0.take<uint32_t>(natiles + 1);
-  uint32_t* d_ablk_tile0 = c0.take<uint32_t>(nb + 1);
   void* d_hws = c0.take<char>(huff_workspace_bytes(nb));
   void* d_stage = c0.take<char>(0);
   size_t stage_bytes = ctx->ws_cap[0] - c0.used;
@@ -756,19 +757,17 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "bwt_sort") : BZG_EHIP;
   HIPX(bwt_output(d_text, d_off, nb, N, SA, d_L, d_primary, nullptr, st));
   // ---- MTF + RUNA/RUNB (the sort's scratch is free again)
-  HIPX(stg.put(d_roff, roff.data(), (nb + 1) * 4));
-  HIPX(stg.put(d_sbase, sbase.data(), nb * 8));
+  HIPX(stg.put_span({{d_sbase, sbase.data(), nb * 8}, {d_roff, roff.data(), (nb + 1) * 4}}));
   e = mtf_run(d_L, d_roff, roff, d_stage, stage_bytes, d_syms, d_sbase, d_nsyms, d_inuse, d_freq, d_err, stg, ctx->err);
   if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
   // ---- Huffman tables, layout
-  HIPX(stg.put(d_selb, selb.data(), (nb + 1) * 8));
-  HIPX(stg.put(d_atile_blk, atile_blk.data(), natiles * 4));
-  HIPX(stg.put(d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4));
+  HIPX(stg.put_span({{d_selb, selb.data(), (nb + 1) * 8},
+                     {d_atile_blk, atile_blk.data(), natiles * 4},
+                     {d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4}}));
   HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,
                 natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
   HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
-  HIPX(stg.put(d_rb, rb.data(), (n_req + 1) * 4));
-  HIPX(stg.put(d_rout, out_off, n_req * 8));
+  HIPX(stg.put_span({{d_rb, rb.data(), (n_req + 1) * 4}, {d_rout, out_off, n_req * 8}}));
   HIPX(pack_layout(nb, n_req, d_rb, d_rout, d_tabs, 0, nullptr, d_blkbit, d_crc, d_info, st));
   uint64_t* h_info = (uint64_t*)pin;
   HIPX(hipMemcpyAsync(h_info, d_info, 16 * (size_t)n_req, hipMemcpyDeviceToHost, st));
@@ -791,8 +790,7 @@ int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, 
                 "stream " + std::to_string(short_r) + " needs " +
                     std::to_string((h_info[2 * short_r] + 31) / 32 * 4) + " bytes (4-byte rounded)");
   // ---- pack
-  HIPX(stg.put(d_ptile_blk, ptile_blk.data(), nptiles * 4));
-  HIPX(stg.put(d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4));
+  HIPX(stg.put_span({{d_ptile_blk, ptile_blk.data(), nptiles * 4}, {d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4}}));
   {
     ProfScope ps("pack", st, 2.0 * N + (double)out_total);  // symbols in, streams out
     HIPX(zero_streams(n_req, max_words, d_rout, d_info, (uint32_t*)d_out, st));

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <map>
 #include <string>
 #include <vector>
@@ -111,6 +112,43 @@ struct Stager {
     memcpy(base + at, src, bytes);
     used = at + bytes;
     return hipMemcpyAsync(dst, base + at, bytes, hipMemcpyHostToDevice, st);
+  }
+  // Several arrays that lie in one device range, uploaded with one copy:
+  // each source lands at its destination's offset in the range.  The bytes
+  // between the arrays are overwritten too, so only alignment padding or
+  // unused capacity of these same arrays may lie between them.
+  struct Piece {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  hipError_t put_span(std::initializer_list<Piece> ps) {
+    char *lo = nullptr, *hi = nullptr;
+    for (const Piece& p : ps) {
+      if (!p.bytes) continue;
+      char* d = (char*)p.dst;
+      if (!lo || d < lo) lo = d;
+      if (!hi || d + p.bytes > hi) hi = d + p.bytes;
+    }
+    if (!lo) return hipSuccess;
+    const size_t span = (size_t)(hi - lo);
+    if (span > cap) {
+      for (const Piece& p : ps) {
+        const hipError_t e = put(p.dst, p.src, p.bytes);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+    size_t at = (used + 255) & ~size_t(255);
+    if (at > cap || cap - at < span) {
+      const hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      at = 0;
+    }
+    for (const Piece& p : ps)
+      if (p.bytes) memcpy(base + at + ((char*)p.dst - lo), p.src, p.bytes);
+    used = at + span;
+    return hipMemcpyAsync(lo, base + at, span, hipMemcpyHostToDevice, st);
   }
 };
 

@@ -744,8 +744,9 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   }
   hipError_t e;
   if (nc == 0) return hipSuccess;
-  if ((e = stg.put(d_chunk_blk, chunk_blk.data(), nc * 4)) != hipSuccess) return e;
-  if ((e = stg.put(d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4)) != hipSuccess) return e;
+  if ((e = stg.put_span({{d_chunk_blk, chunk_blk.data(), nc * 4}, {d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4}})) !=
+      hipSuccess)
+    return e;
   const double n = h_off[nb];
   {
     ProfScope ps("mtf_state", st, n + 256.0 * nc);
