@@ -407,13 +407,27 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
     }
   }
   __syncthreads();
-  for (int i = tid; i < G * MAXA; i += NT) {
-    int t = i / MAXA, v = i % MAXA;
-    if (v < a) {
-      uint8_t L = lens[t][v];
-      uint32_t r = 0;
-      for (int u = 0; u < v; u++) r += (lens[t][u] == L) ? 1u : 0u;
-      T->code[t][v] = s_first[t][L] + r;
+  // code = the first code of its length + its rank among the table's
+  // symbols of that length, in symbol order.  One wave per table, 64 symbols
+  // at a time: lanes of equal length are found by ballots, and a per-length
+  // running count (LDS, this wave's own) carries the ranks across the rounds.
+  {
+    __shared__ uint32_t srun[NT / BZG_WAVE][MAXLEN + 2];
+    const int w = (int)(tid / BZG_WAVE);
+    const uint64_t lt = lanemask_lt();
+    for (int t = w; t < G; t += NT / BZG_WAVE) {
+      if (lane() < MAXLEN + 2) srun[w][lane()] = 0;
+      for (int k = 0; k * BZG_WAVE < a; k++) {
+        const int v = k * BZG_WAVE + (int)lane();
+        const bool ok = v < a;
+        const uint32_t L = ok ? lens[t][v] : 0u;
+        const uint64_t peers = match_digit8(L, __ballot(ok));
+        const uint32_t before = srun[w][L];
+        if (ok) T->code[t][v] = s_first[t][L] + before + (uint32_t)__popcll(peers & lt);
+        // the lowest lane of each length adds the round's count (the wave's
+        // LDS operations complete in order: every lane has read first)
+        if (ok && (uint32_t)(__ffsll((long long)peers) - 1) == lane()) srun[w][L] = before + (uint32_t)__popcll(peers);
+      }
     }
   }
   // selector MTF indices, SEL_CHUNK selectors at a time staged in LDS:

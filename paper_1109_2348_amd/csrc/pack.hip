@@ -198,30 +198,38 @@ __global__ __launch_bounds__(NT) void k_pack_header(const BlockTables* __restric
     }
     pos += tot;
   }
-  // code lengths, one table after another
-  for (uint32_t t = 0; t < G; t++) {
-    if (threadIdx.x == 0) put_bits(words, pos, T->len[t][0], 5);
-    pos += 5;
-    for (uint32_t c = 0; c < a; c += NT) {
-      uint32_t v = c + threadIdx.x;
-      uint32_t n = 0;
-      int d = 0;
-      if (v < a) {
-        int prev = v ? T->len[t][v - 1] : T->len[t][0];
-        d = (int)T->len[t][v] - prev;
-        n = 2u * (uint32_t)(d < 0 ? -d : d) + 1u;
-      }
-      uint64_t tt;
-      uint64_t q = pos + block_excl_sum<uint64_t, NT>((uint64_t)n, sh, &tt);
-      if (v < a) {
-        uint64_t code = 0;
-        uint32_t step = d < 0 ? 3u : 2u;
-        for (int i = 0; i < (d < 0 ? -d : d); i++) code = (code << 2) | step;
-        code <<= 1;
-        put_bits64(words, q, code, n);
-      }
-      pos += tt;
+  // code lengths, one table after another: each table's 5-bit start, then
+  // per symbol the delta code.  Lengths staged in LDS; one workgroup scan of
+  // all tables' bit counts (thread-contiguous items: table i / a, symbol i % a)
+  __shared__ uint8_t slen[MAXG][MAXA];
+  __syncthreads();
+  stage_to_lds<NT, 8>(&slen[0][0], &T->len[0][0], G * MAXA);
+  __syncthreads();
+  constexpr uint32_t PI = (MAXG * MAXA + NT - 1) / NT;  // items per thread (<= 7)
+  const uint32_t nit = G * a;
+  const uint32_t i0 = min(threadIdx.x * PI, nit), i1 = min(i0 + PI, nit);
+  uint64_t mine = 0;
+  for (uint32_t i = i0; i < i1; i++) {
+    const uint32_t t = i / a, v = i % a;
+    const int d = (int)slen[t][v] - (int)slen[t][v ? v - 1 : 0];
+    mine += (v == 0 ? 5u : 0u) + 2u * (uint32_t)(d < 0 ? -d : d) + 1u;
+  }
+  uint64_t tt;
+  uint64_t q = pos + block_excl_sum<uint64_t, NT>(mine, sh, &tt);
+  for (uint32_t i = i0; i < i1; i++) {
+    const uint32_t t = i / a, v = i % a;
+    if (v == 0) {
+      put_bits(words, q, slen[t][0], 5);
+      q += 5;
     }
+    const int d = (int)slen[t][v] - (int)slen[t][v ? v - 1 : 0];
+    const uint32_t ad = (uint32_t)(d < 0 ? -d : d), n = 2u * ad + 1u;
+    uint64_t code = 0;
+    const uint32_t step = d < 0 ? 3u : 2u;
+    for (uint32_t k = 0; k < ad; k++) code = (code << 2) | step;
+    code <<= 1;
+    put_bits64(words, q, code, n);
+    q += n;
   }
 }
 
