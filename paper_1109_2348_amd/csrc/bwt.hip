@@ -733,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // leaves equal-rotation groups to the next round.
 // Segments of at most this many rows are ordered by counting instead of the
 // tile's radix passes.
-constexpr uint32_t COUNT_SORT_MAX = 32;
+constexpr uint32_t COUNT_SORT_MAX = 64;
 
 __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
                                                    const RoundCounters* cnt, const uint32_t* __restrict__ blk_off,

@@ -47,7 +47,7 @@ constexpr uint32_t SMALL_T = 1024;     // packed elements per small-segment tile
 constexpr uint32_t SMALL_MAX = 1024;   // segments up to this size are sorted in LDS
 constexpr uint32_t SMALL_CAP = SMALL_T + SMALL_MAX;  // LDS capacity of a small tile
 constexpr uint32_t RLE_TILE = 4096;    // input bytes per RLE1/CRC tile
-constexpr uint32_t MTF_CHUNK = 8192;   // symbols per move-to-front chunk
+constexpr uint32_t MTF_CHUNK = 4096;   // symbols per move-to-front chunk
 constexpr uint32_t MAX_BLOCK = 1u << 21;  // largest block the sort accepts (ranks fit 21 bits)
 constexpr int GROUP = 50;              // symbols per Huffman selector group
 constexpr int MAXG = 6, MAXA = 258, MAXLEN = 17;

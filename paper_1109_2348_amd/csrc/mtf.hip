@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   last[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_nd = 0;
   __syncthreads();
-  // rows [lo + t*32, +32): last occurrences and the zero-run summary
+  // rows [lo + t*MITEMS, +MITEMS): last occurrences and the zero-run summary
   const uint32_t r0 = g.lo + threadIdx.x * MITEMS;
   uint8_t v[MITEMS];
   uint32_t prev = 0x100u;
