@@ -44,6 +44,7 @@ struct HuffScratch {
   uint32_t key[MAXA];  // (weight << 9) | id
   uint32_t lw[MAXA];   // leaf weights in key order
   uint16_t order[MAXA];
+  uint32_t ids2[MAXA];  // order[i] | order[min(i + 1, a - 1)] << 16: both leaf heads in one read
   uint16_t parent[2 * MAXA];
 };
 
@@ -83,6 +84,8 @@ __device__ void huff_pass_wave(int a, HuffScratch* hs) {
     }
   }
   __builtin_amdgcn_wave_barrier();
+  for (int i = l; i < a; i += 64) hs->ids2[i] = (uint32_t)hs->order[i] | ((uint32_t)hs->order[min(i + 1, a - 1)] << 16);
+  __builtin_amdgcn_wave_barrier();
   // Two-queue merge: leaves by (weight, id) in hs->lw / hs->order, internal
   // nodes in creation order (their weights never decrease) in hs->w (free
   // after the ranking).  Each step reads both heads of both queues in one
@@ -96,8 +99,12 @@ __device__ void huff_pass_wave(int a, HuffScratch* hs) {
     const uint32_t l0 = min(li, A_ - 1u), l1 = min(li + 1u, A_ - 1u);
     const uint32_t n0 = min(ni, A_ - 2u), n1 = min(ni + 1u, A_ - 2u);
     const uint32_t lwa = hs->lw[l0], lwb = hs->lw[l1];
-    const uint32_t ida = hs->order[l0], idb = hs->order[l1];
+    const uint32_t ids = hs->ids2[l0];  // order[l0] and order[l1] (l1 = min(l0 + 1, A_ - 1))
     const uint32_t wna = wn[n0], wnb = wn[n1];
+    // ids is used only by lane 0's writes: without this the compiler moves
+    // its read into that branch and waits for it there, a second round trip
+    asm volatile("" ::"v"(ids));
+    const uint32_t ida = ids & 0xFFFFu, idb = ids >> 16;
     const uint32_t A0 = li < A_ ? lwa : INF, A1 = li + 1u < A_ ? lwb : INF;
     const uint32_t B0 = ni < nn ? wna : INF, B1 = ni + 1u < nn ? wnb : INF;
     const bool p1 = A0 <= B0;  // first pick is a leaf
