@@ -672,17 +672,25 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
     for (int half = 0; half < 2; half++) {
       SegRec rr[PL];
       uint32_t sa[PL], bo[PL], bn[PL], ps[PL], kv[PL];
+      // LDS reads unconditional (positions < SMALL_CAP), the record load from
+      // a clamped index: no read waits alone inside a branch
+      uint32_t spv[PL], mkv[PL];
+#pragma unroll
+      for (int j = 0; j < PL; j++) spv[j] = segp[(half * PL + j) * NT + threadIdx.x];
+#pragma unroll
+      for (int j = 0; j < PL; j++) mkv[j] = mark[spv[j] != NO_SEG ? spv[j] : 0u];
 #pragma unroll
       for (int j = 0; j < PL; j++) {
         const uint32_t p = (half * PL + j) * NT + threadIdx.x;
-        rr[j] = SegRec{0, 0, 0, 0};
-        if (p < n && segp[p] != NO_SEG) rr[j] = segs[mark[segp[p]] - 1];
+        const bool has = (p < n) & (spv[j] != NO_SEG);
+        const SegRec r = segs[has ? mkv[j] - 1u : 0u];
+        rr[j] = has ? r : SegRec{0, 0, 0, 0};
       }
       // positions without a row read row 0 of block 0 (loads stay unbranched)
 #pragma unroll
       for (int j = 0; j < PL; j++) {
         const uint32_t p = (half * PL + j) * NT + threadIdx.x;
-        ps[j] = rr[j].len ? p - segp[p] : 0u;
+        ps[j] = rr[j].len ? p - spv[j] : 0u;
       }
 #pragma unroll
       for (int j = 0; j < PL; j++) {

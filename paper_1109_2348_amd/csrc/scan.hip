@@ -15,11 +15,11 @@ __global__ __launch_bounds__(NT) void k_scan_reduce(const T* __restrict__ in, si
   __shared__ T sh[NT / BZG_WAVE + 1];
   size_t base = (size_t)blockIdx.x * SCAN_TILE;
   T acc = 0;
+  T x[SCAN_ITEMS];  // clamped loads, all in flight before any is added (n >= 1)
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; i++) {
-    size_t k = base + (size_t)i * NT + threadIdx.x;
-    if (k < n) acc += in[k];
-  }
+  for (int i = 0; i < SCAN_ITEMS; i++) x[i] = in[min(base + (size_t)i * NT + threadIdx.x, n - 1)];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) acc += base + (size_t)i * NT + threadIdx.x < n ? x[i] : T(0);
   T tot = block_sum<T, NT>(acc, sh);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(NT) void k_scan_sums(T* sums, size_t ntiles) {
   T carry = 0;
   for (size_t b = 0; b < ntiles; b += NT) {
     size_t k = b + threadIdx.x;
-    T v = k < ntiles ? sums[k] : T(0);
+    T v = sums[min(k, ntiles - 1)];  // clamped (ntiles >= 1)
+    v = k < ntiles ? v : T(0);
     T tot;
     T ex = block_excl_sum<T, NT>(v, sh, &tot);
     if (k < ntiles) sums[k] = ex + carry;
@@ -45,9 +46,10 @@ __global__ __launch_bounds__(NT) void k_scan_down(const T* in, T* out, size_t n,
   T v[SCAN_ITEMS];
   T acc = 0;
 #pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) v[i] = in[min(base + i, n - 1)];  // clamped (n >= 1)
+#pragma unroll
   for (int i = 0; i < SCAN_ITEMS; i++) {
-    size_t k = base + i;
-    v[i] = k < n ? in[k] : T(0);
+    v[i] = base + i < n ? v[i] : T(0);
     acc += v[i];
   }
   T tot;
