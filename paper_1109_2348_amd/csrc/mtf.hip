@@ -213,12 +213,14 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
 // Chunk summaries compose associatively: after chunk X the stack is D_X
 // followed by the rest of the incoming stack in order, and after X then Y it
 // is D_Y, then D_X minus D_Y, then the rest; zero-run summaries compose by
-// zcombine.  So a block's chunks are scanned by SCAN_WAVES waves in three
-// steps: each wave composes the summaries of one contiguous range of chunks;
-// one wave turns those into every range's incoming stack and prefix
-// summary; each wave then walks its range from there.  The serial depth is
-// about 2 * chunks / SCAN_WAVES + SCAN_WAVES steps instead of chunks.
-constexpr int SCAN_WAVES = 8;
+// zcombine.  So a block's chunks are scanned by SW waves in three steps:
+// each wave composes the summaries of one contiguous range of chunks; one
+// wave turns those into every range's incoming stack and prefix summary;
+// each wave then walks its range from there.  The serial depth is about
+// 2 * chunks / SW + SW steps instead of chunks: 16 waves when blocks hold
+// many chunks, 8 otherwise.
+constexpr int SCAN_WAVES = 8, SCAN_WAVES_LARGE = 16;
+constexpr uint32_t SCAN_LARGE_CHUNKS = 64;  // average chunks per block from which 16 waves pay
 
 // Between the steps of one wave's serial work in LDS (no workgroup barrier:
 // the waves run independent loops).
@@ -273,27 +275,28 @@ __device__ __forceinline__ uint32_t zs_out(const ZSum& p) {
   return p.all ? 0u : p.nnz + p.inner + run_digits(p.lz);
 }
 
-// One workgroup of SCAN_WAVES waves per block.  Writes every chunk's incoming
+// One workgroup of SW waves per block.  Writes every chunk's incoming
 // stack, carried zero count and output offset, and the block's symbol count.
-__global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
+template <int SW>
+__global__ __launch_bounds__(SW * BZG_WAVE) void k_mtf_scan(
     const uint32_t* blk_chunk0, const uint32_t* __restrict__ chunk_inuse, uint32_t* __restrict__ inuse,
     uint32_t* __restrict__ freq, uint32_t* __restrict__ err, const uint8_t* __restrict__ L,
     const uint32_t* __restrict__ off, const uint8_t* __restrict__ chunk_D, const uint32_t* __restrict__ chunk_nD,
     const ZSum* __restrict__ chunk_sum, uint8_t* __restrict__ chunk_list, uint32_t* __restrict__ chunk_carry,
     uint32_t* __restrict__ chunk_out, uint32_t* __restrict__ nsyms) {
-  __shared__ uint32_t tmp[SCAN_WAVES][256];
-  __shared__ uint8_t mem[SCAN_WAVES][256];
-  __shared__ uint8_t gD[SCAN_WAVES][256];  // each range's composed D (then incoming stack)
-  __shared__ uint32_t gn[SCAN_WAVES];
-  __shared__ ZSum gz[SCAN_WAVES];
+  __shared__ uint32_t tmp[SW][256];
+  __shared__ uint8_t mem[SW][256];
+  __shared__ uint8_t gD[SW][256];  // each range's composed D (then incoming stack)
+  __shared__ uint32_t gn[SW];
+  __shared__ ZSum gz[SW];
   const uint32_t b = blockIdx.x;
   const uint32_t l = lane(), w = threadIdx.x / BZG_WAVE;
   __shared__ uint32_t sbm[8];
   const uint32_t c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1], nc = c1 - c0;
   // the block's in-use bitmap: wave w ORs word w over the block's chunks
   // (and publishes it); the block's symbol counts start from zero
-  static_assert(SCAN_WAVES == 8, "one wave per bitmap word");
-  {
+  static_assert(SW >= 8, "one wave per bitmap word");
+  if (w < 8) {
     uint32_t x = 0;
 #pragma unroll 4
     for (uint32_t c = c0 + l; c < c1; c += BZG_WAVE) x |= chunk_inuse[(size_t)c * 8 + w];
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
       inuse[b * 8 + w] = x;
     }
   }
-  for (uint32_t i = threadIdx.x; i < (uint32_t)MAXA; i += SCAN_WAVES * BZG_WAVE) freq[(size_t)b * MAXA + i] = 0;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)MAXA; i += SW * BZG_WAVE) freq[(size_t)b * MAXA + i] = 0;
   if (b == 0 && threadIdx.x < 4) err[threadIdx.x] = 0;  // the call's error flags (k_mtf_emit sets them)
   __syncthreads();
   uint32_t bm[8], nu = 0;
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
   const ZSum e0 = row0_zero ? ZSum{1, 1, 0, 0, 1, 1} : ZSum{0, 0, 0, 1, 1, 0};
   const ZSum zid = {0, 0, 0, 0, 0, 1};
   // this wave's chunk range
-  const uint32_t per = (nc + SCAN_WAVES - 1) / SCAN_WAVES;
+  const uint32_t per = (nc + SW - 1) / SW;
   const uint32_t r0 = c0 + min(w * per, nc), r1 = c0 + min(w * per + per, nc);
   auto load_d = [&](uint32_t c, uint32_t dx[4], uint32_t& nd, ZSum& z) {
     nd = chunk_nD[c];
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(SCAN_WAVES * BZG_WAVE) void k_mtf_scan(
     for (int j = 0; j < 4; j++) e[j] = (uint32_t)(j * 64) + l < nu ? tmp[0][j * 64 + l] : 0x100u;
     wave_sync();
     ZSum p = zid;
-    for (int q = 0; q < SCAN_WAVES; q++) {
+    for (int q = 0; q < SW; q++) {
       uint32_t dx[4];
       const uint32_t nd = gn[q];
 #pragma unroll
@@ -759,9 +762,12 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
   }
   {
     ProfScope ps("mtf_scan", st, 512.0 * nc);
-    hipLaunchKernelGGL(k_mtf_scan, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, d_blk_chunk0, d_cin, inuse, freq, err, L,
-                       d_off, d_D, d_nD, d_sum,
-                       d_list, d_carry, d_out, nsyms);
+    if (nc >= SCAN_LARGE_CHUNKS * nb)
+      hipLaunchKernelGGL(k_mtf_scan<SCAN_WAVES_LARGE>, dim3(nb), dim3(SCAN_WAVES_LARGE * BZG_WAVE), 0, st, d_blk_chunk0,
+                         d_cin, inuse, freq, err, L, d_off, d_D, d_nD, d_sum, d_list, d_carry, d_out, nsyms);
+    else
+      hipLaunchKernelGGL(k_mtf_scan<SCAN_WAVES>, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, d_blk_chunk0, d_cin,
+                         inuse, freq, err, L, d_off, d_D, d_nD, d_sum, d_list, d_carry, d_out, nsyms);
   }
   {
     ProfScope ps("mtf_emit", st, 3.0 * n);  // read L, write at most one 2-byte symbol per row
