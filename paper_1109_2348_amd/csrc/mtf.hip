@@ -128,12 +128,16 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
                                                   uint32_t* __restrict__ chunk_inuse, uint8_t* __restrict__ chunk_D,
                                                   uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
   constexpr int MITEMS = CH / NT;  // rows per thread
+  constexpr uint32_t PW = CH / 32;  // words of the last-occurrence position bitmap
   __shared__ uint32_t last[256];
+  __shared__ uint32_t pbits[PW], psuf[PW];
+  __shared__ uint32_t ssh[NT / BZG_WAVE + 1];
   __shared__ ZSum wsum[NT / BZG_WAVE];
   __shared__ uint32_t s_nd;
   const uint32_t c = blockIdx.x;
   ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off, CH);
   last[threadIdx.x] = 0;
+  for (uint32_t i = threadIdx.x; i < PW; i += NT) pbits[i] = 0;
   if (threadIdx.x == 0) s_nd = 0;
   __syncthreads();
   // rows [lo + t*MITEMS, +MITEMS): last occurrences and the zero-run summary
@@ -189,9 +193,20 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
       chunk_inuse[(size_t)c * 8 + 2 * wv] = (uint32_t)present;
       chunk_inuse[(size_t)c * 8 + 2 * wv + 1] = (uint32_t)(present >> 32);
     }
+    // rank = present bytes whose last occurrence is later: the positions
+    // (distinct, 1..CH) go into a bitmap, and a byte's rank is the number of
+    // set bits above its own (suffix counts per word from one scan)
+    if (lx) atomicOr(&pbits[(lx - 1u) >> 5], 1u << ((lx - 1u) & 31u));
+    __syncthreads();
+    static_assert(PW <= NT, "one bitmap word per thread");
+    const uint32_t wc = threadIdx.x < PW ? (uint32_t)__popc(pbits[PW - 1u - threadIdx.x]) : 0u;
+    uint32_t all;
+    const uint32_t above = block_excl_sum<uint32_t, NT>(wc, ssh, &all);  // bits in words after it
+    if (threadIdx.x < PW) psuf[PW - 1u - threadIdx.x] = above;
+    __syncthreads();
     if (lx) {
-      uint32_t r = 0;
-      for (int u = 0; u < 256; u++) r += (last[u] > lx) ? 1u : 0u;
+      const uint32_t q = lx - 1u;
+      const uint32_t r = psuf[q >> 5] + (uint32_t)__popc((pbits[q >> 5] >> (q & 31u)) >> 1);
       chunk_D[(size_t)c * 256 + r] = (uint8_t)x;
       atomicAdd(&s_nd, 1u);
     }
