@@ -254,19 +254,16 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
   const uint32_t j = blockIdx.x;
   const uint32_t b = tile_blk[j];
   const BlockTables* T = &tabs[b];
-  const uint32_t nsel = T->nsel, G = T->G, a = T->alpha;
+  const uint32_t nsel = T->nsel, G = T->G;
   const uint32_t g0 = (j - blk_tile0[b]) * PACK_GROUPS;
   if (g0 >= nsel) return;
   const uint32_t g1 = min(g0 + PACK_GROUPS, nsel);
   const uint32_t ns = nsyms[b];
   const uint32_t s0 = g0 * GROUP, s1 = min(g1 * GROUP, ns);
-  for (uint32_t i = threadIdx.x; i < G * MAXA; i += NT) {
-    uint32_t t = i / MAXA, v = i % MAXA;
-    if (v < a) {
-      slen[t][v] = T->len[t][v];
-      scode[t][v] = T->code[t][v];
-    }
-  }
+  // the block's tables (whole rows of the G tables; entries past the
+  // alphabet are copied but never read), loads batched and unbranched
+  stage_to_lds<NT, 8>(&slen[0][0], &T->len[0][0], G * MAXA);
+  stage_to_lds<NT, 8>(&scode[0][0], &T->code[0][0], G * MAXA);
   for (uint32_t i = threadIdx.x; i < WCAP; i += NT) stage[i] = 0;
   const uint64_t sb = sel_base[b];
   const uint64_t data0 = blk_bit[b] + (mode == 0 ? 105u : 0u) + T->hdr_bits;
