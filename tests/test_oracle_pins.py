@@ -247,7 +247,7 @@ def test_initial_partition_each_table_nonempty():
             assert all(c >= 1 for c in cover) and sum(cover) == a
 
 
-# ------------------------------------------------- stock bzip2 as the judge
+# ----------------------------------------------- stock bzip2 as the arbiter
 
 INPUTS = [b"", b"a", b"ab", b"banana", b"abab", b"abcabcabc", b"mississippi",
           b"a" * 4, b"a" * 5, b"a" * 255, b"a" * 256, b"a" * 1000, b"ab" * 700,
