@@ -180,29 +180,56 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
   }
   for (int v = threadIdx.x; v < a; v += NT) sf[v] = freq[(size_t)b * MAXA + v];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T->G = (uint32_t)G;
-    T->nsel = (ns + GROUP - 1) / GROUP;
-    T->alpha = (uint32_t)a;
-    T->data_bits = 0;
+  // inclusive prefix sums of the counts (two symbols per thread): a table's
+  // range sum is then a difference of two of them
+  __shared__ uint32_t spre[MAXA];
+  __shared__ uint32_t ssh[NT / BZG_WAVE + 1];
+  static_assert(2 * NT >= MAXA, "two symbols per thread");
+  {
+    const int v0 = 2 * (int)threadIdx.x, v1 = v0 + 1;
+    const uint32_t f0 = v0 < a ? sf[v0] : 0u, f1 = v1 < a ? sf[v1] : 0u;
+    uint32_t all;
+    const uint32_t ex = block_excl_sum<uint32_t, NT>(f0 + f1, ssh, &all);
+    if (v0 < a) spre[v0] = ex + f0;
+    if (v1 < a) spre[v1] = ex + f0 + f1;
+  }
+  __syncthreads();
+  // The partition, one table after another: each table takes symbols from
+  // gs on until its count times the tables left reaches the remaining count,
+  // leaving at least one symbol per later table.  Wave 0 tests 64 candidate
+  // range ends at a time and takes the first that stops.
+  if (threadIdx.x < BZG_WAVE) {
+    const int l = (int)lane();
+    if (l == 0) {
+      T->G = (uint32_t)G;
+      T->nsel = (ns + GROUP - 1) / GROUP;
+      T->alpha = (uint32_t)a;
+      T->data_bits = 0;
+    }
     uint64_t rem = ns;
     int gs = 0;
     for (int t = 0; t < G; t++) {
-      int left = G - t, ge;
+      const int left = G - t;
+      int ge;
       uint64_t acc;
       if (left == 1) {
         ge = a - 1;
         acc = rem;
       } else {
-        ge = gs;
-        acc = sf[gs];
-        while (ge + 1 <= a - left && acc * (uint64_t)left < rem) {
-          ge++;
-          acc += sf[ge];
+        const uint32_t before = gs ? spre[gs - 1] : 0u;
+        ge = -1;
+        for (int base = gs; ge < 0; base += BZG_WAVE) {  // ends by base + 63 >= a - left
+          const int v = base + l;
+          const uint64_t sum = (uint64_t)(spre[min(v, a - 1)] - before);
+          const uint64_t m = __ballot((v >= a - left) || (sum * (uint64_t)left >= rem));
+          if (m) ge = base + (int)__ffsll((long long)m) - 1;
         }
+        acc = (uint64_t)(spre[ge] - before);
       }
-      rng[t][0] = gs;
-      rng[t][1] = ge;
+      if (l == 0) {
+        rng[t][0] = gs;
+        rng[t][1] = ge;
+      }
       rem -= acc;
       gs = ge + 1;
     }
