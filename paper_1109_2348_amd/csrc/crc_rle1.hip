@@ -185,6 +185,11 @@ __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, c
                                                     uint32_t* crc_out) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
   __shared__ uint32_t sx[NT];
+  // the powers x^(8 * 2^j) in LDS: the shifts below take one per set bit of
+  // a byte count, each read right before its use
+  __shared__ uint32_t spw[64];
+  if (threadIdx.x < 64) spw[threadIdx.x] = crc_pow[threadIdx.x];
+  __syncthreads();
   const uint32_t b = blockIdx.x;
   const uint32_t t0 = blk_tile0[b], t1 = blk_tile0[b + 1];
   const uint32_t n = (uint32_t)(blk_off[b + 1] - blk_off[b]);
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, c
       tile_out[t] = carry_out + ex;
       tile_rs[t] = rs;  // run start carried into the tile (+1)
     }
-    if (t < t1) x ^= gf2_mulmod(r.crc, gf2_xpow8((uint64_t)(n - min(lo + RLE_TILE, n)), crc_pow));
+    if (t < t1) x ^= gf2_mulmod(r.crc, gf2_xpow8((uint64_t)(n - min(lo + RLE_TILE, n)), spw));
     carry_out += tot;
     carry_rs = sx[NT - 1] > carry_rs ? sx[NT - 1] : carry_rs;
     __syncthreads();
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, c
   if (threadIdx.x == 0) {
     uint32_t c = 0;
     for (int i = 0; i < NT / BZG_WAVE; i++) c ^= sx[i];
-    uint32_t init = gf2_mulmod(0xFFFFFFFFu, gf2_xpow8((uint64_t)n, crc_pow));
+    uint32_t init = gf2_mulmod(0xFFFFFFFFu, gf2_xpow8((uint64_t)n, spw));
     crc_out[b] = ~(init ^ c);
     rle_n[b] = carry_out;
   }
