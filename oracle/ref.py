@@ -398,8 +398,9 @@ def initial_tables(freq: Sequence[int], n_groups: int) -> List[List[int]]:
     return tables
 
 
-def choose_tables(syms: Sequence[int], alpha_size: int):
-    """Returns (lengths per table, selectors)."""
+def choose_tables(syms: Sequence[int], alpha_size: int, n_iters: int = N_ITERS):
+    """Returns (lengths per table, selectors) after n_iters refinement passes
+    (the tests pin single passes with n_iters=1)."""
     n = len(syms)
     freq = [0] * alpha_size
     for s in syms:
@@ -408,7 +409,7 @@ def choose_tables(syms: Sequence[int], alpha_size: int):
     n_sel = (n + GROUP - 1) // GROUP
     lens = initial_tables(freq, g)
     sel = [0] * n_sel
-    for _ in range(N_ITERS):
+    for _ in range(n_iters):
         tf = [[0] * alpha_size for _ in range(g)]
         for j in range(n_sel):
             grp = syms[j * GROUP:(j + 1) * GROUP]
