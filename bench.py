@@ -1,17 +1,16 @@
 """Benchmark of the bzip2 compression stages on one MI355X.  Prints one JSON
 line.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--config 2]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--config 4]
 
---config 2 (default): whole-pipeline compression (CRC, RLE1, BWT, MTF,
-    RUNA/RUNB, Huffman, packing) of 64 MiB in 900,000-byte blocks, input
-    resident in HBM, batched (one call for all blocks) and per-block (one
-    call per block).
+--config 4 (default): whole-pipeline compression (CRC, RLE1, BWT, MTF,
+    RUNA/RUNB, Huffman, packing) of 8192 blocks of log-uniform size
+    1,000..900,000 bytes (uniform/text/sparse thirds), input resident in HBM,
+    batched (one call for all blocks) and per-block (one call per block).
 --config 1: one 100,000-byte block at level 1 (launch-latency point).
+--config 2: 64 MiB in 900,000-byte blocks, batched vs per-block.
 --config 3: the sort alone (bwt_forward_batch) on 256 x 900,000-byte
     periodic / all-same blocks (up to 18 doubling rounds).
---config 4: 8192 blocks of log-uniform size 1,000..900,000 bytes, batched
-    vs per-block.
 --config 5: the serving loop: Poisson arrivals of 4 KB..64 MB requests at
     fractions of the saturated rate; MB/s with p50/p99 latency.
 """
@@ -53,7 +52,8 @@ def _sub_batch(batch, idx):
     return data, offs
 
 
-TRAFFIC_FILE = {2: "profiles/compress_64MiB_900k_blocks_hbm_traffic.md"}
+TRAFFIC_FILE = {2: "profiles/compress_64MiB_900k_blocks_hbm_traffic.md",
+                4: "profiles/compress_8192_uneven_blocks_hbm_traffic.md"}
 
 
 def _traffic(config, kernel):
@@ -212,7 +212,7 @@ def bench_compress(args, batch, level):
 def bench_sort(args):
     import torch
     from paper_1109_2348_amd import native
-    from paper_1109_2348_amd import workloads as W
+    import workloads as W
     batch = W.config3()
     n_in = int(batch.data.size)
     x = torch.from_numpy(batch.data).cuda()
@@ -266,7 +266,7 @@ def bench_sort(args):
 # ---------------------------------------------------------------- config 5
 def bench_serving(args):
     from paper_1109_2348_amd import serving as S
-    from paper_1109_2348_amd import workloads as W
+    import workloads as W
     import torch
     pool_np = [r.data for r in W.requests(args.pool, 1.0, 4000, 64_000_000, 5)]
     mean_mb = float(np.mean([p.size for p in pool_np])) / 1e6
@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--per-block-passes", type=int, default=1)
     ap.add_argument("--cpu-sample-blocks", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
@@ -335,7 +335,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    from paper_1109_2348_amd import workloads as W
+    import workloads as W
     log(f"config {args.config}: generating workload")
     if args.config == 1:
         res = bench_compress(args, W.config1(), level=1)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import cref
-from paper_1109_2348_amd import workloads as W
+import workloads as W
 
 pytestmark = pytest.mark.gpu
 
@@ -191,6 +191,52 @@ def test_huffman_from_oracle_symbols(bz):
         used[rnd.choice(256, size=nu, replace=False)] = 1
         ul.append(used)
     _check_huff(bz, sl, ul, "oracle symbol streams + table-count edges")
+
+
+def _spaced_stream(counts):
+    """Symbols 1..k with the given counts, each symbol's occurrences evenly
+    spaced over the stream (so every 50-symbol group sees the same mix and
+    the refinement keeps one table for almost all of them), then EOB."""
+    n = sum(counts)
+    keys = np.concatenate([(np.arange(c) + 0.5) * n / c + v * 1e-6 for v, c in enumerate(counts)])
+    vals = np.concatenate([np.full(c, v + 1, np.uint16) for v, c in enumerate(counts)])
+    s = vals[np.argsort(keys, kind="stable")]
+    return np.concatenate([s, [len(counts) + 1]]).astype(np.uint16)
+
+
+def _halvings(counts):
+    """Rescale steps the length limit takes for these table counts."""
+    from oracle import ref
+    w = [max(int(x), 1) for x in counts]
+    k = 0
+    while max(ref.huffman_lengths(w, max_len=1 << 30)) > 17:
+        w = [1 + x // 2 for x in w]
+        k += 1
+    return k
+
+
+def test_huffman_length_limit_rescale(bz):
+    """Streams whose final tables need the 17-bit rescale once, twice and
+    three times (Sec. 3.4): the GPU's tables, bit counts and bodies equal
+    the oracle's."""
+    fib = [1, 1]
+    while len(fib) < 26:
+        fib.append(fib[-1] + fib[-2])
+    cases = [("fibonacci", fib[1:24], 1), ("powers of 2 to 2^18", [2 ** k for k in range(18, -1, -1)], 2),
+             ("powers of 2 to 2^19", [2 ** k for k in range(19, -1, -1)], 3)]
+    sl, ul = [], []
+    for name, counts, want in cases:
+        s = _spaced_stream(counts)
+        nu = len(counts)
+        used = np.zeros(256, np.uint8)
+        used[10:10 + nu] = 1
+        _, _, rlens, rsel = cref.body(s, used)
+        got = max(_halvings(np.bincount(s[np.repeat(rsel == t, 50)[:s.size]], minlength=nu + 2))
+                  for t in range(rlens.shape[0]))
+        assert got >= want, f"{name}: final tables need {got} rescale steps, wanted {want}"
+        sl.append(s)
+        ul.append(used)
+    _check_huff(bz, sl, ul, "length-limit rescale (1, 2, 3 halvings)")
 
 
 def _check_compress(bz, data, offs, level, name):
@@ -392,21 +438,34 @@ def test_compress_config2_full(bz):
 
 
 @pytest.mark.slow
-def test_bwt_config3_sampled(bz):
+def test_bwt_config3_all_blocks(bz):
+    """Sort worst case, every block validated: the oracle's property check
+    (a permutation whose adjacent rotations are in order, equal ones by
+    descending start) fixes the suffix order uniquely, so with it L and the
+    primary index follow.  Threaded over the host cores."""
+    import concurrent.futures as cf
+    import time
     b = W.config3()
-    _say("bwt 256 x 900000 periodic / all-same (sampled property check)")
+    _say("bwt 256 x 900000 periodic / all-same (all blocks, property check)")
     L, prim, sa = bz.bwt(_dev(b.data), b.offsets, want_sa=True)
     sa = sa.cpu().numpy().view(np.uint32)
     L = L.cpu().numpy()
     prim = prim.cpu().numpy()
-    rnd = random.Random(3)
-    picks = sorted(rnd.sample(range(b.n_blocks), 4)) + [b.kinds.index("same")]
-    for k in picks:
+    t0 = time.time()
+
+    def one(k):
         a, e = int(b.offsets[k]), int(b.offsets[k + 1])
         blk = b.block(k)
-        assert cref.check_sa(blk, sa[a:e]) == -1, f"block {k} ({b.kinds[k]}): SA not sorted"
-        assert np.array_equal(L[a:e], blk[(sa[a:e].astype(np.int64) - 1) % (e - a)])
-        assert int(sa[a + int(prim[k])]) == 0
-    for k in range(b.n_blocks):  # every block: permutation and primary
-        a, e = int(b.offsets[k]), int(b.offsets[k + 1])
-        assert int(sa[a + int(prim[k])]) == 0
+        s = sa[a:e]
+        if cref.check_sa(blk, s) != -1:
+            return f"block {k} ({b.kinds[k]}): SA not sorted"
+        if not np.array_equal(L[a:e], blk[(s.astype(np.int64) - 1) % (e - a)]):
+            return f"block {k}: L is not the byte before each sorted rotation"
+        if int(s[int(prim[k])]) != 0:
+            return f"block {k}: primary {prim[k]} is not the row of rotation 0"
+        return None
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        errs = [m for m in ex.map(one, range(b.n_blocks)) if m]
+    _say(f"checked {b.n_blocks} blocks in {time.time() - t0:.1f} s")
+    assert not errs, errs[:5]

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import cref, ref
-from paper_1109_2348_amd import workloads as W
+import workloads as W
 
 
 def _small_inputs():

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import cref
 from paper_1109_2348_amd import serving as S
-from paper_1109_2348_amd import workloads as W
+import workloads as W
 
 
 def _budget(max_pass, workers, arena):

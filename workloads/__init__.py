@@ -49,13 +49,24 @@ def zipf_ranks(g: np.random.Generator, size: int, k: int, s: float = 1.1) -> np.
 _walk = None
 
 
+def build() -> str:
+    """Compiles markov_walk.c (the Markov sources' sampling loop) with gcc."""
+    import os, subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    src, lib = os.path.join(here, "markov_walk.c"), os.path.join(here, "libmarkov_walk.so")
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", src, "-o", lib + ".tmp"])
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
 def _walk_lib():
-    """The recurrence in C (markov_walk.c), built on first use; None when no
-    compiler is available (the numpy walk below gives identical bytes)."""
+    """The recurrence in C (markov_walk.c; compiled by build(), or here on
+    first use if it is missing or stale); None when no compiler is available
+    (the numpy walk below gives identical bytes)."""
     global _walk
     if _walk is None:
         import ctypes, os, subprocess
-        here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+        here = os.path.dirname(os.path.abspath(__file__))
         src, lib = os.path.join(here, "markov_walk.c"), os.path.join(here, "libmarkov_walk.so")
         try:
             if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
@@ -78,8 +89,8 @@ def _markov(lengths: Sequence[int], gens: Sequence[np.random.Generator], alphabe
     perms = np.ascontiguousarray(
         table_gen.permuted(np.tile(np.arange(k, dtype=np.int64), (k ** order, 1)), axis=1))
     lib = _walk_lib()
-    out = []
-    for g, n in zip(gens, lengths):
+
+    def one(g, n):
         n = int(n)
         sym = np.zeros(n, dtype=np.uint8)
         start = g.integers(0, k, size=min(order, n))
@@ -100,12 +111,27 @@ def _markov(lengths: Sequence[int], gens: Sequence[np.random.Generator], alphabe
                 sl[t] = x
                 ctx = (ctx * k + x) % kk
             sym = np.asarray(sl, dtype=np.uint8)
-        out.append(alphabet[sym].astype(np.uint8))
-    return out
+        return alphabet[sym].astype(np.uint8)
+
+    return _pmap(one, gens, lengths)
 
 
 TEXT_ALPHABET = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz ", dtype=np.uint8)
 M64_ALPHABET = np.arange(0x20, 0x60, dtype=np.uint8)
+
+
+def _pmap(fn, gens, lengths) -> List[np.ndarray]:
+    """fn(gen, n) for every block, over a few threads (numpy's generators and
+    the C walk release the GIL; each block has its own generator, so the
+    bytes do not depend on the scheduling)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    items = list(zip(gens, lengths))
+    workers = min(16, os.cpu_count() or 1)
+    if len(items) < 8 or workers == 1:
+        return [fn(g, n) for g, n in items]
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda a: fn(*a), items))
 
 
 def source_blocks(kind: str, lengths: Sequence[int], seed: int, first_index: int = 0,
@@ -114,14 +140,13 @@ def source_blocks(kind: str, lengths: Sequence[int], seed: int, first_index: int
     idx = list(indices) if indices is not None else [first_index + i for i in range(len(lengths))]
     gens = [rng(seed, i) for i in idx]
     if kind == "uniform":
-        return [g.integers(0, 256, size=n, dtype=np.uint8) for g, n in zip(gens, lengths)]
+        return _pmap(lambda g, n: g.integers(0, 256, size=n, dtype=np.uint8), gens, lengths)
     if kind == "sparse":
-        out = []
-        for g, n in zip(gens, lengths):
+        def sparse(g, n):
             nz = g.random(n) < 0.05
             v = g.integers(1, 256, size=n, dtype=np.uint8)
-            out.append(np.where(nz, v, 0).astype(np.uint8))
-        return out
+            return np.where(nz, v, 0).astype(np.uint8)
+        return _pmap(sparse, gens, lengths)
     if kind == "text":
         return _markov(lengths, gens, TEXT_ALPHABET, 3, rng(seed, 1 << 40, 3))
     if kind == "markov64":
