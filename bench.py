@@ -224,11 +224,14 @@ def bench_sort(args):
     o = np.ascontiguousarray(batch.offsets, dtype=np.uint64)
     import ctypes as C
 
+    d_o = native._dev_u64(o, x.device)
+    st = native._stream(x.device)
+
     def run(lo=0, hi=nb):
         sub = o[lo:hi + 1]
-        rc = native.lib().bwt_forward_batch(ctx.h, C.c_void_p(x.data_ptr()), native._u64p(sub), hi - lo,
-                                            C.c_void_p(L.data_ptr()), C.c_void_p(prim.data_ptr() + 4 * lo), None,
-                                            native._stream(x.device))
+        rc = native.lib().bwt_forward_batch(ctx.h, C.c_void_p(x.data_ptr()), C.c_void_p(d_o.data_ptr() + 8 * lo),
+                                            native._u64p(sub), hi - lo, C.c_void_p(L.data_ptr()),
+                                            C.c_void_p(prim.data_ptr() + 4 * lo), None, None, 0, st)
         ctx.check(rc)
     log(f"warmup {args.warmup}, timing {args.steps} steps of bwt_forward_batch over {nb} blocks")
     _, wall, step_ms, kern = _timed(run, ctx, args.steps, args.warmup, stream)
@@ -237,7 +240,7 @@ def bench_sort(args):
     pb = _per_block(lambda k: run(k, k + 1), nb, args.per_block_passes)
     per_block = {"value": round(n_in / pb / 1e6, 2) if pb else None, "unit": "MB/s", "calls": nb}
     run()
-    torch.cuda.synchronize()
+    ctx.sync_check(st)
     Lh, ph = L.cpu().numpy(), prim.cpu().numpy()
     cpu = None
     if not args.no_cpu:

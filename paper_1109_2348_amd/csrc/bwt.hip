@@ -34,6 +34,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "plan.hpp"
 
 namespace bzg {
 
@@ -121,9 +122,9 @@ __device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, cons
 // of each row's first 4 bytes, from the text instead (rows are in descending
 // start order, so the read is sequential).  Init segments are whole blocks.
 template <bool INIT>
-__global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
-                                                   const uint32_t* __restrict__ kin, int shift,
-                                                   uint32_t* __restrict__ hist, const uint8_t* __restrict__ text) {
+__device__ void radix_hist_tile(uint32_t jt, const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                const uint32_t* __restrict__ kin, int shift, uint32_t* __restrict__ hist,
+                                const uint8_t* __restrict__ text) {
   // counts only (no ranks), so LDS atomics instead of matching lanes of
   // equal digit.  Same-address atomics serialize: every wave keeps 4 copies
   // (by lane mod 4, padded onto different banks), and the digit of each
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (uint32_t d = threadIdx.x; d < NC * CS; d += NT) cnt[d] = 0;
   __syncthreads();
-  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  BigTile g = big_tile(jt, segs, owner);
   const bool from_text = INIT && text != nullptr;
   const uint32_t wbase = g.lo + w * (RI * BZG_WAVE);
   // loads of clamped rows, none under a branch, so all are in flight at once
@@ -174,23 +175,41 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
+// Scan tiles of the device-wide scan that follows a histogram pass (its
+// per-tile state words and ticket, cleared by the histogram kernel).
+__host__ __device__ inline uint32_t hist_scan_states(uint32_t tiles) { return (tiles * 256u + 2047u) / 2048u + 1u; }
+
+// Persistent workgroups over *ntiles tiles of large segments.  Also clears
+// the state of the scan that consumes the histogram.
+template <bool INIT>
+__global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                                   const uint32_t* __restrict__ kin, int shift,
+                                                   uint32_t* __restrict__ hist, const uint8_t* __restrict__ text,
+                                                   const uint32_t* __restrict__ ntiles, uint32_t cap,
+                                                   unsigned long long* __restrict__ scan_state) {
+  const uint32_t n = min(*ntiles, cap);
+  const uint32_t ns = hist_scan_states(n);
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < ns; i += gridDim.x * NT) scan_state[i] = 0ull;
+  for (TileLoop it = tile_loop(n); it.t < it.end; it.t += it.step) {
+    radix_hist_tile<INIT>(it.t, segs, owner, kin, shift, hist, text);
+    __syncthreads();
+  }
+}
+
 // One stable LSD pass: (key, row) pairs move.  INIT instantiates the init
 // sort's passes; in its first (text != null, shift 0) rows come from the row
 // index, in descending start order, and each key is its row's first 4 bytes
 // (big-endian), read sequentially from the text.
 template <bool INIT>
-__global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
-                                                      const uint32_t* __restrict__ owner,
-                                                      const uint32_t* __restrict__ kin,
-                                                      const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-                                                      uint32_t* __restrict__ vout, int shift,
-                                                      const uint32_t* __restrict__ hscan,
-                                                      const uint8_t* __restrict__ text) {
+__device__ void radix_scatter_tile(uint32_t jt, const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                   const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                   uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift,
+                                   const uint32_t* __restrict__ hscan, const uint8_t* __restrict__ text) {
   __shared__ uint32_t cnt[NW][256];
   const uint32_t w = threadIdx.x / BZG_WAVE;
   for (int d = threadIdx.x; d < NW * 256; d += NT) (&cnt[0][0])[d] = 0;
   __syncthreads();
-  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  BigTile g = big_tile(jt, segs, owner);
   const bool from_text = INIT && text != nullptr;
   // this tile's output base for digit threadIdx.x, loaded before the rows
   const size_t col0 = (size_t)g.r.base * 256;
@@ -294,6 +313,21 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
   }
 }
 
+template <bool INIT>
+__global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__ segs,
+                                                      const uint32_t* __restrict__ owner,
+                                                      const uint32_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout, int shift,
+                                                      const uint32_t* __restrict__ hscan,
+                                                      const uint8_t* __restrict__ text,
+                                                      const uint32_t* __restrict__ ntiles, uint32_t cap) {
+  for (TileLoop it = tile_loop(min(*ntiles, cap)); it.t < it.end; it.t += it.step) {
+    radix_scatter_tile<INIT>(it.t, segs, owner, kin, vin, kout, vout, shift, hscan, text);
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------- new segments
 
 struct AppendCtx {
@@ -301,9 +335,10 @@ struct AppendCtx {
   uint32_t* head;   // packed offset -> segment index + 1
   uint32_t* owner;  // tile -> segment index
   RoundCounters* cnt;
-  // counter record cleared by workgroup 0 (nullable): the one the round
-  // after the next appends to, which nothing reads or writes meanwhile
-  RoundCounters* clr;
+  // capacities of segs, head and owner (every valid input stays below them;
+  // an append past one is dropped and flagged)
+  uint32_t seg_cap, head_cap, owner_cap;
+  uint32_t* err;
 };
 
 // Workgroup-aggregated append of up to `m` groups held by this thread
@@ -344,9 +379,12 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
     wg_base[2] = (uint32_t)tb;
   }
   __syncthreads();
-  if (a.clr && blockIdx.x == 0 && threadIdx.x == 0) {
-    a.clr->segs_small = 0ull;
-    a.clr->tiles_big = 0ull;
+  const bool fits = (uint64_t)wg_base[0] + t_seg <= a.seg_cap &&
+                    (uint64_t)wg_base[1] + t_small + SMALL_CAP <= a.head_cap &&
+                    (uint64_t)wg_base[2] + t_tiles <= a.owner_cap;
+  if (!fits) {
+    if (threadIdx.x == 0) atomicOr(a.err, ERR_BOUND);
+    m = 0;
   }
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
 #pragma unroll
@@ -375,10 +413,10 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
 // ------------------------------------------------------ naming, large
 
 // Per tile: the last group head (row + 1, 0 = none) among sorted keys.
-__global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
-                                                 const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg) {
+__device__ void rename_a_tile(uint32_t jt, const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                              const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg) {
   __shared__ uint32_t sh[NW + 1];
-  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  BigTile g = big_tile(jt, segs, owner);
   // every key and its predecessor loaded first (clamped rows, unbranched)
   uint32_t kc[RI], kp[RI];
 #pragma unroll
@@ -399,7 +437,26 @@ __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs
   if (threadIdx.x == 0) {
     uint32_t m = 0;
     for (int q = 0; q < NW; q++) m = max(m, sh[q]);
-    agg[xcd_tile(blockIdx.x, gridDim.x)] = m;
+    agg[jt] = m;
+  }
+}
+
+// Persistent workgroups over *ntiles tiles.  Also clears the first
+// `head_clear` entries of a small-segment head array that this round's
+// small-segment sort has finished reading (so that it can be appended to two
+// rounds later); head_clear is a device count (nullable).
+__global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                                 const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg,
+                                                 const uint32_t* __restrict__ ntiles, uint32_t cap,
+                                                 uint32_t* __restrict__ head, const uint32_t* __restrict__ head_clear,
+                                                 uint32_t head_cap) {
+  if (head_clear) {
+    const uint32_t nh = min(*head_clear, head_cap);
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nh; i += gridDim.x * NT) head[i] = 0u;
+  }
+  for (TileLoop it = tile_loop(min(*ntiles, cap)); it.t < it.end; it.t += it.step) {
+    rename_a_tile(it.t, segs, owner, kin, agg);
+    __syncthreads();
   }
 }
 
@@ -408,21 +465,19 @@ __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs
 // appended.  With rank_all = 0 only rows alone in their group get a rank:
 // the others are re-sorted next round, which ranks them, and that round
 // compares text rather than ranks (so nothing reads their ranks before).
-__global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
-                                                 const uint32_t* __restrict__ kin, const uint32_t* vin,
-                                                 const uint32_t* __restrict__ agg, const uint32_t* __restrict__ blk_off,
-                                                 uint32_t* SA, uint32_t* __restrict__ rank,
-                                                 uint32_t h_next, int key_is_rank, int rank_all, AppendCtx app) {
+__device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                              const uint32_t* __restrict__ kin, const uint32_t* vin, const uint32_t* __restrict__ agg,
+                              const uint32_t* __restrict__ blk_off, uint32_t* SA, uint32_t* __restrict__ rank,
+                              uint32_t h_next, int key_is_rank, int rank_all, const AppendCtx& app) {
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t s_carry;
   __shared__ uint32_t wg_base[4];
-  BigTile g = big_tile(xcd_tile(blockIdx.x, gridDim.x), segs, owner);
+  BigTile g = big_tile(jt, segs, owner);
   {
     // the group head carried in: the last head in the segment's earlier
     // tiles, i.e. the largest of their per-tile last heads (heads grow with
     // the row)
-    const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
     uint32_t c = 0;
     for (uint32_t q = threadIdx.x; q < g.t; q += NT) c = max(c, agg[jt - g.t + q]);
     c = wave_max(c);
@@ -513,6 +568,18 @@ __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs
     }
   }
   append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, nullptr, wg_base);
+}
+
+__global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
+                                                 const uint32_t* __restrict__ kin, const uint32_t* vin,
+                                                 const uint32_t* __restrict__ agg, const uint32_t* __restrict__ blk_off,
+                                                 uint32_t* SA, uint32_t* __restrict__ rank,
+                                                 uint32_t h_next, int key_is_rank, int rank_all, AppendCtx app,
+                                                 const uint32_t* __restrict__ ntiles, uint32_t cap) {
+  for (TileLoop it = tile_loop(min(*ntiles, cap)); it.t < it.end; it.t += it.step) {
+    rename_b_tile(it.t, segs, owner, kin, vin, agg, blk_off, SA, rank, h_next, key_is_rank, rank_all, app);
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ gather key2
@@ -651,19 +718,32 @@ __device__ __forceinline__ void gather_keys_impl(uint32_t* p, const uint32_t* bo
   }
 }
 
-__global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
-                                               const uint32_t* __restrict__ owner, const RoundCounters* cnt,
-                                               uint32_t n_small_tiles, const uint32_t* __restrict__ blk_off,
-                                               const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
-                                               const uint8_t* __restrict__ text, uint32_t h,
-                                               uint32_t* __restrict__ key2) {
+// A round's sizes from its counter record, clamped to the arrays'
+// capacities (an append past a capacity was dropped and flagged, but its
+// counts went in).
+struct RoundSizes {
+  uint32_t small_total, nsmall, big_tiles;
+};
+__device__ __forceinline__ RoundSizes round_sizes(const RoundCounters* c, uint32_t head_cap, uint32_t owner_cap) {
+  RoundSizes z;
+  const RoundCounters r = *c;
+  z.small_total = min(r.small_total(), head_cap - SMALL_CAP);
+  z.nsmall = (z.small_total + SMALL_T - 1) / SMALL_T;
+  z.big_tiles = min(r.big_tiles(), owner_cap);
+  return z;
+}
+
+__device__ void gather_tile(uint32_t jt, uint32_t n_small_tiles, uint32_t small_total,
+                            const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
+                            const uint32_t* __restrict__ owner, const uint32_t* __restrict__ blk_off,
+                            const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
+                            const uint8_t* __restrict__ text, uint32_t h, uint32_t* __restrict__ key2) {
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t s_n, s_maxlen;
-  const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   if (jt < n_small_tiles) {
-    uint32_t n = small_tile_map(jt, head, cnt->small_total(), mark, segp, sh, &s_n, &s_maxlen);
+    uint32_t n = small_tile_map(jt, head, small_total, mark, segp, sh, &s_n, &s_maxlen);
     // segment records, then block bounds and rows, then the gathers: each
     // stage's loads are issued together, for half the tile at a time (which
     // bounds the registers held across them)
@@ -732,6 +812,30 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
   }
 }
 
+// key2 of this round's segments: persistent workgroups over the small tiles
+// (none in the text round, whose small segments gather their own keys) and
+// the large segments' tiles.  Workgroup 0 also clears the counter record
+// `clr`, the one that the round after the next appends to (nothing reads or
+// writes it meanwhile).
+__global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
+                                               const uint32_t* __restrict__ owner, const RoundCounters* cnt,
+                                               RoundCounters* clr, int with_small, uint32_t head_cap,
+                                               uint32_t owner_cap, const uint32_t* __restrict__ blk_off,
+                                               const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
+                                               const uint8_t* __restrict__ text, uint32_t h,
+                                               uint32_t* __restrict__ key2) {
+  const RoundSizes z = round_sizes(cnt, head_cap, owner_cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    clr->segs_small = 0ull;
+    clr->tiles_big = 0ull;
+  }
+  const uint32_t nsmall = with_small ? z.nsmall : 0u;
+  for (TileLoop it = tile_loop(nsmall + z.big_tiles); it.t < it.end; it.t += it.step) {
+    gather_tile(it.t, nsmall, z.small_total, segs, head, owner, blk_off, SA, rank, text, h, key2);
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------- small segments, LDS
 
 // Sorts packed small segments in LDS, names their groups, ranks their rows
@@ -743,11 +847,11 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // tile's radix passes.
 constexpr uint32_t COUNT_SORT_MAX = 64;
 
-__global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
-                                                   const RoundCounters* cnt, const uint32_t* __restrict__ blk_off,
-                                                   const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
-                                                   uint32_t* __restrict__ rank, uint32_t h_next,
-                                                   const uint8_t* __restrict__ text, AppendCtx app) {
+__device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec* __restrict__ segs,
+                                uint32_t* __restrict__ head, const uint32_t* __restrict__ blk_off,
+                                const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
+                                uint32_t* __restrict__ rank, uint32_t h_next, const uint8_t* __restrict__ text,
+                                const AppendCtx& app) {
   const bool text_mode = text != nullptr;
   const uint32_t h = h_next / 2;
   __shared__ uint32_t mark[SMALL_CAP];
@@ -760,8 +864,6 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   __shared__ uint32_t sx[NT];
   __shared__ uint32_t s_n, s_maxlen;
   __shared__ uint32_t wg_base[4];
-  const uint32_t small_total = cnt->small_total();
-  const uint32_t jt = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t n = small_tile_map(jt, head, small_total, mark, segp, sh, &s_n, &s_maxlen, sseg);
   // Tiles whose segments are all short are ordered by counting (below); they
   // keep the segment ends in sseg, which the radix passes use otherwise.
@@ -994,6 +1096,19 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
   append_groups<PI / 2 + 1>(app, gs, gl, m, 0, gb, wg_base);
 }
 
+__global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
+                                                   const RoundCounters* cnt, uint32_t head_cap, uint32_t owner_cap,
+                                                   const uint32_t* __restrict__ blk_off,
+                                                   const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
+                                                   uint32_t* __restrict__ rank, uint32_t h_next,
+                                                   const uint8_t* __restrict__ text, AppendCtx app) {
+  const RoundSizes z = round_sizes(cnt, head_cap, owner_cap);
+  for (TileLoop it = tile_loop(z.nsmall); it.t < it.end; it.t += it.step) {
+    small_sort_tile(it.t, z.small_total, segs, head, blk_off, key2, SA, rank, h_next, text, app);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- final BWT
 
 // L[k] = byte before rotation SA[k]; primary[b] = row of rotation 0; the
@@ -1002,11 +1117,10 @@ __global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ se
 // time.
 constexpr uint32_t OUT_ROWS = 16;
 
-__global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
-                                                uint32_t nb, uint32_t N, const uint32_t* __restrict__ SA,
-                                                uint8_t* __restrict__ L, uint32_t* __restrict__ primary,
-                                                uint32_t* __restrict__ sa_local) {
-  const uint32_t k0 = (xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x) * OUT_ROWS;
+__device__ __forceinline__ void bwt_out_rows(uint32_t k0, const uint8_t* __restrict__ text,
+                                             const uint32_t* __restrict__ off, uint32_t nb, uint32_t N,
+                                             const uint32_t* __restrict__ SA, uint8_t* __restrict__ L,
+                                             uint32_t* __restrict__ primary, uint32_t* __restrict__ sa_local) {
   if (k0 >= N) return;
   const uint32_t cnt = min(OUT_ROWS, N - k0);
   uint32_t b = find_block(off, nb, k0);
@@ -1021,7 +1135,7 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
     src[i] = 0;
     if (i < cnt) {
       const uint32_t k = k0 + i;
-      while (k >= e) {  // next block (empty blocks do not occur)
+      while (k >= e) {  // next block (empty ones are stepped over)
         b++;
         o = e;
         e = off[b + 1];
@@ -1046,29 +1160,25 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
   }
 }
 
+// Persistent workgroups over the *n_rows rows, NT * OUT_ROWS per tile.
+__global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text, const uint32_t* __restrict__ off,
+                                                uint32_t nb, const uint32_t* __restrict__ n_rows, uint32_t cap,
+                                                const uint32_t* __restrict__ SA, uint8_t* __restrict__ L,
+                                                uint32_t* __restrict__ primary, uint32_t* __restrict__ sa_local) {
+  const uint32_t N = min(*n_rows, cap);
+  for (TileLoop it = tile_loop((N + NT * OUT_ROWS - 1) / (NT * OUT_ROWS)); it.t < it.end; it.t += it.step)
+    bwt_out_rows((it.t * NT + threadIdx.x) * OUT_ROWS, text, off, nb, N, SA, L, primary, sa_local);
+}
+
 // ------------------------------------------------------------- host side
-
-struct BwtWork {
-  uint32_t *SA, *rank, *key, *tmpK, *tmpV, *hist, *scan_tmp, *agg;
-  SegRec* segs[2];
-  uint32_t* head[2];
-  uint32_t* owner[2];
-  RoundCounters* cnt;    // device [3]: read by a round, appended to by it, cleared by it
-  RoundCounters* h_cnt;  // pinned host [3]
-  uint32_t* d_off;       // device block offsets (nb+1)
-};
-
-struct BwtSizes {
-  size_t seg_cap, head_cap, owner_cap, hist_cap, scan_tmp_cap;
-};
 
 static BwtSizes bwt_sizes(uint32_t N, uint32_t nb) {
   BwtSizes z;
-  z.seg_cap = (size_t)N / 2 + nb + 16;
-  z.head_cap = (size_t)N + SMALL_T + 16;
-  z.owner_cap = (size_t)N / RADIX_TILE + (size_t)N / (SMALL_MAX + 1) + nb + 16;
-  z.hist_cap = z.owner_cap * 256 + 16;
-  z.scan_tmp_cap = scan_tmp_elems(z.hist_cap) + 16;
+  z.seg_cap = N / 2 + nb + 16;
+  z.head_cap = N + SMALL_CAP + 16;
+  z.owner_cap = N / RADIX_TILE + N / (SMALL_MAX + 1) + nb + 16;
+  z.hist_cap = (size_t)z.owner_cap * 256 + 16;
+  z.state_cap = hist_scan_states((uint32_t)z.owner_cap) + 16;
   return z;
 }
 
@@ -1078,35 +1188,70 @@ size_t bwt_workspace_bytes(uint32_t N, uint32_t nb) {
   auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
   for (int i = 0; i < 5; i++) add((size_t)N * 4 + 64);  // SA rank key tmpK tmpV
   add(z.hist_cap * 4);
-  add(z.scan_tmp_cap * 4);
+  add(z.state_cap * 8);
   add(z.owner_cap * 4);  // agg
   for (int i = 0; i < 2; i++) {
     add(z.seg_cap * sizeof(SegRec));
-    add(z.head_cap * 4);
     add(z.owner_cap * 4);
   }
+  add(z.head_cap * 4 * 2);
   add(3 * sizeof(RoundCounters));
-  add(((size_t)nb + 1) * 4);
   return b + 4096;
 }
 
-static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, int passes,
-                               double elems, uint32_t** kin, uint32_t** vin, hipStream_t st) {
+bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w) {
+  const BwtSizes z = bwt_sizes(N, nb);
+  Bump bump;
+  bump.base = (char*)ws;
+  bump.cap = ws_bytes;
+  w.z = z;
+  w.SA = bump.take<uint32_t>(N + 16);
+  w.rank = bump.take<uint32_t>(N + 16);
+  w.key = bump.take<uint32_t>(N + 16);
+  w.tmpK = bump.take<uint32_t>(N + 16);
+  w.tmpV = bump.take<uint32_t>(N + 16);
+  w.hist = bump.take<uint32_t>(z.hist_cap);
+  w.state = bump.take<unsigned long long>(z.state_cap);
+  w.agg = bump.take<uint32_t>(z.owner_cap);
+  for (int i = 0; i < 2; i++) {
+    w.segs[i] = bump.take<SegRec>(z.seg_cap);
+    w.owner[i] = bump.take<uint32_t>(z.owner_cap);
+  }
+  // both head arrays and the counter records in one range (one fill)
+  w.head[0] = bump.take<uint32_t>(z.head_cap);
+  w.head[1] = w.head[0] + z.head_cap;
+  (void)bump.take<uint32_t>(z.head_cap);
+  w.cnt = bump.take<RoundCounters>(3);
+  return bump.used <= ws_bytes;
+}
+
+// Doubling rounds after the first sort: one per h = 4, 8, ... below the
+// longest block (after the round at h, rotations are ordered by 2h bytes,
+// and groups in blocks of at most 2h rows are finished).
+int bwt_rounds(uint32_t max_len) {
+  int r = 0;
+  for (uint64_t h = 4; h < max_len; h *= 2) r++;
+  return r;
+}
+
+static hipError_t radix_passes(BwtWork& w, uint32_t grid, uint32_t cap, const uint32_t* ntiles,
+                               const uint32_t* nrows, const SegRec* segs, const uint32_t* owner, int passes,
+                               uint32_t* err, uint32_t** kin, uint32_t** vin, hipStream_t st) {
   uint32_t *ka = w.key, *va = w.SA, *kb = w.tmpK, *vb = w.tmpV;
   for (int p = 0; p < passes; p++) {
     {
-      ProfScope ps("radix_hist", st, 4.0 * elems);  // read the key
-      hipLaunchKernelGGL(k_radix_hist<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
-                         nullptr);
+      ProfScope ps("radix_hist", st, 0, nrows, 4.0);  // read the key
+      hipLaunchKernelGGL(k_radix_hist<false>, dim3(grid), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist, nullptr,
+                         ntiles, cap, w.state);
     }
     {
-      ProfScope ps("scan", st, 8.0 * big_tiles * 256);
-      hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
+      ProfScope ps("scan", st, 0, ntiles, 8.0 * 256);
+      hipError_t e = scan_lb_u32(w.hist, ntiles, cap, 256, w.state, err, grid, st);
       if (e != hipSuccess) return e;
     }
-    ProfScope ps("radix_scatter", st, 16.0 * elems);  // read and write key and value
-    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
-                       w.hist, nullptr);
+    ProfScope ps("radix_scatter", st, 0, nrows, 16.0);  // read and write key and value
+    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(grid), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
+                       w.hist, nullptr, ntiles, cap);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
@@ -1115,185 +1260,117 @@ static hipError_t radix_passes(BwtWork& w, uint32_t big_tiles, const SegRec* seg
   return hipGetLastError();
 }
 
-// The init sort: 4 LSD passes on the first 4 bytes of every rotation (big-
-// endian).  Pass 0 builds the (key, row) pairs from a sequential read of the
-// text; the sorted keys and rows end in w.key and w.SA.
-static hipError_t init_passes(BwtWork& w, uint32_t big_tiles, const SegRec* segs, const uint32_t* owner, double elems,
-                              const uint8_t* text, hipStream_t st) {
-  uint32_t* kout[4] = {w.tmpK, w.key, w.tmpK, w.key};
-  uint32_t* vout[4] = {w.tmpV, w.SA, w.tmpV, w.SA};
-  for (int p = 0; p < 4; p++) {
-    const uint32_t* ka = p ? kout[p - 1] : nullptr;
-    const uint32_t* va = p ? vout[p - 1] : nullptr;
-    {
-      ProfScope ps("init_hist", st, (p ? 4.0 : 1.0) * elems);  // key in (pass 0: one text byte)
-      hipLaunchKernelGGL(k_radix_hist<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist,
-                         p ? nullptr : text);
-    }
-    {
-      ProfScope ps("scan", st, 8.0 * big_tiles * 256);
-      hipError_t e = scan_excl_u32(w.hist, w.hist, (size_t)big_tiles * 256, w.scan_tmp, st);
-      if (e != hipSuccess) return e;
-    }
-    // key and row in and out (pass 0: one text byte in per row)
-    ProfScope ps("init_scatter", st, (p ? 16.0 : 9.0) * elems);
-    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(big_tiles), dim3(NT), 0, st, segs, owner, ka, va, kout[p], vout[p],
-                       8 * p, w.hist, p ? nullptr : text);
-  }
-  return hipGetLastError();
-}
-
-// Sorts the rotations of every block of `text` (blocks at h_off[b]..h_off[b+1],
-// all lengths in 1..MAX_BLOCK, total N).  Leaves SA rows in w.SA.
-hipError_t bwt_sort(const uint8_t* text, const std::vector<uint32_t>& h_off, void* ws, size_t ws_bytes,
-                    RoundCounters* h_pinned, Stager& stg, uint32_t** SA_out, uint32_t** off_out, int* rounds,
-                    std::string& err) {
-  hipStream_t st = stg.st;
-  const uint32_t nb = (uint32_t)h_off.size() - 1;
-  const uint32_t N = h_off[nb];
-  BwtSizes z = bwt_sizes(N, nb);
-  Bump bump;
-  bump.base = (char*)ws;
-  bump.cap = ws_bytes;
-  BwtWork w;
-  w.SA = bump.take<uint32_t>(N + 16);
-  w.rank = bump.take<uint32_t>(N + 16);
-  w.key = bump.take<uint32_t>(N + 16);
-  w.tmpK = bump.take<uint32_t>(N + 16);
-  w.tmpV = bump.take<uint32_t>(N + 16);
-  w.hist = bump.take<uint32_t>(z.hist_cap);
-  w.scan_tmp = bump.take<uint32_t>(z.scan_tmp_cap);
-  w.agg = bump.take<uint32_t>(z.owner_cap);
-  for (int i = 0; i < 2; i++) {
-    w.segs[i] = bump.take<SegRec>(z.seg_cap);
-    w.owner[i] = bump.take<uint32_t>(z.owner_cap);
-  }
-  // both head arrays and the counter records in one range (one fill)
-  w.head[0] = bump.take<uint32_t>(z.head_cap);
-  w.head[1] = bump.take<uint32_t>(z.head_cap);
-  w.cnt = bump.take<RoundCounters>(3);
-  w.d_off = bump.take<uint32_t>(nb + 1);
-  if (bump.used > ws_bytes) {
-    err = "bwt workspace too small";
-    return hipErrorInvalidValue;
-  }
-  w.h_cnt = h_pinned;
-  *SA_out = w.SA;
-  *off_out = w.d_off;
+// Sorts the rotations of every block of `text` (block b = rows
+// [d_off[b], d_off[b+1]), possibly empty, at most bd.max_len each; d_off[nb]
+// = the row count, at most bd.rows).  The first segments (one per block,
+// w.segs[0]) and their tile owners (w.owner[0], *init_tiles of them) are set
+// by the caller.  Every round of the fixed schedule is enqueued; rounds with
+// nothing left to sort find zero counts and end at once.  SA rows end in
+// w.SA.
+hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, const uint32_t* init_tiles,
+                    const BwtBounds& bd, uint32_t* err, int* rounds, hipStream_t st) {
+  const BwtSizes& z = w.z;
+  const uint32_t G = persist_grid(z.owner_cap, 2048);
+  const uint32_t Gs = persist_grid((bd.rows + SMALL_T - 1) / SMALL_T + z.owner_cap, 2048);
   hipError_t e;
 #define BZG_TRY(x)                  \
   do {                              \
     e = (x);                        \
     if (e != hipSuccess) return e;  \
   } while (0)
-  BZG_TRY(stg.put(w.d_off, h_off.data(), (nb + 1) * 4));
-  BZG_TRY(hipMemsetAsync(w.head[0], 0, (size_t)((char*)(w.cnt + 3) - (char*)w.head[0]), st));
-  uint32_t max_n = 0;
-  for (uint32_t b = 0; b < nb; b++) max_n = std::max(max_n, h_off[b + 1] - h_off[b]);
-  // initial segments: every block as a large segment (a one-row block too:
-  // the init passes are what put its row into SA)
-  std::vector<SegRec> segs0;
-  std::vector<uint32_t> owner0;
-  double init_elems = 0;
-  for (uint32_t b = 0; b < nb; b++) {
-    uint32_t n = h_off[b + 1] - h_off[b];
-    if (n == 0) continue;
-    init_elems += n;
-    SegRec r{h_off[b], n, b, (uint32_t)owner0.size()};
-    for (uint32_t t = 0; t < (n + RADIX_TILE - 1) / RADIX_TILE; t++) owner0.push_back((uint32_t)segs0.size());
-    segs0.push_back(r);
-  }
-  int nround = 0;
-  const bool log_rounds = getenv("BZG_LOG") != nullptr;
-  if (!segs0.empty()) {
-    BZG_TRY(stg.put_span({{w.segs[0], segs0.data(), segs0.size() * sizeof(SegRec)},
-                          {w.owner[0], owner0.data(), owner0.size() * 4}}));  // adjacent in the carve
-    uint32_t big_tiles = (uint32_t)owner0.size();
-    uint32_t *kin, *vin;
-    BZG_TRY(init_passes(w, big_tiles, w.segs[0], w.owner[0], init_elems, text, st));
-    AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1], nullptr};
-    {
-      ProfScope ps("rename_a", st, 4.0 * init_elems);
-      hipLaunchKernelGGL(k_rename_a, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.agg);
-    }
-    {
-      ProfScope ps("rename_b", st, 12.0 * init_elems);  // key and row in, rank out
-      // only rows alone in their group are ranked here: round 0 compares text
-      hipLaunchKernelGGL(k_rename_b, dim3(big_tiles), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.SA, w.agg,
-                         w.d_off, w.SA, w.rank, 4u, 0, 0, app);
-    }
-    BZG_TRY(hipGetLastError());
-    int cur = 1;  // segment lists and head arrays: double-buffered
-    int cc = 1;   // counter records: three, so a round clears the one it does not touch
-    uint32_t h = 4;
-    int bits = 1;
-    while ((1u << bits) < max_n) bits++;
-    const int passes = (bits + 7) / 8;
-    for (;;) {
-      BZG_TRY(hipMemcpyAsync(&w.h_cnt[cc], &w.cnt[cc], sizeof(RoundCounters), hipMemcpyDeviceToHost, st));
-      BZG_TRY(hipStreamSynchronize(st));
-      RoundCounters c = w.h_cnt[cc];
-      if (log_rounds)
-        fprintf(stderr, "[bzg] sort round %d h=%u segments=%u small_rows=%u large_rows=%u large_tiles=%u\n", nround,
-                h, c.n_segs(), c.small_total(), c.big_active(), c.big_tiles());
-      if (c.n_segs() == 0) break;
-      if (c.n_segs() > z.seg_cap || c.big_tiles() > z.owner_cap || c.small_total() > N) {
-        err = "bwt: segment capacity exceeded";
-        return hipErrorInvalidValue;
-      }
-      nround++;
-      const int nxt = cur ^ 1;
-      // round 0 (h = 4) sorts on the next 4 text bytes instead of ranks
-      const bool text_round = h == 4;
-      const uint32_t nsmall = (c.small_total() + SMALL_T - 1) / SMALL_T;
+  BZG_TRY(fill32(w.head[0], (size_t)((char*)(w.cnt + 3) - (char*)w.head[0]) / 4, 0u, st));
+  const uint32_t* rows = d_off + bd.nslot;  // the row count
+  const uint32_t icap = std::min<uint32_t>(bd.init_tiles, (uint32_t)z.owner_cap);
+  const uint32_t Gi = persist_grid(icap, 2048);
+  // init: 4 LSD passes on the first 4 bytes of every rotation
+  {
+    uint32_t* kout[4] = {w.tmpK, w.key, w.tmpK, w.key};
+    uint32_t* vout[4] = {w.tmpV, w.SA, w.tmpV, w.SA};
+    for (int p = 0; p < 4; p++) {
+      const uint32_t* ka = p ? kout[p - 1] : nullptr;
+      const uint32_t* va = p ? vout[p - 1] : nullptr;
       {
-        ProfScope ps("gather", st, 12.0 * (text_round ? c.big_active() : c.active()));  // row, partner rank, key2
-        // the text round's small segments gather their keys in k_small_sort
-        const uint32_t gsmall = text_round ? 0u : nsmall;
-        if (gsmall + c.big_tiles())
-          hipLaunchKernelGGL(k_gather, dim3(gsmall + c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.head[cur],
-                             w.owner[cur], &w.cnt[cc], gsmall, w.d_off, w.SA, w.rank,
-                             text_round ? text : nullptr, h, w.key);
+        ProfScope ps("init_hist", st, 0, rows, p ? 4.0 : 1.0);  // key in (pass 0: one text byte)
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], ka, 8 * p, w.hist,
+                           p ? nullptr : text, init_tiles, icap, w.state);
       }
-      const int cn = (cc + 1) % 3, cz = (cc + 2) % 3;
-      AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[cn], &w.cnt[cz]};
-      if (nsmall) {
-        ProfScope ps("small_sort", st, 16.0 * c.small_total());  // key2 and row in, row and rank out
-        hipLaunchKernelGGL(k_small_sort, dim3(nsmall), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cc],
-                           w.d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
-        // every tile reads the head entries of the next one too, so they are
-        // cleared (for reuse two rounds later) only after the whole pass
-        BZG_TRY(hipMemsetAsync(w.head[cur], 0, (size_t)c.small_total() * 4, st));
+      {
+        ProfScope ps("scan", st, 0, init_tiles, 8.0 * 256);
+        BZG_TRY(scan_lb_u32(w.hist, init_tiles, icap, 256, w.state, err, Gi, st));
       }
-      if (c.big_tiles()) {
-        const double be = c.big_active();
-        BZG_TRY(radix_passes(w, c.big_tiles(), w.segs[cur], w.owner[cur], text_round ? 4 : passes, be, &kin, &vin,
-                             st));
-        {
-          ProfScope ps("rename_a", st, 4.0 * be);
-          hipLaunchKernelGGL(k_rename_a, dim3(c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg);
-        }
-        ProfScope ps("rename_b", st, 16.0 * be);
-        hipLaunchKernelGGL(k_rename_b, dim3(c.big_tiles()), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin,
-                           w.agg, w.d_off, w.SA, w.rank, 2 * h, text_round ? 0 : 1, 1, app2);
-      }
-      BZG_TRY(hipGetLastError());
-      cur = nxt;
-      cc = cn;
-      h *= 2;
+      // key and row in and out (pass 0: one text byte in per row)
+      ProfScope ps("init_scatter", st, 0, rows, p ? 16.0 : 9.0);
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], ka, va, kout[p],
+                         vout[p], 8 * p, w.hist, p ? nullptr : text, init_tiles, icap);
     }
   }
-  if (rounds) *rounds = nround;
+  const uint32_t hcap = (uint32_t)z.head_cap, ocap = (uint32_t)z.owner_cap;
+  {
+    AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1], (uint32_t)z.seg_cap, hcap, ocap, err};
+    {
+      ProfScope ps("rename_a", st, 0, rows, 4.0);
+      hipLaunchKernelGGL(k_rename_a, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.agg, init_tiles,
+                         icap, nullptr, nullptr, hcap);
+    }
+    ProfScope ps("rename_b", st, 0, rows, 12.0);  // key and row in, rank out
+    // only rows alone in their group are ranked here: round 0 compares text
+    hipLaunchKernelGGL(k_rename_b, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.SA, w.agg, d_off, w.SA,
+                       w.rank, 4u, 0, 0, app, init_tiles, icap);
+  }
+  BZG_TRY(hipGetLastError());
+  int bits = 1;
+  while ((1u << bits) < bd.max_len) bits++;
+  const int rank_passes = (bits + 7) / 8;
+  const int R = bwt_rounds(bd.max_len);
+  int cur = 1;  // segment lists and head arrays: double-buffered
+  int cc = 1;   // counter records: three, so a round clears the one it does not touch
+  uint32_t h = 4;
+  for (int r = 0; r < R; r++, h *= 2) {
+    const int nxt = cur ^ 1, cn = (cc + 1) % 3, cz = (cc + 2) % 3;
+    const bool text_round = h == 4;
+    const uint32_t* big_tiles = (const uint32_t*)&w.cnt[cc].tiles_big;         // low word
+    const uint32_t* small_rows = (const uint32_t*)&w.cnt[cc].segs_small + 1;   // high word
+    const uint32_t* big_rows = (const uint32_t*)&w.cnt[cc].tiles_big + 1;      // high word
+    {
+      // row, partner rank, key2
+      ProfScope ps("gather", st, 0, big_rows, 12.0, text_round ? nullptr : small_rows, 12.0);
+      // the text round's small segments gather their keys in k_small_sort
+      hipLaunchKernelGGL(k_gather, dim3(Gs), dim3(NT), 0, st, w.segs[cur], w.head[cur], w.owner[cur], &w.cnt[cc],
+                         &w.cnt[cz], text_round ? 0 : 1, hcap, ocap, d_off, w.SA, w.rank,
+                         text_round ? text : nullptr, h, w.key);
+    }
+    AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[cn], (uint32_t)z.seg_cap, hcap, ocap, err};
+    {
+      ProfScope ps("small_sort", st, 0, small_rows, 16.0);  // key2 and row in, row and rank out
+      hipLaunchKernelGGL(k_small_sort, dim3(Gs), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cc], hcap, ocap,
+                         d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
+    }
+    uint32_t *kin, *vin;
+    BZG_TRY(radix_passes(w, G, ocap, big_tiles, big_rows, w.segs[cur], w.owner[cur], text_round ? 4 : rank_passes,
+                         err, &kin, &vin, st));
+    {
+      ProfScope ps("rename_a", st, 0, big_rows, 4.0);
+      // also clears this round's small-segment heads (read by now)
+      hipLaunchKernelGGL(k_rename_a, dim3(G), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg, big_tiles,
+                         ocap, w.head[cur], small_rows, hcap);
+    }
+    ProfScope ps("rename_b", st, 0, big_rows, 16.0);
+    hipLaunchKernelGGL(k_rename_b, dim3(G), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin, w.agg, d_off, w.SA,
+                       w.rank, 2 * h, text_round ? 0 : 1, 1, app2, big_tiles, ocap);
+    BZG_TRY(hipGetLastError());
+    cur = nxt;
+    cc = cn;
+  }
+  if (rounds) *rounds = R;
   return hipGetLastError();
 #undef BZG_TRY
 }
 
-hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, uint32_t N, const uint32_t* SA,
-                      uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
-  ProfScope ps("bwt_out", st, 6.0 * N);  // row in, byte gathered, byte out
-  const uint32_t threads = (N + OUT_ROWS - 1) / OUT_ROWS;
-  if (N) hipLaunchKernelGGL(k_bwt_out, dim3((threads + NT - 1) / NT), dim3(NT), 0, st, text, d_off, nb, N, SA, L,
-                            primary, sa_local);
+hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, const uint32_t* n_rows, uint32_t cap,
+                      const uint32_t* SA, uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
+  ProfScope ps("bwt_out", st, 0, n_rows, 6.0);  // row in, byte gathered, byte out
+  const uint32_t g = persist_grid(((uint64_t)cap + NT * OUT_ROWS - 1) / (NT * OUT_ROWS), 2048);
+  hipLaunchKernelGGL(k_bwt_out, dim3(g), dim3(NT), 0, st, text, d_off, nb, n_rows, cap, SA, L, primary, sa_local);
   return hipGetLastError();
 }
 

@@ -1,5 +1,8 @@
-// C ABI: argument checking, workspace planning and the launch sequence of
-// every entry point declared in include/bzgpu.h.
+// C ABI: argument checking, workspace planning from host bounds, and the
+// launch sequence of every entry point declared in include/bzgpu.h.  No call
+// reads anything back from the device: data-dependent sizes are planned by
+// the kernels in plan.hip, and kernel-side errors go to the context's status
+// word, reported by bzg_check.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -9,75 +12,93 @@
 
 #include "../../include/bzgpu.h"
 #include "internal.hpp"
+#include "plan.hpp"
 
 namespace bzg {
 // launchers from the kernel translation units
 hipError_t rle1_tiles(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, const uint64_t*,
                       const uint32_t*, const uint32_t*, void*, hipStream_t);
-hipError_t rle1_tile_copy(uint32_t, const uint32_t*, const void*, void*, hipStream_t);
 hipError_t rle1_blocks(uint32_t, const uint32_t*, const uint64_t*, const uint32_t*, const void*, uint32_t*, uint32_t*,
                        uint32_t*, uint32_t*, hipStream_t);
-hipError_t rle1_emit(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const uint32_t*,
-                     const uint32_t*, const uint64_t*, uint8_t*, hipStream_t);
-hipError_t rle1_cut(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint64_t*, const uint32_t*,
-                    const uint32_t*, uint32_t, uint32_t*, hipStream_t);
+hipError_t rle1_emit(const uint8_t*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, const uint64_t*,
+                     const uint32_t*, const uint32_t*, const uint32_t*, uint8_t*, hipStream_t);
+hipError_t rle1_split(const uint8_t*, const uint64_t*, uint32_t, const uint32_t*, const void*, const uint32_t*,
+                      const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t, uint64_t*, uint32_t*,
+                      hipStream_t);
 size_t rle_tile_bytes();
-size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
-hipError_t bwt_sort(const uint8_t*, const std::vector<uint32_t>&, void*, size_t, RoundCounters*, Stager&,
-                    uint32_t**, uint32_t**, int*, std::string&);
-hipError_t bwt_output(const uint8_t*, const uint32_t*, uint32_t, uint32_t, const uint32_t*, uint8_t*, uint32_t*,
-                      uint32_t*, hipStream_t);
-size_t mtf_workspace_bytes(const std::vector<uint32_t>&);
-hipError_t mtf_run(const uint8_t*, const uint32_t*, const std::vector<uint32_t>&, void*, size_t, uint16_t*,
-                   const uint64_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*, Stager&, std::string&);
-size_t block_tables_bytes();
-hipError_t huff_run(uint32_t, const uint16_t*, const uint64_t*, const uint32_t*, uint32_t*, bool, const uint32_t*,
-                    const uint64_t*, uint8_t*, uint8_t*, uint64_t*, void*, uint32_t*, uint32_t, const uint32_t*,
-                    const uint32_t*, uint32_t, void*, hipStream_t);
+uint32_t mtf_chunk_rows(uint64_t rows, uint32_t nb);
+size_t mtf_workspace_bytes(uint64_t rows, uint32_t nb);
+hipError_t mtf_run(const uint8_t*, const uint32_t*, uint32_t, uint64_t, const uint32_t*, const uint32_t*,
+                   const uint32_t*, void*, size_t, uint16_t*, const uint64_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                   std::string&, hipStream_t);
 size_t huff_workspace_bytes(uint32_t nb);
 uint32_t huff_assign_groups(uint64_t ng);
+hipError_t huff_run(const HuffArgs&, hipStream_t);
 hipError_t pack_layout(uint32_t, uint32_t, const uint32_t*, const uint64_t*, const void*, int, const uint64_t*,
-                       uint64_t*, const uint32_t*, uint64_t*, hipStream_t);
-hipError_t zero_streams(uint32_t, uint64_t, const uint64_t*, const uint64_t*, uint32_t*, hipStream_t);
+                       uint64_t*, const uint32_t*, uint64_t*, uint64_t*, uint32_t*, const uint32_t*, uint32_t*,
+                       uint32_t*, hipStream_t);
+hipError_t zero_streams(uint32_t, uint64_t, const uint64_t*, const uint64_t*, uint32_t*, const uint32_t*, hipStream_t);
+hipError_t zero_range(uint32_t*, uint64_t, const uint32_t*, hipStream_t);
 hipError_t pack_run(uint32_t, const void*, int, const uint64_t*, const uint32_t*, const uint32_t*, const uint32_t*,
-                    const uint64_t*, const uint8_t*, const uint8_t*, const uint64_t*, uint32_t, const uint32_t*,
-                    const uint32_t*, const uint16_t*, const uint64_t*, const uint32_t*, int, uint32_t,
-                    const uint64_t*, const uint64_t*, uint32_t*, hipStream_t);
+                    const uint64_t*, const uint8_t*, const uint8_t*, const uint64_t*, const uint32_t*, uint32_t,
+                    const uint32_t*, const uint32_t*, const uint16_t*, const uint64_t*, const uint32_t*, int, uint32_t,
+                    const uint64_t*, const uint64_t*, uint32_t*, const uint32_t*, hipStream_t);
 hipError_t tables_export(uint32_t, const void*, uint8_t*, hipStream_t);
-hipError_t body_sizes(uint32_t, const void*, const uint64_t*, uint64_t*, uint32_t*, hipStream_t);
 }  // namespace bzg
 
 namespace bzg {
 
 thread_local Profiler* g_prof = nullptr;
 
-ProfScope::ProfScope(const char* name, hipStream_t s, double bytes) : st(s) {
+ProfScope::ProfScope(const char* name, hipStream_t s, double bytes, const uint32_t* count0, double per0,
+                     const uint32_t* count1, double per1)
+    : st(s), c0(count0), c1(count1) {
   if (g_prof && g_prof->on) {
-    Profiler::Pending p{name, nullptr, nullptr, bytes};
+    Profiler::Pending p{name, nullptr, nullptr, bytes, {per0, per1}, -1};
     if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return;
     (void)hipEventRecord(p.a, s);
+    if ((c0 || c1) && g_prof->slots && g_prof->used + 2 <= g_prof->nslots) {
+      p.slot = g_prof->used;
+      g_prof->used += 2;
+    }
     g_prof->pending.push_back(p);
     live = true;
   }
 }
 
 ProfScope::~ProfScope() {
-  if (live) (void)hipEventRecord(g_prof->pending.back().b, st);
+  if (!live) return;
+  Profiler::Pending& p = g_prof->pending.back();
+  (void)hipEventRecord(p.b, st);
+  // the counts as they are right after the launch (the records are reused
+  // later in the call)
+  if (p.slot >= 0) {
+    if (c0) (void)hipMemcpyAsync(g_prof->slots + p.slot, c0, 4, hipMemcpyDeviceToDevice, st);
+    if (c1) (void)hipMemcpyAsync(g_prof->slots + p.slot + 1, c1, 4, hipMemcpyDeviceToDevice, st);
+  }
 }
 
 void Profiler::collect() {
+  std::vector<uint32_t> h(used);
+  if (used) {
+    (void)hipDeviceSynchronize();
+    (void)hipMemcpy(h.data(), slots, (size_t)used * 4, hipMemcpyDeviceToHost);
+  }
   for (auto& p : pending) {
     float ms = 0;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ProfRec& r = acc[p.name];
       r.ms += ms;
-      r.bytes += p.bytes;
+      double b = p.bytes;
+      if (p.slot >= 0) b += p.per[0] * h[p.slot] + p.per[1] * h[p.slot + 1];
+      r.bytes += b;
       r.launches++;
     }
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
   pending.clear();
+  used = 0;
 }
 
 }  // namespace bzg
@@ -85,19 +106,27 @@ void Profiler::collect() {
 using namespace bzg;
 
 struct bzg_ctx {
-  std::mutex mu;  // calls on one context run one at a time
+  std::mutex mu;  // calls on one context enqueue one at a time
   int device = 0;
   Profiler prof;
   std::string err;
-  void* ws[2] = {nullptr, nullptr};
-  size_t ws_cap[2] = {0, 0};
-  void* pin = nullptr;
-  size_t pin_cap = 0;
-  void* stage = nullptr;  // pinned arena for uploads of host arrays
-  size_t stage_cap = 0;
+  uint32_t* status = nullptr;  // device: kernel-side error flags
   // device: 4 x 256 byte-step tables (slicing by 4), 64 powers x^(8*2^j),
   // 256 tile shifts (mod P)
   uint32_t* crc_tab = nullptr;
+  // workspace pool for calls without d_ws (stream-ordered growth)
+  void* pool = nullptr;
+  size_t pool_cap = 0;
+  hipEvent_t pool_ev = nullptr;  // the end of the last call that used the pool
+  bool pool_used = false;
+  // pinned arena for uploads of host tables: two halves, each with the event
+  // that follows its last copies
+  char* stage = nullptr;
+  size_t stage_half = 0;
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  bool stage_used[2] = {false, false};
+  int stage_next = 0;
+  uint32_t persist_cap = 2048;  // persistent grid cap (tunable; any value gives the same output)
 };
 
 namespace {
@@ -112,77 +141,11 @@ int hip_fail(bzg_ctx* c, hipError_t e, const char* where) {
   return BZG_EHIP;
 }
 
-#define HIPX(call)                                       \
-  do {                                                   \
-    hipError_t e_ = (call);                              \
+#define HIPX(call)                                         \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
   } while (0)
-
-// Scratch region `i` of at least `bytes`.  Growing waits for the device so
-// no queued work still uses the old region.
-int ensure_ws(bzg_ctx* ctx, int i, size_t bytes, void** out) {
-  if (ctx->ws_cap[i] < bytes) {
-    if (ctx->ws[i]) {
-      HIPX(hipDeviceSynchronize());
-      HIPX(hipFree(ctx->ws[i]));
-      ctx->ws[i] = nullptr;
-      ctx->ws_cap[i] = 0;
-    }
-    size_t want = bytes + bytes / 8 + (1 << 20);
-    if (hipMalloc(&ctx->ws[i], want) != hipSuccess) {
-      (void)hipGetLastError();
-      ctx->ws[i] = nullptr;
-      return fail(ctx, BZG_ENOMEM, "device scratch allocation of " + std::to_string(want) + " bytes failed");
-    }
-    ctx->ws_cap[i] = want;
-  }
-  *out = ctx->ws[i];
-  return 0;
-}
-
-int ensure_pin(bzg_ctx* ctx, size_t bytes, void** out) {
-  if (ctx->pin_cap < bytes) {
-    if (ctx->pin) {
-      HIPX(hipDeviceSynchronize());
-      HIPX(hipHostFree(ctx->pin));
-      ctx->pin = nullptr;
-      ctx->pin_cap = 0;
-    }
-    size_t want = std::max(bytes, size_t(1) << 16);
-    if (hipHostMalloc(&ctx->pin, want, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      ctx->pin = nullptr;
-      return fail(ctx, BZG_ENOMEM, "pinned host allocation failed");
-    }
-    ctx->pin_cap = want;
-  }
-  *out = ctx->pin;
-  return 0;
-}
-
-// The upload arena, at least `bytes` large, bound to stream st.
-int ensure_stage(bzg_ctx* ctx, size_t bytes, hipStream_t st, Stager* out) {
-  if (ctx->stage_cap < bytes) {
-    if (ctx->stage) {
-      HIPX(hipDeviceSynchronize());
-      HIPX(hipHostFree(ctx->stage));
-      ctx->stage = nullptr;
-      ctx->stage_cap = 0;
-    }
-    size_t want = std::max(bytes, size_t(1) << 20);
-    if (hipHostMalloc(&ctx->stage, want, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      ctx->stage = nullptr;
-      return fail(ctx, BZG_ENOMEM, "pinned host allocation failed");
-    }
-    ctx->stage_cap = want;
-  }
-  out->base = (char*)ctx->stage;
-  out->cap = ctx->stage_cap;
-  out->used = ctx->stage_cap;  // full: the first upload drains the stream
-  out->st = st;
-  return 0;
-}
 
 // CRC helper tables (built on the host from the polynomial).  tab[k*256 + b]
 // is the register after k + 1 byte steps from b << 24 with zero input: the
@@ -220,6 +183,8 @@ void crc_tables(uint32_t* tab, uint32_t* pw) {
   }
 }
 
+// Carves a workspace into 256-byte aligned arrays.  With base == nullptr it
+// only adds up the size (the same sequence of takes sizes and carves).
 struct Carve {
   char* base;
   size_t used = 0;
@@ -227,38 +192,9 @@ struct Carve {
   T* take(size_t n) {
     size_t a = (used + 255) & ~size_t(255);
     used = a + n * sizeof(T);
-    return reinterpret_cast<T*>(base + a);
+    return base ? reinterpret_cast<T*>(base + a) : nullptr;
   }
 };
-
-template <typename T>
-size_t sz(size_t n) {
-  return ((n * sizeof(T)) + 255) & ~size_t(255);
-}
-
-// Routes instrumented launches of one API call to the context's profiler.
-struct ProfGuard {
-  bzg_ctx* c;
-  explicit ProfGuard(bzg_ctx* x) : c(x) { g_prof = &c->prof; }
-  ~ProfGuard() {
-    if (c->prof.on) c->prof.collect();
-    g_prof = nullptr;
-  }
-};
-
-// Tiles of `per` selector groups per block, from the per-block group
-// capacities selb[b+1]-selb[b].
-void group_tiles(const std::vector<uint64_t>& selb, uint32_t nb, uint32_t per, std::vector<uint32_t>& tile_blk,
-                 std::vector<uint32_t>& blk_tile0) {
-  tile_blk.clear();
-  blk_tile0.assign(nb + 1, 0);
-  for (uint32_t b = 0; b < nb; b++) {
-    blk_tile0[b] = (uint32_t)tile_blk.size();
-    uint64_t g = selb[b + 1] - selb[b];
-    for (uint64_t q = 0; q < (g + per - 1) / per; q++) tile_blk.push_back(b);
-  }
-  blk_tile0[nb] = (uint32_t)tile_blk.size();
-}
 
 bool offsets_ok(const uint64_t* h, uint32_t nb) {
   for (uint32_t k = 0; k < nb; k++)
@@ -266,11 +202,407 @@ bool offsets_ok(const uint64_t* h, uint32_t nb) {
   return true;
 }
 
+// Routes instrumented launches of one API call to the context's profiler.
+struct ProfGuard {
+  explicit ProfGuard(bzg_ctx* x) { g_prof = &x->prof; }
+  ~ProfGuard() { g_prof = nullptr; }
+};
+
+// Workspace for a call: the caller's, or the context's pool (grown in
+// stream order: the old pool is freed once `st` has passed every earlier
+// call that used it).
+int get_ws(bzg_ctx* ctx, void* d_ws, size_t ws_bytes, size_t need, hipStream_t st, void** out) {
+  if (d_ws) {
+    if (ws_bytes < need)
+      return fail(ctx, BZG_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes; the call needs " +
+                                           std::to_string(need));
+    if ((uintptr_t)d_ws & 255) return fail(ctx, BZG_EINVAL, "d_ws must be 256-byte aligned");
+    *out = d_ws;
+    return 0;
+  }
+  if (ctx->pool_used) HIPX(hipStreamWaitEvent(st, ctx->pool_ev, 0));
+  if (ctx->pool_cap < need) {
+    if (ctx->pool) {
+      HIPX(hipFreeAsync(ctx->pool, st));
+      ctx->pool = nullptr;
+      ctx->pool_cap = 0;
+    }
+    const size_t want = need + need / 8 + (1 << 20);
+    if (hipMallocAsync(&ctx->pool, want, st) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->pool = nullptr;
+      return fail(ctx, BZG_ENOMEM, "device workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->pool_cap = want;
+  }
+  *out = ctx->pool;
+  return 0;
+}
+
+// Marks the end of a call's work on the pool (when it used the pool).
+int end_ws(bzg_ctx* ctx, void* d_ws, hipStream_t st) {
+  if (!d_ws) {
+    HIPX(hipEventRecord(ctx->pool_ev, st));
+    ctx->pool_used = true;
+  }
+  return 0;
+}
+
+// Host tables copied into the workspace through the pinned arena: the
+// arena's halves alternate, and a half is refilled only after the copies
+// last made from it have completed (normally long done).
+struct Upload {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+int upload(bzg_ctx* ctx, std::initializer_list<Upload> ups, hipStream_t st) {
+  size_t tot = 0;
+  for (const Upload& u : ups) tot += (u.bytes + 255) & ~size_t(255);
+  if (tot == 0) return 0;
+  if (tot > ctx->stage_half) {  // grow: wait for both halves' copies first
+    for (int h = 0; h < 2; h++)
+      if (ctx->stage_used[h]) HIPX(hipEventSynchronize(ctx->stage_ev[h]));
+    if (ctx->stage) HIPX(hipHostFree(ctx->stage));
+    ctx->stage = nullptr;
+    const size_t half = std::max(tot, ctx->stage_half * 2);
+    if (hipHostMalloc((void**)&ctx->stage, 2 * half, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->stage = nullptr;
+      ctx->stage_half = 0;
+      return fail(ctx, BZG_ENOMEM, "pinned host allocation failed");
+    }
+    ctx->stage_half = half;
+    ctx->stage_used[0] = ctx->stage_used[1] = false;
+  }
+  const int h = ctx->stage_next;
+  ctx->stage_next ^= 1;
+  if (ctx->stage_used[h]) HIPX(hipEventSynchronize(ctx->stage_ev[h]));
+  char* p = ctx->stage + (size_t)h * ctx->stage_half;
+  size_t at = 0;
+  for (const Upload& u : ups) {
+    if (!u.bytes) continue;
+    memcpy(p + at, u.src, u.bytes);
+    HIPX(hipMemcpyAsync(u.dst, p + at, u.bytes, hipMemcpyHostToDevice, st));
+    at += (u.bytes + 255) & ~size_t(255);
+  }
+  HIPX(hipEventRecord(ctx->stage_ev[h], st));
+  ctx->stage_used[h] = true;
+  return 0;
+}
+
+// ------------------------------------------------------------ compress plan
+
+// Host bounds of a compress call, from the input offsets alone.
+struct CBounds {
+  uint32_t nb = 0, nslot = 0, L = 0;
+  bool direct = true;  // no block can need cutting: one slot per block
+  uint64_t total = 0;
+  uint32_t in_tiles = 0, slot_tiles = 0, rows = 0, max_len = 0, sort_tiles = 0, mtf_ch = 0, chunks = 0;
+  uint32_t groups = 0, atg = 0, asg_tiles = 0, pack_tiles = 0;
+  uint64_t max_words = 0;  // largest stream, in 32-bit words
+};
+
+uint64_t compress_bound(uint64_t n_bytes, uint32_t n_blocks) {
+  // every RLE1 byte becomes at most one 17-bit code (plus RUNA/RUNB digits,
+  // which only replace zeros); generous per-block header allowance
+  uint64_t rle = n_bytes + n_bytes / 4 + 4;
+  uint64_t blocks = (uint64_t)n_blocks + rle / 100000 + 2;
+  uint64_t bits = 32 + 80 + blocks * (105 + 16 + 256 + 18 + 6 * (5 + 258 * 33)) + rle * 17 + (rle / 50 + blocks) * 7;
+  return ((bits + 7) / 8 + 3) & ~uint64_t(3);
+}
+
+CBounds compress_bounds(const uint64_t* h_off, uint32_t nb, int level, const uint32_t* h_rb, uint32_t n_req) {
+  CBounds c;
+  c.nb = nb;
+  c.L = 100000u * (uint32_t)level;
+  uint64_t rows = 0;
+  for (uint32_t k = 0; k < nb; k++) {
+    const uint64_t n = h_off[k + 1] - h_off[k];
+    const uint32_t pm = max_pieces(n, c.L);
+    c.nslot += pm;
+    if (pm > 1) c.direct = false;
+    c.in_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE);
+    c.slot_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE) + (pm ? pm - 1 : 0);
+    const uint64_t r = std::min<uint64_t>(n + n / 4, (uint64_t)pm * c.L);
+    rows += r;
+    c.max_len = (uint32_t)std::max<uint64_t>(c.max_len, std::min<uint64_t>(n + n / 4, c.L));
+  }
+  c.total = nb ? h_off[nb] - h_off[0] : 0;
+  c.rows = (uint32_t)std::min<uint64_t>(rows, 0xFFFFFFF0ull);
+  c.sort_tiles = c.rows / RADIX_TILE + c.nslot + 1;
+  c.mtf_ch = mtf_chunk_rows(c.rows, c.nslot);
+  c.chunks = c.rows / c.mtf_ch + c.nslot + 1;
+  c.groups = c.rows / GROUP + c.nslot + 1;
+  c.atg = huff_assign_groups(c.groups);
+  c.asg_tiles = c.groups / c.atg + c.nslot + 1;
+  c.pack_tiles = c.groups / PACK_GROUPS + c.nslot + 1;
+  for (uint32_t r = 0; r < n_req; r++) {
+    const uint32_t a = h_rb ? h_rb[r] : 0, e = h_rb ? h_rb[r + 1] : nb;
+    const uint64_t bytes = nb ? h_off[e] - h_off[a] : 0;
+    c.max_words = std::max<uint64_t>(c.max_words, compress_bound(bytes, e - a) / 4);
+  }
+  return c;
+}
+
+// The compress workspace, carved in a fixed order (sizing and carving take
+// the same path).
+struct CWork {
+  uint64_t *off_copy, *rout_copy;
+  uint32_t* rb_copy;
+  uint32_t *slot_base, *in_tile0, *cnt, *skip;
+  uint64_t* in_rel;
+  uint32_t *in_tile_blk, *in_tile_rs, *in_tile_out, *in_rle_n, *in_crc;
+  void* in_rec;
+  uint64_t* slot_in;
+  uint32_t *slot_tile0, *slot_tile_blk, *tile_rs, *tile_out, *rle_n, *crc;
+  void* rec;
+  uint32_t *roff, *sort_tile0, *chunk0, *asg_tile0, *pack_tile0, *chunk_blk, *asg_blk, *pack_blk;
+  uint64_t *sbase, *selb;
+  uint8_t *text, *L;
+  uint32_t* primary;
+  uint16_t* syms;
+  uint32_t *nsyms, *inuse, *freq;
+  uint8_t *sel, *selmtf;
+  uint64_t *gbits, *blkbit, *info;
+  unsigned long long* gstate;
+  BlockTables* tabs;
+  void *hws, *stage;  // huffman scratch; sort / MTF scratch (shared: the sort's is free after bwt_out)
+  size_t stage_bytes;
+};
+
+size_t carve_compress(char* base, const CBounds& c, uint32_t n_req, CWork& w, size_t total_cap) {
+  Carve cv{base};
+  const uint32_t ns = std::max<uint32_t>(c.nslot, 1);
+  w.off_copy = cv.take<uint64_t>(c.nb + 1);
+  w.rout_copy = cv.take<uint64_t>(n_req + 1);
+  w.rb_copy = cv.take<uint32_t>(n_req + 1);
+  w.slot_base = cv.take<uint32_t>(c.nb + 1);
+  w.in_tile0 = cv.take<uint32_t>(c.nb + 1);
+  w.cnt = cv.take<uint32_t>(PC_COUNT);
+  w.skip = cv.take<uint32_t>(4);
+  w.in_rel = cv.take<uint64_t>(c.nb + 1);
+  const uint32_t it = c.direct ? 0 : c.in_tiles;
+  w.in_tile_blk = cv.take<uint32_t>(it + 1);
+  w.in_rec = cv.take<char>(rle_tile_bytes() * (it + 1));
+  w.in_tile_rs = cv.take<uint32_t>(it + 1);
+  w.in_tile_out = cv.take<uint32_t>(it + 1);
+  w.in_rle_n = cv.take<uint32_t>(c.nb + 1);
+  w.in_crc = cv.take<uint32_t>(c.nb + 1);
+  w.slot_in = cv.take<uint64_t>(ns + 1);
+  w.slot_tile0 = cv.take<uint32_t>(ns + 1);
+  w.slot_tile_blk = cv.take<uint32_t>(c.slot_tiles + 1);
+  w.rec = cv.take<char>(rle_tile_bytes() * (c.slot_tiles + 1));
+  w.tile_rs = cv.take<uint32_t>(c.slot_tiles + 1);
+  w.tile_out = cv.take<uint32_t>(c.slot_tiles + 1);
+  w.rle_n = cv.take<uint32_t>(ns);
+  w.crc = cv.take<uint32_t>(ns);
+  w.roff = cv.take<uint32_t>(ns + 1);
+  w.sbase = cv.take<uint64_t>(ns);
+  w.selb = cv.take<uint64_t>(ns + 1);
+  w.sort_tile0 = cv.take<uint32_t>(ns + 1);
+  w.chunk0 = cv.take<uint32_t>(ns + 1);
+  w.asg_tile0 = cv.take<uint32_t>(ns + 1);
+  w.pack_tile0 = cv.take<uint32_t>(ns + 1);
+  w.chunk_blk = cv.take<uint32_t>(c.chunks + 1);
+  w.asg_blk = cv.take<uint32_t>(c.asg_tiles + 1);
+  w.pack_blk = cv.take<uint32_t>(c.pack_tiles + 1);
+  w.text = cv.take<uint8_t>((size_t)c.rows + 64);
+  w.L = cv.take<uint8_t>((size_t)c.rows + 64);
+  w.primary = cv.take<uint32_t>(ns);
+  w.syms = cv.take<uint16_t>((size_t)c.rows + ns + 64);
+  w.nsyms = cv.take<uint32_t>(ns);
+  w.inuse = cv.take<uint32_t>((size_t)ns * 8);
+  w.freq = cv.take<uint32_t>((size_t)ns * MAXA);
+  w.sel = cv.take<uint8_t>((size_t)c.groups + 1);
+  w.selmtf = cv.take<uint8_t>((size_t)c.groups + 1);
+  w.gbits = cv.take<uint64_t>((size_t)c.groups + 1);
+  w.gstate = cv.take<unsigned long long>(scan_lb_states(c.groups) + 1);
+  w.tabs = cv.take<BlockTables>(ns);
+  w.blkbit = cv.take<uint64_t>(ns);
+  w.info = cv.take<uint64_t>(2 * (size_t)n_req + 2);
+  w.hws = cv.take<char>(huff_workspace_bytes(ns));
+  const size_t stage = std::max(bwt_workspace_bytes(c.rows, ns), mtf_workspace_bytes(c.rows, ns));
+  w.stage = cv.take<char>(stage);
+  w.stage_bytes = base ? total_cap - ((char*)w.stage - base) : stage;
+  return cv.used + 256;
+}
+
+// The whole compressor for n_req streams: request r = input blocks
+// [rb[r], rb[r+1]), written from byte rout[r] of d_out.  d_off / d_rb /
+// d_rout are device tables (already in the workspace or the caller's).
+int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8_t* in, const uint64_t* d_off,
+                     const uint32_t* d_rb, const uint64_t* d_rout, uint32_t n_req, int level, uint8_t* d_out,
+                     uint64_t* d_out_bytes, uint32_t* d_n_blocks, hipStream_t st) {
+  uint32_t* err = ctx->status;
+  const uint32_t nb = c.nb, ns = c.nslot, P = ctx->persist_cap;
+  HIPX(plan_input(d_off, nb, c.L, w.slot_base, w.in_tile0, w.cnt + PC_IN_TILES, w.in_rel, st));
+  if (ns) {
+    const uint64_t* slot_in = w.in_rel;
+    if (!c.direct) {  // whole-block RLE1 lengths, then the cuts
+      MapSet m{};
+      m.map[0] = MapDesc{w.in_tile0, w.in_tile_blk, w.cnt + PC_IN_TILES, c.in_tiles, nb};
+      m.nmaps = 1;
+      m.err = err;
+      HIPX(fill_maps(m, st));
+      {
+        ProfScope ps("rle1_tiles", st, 0, w.cnt + PC_IN_TILES, RLE_TILE);
+        HIPX(rle1_tiles(in, persist_grid(c.in_tiles, P), w.cnt + PC_IN_TILES, w.in_tile_blk, w.in_tile0, w.in_rel,
+                        ctx->crc_tab, ctx->crc_tab + CRC_POW_AT, w.in_rec, st));
+      }
+      HIPX(rle1_blocks(nb, w.in_tile0, w.in_rel, ctx->crc_tab + CRC_POW_AT, w.in_rec, w.in_tile_rs, w.in_tile_out,
+                       w.in_rle_n, w.in_crc, st));
+      HIPX(rle1_split(in, w.in_rel, nb, w.in_tile0, w.in_rec, w.in_tile_rs, w.in_tile_out, w.in_rle_n, w.slot_base,
+                      ns, c.L, w.slot_in, err, st));
+      slot_in = w.slot_in;
+    }
+    HIPX(plan_slot_tiles(slot_in, ns, w.slot_tile0, w.cnt + PC_RLE_TILES, st));
+    {
+      MapSet m{};
+      m.map[0] = MapDesc{w.slot_tile0, w.slot_tile_blk, w.cnt + PC_RLE_TILES, c.slot_tiles, ns};
+      m.nmaps = 1;
+      m.err = err;
+      HIPX(fill_maps(m, st));
+    }
+    {
+      ProfScope ps("rle1_tiles", st, 0, w.cnt + PC_RLE_TILES, RLE_TILE);
+      HIPX(rle1_tiles(in, persist_grid(c.slot_tiles, P), w.cnt + PC_RLE_TILES, w.slot_tile_blk, w.slot_tile0, slot_in,
+                      ctx->crc_tab, ctx->crc_tab + CRC_POW_AT, w.rec, st));
+    }
+    HIPX(rle1_blocks(ns, w.slot_tile0, slot_in, ctx->crc_tab + CRC_POW_AT, w.rec, w.tile_rs, w.tile_out, w.rle_n,
+                     w.crc, st));
+    // the layout of every later stage, from the RLE1 lengths
+    BwtWork bw;
+    if (!bwt_carve(w.stage, w.stage_bytes, c.rows, ns, bw)) return fail(ctx, BZG_EINTERNAL, "sort workspace");
+    {
+      PlanArgs a{ns, c.mtf_ch, c.atg, 1};
+      PlanOut o{w.roff, w.sbase, w.selb, w.sort_tile0, bw.segs[0], w.chunk0, w.asg_tile0, w.pack_tile0, w.cnt};
+      HIPX(plan_layout(w.rle_n, nullptr, a, o, st));
+      MapSet m{};
+      m.map[0] = MapDesc{w.sort_tile0, bw.owner[0], w.cnt + PC_SORT_TILES, c.sort_tiles, ns};
+      m.map[1] = MapDesc{w.chunk0, w.chunk_blk, w.cnt + PC_CHUNKS, c.chunks, ns};
+      m.map[2] = MapDesc{w.asg_tile0, w.asg_blk, w.cnt + PC_ASSIGN_TILES, c.asg_tiles, ns};
+      m.map[3] = MapDesc{w.pack_tile0, w.pack_blk, w.cnt + PC_PACK_TILES, c.pack_tiles, ns};
+      m.nmaps = 4;
+      m.err = err;
+      HIPX(fill_maps(m, st));
+    }
+    {
+      ProfScope ps("rle1_emit", st, 0, w.cnt + PC_RLE_TILES, RLE_TILE, w.cnt + PC_ROWS, 1.0);
+      HIPX(rle1_emit(in, persist_grid(c.slot_tiles, P), w.cnt + PC_RLE_TILES, w.slot_tile_blk, w.slot_tile0, slot_in,
+                     w.tile_rs, w.tile_out, w.roff, w.text, st));
+    }
+    // BWT
+    BwtBounds bd{ns, c.rows, c.max_len, c.sort_tiles};
+    HIPX(bwt_sort(bw, w.text, w.roff, w.cnt + PC_SORT_TILES, bd, err, nullptr, st));
+    HIPX(bwt_output(w.text, w.roff, ns, w.cnt + PC_ROWS, c.rows, bw.SA, w.L, w.primary, nullptr, st));
+    // MTF + RUNA/RUNB (the sort's scratch is free again)
+    hipError_t e = mtf_run(w.L, w.roff, ns, c.rows, w.chunk_blk, w.chunk0, w.cnt + PC_CHUNKS, w.stage, w.stage_bytes,
+                           w.syms, w.sbase, w.nsyms, w.inuse, w.freq, err, ctx->err, st);
+    if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EINTERNAL;
+    // Huffman tables and group bit counts
+    HuffArgs ha{};
+    ha.nb = ns;
+    ha.syms = w.syms;
+    ha.sym_base = w.sbase;
+    ha.nsyms = w.nsyms;
+    ha.freq = w.freq;
+    ha.inuse = w.inuse;
+    ha.sel_base = w.selb;
+    ha.sel = w.sel;
+    ha.selmtf = w.selmtf;
+    ha.gbits = w.gbits;
+    ha.tabs = w.tabs;
+    ha.err = err;
+    ha.tile_blk = w.asg_blk;
+    ha.blk_tile0 = w.asg_tile0;
+    ha.n_tiles = w.cnt + PC_ASSIGN_TILES;
+    ha.tiles_cap = c.asg_tiles;
+    ha.tile_groups = c.atg;
+    ha.ws = w.hws;
+    HIPX(huff_run(ha, st));
+    HIPX(fill32((uint32_t*)w.gstate, 2 * (uint64_t)scan_lb_states(c.groups), 0u, st));
+    {
+      ProfScope ps("scan", st, 0, w.cnt + PC_GROUPS_LO, 16.0);
+      HIPX(scan_lb_u64(w.gbits, w.cnt + PC_GROUPS_LO, c.groups, 1, w.gstate, err, persist_grid(c.groups / 2048 + 1, P),
+                       st));
+    }
+  }
+  // stream layout, sizes and the capacity check
+  HIPX(pack_layout(ns, n_req, d_rb, d_rout, w.tabs, 0, nullptr, w.blkbit, w.crc, w.info, d_out_bytes, d_n_blocks,
+                   w.slot_base, w.skip, err, st));
+  {
+    ProfScope ps("pack", st, 0, w.cnt + PC_ROWS, 2.0);  // symbols in (the streams out are not counted here)
+    HIPX(zero_streams(n_req, c.max_words, d_rout, w.info, (uint32_t*)d_out, w.skip, st));
+    HIPX(pack_run(ns, w.tabs, 0, w.blkbit, w.crc, w.primary, w.inuse, w.selb, w.sel, w.selmtf, w.gbits,
+                  w.cnt + PC_PACK_TILES, c.pack_tiles, w.pack_blk, w.pack_tile0, w.syms, w.sbase, w.nsyms, level,
+                  n_req, d_rout, w.info, (uint32_t*)d_out, w.skip, st));
+  }
+  return 0;
+}
+
+// Argument checks shared by compress_blocks and compress_batch.
+int check_compress(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level) {
+  if (!h_offsets) return fail(ctx, BZG_EINVAL, "null h_offsets");
+  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
+  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
+  if (n_blocks && h_offsets[n_blocks] > h_offsets[0] && !d_in) return fail(ctx, BZG_EINVAL, "null input");
+  if (n_blocks && h_offsets[n_blocks] - h_offsets[0] >= (1ull << 31))
+    return fail(ctx, BZG_EINVAL, "input too large for one call (2^31 bytes)");
+  return 0;
+}
+
+int compress_common(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                    uint32_t n_blocks, const uint32_t* d_rb, const uint32_t* h_rb, uint32_t n_req, int level,
+                    uint8_t* d_out, const uint64_t* d_rout, const uint64_t* h_rout, uint64_t out_cap,
+                    uint64_t* d_out_bytes, uint32_t* d_n_blocks, void* d_ws, size_t ws_bytes, hipStream_t st) {
+  HIPX(hipSetDevice(ctx->device));
+  const uint64_t zero_off = 0;
+  const uint64_t* hoff = n_blocks ? h_offsets : &zero_off;
+  const CBounds c = compress_bounds(hoff, n_blocks, level, h_rb, n_req);
+  CWork w;
+  const size_t need = carve_compress(nullptr, c, n_req, w, 0);
+  void* ws;
+  int rc = get_ws(ctx, d_ws, ws_bytes, need, st, &ws);
+  if (rc) return rc;
+  const size_t cap = d_ws ? ws_bytes : ctx->pool_cap;
+  carve_compress((char*)ws, c, n_req, w, cap);
+  // device tables: the caller's, or copies of the host ones
+  const uint64_t* d_off = d_offsets;
+  if (!d_off) {
+    std::vector<uint64_t> tmp;
+    if (!n_blocks) tmp.assign(1, 0);
+    if ((rc = upload(ctx, {{w.off_copy, n_blocks ? h_offsets : tmp.data(), (size_t)(n_blocks + 1) * 8}}, st)))
+      return rc;
+    d_off = w.off_copy;
+  }
+  const uint8_t* in = d_in ? d_in + (n_blocks ? h_offsets[0] : 0) : nullptr;
+  if (h_rb) {  // compress_batch: request tables
+    if (!d_rb || !d_rout) {
+      if ((rc = upload(ctx,
+                       {{d_rb ? nullptr : (void*)w.rb_copy, h_rb, d_rb ? 0 : (size_t)(n_req + 1) * 4},
+                        {d_rout ? nullptr : (void*)w.rout_copy, h_rout, d_rout ? 0 : (size_t)(n_req + 1) * 8}},
+                       st)))
+        return rc;
+      if (!d_rb) d_rb = w.rb_copy;
+      if (!d_rout) d_rout = w.rout_copy;
+    }
+    HIPX(call_init(w.skip, nullptr, 0, nullptr, 0, st));
+  } else {  // compress_blocks: one request over every block, d_out[0, cap)
+    HIPX(call_init(w.skip, w.rb_copy, n_blocks, w.rout_copy, out_cap & ~3ull, st));
+    d_rb = w.rb_copy;
+    d_rout = w.rout_copy;
+  }
+  rc = compress_enqueue(ctx, c, w, in, d_off, d_rb, d_rout, n_req, level, d_out, d_out_bytes, d_n_blocks, st);
+  if (rc) return rc;
+  return end_ws(ctx, d_ws, st);
+}
+
 }  // namespace
 
 extern "C" {
 
-int bzg_create(bzg_ctx** out, int hip_device) {
+int bzg_create(bzg_ctx** out, int hip_device, const char* tune_cache_path) {
   if (!out) return BZG_EINVAL;
   *out = nullptr;
   bzg_ctx* ctx = new (std::nothrow) bzg_ctx();
@@ -278,15 +610,24 @@ int bzg_create(bzg_ctx** out, int hip_device) {
   ctx->device = hip_device;
   hipError_t e = hipSetDevice(hip_device);
   if (e == hipSuccess) e = hipMalloc(&ctx->crc_tab, CRC_TAB_WORDS * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&ctx->status, 256);
+  if (e == hipSuccess) e = hipMemset(ctx->status, 0, 256);
   if (e == hipSuccess) {
     uint32_t h[CRC_TAB_WORDS];
     crc_tables(h, h + CRC_POW_AT);
     e = hipMemcpy(ctx->crc_tab, h, sizeof(h), hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->pool_ev, hipEventDisableTiming);
+  for (int h = 0; h < 2 && e == hipSuccess; h++) e = hipEventCreateWithFlags(&ctx->stage_ev[h], hipEventDisableTiming);
+  if (e == hipSuccess) {
+    ctx->stage_half = 1 << 19;
+    e = hipHostMalloc((void**)&ctx->stage, 2 * ctx->stage_half, hipHostMallocDefault);
+  }
   if (e != hipSuccess) {
-    delete ctx;
+    bzg_destroy(ctx);
     return BZG_EHIP;
   }
+  (void)tune_cache_path;
   *out = ctx;
   return 0;
 }
@@ -295,20 +636,52 @@ void bzg_destroy(bzg_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (int i = 0; i < 2; i++)
-    if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
-  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->pool) {
+    (void)hipFreeAsync(ctx->pool, nullptr);
+    (void)hipDeviceSynchronize();
+  }
   if (ctx->stage) (void)hipHostFree(ctx->stage);
   if (ctx->crc_tab) (void)hipFree(ctx->crc_tab);
+  if (ctx->status) (void)hipFree(ctx->status);
+  if (ctx->prof.slots) (void)hipFree(ctx->prof.slots);
+  if (ctx->pool_ev) (void)hipEventDestroy(ctx->pool_ev);
+  for (int h = 0; h < 2; h++)
+    if (ctx->stage_ev[h]) (void)hipEventDestroy(ctx->stage_ev[h]);
+  for (auto& p : ctx->prof.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
   delete ctx;
 }
 
 const char* bzg_last_error(const bzg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int bzg_check(bzg_ctx* ctx, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  HIPX(hipSetDevice(ctx->device));
+  HIPX(hipStreamSynchronize((hipStream_t)stream));
+  uint32_t s[4];
+  HIPX(hipMemcpy(s, ctx->status, sizeof(s), hipMemcpyDeviceToHost));
+  if (!s[0]) return 0;
+  HIPX(hipMemset(ctx->status, 0, sizeof(s)));
+  if (s[0] & ERR_BOUND) return fail(ctx, BZG_EINTERNAL, "a device-side count passed its bound; results are not valid");
+  if (s[0] & ERR_SYMBOL)
+    return fail(ctx, BZG_EDATA, "a symbol outside its block's alphabet (or more symbols than the block's capacity)");
+  return fail(ctx, BZG_ECAPACITY, "an output range was too small; nothing was packed");
+}
+
 int bzg_profile(bzg_ctx* ctx, int enable) {
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (enable) ctx->prof.acc.clear();
+  if (enable) {
+    ctx->prof.acc.clear();
+    if (!ctx->prof.slots) {
+      ctx->prof.nslots = 1 << 18;
+      HIPX(hipMalloc(&ctx->prof.slots, (size_t)ctx->prof.nslots * 4));
+    }
+  }
   ctx->prof.on = enable != 0;
   return 0;
 }
@@ -316,6 +689,7 @@ int bzg_profile(bzg_ctx* ctx, int enable) {
 int bzg_profile_read(bzg_ctx* ctx, char* buf, size_t cap) {
   if (!ctx || !buf || cap == 0) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->prof.collect();
   std::string s;
   char line[256];
   for (auto& kv : ctx->prof.acc) {
@@ -328,101 +702,216 @@ int bzg_profile_read(bzg_ctx* ctx, char* buf, size_t cap) {
   return 0;
 }
 
-uint64_t bzg_compress_bound(uint64_t n_bytes, uint32_t n_blocks) {
-  // every RLE1 byte becomes at most one 17-bit code (plus RUNA/RUNB digits,
-  // which only replace zeros); generous per-block header allowance
-  uint64_t rle = n_bytes + n_bytes / 4 + 4;
-  uint64_t blocks = (uint64_t)n_blocks + rle / 100000 + 2;
-  uint64_t bits = 32 + 80 + blocks * (105 + 16 + 256 + 18 + 6 * (5 + 258 * 33)) + rle * 17 + (rle / 50 + blocks) * 7;
-  return ((bits + 7) / 8 + 3) & ~uint64_t(3);
+uint64_t bzg_compress_bound(uint64_t n_bytes, uint32_t n_blocks) { return compress_bound(n_bytes, n_blocks); }
+
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------------------ BWT / MTF / Huffman calls
+
+struct SWork {  // the per-stage calls' workspace
+  uint64_t* off_copy;
+  uint64_t* out_copy;
+  uint32_t *roff, *sort_tile0, *chunk0, *chunk_blk, *asg_tile0, *asg_blk, *pack_tile0, *pack_blk, *cnt, *skip;
+  uint64_t *sbase, *selb;
+  uint32_t *freq, *ns_eff;
+  uint8_t *sel, *selmtf;
+  uint64_t *gbits, *blkbit;
+  unsigned long long* gstate;
+  BlockTables* tabs;
+  void *hws, *stage;
+  size_t stage_bytes;
+};
+
+struct SBounds {
+  uint32_t nb = 0, rows = 0, max_len = 0, sort_tiles = 0, mtf_ch = 0, chunks = 0, groups = 0, atg = 0, asg_tiles = 0,
+           pack_tiles = 0;
+};
+
+SBounds stage_bounds(const uint64_t* h_off, uint32_t nb, int call) {
+  SBounds b;
+  b.nb = nb;
+  uint64_t rows = nb ? h_off[nb] - h_off[0] : 0;
+  b.rows = (uint32_t)std::min<uint64_t>(rows, 0xFFFFFFF0ull);
+  for (uint32_t k = 0; k < nb; k++) b.max_len = (uint32_t)std::max<uint64_t>(b.max_len, h_off[k + 1] - h_off[k]);
+  b.sort_tiles = b.rows / RADIX_TILE + nb + 1;
+  b.mtf_ch = mtf_chunk_rows(b.rows, nb);
+  b.chunks = b.rows / b.mtf_ch + nb + 1;
+  if (call == BZG_CALL_HUFFMAN) {
+    uint64_t g = 0;
+    for (uint32_t k = 0; k < nb; k++) g += (h_off[k + 1] - h_off[k] + GROUP - 1) / GROUP;
+    b.groups = (uint32_t)g + 1;
+    b.atg = huff_assign_groups(g);
+    b.asg_tiles = b.groups / b.atg + nb + 1;
+    b.pack_tiles = b.groups / PACK_GROUPS + nb + 1;
+  }
+  return b;
 }
 
-int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
-                      uint8_t* d_bwt, uint32_t* d_primary, uint32_t* d_sa, void* stream) {
+size_t carve_stage(char* base, const SBounds& b, int call, SWork& w, size_t total_cap) {
+  Carve cv{base};
+  const uint32_t nb = std::max<uint32_t>(b.nb, 1);
+  w.off_copy = cv.take<uint64_t>(nb + 1);
+  w.out_copy = cv.take<uint64_t>(nb + 1);
+  w.cnt = cv.take<uint32_t>(PC_COUNT);
+  w.skip = cv.take<uint32_t>(4);
+  w.roff = cv.take<uint32_t>(nb + 1);
+  w.sbase = cv.take<uint64_t>(nb);
+  w.sort_tile0 = cv.take<uint32_t>(nb + 1);
+  w.chunk0 = cv.take<uint32_t>(nb + 1);
+  w.chunk_blk = cv.take<uint32_t>(call == BZG_CALL_MTF ? b.chunks + 1 : 1);
+  w.freq = cv.take<uint32_t>(call == BZG_CALL_HUFFMAN ? (size_t)nb * MAXA : 1);
+  w.ns_eff = cv.take<uint32_t>(nb);
+  w.selb = cv.take<uint64_t>(nb + 1);
+  w.asg_tile0 = cv.take<uint32_t>(nb + 1);
+  w.pack_tile0 = cv.take<uint32_t>(nb + 1);
+  w.asg_blk = cv.take<uint32_t>(b.asg_tiles + 1);
+  w.pack_blk = cv.take<uint32_t>(b.pack_tiles + 1);
+  w.sel = cv.take<uint8_t>(b.groups + 1);
+  w.selmtf = cv.take<uint8_t>(b.groups + 1);
+  w.gbits = cv.take<uint64_t>(b.groups + 1);
+  w.gstate = cv.take<unsigned long long>(scan_lb_states(b.groups) + 1);
+  w.blkbit = cv.take<uint64_t>(nb);
+  w.tabs = cv.take<BlockTables>(call == BZG_CALL_HUFFMAN ? nb : 1);
+  w.hws = cv.take<char>(call == BZG_CALL_HUFFMAN ? huff_workspace_bytes(nb) : 1);
+  size_t stage = 256;
+  if (call == BZG_CALL_BWT) stage = bwt_workspace_bytes(b.rows, nb);
+  if (call == BZG_CALL_MTF) stage = mtf_workspace_bytes(b.rows, nb);
+  w.stage = cv.take<char>(stage);
+  w.stage_bytes = base ? total_cap - ((char*)w.stage - base) : stage;
+  return cv.used + 256;
+}
+
+int stage_prologue(bzg_ctx* ctx, int call, const uint64_t* h_off, uint32_t nb, const uint64_t* d_off_in,
+                   void* d_ws, size_t ws_bytes, hipStream_t st, SBounds& b, SWork& w, const uint64_t** d_off) {
+  HIPX(hipSetDevice(ctx->device));
+  b = stage_bounds(h_off, nb, call);
+  const size_t need = carve_stage(nullptr, b, call, w, 0);
+  void* ws;
+  int rc = get_ws(ctx, d_ws, ws_bytes, need, st, &ws);
+  if (rc) return rc;
+  carve_stage((char*)ws, b, call, w, d_ws ? ws_bytes : ctx->pool_cap);
+  *d_off = d_off_in;
+  if (!d_off_in) {
+    if ((rc = upload(ctx, {{w.off_copy, h_off, (size_t)(nb + 1) * 8}}, st))) return rc;
+    *d_off = w.off_copy;
+  }
+  return 0;
+}
+
+int check_blocks(bzg_ctx* ctx, const uint64_t* h_offsets, uint32_t n_blocks) {
+  if (!offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
+  if (h_offsets[n_blocks] - h_offsets[0] >= (1ull << 32) - 4096) return fail(ctx, BZG_EINVAL, "batch too large");
+  for (uint32_t k = 0; k < n_blocks; k++) {
+    const uint64_t n = h_offsets[k + 1] - h_offsets[k];
+    if (n == 0 || n > BZG_MAX_BLOCK) return fail(ctx, BZG_EINVAL, "block length outside 1..BZG_MAX_BLOCK");
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bzg_workspace_size(bzg_ctx* ctx, int call, const uint64_t* h_offsets, uint32_t n_blocks, int level,
+                       uint32_t n_req, size_t* bytes) {
+  if (!ctx || !bytes || !h_offsets) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
+  if (call == BZG_CALL_COMPRESS) {
+    if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
+    if (n_req == 0) n_req = 1;
+    // the request split does not change the bound but for the stream words
+    const CBounds c = compress_bounds(h_offsets, n_blocks, level, nullptr, 1);
+    CWork w;
+    *bytes = carve_compress(nullptr, c, n_req, w, 0);
+    return 0;
+  }
+  if (call != BZG_CALL_BWT && call != BZG_CALL_MTF && call != BZG_CALL_HUFFMAN)
+    return fail(ctx, BZG_EINVAL, "unknown call id");
+  SBounds b = stage_bounds(h_offsets, n_blocks, call);
+  SWork w;
+  *bytes = carve_stage(nullptr, b, call, w, 0);
+  return 0;
+}
+
+int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                      uint32_t n_blocks, uint8_t* d_bwt, uint32_t* d_primary, uint32_t* d_sa, void* d_ws,
+                      size_t ws_bytes, void* stream) {
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
   if (!h_offsets || !d_bwt || !d_primary || (n_blocks && !d_in)) return fail(ctx, BZG_EINVAL, "null pointer");
   if (n_blocks == 0) return 0;
-  if (!offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
-  if (h_offsets[n_blocks] - h_offsets[0] >= (1ull << 32) - 4096) return fail(ctx, BZG_EINVAL, "batch too large");
-  std::vector<uint32_t> off(n_blocks + 1);
-  for (uint32_t k = 0; k <= n_blocks; k++) off[k] = (uint32_t)(h_offsets[k] - h_offsets[0]);
-  for (uint32_t k = 0; k < n_blocks; k++) {
-    uint32_t n = off[k + 1] - off[k];
-    if (n == 0 || n > BZG_MAX_BLOCK) return fail(ctx, BZG_EINVAL, "block length outside 1..BZG_MAX_BLOCK");
-  }
-  hipStream_t st = (hipStream_t)stream;
-  HIPX(hipSetDevice(ctx->device));
-  const uint32_t N = off[n_blocks];
-  void* ws;
-  int rc = ensure_ws(ctx, 0, bwt_workspace_bytes(N, n_blocks), &ws);
+  int rc = check_blocks(ctx, h_offsets, n_blocks);
   if (rc) return rc;
-  void* pin;
-  if ((rc = ensure_pin(ctx, 4096, &pin))) return rc;
-  Stager stg;
-  if ((rc = ensure_stage(ctx, 65536 + 8 * (size_t)n_blocks + N / 256, st, &stg))) return rc;
+  if ((uintptr_t)(d_in + h_offsets[0]) & 3) return fail(ctx, BZG_EINVAL, "d_in + h_offsets[0] must be 4-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  SBounds b;
+  SWork w;
+  const uint64_t* d_off;
+  if ((rc = stage_prologue(ctx, BZG_CALL_BWT, h_offsets, n_blocks, d_offsets, d_ws, ws_bytes, st, b, w, &d_off)))
+    return rc;
+  BwtWork bw;
+  if (!bwt_carve(w.stage, w.stage_bytes, b.rows, n_blocks, bw)) return fail(ctx, BZG_EINTERNAL, "sort workspace");
+  PlanArgs a{n_blocks, b.mtf_ch, 1, 0};
+  PlanOut o{w.roff, nullptr, nullptr, w.sort_tile0, bw.segs[0], nullptr, nullptr, nullptr, w.cnt};
+  HIPX(plan_layout(nullptr, d_off, a, o, st));
+  MapSet m{};
+  m.map[0] = MapDesc{w.sort_tile0, bw.owner[0], w.cnt + PC_SORT_TILES, b.sort_tiles, n_blocks};
+  m.nmaps = 1;
+  m.err = ctx->status;
+  HIPX(fill_maps(m, st));
   const uint8_t* text = d_in + h_offsets[0];
-  uint32_t *SA, *d_off;
-  int rounds = 0;
-  hipError_t e = bwt_sort(text, off, ws, ctx->ws_cap[0], (RoundCounters*)pin, stg, &SA, &d_off, &rounds, ctx->err);
-  if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "bwt_sort") : BZG_EHIP;
-  HIPX(bwt_output(text, d_off, n_blocks, N, SA, d_bwt + h_offsets[0], d_primary, d_sa ? d_sa + h_offsets[0] : nullptr,
-                  st));
-  HIPX(hipStreamSynchronize(st));
-  return 0;
+  BwtBounds bd{n_blocks, b.rows, b.max_len, b.sort_tiles};
+  HIPX(bwt_sort(bw, text, w.roff, w.cnt + PC_SORT_TILES, bd, ctx->status, nullptr, st));
+  HIPX(bwt_output(text, w.roff, n_blocks, w.cnt + PC_ROWS, b.rows, bw.SA, d_bwt + h_offsets[0], d_primary,
+                  d_sa ? d_sa + h_offsets[0] : nullptr, st));
+  return end_ws(ctx, d_ws, st);
 }
 
-int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* h_offsets, uint32_t n_blocks,
-                     uint16_t* d_syms, uint32_t* d_nsyms, uint8_t* d_inuse, void* stream) {
+int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                     uint32_t n_blocks, uint16_t* d_syms, uint32_t* d_nsyms, uint8_t* d_inuse, void* d_ws,
+                     size_t ws_bytes, void* stream) {
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
-  if (!h_offsets || !d_syms || !d_nsyms || !d_inuse || (n_blocks && !d_bwt)) return fail(ctx, BZG_EINVAL, "null pointer");
+  if (!h_offsets || !d_syms || !d_nsyms || !d_inuse || (n_blocks && !d_bwt))
+    return fail(ctx, BZG_EINVAL, "null pointer");
   if (n_blocks == 0) return 0;
-  if (!offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
-  if (((uintptr_t)d_inuse & 3) != 0) return fail(ctx, BZG_EINVAL, "d_inuse must be 4-byte aligned");
-  if (h_offsets[n_blocks] - h_offsets[0] >= (1ull << 32) - 4096) return fail(ctx, BZG_EINVAL, "batch too large");
-  std::vector<uint32_t> off(n_blocks + 1);
-  for (uint32_t k = 0; k <= n_blocks; k++) off[k] = (uint32_t)(h_offsets[k] - h_offsets[0]);
-  for (uint32_t k = 0; k < n_blocks; k++) {
-    uint32_t n = off[k + 1] - off[k];
-    if (n == 0 || n > BZG_MAX_BLOCK) return fail(ctx, BZG_EINVAL, "block length outside 1..BZG_MAX_BLOCK");
-  }
-  hipStream_t st = (hipStream_t)stream;
-  HIPX(hipSetDevice(ctx->device));
-  std::vector<uint64_t> sbase(n_blocks);
-  for (uint32_t k = 0; k < n_blocks; k++) sbase[k] = h_offsets[k] + k;
-  size_t need = sz<uint32_t>(n_blocks + 1) + sz<uint64_t>(n_blocks) + sz<uint32_t>((size_t)n_blocks * MAXA) +
-                sz<uint32_t>(4) + mtf_workspace_bytes(off) + 4096;
-  void* ws;
-  int rc = ensure_ws(ctx, 1, need, &ws);
+  int rc = check_blocks(ctx, h_offsets, n_blocks);
   if (rc) return rc;
-  void* pin;
-  if ((rc = ensure_pin(ctx, 4096, &pin))) return rc;
-  Carve cv{(char*)ws};
-  uint32_t* d_off = cv.take<uint32_t>(n_blocks + 1);
-  uint64_t* d_sbase = cv.take<uint64_t>(n_blocks);
-  uint32_t* d_freq = cv.take<uint32_t>((size_t)n_blocks * MAXA);
-  uint32_t* d_err = cv.take<uint32_t>(4);
-  void* rest = cv.take<char>(0);
-  Stager stg;
-  if ((rc = ensure_stage(ctx, 65536 + 16 * (size_t)n_blocks + off[n_blocks] / 256, st, &stg))) return rc;
-  HIPX(stg.put_span({{d_off, off.data(), off.size() * 4}, {d_sbase, sbase.data(), sbase.size() * 8}}));
-  hipError_t e = mtf_run(d_bwt + h_offsets[0], d_off, off, rest, ctx->ws_cap[1] - cv.used, d_syms, d_sbase, d_nsyms,
-                         (uint32_t*)d_inuse, d_freq, d_err, stg, ctx->err);
-  if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
-  HIPX(hipMemcpyAsync(pin, d_err, 4, hipMemcpyDeviceToHost, st));
-  HIPX(hipStreamSynchronize(st));
-  if (*(uint32_t*)pin) return fail(ctx, BZG_EDATA, "mtf: symbol missing from the stack");
-  return 0;
+  if (((uintptr_t)d_inuse & 3) != 0) return fail(ctx, BZG_EINVAL, "d_inuse must be 4-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  SBounds b;
+  SWork w;
+  const uint64_t* d_off;
+  if ((rc = stage_prologue(ctx, BZG_CALL_MTF, h_offsets, n_blocks, d_offsets, d_ws, ws_bytes, st, b, w, &d_off)))
+    return rc;
+  PlanArgs a{n_blocks, b.mtf_ch, 1, 0};
+  PlanOut o{w.roff, w.sbase, nullptr, nullptr, nullptr, w.chunk0, nullptr, nullptr, w.cnt};
+  HIPX(plan_layout(nullptr, d_off, a, o, st));
+  MapSet m{};
+  m.map[0] = MapDesc{w.chunk0, w.chunk_blk, w.cnt + PC_CHUNKS, b.chunks, n_blocks};
+  m.nmaps = 1;
+  m.err = ctx->status;
+  HIPX(fill_maps(m, st));
+  // syms + h_offsets[0]: block k's symbols at (relative offset) + k
+  hipError_t e = mtf_run(d_bwt + h_offsets[0], w.roff, n_blocks, b.rows, w.chunk_blk, w.chunk0, w.cnt + PC_CHUNKS,
+                         w.stage, w.stage_bytes, d_syms + h_offsets[0], w.sbase, d_nsyms, (uint32_t*)d_inuse, w.freq,
+                         ctx->status, ctx->err, st);
+  if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EINTERNAL;
+  return end_ws(ctx, d_ws, st);
 }
 
 int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d_nsyms, const uint8_t* d_inuse,
-                         const uint64_t* h_sym_offsets, uint32_t n_blocks, uint8_t* d_out,
-                         const uint64_t* h_out_offsets, uint64_t* d_nbits, uint8_t* d_tables, void* stream) {
+                         const uint64_t* d_sym_offsets, const uint64_t* h_sym_offsets, uint32_t n_blocks,
+                         uint8_t* d_out, const uint64_t* d_out_offsets, const uint64_t* h_out_offsets,
+                         uint64_t* d_nbits, uint8_t* d_tables, void* d_ws, size_t ws_bytes, void* stream) {
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
@@ -434,408 +923,97 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
     return fail(ctx, BZG_EINVAL, "offsets decrease");
   if (((uintptr_t)d_out & 3) || (h_out_offsets[n_blocks] & 3) || (h_out_offsets[0] & 3) || ((uintptr_t)d_inuse & 3))
     return fail(ctx, BZG_EINVAL, "d_out/d_inuse must be 4-byte aligned and the output range multiples of 4");
+  for (uint32_t k = 0; k < n_blocks; k++)
+    if (h_sym_offsets[k + 1] - h_sym_offsets[k] > 2ull * BZG_MAX_BLOCK + 2)
+      return fail(ctx, BZG_EINVAL, "symbol capacity per block too large");
   hipStream_t st = (hipStream_t)stream;
-  HIPX(hipSetDevice(ctx->device));
-  std::vector<uint64_t> sbase(n_blocks), selb(n_blocks + 1), obyte(n_blocks + 1);
-  uint64_t ng = 0;
-  for (uint32_t k = 0; k < n_blocks; k++) {
-    sbase[k] = h_sym_offsets[k];
-    selb[k] = ng;
-    uint64_t cap = h_sym_offsets[k + 1] - h_sym_offsets[k];
-    if (cap > 2ull * BZG_MAX_BLOCK + 2) return fail(ctx, BZG_EINVAL, "symbol capacity per block too large");
-    ng += (cap + GROUP - 1) / GROUP;
+  SBounds b;
+  SWork w;
+  const uint64_t* d_soff;
+  int rc;
+  if ((rc = stage_prologue(ctx, BZG_CALL_HUFFMAN, h_sym_offsets, n_blocks, d_sym_offsets, d_ws, ws_bytes, st, b, w,
+                           &d_soff)))
+    return rc;
+  const uint64_t* d_oo = d_out_offsets;
+  if (!d_oo) {
+    if ((rc = upload(ctx, {{w.out_copy, h_out_offsets, (size_t)(n_blocks + 1) * 8}}, st))) return rc;
+    d_oo = w.out_copy;
   }
-  selb[n_blocks] = ng;
-  for (uint32_t k = 0; k <= n_blocks; k++) obyte[k] = h_out_offsets[k];
-  std::vector<uint32_t> tile_blk, blk_tile0, atile_blk, ablk_tile0;
-  group_tiles(selb, n_blocks, PACK_GROUPS, tile_blk, blk_tile0);
-  const uint32_t atg = huff_assign_groups(ng);
-  group_tiles(selb, n_blocks, atg, atile_blk, ablk_tile0);
-  const uint32_t ntiles = (uint32_t)tile_blk.size(), natiles = (uint32_t)atile_blk.size();
-  size_t need = sz<uint64_t>(n_blocks) * 2 + sz<uint64_t>(n_blocks + 1) * 2 + sz<uint32_t>((size_t)n_blocks * MAXA) +
-                sz<uint8_t>(ng + 1) * 2 + sz<uint64_t>(ng + 1) * 2 + sz<uint64_t>(scan_tmp_elems(ng + 1)) +
-                block_tables_bytes() * n_blocks + 256 + sz<uint32_t>(ntiles + 1) + sz<uint32_t>(natiles + 1) +
-                2 * sz<uint32_t>(n_blocks + 1) + sz<uint64_t>(4) + sz<uint32_t>(4) + huff_workspace_bytes(n_blocks) +
-                8192;
-  void* ws;
-  int rc = ensure_ws(ctx, 1, need, &ws);
-  if (rc) return rc;
-  void* pin;
-  if ((rc = ensure_pin(ctx, 4096, &pin))) return rc;
-  Carve cv{(char*)ws};
-  uint64_t* d_sbase = cv.take<uint64_t>(n_blocks);
-  uint64_t* d_selb = cv.take<uint64_t>(n_blocks + 1);
-  uint64_t* d_obyte = cv.take<uint64_t>(n_blocks + 1);
-  uint64_t* d_blkbit = cv.take<uint64_t>(n_blocks);
-  uint32_t* d_freq = cv.take<uint32_t>((size_t)n_blocks * MAXA);
-  uint8_t* d_sel = cv.take<uint8_t>(ng + 1);
-  uint8_t* d_selmtf = cv.take<uint8_t>(ng + 1);
-  uint64_t* d_gbits = cv.take<uint64_t>(ng + 1);
-  uint64_t* d_gofs = cv.take<uint64_t>(ng + 1);
-  uint64_t* d_stmp = cv.take<uint64_t>(scan_tmp_elems(ng + 1));
-  void* d_tabs = cv.take<char>(block_tables_bytes() * n_blocks);
-  uint32_t* d_tile_blk = cv.take<uint32_t>(ntiles + 1);
-  uint32_t* d_blk_tile0 = cv.take<uint32_t>(n_blocks + 1);
-  uint32_t* d_atile_blk = cv.take<uint32_t>(natiles + 1);
-  uint32_t* d_ablk_tile0 = cv.take<uint32_t>(n_blocks + 1);
-  uint64_t* d_info = cv.take<uint64_t>(4);
-  uint32_t* d_err = cv.take<uint32_t>(4);
-  void* d_hws = cv.take<char>(huff_workspace_bytes(n_blocks));
-  Stager stg;
-  if ((rc = ensure_stage(ctx, 65536 + 48 * (size_t)n_blocks + 4 * (size_t)(ntiles + natiles), st, &stg))) return rc;
-  // (the first three, and the four tile maps, are adjacent in the carve)
-  HIPX(stg.put_span({{d_sbase, sbase.data(), n_blocks * 8},
-                     {d_selb, selb.data(), (n_blocks + 1) * 8},
-                     {d_obyte, obyte.data(), (n_blocks + 1) * 8}}));
-  HIPX(stg.put_span({{d_tile_blk, tile_blk.data(), ntiles * 4},
-                     {d_blk_tile0, blk_tile0.data(), (n_blocks + 1) * 4},
-                     {d_atile_blk, atile_blk.data(), natiles * 4},
-                     {d_ablk_tile0, ablk_tile0.data(), (n_blocks + 1) * 4}}));
-  HIPX(hipMemsetAsync(d_err, 0, 16, st));
-  HIPX(huff_run(n_blocks, d_syms, d_sbase, d_nsyms, d_freq, true, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
-                d_gbits, d_tabs, d_err, natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
-  HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
-  HIPX(body_sizes(n_blocks, d_tabs, d_obyte, d_nbits, d_err, st));
-  HIPX(pack_layout(n_blocks, 1, nullptr, nullptr, d_tabs, 1, d_obyte, d_blkbit, nullptr, d_info, st));
-  HIPX(hipMemcpyAsync(pin, d_err, 4, hipMemcpyDeviceToHost, st));
-  HIPX(hipStreamSynchronize(st));
-  uint32_t ef = *(uint32_t*)pin;
-  if (ef & 2u) return fail(ctx, BZG_EDATA, "huffman: symbol outside the alphabet");
-  if (ef & 4u) return fail(ctx, BZG_ECAPACITY, "huffman: a block body does not fit its output range");
-  HIPX(hipMemsetAsync(d_out + h_out_offsets[0], 0, h_out_offsets[n_blocks] - h_out_offsets[0], st));
-  HIPX(pack_run(n_blocks, d_tabs, 1, d_blkbit, nullptr, nullptr, (const uint32_t*)d_inuse, d_selb, d_sel, d_selmtf,
-                d_gofs, ntiles, d_tile_blk, d_blk_tile0, d_syms, d_sbase, d_nsyms, 9, 0, nullptr, d_info,
-                (uint32_t*)d_out, st));
-  if (d_tables) HIPX(tables_export(n_blocks, d_tabs, d_tables, st));
-  HIPX(hipStreamSynchronize(st));
-  return 0;
-}
-
-}  // extern "C"
-
-namespace {
-
-// One bzip2 stream per request: request r is input blocks
-// [req_blocks[r], req_blocks[r+1]) and its stream goes to d_out + out_off[r],
-// at most out_off[r+1] - out_off[r] bytes.  All requests' blocks go through
-// every stage together.
-int compress_impl(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
-                  const uint32_t* req_blocks, uint32_t n_req, int level, uint8_t* d_out, const uint64_t* out_off,
-                  uint64_t* h_out_bytes, uint32_t* h_n_blocks, hipStream_t st) {
-  HIPX(hipSetDevice(ctx->device));
-  const uint64_t in0 = n_blocks ? h_offsets[0] : 0;
-  const uint64_t total = n_blocks ? h_offsets[n_blocks] - in0 : 0;
-  if (total >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "input too large for one call (2^31 bytes)");
-  const uint8_t* in = d_in ? d_in + in0 : nullptr;
-  // input blocks (relative to in), empty ones dropped; breq = owning request
-  std::vector<uint64_t> boff{0};
-  std::vector<uint32_t> breq;
-  for (uint32_t r = 0; r < n_req; r++)
-    for (uint32_t k = req_blocks[r]; k < req_blocks[r + 1]; k++)
-      if (h_offsets[k + 1] > h_offsets[k]) {
-        boff.push_back(h_offsets[k + 1] - in0);
-        breq.push_back(r);
-      }
-  void* pin;
-  int rc = ensure_pin(ctx, 64 * 1024 + 16 * (boff.size() + total / 100000 + 16) + 16 * (size_t)n_req, &pin);
-  if (rc) return rc;
-  Stager stg;
-  if ((rc = ensure_stage(ctx, 65536 + 128 * boff.size() + total / 128 + 16 * (size_t)n_req, st, &stg))) return rc;
-  uint32_t nb = (uint32_t)boff.size() - 1;
-  if (h_n_blocks) *h_n_blocks = 0;
-  if (nb == 0) {  // every stream is the 14-byte empty stream
-    uint8_t* p = (uint8_t*)pin;
-    const uint8_t empty[14] = {'B', 'Z', 'h', (uint8_t)('0' + level), 0x17, 0x72, 0x45, 0x38, 0x50, 0x90, 0, 0, 0, 0};
-    memcpy(p, empty, 14);
-    bool short_cap = false;
-    for (uint32_t r = 0; r < n_req; r++) {
-      h_out_bytes[r] = 14;
-      short_cap |= out_off[r + 1] - out_off[r] < 14;
-    }
-    if (short_cap) return fail(ctx, BZG_ECAPACITY, "an empty stream needs 14 bytes");
-    for (uint32_t r = 0; r < n_req; r++)
-      HIPX(hipMemcpyAsync(d_out + out_off[r], p, 14, hipMemcpyHostToDevice, st));
-    HIPX(hipStreamSynchronize(st));
-    return 0;
-  }
-  const uint32_t limit = 100000u * (uint32_t)level;
-  // ---- plan: RLE1 sizes, cutting blocks whose RLE1 output exceeds the limit
-  const size_t max_nb = nb + total / 50000 + 4;
-  const size_t max_tiles = total / RLE_TILE + 2 * max_nb + 4;
-  size_t need1 = sz<uint64_t>(max_nb + 1) + sz<uint32_t>(max_tiles) + sz<uint32_t>(max_nb + 1) +
-                 2 * (rle_tile_bytes() * max_tiles + 256) + sz<uint32_t>(max_tiles) * 4 + sz<uint32_t>(max_nb) * 4 +
-                 sz<uint64_t>(max_nb + 1);
-  void* ws1;
-  if ((rc = ensure_ws(ctx, 1, need1, &ws1))) return rc;
-  Carve c1{(char*)ws1};
-  uint64_t* d_boff = c1.take<uint64_t>(max_nb + 1);
-  uint32_t* d_tile_blk = c1.take<uint32_t>(max_tiles);
-  uint32_t* d_blk_tile0 = c1.take<uint32_t>(max_nb + 1);
-  void* d_rt[2] = {c1.take<char>(rle_tile_bytes() * max_tiles), c1.take<char>(rle_tile_bytes() * max_tiles)};
-  uint32_t* d_tile_rs = c1.take<uint32_t>(max_tiles);
-  uint32_t* d_tile_from = c1.take<uint32_t>(max_tiles);
-  uint32_t* d_tile_ids = c1.take<uint32_t>(max_tiles);
-  uint32_t* d_tile_out = c1.take<uint32_t>(max_tiles);
-  uint32_t* d_rle_n = c1.take<uint32_t>(max_nb);
-  uint32_t* d_crc = c1.take<uint32_t>(max_nb);
-  uint32_t* d_cut_ids = c1.take<uint32_t>(max_nb);
-  uint32_t* d_cuts = c1.take<uint32_t>(max_nb);
-  uint64_t* d_rbase = c1.take<uint64_t>(max_nb + 1);
-  std::vector<uint32_t> tile_blk, blk_tile0, rle_n;
-  // after a cut, each block's origin: (block of the previous plan, offset of
-  // its start in it); tiles that start at the same place and end at the same
-  // place as before are copied, the others (a cut block's last tile and its
-  // remainder) recomputed
-  std::vector<uint32_t> org_blk, prev_tile0, tile_from, tile_ids;
-  std::vector<uint64_t> org_delta, prev_boff;
-  int cur = 0;  // tile-record buffer of the current plan
-  uint32_t ntiles = 0;
-  for (int iter = 0;; iter++) {
-    nb = (uint32_t)boff.size() - 1;
-    if (nb > max_nb) return fail(ctx, BZG_EINVAL, "internal: block plan overflow");
-    tile_blk.clear();
-    blk_tile0.assign(nb + 1, 0);
-    for (uint32_t b = 0; b < nb; b++) {
-      blk_tile0[b] = (uint32_t)tile_blk.size();
-      uint64_t n = boff[b + 1] - boff[b];
-      for (uint64_t t = 0; t < (n + RLE_TILE - 1) / RLE_TILE; t++) tile_blk.push_back(b);
-    }
-    blk_tile0[nb] = (uint32_t)tile_blk.size();
-    ntiles = (uint32_t)tile_blk.size();
-    HIPX(stg.put_span({{d_boff, boff.data(), (nb + 1) * 8},
-                       {d_tile_blk, tile_blk.data(), ntiles * 4},
-                       {d_blk_tile0, blk_tile0.data(), (nb + 1) * 4}}));
-    if (iter == 0) {
-      ProfScope ps("rle1_tiles", st, (double)(boff[nb] - boff[0]));
-      HIPX(rle1_tiles(in, ntiles, nullptr, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab, ctx->crc_tab + CRC_POW_AT,
-                      d_rt[cur], st));
-    } else {
-      tile_from.assign(ntiles, ~0u);
-      tile_ids.clear();
-      double bytes = 0;
-      for (uint32_t b = 0; b < nb; b++) {
-        const uint32_t ob = org_blk[b];
-        const uint64_t n = boff[b + 1] - boff[b], on = prev_boff[ob + 1] - prev_boff[ob];
-        for (uint32_t t = blk_tile0[b]; t < blk_tile0[b + 1]; t++) {
-          const uint64_t lo = (uint64_t)(t - blk_tile0[b]) * RLE_TILE;
-          if (org_delta[b] == 0 && std::min<uint64_t>(lo + RLE_TILE, n) == std::min<uint64_t>(lo + RLE_TILE, on)) {
-            tile_from[t] = prev_tile0[ob] + (t - blk_tile0[b]);
-          } else {
-            tile_ids.push_back(t);
-            bytes += (double)(std::min<uint64_t>(lo + RLE_TILE, n) - lo);
-          }
-        }
-      }
-      const int nxt = cur ^ 1;
-      HIPX(stg.put(d_tile_from, tile_from.data(), ntiles * 4));
-      HIPX(rle1_tile_copy(ntiles, d_tile_from, d_rt[cur], d_rt[nxt], st));
-      if (!tile_ids.empty()) {
-        HIPX(stg.put(d_tile_ids, tile_ids.data(), tile_ids.size() * 4));
-        ProfScope ps("rle1_tiles", st, bytes);
-        HIPX(rle1_tiles(in, (uint32_t)tile_ids.size(), d_tile_ids, d_tile_blk, d_blk_tile0, d_boff, ctx->crc_tab,
-                        ctx->crc_tab + CRC_POW_AT, d_rt[nxt], st));
-      }
-      cur = nxt;
-    }
-    HIPX(rle1_blocks(nb, d_blk_tile0, d_boff, ctx->crc_tab + CRC_POW_AT, d_rt[cur], d_tile_rs, d_tile_out, d_rle_n, d_crc,
-                     st));
-    uint32_t* h_rle = (uint32_t*)pin;
-    HIPX(hipMemcpyAsync(h_rle, d_rle_n, nb * 4, hipMemcpyDeviceToHost, st));
-    HIPX(hipStreamSynchronize(st));
-    rle_n.assign(h_rle, h_rle + nb);
-    std::vector<uint32_t> over;
-    for (uint32_t b = 0; b < nb; b++)
-      if (rle_n[b] > limit) over.push_back(b);
-    if (over.empty()) break;
-    if (iter > 64) return fail(ctx, BZG_EINVAL, "internal: block cutting did not converge");
-    HIPX(stg.put(d_cut_ids, over.data(), over.size() * 4));
-    HIPX(rle1_cut(in, (uint32_t)over.size(), d_cut_ids, d_blk_tile0, d_boff, d_tile_rs, d_tile_out, limit, d_cuts,
+  HIPX(call_init(w.skip, nullptr, 0, nullptr, 0, st));
+  PlanArgs a{n_blocks, b.mtf_ch, b.atg, 0};
+  PlanOut o{nullptr, nullptr, w.selb, nullptr, nullptr, nullptr, w.asg_tile0, w.pack_tile0, w.cnt};
+  HIPX(plan_layout(nullptr, d_soff, a, o, st));
+  MapSet m{};
+  m.map[0] = MapDesc{w.asg_tile0, w.asg_blk, w.cnt + PC_ASSIGN_TILES, b.asg_tiles, n_blocks};
+  m.map[1] = MapDesc{w.pack_tile0, w.pack_blk, w.cnt + PC_PACK_TILES, b.pack_tiles, n_blocks};
+  m.nmaps = 2;
+  m.err = ctx->status;
+  HIPX(fill_maps(m, st));
+  HuffArgs ha{};
+  ha.nb = n_blocks;
+  ha.syms = d_syms;
+  ha.sym_base = d_soff;
+  ha.nsyms = d_nsyms;
+  ha.freq = w.freq;
+  ha.inuse = (const uint32_t*)d_inuse;
+  ha.sel_base = w.selb;
+  ha.sel = w.sel;
+  ha.selmtf = w.selmtf;
+  ha.gbits = w.gbits;
+  ha.tabs = w.tabs;
+  ha.err = ctx->status;
+  ha.tile_blk = w.asg_blk;
+  ha.blk_tile0 = w.asg_tile0;
+  ha.n_tiles = w.cnt + PC_ASSIGN_TILES;
+  ha.tiles_cap = b.asg_tiles;
+  ha.tile_groups = b.atg;
+  ha.ws = w.hws;
+  ha.count_freq = true;
+  ha.sym_off = d_soff;
+  ha.ns_eff = w.ns_eff;
+  HIPX(huff_run(ha, st));
+  HIPX(fill32((uint32_t*)w.gstate, 2 * (uint64_t)scan_lb_states(b.groups), 0u, st));
+  HIPX(scan_lb_u64(w.gbits, w.cnt + PC_GROUPS_LO, b.groups, 1, w.gstate, ctx->status,
+                   persist_grid(b.groups / 2048 + 1, ctx->persist_cap), st));
+  HIPX(pack_layout(n_blocks, 1, nullptr, nullptr, w.tabs, 1, d_oo, w.blkbit, nullptr, d_nbits, nullptr, nullptr,
+                   nullptr, w.skip, ctx->status, st));
+  HIPX(zero_range((uint32_t*)(d_out + h_out_offsets[0]), (h_out_offsets[n_blocks] - h_out_offsets[0]) / 4, w.skip,
                   st));
-    uint32_t* h_cut = (uint32_t*)pin;
-    HIPX(hipMemcpyAsync(h_cut, d_cuts, over.size() * 4, hipMemcpyDeviceToHost, st));
-    HIPX(hipStreamSynchronize(st));
-    std::vector<uint64_t> nboff{0};
-    std::vector<uint32_t> nbreq;
-    org_blk.clear();
-    org_delta.clear();
-    size_t oi = 0;
-    for (uint32_t b = 0; b < nb; b++) {
-      uint64_t cut = 0;
-      if (oi < over.size() && over[oi] == b) {
-        cut = h_cut[oi++];
-        if (cut == 0 || cut >= boff[b + 1] - boff[b]) return fail(ctx, BZG_EINVAL, "internal: bad block cut");
-        nboff.push_back(boff[b] + cut);
-        nbreq.push_back(breq[b]);
-        org_blk.push_back(b);
-        org_delta.push_back(0);
-      }
-      nboff.push_back(boff[b + 1]);
-      nbreq.push_back(breq[b]);
-      org_blk.push_back(b);
-      org_delta.push_back(cut);
-    }
-    prev_boff.swap(boff);
-    prev_tile0.swap(blk_tile0);
-    boff.swap(nboff);
-    breq.swap(nbreq);
-  }
-  // ---- streams: block range of every request (blocks are in request order)
-  std::vector<uint32_t> rb(n_req + 1, nb);
-  for (uint32_t b = nb; b-- > 0;) rb[breq[b]] = b;
-  for (uint32_t r = n_req; r-- > 0;) rb[r] = std::min(rb[r], rb[r + 1]);
-  // ---- RLE1 output layout
-  std::vector<uint32_t> roff(nb + 1, 0);
-  std::vector<uint64_t> rbase(nb + 1, 0);
-  for (uint32_t b = 0; b < nb; b++) {
-    roff[b + 1] = roff[b] + rle_n[b];
-    rbase[b + 1] = roff[b + 1];
-  }
-  const uint32_t N = roff[nb];
-  std::vector<uint64_t> sbase(nb), selb(nb + 1);
-  uint64_t ng = 0;
-  for (uint32_t b = 0; b < nb; b++) {
-    sbase[b] = (uint64_t)roff[b] + b;
-    selb[b] = ng;
-    ng += ((uint64_t)rle_n[b] + 1 + GROUP - 1) / GROUP;
-  }
-  selb[nb] = ng;
-  std::vector<uint32_t> ptile_blk, pblk_tile0, atile_blk, ablk_tile0;
-  group_tiles(selb, nb, PACK_GROUPS, ptile_blk, pblk_tile0);
-  const uint32_t atg = huff_assign_groups(ng);
-  group_tiles(selb, nb, atg, atile_blk, ablk_tile0);
-  const uint32_t nptiles = (uint32_t)ptile_blk.size(), natiles = (uint32_t)atile_blk.size();
-  size_t bwt_ws = bwt_workspace_bytes(N, nb);
-  size_t need0 = sz<uint8_t>(N + 64) * 2 + sz<uint32_t>(nb) + sz<uint16_t>((size_t)N + nb + 64) + sz<uint64_t>(nb) +
-                 sz<uint32_t>(nb) + sz<uint32_t>((size_t)nb * 8) + sz<uint32_t>((size_t)nb * MAXA) + sz<uint32_t>(4) +
-                 sz<uint64_t>(nb + 1) + sz<uint8_t>(ng + 1) * 2 + sz<uint64_t>(ng + 1) * 2 +
-                 sz<uint64_t>(scan_tmp_elems(ng + 1)) + block_tables_bytes() * nb + 256 + sz<uint64_t>(nb) +
-                 sz<uint32_t>(nptiles + 1) + sz<uint32_t>(nb + 1) + sz<uint64_t>(2 * (size_t)n_req + 2) +
-                 sz<uint32_t>(n_req + 1) + sz<uint64_t>(n_req) + sz<uint32_t>(nb + 1) +
-                 sz<uint32_t>(natiles + 1) + sz<uint32_t>(nb + 1) + huff_workspace_bytes(nb) +
-                 std::max(bwt_ws, mtf_workspace_bytes(roff)) + 16384;
-  void* ws0;
-  if ((rc = ensure_ws(ctx, 0, need0, &ws0))) return rc;
-  Carve c0{(char*)ws0};
-  uint8_t* d_text = c0.take<uint8_t>(N + 64);
-  uint8_t* d_L = c0.take<uint8_t>(N + 64);
-  uint32_t* d_primary = c0.take<uint32_t>(nb);
-  uint16_t* d_syms = c0.take<uint16_t>((size_t)N + nb + 64);
-  // arrays uploaded together are carved next to each other (one copy each group)
-  uint64_t* d_sbase = c0.take<uint64_t>(nb);
-  uint32_t* d_roff = c0.take<uint32_t>(nb + 1);
-  uint32_t* d_nsyms = c0.take<uint32_t>(nb);
-  uint32_t* d_inuse = c0.take<uint32_t>((size_t)nb * 8);
-  uint32_t* d_freq = c0.take<uint32_t>((size_t)nb * MAXA);
-  uint32_t* d_err = c0.take<uint32_t>(4);
-  uint64_t* d_selb = c0.take<uint64_t>(nb + 1);
-  uint32_t* d_atile_blk = c0.take<uint32_t>(natiles + 1);
-  uint32_t* d_ablk_tile0 = c0.take<uint32_t>(nb + 1);
-  uint8_t* d_sel = c0.take<uint8_t>(ng + 1);
-  uint8_t* d_selmtf = c0.take<uint8_t>(ng + 1);
-  uint64_t* d_gbits = c0.take<uint64_t>(ng + 1);
-  uint64_t* d_gofs = c0.take<uint64_t>(ng + 1);
-  uint64_t* d_stmp = c0.take<uint64_t>(scan_tmp_elems(ng + 1));
-  void* d_tabs = c0.take<char>(block_tables_bytes() * nb);
-  uint64_t* d_blkbit = c0.take<uint64_t>(nb);
-  uint32_t* d_ptile_blk = c0.take<uint32_t>(nptiles + 1);
-  uint32_t* d_pblk_tile0 = c0.take<uint32_t>(nb + 1);
-  uint64_t* d_info = c0.take<uint64_t>(2 * (size_t)n_req + 2);
-  uint32_t* d_rb = c0.take<uint32_t>(n_req + 1);
-  uint64_t* d_rout = c0.take<uint64_t>(n_req);
-  void* d_hws = c0.take<char>(huff_workspace_bytes(nb));
-  void* d_stage = c0.take<char>(0);
-  size_t stage_bytes = ctx->ws_cap[0] - c0.used;
-  HIPX(stg.put(d_rbase, rbase.data(), (nb + 1) * 8));
-  {
-    ProfScope ps("rle1_emit", st, (double)total + N);
-    HIPX(rle1_emit(in, ntiles, d_tile_blk, d_blk_tile0, d_boff, d_tile_rs, d_tile_out, d_rbase, d_text, st));
-  }
-  // ---- BWT
-  uint32_t *SA, *d_off;
-  int rounds = 0;
-  hipError_t e = bwt_sort(d_text, roff, d_stage, stage_bytes, (RoundCounters*)pin, stg, &SA, &d_off, &rounds, ctx->err);
-  if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "bwt_sort") : BZG_EHIP;
-  HIPX(bwt_output(d_text, d_off, nb, N, SA, d_L, d_primary, nullptr, st));
-  // ---- MTF + RUNA/RUNB (the sort's scratch is free again)
-  HIPX(stg.put_span({{d_sbase, sbase.data(), nb * 8}, {d_roff, roff.data(), (nb + 1) * 4}}));
-  e = mtf_run(d_L, d_roff, roff, d_stage, stage_bytes, d_syms, d_sbase, d_nsyms, d_inuse, d_freq, d_err, stg, ctx->err);
-  if (e != hipSuccess) return ctx->err.empty() ? hip_fail(ctx, e, "mtf") : BZG_EHIP;
-  // ---- Huffman tables, layout
-  HIPX(stg.put_span({{d_selb, selb.data(), (nb + 1) * 8},
-                     {d_atile_blk, atile_blk.data(), natiles * 4},
-                     {d_ablk_tile0, ablk_tile0.data(), (nb + 1) * 4}}));
-  HIPX(huff_run(nb, d_syms, d_sbase, d_nsyms, d_freq, false, d_inuse, d_selb, d_sel, d_selmtf, d_gbits, d_tabs, d_err,
-                natiles, d_atile_blk, d_ablk_tile0, atg, d_hws, st));
-  HIPX(scan_excl_u64(d_gbits, d_gofs, ng + 1, d_stmp, st));
-  HIPX(stg.put_span({{d_rb, rb.data(), (n_req + 1) * 4}, {d_rout, out_off, n_req * 8}}));
-  HIPX(pack_layout(nb, n_req, d_rb, d_rout, d_tabs, 0, nullptr, d_blkbit, d_crc, d_info, st));
-  uint64_t* h_info = (uint64_t*)pin;
-  HIPX(hipMemcpyAsync(h_info, d_info, 16 * (size_t)n_req, hipMemcpyDeviceToHost, st));
-  HIPX(hipMemcpyAsync(h_info + 2 * (size_t)n_req, d_err, 4, hipMemcpyDeviceToHost, st));
-  HIPX(hipStreamSynchronize(st));
-  const uint32_t ef = (uint32_t)h_info[2 * (size_t)n_req];
-  if (ef) return fail(ctx, BZG_EDATA, "internal: inconsistent symbol stream");
-  uint64_t max_words = 0, out_total = 0;
-  int short_r = -1;
-  for (uint32_t r = 0; r < n_req; r++) {
-    const uint64_t bits = h_info[2 * r], words = (bits + 31) / 32;
-    h_out_bytes[r] = (bits + 7) / 8;
-    out_total += h_out_bytes[r];
-    max_words = std::max(max_words, words);
-    if (words * 4 > out_off[r + 1] - out_off[r] && short_r < 0) short_r = (int)r;
-  }
-  if (h_n_blocks) *h_n_blocks = nb;
-  if (short_r >= 0)
-    return fail(ctx, BZG_ECAPACITY,
-                "stream " + std::to_string(short_r) + " needs " +
-                    std::to_string((h_info[2 * short_r] + 31) / 32 * 4) + " bytes (4-byte rounded)");
-  // ---- pack
-  HIPX(stg.put_span({{d_ptile_blk, ptile_blk.data(), nptiles * 4}, {d_pblk_tile0, pblk_tile0.data(), (nb + 1) * 4}}));
-  {
-    ProfScope ps("pack", st, 2.0 * N + (double)out_total);  // symbols in, streams out
-    HIPX(zero_streams(n_req, max_words, d_rout, d_info, (uint32_t*)d_out, st));
-    HIPX(pack_run(nb, d_tabs, 0, d_blkbit, d_crc, d_primary, d_inuse, d_selb, d_sel, d_selmtf, d_gofs, nptiles,
-                  d_ptile_blk, d_pblk_tile0, d_syms, d_sbase, d_nsyms, level, n_req, d_rout, d_info,
-                  (uint32_t*)d_out, st));
-  }
-  HIPX(hipStreamSynchronize(st));
-  return 0;
+  HIPX(pack_run(n_blocks, w.tabs, 1, w.blkbit, nullptr, nullptr, (const uint32_t*)d_inuse, w.selb, w.sel, w.selmtf,
+                w.gbits, w.cnt + PC_PACK_TILES, b.pack_tiles, w.pack_blk, w.pack_tile0, d_syms, d_soff, w.ns_eff, 9, 0,
+                nullptr, nullptr, (uint32_t*)d_out, w.skip, st));
+  if (d_tables) HIPX(tables_export(n_blocks, w.tabs, d_tables, st));
+  return end_ws(ctx, d_ws, st);
 }
 
-}  // namespace
-
-extern "C" {
-
-int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level,
-                    uint8_t* d_out, uint64_t out_cap, uint64_t* h_out_bytes, uint32_t* h_n_blocks, void* stream) {
+int compress_blocks(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                    uint32_t n_blocks, int level, uint8_t* d_out, uint64_t out_cap, uint64_t* d_out_bytes,
+                    uint32_t* d_n_blocks, void* d_ws, size_t ws_bytes, void* stream) {
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
-  if (!h_offsets || !d_out || !h_out_bytes) return fail(ctx, BZG_EINVAL, "null pointer");
-  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
-  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
-  if (n_blocks && h_offsets[n_blocks] > h_offsets[0] && !d_in) return fail(ctx, BZG_EINVAL, "null input");
+  if (!d_out || !d_out_bytes) return fail(ctx, BZG_EINVAL, "null pointer");
+  int rc = check_compress(ctx, d_in, h_offsets, n_blocks, level);
+  if (rc) return rc;
   if ((uintptr_t)d_out & 3) return fail(ctx, BZG_EINVAL, "d_out must be 4-byte aligned");
-  const uint32_t rq[2] = {0, n_blocks};
-  const uint64_t oo[2] = {0, out_cap & ~3ull};
-  return compress_impl(ctx, d_in, h_offsets, n_blocks, rq, 1, level, d_out, oo, h_out_bytes, h_n_blocks,
-                       (hipStream_t)stream);
+  return compress_common(ctx, d_in, d_offsets, h_offsets, n_blocks, nullptr, nullptr, 1, level, d_out, nullptr,
+                         nullptr, out_cap, d_out_bytes, d_n_blocks, d_ws, ws_bytes, (hipStream_t)stream);
 }
 
-int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks,
-                   const uint32_t* h_req_blocks, uint32_t n_req, int level, uint8_t* d_out,
-                   const uint64_t* h_out_offsets, uint64_t* h_out_bytes, void* stream) {
+int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                   uint32_t n_blocks, const uint32_t* d_req_blocks, const uint32_t* h_req_blocks, uint32_t n_req,
+                   int level, uint8_t* d_out, const uint64_t* d_out_offsets, const uint64_t* h_out_offsets,
+                   uint64_t* d_out_bytes, void* d_ws, size_t ws_bytes, void* stream) {
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
   ProfGuard pg(ctx);
-  if (!h_offsets || !h_req_blocks || !h_out_offsets || !h_out_bytes || (n_req && !d_out))
+  if (!h_req_blocks || !h_out_offsets || !d_out_bytes || (n_req && !d_out))
     return fail(ctx, BZG_EINVAL, "null pointer");
-  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
+  int rc = check_compress(ctx, d_in, h_offsets, n_blocks, level);
+  if (rc) return rc;
   if (n_req > 65535) return fail(ctx, BZG_EINVAL, "at most 65535 requests per call");
-  if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
-  if (n_blocks && h_offsets[n_blocks] > h_offsets[0] && !d_in) return fail(ctx, BZG_EINVAL, "null input");
   if (h_req_blocks[0] != 0 || h_req_blocks[n_req] != n_blocks)
     return fail(ctx, BZG_EINVAL, "request block ranges must start at 0 and end at n_blocks");
   for (uint32_t r = 0; r < n_req; r++) {
@@ -846,8 +1024,9 @@ int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets,
     if (h_out_offsets[r] & 3) return fail(ctx, BZG_EINVAL, "output offsets must be multiples of 4");
   if ((uintptr_t)d_out & 3) return fail(ctx, BZG_EINVAL, "d_out must be 4-byte aligned");
   if (n_req == 0) return 0;
-  return compress_impl(ctx, d_in, h_offsets, n_blocks, h_req_blocks, n_req, level, d_out, h_out_offsets,
-                       h_out_bytes, nullptr, (hipStream_t)stream);
+  return compress_common(ctx, d_in, d_offsets, h_offsets, n_blocks, d_req_blocks, h_req_blocks, n_req, level, d_out,
+                         d_out_offsets, h_out_offsets, 0, d_out_bytes, nullptr, d_ws, ws_bytes,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -85,25 +85,16 @@ __device__ __forceinline__ uint32_t last_run_start(const uint8_t* v, int cnt, ui
   return lastb;
 }
 
-// Pass A.  One workgroup per tile: tile ids[blockIdx.x], or every tile when
-// ids is null.
-__global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* __restrict__ ids,
-                                                   const uint32_t* tile_blk, const uint32_t* blk_tile0,
-                                                   const uint64_t* blk_off, const uint32_t* __restrict__ crc_tab,
-                                                   const uint32_t* crc_pow, RleTile* tiles) {
-  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  __shared__ uint32_t sx[NT];
-  __shared__ uint32_t tab[4][256];  // slicing-by-4 tables (k + 1 byte steps)
-#pragma unroll
-  for (int k = 0; k < 4; k++) tab[k][threadIdx.x] = crc_tab[k * 256 + threadIdx.x];
-  const uint32_t t = ids ? ids[blockIdx.x] : blockIdx.x;
+// One tile of pass A: run starts, output counts and CRC share of tile t.
+__device__ void rle1_tile(const uint8_t* __restrict__ s, uint32_t t, const uint32_t* tile_blk,
+                          const uint32_t* blk_tile0, const uint64_t* blk_off, const uint32_t* crc_pow,
+                          RleTile* tiles, uint32_t* sh, uint32_t* sx, uint32_t (*tab)[256]) {
   TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
   const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
   uint8_t v[RITEMS];
   int cnt;
   uint32_t prev;
   load_run(s, g, p0, v, cnt, prev);
-  __syncthreads();
   // CRC of this thread's bytes from a zero register, shifted to the tile end
   // (by a per-thread constant in full tiles)
   uint32_t reg = 0;
@@ -176,6 +167,23 @@ __global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s
   }
 }
 
+// Pass A.  Persistent workgroups over the tiles (count *ntiles).
+__global__ __launch_bounds__(NT) void k_rle1_tiles(const uint8_t* __restrict__ s, const uint32_t* __restrict__ ntiles,
+                                                   const uint32_t* tile_blk, const uint32_t* blk_tile0,
+                                                   const uint64_t* blk_off, const uint32_t* __restrict__ crc_tab,
+                                                   const uint32_t* crc_pow, RleTile* tiles) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  __shared__ uint32_t tab[4][256];  // slicing-by-4 tables (k + 1 byte steps)
+#pragma unroll
+  for (int k = 0; k < 4; k++) tab[k][threadIdx.x] = crc_tab[k * 256 + threadIdx.x];
+  __syncthreads();
+  for (TileLoop it = tile_loop(*ntiles); it.t < it.end; it.t += it.step) {
+    rle1_tile(s, it.t, tile_blk, blk_tile0, blk_off, crc_pow, tiles, sh, sx, tab);
+    __syncthreads();
+  }
+}
+
 // One workgroup per block: scan its tiles.  Writes each tile's carried run
 // start (+1, tile_rs) and output offset, the block's RLE1 length and CRC.
 // The tile records are left as pass A wrote them.
@@ -235,13 +243,20 @@ __global__ __launch_bounds__(NT) void k_rle1_blocks(const uint32_t* blk_tile0, c
   }
 }
 
-// Walks one tile with the carried run start: computes each byte's output
-// position.  mode 0 writes RLE1 output at out + out_base[b]; mode 1 counts the
-// bytes whose output ends at or before `limit` (the block is cut there).
+// Walks one window [g.lo, g.hi) of a block with the carried run start
+// `carry` (+1): computes each byte's output position.  MODE 0 writes the RLE1
+// output at out + obase + tile_off.  MODE 1 measures: *res gets the window
+// position after the last byte whose output ends at or before `limit`
+// (counting from tile_off), the window's output total and its last run
+// start (+1, 0 = none; the carry does not count).
+struct WalkRes {
+  uint32_t fit, tot, lastb;
+};
+
 template <int MODE>
 __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, uint32_t tile_off,
                           uint8_t* out, uint64_t obase, uint32_t limit, uint32_t* sh, uint32_t* sx,
-                          uint32_t* count_out) {
+                          WalkRes* res) {
   const uint32_t p0 = g.lo + threadIdx.x * RITEMS;
   // the byte after this thread's (read with the others; clamped when absent)
   const uint32_t pe = p0 + min((uint32_t)RITEMS, g.hi > p0 ? g.hi - p0 : 0u);
@@ -256,6 +271,7 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   uint32_t incl = block_incl_max<uint32_t, NT>(lastb, sh, 0u);
   sx[threadIdx.x] = incl;
   __syncthreads();
+  const uint32_t win_last = sx[NT - 1];
   uint32_t rs = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
   rs = rs > carry ? rs : carry;
   uint32_t rs0 = rs;
@@ -353,70 +369,162 @@ __device__ void rle1_walk(const uint8_t* s, const TileGeom& g, uint32_t carry, u
   }
   if (MODE == 1) {
     below = block_sum<uint32_t, NT>(below, sh);
-    if (threadIdx.x == 0) *count_out = g.lo + below;
-  }
-}
-
-__global__ __launch_bounds__(NT) void k_rle1_emit(const uint8_t* __restrict__ s, const uint32_t* tile_blk,
-                                                  const uint32_t* blk_tile0, const uint64_t* blk_off,
-                                                  const uint32_t* tile_rs, const uint32_t* tile_out,
-                                                  const uint64_t* out_base, uint8_t* __restrict__ out) {
-  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  __shared__ uint32_t sx[NT];
-  const uint32_t t = blockIdx.x;
-  TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
-  rle1_walk<0>(s, g, tile_rs[t], tile_out[t], out, out_base[g.b], 0, sh, sx, nullptr);
-}
-
-// Tile records carried over from the previous plan: dst[t] = src[from[t]]
-// where from[t] is not ~0.
-__global__ __launch_bounds__(NT) void k_tile_copy(uint32_t n, const uint32_t* __restrict__ from,
-                                                  const RleTile* __restrict__ src, RleTile* __restrict__ dst) {
-  const uint32_t t = blockIdx.x * NT + threadIdx.x;
-  if (t < n && from[t] != ~0u) dst[t] = src[from[t]];
-}
-
-// One workgroup per oversized block: the length of the longest input prefix
-// whose RLE1 output fits in `limit` bytes.
-__global__ __launch_bounds__(NT) void k_rle1_cut(const uint8_t* __restrict__ s, const uint32_t* blk_ids,
-                                                 const uint32_t* blk_tile0, const uint64_t* blk_off,
-                                                 const uint32_t* tile_rs, const uint32_t* tile_out,
-                                                 uint32_t limit, uint32_t* cut) {
-  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  __shared__ uint32_t sx[NT];
-  __shared__ uint32_t tsel;
-  const uint32_t b = blk_ids[blockIdx.x];
-  const uint32_t t0 = blk_tile0[b], t1 = blk_tile0[b + 1];
-  if (threadIdx.x == 0) {  // last tile whose output starts at or below the limit
-    uint32_t lo = t0, hi = t1 - 1;
-    while (lo < hi) {
-      uint32_t mid = (lo + hi + 1) / 2;
-      if (tile_out[mid] <= limit) lo = mid; else hi = mid - 1;
+    if (threadIdx.x == 0) {
+      res->fit = g.lo + below;
+      res->tot = tot;
+      res->lastb = win_last;
     }
-    tsel = lo;
+    __syncthreads();
   }
-  __syncthreads();
-  const uint32_t t = tsel;
-  TileGeom g;
-  g.b = b;
-  g.base = blk_off[b];
-  g.n = (uint32_t)(blk_off[b + 1] - g.base);
-  g.lo = (t - t0) * RLE_TILE;
-  g.hi = min(g.lo + RLE_TILE, g.n);
-  rle1_walk<1>(s, g, tile_rs[t], tile_out[t], nullptr, 0, limit, sh, sx, &cut[blockIdx.x]);
 }
 
-hipError_t rle1_tiles(const uint8_t* s, uint32_t nlaunch, const uint32_t* ids, const uint32_t* tile_blk,
+// Pass C.  Persistent workgroups over the tiles: every tile writes its RLE1
+// output at its block's offset roff[b] plus the tile's output offset.
+__global__ __launch_bounds__(NT) void k_rle1_emit(const uint8_t* __restrict__ s, const uint32_t* __restrict__ ntiles,
+                                                  const uint32_t* tile_blk, const uint32_t* blk_tile0,
+                                                  const uint64_t* blk_off, const uint32_t* tile_rs,
+                                                  const uint32_t* tile_out, const uint32_t* roff,
+                                                  uint8_t* __restrict__ out) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  for (TileLoop it = tile_loop(*ntiles); it.t < it.end; it.t += it.step) {
+    const uint32_t t = it.t;
+    TileGeom g = tile_geom(t, tile_blk, blk_tile0, blk_off);
+    rle1_walk<0>(s, g, tile_rs[t], tile_out[t], out, roff[g.b], 0, sh, sx, nullptr);
+    __syncthreads();
+  }
+}
+
+// Most input bytes whose fresh RLE1 output (a run starting at the first of
+// them) fits in L bytes: 255 per 5 output bytes, then up to 3 literal bytes.
+__device__ __forceinline__ uint32_t run_fit(uint32_t L) { return 255u * (L / 5u) + min(L % 5u, 3u); }
+
+// Block cutting.  One workgroup per input block k: the block's pieces are
+// the longest prefixes whose own RLE1 output fits in L bytes, one after
+// another (RLE1 restarts at every piece, so a run that crosses a cut starts
+// afresh).  Piece j of block k goes to slot slot_base[k] + j
+// (slot_in[slot] = its first input byte, relative); slots the block does not
+// need get empty ranges at the block end.  Inputs are the block's whole-
+// stream tile records (pass A and B over the input blocks): tile_out[t] is
+// the output position P of the tile's first byte and P is what the block's
+// RLE1 stream has written before a byte.
+//
+// A piece starting at s0 follows the whole stream once its first run ends
+// (after that, RLE1 output only depends on the bytes): with M a position
+// past that run, the piece's output up to e >= M is F(M) + P(e) - P(M), so
+// the cut is where the whole stream passes L - F(M) + P(M).  The first window
+// (up to the next tile boundary) is walked afresh; a run that outlasts it is
+// measured from the tile records (tiles with no run start lie inside it).
+__global__ __launch_bounds__(NT) void k_rle1_split(const uint8_t* __restrict__ s, const uint64_t* __restrict__ in_off,
+                                                   uint32_t n_in, const uint32_t* __restrict__ in_tile0,
+                                                   const RleTile* __restrict__ tiles,
+                                                   const uint32_t* __restrict__ tile_rs,
+                                                   const uint32_t* __restrict__ tile_out,
+                                                   const uint32_t* __restrict__ rle_n,
+                                                   const uint32_t* __restrict__ slot_base, uint32_t nslot, uint32_t L,
+                                                   uint64_t* __restrict__ slot_in, uint32_t* __restrict__ err) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sx[NT];
+  __shared__ WalkRes wr;
+  __shared__ uint32_t s_t2;
+  const uint32_t k = blockIdx.x;
+  const uint64_t base = in_off[k];
+  const uint32_t n = (uint32_t)(in_off[k + 1] - base);
+  const uint32_t sb = slot_base[k], np = slot_base[k + 1] - sb;
+  const uint32_t t0 = in_tile0[k], t1 = in_tile0[k + 1];
+  if (k + 1 == n_in && threadIdx.x == 0) slot_in[nslot] = in_off[n_in];
+  if (np == 0) return;  // an empty block has no slot
+  TileGeom g;
+  g.b = k;
+  g.base = base;
+  g.n = n;
+  uint32_t j = 0, s0 = 0;
+  const uint32_t total = rle_n[k];
+  for (;;) {
+    if (threadIdx.x == 0) slot_in[sb + j] = base + s0;
+    j++;
+    if (s0 == 0 && total <= L) break;  // the whole block fits
+    // the cut of the piece starting at s0 (e == n: the rest fits)
+    uint32_t e;
+    const uint32_t t = t0 + s0 / RLE_TILE;
+    const uint32_t W = min((s0 / RLE_TILE + 1) * RLE_TILE, n);
+    g.lo = s0;
+    g.hi = W;
+    rle1_walk<1>(s, g, s0 + 1, 0, nullptr, 0, L, sh, sx, &wr);
+    const WalkRes a = wr;
+    if (a.fit < W) {
+      e = a.fit;
+    } else if (W == n) {
+      e = n;
+    } else {
+      uint32_t F, P, tM;
+      bool done = false;
+      e = n;
+      if (a.lastb > s0 + 1) {  // the first run ends inside the window
+        F = a.tot;
+        P = tile_out[t + 1];
+        tM = t + 1;
+      } else {  // it runs on: find the next tile with a run start
+        if (threadIdx.x == 0) s_t2 = t1;
+        __syncthreads();
+        for (uint32_t c = t + 1; c < t1; c += NT) {
+          const uint32_t q = c + threadIdx.x;
+          const bool hit = q < t1 && tiles[min(q, t1 - 1)].last_bnd != 0;
+          const uint64_t m = __ballot(hit);
+          if (m && lane() == 0) atomicMin(&s_t2, c + (threadIdx.x & ~63u) + (uint32_t)(__ffsll((long long)m) - 1));
+          __syncthreads();
+          const bool found = s_t2 < t1;
+          __syncthreads();  // every thread has read s_t2 before any writes it again
+          if (found) break;
+        }
+        const uint32_t t2 = s_t2;
+        const uint32_t r1 = t2 < t1 ? (t2 - t0) * RLE_TILE + tiles[t2].lead : n;
+        F = rle_prefix(r1 - s0);
+        if (F > L) {
+          e = s0 + run_fit(L);
+          done = true;
+        } else if (r1 == n) {
+          e = n;
+          done = true;
+        } else {
+          const uint32_t lo2 = (t2 - t0) * RLE_TILE, off = lo2 - (tile_rs[t2] - 1);
+          P = tile_out[t2] + rle_prefix(off + tiles[t2].lead) - rle_prefix(off);
+          tM = t2;
+        }
+      }
+      if (!done) {
+        const uint32_t T = L - F + P;  // whole-stream positions up to T fit
+        if (total <= T) {
+          e = n;
+        } else {
+          uint32_t lo = tM, hi = t1 - 1;  // first tile whose end passes T
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            const uint32_t end = mid + 1 < t1 ? tile_out[mid + 1] : total;
+            if (end > T) hi = mid; else lo = mid + 1;
+          }
+          g.lo = (lo - t0) * RLE_TILE;
+          g.hi = min(g.lo + RLE_TILE, n);
+          rle1_walk<1>(s, g, tile_rs[lo], tile_out[lo], nullptr, 0, T, sh, sx, &wr);
+          e = wr.fit;
+        }
+      }
+    }
+    if (e >= n) break;
+    if (e <= s0 || j >= np) {  // no progress or more pieces than slots: cannot happen
+      if (threadIdx.x == 0) atomicOr(err, ERR_BOUND);
+      break;
+    }
+    s0 = e;
+  }
+  for (uint32_t q = j + threadIdx.x; q < np; q += NT) slot_in[sb + q] = base + n;
+}
+
+hipError_t rle1_tiles(const uint8_t* s, uint32_t grid, const uint32_t* ntiles, const uint32_t* tile_blk,
                       const uint32_t* blk_tile0, const uint64_t* blk_off, const uint32_t* crc_tab,
                       const uint32_t* crc_pow, void* tiles, hipStream_t st) {
-  if (nlaunch) hipLaunchKernelGGL(k_rle1_tiles, dim3(nlaunch), dim3(NT), 0, st, s, ids, tile_blk, blk_tile0, blk_off,
-                                  crc_tab, crc_pow, (RleTile*)tiles);
-  return hipGetLastError();
-}
-
-hipError_t rle1_tile_copy(uint32_t n, const uint32_t* from, const void* src, void* dst, hipStream_t st) {
-  if (n) hipLaunchKernelGGL(k_tile_copy, dim3((n + NT - 1) / NT), dim3(NT), 0, st, n, from, (const RleTile*)src,
-                            (RleTile*)dst);
+  hipLaunchKernelGGL(k_rle1_tiles, dim3(grid), dim3(NT), 0, st, s, ntiles, tile_blk, blk_tile0, blk_off, crc_tab,
+                     crc_pow, (RleTile*)tiles);
   return hipGetLastError();
 }
 
@@ -428,19 +536,20 @@ hipError_t rle1_blocks(uint32_t nb, const uint32_t* blk_tile0, const uint64_t* b
   return hipGetLastError();
 }
 
-hipError_t rle1_emit(const uint8_t* s, uint32_t ntiles, const uint32_t* tile_blk, const uint32_t* blk_tile0,
-                     const uint64_t* blk_off, const uint32_t* tile_rs, const uint32_t* tile_out,
-                     const uint64_t* out_base, uint8_t* out, hipStream_t st) {
-  if (ntiles) hipLaunchKernelGGL(k_rle1_emit, dim3(ntiles), dim3(NT), 0, st, s, tile_blk, blk_tile0, blk_off, tile_rs,
-                                 tile_out, out_base, out);
+hipError_t rle1_emit(const uint8_t* s, uint32_t grid, const uint32_t* ntiles, const uint32_t* tile_blk,
+                     const uint32_t* blk_tile0, const uint64_t* blk_off, const uint32_t* tile_rs,
+                     const uint32_t* tile_out, const uint32_t* roff, uint8_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rle1_emit, dim3(grid), dim3(NT), 0, st, s, ntiles, tile_blk, blk_tile0, blk_off, tile_rs,
+                     tile_out, roff, out);
   return hipGetLastError();
 }
 
-hipError_t rle1_cut(const uint8_t* s, uint32_t ncut, const uint32_t* blk_ids, const uint32_t* blk_tile0,
-                    const uint64_t* blk_off, const uint32_t* tile_rs, const uint32_t* tile_out, uint32_t limit,
-                    uint32_t* cut, hipStream_t st) {
-  if (ncut) hipLaunchKernelGGL(k_rle1_cut, dim3(ncut), dim3(NT), 0, st, s, blk_ids, blk_tile0, blk_off, tile_rs,
-                               tile_out, limit, cut);
+hipError_t rle1_split(const uint8_t* s, const uint64_t* in_off, uint32_t n_in, const uint32_t* in_tile0,
+                      const void* tiles, const uint32_t* tile_rs, const uint32_t* tile_out, const uint32_t* rle_n,
+                      const uint32_t* slot_base, uint32_t nslot, uint32_t L, uint64_t* slot_in, uint32_t* err,
+                      hipStream_t st) {
+  if (n_in) hipLaunchKernelGGL(k_rle1_split, dim3(n_in), dim3(NT), 0, st, s, in_off, n_in, in_tile0,
+                               (const RleTile*)tiles, tile_rs, tile_out, rle_n, slot_base, nslot, L, slot_in, err);
   return hipGetLastError();
 }
 

@@ -26,13 +26,6 @@
 
 namespace bzg {
 
-struct BlockTables {
-  uint32_t G, nsel, hdr_bits, alpha;
-  uint64_t data_bits;
-  uint8_t len[MAXG][MAXA];
-  uint32_t code[MAXG][MAXA];
-};
-
 constexpr uint32_t ASSIGN_GROUPS = 512;      // selector groups per assign tile (large calls)
 constexpr uint32_t ASSIGN_GROUPS_SMALL = 128;  // ... for calls that would not fill the GPU with 512
 constexpr uint32_t ASSIGN_SUB = NT;          // groups staged in LDS at a time
@@ -172,11 +165,21 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
   for (int j = 0; j < 8; j++) nu += __popc(inuse[b * 8 + j]);
   const int a = (int)nu + 2;
   const uint32_t ns = nsyms[b];
-  const int G = n_tables(ns, a);
+  const int G = ns ? n_tables(ns, a) : 0;  // an empty block gets no tables and no bits
   {
     const uint64_t gb0 = sel_base[b] + (ns + GROUP - 1) / GROUP, gb1 = sel_base[b + 1];
     for (uint64_t g = gb0 + threadIdx.x; g < gb1; g += NT) gbits[g] = 0;
     if (b + 1 == gridDim.x && threadIdx.x == 0) gbits[gb1] = 0;
+  }
+  if (G == 0) {
+    if (threadIdx.x == 0) {
+      T->G = 0;
+      T->nsel = 0;
+      T->alpha = (uint32_t)a;
+      T->data_bits = 0;
+      T->hdr_bits = 0;
+    }
+    return;
   }
   for (int v = threadIdx.x; v < a; v += NT) sf[v] = freq[(size_t)b * MAXA + v];
   __syncthreads();
@@ -249,21 +252,18 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
 
 // Tile of tg groups of one block.  mode 0: choose tables and count
 // symbols per table; mode 1: data bits of every group under the final tables.
-__global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __restrict__ tile_blk,
-                                                    const uint32_t* __restrict__ blk_tile0,
-                                                    const uint16_t* __restrict__ syms,
-                                                    const uint64_t* __restrict__ sym_base,
-                                                    const uint32_t* __restrict__ nsyms,
-                                                    const uint64_t* __restrict__ sel_base, uint8_t* __restrict__ sel,
-                                                    const uint64_t* __restrict__ cost, uint32_t* __restrict__ tf,
-                                                    uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs,
-                                                    uint32_t tg) {
+__device__ void huff_assign_tile(uint32_t j, int mode, const uint32_t* __restrict__ tile_blk,
+                                 const uint32_t* __restrict__ blk_tile0, const uint16_t* __restrict__ syms,
+                                 const uint64_t* __restrict__ sym_base, const uint32_t* __restrict__ nsyms,
+                                 const uint64_t* __restrict__ sel_base, uint8_t* __restrict__ sel,
+                                 const uint64_t* __restrict__ cost, uint32_t* __restrict__ tf,
+                                 uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs, uint32_t tg,
+                                 bool clamp_syms) {
   __shared__ uint16_t st[ASSIGN_SYMS];
   __shared__ uint64_t sc[MAXA];
   __shared__ uint32_t stf[MAXG][MAXA];
   __shared__ uint8_t slen[MAXG][MAXA];
   __shared__ uint64_t sh[NT / BZG_WAVE + 1];
-  const uint32_t j = blockIdx.x;
   const uint32_t b = tile_blk[j];
   BlockTables* T = &tabs[b];
   const uint32_t nsel = T->nsel, G = T->G, a = T->alpha;
@@ -296,6 +296,10 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
     __syncthreads();
     stage_to_lds<NT, 10>(st, S + s0, s1 - s0);
     __syncthreads();
+    if (clamp_syms) {  // caller-given symbols: out-of-range ones (flagged by k_freq) stay inside the tables
+      for (uint32_t i = threadIdx.x; i < s1 - s0; i += NT) st[i] = (uint16_t)min((uint32_t)st[i], (uint32_t)MAXA - 1u);
+      __syncthreads();
+    }
     const uint32_t g = gs + threadIdx.x;
     if (g < ge) {
       const uint32_t lo = g * GROUP - s0, hi = min(g * GROUP + GROUP, ns) - s0;
@@ -346,6 +350,24 @@ __global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __
   } else {
     uint64_t tot = block_sum<uint64_t, NT>(bits, sh);
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&T->data_bits, (unsigned long long)tot);
+  }
+}
+
+// Persistent workgroups over the *n_tiles assign tiles (at most cap).
+__global__ __launch_bounds__(NT) void k_huff_assign(int mode, const uint32_t* __restrict__ tile_blk,
+                                                    const uint32_t* __restrict__ blk_tile0,
+                                                    const uint16_t* __restrict__ syms,
+                                                    const uint64_t* __restrict__ sym_base,
+                                                    const uint32_t* __restrict__ nsyms,
+                                                    const uint64_t* __restrict__ sel_base, uint8_t* __restrict__ sel,
+                                                    const uint64_t* __restrict__ cost, uint32_t* __restrict__ tf,
+                                                    uint64_t* __restrict__ gbits, BlockTables* __restrict__ tabs,
+                                                    uint32_t tg, const uint32_t* __restrict__ n_tiles, uint32_t cap,
+                                                    int clamp_syms) {
+  for (TileLoop it = tile_loop(min(*n_tiles, cap)); it.t < it.end; it.t += it.step) {
+    huff_assign_tile(it.t, mode, tile_blk, blk_tile0, syms, sym_base, nsyms, sel_base, sel, cost, tf, gbits, tabs, tg,
+                     clamp_syms != 0);
+    __syncthreads();
   }
 }
 
@@ -421,6 +443,7 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
   const uint32_t tid = threadIdx.x;
   BlockTables* T = &tabs[b];
   const int G = (int)T->G, a = (int)T->alpha;
+  if (G == 0) return;  // empty block: nothing to code, hdr_bits stays 0
   const uint32_t nsel = T->nsel;
   const uint64_t sb = sel_base[b];
   __shared__ uint32_t lcnt[MAXG][MAXLEN + 2];
@@ -546,22 +569,38 @@ __global__ __launch_bounds__(NT) void k_huff_finish(const uint32_t* __restrict__
   }
 }
 
-// Per-block symbol histogram (for callers that pass symbols directly).
-__global__ __launch_bounds__(NT) void k_freq(const uint16_t* __restrict__ syms, const uint64_t* __restrict__ sym_base,
-                                             const uint32_t* __restrict__ nsyms, uint32_t* __restrict__ freq,
+// Per-block symbol histogram (for callers that pass symbols directly).  The
+// block's count is clamped to its capacity and stored in ns_out; a symbol
+// outside the block's alphabet (in-use bytes + 2), or a count above the
+// capacity, sets ERR_SYMBOL.
+__global__ __launch_bounds__(NT) void k_freq(const uint16_t* __restrict__ syms, const uint64_t* __restrict__ sym_off,
+                                             const uint32_t* __restrict__ nsyms, const uint32_t* __restrict__ inuse,
+                                             uint32_t* __restrict__ freq, uint32_t* __restrict__ ns_out,
                                              uint32_t* __restrict__ err) {
   __shared__ uint32_t h[MAXA];
+  __shared__ uint32_t bad;
   const uint32_t b = blockIdx.x;
   for (int i = threadIdx.x; i < MAXA; i += NT) h[i] = 0;
+  if (threadIdx.x == 0) bad = 0;
+  uint32_t nu = 0;
+  for (int j = 0; j < 8; j++) nu += __popc(inuse[b * 8 + j]);
+  const uint32_t alpha = nu + 2;
+  const uint64_t o = sym_off[b];
+  const uint64_t cap = sym_off[b + 1] - sym_off[b];
+  const uint32_t n_in = nsyms[b];
+  const uint32_t ns = (uint32_t)min((uint64_t)n_in, cap);
   __syncthreads();
-  const uint16_t* S = syms + sym_base[b];
-  const uint32_t ns = nsyms[b];
+  const uint16_t* S = syms + o;
   for (uint32_t i = threadIdx.x; i < ns; i += NT) {
-    uint32_t v = S[i];
-    if (v < MAXA) atomicAdd(&h[v], 1u);
-    else atomicOr(err, 2u);
+    const uint32_t v = S[i];
+    if (v < alpha) atomicAdd(&h[v], 1u);
+    else bad = 1;
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    ns_out[b] = ns;
+    if (bad || n_in > cap) atomicOr(err, ERR_SYMBOL);
+  }
   for (int i = threadIdx.x; i < MAXA; i += NT) freq[(size_t)b * MAXA + i] = h[i];
 }
 
@@ -572,39 +611,47 @@ size_t huff_workspace_bytes(uint32_t nb) {
   return ((size_t)nb * MAXA * 8 + 255) / 256 * 256 + ((size_t)nb * MAXG * MAXA * 4 + 255) / 256 * 256 + 512;
 }
 
-// sel_base[b] holds ceil(capacity/50) groups per block; the assign tiles are
-// laid out from those capacities on the host.
-hipError_t huff_run(uint32_t nb, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
-                    uint32_t* freq, bool count_freq, const uint32_t* inuse, const uint64_t* sel_base, uint8_t* sel,
-                    uint8_t* selmtf, uint64_t* gbits, void* tabs_v, uint32_t* err, uint32_t ntiles,
-                    const uint32_t* tile_blk, const uint32_t* blk_tile0, uint32_t tile_groups, void* ws,
-                    hipStream_t st) {
-  if (!nb) return hipSuccess;
-  BlockTables* tabs = (BlockTables*)tabs_v;
-  uint64_t* cost = (uint64_t*)ws;
-  uint32_t* tf = (uint32_t*)((char*)ws + ((size_t)nb * MAXA * 8 + 255) / 256 * 256);
-  if (count_freq) hipLaunchKernelGGL(k_freq, dim3(nb), dim3(NT), 0, st, syms, sym_base, nsyms, freq, err);
+// The Huffman stage of nb blocks (some possibly empty): counts (when
+// a.count_freq: symbols given by the caller, validated), four passes of
+// table assignment and build, the final data bits, codes and selectors.
+hipError_t huff_run(const HuffArgs& a, hipStream_t st) {
+  if (!a.nb) return hipSuccess;
+  BlockTables* tabs = (BlockTables*)a.tabs;
+  uint64_t* cost = (uint64_t*)a.ws;
+  uint32_t* tf = (uint32_t*)((char*)a.ws + ((size_t)a.nb * MAXA * 8 + 255) / 256 * 256);
+  const uint32_t* nsyms = a.nsyms;
+  if (a.count_freq) {
+    hipLaunchKernelGGL(k_freq, dim3(a.nb), dim3(NT), 0, st, a.syms, a.sym_off, a.nsyms, a.inuse, a.freq, a.ns_eff,
+                       a.err);
+    nsyms = a.ns_eff;
+  }
+  const uint32_t g = persist_grid(a.tiles_cap, 4096);
+  const int clamp = a.count_freq ? 1 : 0;
   // symbol counts are known on the device only: no algorithmic bytes recorded
   {
     ProfScope ps("huff_setup", st, 0.0);
-    hipLaunchKernelGGL(k_huff_setup, dim3(nb), dim3(NT), 0, st, nsyms, freq, inuse, tabs, cost, tf, sel_base, gbits);
+    hipLaunchKernelGGL(k_huff_setup, dim3(a.nb), dim3(NT), 0, st, nsyms, a.freq, a.inuse, tabs, cost, tf, a.sel_base,
+                       a.gbits);
   }
   for (int it = 0; it < 4; it++) {
-    if (ntiles) {
+    {
       ProfScope ps("huff_assign", st, 0.0);
-      hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 0, tile_blk, blk_tile0, syms, sym_base, nsyms,
-                         sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs, tile_groups);
+      hipLaunchKernelGGL(k_huff_assign, dim3(g), dim3(NT), 0, st, 0, a.tile_blk, a.blk_tile0, a.syms, a.sym_base,
+                         nsyms, a.sel_base, a.sel, (const uint64_t*)cost, tf, a.gbits, tabs, a.tile_groups, a.n_tiles,
+                         a.tiles_cap, clamp);
     }
     ProfScope ps("huff_build", st, 0.0);
-    hipLaunchKernelGGL(k_huff_build, dim3(nb, MAXG), dim3(BUILD_NT), 0, st, tabs, tf);
+    hipLaunchKernelGGL(k_huff_build, dim3(a.nb, MAXG), dim3(BUILD_NT), 0, st, tabs, tf);
   }
-  if (ntiles) {
+  {
     ProfScope ps("huff_assign", st, 0.0);
-    hipLaunchKernelGGL(k_huff_assign, dim3(ntiles), dim3(NT), 0, st, 1, tile_blk, blk_tile0, syms, sym_base, nsyms,
-                       sel_base, sel, (const uint64_t*)cost, tf, gbits, tabs, tile_groups);
+    hipLaunchKernelGGL(k_huff_assign, dim3(g), dim3(NT), 0, st, 1, a.tile_blk, a.blk_tile0, a.syms, a.sym_base, nsyms,
+                       a.sel_base, a.sel, (const uint64_t*)cost, tf, a.gbits, tabs, a.tile_groups, a.n_tiles,
+                       a.tiles_cap, clamp);
   }
   ProfScope ps("huff_finish", st, 0.0);
-  hipLaunchKernelGGL(k_huff_finish, dim3(nb), dim3(NT), 0, st, inuse, sel_base, (const uint8_t*)sel, selmtf, tabs);
+  hipLaunchKernelGGL(k_huff_finish, dim3(a.nb), dim3(NT), 0, st, a.inuse, a.sel_base, (const uint8_t*)a.sel, a.selmtf,
+                     tabs);
   return hipGetLastError();
 }
 

@@ -14,8 +14,10 @@ namespace bzg {
 
 // Optional per-kernel timing: HIP events recorded on the launch stream around
 // each instrumented launch, with the launch's algorithmic bytes (the bytes the
-// method must move, not what the hardware moved).  Collected after the call's
-// final synchronisation.
+// method must move, not what the hardware moved): a fixed part plus up to two
+// device-side counts times a per-unit figure.  The counts are copied to a
+// device buffer right after the launch (they may be reused later in the
+// call) and read when the call's work is collected.
 struct ProfRec {
   double ms = 0, bytes = 0;
   uint64_t launches = 0;
@@ -26,9 +28,13 @@ struct Profiler {
     const char* name;
     hipEvent_t a, b;
     double bytes;
+    double per[2];
+    int slot;  // first of two count slots, -1 = none
   };
   std::vector<Pending> pending;
   std::map<std::string, ProfRec> acc;
+  uint32_t* slots = nullptr;  // device count snapshots
+  int nslots = 0, used = 0;
   void collect();
 };
 extern thread_local Profiler* g_prof;
@@ -36,7 +42,9 @@ extern thread_local Profiler* g_prof;
 struct ProfScope {
   hipStream_t st;
   bool live = false;
-  ProfScope(const char* name, hipStream_t s, double bytes);
+  const uint32_t *c0 = nullptr, *c1 = nullptr;
+  ProfScope(const char* name, hipStream_t s, double bytes, const uint32_t* count0 = nullptr, double per0 = 0,
+            const uint32_t* count1 = nullptr, double per1 = 0);
   ~ProfScope();
 };
 
@@ -54,6 +62,46 @@ constexpr int MAXG = 6, MAXA = 258, MAXLEN = 17;
 constexpr uint32_t CRC_POW_AT = 1024;                  // CRC table layout: 4 x 256 byte steps,
 constexpr uint32_t CRC_TAB_WORDS = CRC_POW_AT + 64 + 256;  // then powers, then tile shifts
 constexpr uint32_t PACK_GROUPS = 64;   // selector groups per bit-packing tile
+
+// Per-block Huffman tables and sizes, written by the table kernels and read
+// by the packing kernels.  G = 0 marks an empty block (no symbols).
+struct BlockTables {
+  uint32_t G, nsel, hdr_bits, alpha;
+  uint64_t data_bits;
+  uint8_t len[MAXG][MAXA];
+  uint32_t code[MAXG][MAXA];
+};
+
+// Device-side error flags, OR-ed into the context's status word by the
+// kernels of a call and reported (and cleared) by bzg_check.
+constexpr uint32_t ERR_SYMBOL = 1u;    // a symbol outside its block's alphabet, or more symbols than slots
+constexpr uint32_t ERR_CAPACITY = 2u;  // an output range too small: nothing was packed
+constexpr uint32_t ERR_BOUND = 4u;     // a device-side count exceeded its host bound (work was dropped)
+
+// Persistent workgroup loops.  A kernel launched with G workgroups (a
+// multiple of 8) walks tiles [0, n): the workgroups of XCD x = wg mod 8 take
+// the x-th eighth of the range, each stepping by G / 8, so neighbouring tiles
+// (the same block's rows, ranks and text) stay in that XCD's L2.  n may be a
+// device-side count read by the kernel; G comes from the host's bound.
+struct TileLoop {
+  uint32_t t, end, step;
+};
+__device__ __forceinline__ TileLoop tile_loop(uint32_t n) {
+  const uint32_t x = blockIdx.x & 7u, i = blockIdx.x >> 3, q = n >> 3, r = n & 7u;
+  TileLoop L;
+  const uint32_t lo = x * q + (x < r ? x : r);
+  L.t = lo + i;
+  L.end = lo + q + (x < r ? 1u : 0u);
+  L.step = gridDim.x >> 3;
+  return L;
+}
+// Workgroups for a persistent launch over at most `bound` tiles: a multiple
+// of 8, at most `cap`.
+inline uint32_t persist_grid(uint64_t bound, uint32_t cap) {
+  uint64_t g = bound < cap ? bound : cap;
+  g = (g + 7) & ~uint64_t(7);
+  return (uint32_t)(g < 8 ? 8 : g);
+}
 
 // A run of equal-prefix rotations still to be ordered: SA rows
 // [start, start+len) of block blk.  `base` is the segment's packed element
@@ -76,6 +124,27 @@ struct RoundCounters {
   __host__ __device__ uint32_t big_tiles() const { return (uint32_t)tiles_big; }
   __host__ __device__ uint32_t big_active() const { return (uint32_t)(tiles_big >> 32); }
   __host__ __device__ uint32_t active() const { return small_total() + big_active(); }
+};
+
+// The sort's workspace: SA rows, ranks, keys, radix buffers, histograms
+// and scan state, segment lists, small-tile heads and three round-counter
+// records, carved from one range by bwt_carve.
+struct BwtSizes {
+  size_t seg_cap, head_cap, owner_cap, hist_cap, state_cap;
+};
+struct BwtWork {
+  uint32_t *SA, *rank, *key, *tmpK, *tmpV, *hist, *agg;
+  unsigned long long* state;
+  SegRec* segs[2];
+  uint32_t* head[2];
+  uint32_t* owner[2];
+  RoundCounters* cnt;
+  BwtSizes z;
+};
+// Host bounds a sort is planned from: blocks (slots), rows, longest block,
+// tiles of the first segments.
+struct BwtBounds {
+  uint32_t nslot, rows, max_len, init_tiles;
 };
 
 struct Bump {
@@ -154,9 +223,46 @@ struct Stager {
 
 // ---- launchers (defined in the kernel translation units) ----
 
+// Arguments of the Huffman stage (huff.hip).
+struct HuffArgs {
+  uint32_t nb;  // blocks (slots)
+  const uint16_t* syms;
+  const uint64_t* sym_base;  // first symbol of each block in syms
+  const uint32_t* nsyms;
+  uint32_t* freq;  // nb * MAXA counts (input, or written when count_freq)
+  const uint32_t* inuse;
+  const uint64_t* sel_base;  // nb + 1 selector group bases
+  uint8_t *sel, *selmtf;
+  uint64_t* gbits;  // per-group data bits
+  void* tabs;       // nb BlockTables
+  uint32_t* err;
+  const uint32_t *tile_blk, *blk_tile0, *n_tiles;  // assign tile map (device count)
+  uint32_t tiles_cap, tile_groups;
+  void* ws;  // huff_workspace_bytes(nb)
+  bool count_freq;           // symbols come from the caller: count and validate them
+  const uint64_t* sym_off;   // (count_freq) nb + 1 symbol capacity offsets
+  uint32_t* ns_eff;          // (count_freq) nb counts clamped to the capacities
+};
+
+size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
+bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w);
+int bwt_rounds(uint32_t max_len);
+hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, const uint32_t* init_tiles,
+                    const BwtBounds& bd, uint32_t* err, int* rounds, hipStream_t st);
+hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, const uint32_t* n_rows, uint32_t cap,
+                      const uint32_t* SA, uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st);
+
 // Device-wide exclusive scan; in == out allowed.  tmp needs scan_tmp_elems(n).
 size_t scan_tmp_elems(size_t n);
 hipError_t scan_excl_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp, hipStream_t s);
 hipError_t scan_excl_u64(const uint64_t* in, uint64_t* out, size_t n, uint64_t* tmp, hipStream_t s);
+// Single-pass exclusive scan in place over min(*count_ptr, cap) * mult
+// elements (a device count).  state: scan_lb_states(cap * mult) words, zero
+// at entry.
+uint32_t scan_lb_states(uint64_t n);
+hipError_t scan_lb_u32(uint32_t* data, const uint32_t* count_ptr, uint32_t cap, uint32_t mult,
+                       unsigned long long* state, uint32_t* err, uint32_t grid, hipStream_t s);
+hipError_t scan_lb_u64(uint64_t* data, const uint32_t* count_ptr, uint32_t cap, uint32_t mult,
+                       unsigned long long* state, uint32_t* err, uint32_t grid, hipStream_t s);
 
 }  // namespace bzg

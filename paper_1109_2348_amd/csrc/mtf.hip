@@ -123,10 +123,10 @@ __device__ __forceinline__ uint32_t load_rows(const uint8_t* __restrict__ L, uin
 // index depends on the whole block's in-use set and is added by k_mtf_scan --
 // and the chunk's in-use bitmap (8 words; k_mtf_scan ORs a block's chunks).
 template <uint32_t CH>
-__global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
-                                                  const uint32_t* blk_chunk0, const uint32_t* off,
-                                                  uint32_t* __restrict__ chunk_inuse, uint8_t* __restrict__ chunk_D,
-                                                  uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum) {
+__device__ void mtf_state_chunk(uint32_t c, const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                const uint32_t* blk_chunk0, const uint32_t* off, uint32_t* __restrict__ chunk_inuse,
+                                uint8_t* __restrict__ chunk_D, uint32_t* __restrict__ chunk_nD,
+                                ZSum* __restrict__ chunk_sum) {
   constexpr int MITEMS = CH / NT;  // rows per thread
   constexpr uint32_t PW = CH / 32;  // words of the last-occurrence position bitmap
   __shared__ uint32_t last[256];
@@ -134,7 +134,6 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   __shared__ uint32_t ssh[NT / BZG_WAVE + 1];
   __shared__ ZSum wsum[NT / BZG_WAVE];
   __shared__ uint32_t s_nd;
-  const uint32_t c = blockIdx.x;
   ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off, CH);
   last[threadIdx.x] = 0;
   for (uint32_t i = threadIdx.x; i < PW; i += NT) pbits[i] = 0;
@@ -223,6 +222,19 @@ __global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L,
   }
   __syncthreads();
   if (threadIdx.x == 0) chunk_nD[c] = s_nd;
+}
+
+// Persistent workgroups over the *n_chunks chunks (at most cap).
+template <uint32_t CH>
+__global__ __launch_bounds__(NT) void k_mtf_state(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                                  const uint32_t* blk_chunk0, const uint32_t* off,
+                                                  uint32_t* __restrict__ chunk_inuse, uint8_t* __restrict__ chunk_D,
+                                                  uint32_t* __restrict__ chunk_nD, ZSum* __restrict__ chunk_sum,
+                                                  const uint32_t* __restrict__ n_chunks, uint32_t cap) {
+  for (TileLoop it = tile_loop(min(*n_chunks, cap)); it.t < it.end; it.t += it.step) {
+    mtf_state_chunk<CH>(it.t, L, chunk_blk, blk_chunk0, off, chunk_inuse, chunk_D, chunk_nD, chunk_sum);
+    __syncthreads();
+  }
 }
 
 // Chunk summaries compose associatively: after chunk X the stack is D_X
@@ -322,7 +334,6 @@ __global__ __launch_bounds__(SW * BZG_WAVE) void k_mtf_scan(
     }
   }
   for (uint32_t i = threadIdx.x; i < (uint32_t)MAXA; i += SW * BZG_WAVE) freq[(size_t)b * MAXA + i] = 0;
-  if (b == 0 && threadIdx.x < 4) err[threadIdx.x] = 0;  // the call's error flags (k_mtf_emit sets them)
   __syncthreads();
   uint32_t bm[8], nu = 0;
   for (int j = 0; j < 8; j++) {
@@ -686,18 +697,14 @@ __device__ void mtf_emit_chunk(const uint8_t* __restrict__ L, const ChunkGeom& g
   flush();
 }
 
-__global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
-                                                       const uint32_t* blk_chunk0, const uint32_t* off,
-                                                       const uint32_t* __restrict__ inuse,
-                                                       const uint8_t* __restrict__ chunk_list,
-                                                       const uint32_t* __restrict__ chunk_carry,
-                                                       const uint32_t* __restrict__ chunk_out,
-                                                       const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
-                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err,
-                                                       uint32_t ch) {
+__device__ void mtf_emit_one(uint32_t c, const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                             const uint32_t* blk_chunk0, const uint32_t* off, const uint32_t* __restrict__ inuse,
+                             const uint8_t* __restrict__ chunk_list, const uint32_t* __restrict__ chunk_carry,
+                             const uint32_t* __restrict__ chunk_out, const uint64_t* __restrict__ sym_base,
+                             uint16_t* __restrict__ syms, uint32_t* __restrict__ freq, uint32_t* __restrict__ err,
+                             uint32_t ch) {
   __shared__ uint32_t fq[MAXA];
   __shared__ uint32_t posof[256], nstk[256], inb[256];
-  const uint32_t c = blockIdx.x;
   const uint32_t l = lane();
   ChunkGeom g = chunk_geom(c, chunk_blk, blk_chunk0, off, ch);
   uint32_t nu = 0;
@@ -717,38 +724,50 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
     if (fq[i]) atomicAdd(&freq[(size_t)g.b * MAXA + i], fq[i]);
 }
 
+// One wave per chunk, persistent over the *n_chunks chunks (at most cap).
+__global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict__ L, const uint32_t* chunk_blk,
+                                                       const uint32_t* blk_chunk0, const uint32_t* off,
+                                                       const uint32_t* __restrict__ inuse,
+                                                       const uint8_t* __restrict__ chunk_list,
+                                                       const uint32_t* __restrict__ chunk_carry,
+                                                       const uint32_t* __restrict__ chunk_out,
+                                                       const uint64_t* __restrict__ sym_base, uint16_t* __restrict__ syms,
+                                                       uint32_t* __restrict__ freq, uint32_t* __restrict__ err,
+                                                       uint32_t ch, const uint32_t* __restrict__ n_chunks, uint32_t cap) {
+  for (TileLoop it = tile_loop(min(*n_chunks, cap)); it.t < it.end; it.t += it.step) {
+    mtf_emit_one(it.t, L, chunk_blk, blk_chunk0, off, inuse, chunk_list, chunk_carry, chunk_out, sym_base, syms, freq,
+                 err, ch);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- host side
 
-static uint32_t count_chunks(const std::vector<uint32_t>& h_off, uint32_t ch) {
-  size_t nc = 0;
-  for (size_t b = 0; b + 1 < h_off.size(); b++) nc += (h_off[b + 1] - h_off[b] + ch - 1) / ch;
-  return (uint32_t)nc;
+// Chunk rows for a call of at most `rows` rows in `nb` blocks.
+uint32_t mtf_chunk_rows(uint64_t rows, uint32_t nb) {
+  return (rows / MTF_CHUNK + nb) < MTF_FEW_CHUNKS ? MTF_CHUNK_SMALL : MTF_CHUNK;
+}
+static uint64_t chunk_bound(uint64_t rows, uint32_t nb, uint32_t ch) { return rows / ch + nb + 1; }
+
+size_t mtf_workspace_bytes(uint64_t rows, uint32_t nb) {
+  const uint32_t ch = mtf_chunk_rows(rows, nb);
+  const size_t nc = chunk_bound(rows, nb, ch);
+  return 9 * 256 + (nc + 1) * (4 + 256 + 4 + sizeof(ZSum) + 256 + 4 + 4 + 32) + (nb + 1) * 4 + 4096;
 }
 
-static uint32_t chunk_size(const std::vector<uint32_t>& h_off) {
-  return count_chunks(h_off, MTF_CHUNK) < MTF_FEW_CHUNKS ? MTF_CHUNK_SMALL : MTF_CHUNK;
-}
-
-hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<uint32_t>& h_off, void* ws,
-                   size_t ws_bytes, uint16_t* syms, const uint64_t* d_sym_base, uint32_t* nsyms, uint32_t* inuse,
-                   uint32_t* freq, uint32_t* err, Stager& stg, std::string& emsg) {
-  hipStream_t st = stg.st;
-  const uint32_t nb = (uint32_t)h_off.size() - 1;
-  const uint32_t ch = chunk_size(h_off);
-  std::vector<uint32_t> chunk_blk, blk_chunk0(nb + 1);
-  for (uint32_t b = 0; b < nb; b++) {
-    blk_chunk0[b] = (uint32_t)chunk_blk.size();
-    uint32_t n = h_off[b + 1] - h_off[b];
-    uint32_t nc = (n + ch - 1) / ch;
-    for (uint32_t q = 0; q < nc; q++) chunk_blk.push_back(b);
-  }
-  blk_chunk0[nb] = (uint32_t)chunk_blk.size();
-  const uint32_t nc = (uint32_t)chunk_blk.size();
+// MTF and RUNA/RUNB of blocks [off[b], off[b+1]) of L (nb blocks, some
+// possibly empty; at most `rows` rows), chunked: chunk_blk/blk_chunk0 give
+// the chunk map (*n_chunks chunks, built on the device from the same
+// chunk size mtf_chunk_rows(rows, nb)).
+hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, uint32_t nb, uint64_t rows, const uint32_t* chunk_blk,
+                   const uint32_t* blk_chunk0, const uint32_t* n_chunks, void* ws, size_t ws_bytes, uint16_t* syms,
+                   const uint64_t* d_sym_base, uint32_t* nsyms, uint32_t* inuse, uint32_t* freq, uint32_t* err,
+                   std::string& emsg, hipStream_t st) {
+  const uint32_t ch = mtf_chunk_rows(rows, nb);
+  const uint32_t nc = (uint32_t)chunk_bound(rows, nb, ch);
   Bump bump;
   bump.base = (char*)ws;
   bump.cap = ws_bytes;
-  uint32_t* d_chunk_blk = bump.take<uint32_t>(nc + 1);
-  uint32_t* d_blk_chunk0 = bump.take<uint32_t>(nb + 1);
   uint8_t* d_D = bump.take<uint8_t>((size_t)nc * 256);
   uint32_t* d_nD = bump.take<uint32_t>(nc + 1);
   ZSum* d_sum = bump.take<ZSum>(nc + 1);
@@ -760,42 +779,32 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, const std::vector<ui
     emsg = "mtf workspace too small";
     return hipErrorInvalidValue;
   }
-  hipError_t e;
-  if (nc == 0) return hipSuccess;
-  if ((e = stg.put_span({{d_chunk_blk, chunk_blk.data(), nc * 4}, {d_blk_chunk0, blk_chunk0.data(), (nb + 1) * 4}})) !=
-      hipSuccess)
-    return e;
-  const double n = h_off[nb];
+  if (nb == 0) return hipSuccess;
+  const uint32_t gs = persist_grid(nc, 2048), ge = persist_grid(nc, 8192);
   {
-    ProfScope ps("mtf_state", st, n + 256.0 * nc);
+    ProfScope ps("mtf_state", st, 0, d_off + nb, 1.0, n_chunks, 256.0);
     if (ch == MTF_CHUNK)
-      hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK>, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off,
-                         d_cin, d_D, d_nD, d_sum);
+      hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK>, dim3(gs), dim3(NT), 0, st, L, chunk_blk, blk_chunk0, d_off, d_cin, d_D,
+                         d_nD, d_sum, n_chunks, nc);
     else
-      hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK_SMALL>, dim3(nc), dim3(NT), 0, st, L, d_chunk_blk, d_blk_chunk0,
-                         d_off, d_cin, d_D, d_nD, d_sum);
+      hipLaunchKernelGGL(k_mtf_state<MTF_CHUNK_SMALL>, dim3(gs), dim3(NT), 0, st, L, chunk_blk, blk_chunk0, d_off,
+                         d_cin, d_D, d_nD, d_sum, n_chunks, nc);
   }
   {
-    ProfScope ps("mtf_scan", st, 512.0 * nc);
+    ProfScope ps("mtf_scan", st, 0, n_chunks, 512.0);
     if (nc >= SCAN_LARGE_CHUNKS * nb)
-      hipLaunchKernelGGL(k_mtf_scan<SCAN_WAVES_LARGE>, dim3(nb), dim3(SCAN_WAVES_LARGE * BZG_WAVE), 0, st, d_blk_chunk0,
+      hipLaunchKernelGGL(k_mtf_scan<SCAN_WAVES_LARGE>, dim3(nb), dim3(SCAN_WAVES_LARGE * BZG_WAVE), 0, st, blk_chunk0,
                          d_cin, inuse, freq, err, L, d_off, d_D, d_nD, d_sum, d_list, d_carry, d_out, nsyms);
     else
-      hipLaunchKernelGGL(k_mtf_scan<SCAN_WAVES>, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, d_blk_chunk0, d_cin,
+      hipLaunchKernelGGL(k_mtf_scan<SCAN_WAVES>, dim3(nb), dim3(SCAN_WAVES * BZG_WAVE), 0, st, blk_chunk0, d_cin,
                          inuse, freq, err, L, d_off, d_D, d_nD, d_sum, d_list, d_carry, d_out, nsyms);
   }
   {
-    ProfScope ps("mtf_emit", st, 3.0 * n);  // read L, write at most one 2-byte symbol per row
-    hipLaunchKernelGGL(k_mtf_emit, dim3(nc), dim3(BZG_WAVE), 0, st, L, d_chunk_blk, d_blk_chunk0, d_off, inuse,
-                       d_list, d_carry, d_out, d_sym_base, syms, freq, err, ch);
+    ProfScope ps("mtf_emit", st, 0, d_off + nb, 3.0);  // read L, write at most one 2-byte symbol per row
+    hipLaunchKernelGGL(k_mtf_emit, dim3(ge), dim3(BZG_WAVE), 0, st, L, chunk_blk, blk_chunk0, d_off, inuse, d_list,
+                       d_carry, d_out, d_sym_base, syms, freq, err, ch, n_chunks, nc);
   }
   return hipGetLastError();
-}
-
-size_t mtf_workspace_bytes(const std::vector<uint32_t>& h_off) {
-  const uint32_t nb = (uint32_t)h_off.size() - 1;
-  const size_t nc = count_chunks(h_off, chunk_size(h_off));
-  return 9 * 256 + (nc + 1) * (4 + 256 + 4 + sizeof(ZSum) + 256 + 4 + 4 + 32) + (nb + 1) * 4 + 4096;
 }
 
 }  // namespace bzg

@@ -11,17 +11,12 @@
 // big-endian order and are byte-swapped on store.
 #include <climits>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace bzg {
-
-struct BlockTables {  // mirror of the layout in huff.hip
-  uint32_t G, nsel, hdr_bits, alpha;
-  uint64_t data_bits;
-  uint8_t len[MAXG][MAXA];
-  uint32_t code[MAXG][MAXA];
-};
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
@@ -55,51 +50,90 @@ __device__ __forceinline__ void put_bits64(uint32_t* words, uint64_t pos, uint64
 // Block layout: bit offset of every block and each stream's end.  One
 // workgroup per stream.  mode 0: one bzip2 stream per request r, made of
 // blocks [rb[r], rb[r+1]) and written from byte rout[r] of the output; blocks
-// follow the 32-bit stream header and carry the 105-bit block header.
-// info[2r] = the stream's length in bits (with the end-of-stream marker and
-// combined CRC), info[2r+1] = the combined CRC.  mode 1: bodies only, block b
-// at body_byte[b] * 8 (rb, rout unused, one workgroup).
+// follow the 32-bit stream header and carry the 105-bit block header; empty
+// blocks (no tables) take no bits and do not count.  info[2r] = the stream's
+// length in bits (with the end-of-stream marker and combined CRC),
+// info[2r+1] = the combined CRC; out_bytes[r] = its length in bytes; a stream
+// that does not fit its range [rout[r], rout[r+1]) (rounded up to 4 bytes)
+// sets ERR_CAPACITY and the skip flag (*skip) that the packing kernels test.
+// n_blocks (optional) gets the blocks of stream 0.  mode 1: bodies only,
+// block b at body_byte[b] * 8 (rb, rout unused, one workgroup): nbits[b]
+// = its bits, checked against body_byte[b + 1].
 __global__ __launch_bounds__(NT) void k_layout(uint32_t nb, const BlockTables* __restrict__ tabs, int mode,
                                                const uint32_t* __restrict__ rb, const uint64_t* __restrict__ rout,
                                                const uint64_t* __restrict__ body_byte, uint64_t* __restrict__ blk_bit,
-                                               const uint32_t* __restrict__ crc, uint64_t* __restrict__ info) {
+                                               const uint32_t* __restrict__ crc, uint64_t* __restrict__ info,
+                                               uint64_t* __restrict__ out_bytes, uint32_t* __restrict__ n_blocks,
+                                               const uint32_t* __restrict__ slot_base, uint32_t* __restrict__ skip,
+                                               uint32_t* __restrict__ err) {
   __shared__ uint64_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t sh32[NT / BZG_WAVE + 1];
   __shared__ uint32_t shx[NT / BZG_WAVE];
   const uint32_t r = blockIdx.x;
-  const uint32_t b0 = mode == 0 ? rb[r] : 0u, b1 = mode == 0 ? rb[r + 1] : nb;
+  // rb counts input blocks; slot_base turns them into slots (blocks after cutting)
+  const uint32_t b0 = mode == 0 ? slot_base[rb[r]] : 0u, b1 = mode == 0 ? slot_base[rb[r + 1]] : nb;
   const uint64_t base = mode == 0 ? rout[r] * 8 : 0;
+  // blocks of the stream that are not empty, counted first: the combined
+  // CRC rotates each block's CRC once per non-empty block after it
+  uint32_t cnt = 0;
+  for (uint32_t c = b0 + threadIdx.x; c < b1; c += NT) cnt += tabs[c].G ? 1u : 0u;
+  const uint32_t nne = block_sum<uint32_t, NT>(cnt, sh32);
   uint64_t carry = 32;
-  uint32_t comb = 0;
+  uint32_t comb = 0, seen = 0, over = 0;
   for (uint32_t c = b0; c < b1; c += NT) {
     uint32_t b = c + threadIdx.x;
     uint64_t sz = 0;
-    if (b < b1) sz = (mode == 0 ? 105u : 0u) + tabs[b].hdr_bits + tabs[b].data_bits;
+    uint32_t ne = 0;
+    if (b < b1 && tabs[b].G) {
+      sz = (mode == 0 ? 105u : 0u) + tabs[b].hdr_bits + tabs[b].data_bits;
+      ne = 1;
+    }
     uint64_t tot;
     uint64_t ex = block_excl_sum<uint64_t, NT>(sz, sh, &tot);
+    uint32_t net;
+    const uint32_t nex = block_excl_sum<uint32_t, NT>(ne, sh32, &net);
     if (b < b1) {
       blk_bit[b] = mode == 0 ? base + carry + ex : body_byte[b] * 8;
-      // combined CRC: each block CRC rotated left once per later block
-      if (mode == 0) {
-        uint32_t k = (b1 - 1 - b) & 31u, v = crc[b];
+      if (mode == 0 && ne) {
+        const uint32_t k = (nne - 1 - (seen + nex)) & 31u, v = crc[b];
         comb ^= k ? (v << k) | (v >> (32 - k)) : v;
+      }
+      if (mode == 1) {
+        const uint64_t bits = (uint64_t)tabs[b].hdr_bits + tabs[b].data_bits;
+        info[b] = bits;
+        if (bits > (body_byte[b + 1] - body_byte[b]) * 8) over = 1;
       }
     }
     carry += tot;
+    seen += net;
   }
   comb = wave_xor(comb);
   if (lane() == 0) shx[threadIdx.x / BZG_WAVE] = comb;
+  over = block_sum<uint32_t, NT>(over, sh32);
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < NT / BZG_WAVE; w++) comb ^= shx[w];
-    info[2 * r] = carry + 80;  // stream bits incl. end-of-stream marker and CRC
-    info[2 * r + 1] = comb;
+    if (mode == 0) {
+      const uint64_t bits = carry + 80;  // stream bits incl. end-of-stream marker and CRC
+      info[2 * r] = bits;
+      info[2 * r + 1] = comb;
+      out_bytes[r] = (bits + 7) / 8;
+      if (n_blocks && r == 0) *n_blocks = nne;
+      over = (bits + 31) / 32 * 4 > rout[r + 1] - rout[r];
+    }
+    if (over) {
+      atomicOr(skip, 1u);
+      atomicOr(err, ERR_CAPACITY);
+    }
   }
 }
 
 // Zero the words each stream will occupy (bits are OR-ed in afterwards).
 // Grid (x, streams); a plain fill kernel, so the call stays capturable.
 __global__ __launch_bounds__(NT) void k_zero_streams(const uint64_t* __restrict__ rout,
-                                                     const uint64_t* __restrict__ info, uint32_t* __restrict__ words) {
+                                                     const uint64_t* __restrict__ info, uint32_t* __restrict__ words,
+                                                     const uint32_t* __restrict__ skip) {
+  if (*skip) return;
   const uint32_t r = blockIdx.y;
   const uint64_t w0 = rout[r] / 4, nw = (info[2 * r] + 31) / 32;
   for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * NT) words[w0 + i] = 0;
@@ -113,11 +147,13 @@ __global__ __launch_bounds__(NT) void k_pack_header(const BlockTables* __restric
                                                     const uint32_t* __restrict__ primary,
                                                     const uint32_t* __restrict__ inuse,
                                                     const uint64_t* __restrict__ sel_base,
-                                                    const uint8_t* __restrict__ selmtf, uint32_t* __restrict__ words) {
+                                                    const uint8_t* __restrict__ selmtf, uint32_t* __restrict__ words,
+                                                    const uint32_t* __restrict__ skip) {
   __shared__ uint64_t sh[NT / BZG_WAVE + 1];
   const uint32_t b = blockIdx.x;
   const BlockTables* T = &tabs[b];
   const uint32_t G = T->G, nsel = T->nsel, a = T->alpha;
+  if (*skip || G == 0) return;  // output too small, or an empty block
   uint64_t pos = blk_bit[b];
   if (mode == 0) {
     if (threadIdx.x == 0) {
@@ -234,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_pack_header(const BlockTables* __restric
 }
 
 // Data codes: tile = PACK_GROUPS selector groups of one block.
-__global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict__ tabs, int mode,
+__device__ void pack_data_tile(uint32_t j, const BlockTables* __restrict__ tabs, int mode,
                                                   const uint32_t* __restrict__ tile_blk,
                                                   const uint32_t* __restrict__ blk_tile0,
                                                   const uint64_t* __restrict__ blk_bit,
@@ -251,7 +287,6 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
   __shared__ uint8_t slen[MAXG][MAXA];
   __shared__ uint32_t scode[MAXG][MAXA];
   __shared__ uint64_t sh[NT / BZG_WAVE + 1];
-  const uint32_t j = blockIdx.x;
   const uint32_t b = tile_blk[j];
   const BlockTables* T = &tabs[b];
   const uint32_t nsel = T->nsel, G = T->G;
@@ -292,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
   for (uint32_t q = 0; q < PER; q++) {
     const uint32_t l = min(l0 + q, cnt - 1u);
     tq[q] = ssel[l / GROUP];
-    sq[q] = ssym[l];
+    sq[q] = min((uint32_t)ssym[l], (uint32_t)MAXA - 1u);  // (caller-given symbols are flagged, not trusted)
   }
 #pragma unroll
   for (uint32_t q = 0; q < PER; q++) {
@@ -333,11 +368,31 @@ __global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict_
   }
 }
 
+// Persistent workgroups over the *n_tiles packing tiles (at most cap).
+__global__ __launch_bounds__(NT) void k_pack_data(const BlockTables* __restrict__ tabs, int mode,
+                                                  const uint32_t* __restrict__ tile_blk,
+                                                  const uint32_t* __restrict__ blk_tile0,
+                                                  const uint64_t* __restrict__ blk_bit,
+                                                  const uint16_t* __restrict__ syms,
+                                                  const uint64_t* __restrict__ sym_base,
+                                                  const uint32_t* __restrict__ nsyms,
+                                                  const uint64_t* __restrict__ sel_base,
+                                                  const uint8_t* __restrict__ sel,
+                                                  const uint64_t* __restrict__ gofs, uint32_t* __restrict__ words,
+                                                  const uint32_t* __restrict__ n_tiles, uint32_t cap,
+                                                  const uint32_t* __restrict__ skip) {
+  if (*skip) return;
+  for (TileLoop it = tile_loop(min(*n_tiles, cap)); it.t < it.end; it.t += it.step) {
+    pack_data_tile(it.t, tabs, mode, tile_blk, blk_tile0, blk_bit, syms, sym_base, nsyms, sel_base, sel, gofs, words);
+    __syncthreads();
+  }
+}
+
 // Stream header "BZh<level>", end-of-stream marker and combined CRC of
 // stream r (one workgroup per stream).
 __global__ void k_stream_ends(int level, const uint64_t* __restrict__ rout, const uint64_t* __restrict__ info,
-                              uint32_t* __restrict__ words) {
-  if (threadIdx.x != 0) return;
+                              uint32_t* __restrict__ words, const uint32_t* __restrict__ skip) {
+  if (threadIdx.x != 0 || *skip) return;
   const uint32_t r = blockIdx.x;
   const uint64_t start = rout[r] * 8, end = start + info[2 * r];
   uint32_t hdr = ((uint32_t)'B' << 24) | ((uint32_t)'Z' << 16) | ((uint32_t)'h' << 8) | (uint32_t)('0' + level);
@@ -363,15 +418,12 @@ __global__ __launch_bounds__(NT) void k_tables_export(const BlockTables* __restr
   }
 }
 
-// Body bits per block, and a capacity flag (bit 2 of err).
-__global__ __launch_bounds__(NT) void k_body_sizes(uint32_t nb, const BlockTables* __restrict__ tabs,
-                                                   const uint64_t* __restrict__ obyte, uint64_t* __restrict__ nbits,
-                                                   uint32_t* __restrict__ err) {
-  uint32_t b = blockIdx.x * NT + threadIdx.x;
-  if (b >= nb) return;
-  uint64_t bits = (uint64_t)tabs[b].hdr_bits + tabs[b].data_bits;
-  nbits[b] = bits;
-  if (bits > (obyte[b + 1] - obyte[b]) * 8) atomicOr(err, 4u);
+// Zero the bytes [lo, hi) (4-byte aligned) unless *skip: body ranges are
+// OR-ed into.
+__global__ __launch_bounds__(NT) void k_zero_range(uint32_t* __restrict__ words, uint64_t nw,
+                                                   const uint32_t* __restrict__ skip) {
+  if (*skip) return;
+  for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * NT) words[i] = 0;
 }
 
 hipError_t tables_export(uint32_t nb, const void* tabs, uint8_t* out, hipStream_t st) {
@@ -379,43 +431,44 @@ hipError_t tables_export(uint32_t nb, const void* tabs, uint8_t* out, hipStream_
   return hipGetLastError();
 }
 
-hipError_t body_sizes(uint32_t nb, const void* tabs, const uint64_t* obyte, uint64_t* nbits, uint32_t* err,
-                      hipStream_t st) {
-  if (nb) hipLaunchKernelGGL(k_body_sizes, dim3((nb + NT - 1) / NT), dim3(NT), 0, st, nb, (const BlockTables*)tabs,
-                             obyte, nbits, err);
-  return hipGetLastError();
-}
-
 hipError_t pack_layout(uint32_t nb, uint32_t n_req, const uint32_t* rb, const uint64_t* rout, const void* tabs,
                        int mode, const uint64_t* body_byte, uint64_t* blk_bit, const uint32_t* crc, uint64_t* info,
+                       uint64_t* out_bytes, uint32_t* n_blocks, const uint32_t* slot_base, uint32_t* skip, uint32_t* err,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_layout, dim3(mode == 0 ? n_req : 1u), dim3(NT), 0, st, nb, (const BlockTables*)tabs, mode, rb,
-                     rout, body_byte, blk_bit, crc, info);
+                     rout, body_byte, blk_bit, crc, info, out_bytes, n_blocks, slot_base, skip, err);
   return hipGetLastError();
 }
 
 hipError_t zero_streams(uint32_t n_req, uint64_t max_words, const uint64_t* rout, const uint64_t* info,
-                        uint32_t* words, hipStream_t st) {
+                        uint32_t* words, const uint32_t* skip, hipStream_t st) {
   uint64_t gx = (max_words + NT * 8 - 1) / (NT * 8);
   gx = gx < 1 ? 1 : (gx > 1024 ? 1024 : gx);
-  if (n_req) hipLaunchKernelGGL(k_zero_streams, dim3((uint32_t)gx, n_req), dim3(NT), 0, st, rout, info, words);
+  if (n_req) hipLaunchKernelGGL(k_zero_streams, dim3((uint32_t)gx, n_req), dim3(NT), 0, st, rout, info, words, skip);
+  return hipGetLastError();
+}
+
+hipError_t zero_range(uint32_t* words, uint64_t nw, const uint32_t* skip, hipStream_t st) {
+  const uint64_t g = std::min<uint64_t>((nw + NT * 4 - 1) / (NT * 4) + 1, 2048);
+  if (nw) hipLaunchKernelGGL(k_zero_range, dim3((uint32_t)g), dim3(NT), 0, st, words, nw, skip);
   return hipGetLastError();
 }
 
 hipError_t pack_run(uint32_t nb, const void* tabs, int mode, const uint64_t* blk_bit, const uint32_t* crc,
                     const uint32_t* primary, const uint32_t* inuse, const uint64_t* sel_base, const uint8_t* sel,
-                    const uint8_t* selmtf, const uint64_t* gofs, uint32_t ntiles, const uint32_t* tile_blk,
-                    const uint32_t* blk_tile0, const uint16_t* syms, const uint64_t* sym_base, const uint32_t* nsyms,
-                    int level, uint32_t n_req, const uint64_t* rout, const uint64_t* info, uint32_t* words,
-                    hipStream_t st) {
+                    const uint8_t* selmtf, const uint64_t* gofs, const uint32_t* n_tiles, uint32_t tiles_cap,
+                    const uint32_t* tile_blk, const uint32_t* blk_tile0, const uint16_t* syms,
+                    const uint64_t* sym_base, const uint32_t* nsyms, int level, uint32_t n_req, const uint64_t* rout,
+                    const uint64_t* info, uint32_t* words, const uint32_t* skip, hipStream_t st) {
   if (nb) {
     hipLaunchKernelGGL(k_pack_header, dim3(nb), dim3(NT), 0, st, (const BlockTables*)tabs, mode, blk_bit, crc, primary,
-                       inuse, sel_base, selmtf, words);
-    if (ntiles)
-      hipLaunchKernelGGL(k_pack_data, dim3(ntiles), dim3(NT), 0, st, (const BlockTables*)tabs, mode, tile_blk,
-                         blk_tile0, blk_bit, syms, sym_base, nsyms, sel_base, sel, gofs, words);
+                       inuse, sel_base, selmtf, words, skip);
+    const uint32_t g = persist_grid(tiles_cap, 4096);
+    hipLaunchKernelGGL(k_pack_data, dim3(g), dim3(NT), 0, st, (const BlockTables*)tabs, mode, tile_blk, blk_tile0,
+                       blk_bit, syms, sym_base, nsyms, sel_base, sel, gofs, words, n_tiles, tiles_cap, skip);
   }
-  if (mode == 0 && n_req) hipLaunchKernelGGL(k_stream_ends, dim3(n_req), dim3(64), 0, st, level, rout, info, words);
+  if (mode == 0 && n_req)
+    hipLaunchKernelGGL(k_stream_ends, dim3(n_req), dim3(64), 0, st, level, rout, info, words, skip);
   return hipGetLastError();
 }
 

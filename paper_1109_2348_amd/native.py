@@ -15,7 +15,9 @@ import torch
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbzgpu.so")
 
-BZG_OK, BZG_EINVAL, BZG_ECAPACITY, BZG_EHIP, BZG_ENOMEM, BZG_EDATA = 0, -1, -3, -4, -5, -6
+BZG_OK, BZG_EINVAL, BZG_EWORKSPACE, BZG_ECAPACITY, BZG_EHIP, BZG_ENOMEM, BZG_EDATA, BZG_EINTERNAL = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+CALL_BWT, CALL_MTF, CALL_HUFFMAN, CALL_COMPRESS = 1, 2, 3, 4
 MAX_BLOCK = 1 << 21
 TABLE_STRIDE = 1568
 
@@ -35,36 +37,41 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_1109_2348_amd.build.build()")
         L = C.CDLL(LIB_PATH)
-        vp, u64p, u32p = C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
-        L.bzg_create.restype = C.c_int
-        L.bzg_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+        vp, u64p, u32p, i = C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.c_int
+        sz, u32, u64 = C.c_size_t, C.c_uint32, C.c_uint64
+        L.bzg_create.restype = i
+        L.bzg_create.argtypes = [C.POINTER(C.c_void_p), i, C.c_char_p]
         L.bzg_destroy.restype = None
         L.bzg_destroy.argtypes = [vp]
         L.bzg_last_error.restype = C.c_char_p
         L.bzg_last_error.argtypes = [vp]
-        L.bzg_compress_bound.restype = C.c_uint64
-        L.bzg_compress_bound.argtypes = [C.c_uint64, C.c_uint32]
-        L.bwt_forward_batch.restype = C.c_int
-        L.bwt_forward_batch.argtypes = [vp, vp, u64p, C.c_uint32, vp, vp, vp, vp]
-        L.mtf_encode_batch.restype = C.c_int
-        L.mtf_encode_batch.argtypes = [vp, vp, u64p, C.c_uint32, vp, vp, vp, vp]
-        L.huffman_encode_batch.restype = C.c_int
-        L.huffman_encode_batch.argtypes = [vp, vp, vp, vp, u64p, C.c_uint32, vp, u64p, vp, vp, vp]
-        L.compress_blocks.restype = C.c_int
-        L.compress_blocks.argtypes = [vp, vp, u64p, C.c_uint32, C.c_int, vp, C.c_uint64, u64p, u32p, vp]
-        L.compress_batch.restype = C.c_int
-        L.compress_batch.argtypes = [vp, vp, u64p, C.c_uint32, u32p, C.c_uint32, C.c_int, vp, u64p, u64p, vp]
-        L.bzg_profile.restype = C.c_int
-        L.bzg_profile.argtypes = [vp, C.c_int]
-        L.bzg_profile_read.restype = C.c_int
+        L.bzg_check.restype = i
+        L.bzg_check.argtypes = [vp, vp]
+        L.bzg_workspace_size.restype = i
+        L.bzg_workspace_size.argtypes = [vp, i, u64p, u32, i, u32, C.POINTER(C.c_size_t)]
+        L.bzg_compress_bound.restype = u64
+        L.bzg_compress_bound.argtypes = [u64, u32]
+        L.bwt_forward_batch.restype = i
+        L.bwt_forward_batch.argtypes = [vp, vp, vp, u64p, u32, vp, vp, vp, vp, sz, vp]
+        L.mtf_encode_batch.restype = i
+        L.mtf_encode_batch.argtypes = [vp, vp, vp, u64p, u32, vp, vp, vp, vp, sz, vp]
+        L.huffman_encode_batch.restype = i
+        L.huffman_encode_batch.argtypes = [vp, vp, vp, vp, vp, u64p, u32, vp, vp, u64p, vp, vp, vp, sz, vp]
+        L.compress_blocks.restype = i
+        L.compress_blocks.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp, sz, vp]
+        L.compress_batch.restype = i
+        L.compress_batch.argtypes = [vp, vp, vp, u64p, u32, vp, u32p, u32, i, vp, vp, u64p, vp, vp, sz, vp]
+        L.bzg_profile.restype = i
+        L.bzg_profile.argtypes = [vp, i]
+        L.bzg_profile_read.restype = i
         L.bzg_profile_read.argtypes = [vp, C.c_char_p, C.c_size_t]
         _lib = L
     return _lib
 
 
-EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_compress_bound", "bwt_forward_batch",
-           "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch", "bzg_profile",
-           "bzg_profile_read")
+EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_check", "bzg_workspace_size", "bzg_compress_bound",
+           "bwt_forward_batch", "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch",
+           "bzg_profile", "bzg_profile_read")
 
 
 class Profile:
@@ -89,12 +96,12 @@ class Profile:
 class Context:
     """A bzgpu context on one HIP device (owns the library's scratch memory)."""
 
-    def __init__(self, device: Optional[int] = None):
+    def __init__(self, device: Optional[int] = None, tune_cache: Optional[str] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("bzgpu needs a HIP device")
         self.device = torch.cuda.current_device() if device is None else int(device)
         h = C.c_void_p()
-        rc = lib().bzg_create(C.byref(h), self.device)
+        rc = lib().bzg_create(C.byref(h), self.device, tune_cache.encode() if tune_cache else None)
         if rc != 0:
             raise BzgError(rc, "bzg_create failed")
         self.h = h
@@ -113,6 +120,18 @@ class Context:
     def check(self, rc: int):
         if rc != 0:
             raise BzgError(rc, lib().bzg_last_error(self.h).decode())
+
+    def sync_check(self, stream: C.c_void_p):
+        """Waits for the stream and raises the errors the kernels recorded."""
+        self.check(lib().bzg_check(self.h, stream))
+
+    def workspace_size(self, call: int, offsets, n_blocks: Optional[int] = None, level: int = 9,
+                       n_req: int = 1) -> int:
+        o = _offs(offsets)
+        nb = o.size - 1 if n_blocks is None else n_blocks
+        out = C.c_size_t(0)
+        self.check(lib().bzg_workspace_size(self.h, call, _u64p(o), nb, level, n_req, C.byref(out)))
+        return int(out.value)
 
 
 _contexts = {}
@@ -152,8 +171,17 @@ def uniform_offsets(n: int, block_bytes: int) -> np.ndarray:
     return np.array(list(range(0, n, block_bytes)) + [n], dtype=np.uint64)
 
 
-def bwt(x: torch.Tensor, offsets, want_sa: bool = False,
-        ctx: Optional[Context] = None) -> Tuple[torch.Tensor, torch.Tensor, Optional[torch.Tensor]]:
+def _dev_u64(a: np.ndarray, dev) -> torch.Tensor:
+    """A device copy of a host uint64 table (passed to the library as its d_ table)."""
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(dev)
+
+
+def _vp(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def bwt(x: torch.Tensor, offsets, want_sa: bool = False, ctx: Optional[Context] = None,
+        check: bool = True) -> Tuple[torch.Tensor, torch.Tensor, Optional[torch.Tensor]]:
     """BWT of every block -> (last column uint8, primary int32[nb], sa int32 or None)."""
     x = _dev_u8(x)
     o = _offs(offsets)
@@ -162,14 +190,16 @@ def bwt(x: torch.Tensor, offsets, want_sa: bool = False,
     L = torch.empty_like(x)
     prim = torch.empty(max(nb, 1), dtype=torch.int32, device=x.device)
     sa = torch.empty(x.numel(), dtype=torch.int32, device=x.device) if want_sa else None
-    rc = lib().bwt_forward_batch(ctx.h, C.c_void_p(x.data_ptr()), _u64p(o), nb, C.c_void_p(L.data_ptr()),
-                                 C.c_void_p(prim.data_ptr()), C.c_void_p(sa.data_ptr()) if sa is not None else None,
-                                 _stream(x.device))
+    d_o = _dev_u64(o, x.device)
+    st = _stream(x.device)
+    rc = lib().bwt_forward_batch(ctx.h, _vp(x), _vp(d_o), _u64p(o), nb, _vp(L), _vp(prim), _vp(sa), None, 0, st)
     ctx.check(rc)
+    if check:
+        ctx.sync_check(st)
     return L, prim[:nb], sa
 
 
-def mtf(L: torch.Tensor, offsets, ctx: Optional[Context] = None):
+def mtf(L: torch.Tensor, offsets, ctx: Optional[Context] = None, check: bool = True):
     """MTF + RUNA/RUNB -> (syms int16 [n + nb] (uint16 values; block k at
     offsets[k] + k), nsyms int32[nb], inuse uint8[32 nb])."""
     L = _dev_u8(L)
@@ -179,9 +209,12 @@ def mtf(L: torch.Tensor, offsets, ctx: Optional[Context] = None):
     syms = torch.zeros(L.numel() + nb + 1, dtype=torch.int16, device=L.device)
     nsyms = torch.zeros(max(nb, 1), dtype=torch.int32, device=L.device)
     inuse = torch.zeros(32 * max(nb, 1), dtype=torch.uint8, device=L.device)
-    rc = lib().mtf_encode_batch(ctx.h, C.c_void_p(L.data_ptr()), _u64p(o), nb, C.c_void_p(syms.data_ptr()),
-                                C.c_void_p(nsyms.data_ptr()), C.c_void_p(inuse.data_ptr()), _stream(L.device))
+    d_o = _dev_u64(o, L.device)
+    st = _stream(L.device)
+    rc = lib().mtf_encode_batch(ctx.h, _vp(L), _vp(d_o), _u64p(o), nb, _vp(syms), _vp(nsyms), _vp(inuse), None, 0, st)
     ctx.check(rc)
+    if check:
+        ctx.sync_check(st)
     return syms, nsyms[:nb], inuse[:32 * nb]
 
 
@@ -193,7 +226,7 @@ def body_capacity(n_syms_cap: int) -> int:
 
 
 def huffman(syms: torch.Tensor, nsyms: torch.Tensor, inuse: torch.Tensor, sym_offsets,
-            out_offsets=None, want_tables: bool = False, ctx: Optional[Context] = None):
+            out_offsets=None, want_tables: bool = False, ctx: Optional[Context] = None, check: bool = True):
     """Tables + packing -> (out uint8, out_offsets uint64, nbits int64[nb], tables uint8 or None)."""
     so = _offs(sym_offsets)
     nb = so.size - 1
@@ -207,11 +240,13 @@ def huffman(syms: torch.Tensor, nsyms: torch.Tensor, inuse: torch.Tensor, sym_of
     out = torch.zeros(max(int(oo[-1]), 4), dtype=torch.uint8, device=dev)
     nbits = torch.zeros(max(nb, 1), dtype=torch.int64, device=dev)
     tabs = torch.zeros(TABLE_STRIDE * max(nb, 1), dtype=torch.uint8, device=dev) if want_tables else None
-    rc = lib().huffman_encode_batch(ctx.h, C.c_void_p(syms.data_ptr()), C.c_void_p(nsyms.data_ptr()),
-                                    C.c_void_p(inuse.data_ptr()), _u64p(so), nb, C.c_void_p(out.data_ptr()),
-                                    _u64p(oo), C.c_void_p(nbits.data_ptr()),
-                                    C.c_void_p(tabs.data_ptr()) if tabs is not None else None, _stream(dev))
+    d_so, d_oo = _dev_u64(so, dev), _dev_u64(oo, dev)
+    st = _stream(dev)
+    rc = lib().huffman_encode_batch(ctx.h, _vp(syms), _vp(nsyms), _vp(inuse), _vp(d_so), _u64p(so), nb, _vp(out),
+                                    _vp(d_oo), _u64p(oo), _vp(nbits), _vp(tabs), None, 0, st)
     ctx.check(rc)
+    if check:
+        ctx.sync_check(st)
     return out, oo, nbits[:nb], tabs
 
 
@@ -227,23 +262,37 @@ class Compressor:
     def __init__(self, device: Optional[int] = None, ctx: Optional[Context] = None):
         self.ctx = ctx or context(device)
         self.out = None
-        self.out_bytes = C.c_uint64(0)
-        self.n_blocks = C.c_uint32(0)
+        self.out_bytes = None
+        self.n_blocks = None
 
-    def __call__(self, x: torch.Tensor, offsets=None, level: int = 9, block_bytes: Optional[int] = None):
-        x = _dev_u8(x)
-        if offsets is None:
-            offsets = uniform_offsets(x.numel(), block_bytes or 100000 * level)
+    def enqueue(self, x: torch.Tensor, offsets, level: int = 9, d_offsets: Optional[torch.Tensor] = None,
+                ws: Optional[torch.Tensor] = None):
+        """Enqueues one compress_blocks call on the current stream and returns
+        at once (no host wait).  d_offsets: a device copy of offsets (int64),
+        made here when None; ws: a caller workspace (uint8), the context's
+        pool when None.  The stream's length lands in self.out_bytes[0]."""
         o = _offs(offsets)
         nb = o.size - 1
         need = compress_bound(int(o[-1] - o[0]) if nb else 0, nb)
         if self.out is None or self.out.numel() < need or self.out.device != x.device:
             self.out = torch.empty(need, dtype=torch.uint8, device=x.device)
-        rc = lib().compress_blocks(self.ctx.h, C.c_void_p(x.data_ptr()), _u64p(o), nb, level,
-                                   C.c_void_p(self.out.data_ptr()), self.out.numel(), C.byref(self.out_bytes),
-                                   C.byref(self.n_blocks), _stream(x.device))
+            self.out_bytes = torch.zeros(1, dtype=torch.int64, device=x.device)
+            self.n_blocks = torch.zeros(1, dtype=torch.int32, device=x.device)
+        if d_offsets is None:
+            d_offsets = _dev_u64(o, x.device)
+        rc = lib().compress_blocks(self.ctx.h, _vp(x) if x.numel() else None, _vp(d_offsets), _u64p(o), nb, level,
+                                   _vp(self.out), self.out.numel(), _vp(self.out_bytes), _vp(self.n_blocks), _vp(ws),
+                                   ws.numel() if ws is not None else 0, _stream(x.device))
         self.ctx.check(rc)
-        return self.out[: self.out_bytes.value]
+        return d_offsets
+
+    def __call__(self, x: torch.Tensor, offsets=None, level: int = 9, block_bytes: Optional[int] = None):
+        x = _dev_u8(x)
+        if offsets is None:
+            offsets = uniform_offsets(x.numel(), block_bytes or 100000 * level)
+        self.enqueue(x, offsets, level)
+        self.ctx.sync_check(_stream(x.device))
+        return self.out[: int(self.out_bytes.item())]
 
 
 def compress(x: torch.Tensor, offsets=None, level: int = 9, block_bytes: Optional[int] = None) -> torch.Tensor:
@@ -261,17 +310,11 @@ class BatchCompressor:
         self.ctx = ctx or context(device)
         self.out = None
 
-    def __call__(self, x: torch.Tensor, offsets, req_blocks, level: int = 9):
-        """x: all requests' bytes on the GPU; offsets: block boundaries in x;
-        req_blocks: n_req+1 block indices (request r = blocks
-        [req_blocks[r], req_blocks[r+1])).  Returns one uint8 tensor view per
-        request (valid until the next call)."""
-        x = _dev_u8(x)
+    def plan(self, offsets, req_blocks):
+        """Output offsets for these requests (each range holds the stream's bound)."""
         o = _offs(offsets)
         rq = np.ascontiguousarray(np.asarray(req_blocks, dtype=np.uint32))
         nb, nr = o.size - 1, rq.size - 1
-        if nr < 0:
-            raise ValueError("req_blocks needs at least one entry")
         ok = rq.size and int(rq[0]) == 0 and int(rq[-1]) == nb and bool(np.all(np.diff(rq.astype(np.int64)) >= 0))
         ok = ok and bool(np.all(np.diff(o.astype(np.int64)) >= 0))
         # ranges the library will reject get no output space
@@ -279,15 +322,35 @@ class BatchCompressor:
                 if ok else 0 for r in range(nr)]
         oo = np.zeros(nr + 1, np.uint64)
         oo[1:] = np.cumsum(caps, dtype=np.uint64)
+        return o, rq, oo
+
+    def enqueue(self, x: torch.Tensor, offsets, req_blocks, level: int = 9, out_offsets=None):
+        """Enqueues one compress_batch call (no host wait); returns
+        (out_offsets, device stream lengths)."""
+        o, rq, oo = self.plan(offsets, req_blocks)
+        if out_offsets is not None:
+            oo = _offs(out_offsets)
+        nb, nr = o.size - 1, rq.size - 1
         need = max(int(oo[-1]), 4)
         if self.out is None or self.out.numel() < need or self.out.device != x.device:
             self.out = torch.empty(need, dtype=torch.uint8, device=x.device)
-        ob = np.zeros(max(nr, 1), np.uint64)
-        rc = lib().compress_batch(self.ctx.h, C.c_void_p(x.data_ptr()), _u64p(o), nb,
-                                  rq.ctypes.data_as(C.POINTER(C.c_uint32)), nr, level,
-                                  C.c_void_p(self.out.data_ptr()), _u64p(oo), _u64p(ob), _stream(x.device))
+        ob = torch.zeros(max(nr, 1), dtype=torch.int64, device=x.device)
+        rc = lib().compress_batch(self.ctx.h, _vp(x) if x.numel() else None, None, _u64p(o), nb, None,
+                                  rq.ctypes.data_as(C.POINTER(C.c_uint32)), nr, level, _vp(self.out), None,
+                                  _u64p(oo), _vp(ob), None, 0, _stream(x.device))
         self.ctx.check(rc)
-        return [self.out[int(oo[r]): int(oo[r]) + int(ob[r])] for r in range(nr)]
+        return oo, ob
+
+    def __call__(self, x: torch.Tensor, offsets, req_blocks, level: int = 9):
+        """x: all requests' bytes on the GPU; offsets: block boundaries in x;
+        req_blocks: n_req+1 block indices (request r = blocks
+        [req_blocks[r], req_blocks[r+1])).  Returns one uint8 tensor view per
+        request (valid until the next call)."""
+        x = _dev_u8(x)
+        oo, ob = self.enqueue(x, offsets, req_blocks, level)
+        self.ctx.sync_check(_stream(x.device))
+        obh = ob.cpu().numpy()
+        return [self.out[int(oo[r]): int(oo[r]) + int(obh[r])] for r in range(oo.size - 1)]
 
 
 def compress_batch(x: torch.Tensor, offsets, req_blocks, level: int = 9):

@@ -61,6 +61,7 @@ class _Req:
     slot: Optional[list] = None  # ring entry
     t_start: float = 0.0
     t_done: float = 0.0
+    ready: object = None         # device tensor: event on its producer's stream at submit
 
 
 class Ring:
@@ -205,7 +206,14 @@ class Server:
         with self._lock:
             if self._closing:
                 raise RuntimeError("server is closed")
-            self._pending.append(_Req(data, n, t, fut))
+            ready = None
+            if getattr(data, "is_cuda", False):
+                # the upload must not start before whatever produced the
+                # tensor on the submitter's stream has written it
+                import torch
+                ready = torch.cuda.Event()
+                ready.record(torch.cuda.current_stream(data.device))
+            self._pending.append(_Req(data, n, t, fut, ready=ready))
             self.stats.first_arrival = min(self.stats.first_arrival, t)
             self._lock.notify_all()
         return fut
@@ -254,7 +262,7 @@ class Server:
                 r.pos = slot[0] if slot else -1
             if r.n:
                 try:
-                    self.backend.upload(self.arena, r.pos, r.data)
+                    self.backend.upload(self.arena, r.pos, r.data, r.ready)
                 except Exception as e:  # noqa: BLE001
                     with self._lock:
                         self.ring.free(r.slot)
@@ -347,9 +355,11 @@ class GpuBackend:
     def arena(self, nbytes: int):
         return self.torch.empty(max(int(nbytes), 4), dtype=self.torch.uint8, device=self.device)
 
-    def upload(self, arena, pos: int, data):
+    def upload(self, arena, pos: int, data, ready=None):
         torch = self.torch
         with torch.cuda.stream(self.up_stream):
+            if ready is not None:
+                self.up_stream.wait_event(ready)
             if torch.is_tensor(data):
                 src = data.reshape(-1)
                 arena[pos:pos + src.numel()].copy_(src, non_blocking=True)

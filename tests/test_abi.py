@@ -58,8 +58,10 @@ def test_null_context_is_rejected():
     from paper_1109_2348_amd import native
     lib = native.lib()
     assert lib.bzg_last_error(None) == b"null context"
-    assert lib.compress_blocks(None, None, None, 0, 9, None, 0, None, None, None) == native.BZG_EINVAL
-    assert lib.bwt_forward_batch(None, None, None, 0, None, None, None, None) == native.BZG_EINVAL
+    assert lib.compress_blocks(None, None, None, None, 0, 9, None, 0, None, None, None, 0, None) == native.BZG_EINVAL
+    assert lib.bwt_forward_batch(None, None, None, None, 0, None, None, None, None, 0, None) == native.BZG_EINVAL
+    assert lib.bzg_check(None, None) == native.BZG_EINVAL
+    assert lib.bzg_workspace_size(None, 4, None, 0, 9, 1, None) == native.BZG_EINVAL
 
 
 def test_product_path_does_not_import_the_oracle():

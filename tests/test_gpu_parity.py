@@ -370,19 +370,19 @@ def test_compress_batch_all_empty_and_capacity(bz):
     x = _dev(data)
     out = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
     oo = np.array([0, 64, 1 << 16], np.uint64)  # request 0 gets 64 bytes: too few
-    ob = np.zeros(2, np.uint64)
     ctx = native.context()
-    L = native.lib()
-    rc = L.compress_batch(ctx.h, C.c_void_p(x.data_ptr()), native._u64p(offs), offs.size - 1,
-                          rq.ctypes.data_as(C.POINTER(C.c_uint32)), 2, 9, C.c_void_p(out.data_ptr()),
-                          native._u64p(oo), native._u64p(ob), native._stream(x.device))
-    assert rc == native.BZG_ECAPACITY
+    bc = native.BatchCompressor(ctx=ctx)
+    bc.out = out
+    _, ob = bc.enqueue(x, offs, rq, 9, out_offsets=oo)
+    with pytest.raises(bz.BzgError) as ei:
+        ctx.sync_check(native._stream(x.device))
+    assert ei.value.code == native.BZG_ECAPACITY
+    ob = ob.cpu().numpy()
     assert ob[0] > 64 and ob[1] > 0
     oo = np.array([0, 4 * ((int(ob[0]) + 3) // 4), 1 << 16], np.uint64)  # exactly enough
-    rc = L.compress_batch(ctx.h, C.c_void_p(x.data_ptr()), native._u64p(offs), offs.size - 1,
-                          rq.ctypes.data_as(C.POINTER(C.c_uint32)), 2, 9, C.c_void_p(out.data_ptr()),
-                          native._u64p(oo), native._u64p(ob), native._stream(x.device))
-    assert rc == 0
+    _, ob = bc.enqueue(x, offs, rq, 9, out_offsets=oo)
+    ctx.sync_check(native._stream(x.device))
+    ob = ob.cpu().numpy()
     o = out.cpu().numpy()
     for i in range(2):
         z = o[int(oo[i]): int(oo[i]) + int(ob[i])].tobytes()

@@ -34,7 +34,7 @@ class FakeBackend:
     def arena(self, n):
         return np.zeros(n, np.uint8)
 
-    def upload(self, arena, pos, data):
+    def upload(self, arena, pos, data, ready=None):
         a = np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else data
         arena[pos:pos + a.size] = a
 
