@@ -30,6 +30,7 @@
 // gather of key2 runs as its own kernel so that no rank is read after it has
 // been refined in the same round.
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 
 #include "common.hpp"
@@ -175,21 +176,16 @@ __device__ void radix_hist_tile(uint32_t jt, const SegRec* __restrict__ segs, co
   hist[(size_t)g.r.base * 256 + (size_t)d * g.nt + g.t] = s;
 }
 
-// Scan tiles of the device-wide scan that follows a histogram pass (its
-// per-tile state words and ticket, cleared by the histogram kernel).
+// Tiles of the scan that follows a histogram pass (its scratch).
 __host__ __device__ inline uint32_t hist_scan_states(uint32_t tiles) { return (tiles * 256u + 2047u) / 2048u + 1u; }
 
-// Persistent workgroups over *ntiles tiles of large segments.  Also clears
-// the state of the scan that consumes the histogram.
+// Workgroups over *ntiles tiles of large segments.
 template <bool INIT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                    const uint32_t* __restrict__ kin, int shift,
                                                    uint32_t* __restrict__ hist, const uint8_t* __restrict__ text,
-                                                   const uint32_t* __restrict__ ntiles, uint32_t cap,
-                                                   unsigned long long* __restrict__ scan_state) {
+                                                   const uint32_t* __restrict__ ntiles, uint32_t cap) {
   const uint32_t n = min(*ntiles, cap);
-  const uint32_t ns = hist_scan_states(n);
-  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < ns; i += gridDim.x * NT) scan_state[i] = 0ull;
   for (TileLoop it = tile_loop(n); it.t < it.end; it.t += it.step) {
     radix_hist_tile<INIT>(it.t, segs, owner, kin, shift, hist, text);
     __syncthreads();
@@ -1234,23 +1230,29 @@ int bwt_rounds(uint32_t max_len) {
   return r;
 }
 
-static hipError_t radix_passes(BwtWork& w, uint32_t grid, uint32_t cap, const uint32_t* ntiles,
-                               const uint32_t* nrows, const SegRec* segs, const uint32_t* owner, int passes,
-                               uint32_t* err, uint32_t** kin, uint32_t** vin, hipStream_t st) {
+static hipError_t radix_passes(BwtWork& w, uint32_t cap, const uint32_t* ntiles, const uint32_t* nrows,
+                               const SegRec* segs, const uint32_t* owner, int passes, uint32_t* err, uint32_t** kin,
+                               uint32_t** vin, hipStream_t st) {
+  // round passes: tile counts are device-side and usually far below their
+  // bound, so the workgroups are persistent, as many as are resident
+  const uint32_t gh = resident_grid((const void*)k_radix_hist<false>, NT);
+  const uint32_t gs = resident_grid((const void*)k_radix_scatter<false>, NT);
+  const uint32_t gq = std::min(resident_grid((const void*)k_radix_hist<false>, NT),
+                               persist_grid(scan_dev_tiles((uint64_t)cap * 256), ONE_TILE_EACH));
   uint32_t *ka = w.key, *va = w.SA, *kb = w.tmpK, *vb = w.tmpV;
   for (int p = 0; p < passes; p++) {
     {
       ProfScope ps("radix_hist", st, 0, nrows, 4.0);  // read the key
-      hipLaunchKernelGGL(k_radix_hist<false>, dim3(grid), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist, nullptr,
-                         ntiles, cap, w.state);
+      hipLaunchKernelGGL(k_radix_hist<false>, dim3(gh), dim3(NT), 0, st, segs, owner, ka, 8 * p, w.hist, nullptr,
+                         ntiles, cap);
     }
     {
       ProfScope ps("scan", st, 0, ntiles, 8.0 * 256);
-      hipError_t e = scan_lb_u32(w.hist, ntiles, cap, 256, w.state, err, grid, st);
+      hipError_t e = scan_lb_u32(w.hist, ntiles, cap, 256, w.state, err, gq, st);
       if (e != hipSuccess) return e;
     }
     ProfScope ps("radix_scatter", st, 0, nrows, 16.0);  // read and write key and value
-    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(grid), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
+    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(gs), dim3(NT), 0, st, segs, owner, ka, va, kb, vb, 8 * p,
                        w.hist, nullptr, ntiles, cap);
     std::swap(ka, kb);
     std::swap(va, vb);
@@ -1270,8 +1272,11 @@ static hipError_t radix_passes(BwtWork& w, uint32_t grid, uint32_t cap, const ui
 hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, const uint32_t* init_tiles,
                     const BwtBounds& bd, uint32_t* err, int* rounds, hipStream_t st) {
   const BwtSizes& z = w.z;
-  const uint32_t G = persist_grid(z.owner_cap, 2048);
-  const uint32_t Gs = persist_grid((bd.rows + SMALL_T - 1) / SMALL_T + z.owner_cap, 2048);
+  // round kernels: persistent, as many workgroups as are resident
+  const uint32_t Gg = resident_grid((const void*)k_gather, NT);
+  const uint32_t Gs = resident_grid((const void*)k_small_sort, NT);
+  const uint32_t Ga = resident_grid((const void*)k_rename_a, NT);
+  const uint32_t Gb = resident_grid((const void*)k_rename_b, NT);
   hipError_t e;
 #define BZG_TRY(x)                  \
   do {                              \
@@ -1281,7 +1286,8 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
   BZG_TRY(fill32(w.head[0], (size_t)((char*)(w.cnt + 3) - (char*)w.head[0]) / 4, 0u, st));
   const uint32_t* rows = d_off + bd.nslot;  // the row count
   const uint32_t icap = std::min<uint32_t>(bd.init_tiles, (uint32_t)z.owner_cap);
-  const uint32_t Gi = persist_grid(icap, 2048);
+  const uint32_t Gi = persist_grid(icap, ONE_TILE_EACH);  // first sort: one tile per workgroup
+  const uint32_t Gsi = persist_grid(scan_dev_tiles((uint64_t)icap * 256), ONE_TILE_EACH);
   // init: 4 LSD passes on the first 4 bytes of every rotation
   {
     uint32_t* kout[4] = {w.tmpK, w.key, w.tmpK, w.key};
@@ -1292,11 +1298,11 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
       {
         ProfScope ps("init_hist", st, 0, rows, p ? 4.0 : 1.0);  // key in (pass 0: one text byte)
         hipLaunchKernelGGL(k_radix_hist<true>, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], ka, 8 * p, w.hist,
-                           p ? nullptr : text, init_tiles, icap, w.state);
+                           p ? nullptr : text, init_tiles, icap);
       }
       {
         ProfScope ps("scan", st, 0, init_tiles, 8.0 * 256);
-        BZG_TRY(scan_lb_u32(w.hist, init_tiles, icap, 256, w.state, err, Gi, st));
+        BZG_TRY(scan_lb_u32(w.hist, init_tiles, icap, 256, w.state, err, Gsi, st));
       }
       // key and row in and out (pass 0: one text byte in per row)
       ProfScope ps("init_scatter", st, 0, rows, p ? 16.0 : 9.0);
@@ -1335,7 +1341,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
       // row, partner rank, key2
       ProfScope ps("gather", st, 0, big_rows, 12.0, text_round ? nullptr : small_rows, 12.0);
       // the text round's small segments gather their keys in k_small_sort
-      hipLaunchKernelGGL(k_gather, dim3(Gs), dim3(NT), 0, st, w.segs[cur], w.head[cur], w.owner[cur], &w.cnt[cc],
+      hipLaunchKernelGGL(k_gather, dim3(Gg), dim3(NT), 0, st, w.segs[cur], w.head[cur], w.owner[cur], &w.cnt[cc],
                          &w.cnt[cz], text_round ? 0 : 1, hcap, ocap, d_off, w.SA, w.rank,
                          text_round ? text : nullptr, h, w.key);
     }
@@ -1346,16 +1352,16 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
                          d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
     }
     uint32_t *kin, *vin;
-    BZG_TRY(radix_passes(w, G, ocap, big_tiles, big_rows, w.segs[cur], w.owner[cur], text_round ? 4 : rank_passes,
+    BZG_TRY(radix_passes(w, ocap, big_tiles, big_rows, w.segs[cur], w.owner[cur], text_round ? 4 : rank_passes,
                          err, &kin, &vin, st));
     {
       ProfScope ps("rename_a", st, 0, big_rows, 4.0);
       // also clears this round's small-segment heads (read by now)
-      hipLaunchKernelGGL(k_rename_a, dim3(G), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg, big_tiles,
+      hipLaunchKernelGGL(k_rename_a, dim3(Ga), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg, big_tiles,
                          ocap, w.head[cur], small_rows, hcap);
     }
     ProfScope ps("rename_b", st, 0, big_rows, 16.0);
-    hipLaunchKernelGGL(k_rename_b, dim3(G), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin, w.agg, d_off, w.SA,
+    hipLaunchKernelGGL(k_rename_b, dim3(Gb), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin, w.agg, d_off, w.SA,
                        w.rank, 2 * h, text_round ? 0 : 1, 1, app2, big_tiles, ocap);
     BZG_TRY(hipGetLastError());
     cur = nxt;
@@ -1369,7 +1375,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
 hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, const uint32_t* n_rows, uint32_t cap,
                       const uint32_t* SA, uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
   ProfScope ps("bwt_out", st, 0, n_rows, 6.0);  // row in, byte gathered, byte out
-  const uint32_t g = persist_grid(((uint64_t)cap + NT * OUT_ROWS - 1) / (NT * OUT_ROWS), 2048);
+  const uint32_t g = persist_grid(((uint64_t)cap + NT * OUT_ROWS - 1) / (NT * OUT_ROWS), ONE_TILE_EACH);
   hipLaunchKernelGGL(k_bwt_out, dim3(g), dim3(NT), 0, st, text, d_off, nb, n_rows, cap, SA, L, primary, sa_local);
   return hipGetLastError();
 }

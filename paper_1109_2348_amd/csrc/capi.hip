@@ -126,7 +126,6 @@ struct bzg_ctx {
   hipEvent_t stage_ev[2] = {nullptr, nullptr};
   bool stage_used[2] = {false, false};
   int stage_next = 0;
-  uint32_t persist_cap = 2048;  // persistent grid cap (tunable; any value gives the same output)
 };
 
 namespace {
@@ -435,7 +434,7 @@ int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8
                      const uint32_t* d_rb, const uint64_t* d_rout, uint32_t n_req, int level, uint8_t* d_out,
                      uint64_t* d_out_bytes, uint32_t* d_n_blocks, hipStream_t st) {
   uint32_t* err = ctx->status;
-  const uint32_t nb = c.nb, ns = c.nslot, P = ctx->persist_cap;
+  const uint32_t nb = c.nb, ns = c.nslot;
   HIPX(plan_input(d_off, nb, c.L, w.slot_base, w.in_tile0, w.cnt + PC_IN_TILES, w.in_rel, st));
   if (ns) {
     const uint64_t* slot_in = w.in_rel;
@@ -447,7 +446,7 @@ int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8
       HIPX(fill_maps(m, st));
       {
         ProfScope ps("rle1_tiles", st, 0, w.cnt + PC_IN_TILES, RLE_TILE);
-        HIPX(rle1_tiles(in, persist_grid(c.in_tiles, P), w.cnt + PC_IN_TILES, w.in_tile_blk, w.in_tile0, w.in_rel,
+        HIPX(rle1_tiles(in, persist_grid(c.in_tiles, ONE_TILE_EACH), w.cnt + PC_IN_TILES, w.in_tile_blk, w.in_tile0, w.in_rel,
                         ctx->crc_tab, ctx->crc_tab + CRC_POW_AT, w.in_rec, st));
       }
       HIPX(rle1_blocks(nb, w.in_tile0, w.in_rel, ctx->crc_tab + CRC_POW_AT, w.in_rec, w.in_tile_rs, w.in_tile_out,
@@ -466,7 +465,7 @@ int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8
     }
     {
       ProfScope ps("rle1_tiles", st, 0, w.cnt + PC_RLE_TILES, RLE_TILE);
-      HIPX(rle1_tiles(in, persist_grid(c.slot_tiles, P), w.cnt + PC_RLE_TILES, w.slot_tile_blk, w.slot_tile0, slot_in,
+      HIPX(rle1_tiles(in, persist_grid(c.slot_tiles, ONE_TILE_EACH), w.cnt + PC_RLE_TILES, w.slot_tile_blk, w.slot_tile0, slot_in,
                       ctx->crc_tab, ctx->crc_tab + CRC_POW_AT, w.rec, st));
     }
     HIPX(rle1_blocks(ns, w.slot_tile0, slot_in, ctx->crc_tab + CRC_POW_AT, w.rec, w.tile_rs, w.tile_out, w.rle_n,
@@ -489,7 +488,7 @@ int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8
     }
     {
       ProfScope ps("rle1_emit", st, 0, w.cnt + PC_RLE_TILES, RLE_TILE, w.cnt + PC_ROWS, 1.0);
-      HIPX(rle1_emit(in, persist_grid(c.slot_tiles, P), w.cnt + PC_RLE_TILES, w.slot_tile_blk, w.slot_tile0, slot_in,
+      HIPX(rle1_emit(in, persist_grid(c.slot_tiles, ONE_TILE_EACH), w.cnt + PC_RLE_TILES, w.slot_tile_blk, w.slot_tile0, slot_in,
                      w.tile_rs, w.tile_out, w.roff, w.text, st));
     }
     // BWT
@@ -521,10 +520,9 @@ int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8
     ha.tile_groups = c.atg;
     ha.ws = w.hws;
     HIPX(huff_run(ha, st));
-    HIPX(fill32((uint32_t*)w.gstate, 2 * (uint64_t)scan_lb_states(c.groups), 0u, st));
     {
       ProfScope ps("scan", st, 0, w.cnt + PC_GROUPS_LO, 16.0);
-      HIPX(scan_lb_u64(w.gbits, w.cnt + PC_GROUPS_LO, c.groups, 1, w.gstate, err, persist_grid(c.groups / 2048 + 1, P),
+      HIPX(scan_lb_u64(w.gbits, w.cnt + PC_GROUPS_LO, c.groups, 1, w.gstate, err, persist_grid(scan_dev_tiles(c.groups), ONE_TILE_EACH),
                        st));
     }
   }
@@ -972,9 +970,8 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   ha.sym_off = d_soff;
   ha.ns_eff = w.ns_eff;
   HIPX(huff_run(ha, st));
-  HIPX(fill32((uint32_t*)w.gstate, 2 * (uint64_t)scan_lb_states(b.groups), 0u, st));
   HIPX(scan_lb_u64(w.gbits, w.cnt + PC_GROUPS_LO, b.groups, 1, w.gstate, ctx->status,
-                   persist_grid(b.groups / 2048 + 1, ctx->persist_cap), st));
+                   persist_grid(scan_dev_tiles(b.groups), ONE_TILE_EACH), st));
   HIPX(pack_layout(n_blocks, 1, nullptr, nullptr, w.tabs, 1, d_oo, w.blkbit, nullptr, d_nbits, nullptr, nullptr,
                    nullptr, w.skip, ctx->status, st));
   HIPX(zero_range((uint32_t*)(d_out + h_out_offsets[0]), (h_out_offsets[n_blocks] - h_out_offsets[0]) / 4, w.skip,

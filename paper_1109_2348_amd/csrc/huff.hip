@@ -625,7 +625,7 @@ hipError_t huff_run(const HuffArgs& a, hipStream_t st) {
                        a.err);
     nsyms = a.ns_eff;
   }
-  const uint32_t g = persist_grid(a.tiles_cap, 4096);
+  const uint32_t g = persist_grid(a.tiles_cap, ONE_TILE_EACH);
   const int clamp = a.count_freq ? 1 : 0;
   // symbol counts are known on the device only: no algorithmic bytes recorded
   {

@@ -95,13 +95,21 @@ __device__ __forceinline__ TileLoop tile_loop(uint32_t n) {
   L.step = gridDim.x >> 3;
   return L;
 }
-// Workgroups for a persistent launch over at most `bound` tiles: a multiple
-// of 8, at most `cap`.
+// Workgroups for a launch over at most `bound` tiles: a multiple of 8, at
+// most `cap`.  With cap >= bound every workgroup takes at most one tile (the
+// hardware dispatches them as slots free up); a smaller cap makes the
+// workgroups persistent.
 inline uint32_t persist_grid(uint64_t bound, uint32_t cap) {
   uint64_t g = bound < cap ? bound : cap;
   g = (g + 7) & ~uint64_t(7);
   return (uint32_t)(g < 8 ? 8 : g);
 }
+constexpr uint32_t ONE_TILE_EACH = 0x7FFFFFF8u;  // cap for one tile per workgroup
+
+// Workgroups of `kernel` (block of `threads`) that are resident on the
+// device at once: the grid of a persistent launch whose tile count is
+// usually far below its bound.
+uint32_t resident_grid(const void* kernel, int threads);
 
 // A run of equal-prefix rotations still to be ordered: SA rows
 // [start, start+len) of block blk.  `base` is the segment's packed element
@@ -256,10 +264,12 @@ hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, c
 size_t scan_tmp_elems(size_t n);
 hipError_t scan_excl_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp, hipStream_t s);
 hipError_t scan_excl_u64(const uint64_t* in, uint64_t* out, size_t n, uint64_t* tmp, hipStream_t s);
-// Single-pass exclusive scan in place over min(*count_ptr, cap) * mult
-// elements (a device count).  state: scan_lb_states(cap * mult) words, zero
-// at entry.
+// Exclusive scan in place over min(*count_ptr, cap) * mult elements (a
+// device count): three launches (tile sums, their scan, the tiles' scans).
+// state: scan_lb_states(cap * mult) elements of scratch; grid: workgroups of
+// the tile passes (they loop over the tiles).
 uint32_t scan_lb_states(uint64_t n);
+uint32_t scan_dev_tiles(uint64_t n);
 hipError_t scan_lb_u32(uint32_t* data, const uint32_t* count_ptr, uint32_t cap, uint32_t mult,
                        unsigned long long* state, uint32_t* err, uint32_t grid, hipStream_t s);
 hipError_t scan_lb_u64(uint64_t* data, const uint32_t* count_ptr, uint32_t cap, uint32_t mult,

@@ -780,7 +780,7 @@ hipError_t mtf_run(const uint8_t* L, const uint32_t* d_off, uint32_t nb, uint64_
     return hipErrorInvalidValue;
   }
   if (nb == 0) return hipSuccess;
-  const uint32_t gs = persist_grid(nc, 2048), ge = persist_grid(nc, 8192);
+  const uint32_t gs = persist_grid(nc, ONE_TILE_EACH), ge = persist_grid(nc, ONE_TILE_EACH);
   {
     ProfScope ps("mtf_state", st, 0, d_off + nb, 1.0, n_chunks, 256.0);
     if (ch == MTF_CHUNK)

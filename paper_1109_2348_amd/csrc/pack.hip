@@ -463,7 +463,7 @@ hipError_t pack_run(uint32_t nb, const void* tabs, int mode, const uint64_t* blk
   if (nb) {
     hipLaunchKernelGGL(k_pack_header, dim3(nb), dim3(NT), 0, st, (const BlockTables*)tabs, mode, blk_bit, crc, primary,
                        inuse, sel_base, selmtf, words, skip);
-    const uint32_t g = persist_grid(tiles_cap, 4096);
+    const uint32_t g = persist_grid(tiles_cap, ONE_TILE_EACH);
     hipLaunchKernelGGL(k_pack_data, dim3(g), dim3(NT), 0, st, (const BlockTables*)tabs, mode, tile_blk, blk_tile0,
                        blk_bit, syms, sym_base, nsyms, sel_base, sel, gofs, words, n_tiles, tiles_cap, skip);
   }

@@ -13,6 +13,9 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace bzg {
 
@@ -236,6 +239,22 @@ hipError_t fill_maps(const MapSet& m, hipStream_t st) {
   const uint32_t g = (uint32_t)std::min<uint64_t>((tot + NT - 1) / NT + 1, 4096);
   if (m.nmaps) hipLaunchKernelGGL(k_fill_maps, dim3(g), dim3(NT), 0, st, m);
   return hipGetLastError();
+}
+
+uint32_t resident_grid(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, uint32_t> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({dev, kernel});
+  if (it != cache.end()) return it->second;
+  int occ = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess || occ < 1) occ = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  const uint32_t g = persist_grid((uint64_t)occ * cus, ONE_TILE_EACH);
+  cache[{dev, kernel}] = g;
+  return g;
 }
 
 hipError_t fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {

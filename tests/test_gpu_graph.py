@@ -56,28 +56,45 @@ def test_compress_blocks_graph_replay_bit_exact():
 
 def test_calls_enqueue_without_waiting():
     """A call returns before its work is done: with the device kept busy by
-    a long kernel queued first, compress_blocks still returns at once and
-    the stream only then completes."""
+    a long chain of kernels queued first, compress_blocks returns at once
+    (with the caller's device tables and workspace, and with the library
+    copying the host offsets itself), and the stream completes later."""
+    import ctypes as C
     import time
     import torch
     from paper_1109_2348_amd import native
     dev = torch.device("cuda", 0)
     b = W.config2(total=3 * 100000, block=100000, seed=29)
     x = torch.from_numpy(b.data).to(dev)
+    o = np.ascontiguousarray(b.offsets, dtype=np.uint64)
     ctx = native.Context(0)
     comp = native.Compressor(ctx=ctx)
-    comp(x, b.offsets, level=9)  # sizes buffers and the pool
-    a = torch.randn(4096, 4096, device=dev)
-    torch.cuda.synchronize()
-    for _ in range(40):  # a few hundred ms of queued work
-        a = a @ a
-        a = a / a.norm()
-    t0 = time.perf_counter()
-    comp.enqueue(x, b.offsets, 9)
-    t_call = time.perf_counter() - t0
+    ref = cref.compress(b.data, b.offsets, level=9, threads=16)
+    d_o = native._dev_u64(o, dev)
+    ws = torch.empty(ctx.workspace_size(native.CALL_COMPRESS, o, level=9), dtype=torch.uint8, device=dev)
+    comp.enqueue(x, o, 9, d_offsets=d_o, ws=ws)  # sizes the output buffers
     ctx.sync_check(native._stream(dev))
-    t_all = time.perf_counter() - t0
-    _say(f"enqueue {t_call * 1e3:.2f} ms, until done {t_all * 1e3:.2f} ms")
-    assert t_call < 0.5 * t_all
-    z = comp.out[: int(comp.out_bytes.item())].cpu().numpy().tobytes()
-    assert z == cref.compress(b.data, b.offsets, level=9, threads=16)
+    st = native._stream(dev)
+    for mode in ("caller tables and workspace", "library upload and pool"):
+        a = torch.randn(4096, 4096, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(40):  # tens of ms of queued work
+            a = a @ a
+            a = a / a.norm()
+        t0 = time.perf_counter()
+        if mode.startswith("caller"):
+            rc = native.lib().compress_blocks(ctx.h, native._vp(x), native._vp(d_o), native._u64p(o), o.size - 1, 9,
+                                              native._vp(comp.out), comp.out.numel(), native._vp(comp.out_bytes),
+                                              None, native._vp(ws), ws.numel(), st)
+        else:
+            rc = native.lib().compress_blocks(ctx.h, native._vp(x), None, native._u64p(o), o.size - 1, 9,
+                                              native._vp(comp.out), comp.out.numel(), native._vp(comp.out_bytes),
+                                              None, None, 0, st)
+        t_call = time.perf_counter() - t0
+        ctx.check(rc)
+        ctx.sync_check(st)
+        t_all = time.perf_counter() - t0
+        _say(f"{mode}: enqueue {t_call * 1e3:.2f} ms, until done {t_all * 1e3:.2f} ms")
+        assert t_call < 0.5 * t_all
+        z = comp.out[: int(comp.out_bytes.item())].cpu().numpy().tobytes()
+        assert z == ref
