@@ -321,7 +321,7 @@ CBounds compress_bounds(const uint64_t* h_off, uint32_t nb, int level, const uin
     const uint32_t pm = max_pieces(n, c.L);
     c.nslot += pm;
     if (pm > 1) c.direct = false;
-    c.in_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE);
+    if (pm > 1) c.in_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE);
     c.slot_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE) + (pm ? pm - 1 : 0);
     const uint64_t r = std::min<uint64_t>(n + n / 4, (uint64_t)pm * c.L);
     rows += r;
@@ -621,6 +621,7 @@ int bzg_create(bzg_ctx** out, int hip_device, const char* tune_cache_path) {
     ctx->stage_half = 1 << 19;
     e = hipHostMalloc((void**)&ctx->stage, 2 * ctx->stage_half, hipHostMallocDefault);
   }
+
   if (e != hipSuccess) {
     bzg_destroy(ctx);
     return BZG_EHIP;

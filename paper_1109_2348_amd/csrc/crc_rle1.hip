@@ -405,7 +405,9 @@ __device__ __forceinline__ uint32_t run_fit(uint32_t L) { return 255u * (L / 5u)
 // afresh).  Piece j of block k goes to slot slot_base[k] + j
 // (slot_in[slot] = its first input byte, relative); slots the block does not
 // need get empty ranges at the block end.  Inputs are the block's whole-
-// stream tile records (pass A and B over the input blocks): tile_out[t] is
+// stream tile records (pass A and B over the input blocks that may need
+// cutting; a block with one slot has no tiles, RLE1 length 0, and keeps its
+// whole range): tile_out[t] is
 // the output position P of the tile's first byte and P is what the block's
 // RLE1 stream has written before a byte.
 //

@@ -45,8 +45,8 @@ __device__ __forceinline__ uint32_t ceil_div(uint64_t a, uint32_t b) { return (u
 // Input blocks -> slots.  in_off: the caller's n_in + 1 offsets (absolute;
 // in0 = in_off[0] is subtracted).  Writes in_rel (the offsets relative to
 // in0), slot_base[k] (exclusive scan of the block's slot count, n_in + 1
-// entries) and, per block, its tile range over RLE_TILE-byte tiles
-// (tile0[k], total in cnt[0]).
+// entries) and, per block that may need cutting, its tile range over
+// RLE_TILE-byte tiles (tile0[k], total in cnt[0]; other blocks get none).
 __global__ __launch_bounds__(PNT) void k_plan_input(const uint64_t* __restrict__ in_off, uint32_t n_in, uint32_t L,
                                                     uint32_t* __restrict__ slot_base, uint32_t* __restrict__ tile0,
                                                     uint32_t* __restrict__ cnt, uint64_t* __restrict__ in_rel) {
@@ -57,8 +57,9 @@ __global__ __launch_bounds__(PNT) void k_plan_input(const uint64_t* __restrict__
       n_in, [&](uint32_t k) { return max_pieces(len(k), L); },
       [&](uint32_t k, uint32_t ex) { slot_base[k] = ex; }, sh);
   __syncthreads();
+  // only blocks that may need cutting are measured whole (the others fit)
   wg_scan<uint32_t>(
-      n_in, [&](uint32_t k) { return ceil_div(len(k), RLE_TILE); },
+      n_in, [&](uint32_t k) { return max_pieces(len(k), L) > 1 ? ceil_div(len(k), RLE_TILE) : 0u; },
       [&](uint32_t k, uint32_t ex) {
         tile0[k] = ex;
         if (k == n_in) cnt[0] = ex;
