@@ -215,6 +215,24 @@ int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets,
                    uint64_t* d_out_bytes, void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * compress_blocks for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same stream as compress_blocks, with its workspace in a static device
+ * array of 128 MiB that the library holds per GPU until the process ends
+ * (enough for about 1.5 MB of input; a call that needs more returns
+ * BZG_EWORKSPACE with the size in bzg_last_error()).  The call allocates
+ * nothing: d_offsets (device copy of h_offsets) is required, and no
+ * profiling scopes are recorded.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other contexts,
+ * other host threads) race, so a caller serialises them.  The kernels
+ * initialise every part of the array they read.  Arguments and results as
+ * for compress_blocks.
+ */
+int compress_blocks_noalloc(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                            uint32_t n_blocks, int level, uint8_t* d_out, uint64_t out_cap, uint64_t* d_out_bytes,
+                            uint32_t* d_n_blocks, void* stream);
+
+/*
  * Diagnostics: per-kernel timing.  While enabled, every instrumented launch
  * is bracketed by HIP events on its stream, and the device counts that give
  * its algorithmic bytes (the array traffic the method needs, not what the

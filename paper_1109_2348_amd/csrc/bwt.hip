@@ -1372,6 +1372,15 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
 #undef BZG_TRY
 }
 
+void bwt_warm_grids() {
+  (void)resident_grid((const void*)k_gather, NT);
+  (void)resident_grid((const void*)k_small_sort, NT);
+  (void)resident_grid((const void*)k_rename_a, NT);
+  (void)resident_grid((const void*)k_rename_b, NT);
+  (void)resident_grid((const void*)k_radix_hist<false>, NT);
+  (void)resident_grid((const void*)k_radix_scatter<false>, NT);
+}
+
 hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, const uint32_t* n_rows, uint32_t cap,
                       const uint32_t* SA, uint8_t* L, uint32_t* primary, uint32_t* sa_local, hipStream_t st) {
   ProfScope ps("bwt_out", st, 0, n_rows, 6.0);  // row in, byte gathered, byte out

@@ -105,6 +105,13 @@ void Profiler::collect() {
 
 using namespace bzg;
 
+// Scratch of compress_blocks_noalloc: a file-scope device array, one per
+// GPU, allocated when the code object loads and held until the process
+// ends.  Host code uses the per-device address from hipGetSymbolAddress
+// (bzg_ctx::scratch), never this name.
+constexpr size_t SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
 struct bzg_ctx {
   std::mutex mu;  // calls on one context enqueue one at a time
   int device = 0;
@@ -126,6 +133,7 @@ struct bzg_ctx {
   hipEvent_t stage_ev[2] = {nullptr, nullptr};
   bool stage_used[2] = {false, false};
   int stage_next = 0;
+  void* scratch = nullptr;  // this device's copy of `scratch`
 };
 
 namespace {
@@ -621,7 +629,8 @@ int bzg_create(bzg_ctx** out, int hip_device, const char* tune_cache_path) {
     ctx->stage_half = 1 << 19;
     e = hipHostMalloc((void**)&ctx->stage, 2 * ctx->stage_half, hipHostMallocDefault);
   }
-
+  if (e == hipSuccess) e = hipGetSymbolAddress(&ctx->scratch, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) bwt_warm_grids();  // grid sizes cached now, so later calls compute none
   if (e != hipSuccess) {
     bzg_destroy(ctx);
     return BZG_EHIP;
@@ -1025,6 +1034,28 @@ int compress_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets,
   return compress_common(ctx, d_in, d_offsets, h_offsets, n_blocks, d_req_blocks, h_req_blocks, n_req, level, d_out,
                          d_out_offsets, h_out_offsets, 0, d_out_bytes, nullptr, d_ws, ws_bytes,
                          (hipStream_t)stream);
+}
+
+int compress_blocks_noalloc(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets, const uint64_t* h_offsets,
+                            uint32_t n_blocks, int level, uint8_t* d_out, uint64_t out_cap, uint64_t* d_out_bytes,
+                            uint32_t* d_n_blocks, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!d_out || !d_out_bytes || !d_offsets) return fail(ctx, BZG_EINVAL, "null pointer (d_offsets is required)");
+  int rc = check_compress(ctx, d_in, h_offsets, n_blocks, level);
+  if (rc) return rc;
+  if ((uintptr_t)d_out & 3) return fail(ctx, BZG_EINVAL, "d_out must be 4-byte aligned");
+  const uint64_t zero_off = 0;
+  const CBounds c = compress_bounds(n_blocks ? h_offsets : &zero_off, n_blocks, level, nullptr, 1);
+  CWork w;
+  const size_t need = carve_compress(nullptr, c, 1, w, 0);
+  if (need > SCRATCH_BYTES)
+    return fail(ctx, BZG_EWORKSPACE, "the call needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                         std::to_string(SCRATCH_BYTES));
+  // no profiling scopes here: they create events
+  return compress_common(ctx, d_in, d_offsets, h_offsets, n_blocks, nullptr, nullptr, 1, level, d_out, nullptr,
+                         nullptr, out_cap, d_out_bytes, d_n_blocks, ctx->scratch, SCRATCH_BYTES, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -255,6 +255,7 @@ struct HuffArgs {
 size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
 bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w);
 int bwt_rounds(uint32_t max_len);
+void bwt_warm_grids();  // computes the sort's resident grid sizes once
 hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, const uint32_t* init_tiles,
                     const BwtBounds& bd, uint32_t* err, int* rounds, hipStream_t st);
 hipError_t bwt_output(const uint8_t* text, const uint32_t* d_off, uint32_t nb, const uint32_t* n_rows, uint32_t cap,

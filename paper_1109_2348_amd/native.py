@@ -61,6 +61,8 @@ def lib() -> C.CDLL:
         L.compress_blocks.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp, sz, vp]
         L.compress_batch.restype = i
         L.compress_batch.argtypes = [vp, vp, vp, u64p, u32, vp, u32p, u32, i, vp, vp, u64p, vp, vp, sz, vp]
+        L.compress_blocks_noalloc.restype = i
+        L.compress_blocks_noalloc.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp]
         L.bzg_profile.restype = i
         L.bzg_profile.argtypes = [vp, i]
         L.bzg_profile_read.restype = i
@@ -71,7 +73,7 @@ def lib() -> C.CDLL:
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_check", "bzg_workspace_size", "bzg_compress_bound",
            "bwt_forward_batch", "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch",
-           "bzg_profile", "bzg_profile_read")
+           "compress_blocks_noalloc", "bzg_profile", "bzg_profile_read")
 
 
 class Profile:
