@@ -382,6 +382,14 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
     if (threadIdx.x == 0) atomicOr(a.err, ERR_BOUND);
     m = 0;
   }
+  // The workgroup's packed range holds its segments back to back: every
+  // position is written (0, then each segment's mark at its start), so a
+  // head array needs no clearing before it is appended to.
+  {
+    const uint32_t lo = wg_base[1], hi = (uint32_t)min((uint64_t)lo + t_small, (uint64_t)a.head_cap);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += NT) a.head[i] = 0u;
+  }
+  __syncthreads();
   uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
 #pragma unroll
   for (int g = 0; g < M; g++) {
@@ -437,19 +445,10 @@ __device__ void rename_a_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
   }
 }
 
-// Persistent workgroups over *ntiles tiles.  Also clears the first
-// `head_clear` entries of a small-segment head array that this round's
-// small-segment sort has finished reading (so that it can be appended to two
-// rounds later); head_clear is a device count (nullable).
+// Persistent workgroups over *ntiles tiles.
 __global__ __launch_bounds__(NT) void k_rename_a(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                                  const uint32_t* __restrict__ kin, uint32_t* __restrict__ agg,
-                                                 const uint32_t* __restrict__ ntiles, uint32_t cap,
-                                                 uint32_t* __restrict__ head, const uint32_t* __restrict__ head_clear,
-                                                 uint32_t head_cap) {
-  if (head_clear) {
-    const uint32_t nh = min(*head_clear, head_cap);
-    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nh; i += gridDim.x * NT) head[i] = 0u;
-  }
+                                                 const uint32_t* __restrict__ ntiles, uint32_t cap) {
   for (TileLoop it = tile_loop(min(*ntiles, cap)); it.t < it.end; it.t += it.step) {
     rename_a_tile(it.t, segs, owner, kin, agg);
     __syncthreads();
@@ -839,9 +838,11 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // (segment position << 21 | key2) in 4 passes; the text round (text_mode,
 // 32-bit keys) sorts on key2 and then the segment position, 6 passes, and
 // leaves equal-rotation groups to the next round.
-// Segments of at most this many rows are ordered by counting instead of the
-// tile's radix passes.
-constexpr uint32_t COUNT_SORT_MAX = 64;
+// A tile is ordered by counting instead of radix passes when the counting
+// costs its slowest wave at most this many steps per radix pass the tile
+// would otherwise run (a counting step of 64 rows and a radix pass over 64
+// rows cost about this much in issued instructions, measured as counters).
+constexpr uint32_t COUNT_STEPS_PER_PASS = 48;
 
 __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec* __restrict__ segs,
                                 uint32_t* __restrict__ head, const uint32_t* __restrict__ blk_off,
@@ -851,35 +852,36 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
   const bool text_mode = text != nullptr;
   const uint32_t h = h_next / 2;
   __shared__ uint32_t mark[SMALL_CAP];
+  __shared__ uint32_t sval[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t skey[SMALL_CAP];
-  __shared__ uint32_t sval[SMALL_CAP];
-  __shared__ uint16_t sseg[SMALL_CAP];  // text round: segment position of each key
+  __shared__ uint16_t sseg[SMALL_CAP];  // segment ends (counting) or each key's segment position (radix)
   __shared__ uint32_t scnt[NW][256];
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t sx[NT];
-  __shared__ uint32_t s_n, s_maxlen;
+  __shared__ uint32_t s_n, s_maxlen, s_cost;
   __shared__ uint32_t wg_base[4];
+  if (threadIdx.x == 0) s_cost = 0;
   const uint32_t n = small_tile_map(jt, head, small_total, mark, segp, sh, &s_n, &s_maxlen, sseg);
-  // Tiles whose segments are all short are ordered by counting (below); they
-  // keep the segment ends in sseg, which the radix passes use otherwise.
-  const bool counting = s_maxlen <= COUNT_SORT_MAX;
   constexpr int PI = SMALL_CAP / NT;  // 8
-  // The naming at the end needs the segment record and block bounds of
-  // each of this thread's positions there (PI consecutive ones): loaded
-  // now, so that their latency passes during the loads and the sort.
-  // (records with the loads' first stage, block bounds after their second)
-  SegRec rr[PI];
-  uint32_t bo[PI], be[PI];
+  const int npass_radix = text_mode ? 6 : 4;
+  // Counting (below) ranks each row among its segment's rows in as many
+  // steps as the longest segment among the wave's 64 positions; the tile is
+  // counted when its slowest wave's steps cost less than the radix passes.
+  // Counted tiles keep the segment ends in sseg.
   {
-    const uint32_t p0 = threadIdx.x * PI;
+    uint32_t steps = 0;
 #pragma unroll
-    for (int i = 0; i < PI; i++) {
-      const uint32_t p = p0 + i;
-      rr[i] = SegRec{0, 0, 0, 0};
-      if (p < n && segp[p] != NO_SEG) rr[i] = segs[mark[segp[p]] - 1];
+    for (int j = 0; j < PI; j++) {
+      const uint32_t p = j * NT + threadIdx.x;
+      const uint32_t spv = p < n ? segp[p] : NO_SEG;
+      const uint32_t len = spv != NO_SEG ? (uint32_t)sseg[spv] - spv : 0u;
+      steps += wave_max(len);
     }
+    if (lane() == 0) atomicMax(&s_cost, steps);
   }
+  __syncthreads();
+  const bool counting = s_cost <= COUNT_STEPS_PER_PASS * (uint32_t)npass_radix;
   // load (segment start << 21 | key2, SA value).  Positions before the
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
@@ -921,12 +923,6 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
       }
       gather_keys_impl<PL, false>(k2, o, nbk, text, nullptr);
     }
-    __builtin_amdgcn_sched_barrier(0);  // issue order: these loads stay after the rows'
-#pragma unroll
-    for (int i = 0; i < PI; i++) {
-      bo[i] = blk_off[rr[i].blk];
-      be[i] = blk_off[rr[i].blk + 1];
-    }
     // (selects, not branches: a load used only under a branch would be
     // moved into it and waited for there)
 #pragma unroll
@@ -947,30 +943,29 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
   // (smaller key, or equal key further up); keys compare equal inside a
   // segment exactly when key2 does.
   if (counting) {
-    const uint32_t ml = s_maxlen;
     uint32_t dst[PI], kv[PI], vv[PI];
 #pragma unroll
     for (int j = 0; j < PI; j++) {
       const uint32_t p = j * NT + threadIdx.x;
-      dst[j] = 0xFFFFFFFFu;
-      if (p < n && segp[p] != NO_SEG) {
-        const uint32_t sp = segp[p];
-        const uint32_t me = skey[p];
-        const uint32_t len = sseg[sp] - sp, d = p - sp;
-        uint32_t r = 0;
-        // a fixed count of steps (the tile's longest segment)
-        // (bitwise, not short-circuit, tests: a load used only under a
-        // branch would be moved into it and waited for there, one LDS round
-        // trip per step)
+      const uint32_t spv = p < n ? segp[p] : NO_SEG;
+      const bool has = spv != NO_SEG;
+      const uint32_t sp = has ? spv : 0u;
+      const uint32_t len = has ? (uint32_t)sseg[sp] - sp : 0u, d = p - sp;
+      const uint32_t me = skey[p];
+      // the wave steps through the longest segment among its positions
+      const uint32_t wl = wave_max(len);
+      uint32_t r = 0;
+      // (bitwise, not short-circuit, tests: a load used only under a branch
+      // would be moved into it and waited for there, one LDS round trip per
+      // step)
 #pragma unroll 8
-        for (uint32_t i = 0; i < ml; i++) {
-          const uint32_t o = skey[min(sp + i, SMALL_CAP - 1u)];
-          r += (uint32_t)(i < len) & ((uint32_t)(o < me) | ((uint32_t)(o == me) & (uint32_t)(i < d)));
-        }
-        dst[j] = sp + r;
-        kv[j] = me;
-        vv[j] = sval[p];
+      for (uint32_t i = 0; i < wl; i++) {
+        const uint32_t o = skey[min(sp + i, SMALL_CAP - 1u)];
+        r += (uint32_t)(i < len) & ((uint32_t)(o < me) | ((uint32_t)(o == me) & (uint32_t)(i < d)));
       }
+      dst[j] = has ? sp + r : 0xFFFFFFFFu;
+      kv[j] = me;
+      vv[j] = sval[p];
     }
     __syncthreads();
 #pragma unroll
@@ -981,7 +976,7 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
       }
     __syncthreads();
   }
-  const int npass = counting ? 0 : text_mode ? 6 : 4;
+  const int npass = counting ? 0 : npass_radix;
   // the passes sort positions [0, 4 * 64 * R) only, R items per lane: the
   // positions from n on hold the largest key and stay behind anyway
   const int R = (int)((n + NW * BZG_WAVE - 1) / (NW * BZG_WAVE));
@@ -1043,6 +1038,23 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
     sg[i] = segp[p0 + i];
     sv[i] = sval[p0 + i];
   }
+  // segment records and block bounds of the thread's positions (loaded here,
+  // not before the sort, so that they hold no registers through it: that
+  // leaves room for a fourth workgroup per CU); record 0 where none
+  SegRec rr[PI];
+  uint32_t bo[PI], be[PI];
+  {
+    uint32_t ri[PI];
+#pragma unroll
+    for (int i = 0; i < PI; i++) ri[i] = sg[i] != NO_SEG ? mark[sg[i]] : 0u;
+#pragma unroll
+    for (int i = 0; i < PI; i++) rr[i] = segs[ri[i] ? ri[i] - 1u : 0u];
+#pragma unroll
+    for (int i = 0; i < PI; i++) {
+      bo[i] = blk_off[rr[i].blk];
+      be[i] = blk_off[rr[i].blk + 1];
+    }
+  }
   uint32_t lastb = 0;
 #pragma unroll
   for (int i = 0; i < PI; i++) {
@@ -1092,7 +1104,7 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
   append_groups<PI / 2 + 1>(app, gs, gl, m, 0, gb, wg_base);
 }
 
-__global__ __launch_bounds__(NT) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
+__global__ __launch_bounds__(NT, 4) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
                                                    const RoundCounters* cnt, uint32_t head_cap, uint32_t owner_cap,
                                                    const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
@@ -1213,10 +1225,8 @@ bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w) {
     w.segs[i] = bump.take<SegRec>(z.seg_cap);
     w.owner[i] = bump.take<uint32_t>(z.owner_cap);
   }
-  // both head arrays and the counter records in one range (one fill)
   w.head[0] = bump.take<uint32_t>(z.head_cap);
-  w.head[1] = w.head[0] + z.head_cap;
-  (void)bump.take<uint32_t>(z.head_cap);
+  w.head[1] = bump.take<uint32_t>(z.head_cap);
   w.cnt = bump.take<RoundCounters>(3);
   return bump.used <= ws_bytes;
 }
@@ -1283,7 +1293,9 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     e = (x);                        \
     if (e != hipSuccess) return e;  \
   } while (0)
-  BZG_TRY(fill32(w.head[0], (size_t)((char*)(w.cnt + 3) - (char*)w.head[0]) / 4, 0u, st));
+  // the counter records start at zero; the head arrays need no clearing
+  // (each append writes its whole range)
+  BZG_TRY(fill32((uint32_t*)w.cnt, 3 * sizeof(RoundCounters) / 4, 0u, st));
   const uint32_t* rows = d_off + bd.nslot;  // the row count
   const uint32_t icap = std::min<uint32_t>(bd.init_tiles, (uint32_t)z.owner_cap);
   const uint32_t Gi = persist_grid(icap, ONE_TILE_EACH);  // first sort: one tile per workgroup
@@ -1316,7 +1328,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     {
       ProfScope ps("rename_a", st, 0, rows, 4.0);
       hipLaunchKernelGGL(k_rename_a, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.agg, init_tiles,
-                         icap, nullptr, nullptr, hcap);
+                         icap);
     }
     ProfScope ps("rename_b", st, 0, rows, 12.0);  // key and row in, rank out
     // only rows alone in their group are ranked here: round 0 compares text
@@ -1356,9 +1368,8 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
                          err, &kin, &vin, st));
     {
       ProfScope ps("rename_a", st, 0, big_rows, 4.0);
-      // also clears this round's small-segment heads (read by now)
       hipLaunchKernelGGL(k_rename_a, dim3(Ga), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, w.agg, big_tiles,
-                         ocap, w.head[cur], small_rows, hcap);
+                         ocap);
     }
     ProfScope ps("rename_b", st, 0, big_rows, 16.0);
     hipLaunchKernelGGL(k_rename_b, dim3(Gb), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin, w.agg, d_off, w.SA,
