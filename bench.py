@@ -205,7 +205,33 @@ def bench_compress(args, batch, level):
                          + "), oracle compress with one thread per block; GPU stream on the sample bit-identical"}
     config = {"workload": batch.name, "input_bytes": n_in, "blocks": batch.n_blocks, "level": level,
               "output_bytes": out_bytes, "ratio": round(out_bytes / n_in, 4)}
-    return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block)
+    extra = {"host_input": _host_input(args, bz, batch, level)} if args.host_input else None
+    return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extra)
+
+
+def _host_input(args, bz, batch, level):
+    """The same bytes from pinned host memory to streams in pinned host
+    memory (compress_host, 100000*level-byte blocks): uploads, kernels and
+    downloads overlapped over chunks, against one chunk (no overlap).  The
+    host link is inside this rate, so it is never the headline value."""
+    import torch
+    n_in = int(batch.data.size)
+    hx = torch.empty(n_in, dtype=torch.uint8, pin_memory=True)
+    hx.numpy()[:] = batch.data
+    hout = torch.empty(n_in + n_in // 8 + (64 << 20), dtype=torch.uint8, pin_memory=True)
+    res = {"unit": "MB/s", "block_bytes": 100000 * level}
+    for name, chunk in (("overlapped", args.host_chunk_blocks * 100000 * level), ("one_chunk", n_in)):
+        log(f"host input, {name}")
+        bz.compress_host(hx, level=level, chunk_bytes=chunk, out=hout)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            z = bz.compress_host(hx, level=level, chunk_bytes=chunk, out=hout)
+            ts.append(time.perf_counter() - t0)
+        res[name] = round(n_in / min(ts) / 1e6, 2)
+        res[name + "_output_bytes"] = int(z.size)
+    res["chunk_blocks"] = args.host_chunk_blocks
+    return res
 
 
 # ---------------------------------------------------------------- config 3
@@ -332,6 +358,9 @@ def main():
     ap.add_argument("--workers", type=int, default=2)
     ap.add_argument("--max-pass-mib", type=int, default=256)
     ap.add_argument("--host-arrays", action="store_true", help="config 5 requests as pageable host arrays")
+    ap.add_argument("--host-input", action="store_true",
+                    help="configs 1, 2, 4: also time compress_host from pinned host memory (reported beside)")
+    ap.add_argument("--host-chunk-blocks", type=int, default=128, help="blocks per chunk for --host-input")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",

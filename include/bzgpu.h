@@ -233,6 +233,53 @@ int compress_blocks_noalloc(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d
                             uint32_t* d_n_blocks, void* stream);
 
 /*
+ * Precomputed Huffman tables (Sec. 4: the tables may be computed beforehand
+ * by analysing data instead of built per block).  With n_tables = 2..6,
+ * every later compress_blocks / compress_batch / compress_host /
+ * compress_blocks_noalloc / huffman_encode_batch call on this context codes
+ * its blocks with these tables instead of building its own: block b (with
+ * alphabet size a = in-use bytes + 2) uses symbols 0..a-2 of each table as
+ * given and the length of symbol 257 for its end-of-block symbol; each
+ * 50-symbol group takes the table that codes it in the fewest bits (lowest
+ * index on ties).  The four refinement passes and every tree build are
+ * skipped; the stream stays a standard bzip2 stream (the tables are written
+ * into every block as usual).  n_tables = 0 returns to built tables.
+ *   h_lens  n_tables rows of 258 code lengths (row stride 258), each 1..17,
+ *           each row a prefix code (sum of 2^-len at most 1), so that every
+ *           restriction is one too; otherwise BZG_EINVAL.
+ * Synchronous: waits for the device, so work already enqueued keeps the
+ * tables it was enqueued with.  A table set for a kind of data comes from a
+ * sample of it (the Python layer's fixed_tables_from_sample runs the
+ * sample's symbols through this library's own table heuristic).
+ */
+int bzg_set_fixed_tables(bzg_ctx* ctx, const uint8_t* h_lens, int n_tables);
+
+/*
+ * Input in host memory, overlapped with the device work (Sec. 2 and Sec. 4:
+ * the host link, not the kernels, limits a GPU compressor fed from the
+ * host).  The input is cut into blocks of block_bytes (0: 100000*level) and
+ * the blocks into chunks of chunk_bytes (rounded down to whole blocks, at
+ * least one; 0: 128 blocks).  Each chunk becomes one bzip2 stream, identical
+ * to compress_blocks on that chunk's blocks, and the output is the streams
+ * one after another (a multi-stream file, which bzip2 decoders read as one).
+ * Two device buffers alternate: the upload of chunk i+1 and the download of
+ * chunk i-1 run on streams of their own while chunk i is compressed on
+ * `stream`.  A pageable h_in is staged through pinned buffers by the host
+ * thread; a pinned one (hipHostMalloc) is copied directly.
+ *   h_in         n_bytes of input (may be NULL when n_bytes is 0: one empty
+ *                stream).
+ *   h_out        out_cap bytes of output (pinned or pageable).
+ *   h_out_bytes  receives the output length.
+ * Unlike the calls above this one is synchronous: it returns once h_out is
+ * filled (or with an error: BZG_ECAPACITY when the streams do not fit in
+ * out_cap, the device-side errors as bzg_check reports them).  Device
+ * buffers of two chunks and their outputs stay with the context for later
+ * calls; the workspace comes from the context's pool.
+ */
+int compress_host(bzg_ctx* ctx, const uint8_t* h_in, uint64_t n_bytes, uint32_t block_bytes, int level,
+                  uint64_t chunk_bytes, uint8_t* h_out, uint64_t out_cap, uint64_t* h_out_bytes, void* stream);
+
+/*
  * Diagnostics: per-kernel timing.  While enabled, every instrumented launch
  * is bracketed by HIP events on its stream, and the device counts that give
  * its algorithmic bytes (the array traffic the method needs, not what the

@@ -60,6 +60,9 @@ def lib():
         L.ref_split_blocks.argtypes = [u8p, u64p, C.c_uint32, C.c_uint64, u64p, C.c_uint64]
         L.ref_compress.restype = C.c_int64
         L.ref_compress.argtypes = [u8p, u64p, C.c_uint32, C.c_int, u8p, C.c_uint64, u64p, C.c_int]
+        L.ref_compress_fixed.restype = C.c_int64
+        L.ref_compress_fixed.argtypes = [u8p, u64p, C.c_uint32, C.c_int, u8p, C.c_int, u8p, C.c_uint64, u64p,
+                                         C.c_int]
         L.ref_body.restype = C.c_int64
         L.ref_body.argtypes = [u16p, C.c_uint32, u8p, u8p, C.c_uint64, u8p, u8p,
                                C.POINTER(C.c_int)]
@@ -173,8 +176,29 @@ def split_blocks(data, offsets, limit: int) -> np.ndarray:
     return out[:m + 1].copy()
 
 
-def compress(data, offsets=None, level: int = 9, threads: int = 1) -> bytes:
+def tables_from_sample(blocks):
+    """Precomputed tables from sample blocks (see ref.tables_from_sample):
+    every block's symbols through RLE1, BWT and MTF + RUNA/RUNB, mapped to the
+    258-symbol alphabet (EOB -> 257), pooled, and given the table heuristic
+    as one block.  Returns lens uint8[G][258]."""
+    pooled = []
+    for blk in blocks:
+        r1 = rle1(blk)
+        if r1.size == 0:
+            continue
+        _, last, _ = bwt(r1)
+        syms, _, nu, _ = mtf_zrle(last)
+        syms = syms.astype(np.uint16)
+        syms[syms == nu + 1] = MAXA - 1
+        pooled.append(syms)
+    lens, _ = tables(np.concatenate(pooled) if pooled else np.zeros(0, np.uint16), MAXA)
+    return lens
+
+
+def compress(data, offsets=None, level: int = 9, threads: int = 1, fixed=None) -> bytes:
+    """One bzip2 stream; fixed: optional precomputed tables uint8[G][258]."""
     a = _u8(data)
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8).reshape(-1, MAXA)
     if offsets is None:
         bb = 100000 * level
         offsets = list(range(0, a.size, bb)) + [a.size] if a.size else [0]
@@ -184,8 +208,13 @@ def compress(data, offsets=None, level: int = 9, threads: int = 1) -> bytes:
     out = np.zeros(cap, np.uint8)
     need = C.c_uint64(0)
     while True:
-        r = lib().ref_compress(_p(a, C.c_uint8) if a.size else None, _p(offs, C.c_uint64), nb,
-                               level, _p(out, C.c_uint8), cap, C.byref(need), threads)
+        if fx is None:
+            r = lib().ref_compress(_p(a, C.c_uint8) if a.size else None, _p(offs, C.c_uint64), nb,
+                                   level, _p(out, C.c_uint8), cap, C.byref(need), threads)
+        else:
+            r = lib().ref_compress_fixed(_p(a, C.c_uint8) if a.size else None, _p(offs, C.c_uint64), nb,
+                                         level, _p(fx, C.c_uint8), fx.shape[0], _p(out, C.c_uint8), cap,
+                                         C.byref(need), threads)
         if r < 0:
             raise ValueError("oracle compress failed")
         if r > 0:

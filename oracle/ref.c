@@ -394,6 +394,31 @@ typedef struct {
   int err;
 } block_out;
 
+/* Precomputed tables (Sec. 4): lens over the 258 symbols of a block with
+ * every byte in use, g of them.  A block of alphabet a uses symbols
+ * 0..a-2 as they are and takes symbol 257's length for its EOB; each group
+ * picks the cheapest table (lowest index on ties).  No table is built. */
+static int fixed_tables(const uint8_t *fixed, int fg, const uint16_t *syms, uint32_t nsyms, int a,
+                        uint8_t *lens, uint8_t *sel) {
+  for (int t = 0; t < fg; t++)
+    for (int v = 0; v < a; v++) lens[t * MAXA + v] = fixed[t * MAXA + (v == a - 1 ? MAXA - 1 : v)];
+  uint32_t nsel = (nsyms + GRP - 1) / GRP;
+  for (uint32_t j = 0; j < nsel; j++) {
+    uint32_t lo = j * GRP, hi = lo + GRP < nsyms ? lo + GRP : nsyms;
+    uint32_t best = 0, bestc = 0xFFFFFFFFu;
+    for (int t = 0; t < fg; t++) {
+      uint32_t c = 0;
+      for (uint32_t i = lo; i < hi; i++) c += lens[t * MAXA + syms[i]];
+      if (c < bestc) { bestc = c; best = (uint32_t)t; }
+    }
+    sel[j] = (uint8_t)best;
+  }
+  return fg;
+}
+
+static const uint8_t *g_fixed;  /* set for the duration of ref_compress_fixed */
+static int g_fixed_g;
+
 static void encode_one(const uint8_t *raw, uint64_t n, block_out *bo) {
   memset(bo, 0, sizeof(*bo));
   bo->crc = ref_crc32(raw, n);
@@ -413,7 +438,7 @@ static void encode_one(const uint8_t *raw, uint64_t n, block_out *bo) {
   uint8_t lens[MAXG * MAXA];
   uint32_t nsel = (ns + GRP - 1) / GRP;
   uint8_t *sel = (uint8_t *)malloc(nsel);
-  int g = ref_tables(syms, ns, a, lens, sel);
+  int g = g_fixed ? fixed_tables(g_fixed, g_fixed_g, syms, ns, a, lens, sel) : ref_tables(syms, ns, a, lens, sel);
   write_body(&bo->body, used, g, nsel, sel, lens, a, syms, ns);
   free(sel);
 done:
@@ -485,6 +510,20 @@ int64_t ref_compress(const uint8_t *in, const uint64_t *offs0, uint32_t nb0, int
   memcpy(out, w.buf, len);
   free(w.buf);
   return (int64_t)len;
+}
+
+/* ref_compress with precomputed tables (fixed: g x 258 lengths, row
+ * stride 258).  Not reentrant (the tables are held in a file-scope pointer
+ * for the workers). */
+int64_t ref_compress_fixed(const uint8_t *in, const uint64_t *offs0, uint32_t nb0, int level,
+                           const uint8_t *fixed, int g, uint8_t *out, uint64_t out_cap, uint64_t *need,
+                           int threads) {
+  g_fixed = fixed;
+  g_fixed_g = g;
+  int64_t r = ref_compress(in, offs0, nb0, level, out, out_cap, need, threads);
+  g_fixed = NULL;
+  g_fixed_g = 0;
+  return r;
 }
 
 /* Stage entry for tests: the body bits (symbol map .. last code) of one

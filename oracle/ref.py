@@ -501,14 +501,67 @@ def write_block_body(w: BitWriter, used: Sequence[int], lens, sel, syms):
         w.put(codes[t][s], lens[t][s])
 
 
-def encode_block(raw: bytes) -> dict:
-    """All stages for one block; returns every intermediate for tests."""
+# ---------------------------------------------------------------------------
+# Precomputed tables (Sec. 4: tables computed beforehand by analysing data,
+# so that no Huffman tree is built per block).
+# ---------------------------------------------------------------------------
+
+FULL_ALPHA = 258  # RUNA, RUNB, MTF values 1..255, EOB for 256 bytes in use
+
+
+def to_full_alphabet(syms: Sequence[int], alpha_size: int) -> List[int]:
+    """A block's symbols in the alphabet of a block with every byte in use:
+    RUNA, RUNB and MTF values keep their numbers, EOB becomes 257.
+    Reading: precomputed tables are indexed this way."""
+    return [FULL_ALPHA - 1 if s == alpha_size - 1 else s for s in syms]
+
+
+def tables_from_sample(block_syms: Sequence[Tuple[Sequence[int], int]]):
+    """Reading of "chosen by analysing the data": the blocks' symbol streams
+    (each with its alphabet size), in the full alphabet and one after another,
+    get the same table heuristic as one block (choose_tables).  Returns the
+    tables' code lengths over the 258 symbols."""
+    pooled: List[int] = []
+    for syms, a in block_syms:
+        pooled += to_full_alphabet(syms, a)
+    lens, _ = choose_tables(pooled, FULL_ALPHA)
+    return lens
+
+
+def restrict_tables(fixed, alpha_size: int):
+    """The fixed tables as a block of alphabet alpha_size uses them: symbols
+    0..alpha_size-2 keep their lengths, EOB takes the length of symbol 257.
+    A subset of a prefix code's lengths still satisfies Kraft's inequality,
+    so canonical codes of the restriction form a prefix code."""
+    return [[t[v] for v in range(alpha_size - 1)] + [t[FULL_ALPHA - 1]] for t in fixed]
+
+
+def select_fixed(syms: Sequence[int], lens) -> List[int]:
+    """Each 50-symbol group takes the table that codes it in the fewest bits,
+    the lowest index on ties (the selector step of choose_tables, once)."""
+    n_sel = (len(syms) + GROUP - 1) // GROUP
+    sel = []
+    for j in range(n_sel):
+        grp = syms[j * GROUP:(j + 1) * GROUP]
+        costs = [sum(t[s] for s in grp) for t in lens]
+        sel.append(min(range(len(lens)), key=lambda t: (costs[t], t)))
+    return sel
+
+
+def encode_block(raw: bytes, fixed=None) -> dict:
+    """All stages for one block; returns every intermediate for tests.  With
+    `fixed` (precomputed tables over 258 symbols) the tables are not built:
+    the block uses their restriction and only chooses selectors."""
     crc = crc32_bzip2(raw)
     r1 = rle1_encode(raw)
     last, optr = bwt_encode(r1)
     mtf, used = mtf_encode(last)
     syms = zrle_encode(mtf, len(used))
-    lens, sel = choose_tables(syms, len(used) + 2)
+    if fixed is None:
+        lens, sel = choose_tables(syms, len(used) + 2)
+    else:
+        lens = restrict_tables(fixed, len(used) + 2)
+        sel = select_fixed(syms, lens)
     return {"crc": crc, "rle1": r1, "bwt": last, "orig_ptr": optr, "mtf": mtf,
             "used": used, "syms": syms, "lens": lens, "sel": sel}
 
@@ -551,13 +604,14 @@ def split_for_limit(data: bytes, offsets: Sequence[int], limit: int) -> List[int
     return out
 
 
-def compress(data: bytes, level: int = 9, offsets: Sequence[int] | None = None) -> bytes:
+def compress(data: bytes, level: int = 9, offsets: Sequence[int] | None = None, fixed=None) -> bytes:
     """Reading: the header digit is the level; blocks are first cut so that no
-    RLE1 output exceeds 100000 * level (split_for_limit)."""
+    RLE1 output exceeds 100000 * level (split_for_limit).  fixed: optional
+    precomputed tables (lengths over 258 symbols, 2..6 tables)."""
     if offsets is None:
         offsets = cut_blocks(len(data), 100000 * level)
     offsets = split_for_limit(data, offsets, rle1_limit(level))
-    blocks = [encode_block(data[offsets[k]:offsets[k + 1]])
+    blocks = [encode_block(data[offsets[k]:offsets[k + 1]], fixed)
               for k in range(len(offsets) - 1) if offsets[k + 1] > offsets[k]]
     w = BitWriter()
     w.put(ord("B"), 8)

@@ -5,5 +5,6 @@ ABI in include/bzgpu.h.
     from paper_1109_2348_amd import compress, bwt, mtf, huffman
 """
 
-from .native import (BzgError, Compressor, Context, bwt, compress, compress_bound, context, huffman,  # noqa: F401
-                     mtf, uniform_offsets)
+from . import native  # noqa: F401
+from .native import (BzgError, Compressor, Context, bwt, compress, compress_bound, compress_host,  # noqa: F401
+                     context, huffman, mtf, uniform_offsets)

@@ -134,6 +134,20 @@ struct bzg_ctx {
   bool stage_used[2] = {false, false};
   int stage_next = 0;
   void* scratch = nullptr;  // this device's copy of `scratch`
+  // precomputed Huffman tables (bzg_set_fixed_tables): MAXG x MAXA lengths
+  uint8_t* fixed_tab = nullptr;
+  int fixed_g = 0;
+  // compress_host: two input and two output buffers on the device, two
+  // pinned input halves (for pageable inputs), pinned size words, the copy
+  // streams and their events; kept between calls, grown on demand
+  struct HostIo {
+    size_t in_cap = 0, out_cap = 0, pin_cap = 0;
+    uint8_t *din[2] = {nullptr, nullptr}, *dout[2] = {nullptr, nullptr}, *pin[2] = {nullptr, nullptr};
+    uint64_t* dsize = nullptr;  // device: stream sizes of the two buffers
+    uint64_t* hsize = nullptr;  // pinned: their copies
+    hipStream_t up = nullptr, down = nullptr;
+    hipEvent_t in_ev[2] = {nullptr, nullptr}, comp_ev[2] = {nullptr, nullptr}, out_ev[2] = {nullptr, nullptr};
+  } hio;
 };
 
 namespace {
@@ -527,6 +541,8 @@ int compress_enqueue(bzg_ctx* ctx, const CBounds& c, const CWork& w, const uint8
     ha.tiles_cap = c.asg_tiles;
     ha.tile_groups = c.atg;
     ha.ws = w.hws;
+    ha.fixed = ctx->fixed_g ? ctx->fixed_tab : nullptr;
+    ha.fixed_g = ctx->fixed_g;
     HIPX(huff_run(ha, st));
     {
       ProfScope ps("scan", st, 0, w.cnt + PC_GROUPS_LO, 16.0);
@@ -604,6 +620,19 @@ int compress_common(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets
   return end_ws(ctx, d_ws, st);
 }
 
+// The device-side error flags of the calls so far (the work that set them
+// has completed), as a return code; the flags are cleared.
+int status_result(bzg_ctx* ctx) {
+  uint32_t s[4];
+  HIPX(hipMemcpy(s, ctx->status, sizeof(s), hipMemcpyDeviceToHost));
+  if (!s[0]) return 0;
+  HIPX(hipMemset(ctx->status, 0, sizeof(s)));
+  if (s[0] & ERR_BOUND) return fail(ctx, BZG_EINTERNAL, "a device-side count passed its bound; results are not valid");
+  if (s[0] & ERR_SYMBOL)
+    return fail(ctx, BZG_EDATA, "a symbol outside its block's alphabet (or more symbols than the block's capacity)");
+  return fail(ctx, BZG_ECAPACITY, "an output range was too small; nothing was packed");
+}
+
 }  // namespace
 
 extern "C" {
@@ -650,6 +679,7 @@ void bzg_destroy(bzg_ctx* ctx) {
   }
   if (ctx->stage) (void)hipHostFree(ctx->stage);
   if (ctx->crc_tab) (void)hipFree(ctx->crc_tab);
+  if (ctx->fixed_tab) (void)hipFree(ctx->fixed_tab);
   if (ctx->status) (void)hipFree(ctx->status);
   if (ctx->prof.slots) (void)hipFree(ctx->prof.slots);
   if (ctx->pool_ev) (void)hipEventDestroy(ctx->pool_ev);
@@ -659,6 +689,18 @@ void bzg_destroy(bzg_ctx* ctx) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
+  bzg_ctx::HostIo& h = ctx->hio;
+  for (int b = 0; b < 2; b++) {
+    if (h.din[b]) (void)hipFree(h.din[b]);
+    if (h.dout[b]) (void)hipFree(h.dout[b]);
+    if (h.pin[b]) (void)hipHostFree(h.pin[b]);
+    for (hipEvent_t e : {h.in_ev[b], h.comp_ev[b], h.out_ev[b]})
+      if (e) (void)hipEventDestroy(e);
+  }
+  if (h.dsize) (void)hipFree(h.dsize);
+  if (h.hsize) (void)hipHostFree(h.hsize);
+  if (h.up) (void)hipStreamDestroy(h.up);
+  if (h.down) (void)hipStreamDestroy(h.down);
   delete ctx;
 }
 
@@ -670,14 +712,35 @@ int bzg_check(bzg_ctx* ctx, void* stream) {
   ctx->err.clear();
   HIPX(hipSetDevice(ctx->device));
   HIPX(hipStreamSynchronize((hipStream_t)stream));
-  uint32_t s[4];
-  HIPX(hipMemcpy(s, ctx->status, sizeof(s), hipMemcpyDeviceToHost));
-  if (!s[0]) return 0;
-  HIPX(hipMemset(ctx->status, 0, sizeof(s)));
-  if (s[0] & ERR_BOUND) return fail(ctx, BZG_EINTERNAL, "a device-side count passed its bound; results are not valid");
-  if (s[0] & ERR_SYMBOL)
-    return fail(ctx, BZG_EDATA, "a symbol outside its block's alphabet (or more symbols than the block's capacity)");
-  return fail(ctx, BZG_ECAPACITY, "an output range was too small; nothing was packed");
+  return status_result(ctx);
+}
+
+int bzg_set_fixed_tables(bzg_ctx* ctx, const uint8_t* h_lens, int n_tables) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (n_tables == 0) {
+    ctx->fixed_g = 0;
+    return 0;
+  }
+  if (n_tables < 2 || n_tables > MAXG || !h_lens) return fail(ctx, BZG_EINVAL, "2..6 tables of 258 lengths");
+  for (int t = 0; t < n_tables; t++) {
+    uint64_t kraft = 0;  // in units of 2^-MAXLEN
+    for (int v = 0; v < MAXA; v++) {
+      const int l = h_lens[t * MAXA + v];
+      if (l < 1 || l > MAXLEN) return fail(ctx, BZG_EINVAL, "code lengths must be 1..17");
+      kraft += 1ull << (MAXLEN - l);
+    }
+    if (kraft > (1ull << MAXLEN))
+      return fail(ctx, BZG_EINVAL, "table " + std::to_string(t) + " is not a prefix code (Kraft sum above 1)");
+  }
+  HIPX(hipSetDevice(ctx->device));
+  if (!ctx->fixed_tab) HIPX(hipMalloc((void**)&ctx->fixed_tab, MAXG * MAXA));
+  // synchronous: earlier calls that read the old tables have completed first
+  HIPX(hipDeviceSynchronize());
+  HIPX(hipMemcpy(ctx->fixed_tab, h_lens, (size_t)n_tables * MAXA, hipMemcpyHostToDevice));
+  ctx->fixed_g = n_tables;
+  return 0;
 }
 
 int bzg_profile(bzg_ctx* ctx, int enable) {
@@ -979,6 +1042,8 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   ha.count_freq = true;
   ha.sym_off = d_soff;
   ha.ns_eff = w.ns_eff;
+  ha.fixed = ctx->fixed_g ? ctx->fixed_tab : nullptr;
+  ha.fixed_g = ctx->fixed_g;
   HIPX(huff_run(ha, st));
   HIPX(scan_lb_u64(w.gbits, w.cnt + PC_GROUPS_LO, b.groups, 1, w.gstate, ctx->status,
                    persist_grid(scan_dev_tiles(b.groups), ONE_TILE_EACH), st));
@@ -1056,6 +1121,154 @@ int compress_blocks_noalloc(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d
   // no profiling scopes here: they create events
   return compress_common(ctx, d_in, d_offsets, h_offsets, n_blocks, nullptr, nullptr, 1, level, d_out, nullptr,
                          nullptr, out_cap, d_out_bytes, d_n_blocks, ctx->scratch, SCRATCH_BYTES, (hipStream_t)stream);
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------ input in host memory
+
+namespace {
+
+bool is_pinned(const void* p) {
+  hipPointerAttribute_t a{};
+  const bool ok = hipPointerGetAttributes(&a, p) == hipSuccess && a.type == hipMemoryTypeHost;
+  (void)hipGetLastError();  // pageable memory may leave an error behind
+  return ok;
+}
+
+// The buffers of compress_host for chunks of `in_bytes` input and
+// `out_bytes` output (grown when too small; the old ones are idle then,
+// since every call ends synchronised).
+int hio_reserve(bzg_ctx* ctx, size_t in_bytes, size_t out_bytes, bool pin) {
+  bzg_ctx::HostIo& h = ctx->hio;
+  if (!h.up) {
+    HIPX(hipStreamCreateWithFlags(&h.up, hipStreamNonBlocking));
+    HIPX(hipStreamCreateWithFlags(&h.down, hipStreamNonBlocking));
+    for (int b = 0; b < 2; b++) {
+      HIPX(hipEventCreateWithFlags(&h.in_ev[b], hipEventDisableTiming));
+      HIPX(hipEventCreateWithFlags(&h.comp_ev[b], hipEventDisableTiming));
+      HIPX(hipEventCreateWithFlags(&h.out_ev[b], hipEventDisableTiming));
+    }
+    HIPX(hipMalloc((void**)&h.dsize, 2 * sizeof(uint64_t)));
+    HIPX(hipHostMalloc((void**)&h.hsize, 2 * sizeof(uint64_t), hipHostMallocDefault));
+  }
+  for (int b = 0; b < 2; b++) {
+    if (h.in_cap < in_bytes) {
+      if (h.din[b]) HIPX(hipFree(h.din[b]));
+      h.din[b] = nullptr;
+      if (hipMalloc((void**)&h.din[b], in_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, BZG_ENOMEM, "device input buffer");
+      }
+    }
+    if (h.out_cap < out_bytes) {
+      if (h.dout[b]) HIPX(hipFree(h.dout[b]));
+      h.dout[b] = nullptr;
+      if (hipMalloc((void**)&h.dout[b], out_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, BZG_ENOMEM, "device output buffer");
+      }
+    }
+    if (pin && h.pin_cap < in_bytes) {
+      if (h.pin[b]) HIPX(hipHostFree(h.pin[b]));
+      h.pin[b] = nullptr;
+      if (hipHostMalloc((void**)&h.pin[b], in_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, BZG_ENOMEM, "pinned input buffer");
+      }
+    }
+  }
+  h.in_cap = std::max(h.in_cap, in_bytes);
+  h.out_cap = std::max(h.out_cap, out_bytes);
+  if (pin) h.pin_cap = std::max(h.pin_cap, in_bytes);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int compress_host(bzg_ctx* ctx, const uint8_t* h_in, uint64_t n_bytes, uint32_t block_bytes, int level,
+                  uint64_t chunk_bytes, uint8_t* h_out, uint64_t out_cap, uint64_t* h_out_bytes, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  ProfGuard pg(ctx);
+  if (!h_out || !h_out_bytes || (n_bytes && !h_in)) return fail(ctx, BZG_EINVAL, "null pointer");
+  if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
+  if (block_bytes == 0) block_bytes = 100000u * (uint32_t)level;
+  uint64_t per = chunk_bytes ? chunk_bytes / block_bytes : 128;  // blocks per chunk
+  if (per == 0) per = 1;
+  const uint64_t cb = per * block_bytes;
+  if (cb >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "a chunk must hold less than 2^31 bytes");
+  HIPX(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t nc = n_bytes ? (n_bytes + cb - 1) / cb : 1;  // an empty input gives one empty stream
+  const uint64_t cin = std::min<uint64_t>(cb, n_bytes ? n_bytes : 1);
+  const uint64_t cout = compress_bound(cin, (uint32_t)std::min<uint64_t>(per, (cin + block_bytes - 1) / block_bytes));
+  const bool pin_in = n_bytes && !is_pinned(h_in);
+  const bool pin_out = is_pinned(h_out);
+  int rc = hio_reserve(ctx, (cin + 255) & ~uint64_t(255), (cout + 255) & ~uint64_t(255), pin_in);
+  if (rc) return rc;
+  bzg_ctx::HostIo& h = ctx->hio;
+  uint64_t pos = 0;
+  int err = 0;
+  // After chunk j's stream is done: its size, then its copy to the host.
+  auto drain = [&](uint64_t j) -> int {
+    const int b = (int)(j & 1);
+    HIPX(hipEventSynchronize(h.comp_ev[b]));
+    const uint64_t sz = h.hsize[b];
+    if (err || pos + sz > out_cap) {
+      err = BZG_ECAPACITY;
+      return 0;
+    }
+    HIPX(hipStreamWaitEvent(h.down, h.comp_ev[b], 0));
+    HIPX(hipMemcpyAsync(h_out + pos, h.dout[b], sz, hipMemcpyDeviceToHost, h.down));
+    HIPX(hipEventRecord(h.out_ev[b], h.down));
+    if (!pin_out) HIPX(hipEventSynchronize(h.out_ev[b]));
+    pos += sz;
+    return 0;
+  };
+  for (uint64_t i = 0; i < nc; i++) {
+    const int b = (int)(i & 1);
+    const uint64_t lo = i * cb, len = std::min<uint64_t>(cb, n_bytes - std::min(lo, n_bytes));
+    // input: buffer b is free once chunk i - 2 has been compressed
+    if (i >= 2) HIPX(hipStreamWaitEvent(h.up, h.comp_ev[b], 0));
+    if (len) {
+      const uint8_t* src = h_in + lo;
+      if (pin_in) {  // staged: the pinned half is free once its last copy is done
+        if (i >= 2) HIPX(hipEventSynchronize(h.in_ev[b]));
+        memcpy(h.pin[b], src, len);
+        src = h.pin[b];
+      }
+      HIPX(hipMemcpyAsync(h.din[b], src, len, hipMemcpyHostToDevice, h.up));
+    }
+    HIPX(hipEventRecord(h.in_ev[b], h.up));
+    // compress chunk i into output buffer b (free once chunk i - 2's copy is done)
+    HIPX(hipStreamWaitEvent(st, h.in_ev[b], 0));
+    if (i >= 2) HIPX(hipStreamWaitEvent(st, h.out_ev[b], 0));
+    std::vector<uint64_t> off;
+    for (uint64_t o = 0; o < len; o += block_bytes) off.push_back(o);
+    off.push_back(len);
+    const uint32_t nblk = (uint32_t)off.size() - 1;
+    rc = compress_common(ctx, h.din[b], nullptr, off.data(), nblk, nullptr, nullptr, 1, level, h.dout[b], nullptr,
+                         nullptr, cout & ~uint64_t(3), h.dsize + b, nullptr, nullptr, 0, st);
+    if (rc) {
+      (void)hipStreamSynchronize(st);
+      return rc;
+    }
+    HIPX(hipMemcpyAsync(h.hsize + b, h.dsize + b, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPX(hipEventRecord(h.comp_ev[b], st));
+    if (i >= 1 && (rc = drain(i - 1))) return rc;
+  }
+  if ((rc = drain(nc - 1))) return rc;
+  HIPX(hipStreamSynchronize(h.down));
+  HIPX(hipStreamSynchronize(st));
+  if ((rc = status_result(ctx))) return rc;
+  if (err) return fail(ctx, err, "output capacity too small for the streams");
+  *h_out_bytes = pos;
+  return 0;
 }
 
 }  // extern "C"

@@ -250,6 +250,43 @@ __global__ __launch_bounds__(NT) void k_huff_setup(const uint32_t* __restrict__ 
   for (int i = threadIdx.x; i < MAXG * MAXA; i += NT) tf[(size_t)b * MAXG * MAXA + i] = 0;
 }
 
+// Precomputed tables (Sec. 4: tables made beforehand from data, so no tree
+// is built per block): block b takes the fixed_g given tables restricted to
+// its alphabet -- symbols 0..a-2 as they are, EOB (a-1) with the length of
+// symbol MAXA-1, the EOB of a block with every byte in use.  The selectors
+// are then chosen once (k_huff_assign mode 0) and no table is rebuilt.
+__global__ __launch_bounds__(NT) void k_huff_fixed_setup(const uint32_t* __restrict__ nsyms,
+                                                         const uint32_t* __restrict__ inuse,
+                                                         BlockTables* __restrict__ tabs, uint32_t* __restrict__ tf,
+                                                         const uint64_t* __restrict__ sel_base,
+                                                         uint64_t* __restrict__ gbits,
+                                                         const uint8_t* __restrict__ fixed, int fixed_g) {
+  const uint32_t b = blockIdx.x;
+  BlockTables* T = &tabs[b];
+  uint32_t nu = 0;
+  for (int j = 0; j < 8; j++) nu += __popc(inuse[b * 8 + j]);
+  const int a = (int)nu + 2;
+  const uint32_t ns = nsyms[b];
+  const int G = ns ? fixed_g : 0;
+  {
+    const uint64_t gb0 = sel_base[b] + (ns + GROUP - 1) / GROUP, gb1 = sel_base[b + 1];
+    for (uint64_t g = gb0 + threadIdx.x; g < gb1; g += NT) gbits[g] = 0;
+    if (b + 1 == gridDim.x && threadIdx.x == 0) gbits[gb1] = 0;
+  }
+  if (threadIdx.x == 0) {
+    T->G = (uint32_t)G;
+    T->nsel = G ? (ns + GROUP - 1) / GROUP : 0;
+    T->alpha = (uint32_t)a;
+    T->data_bits = 0;
+    T->hdr_bits = 0;
+  }
+  for (int i = threadIdx.x; i < G * MAXA; i += NT) {
+    const int t = i / MAXA, v = i % MAXA;
+    if (v < a) T->len[t][v] = fixed[t * MAXA + (v == a - 1 ? MAXA - 1 : v)];
+  }
+  for (int i = threadIdx.x; i < MAXG * MAXA; i += NT) tf[(size_t)b * MAXG * MAXA + i] = 0;
+}
+
 // Tile of tg groups of one block.  mode 0: choose tables and count
 // symbols per table; mode 1: data bits of every group under the final tables.
 __device__ void huff_assign_tile(uint32_t j, int mode, const uint32_t* __restrict__ tile_blk,
@@ -613,7 +650,8 @@ size_t huff_workspace_bytes(uint32_t nb) {
 
 // The Huffman stage of nb blocks (some possibly empty): counts (when
 // a.count_freq: symbols given by the caller, validated), four passes of
-// table assignment and build, the final data bits, codes and selectors.
+// table assignment and build (with precomputed tables: one assignment),
+// the final data bits, codes and selectors.
 hipError_t huff_run(const HuffArgs& a, hipStream_t st) {
   if (!a.nb) return hipSuccess;
   BlockTables* tabs = (BlockTables*)a.tabs;
@@ -628,18 +666,25 @@ hipError_t huff_run(const HuffArgs& a, hipStream_t st) {
   const uint32_t g = persist_grid(a.tiles_cap, ONE_TILE_EACH);
   const int clamp = a.count_freq ? 1 : 0;
   // symbol counts are known on the device only: no algorithmic bytes recorded
-  {
+  if (a.fixed) {
+    ProfScope ps("huff_setup", st, 0.0);
+    hipLaunchKernelGGL(k_huff_fixed_setup, dim3(a.nb), dim3(NT), 0, st, nsyms, a.inuse, tabs, tf, a.sel_base, a.gbits,
+                       a.fixed, a.fixed_g);
+  } else {
     ProfScope ps("huff_setup", st, 0.0);
     hipLaunchKernelGGL(k_huff_setup, dim3(a.nb), dim3(NT), 0, st, nsyms, a.freq, a.inuse, tabs, cost, tf, a.sel_base,
                        a.gbits);
   }
-  for (int it = 0; it < 4; it++) {
+  // precomputed tables: one selector pass and no rebuild
+  const int passes = a.fixed ? 1 : 4;
+  for (int it = 0; it < passes; it++) {
     {
       ProfScope ps("huff_assign", st, 0.0);
       hipLaunchKernelGGL(k_huff_assign, dim3(g), dim3(NT), 0, st, 0, a.tile_blk, a.blk_tile0, a.syms, a.sym_base,
                          nsyms, a.sel_base, a.sel, (const uint64_t*)cost, tf, a.gbits, tabs, a.tile_groups, a.n_tiles,
                          a.tiles_cap, clamp);
     }
+    if (a.fixed) break;
     ProfScope ps("huff_build", st, 0.0);
     hipLaunchKernelGGL(k_huff_build, dim3(a.nb, MAXG), dim3(BUILD_NT), 0, st, tabs, tf);
   }

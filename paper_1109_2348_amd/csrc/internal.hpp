@@ -247,6 +247,8 @@ struct HuffArgs {
   const uint32_t *tile_blk, *blk_tile0, *n_tiles;  // assign tile map (device count)
   uint32_t tiles_cap, tile_groups;
   void* ws;  // huff_workspace_bytes(nb)
+  const uint8_t* fixed = nullptr;  // precomputed tables (fixed_g x MAXA lengths) or null
+  int fixed_g = 0;
   bool count_freq;           // symbols come from the caller: count and validate them
   const uint64_t* sym_off;   // (count_freq) nb + 1 symbol capacity offsets
   uint32_t* ns_eff;          // (count_freq) nb counts clamped to the capacities

@@ -63,6 +63,8 @@ def lib() -> C.CDLL:
         L.compress_batch.argtypes = [vp, vp, vp, u64p, u32, vp, u32p, u32, i, vp, vp, u64p, vp, vp, sz, vp]
         L.compress_blocks_noalloc.restype = i
         L.compress_blocks_noalloc.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp]
+        L.compress_host.restype = i
+        L.compress_host.argtypes = [vp, vp, u64, u32, i, u64, vp, u64, C.POINTER(C.c_uint64), vp]
         L.bzg_profile.restype = i
         L.bzg_profile.argtypes = [vp, i]
         L.bzg_profile_read.restype = i
@@ -73,7 +75,7 @@ def lib() -> C.CDLL:
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_check", "bzg_workspace_size", "bzg_compress_bound",
            "bwt_forward_batch", "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch",
-           "compress_blocks_noalloc", "bzg_profile", "bzg_profile_read")
+           "compress_blocks_noalloc", "compress_host", "bzg_profile", "bzg_profile_read")
 
 
 class Profile:
@@ -358,3 +360,36 @@ class BatchCompressor:
 def compress_batch(x: torch.Tensor, offsets, req_blocks, level: int = 9):
     """One bzip2 stream per request (list of uint8 tensors on x's device)."""
     return [z.clone() for z in BatchCompressor(x.device.index)(x, offsets, req_blocks, level)]
+
+
+def compress_host(data, level: int = 9, block_bytes: Optional[int] = None, chunk_bytes: Optional[int] = None,
+                  out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> np.ndarray:
+    """Compresses input that lives in host memory (bytes, a numpy array or a
+    CPU tensor, pinned or not) chunk by chunk with the uploads, the kernels
+    and the downloads overlapped; one bzip2 stream per chunk, concatenated.
+    out: optional CPU uint8 tensor for the result (pinned for an overlapped
+    download).  Returns a numpy view of the output."""
+    if isinstance(data, torch.Tensor):
+        if data.is_cuda or data.dtype != torch.uint8:
+            raise TypeError("expected a uint8 tensor in host memory")
+        src = data.contiguous()
+        ptr, n = src.data_ptr(), src.numel()
+    else:
+        src = np.ascontiguousarray(np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray))
+                                   else np.asarray(data, dtype=np.uint8)).reshape(-1)
+        ptr, n = src.ctypes.data, src.size
+    ctx = ctx or context()
+    bb = block_bytes or 100000 * level
+    blocks = max(1, -(-n // bb))
+    cap = compress_bound(n, blocks) + 64 * (blocks + 1) + 64
+    if out is None:
+        out = torch.empty(cap, dtype=torch.uint8)
+    elif out.is_cuda or out.dtype != torch.uint8 or out.numel() < 1:
+        raise TypeError("out must be a uint8 tensor in host memory")
+    got = C.c_uint64(0)
+    dev = torch.device("cuda", ctx.device)
+    ctx.check(lib().compress_host(ctx.h, C.c_void_p(ptr) if n else None, n, block_bytes or 0, level,
+                                  chunk_bytes or 0, C.c_void_p(out.data_ptr()), out.numel(), C.byref(got),
+                                  _stream(dev)))
+    return out[: got.value].numpy()
+
