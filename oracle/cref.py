@@ -176,22 +176,26 @@ def split_blocks(data, offsets, limit: int) -> np.ndarray:
     return out[:m + 1].copy()
 
 
+SAMPLE_SYMS = 900000
+
+
 def tables_from_sample(blocks):
     """Precomputed tables from sample blocks (see ref.tables_from_sample):
-    every block's symbols through RLE1, BWT and MTF + RUNA/RUNB, mapped to the
-    258-symbol alphabet (EOB -> 257), pooled, and given the table heuristic
-    as one block.  Returns lens uint8[G][258]."""
+    every block's symbols through BWT and MTF + RUNA/RUNB (no RLE1), mapped
+    to the 258-symbol alphabet (EOB -> 257), pooled, cut to the first
+    SAMPLE_SYMS, and given the table heuristic as one block.  Returns lens
+    uint8[G][258]."""
     pooled = []
     for blk in blocks:
-        r1 = rle1(blk)
-        if r1.size == 0:
+        if len(blk) == 0:
             continue
-        _, last, _ = bwt(r1)
+        _, last, _ = bwt(blk)
         syms, _, nu, _ = mtf_zrle(last)
         syms = syms.astype(np.uint16)
-        syms[syms == nu + 1] = MAXA - 1
+        syms[-1] = MAXA - 1  # EOB
         pooled.append(syms)
-    lens, _ = tables(np.concatenate(pooled) if pooled else np.zeros(0, np.uint16), MAXA)
+    allsyms = np.concatenate(pooled)[:SAMPLE_SYMS] if pooled else np.zeros(0, np.uint16)
+    lens, _ = tables(allsyms, MAXA)
     return lens
 
 

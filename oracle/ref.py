@@ -516,15 +516,27 @@ def to_full_alphabet(syms: Sequence[int], alpha_size: int) -> List[int]:
     return [FULL_ALPHA - 1 if s == alpha_size - 1 else s for s in syms]
 
 
+SAMPLE_SYMS = 900000  # symbols a sample contributes at most (about one block's worth)
+
+
+def sample_symbols(block: bytes) -> Tuple[List[int], int]:
+    """A sample block's symbols: BWT, MTF and RUNA/RUNB of the block as
+    given (Reading: no RLE1 in the analysis), with its alphabet size."""
+    last, _ = bwt_encode(block)
+    mtf, used = mtf_encode(last)
+    return zrle_encode(mtf, len(used)), len(used) + 2
+
+
 def tables_from_sample(block_syms: Sequence[Tuple[Sequence[int], int]]):
     """Reading of "chosen by analysing the data": the blocks' symbol streams
     (each with its alphabet size), in the full alphabet and one after another,
-    get the same table heuristic as one block (choose_tables).  Returns the
-    tables' code lengths over the 258 symbols."""
+    cut to the first SAMPLE_SYMS symbols, get the same table heuristic as one
+    block (choose_tables).  Returns the tables' code lengths over the 258
+    symbols."""
     pooled: List[int] = []
     for syms, a in block_syms:
         pooled += to_full_alphabet(syms, a)
-    lens, _ = choose_tables(pooled, FULL_ALPHA)
+    lens, _ = choose_tables(pooled[:SAMPLE_SYMS], FULL_ALPHA)
     return lens
 
 

@@ -317,7 +317,7 @@ int upload(bzg_ctx* ctx, std::initializer_list<Upload> ups, hipStream_t st) {
 // Host bounds of a compress call, from the input offsets alone.
 struct CBounds {
   uint32_t nb = 0, nslot = 0, L = 0;
-  bool direct = true;  // no block can need cutting: one slot per block
+  bool direct = true;  // every block is one slot (none empty, none that may need cutting)
   uint64_t total = 0;
   uint32_t in_tiles = 0, slot_tiles = 0, rows = 0, max_len = 0, sort_tiles = 0, mtf_ch = 0, chunks = 0;
   uint32_t groups = 0, atg = 0, asg_tiles = 0, pack_tiles = 0;
@@ -342,7 +342,9 @@ CBounds compress_bounds(const uint64_t* h_off, uint32_t nb, int level, const uin
     const uint64_t n = h_off[k + 1] - h_off[k];
     const uint32_t pm = max_pieces(n, c.L);
     c.nslot += pm;
-    if (pm > 1) c.direct = false;
+    // slots are then the input blocks themselves; an empty block has no slot,
+    // so it takes the planned path too
+    if (pm != 1) c.direct = false;
     if (pm > 1) c.in_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE);
     c.slot_tiles += (uint32_t)((n + RLE_TILE - 1) / RLE_TILE) + (pm ? pm - 1 : 0);
     const uint64_t r = std::min<uint64_t>(n + n / 4, (uint64_t)pm * c.L);

@@ -63,6 +63,8 @@ def lib() -> C.CDLL:
         L.compress_batch.argtypes = [vp, vp, vp, u64p, u32, vp, u32p, u32, i, vp, vp, u64p, vp, vp, sz, vp]
         L.compress_blocks_noalloc.restype = i
         L.compress_blocks_noalloc.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp]
+        L.bzg_set_fixed_tables.restype = i
+        L.bzg_set_fixed_tables.argtypes = [vp, vp, i]
         L.compress_host.restype = i
         L.compress_host.argtypes = [vp, vp, u64, u32, i, u64, vp, u64, C.POINTER(C.c_uint64), vp]
         L.bzg_profile.restype = i
@@ -75,7 +77,8 @@ def lib() -> C.CDLL:
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_check", "bzg_workspace_size", "bzg_compress_bound",
            "bwt_forward_batch", "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch",
-           "compress_blocks_noalloc", "compress_host", "bzg_profile", "bzg_profile_read")
+           "compress_blocks_noalloc", "compress_host", "bzg_set_fixed_tables", "bzg_profile",
+           "bzg_profile_read")
 
 
 class Profile:
@@ -128,6 +131,17 @@ class Context:
     def sync_check(self, stream: C.c_void_p):
         """Waits for the stream and raises the errors the kernels recorded."""
         self.check(lib().bzg_check(self.h, stream))
+
+    def set_fixed_tables(self, lens: Optional[np.ndarray]):
+        """Precomputed Huffman tables (G x 258 code lengths, G = 2..6) for
+        every later call on this context; None returns to built tables."""
+        if lens is None:
+            self.check(lib().bzg_set_fixed_tables(self.h, None, 0))
+            return
+        a = np.ascontiguousarray(np.asarray(lens, dtype=np.uint8))
+        if a.ndim != 2 or a.shape[1] != 258:
+            raise ValueError("expected a G x 258 array of code lengths")
+        self.check(lib().bzg_set_fixed_tables(self.h, C.c_void_p(a.ctypes.data), a.shape[0]))
 
     def workspace_size(self, call: int, offsets, n_blocks: Optional[int] = None, level: int = 9,
                        n_req: int = 1) -> int:
@@ -252,6 +266,42 @@ def huffman(syms: torch.Tensor, nsyms: torch.Tensor, inuse: torch.Tensor, sym_of
     if check:
         ctx.sync_check(st)
     return out, oo, nbits[:nb], tabs
+
+
+SAMPLE_SYMS = 900_000  # symbols a table sample contributes at most
+
+
+def fixed_tables_from_sample(x: torch.Tensor, offsets, ctx: Optional[Context] = None) -> np.ndarray:
+    """Precomputed Huffman tables from sample blocks on the GPU: the blocks'
+    BWT and MTF + RUNA/RUNB symbols (no RLE1), mapped to the alphabet of a
+    block with every byte in use (each block's EOB becomes 257), pooled and
+    cut to the first SAMPLE_SYMS symbols, then this library's table
+    heuristic on them as one block.  Returns uint8[G][258] for
+    Context.set_fixed_tables.  ctx must not have fixed tables set."""
+    x = _dev_u8(x)
+    o = _offs(offsets)
+    ctx = ctx or context(x.device.index)
+    L, _, _ = bwt(x, o, ctx=ctx)
+    syms, nsyms, _ = mtf(L, o, ctx=ctx)
+    ns = nsyms.cpu().numpy().astype(np.int64)
+    nb = o.size - 1
+    starts = o[:-1].astype(np.int64) + np.arange(nb)
+    keep = ns > 0
+    idx = np.concatenate([np.arange(a, a + n) for a, n in zip(starts[keep], ns[keep])]) if keep.any() \
+        else np.zeros(0, np.int64)
+    eob = np.cumsum(ns[keep]) - 1
+    pooled = syms[torch.from_numpy(idx).to(x.device)].clone()
+    pooled[torch.from_numpy(eob).to(x.device)] = 257
+    pooled = pooled[:SAMPLE_SYMS].contiguous()
+    total = int(pooled.numel())
+    if total == 0:
+        raise ValueError("the sample holds no symbols")
+    cnt = torch.tensor([total], dtype=torch.int32, device=x.device)
+    inuse = torch.full((32,), 0xFF, dtype=torch.uint8, device=x.device)
+    _, _, _, tabs = huffman(pooled, cnt, inuse, [0, total], want_tables=True, ctx=ctx)
+    t = tabs.cpu().numpy()
+    g = int(t[0])
+    return t[16:16 + 258 * g].reshape(g, 258).copy()
 
 
 def compress_bound(n_bytes: int, n_blocks: int) -> int:

@@ -85,11 +85,7 @@ def test_tables_from_sample_tiers_agree():
     data, offs = _data(8000, 2000, seed=14)
     blocks = [data[offs[k]:offs[k + 1]] for k in range(len(offs) - 1)]
     c = cref.tables_from_sample(blocks)
-    per = []
-    for blk in blocks:
-        enc = ref.encode_block(blk.tobytes())
-        per.append((enc["syms"], len(enc["used"]) + 2))
-    t = ref.tables_from_sample(per)
+    t = ref.tables_from_sample([ref.sample_symbols(blk.tobytes()) for blk in blocks])
     assert [list(map(int, r)) for r in c] == [list(r) for r in t]
     assert all(1 <= x <= 17 for r in t for x in r)
     assert all(abs(_kraft(r) - 1.0) < 1e-12 for r in t)

@@ -297,6 +297,17 @@ def test_compress_uneven_blocks(bz):
     assert bz2.decompress(z) == b.data.tobytes()
 
 
+@pytest.mark.parametrize("level", [9, 5])
+def test_compress_empty_blocks_without_cuts(bz, level):
+    # no block needs cutting at these levels, and empty blocks sit at the
+    # front, in the middle and at the end: every non-empty block must stay
+    b = W.config2(total=6 * 80000 + 777, block=80000, seed=23)
+    o = [int(x) for x in b.offsets]
+    offs = [0, 0] + o[1:4] + [o[3]] + o[4:] + [o[-1], o[-1]]
+    z = _check_compress(bz, b.data, offs, level, f"empty blocks among {len(o) - 1} uncut blocks, level {level}")
+    assert bz2.decompress(z) == b.data.tobytes()
+
+
 def test_compress_rejects_bad_args(bz):
     x = _dev(np.zeros(10, np.uint8))
     with pytest.raises(bz.BzgError):
