@@ -280,6 +280,34 @@ int compress_host(bzg_ctx* ctx, const uint8_t* h_in, uint64_t n_bytes, uint32_t 
                   uint64_t chunk_bytes, uint8_t* h_out, uint64_t out_cap, uint64_t* h_out_bytes, void* stream);
 
 /*
+ * Decompression on the GPU: one bzip2 stream, or several one after another,
+ * back to the original bytes.  Every stage runs on the device: the block
+ * and end-of-stream markers are found by a bit-parallel search; each block's
+ * Huffman codes, RUNA/RUNB runs and move-to-front list are decoded by one
+ * wave (code boundaries are only known serially, Sec. 3.4; the list step is
+ * a constant-time lookup, Sec. 3.3); the inverse BWT starts walks of the
+ * last-to-first map from many sampled rows and places their pieces by the
+ * chain of samples (Sec. 3.1); RLE1 is undone in the Figure 2 pattern (per
+ * segment lengths under each incoming state, a scan, then the expansion,
+ * Sec. 3.2); every block CRC and stream CRC is checked.
+ *   d_in, n_bytes  the compressed bytes (device memory).  Bytes after the
+ *                  last stream that do not start another stream are ignored.
+ *   d_out          out_cap bytes for the decoded data.
+ *   d_out_bytes    device uint64 output: the decoded length.  When it
+ *                  exceeds out_cap, nothing is written and bzg_check reports
+ *                  BZG_ECAPACITY (*d_out_bytes still holds the length).
+ * Unlike the compression calls, this one waits once for the device: the
+ * host reads the marker list back to lay the blocks out (and returns
+ * BZG_EDATA at once when the input is not a bzip2 stream); the decoding
+ * itself is enqueued on `stream` and the call returns without waiting for
+ * it.  A stream that does not decode (a bad code, a block that does not end
+ * at the next marker, a CRC mismatch, a randomised block) is reported as
+ * BZG_EDATA by bzg_check.  The workspace comes from the context's pool.
+ */
+int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_out, uint64_t out_cap,
+               uint64_t* d_out_bytes, void* stream);
+
+/*
  * Diagnostics: per-kernel timing.  While enabled, every instrumented launch
  * is bracketed by HIP events on its stream, and the device counts that give
  * its algorithmic bytes (the array traffic the method needs, not what the

@@ -630,6 +630,8 @@ int status_result(bzg_ctx* ctx) {
   if (!s[0]) return 0;
   HIPX(hipMemset(ctx->status, 0, sizeof(s)));
   if (s[0] & ERR_BOUND) return fail(ctx, BZG_EINTERNAL, "a device-side count passed its bound; results are not valid");
+  if (s[0] & ERR_STREAM)
+    return fail(ctx, BZG_EDATA, "a compressed stream does not decode (corrupt, or a form this decoder does not read)");
   if (s[0] & ERR_SYMBOL)
     return fail(ctx, BZG_EDATA, "a symbol outside its block's alphabet (or more symbols than the block's capacity)");
   return fail(ctx, BZG_ECAPACITY, "an output range was too small; nothing was packed");
@@ -1273,4 +1275,219 @@ int compress_host(bzg_ctx* ctx, const uint8_t* h_in, uint64_t n_bytes, uint32_t 
   return 0;
 }
 
+
 }  // extern "C"
+
+// ------------------------------------------------------------ decompression
+
+namespace {
+
+struct Stream {
+  uint32_t b0, crc;
+};
+
+// The block layout of the input from its markers (bit position | end-marker
+// flag << 63, the 32 bits after it | for end markers the 4 bytes where the
+// next stream's header would start << 32): streams one after another, each
+// "BZh" + level digit, blocks, end marker and CRC, padded to a byte.  Bytes
+// after the last stream that do not start a stream header are ignored.
+int lay_out_blocks(bzg_ctx* ctx, const std::vector<uint64_t>& cand, uint32_t first4, uint64_t n_bytes,
+                   std::vector<DecBlk>& blocks, std::vector<Stream>& streams) {
+  const size_t m = cand.size() / 2;
+  uint64_t hb = 0;
+  uint32_t hdr = first4;
+  size_t i = 0;
+  for (;;) {
+    const uint32_t digit = hdr & 255u;
+    if ((hdr >> 8) != 0x425A68u || digit < '1' || digit > '9') {
+      if (streams.empty()) return fail(ctx, BZG_EDATA, "not a bzip2 stream (no BZh header)");
+      break;
+    }
+    const uint32_t level = digit - '0';
+    const uint64_t expect = hb * 8 + 32;
+    if (i >= m || (cand[2 * i] & ~(1ull << 63)) != expect)
+      return fail(ctx, BZG_EDATA, "no block or end marker right after the stream header at byte " + std::to_string(hb));
+    Stream s{(uint32_t)blocks.size(), 0};
+    for (;;) {
+      if (i >= m) return fail(ctx, BZG_EDATA, "a stream without its end marker");
+      const uint64_t pos = cand[2 * i] & ~(1ull << 63);
+      const bool eos = cand[2 * i] >> 63;
+      if (eos) {
+        s.crc = (uint32_t)cand[2 * i + 1];
+        hb = (pos + 80 + 7) / 8;
+        hdr = (uint32_t)(cand[2 * i + 1] >> 32);
+        i++;
+        break;
+      }
+      if (i + 1 >= m) return fail(ctx, BZG_EDATA, "a block without a following marker");
+      DecBlk d{};
+      d.start = pos + 48;
+      d.end = cand[2 * (i + 1)] & ~(1ull << 63);
+      d.cap = 100000u * level;
+      blocks.push_back(d);
+      i++;
+    }
+    streams.push_back(s);
+    if (hb + 4 > n_bytes) break;
+    while (i < m && (cand[2 * i] & ~(1ull << 63)) < hb * 8 + 32) i++;  // (none expected)
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_out, uint64_t out_cap,
+               uint64_t* d_out_bytes, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  ProfGuard pg(ctx);
+  if (!d_out_bytes || !d_in || (out_cap && !d_out)) return fail(ctx, BZG_EINVAL, "null pointer");
+  if (n_bytes < 14) return fail(ctx, BZG_EDATA, "input shorter than the smallest bzip2 stream");
+  HIPX(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // markers: counted per tile, then written in order; the host reads them back
+  const uint64_t tiles = dec_find_tiles(n_bytes);
+  if (tiles >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "input too large");
+  uint64_t count = 0;
+  std::vector<uint64_t> cand;
+  uint32_t first4 = 0;
+  for (int round = 0; round < 2; round++) {
+    Carve cv{nullptr};
+    (void)cv.take<uint32_t>(tiles);
+    (void)cv.take<uint64_t>(tiles + 1);
+    (void)cv.take<uint64_t>(2 * count + 2);
+    void* ws;
+    int rc = get_ws(ctx, nullptr, 0, cv.used + 256, st, &ws);
+    if (rc) return rc;
+    Carve c2{(char*)ws};
+    uint32_t* tile_cnt = c2.take<uint32_t>(tiles);
+    uint64_t* tile_off = c2.take<uint64_t>(tiles + 1);
+    uint64_t* dcand = c2.take<uint64_t>(2 * count + 2);
+    HIPX(dec_find(d_in, n_bytes, 0, tile_cnt, nullptr, nullptr, 0, st));
+    HIPX(dec_scan_counts(tile_cnt, (uint32_t)tiles, tile_off, st));
+    if (round == 0) {
+      HIPX(hipMemcpyAsync(&count, tile_off + tiles, sizeof(count), hipMemcpyDeviceToHost, st));
+      HIPX(hipMemcpyAsync(&first4, d_in, 4, hipMemcpyDeviceToHost, st));
+      if ((rc = end_ws(ctx, nullptr, st))) return rc;
+      HIPX(hipStreamSynchronize(st));
+      if (count == 0) return fail(ctx, BZG_EDATA, "no block or end marker found");
+      if (count > (1ull << 26)) return fail(ctx, BZG_EDATA, "implausibly many markers");
+      continue;
+    }
+    HIPX(dec_find(d_in, n_bytes, 1, tile_cnt, tile_off, dcand, count, st));
+    cand.resize(2 * count);
+    HIPX(hipMemcpyAsync(cand.data(), dcand, 16 * count, hipMemcpyDeviceToHost, st));
+    if ((rc = end_ws(ctx, nullptr, st))) return rc;
+    HIPX(hipStreamSynchronize(st));
+  }
+  first4 = __builtin_bswap32(first4);
+  std::vector<DecBlk> blocks;
+  std::vector<Stream> streams;
+  int rc = lay_out_blocks(ctx, cand, first4, n_bytes, blocks, streams);
+  if (rc) return rc;
+  const uint32_t nb = (uint32_t)blocks.size(), ns = (uint32_t)streams.size();
+  if (nb >= (1u << 24)) return fail(ctx, BZG_EINVAL, "too many blocks");
+  // per block: BWT column, text and map ranges, walker and segment slots
+  std::vector<uint64_t> walk0(nb + 1, 0), rle0(nb + 1, 0);
+  std::vector<uint32_t> sb0(ns + 1, 0), scrc(ns, 0);
+  uint64_t lsum = 0;
+  for (uint32_t b = 0; b < nb; b++) {
+    blocks[b].l_off = lsum;
+    lsum += blocks[b].cap;
+    walk0[b + 1] = walk0[b] + dec_walk_slots(blocks[b].cap);
+    rle0[b + 1] = rle0[b] + dec_rle_slots(blocks[b].cap);
+  }
+  for (uint32_t k = 0; k < ns; k++) {
+    sb0[k] = streams[k].b0;
+    scrc[k] = streams[k].crc;
+  }
+  sb0[ns] = nb;
+  if (nb == 0) {  // empty streams only: their CRCs must be 0
+    for (uint32_t k = 0; k < ns; k++)
+      if (scrc[k]) return fail(ctx, BZG_EDATA, "an empty stream with a non-zero CRC");
+    const uint64_t zero = 0;
+    return upload(ctx, {{d_out_bytes, &zero, 8}}, st);
+  }
+  const uint64_t wt = walk0[nb], rt = rle0[nb];
+  const uint64_t tcap = out_cap / RLE_TILE + nb + 1;
+  if (tcap >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "out_cap too large");
+  DecRun d{};
+  auto carve = [&](char* base, DecRun& r, uint32_t** misc) -> size_t {
+    Carve cv{base};
+    r.blks = cv.take<DecBlk>(nb);
+    r.walk0 = cv.take<uint64_t>(nb + 1);
+    r.rle0 = cv.take<uint64_t>(nb + 1);
+    misc[0] = cv.take<uint32_t>(ns + 1);  // stream first blocks
+    misc[1] = cv.take<uint32_t>(ns + 1);  // stream CRCs
+    r.L = cv.take<uint8_t>(lsum + 64);
+    r.T = cv.take<uint8_t>(lsum + 64);
+    r.FL = cv.take<uint32_t>(lsum + 16);
+    r.sel = cv.take<uint8_t>((size_t)nb * dec_sel_stride());
+    r.n_rows = cv.take<uint32_t>(nb);
+    r.orig = cv.take<uint32_t>(nb);
+    r.crc_want = cv.take<uint32_t>(nb);
+    r.period = cv.take<uint32_t>(nb);
+    r.out_len = cv.take<uint32_t>(nb);
+    r.hist = cv.take<uint32_t>((size_t)nb * 256);
+    r.nxt = cv.take<uint32_t>(wt);
+    r.steps = cv.take<uint32_t>(wt);
+    r.pos = cv.take<uint32_t>(wt);
+    r.summ = cv.take<uint64_t>(rt * 5);
+    r.seg_in = cv.take<uint32_t>(rt);
+    r.seg_off = cv.take<uint32_t>(rt);
+    r.out_off = cv.take<uint64_t>(nb + 1);
+    r.skip = cv.take<uint32_t>(4);
+    misc[2] = cv.take<uint32_t>(nb + 1);      // CRC tiles: first tile per block
+    misc[3] = cv.take<uint32_t>(PC_COUNT);    // tile count
+    misc[4] = cv.take<uint32_t>(tcap + 1);    // tile -> block
+    misc[5] = (uint32_t*)cv.take<char>(rle_tile_bytes() * (tcap + 1));
+    misc[6] = cv.take<uint32_t>(tcap + 1);    // (run starts, unused here)
+    misc[7] = cv.take<uint32_t>(tcap + 1);    // (RLE1 offsets, unused here)
+    misc[8] = cv.take<uint32_t>(nb);          // (RLE1 lengths, unused here)
+    misc[9] = cv.take<uint32_t>(nb);          // CRC of each decoded block
+    return cv.used + 256;
+  };
+  uint32_t* misc[10];
+  const size_t need = carve(nullptr, d, misc);
+  void* ws;
+  if ((rc = get_ws(ctx, nullptr, 0, need, st, &ws))) return rc;
+  carve((char*)ws, d, misc);
+  if ((rc = upload(ctx,
+                   {{(void*)d.blks, blocks.data(), nb * sizeof(DecBlk)},
+                    {(void*)d.walk0, walk0.data(), (nb + 1) * 8},
+                    {(void*)d.rle0, rle0.data(), (nb + 1) * 8},
+                    {misc[0], sb0.data(), (ns + 1) * 4},
+                    {misc[1], scrc.data(), ns * 4}},
+                   st)))
+    return rc;
+  d.in = d_in;
+  d.n_in = n_bytes;
+  d.nb = nb;
+  d.out = d_out;
+  d.err = ctx->status;
+  d.walk_total = wt;
+  d.rle_total = rt;
+  d.out_cap = out_cap;
+  d.out_bytes = d_out_bytes;
+  HIPX(dec_run(d, st));
+  // block CRCs of the output (the compressor's tile CRC and its combination)
+  HIPX(plan_slot_tiles(d.out_off, nb, misc[2], misc[3], st));
+  {
+    MapSet mm{};
+    mm.map[0] = MapDesc{misc[2], misc[4], misc[3], (uint32_t)tcap, nb};
+    mm.nmaps = 1;
+    mm.err = ctx->status;
+    HIPX(fill_maps(mm, st));
+  }
+  HIPX(rle1_tiles(d_out, persist_grid(tcap, ONE_TILE_EACH), misc[3], misc[4], misc[2], d.out_off, ctx->crc_tab,
+                  ctx->crc_tab + CRC_POW_AT, misc[5], st));
+  HIPX(rle1_blocks(nb, misc[2], d.out_off, ctx->crc_tab + CRC_POW_AT, misc[5], misc[6], misc[7], misc[8], misc[9], st));
+  HIPX(dec_check(nb, misc[9], d.crc_want, ns, misc[0], misc[1], d.skip, ctx->status, st));
+  return end_ws(ctx, nullptr, st);
+}
+
+}  // extern "C"
+

@@ -1,0 +1,784 @@
+// Decompression of bzip2 streams on the GPU: the decoding half the paper
+// discusses stage by stage --
+//   variable-length decoding (Sec. 3.4: code boundaries are only known
+//     serially; blocks are decoded in parallel, one wave each, with the
+//     RUNA/RUNB runs and the inverse move-to-front (Sec. 3.3) fused in);
+//   the inverse BWT started from many points (Sec. 3.1): walkers start at
+//     sampled rows of the last-to-first map, each stops at the next sampled
+//     row, a pass along the chain of samples places every walker's piece,
+//     and a second walk writes it;
+//   run-length decoding in the Figure 2 pattern (Sec. 3.2): per segment, the
+//     output length and outgoing state for every incoming state; a scan
+//     gives each segment its state and output offset; then every segment
+//     expands its runs at its offset.
+// Blocks are found by a bit-parallel search for the block and end-of-stream
+// markers; the host reads back the marker list to lay the blocks out.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bzg {
+
+constexpr uint64_t MAGIC_BLOCK = 0x314159265359ull;
+constexpr uint64_t MAGIC_EOS = 0x177245385090ull;
+constexpr uint32_t FIND_BYTES = 16;                 // input bytes per thread of the marker search
+constexpr uint32_t FIND_TILE = NT * FIND_BYTES;     // per workgroup
+constexpr uint32_t DEC_LUT_BITS = 10;               // first-level decoding table
+constexpr uint32_t WALK_STRIDE = 128;               // one sampled row per this many rows
+constexpr uint32_t RLE_SEG = 64;                    // bytes per run-length decoding segment
+
+// --------------------------------------------------------- marker search
+
+// Marker candidates of the 16 bytes at b0 (bit positions 8*b0 .. +127 whose
+// 48 bits lie inside the input): a bit mask per 64 positions for each kind.
+__device__ __forceinline__ void find_markers(const uint8_t* __restrict__ in, uint64_t n, uint64_t b0,
+                                             uint64_t m[2][2]) {
+  uint64_t W[3];
+#pragma unroll
+  for (int w = 0; w < 3; w++) {
+    uint64_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const uint64_t q = b0 + 8 * w + i;
+      v = (v << 8) | (q < n ? in[q] : 0u);
+    }
+    W[w] = v;
+  }
+  const uint64_t nbits = 8 * n;
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    uint64_t mb = 0, me = 0;
+#pragma unroll 8
+    for (int p = 0; p < 64; p++) {
+      const uint64_t hi = p ? (W[h] << p) | (W[h + 1] >> (64 - p)) : W[h];
+      const uint64_t v = hi >> 16;
+      const bool inside = 8 * b0 + 64 * h + p + 48 <= nbits;
+      mb |= (uint64_t)(inside && v == MAGIC_BLOCK) << p;
+      me |= (uint64_t)(inside && v == MAGIC_EOS) << p;
+    }
+    m[0][h] = mb;
+    m[1][h] = me;
+  }
+}
+
+// 32 bits starting at bit q of the input (bits past the end read as 0).
+__device__ __forceinline__ uint32_t bits32_at(const uint8_t* __restrict__ in, uint64_t n, uint64_t q) {
+  const uint64_t b = q >> 3;
+  uint64_t v = 0;
+#pragma unroll
+  for (int i = 0; i < 5; i++) v = (v << 8) | (b + i < n ? in[b + i] : 0u);
+  return (uint32_t)(v >> (8 - (q & 7)));
+}
+
+// Pass 0: markers per workgroup tile.  Pass 1: the markers in input order,
+// from the tiles' exclusive offsets: (bit position | kind << 63, the 32 bits
+// after the marker | for end markers, the 4 bytes where the next stream's
+// header would start << 32).
+__global__ __launch_bounds__(NT) void k_find_markers(const uint8_t* __restrict__ in, uint64_t n, int pass,
+                                                     uint32_t* __restrict__ tile_cnt,
+                                                     const uint64_t* __restrict__ tile_off,
+                                                     uint64_t* __restrict__ cand, uint64_t cand_cap) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  const uint64_t b0 = ((uint64_t)blockIdx.x * NT + threadIdx.x) * FIND_BYTES;
+  uint64_t m[2][2] = {{0, 0}, {0, 0}};
+  if (b0 < n) find_markers(in, n, b0, m);
+  const uint32_t c = __popcll(m[0][0]) + __popcll(m[0][1]) + __popcll(m[1][0]) + __popcll(m[1][1]);
+  uint32_t tot;
+  const uint32_t ex = block_excl_sum<uint32_t, NT>(c, sh, &tot);
+  if (pass == 0) {
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
+    return;
+  }
+  if (!c) return;
+  uint64_t o = tile_off[blockIdx.x] + ex;
+  // in bit order: both halves, each kind merged by position
+  for (int h = 0; h < 2; h++) {
+    uint64_t mb = m[0][h], me = m[1][h];
+    while (mb | me) {
+      const int pb = mb ? __ffsll((long long)mb) - 1 : 64, pe = me ? __ffsll((long long)me) - 1 : 64;
+      const bool eos = pe < pb;
+      const int p = eos ? pe : pb;
+      if (eos) me &= me - 1; else mb &= mb - 1;
+      const uint64_t pos = 8 * b0 + 64 * h + p;
+      uint64_t aux = bits32_at(in, n, pos + 48);
+      if (eos) aux |= (uint64_t)bits32_at(in, n, ((pos + 80 + 7) >> 3) << 3) << 32;
+      if (o < cand_cap) {
+        cand[2 * o] = pos | ((uint64_t)eos << 63);
+        cand[2 * o + 1] = aux;
+      }
+      o++;
+    }
+  }
+}
+
+// Exclusive offsets of n counts (one workgroup of 1024 threads); off[n] =
+// the total.
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, uint32_t n,
+                                                      uint64_t* __restrict__ off) {
+  __shared__ uint64_t sh[1024 / BZG_WAVE + 1];
+  const uint32_t per = (n + 1023) / 1024, lo = min(threadIdx.x * per, n), hi = min(lo + per, n);
+  uint64_t s = 0;
+  for (uint32_t i = lo; i < hi; i++) s += cnt[i];
+  uint64_t tot;
+  uint64_t run = block_excl_sum<uint64_t, 1024>(s, sh, &tot);
+  for (uint32_t i = lo; i < hi; i++) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (threadIdx.x == 0) off[n] = tot;
+}
+
+// ------------------------------------------------------- block decoding
+
+struct BitIn {
+  const uint8_t* in;
+  uint64_t n;
+  uint64_t fetch;  // next byte to load
+  uint64_t buf;    // bits not yet used, from the top
+  int nb;          // how many
+  uint64_t used;   // bits consumed
+  __device__ __forceinline__ uint32_t word(uint64_t b) const {
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) v = (v << 8) | (b + i < n ? in[b + i] : 0u);
+    return v;
+  }
+  __device__ __forceinline__ void refill() {
+    if (nb <= 32) {
+      buf |= (uint64_t)word(fetch) << (32 - nb);
+      nb += 32;
+      fetch += 4;
+    }
+  }
+  __device__ __forceinline__ uint32_t peek(int k) const { return (uint32_t)(buf >> (64 - k)); }
+  __device__ __forceinline__ void skip(int k) {
+    buf <<= k;
+    nb -= k;
+    used += k;
+  }
+  __device__ __forceinline__ uint32_t get(int k) {  // k <= 24
+    refill();
+    const uint32_t v = peek(k);
+    skip(k);
+    return v;
+  }
+};
+
+constexpr uint32_t MAX_SEL = 18002;  // selectors kept per block (more are read and dropped)
+constexpr uint32_t SEL_STRIDE = 18048;
+constexpr int DEC_MAXLEN = 20;
+
+// One wave per block: header, symbol map, selectors, code tables, then
+// every symbol: Huffman code (first-level table, then the canonical limits),
+// RUNA/RUNB runs, inverse move-to-front.  The move-to-front list is held
+// four entries per lane in one register and moved with lane shifts.  Writes
+// the BWT column, its length, origPtr, the stored CRC and the byte counts.
+__global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restrict__ in, uint64_t n_in,
+                                                        const DecBlk* __restrict__ blks, uint8_t* __restrict__ L,
+                                                        uint8_t* __restrict__ selws, uint32_t* __restrict__ out_n,
+                                                        uint32_t* __restrict__ out_orig,
+                                                        uint32_t* __restrict__ out_crc,
+                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
+  __shared__ uint16_t lut[MAXG][1u << DEC_LUT_BITS];
+  __shared__ uint16_t perm[MAXG][MAXA];
+  __shared__ int32_t limit[MAXG][DEC_MAXLEN + 2];
+  __shared__ uint32_t first[MAXG][DEC_MAXLEN + 2], start[MAXG][DEC_MAXLEN + 2];
+  __shared__ uint8_t lens[MAXG][MAXA];
+  __shared__ uint8_t unseq[256];
+  __shared__ uint32_t sh_hist[256];
+  __shared__ uint32_t srun[DEC_MAXLEN + 2];
+  const uint32_t b = blockIdx.x;
+  const DecBlk B = blks[b];
+  uint8_t* sel = selws + (size_t)b * SEL_STRIDE;
+  uint8_t* Lb = L + B.l_off;
+  const uint32_t ln = lane();
+  for (uint32_t i = ln; i < 256; i += BZG_WAVE) sh_hist[i] = 0;
+  BitIn r{in, n_in, B.start >> 3, 0, 0, 0};
+  {
+    // start mid-byte: load the byte holding the first bit and drop the bits before it
+    const int drop = (int)(B.start & 7);
+    r.refill();
+    r.buf <<= drop;
+    r.nb -= drop;
+  }
+  uint32_t bad = 0;
+  const uint32_t crc_hi = r.get(16);
+  const uint32_t crc = (crc_hi << 16) | r.get(16);
+  const uint32_t rnd = r.get(1);
+  const uint32_t orig = r.get(24);
+  bad |= rnd;  // randomised blocks (an obsolete encoder option) are not decoded
+  // symbol map
+  const uint32_t r16 = r.get(16);
+  uint32_t nin = 0;
+  for (int i = 0; i < 16; i++) {
+    if (!((r16 >> (15 - i)) & 1u)) continue;
+    const uint32_t bits = r.get(16);
+    for (int j = 0; j < 16; j++)
+      if ((bits >> (15 - j)) & 1u) {
+        if (ln == 0) unseq[nin] = (uint8_t)(16 * i + j);
+        nin++;
+      }
+  }
+  bad |= nin == 0;
+  const int a = (int)nin + 2;
+  const int G = (int)r.get(3);
+  const uint32_t nsel = r.get(15);
+  bad |= (G < 2) | (G > MAXG) | (nsel == 0);
+  uint32_t lst = 0x543210u;  // table list, 4 bits per entry, front in the low bits
+  for (uint32_t s = 0; s < nsel && !bad; s++) {
+    uint32_t j = 0;
+    while (r.get(1)) {
+      j++;
+      if (j >= (uint32_t)G) {
+        bad = 1;
+        break;
+      }
+    }
+    if (bad) break;
+    const uint32_t t = (lst >> (4 * j)) & 15u;
+    const uint32_t below = lst & ((1u << (4 * j)) - 1u);
+    lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
+    if (s < MAX_SEL && ln == 0) sel[s] = (uint8_t)t;
+  }
+  const uint32_t nsel_kept = min(nsel, MAX_SEL);
+  // code lengths, delta coded
+  for (int t = 0; t < G && !bad; t++) {
+    int cur = (int)r.get(5);
+    for (int i = 0; i < a; i++) {
+      for (;;) {
+        if (cur < 1 || cur > DEC_MAXLEN) {
+          bad = 1;
+          break;
+        }
+        if (!r.get(1)) break;
+        cur += r.get(1) ? -1 : 1;
+      }
+      if (bad) break;
+      if (ln == 0) lens[t][i] = (uint8_t)cur;
+    }
+  }
+  __syncthreads();
+  // decoding tables: canonical first codes, limits, symbols by length
+  if (!bad) {
+    for (int t = 0; t < G; t++) {
+      if (ln < DEC_MAXLEN + 2) srun[ln] = 0;
+      __syncthreads();
+      for (int i = ln; i < a; i += BZG_WAVE) atomicAdd(&srun[lens[t][i]], 1u);
+      __syncthreads();
+      if (ln == 0) {
+        uint32_t code = 0, st = 0;
+        for (int l = 1; l <= DEC_MAXLEN; l++) {
+          const uint32_t c = srun[l];
+          first[t][l] = code;
+          start[t][l] = st;
+          limit[t][l] = (int32_t)(code + c) - 1;
+          code = (code + c) << 1;
+          st += c;
+        }
+      }
+      __syncthreads();
+      if (ln < DEC_MAXLEN + 2) srun[ln] = 0;
+      __syncthreads();
+      // symbols of each length in symbol order: ranks by ballots, 64 at a time
+      for (int k = 0; k * BZG_WAVE < a; k++) {
+        const int v = k * BZG_WAVE + (int)ln;
+        const bool ok = v < a;
+        const uint32_t l = ok ? lens[t][v] : 0u;
+        const uint64_t peers = match_digit8(l, __ballot(ok));
+        const uint32_t before = srun[l];
+        if (ok) perm[t][start[t][l] + before + (uint32_t)__popcll(peers & lanemask_lt())] = (uint16_t)v;
+        if (ok && (uint32_t)(__ffsll((long long)peers) - 1) == ln) srun[l] = before + (uint32_t)__popcll(peers);
+        __syncthreads();
+      }
+      // first-level table: the shortest code length whose limit admits the prefix
+      for (uint32_t x = ln; x < (1u << DEC_LUT_BITS); x += BZG_WAVE) {
+        uint16_t e = 0;
+        for (int l = 1; l <= (int)DEC_LUT_BITS; l++) {
+          const int32_t v = (int32_t)(x >> (DEC_LUT_BITS - l));
+          if (v <= limit[t][l]) {
+            const uint32_t idx = start[t][l] + (uint32_t)v - first[t][l];
+            e = idx < (uint32_t)a ? (uint16_t)(perm[t][idx] | (l << 9)) : 0;
+            break;
+          }
+        }
+        lut[t][x] = e;
+      }
+    }
+  }
+  __syncthreads();
+  // symbols
+  uint32_t stk = 0;  // move-to-front list entries 4*ln .. 4*ln+3, one byte each
+#pragma unroll
+  for (int j = 0; j < 4; j++) stk |= (uint32_t)((4 * ln + j) & 255u) << (8 * j);
+  const uint32_t cap = B.cap;
+  uint32_t cnt = 0, zrun = 0, zN = 1, gsel = 0, gleft = 0, t = 0;
+  const uint32_t eob = (uint32_t)a - 1;
+  while (!bad) {
+    if (gleft == 0) {
+      if (gsel >= nsel_kept) {
+        bad = 1;
+        break;
+      }
+      // read back by the lane that wrote it, then shared
+      const uint32_t tv = ln == 0 ? sel[gsel] : 0u;
+      t = (uint32_t)__builtin_amdgcn_readfirstlane((int)tv);
+      gsel++;
+      gleft = GROUP;
+    }
+    gleft--;
+    r.refill();
+    const uint32_t e = lut[t][r.peek(DEC_LUT_BITS)];
+    uint32_t sym;
+    if (e >> 9) {
+      sym = e & 511u;
+      r.skip((int)(e >> 9));
+    } else {
+      int zn = DEC_LUT_BITS + 1;
+      while (zn <= DEC_MAXLEN && (int32_t)r.peek(zn) > limit[t][zn]) zn++;
+      if (zn > DEC_MAXLEN) {
+        bad = 1;
+        break;
+      }
+      const uint32_t idx = start[t][zn] + r.peek(zn) - first[t][zn];
+      if (idx >= (uint32_t)a) {
+        bad = 1;
+        break;
+      }
+      sym = perm[t][idx];
+      r.skip(zn);
+    }
+    if (sym <= 1) {  // RUNA / RUNB: a digit of the zero run, least significant first
+      zrun += (sym + 1) * zN;
+      zN <<= 1;
+      if (zrun > cap || zN > (1u << 24)) {
+        bad = 1;
+        break;
+      }
+      continue;
+    }
+    if (zrun) {  // the run: copies of the list's front byte
+      if (cnt + zrun > cap) {
+        bad = 1;
+        break;
+      }
+      const uint32_t front = (uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u;
+      const uint8_t by = unseq[front];
+      for (uint32_t j = ln; j < zrun; j += BZG_WAVE) Lb[cnt + j] = by;
+      if (ln == 0) sh_hist[by] += zrun;
+      cnt += zrun;
+      zrun = 0;
+      zN = 1;
+    }
+    if (sym == eob) break;
+    const uint32_t i = sym - 1;  // list position, 1 .. nin-1
+    if (i >= nin || cnt >= cap) {
+      bad = 1;
+      break;
+    }
+    const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)stk, (int)(i >> 2));
+    const uint32_t uc = (word >> (8 * (i & 3u))) & 255u;
+    // positions 0 .. i-1 move up one, uc goes to the front
+    const uint32_t prev = wave_shr1(0u, stk);
+    const uint32_t up = (stk << 8) | (prev >> 24);
+    const int q0 = 4 * (int)ln;
+    const int take = min(max((int)i - q0 + 1, 0), 4);  // bytes of this lane at positions <= i
+    const uint32_t m = take == 4 ? 0xFFFFFFFFu : ((1u << (8 * take)) - 1u);
+    stk = (up & m) | (stk & ~m);
+    if (ln == 0) stk = (stk & ~255u) | uc;
+    const uint8_t by = unseq[uc];
+    if (ln == 0) {
+      Lb[cnt] = by;
+      sh_hist[by] += 1;
+    }
+    cnt++;
+  }
+  // the block's bits must end exactly where the next marker starts
+  bad |= (B.start + r.used != B.end);
+  bad |= (cnt == 0) | (orig >= cnt);
+  __syncthreads();
+  for (uint32_t i = ln; i < 256; i += BZG_WAVE) hist[(size_t)b * 256 + i] = bad ? 0u : sh_hist[i];
+  if (ln == 0) {
+    out_n[b] = bad ? 0u : cnt;
+    out_orig[b] = bad ? 0u : orig;
+    out_crc[b] = crc;
+    if (bad) atomicOr(err, ERR_STREAM);
+  }
+}
+
+// ------------------------------------------------------ inverse BWT map
+
+// FL of one block: the row that holds, in the last column, the k-th
+// occurrence of the byte that is first in row C[byte] + k -- a stable
+// counting sort of the column (one workgroup per block, 256 rows a step).
+__global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, const uint8_t* __restrict__ L,
+                                               const uint32_t* __restrict__ n_rows,
+                                               const uint32_t* __restrict__ hist, uint32_t* __restrict__ FL) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wc[NT / BZG_WAVE][256];
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  const uint32_t b = blockIdx.x, tid = threadIdx.x, w = tid / BZG_WAVE;
+  const uint32_t n = n_rows[b];
+  const uint8_t* Lb = L + blks[b].l_off;
+  uint32_t* F = FL + blks[b].l_off;
+  {
+    uint32_t tot;
+    const uint32_t c = hist[(size_t)b * 256 + tid];
+    base[tid] = block_excl_sum<uint32_t, NT>(c, sh, &tot);
+    for (int q = 0; q < NT / BZG_WAVE; q++) wc[q][tid] = 0;
+  }
+  __syncthreads();
+  for (uint32_t k0 = 0; k0 < n; k0 += NT) {
+    const uint32_t k = k0 + tid;
+    const bool ok = k < n;
+    const uint32_t d = ok ? Lb[k] : 0u;
+    const uint64_t peers = match_digit8(d, __ballot(ok));
+    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+    if (ok && (uint32_t)(__ffsll((long long)peers) - 1) == lane()) wc[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < w; q++) before += wc[q][d];
+    if (ok) F[base[d] + before + rank] = k;
+    __syncthreads();
+    uint32_t all = 0;
+    for (int q = 0; q < NT / BZG_WAVE; q++) {
+      all += wc[q][tid];
+      wc[q][tid] = 0;
+    }
+    base[tid] += all;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------- inverse BWT from many points
+
+// Sampled rows of a block: every WALK_STRIDE-th row, and origPtr.
+__device__ __forceinline__ uint32_t samples_of(uint32_t n, uint32_t orig) {
+  const uint32_t s = (n + WALK_STRIDE - 1) / WALK_STRIDE;
+  return s + (orig % WALK_STRIDE ? 1u : 0u);
+}
+__device__ __forceinline__ uint32_t sample_row(uint32_t s, uint32_t n, uint32_t orig) {
+  const uint32_t m = (n + WALK_STRIDE - 1) / WALK_STRIDE;
+  return s < m ? s * WALK_STRIDE : orig;
+}
+__device__ __forceinline__ bool is_sample(uint32_t row, uint32_t orig) {
+  return row % WALK_STRIDE == 0 || row == orig;
+}
+__device__ __forceinline__ uint32_t sample_index(uint32_t row, uint32_t n, uint32_t orig) {
+  return row % WALK_STRIDE == 0 ? row / WALK_STRIDE : (n + WALK_STRIDE - 1) / WALK_STRIDE;
+}
+
+// The block owning flat slot j of a per-block slot layout (offsets s0[0..nb]).
+__device__ __forceinline__ uint32_t owner_of(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
+  uint32_t lo = 0, hi = nb;  // s0[lo] <= j < s0[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (s0[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+constexpr uint32_t UNVISITED = 0xFFFFFFFFu;
+
+// Walker per sampled row: follows FL until the next sampled row; records
+// the steps and which sample it reached.
+__global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
+                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
+                                                 uint32_t* __restrict__ nxt, uint32_t* __restrict__ steps,
+                                                 uint32_t* __restrict__ pos) {
+  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= total) return;
+  const uint32_t b = owner_of(s0, nb, j);
+  const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b];
+  pos[j] = UNVISITED;
+  if (n == 0 || s >= samples_of(n, orig)) return;
+  const uint32_t* F = FL + blks[b].l_off;
+  uint32_t row = sample_row(s, n, orig), c = 0;
+  do {
+    row = F[row];
+    c++;
+  } while (!is_sample(row, orig) && c < n);
+  nxt[j] = sample_index(row, n, orig);
+  steps[j] = c;
+}
+
+// Per block: the chain of samples from origPtr gives every walker on it its
+// output position; its length is the period of the text (the whole block
+// unless the block repeats a shorter string).
+__global__ void k_dec_chain(const uint64_t* __restrict__ s0, uint32_t nb, const uint32_t* __restrict__ n_rows,
+                            const uint32_t* __restrict__ origs, const uint32_t* __restrict__ nxt,
+                            const uint32_t* __restrict__ steps, uint32_t* __restrict__ pos,
+                            uint32_t* __restrict__ period, uint32_t* __restrict__ err) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const uint32_t n = n_rows[b], orig = origs[b];
+  if (n == 0) {
+    period[b] = 0;
+    return;
+  }
+  const uint64_t base = s0[b];
+  const uint32_t ns = samples_of(n, orig), s_start = sample_index(orig, n, orig);
+  uint32_t s = s_start, p = 0, it = 0;
+  do {
+    pos[base + s] = p;
+    p += steps[base + s];
+    s = nxt[base + s];
+  } while (s != s_start && p < n && ++it <= ns && s < ns);
+  const bool ok = s == s_start && p <= n && p > 0 && n % p == 0;
+  period[b] = ok ? p : 0u;
+  if (!ok) atomicOr(err, ERR_STREAM);
+}
+
+// Walkers on the chain write their pieces of the text (the RLE1 bytes).
+__global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
+                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
+                                                 const uint8_t* __restrict__ L, const uint32_t* __restrict__ steps,
+                                                 const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
+                                                 uint8_t* __restrict__ T) {
+  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= total) return;
+  const uint32_t p0 = pos[j];
+  if (p0 == UNVISITED) return;
+  const uint32_t b = owner_of(s0, nb, j);
+  const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b], per = period[b];
+  if (per == 0) return;
+  const uint64_t o = blks[b].l_off;
+  const uint32_t* F = FL + o;
+  const uint8_t* Lb = L + o;
+  uint8_t* Tb = T + o;
+  uint32_t row = sample_row(s, n, orig);
+  const uint32_t c = steps[j];
+  for (uint32_t k = 0; k < c && p0 + k < per; k++) {
+    row = F[row];
+    Tb[p0 + k] = Lb[row];
+  }
+}
+
+// A block that repeats a string of the period: the rest is copies.
+__global__ __launch_bounds__(NT) void k_dec_repeat(const DecBlk* __restrict__ blks,
+                                                   const uint32_t* __restrict__ n_rows,
+                                                   const uint32_t* __restrict__ period, uint8_t* __restrict__ T) {
+  const uint32_t b = blockIdx.x, n = n_rows[b], p = period[b];
+  if (p == 0 || p >= n) return;
+  uint8_t* Tb = T + blks[b].l_off;
+  for (uint32_t i = p + threadIdx.x; i < n; i += NT) Tb[i] = Tb[i % p];
+}
+
+// ------------------------------------------------ run-length decoding
+
+// RLE1 decoding state before a byte: 0 fresh, 1..3 that many equal bytes
+// just written (the last one `last`), 4 a count byte expected (it repeats
+// `last`).  One step on byte x: the bytes it writes and the next state.
+__device__ __forceinline__ uint32_t rle_step(uint32_t& st, uint32_t& last, uint32_t x) {
+  if (st == 4) {
+    st = 0;
+    return x;  // x more copies of last
+  }
+  if (st >= 1 && x == last) {
+    st++;
+    return 1;
+  }
+  st = 1;
+  last = x;
+  return 1;
+}
+
+// Per segment of RLE_SEG text bytes, for each incoming state s (with `last`
+// = the segment's first byte for s = 1..3): output bytes, outgoing state and
+// last byte, packed as len | st << 32 | last << 40.
+__global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
+                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                                 uint64_t* __restrict__ summ) {
+  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= total) return;
+  const uint32_t b = owner_of(g0, nb, j);
+  const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
+  if ((uint64_t)g * RLE_SEG >= n) return;
+  const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
+  const uint32_t m = min(RLE_SEG, n - g * RLE_SEG);
+  uint8_t x[RLE_SEG];
+#pragma unroll
+  for (uint32_t i = 0; i < RLE_SEG; i++) x[i] = Tb[min(i, m - 1)];
+#pragma unroll
+  for (uint32_t s = 0; s < 5; s++) {
+    uint32_t st = s, last = x[0], len = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < RLE_SEG; i++)
+      if (i < m) len += rle_step(st, last, x[i]);
+    summ[j * 5 + s] = (uint64_t)len | ((uint64_t)st << 32) | ((uint64_t)last << 40);
+  }
+}
+
+// Per block, the segments in order: each one's incoming state (and last
+// byte) and output offset within the block; the block's output length.
+__global__ void k_rle_chain(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0, uint32_t nb,
+                            const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ period,
+                            const uint8_t* __restrict__ T, const uint64_t* __restrict__ summ,
+                            uint32_t* __restrict__ seg_in, uint32_t* __restrict__ seg_off,
+                            uint32_t* __restrict__ out_len) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const uint32_t n = period[b] ? n_rows[b] : 0u;
+  const uint32_t ns = (n + RLE_SEG - 1) / RLE_SEG;
+  const uint8_t* Tb = T + blks[b].l_off;
+  const uint64_t base = g0[b];
+  uint32_t st = 0, last = 0, off = 0;
+  for (uint32_t g = 0; g < ns; g++) {
+    seg_in[base + g] = st | (last << 8);
+    seg_off[base + g] = off;
+    const uint64_t v = summ[(base + g) * 5 + st];
+    off += (uint32_t)v;
+    const uint32_t so = (uint32_t)(v >> 32) & 255u, lo = (uint32_t)(v >> 40) & 255u;
+    if (g + 1 < ns) {
+      const uint32_t x0 = Tb[(g + 1) * RLE_SEG];
+      st = (so >= 1 && so <= 3) ? (lo == x0 ? so : 0u) : so;
+      last = lo;
+    }
+  }
+  out_len[b] = off;
+}
+
+// Block output offsets (one workgroup) and the total; when the total does
+// not fit out_cap, every block is emptied (nothing is written) and the
+// capacity error is flagged.
+__global__ __launch_bounds__(1024) void k_rle_offsets(const uint32_t* __restrict__ out_len, uint32_t nb,
+                                                      uint64_t out_cap, uint64_t* __restrict__ out_off,
+                                                      uint64_t* __restrict__ out_bytes, uint32_t* __restrict__ skip,
+                                                      uint32_t* __restrict__ err) {
+  __shared__ uint64_t sh[1024 / BZG_WAVE + 1];
+  const uint32_t per = (nb + 1023) / 1024, lo = min(threadIdx.x * per, nb), hi = min(lo + per, nb);
+  uint64_t s = 0;
+  for (uint32_t i = lo; i < hi; i++) s += out_len[i];
+  uint64_t tot;
+  uint64_t run = block_excl_sum<uint64_t, 1024>(s, sh, &tot);
+  const bool fits = tot <= out_cap;
+  for (uint32_t i = lo; i < hi; i++) {
+    out_off[i] = fits ? run : 0u;
+    run += out_len[i];
+  }
+  if (threadIdx.x == 0) {
+    out_off[nb] = fits ? tot : 0u;
+    *out_bytes = tot;
+    *skip = fits ? 0u : 1u;
+    if (!fits) atomicOr(err, ERR_CAPACITY);
+  }
+}
+
+// Every segment expands its bytes at its offset (Figure 2's scatter).
+__global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
+                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                                 const uint32_t* __restrict__ seg_in,
+                                                 const uint32_t* __restrict__ seg_off,
+                                                 const uint64_t* __restrict__ out_off,
+                                                 const uint32_t* __restrict__ skip, uint8_t* __restrict__ out) {
+  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= total || *skip) return;
+  const uint32_t b = owner_of(g0, nb, j);
+  const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
+  if ((uint64_t)g * RLE_SEG >= n) return;
+  const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
+  const uint32_t m = min(RLE_SEG, n - g * RLE_SEG);
+  uint8_t* o = out + out_off[b] + seg_off[j];
+  uint32_t st = seg_in[j] & 255u, last = seg_in[j] >> 8;
+  uint32_t w = 0;
+  for (uint32_t i = 0; i < m; i++) {
+    const uint32_t x = Tb[i];
+    if (st == 4) {
+      for (uint32_t k = 0; k < x; k++) o[w + k] = (uint8_t)last;
+      w += x;
+    } else {
+      o[w++] = (uint8_t)x;
+    }
+    (void)rle_step(st, last, x);
+  }
+}
+
+// Block CRCs against the stored ones, and every stream's combined CRC.
+__global__ void k_dec_check(uint32_t nb, const uint32_t* __restrict__ crc_got, const uint32_t* __restrict__ crc_want,
+                            uint32_t n_streams, const uint32_t* __restrict__ stream_b0,
+                            const uint32_t* __restrict__ stream_crc, const uint32_t* __restrict__ skip,
+                            uint32_t* __restrict__ err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (*skip) return;
+  if (i < nb && crc_got[i] != crc_want[i]) atomicOr(err, ERR_STREAM);
+  if (i < n_streams) {
+    uint32_t comb = 0;
+    for (uint32_t k = stream_b0[i]; k < stream_b0[i + 1]; k++) comb = ((comb << 1) | (comb >> 31)) ^ crc_want[k];
+    if (comb != stream_crc[i]) atomicOr(err, ERR_STREAM);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+hipError_t dec_find(const uint8_t* in, uint64_t n, int pass, uint32_t* tile_cnt, const uint64_t* tile_off,
+                    uint64_t* cand, uint64_t cand_cap, hipStream_t st) {
+  const uint64_t tiles = (n + FIND_TILE - 1) / FIND_TILE;
+  ProfScope ps("dec_find", st, (double)n);
+  hipLaunchKernelGGL(k_find_markers, dim3((uint32_t)std::max<uint64_t>(tiles, 1)), dim3(NT), 0, st, in, n, pass,
+                     tile_cnt, tile_off, cand, cand_cap);
+  return hipGetLastError();
+}
+uint64_t dec_find_tiles(uint64_t n) { return std::max<uint64_t>((n + FIND_TILE - 1) / FIND_TILE, 1); }
+
+hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, n, off);
+  return hipGetLastError();
+}
+
+uint32_t dec_walk_slots(uint32_t cap) { return cap / WALK_STRIDE + 2; }
+uint32_t dec_rle_slots(uint32_t cap) { return cap / RLE_SEG + 1; }
+size_t dec_sel_stride() { return SEL_STRIDE; }
+
+hipError_t dec_run(const DecRun& d, hipStream_t st) {
+  const uint32_t nb = d.nb;
+  {
+    ProfScope ps("dec_block", st, 0.0);
+    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.L,
+                       d.sel, d.n_rows, d.orig, d.crc_want, d.hist, d.err);
+  }
+  {
+    ProfScope ps("dec_fl", st, 0.0);
+    hipLaunchKernelGGL(k_dec_fl, dim3(nb), dim3(NT), 0, st, d.blks, d.L, d.n_rows, d.hist, d.FL);
+  }
+  const uint32_t gw = (uint32_t)((d.walk_total + NT - 1) / NT);
+  {
+    ProfScope ps("dec_walk", st, 0.0);
+    hipLaunchKernelGGL(k_dec_walk, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
+                       d.walk_total, d.n_rows, d.orig, d.FL, d.nxt, d.steps, d.pos);
+  }
+  hipLaunchKernelGGL(k_dec_chain, dim3((nb + 63) / 64), dim3(64), 0, st, d.walk0, nb, d.n_rows, d.orig, d.nxt,
+                     d.steps, d.pos, d.period, d.err);
+  {
+    ProfScope ps("dec_emit", st, 0.0);
+    hipLaunchKernelGGL(k_dec_emit, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
+                       d.walk_total, d.n_rows, d.orig, d.FL, d.L, d.steps, d.pos, d.period, d.T);
+  }
+  hipLaunchKernelGGL(k_dec_repeat, dim3(nb), dim3(NT), 0, st, d.blks, d.n_rows, d.period, d.T);
+  const uint32_t gr = (uint32_t)((d.rle_total + NT - 1) / NT);
+  {
+    ProfScope ps("dec_rle", st, 0.0);
+    hipLaunchKernelGGL(k_rle_summ, dim3(std::max(gr, 1u)), dim3(NT), 0, st, d.blks, d.rle0, nb,
+                       d.rle_total, d.n_rows, d.period, d.T, d.summ);
+    hipLaunchKernelGGL(k_rle_chain, dim3((nb + 63) / 64), dim3(64), 0, st, d.blks, d.rle0, nb,
+                       d.n_rows, d.period, d.T, d.summ, d.seg_in, d.seg_off, d.out_len);
+    hipLaunchKernelGGL(k_rle_offsets, dim3(1), dim3(1024), 0, st, d.out_len, nb, d.out_cap, d.out_off, d.out_bytes,
+                       d.skip, d.err);
+    hipLaunchKernelGGL(k_rle_emit, dim3(std::max(gr, 1u)), dim3(NT), 0, st, d.blks, d.rle0, nb,
+                       d.rle_total, d.n_rows, d.period, d.T, d.seg_in, d.seg_off, d.out_off, d.skip, d.out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
+                     const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
+                     hipStream_t st) {
+  const uint32_t n = std::max(nb, n_streams);
+  hipLaunchKernelGGL(k_dec_check, dim3((n + 255) / 256 + 1), dim3(256), 0, st, nb, crc_got, crc_want, n_streams,
+                     stream_b0, stream_crc, skip, err);
+  return hipGetLastError();
+}
+
+}  // namespace bzg

@@ -76,6 +76,7 @@ struct BlockTables {
 // kernels of a call and reported (and cleared) by bzg_check.
 constexpr uint32_t ERR_SYMBOL = 1u;    // a symbol outside its block's alphabet, or more symbols than slots
 constexpr uint32_t ERR_CAPACITY = 2u;  // an output range too small: nothing was packed
+constexpr uint32_t ERR_STREAM = 8u;    // a compressed stream that does not decode (corrupt or unsupported)
 constexpr uint32_t ERR_BOUND = 4u;     // a device-side count exceeded its host bound (work was dropped)
 
 // Persistent workgroup loops.  A kernel launched with G workgroups (a
@@ -253,6 +254,43 @@ struct HuffArgs {
   const uint64_t* sym_off;   // (count_freq) nb + 1 symbol capacity offsets
   uint32_t* ns_eff;          // (count_freq) nb counts clamped to the capacities
 };
+
+// Decompression (decode.hip).  A block to decode, laid out by the host from
+// the markers: its bits [start, end) after the block marker; `cap` (the
+// stream's level limit) bytes of BWT column at l_off.
+struct DecBlk {
+  uint64_t start, end, l_off;
+  uint32_t cap, pad;
+};
+// The arrays of one call, carved by the host.
+struct DecRun {
+  const uint8_t* in;
+  uint64_t n_in;
+  uint32_t nb;
+  const DecBlk* blks;
+  uint8_t *L, *T, *sel, *out;
+  uint32_t *n_rows, *orig, *crc_want, *hist, *err, *FL;
+  const uint64_t* walk0;  // nb + 1 walker slot offsets
+  uint64_t walk_total;
+  uint32_t *nxt, *steps, *pos, *period;
+  const uint64_t* rle0;  // nb + 1 segment slot offsets
+  uint64_t rle_total;
+  uint64_t* summ;  // 5 per segment slot
+  uint32_t *seg_in, *seg_off, *out_len, *skip;
+  uint64_t out_cap;
+  uint64_t *out_off, *out_bytes;
+};
+hipError_t dec_find(const uint8_t* in, uint64_t n, int pass, uint32_t* tile_cnt, const uint64_t* tile_off,
+                    uint64_t* cand, uint64_t cand_cap, hipStream_t st);
+uint64_t dec_find_tiles(uint64_t n);
+hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipStream_t st);
+uint32_t dec_walk_slots(uint32_t cap);
+uint32_t dec_rle_slots(uint32_t cap);
+size_t dec_sel_stride();
+hipError_t dec_run(const DecRun& d, hipStream_t st);
+hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
+                     const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
+                     hipStream_t st);
 
 size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
 bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w);

@@ -63,6 +63,8 @@ def lib() -> C.CDLL:
         L.compress_batch.argtypes = [vp, vp, vp, u64p, u32, vp, u32p, u32, i, vp, vp, u64p, vp, vp, sz, vp]
         L.compress_blocks_noalloc.restype = i
         L.compress_blocks_noalloc.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp]
+        L.decompress.restype = i
+        L.decompress.argtypes = [vp, vp, u64, vp, u64, vp, vp]
         L.bzg_set_fixed_tables.restype = i
         L.bzg_set_fixed_tables.argtypes = [vp, vp, i]
         L.compress_host.restype = i
@@ -77,7 +79,7 @@ def lib() -> C.CDLL:
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_check", "bzg_workspace_size", "bzg_compress_bound",
            "bwt_forward_batch", "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch",
-           "compress_blocks_noalloc", "compress_host", "bzg_set_fixed_tables", "bzg_profile",
+           "compress_blocks_noalloc", "compress_host", "bzg_set_fixed_tables", "decompress", "bzg_profile",
            "bzg_profile_read")
 
 
@@ -442,4 +444,28 @@ def compress_host(data, level: int = 9, block_bytes: Optional[int] = None, chunk
                                   chunk_bytes or 0, C.c_void_p(out.data_ptr()), out.numel(), C.byref(got),
                                   _stream(dev)))
     return out[: got.value].numpy()
+
+
+def decompress(z: torch.Tensor, out_cap: Optional[int] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Decodes one bzip2 stream, or several one after another, on the GPU:
+    returns the original bytes (uint8 tensor on z's device).  When out_cap
+    (default 4x the input, at least 1 MiB) is too small, the call is repeated
+    with the size the first attempt reported."""
+    z = _dev_u8(z)
+    ctx = ctx or context(z.device.index)
+    st = _stream(z.device)
+    cap = out_cap or max(4 * z.numel(), 1 << 20)
+    nbytes = torch.zeros(1, dtype=torch.int64, device=z.device)
+    for attempt in range(2):
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=z.device)
+        ctx.check(lib().decompress(ctx.h, _vp(z), z.numel(), _vp(out), cap, _vp(nbytes), st))
+        try:
+            ctx.sync_check(st)
+        except BzgError as e:
+            if e.code != BZG_ECAPACITY or attempt:
+                raise
+            cap = int(nbytes.item())
+            continue
+        return out[: int(nbytes.item())]
+    raise BzgError(BZG_ECAPACITY, "output size changed between attempts")
 

@@ -63,6 +63,7 @@ def test_null_context_is_rejected():
     assert lib.bzg_check(None, None) == native.BZG_EINVAL
     assert lib.bzg_workspace_size(None, 4, None, 0, 9, 1, None) == native.BZG_EINVAL
     assert lib.compress_host(None, None, 0, 0, 9, 0, None, 0, None, None) == native.BZG_EINVAL
+    assert lib.decompress(None, None, 0, None, 0, None, None) == native.BZG_EINVAL
 
 
 def test_product_path_does_not_import_the_oracle():
