@@ -205,8 +205,63 @@ def bench_compress(args, batch, level):
                          + "), oracle compress with one thread per block; GPU stream on the sample bit-identical"}
     config = {"workload": batch.name, "input_bytes": n_in, "blocks": batch.n_blocks, "level": level,
               "output_bytes": out_bytes, "ratio": round(out_bytes / n_in, 4)}
-    extra = {"host_input": _host_input(args, bz, batch, level)} if args.host_input else None
-    return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extra)
+    extra = {}
+    if args.host_input:
+        extra["host_input"] = _host_input(args, bz, batch, level)
+    if args.fixed_tables:
+        extra["fixed_tables"] = _fixed_tables(args, bz, batch, level, x)
+    if args.decompress:
+        extra["decompress"] = _decompress(args, bz, z.clone(), batch)
+    return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extra or None)
+
+
+def _fixed_tables(args, bz, batch, level, x):
+    """The same batch with precomputed tables (chosen from a sample of the
+    batch's first blocks): no table is built per block."""
+    import torch
+    from paper_1109_2348_amd import native
+    ctx = native.Context()
+    k = min(batch.n_blocks, 48)
+    sample = x[: int(batch.offsets[k])]
+    fixed = bz.fixed_tables_from_sample(sample, batch.offsets[: k + 1], ctx=ctx)
+    ctx.set_fixed_tables(fixed)
+    comp = bz.Compressor(ctx=ctx)
+    stream = torch.cuda.current_stream()
+    log(f"fixed tables ({fixed.shape[0]} from {k} sample blocks)")
+    z, wall, step_ms, kern = _timed(lambda: comp(x, batch.offsets, level=level), ctx, args.steps, args.warmup,
+                                    stream)
+    n_in = int(batch.data.size)
+    huff_ms = sum(v["ms"] for kname, v in kern.items() if kname.startswith("huff")) / args.steps
+    return {"value": round(args.steps * n_in / wall / 1e6, 2), "unit": "MB/s", "ms_per_step": round(wall / args.steps * 1e3, 3),
+            "output_bytes": int(z.numel()), "ratio": round(int(z.numel()) / n_in, 4),
+            "huffman_ms_per_step": round(huff_ms, 3), "sample_blocks": k}
+
+
+def _decompress(args, bz, z, batch):
+    """GPU decompression of the batch's stream back to the input bytes."""
+    import torch
+    from paper_1109_2348_amd import native
+    n_out = int(batch.data.size)
+    ctx = native.context()
+    st = torch.cuda.current_stream()
+    out = torch.empty(n_out + 1024, dtype=torch.uint8, device=z.device)
+    nbytes = torch.zeros(1, dtype=torch.int64, device=z.device)
+    sv = native.C.c_void_p(st.cuda_stream)
+
+    def run():
+        ctx.check(native.lib().decompress(ctx.h, native._vp(z), z.numel(), native._vp(out), out.numel(),
+                                          native._vp(nbytes), sv))
+    run()
+    ctx.sync_check(sv)
+    ok = int(nbytes.item()) == n_out and torch.equal(out[:n_out].cpu(), torch.from_numpy(batch.data))
+    if not ok:
+        log("ERROR: decompressed bytes differ from the input")
+        sys.exit(1)
+    log("decompress")
+    _, wall, step_ms, kern = _timed(run, ctx, args.steps, 1, st)
+    return {"value": round(args.steps * n_out / wall / 1e6, 2), "unit": "MB/s (decoded bytes)",
+            "ms_per_step": round(wall / args.steps * 1e3, 3), "input_bytes": int(z.numel()),
+            "kernels": _kernels(kern, args.steps), "checked": "bytes identical to the input"}
 
 
 def _host_input(args, bz, batch, level):
@@ -361,6 +416,8 @@ def main():
     ap.add_argument("--host-input", action="store_true",
                     help="configs 1, 2, 4: also time compress_host from pinned host memory (reported beside)")
     ap.add_argument("--host-chunk-blocks", type=int, default=128, help="blocks per chunk for --host-input")
+    ap.add_argument("--fixed-tables", action="store_true", help="configs 1, 2, 4: also time precomputed tables")
+    ap.add_argument("--decompress", action="store_true", help="configs 1, 2, 4: also time GPU decompression")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",

@@ -75,8 +75,9 @@ enum { BZG_CALL_BWT = 1, BZG_CALL_MTF = 2, BZG_CALL_HUFFMAN = 3, BZG_CALL_COMPRE
 #define BZG_MAX_BLOCK (1u << 21)
 
 /* Creates a context bound to HIP device `hip_device`.  tune_cache_path
- * (nullable) names a JSON file of tuned launch parameters, read if present
- * (see bzg_tune).  Returns 0 or BZG_E*. */
+ * (nullable) names a JSON file of tuned launch parameters: its entries for
+ * this device and HIP runtime are read now, and bzg_tune adds to it.
+ * Returns 0 or BZG_E*. */
 int bzg_create(bzg_ctx** out, int hip_device, const char* tune_cache_path);
 
 /* Waits for the device, then releases the context and its pool.  NULL is
@@ -233,6 +234,32 @@ int compress_blocks_noalloc(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d
                             uint32_t* d_n_blocks, void* stream);
 
 /*
+ * Launch parameters.  Three choices change only how the work is spread over
+ * the GPU, never a byte of any output: the move-to-front chunk length
+ * (mtf_chunk: 2048 or 4096 rows), the Huffman selector groups per
+ * assignment tile (assign_groups: 128 or 512) and how many counting steps
+ * the small-segment sort may spend per radix pass it saves (count_steps,
+ * 1..1024).  0 leaves the built-in choice (which depends on the call's
+ * size).  bzg_set_tune fixes them for every later call on the context (all
+ * zero: back to the tuned or built-in choices).
+ */
+int bzg_set_tune(bzg_ctx* ctx, uint32_t mtf_chunk, uint32_t assign_groups, uint32_t count_steps);
+
+/*
+ * Autotuning: runs compress_blocks on the given batch at every combination
+ * of the launch parameters above (12 points), three times each, checks that
+ * every point gives the same stream bytes as the first (BZG_EINTERNAL
+ * otherwise), and keeps the fastest for calls of this batch's size bucket
+ * (floor(log2 bytes), floor(log2 blocks)) on this context; with a tune cache
+ * file (bzg_create) the entry is written there, keyed by the GPU's
+ * architecture, the HIP runtime version and the bucket, so later contexts
+ * start tuned.  Synchronous; allocates its own output buffers.  h_chosen
+ * (nullable) receives {mtf_chunk, assign_groups, count_steps}.
+ */
+int bzg_tune(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level, void* stream,
+             uint32_t* h_chosen);
+
+/*
  * Precomputed Huffman tables (Sec. 4: the tables may be computed beforehand
  * by analysing data instead of built per block).  With n_tables = 2..6,
  * every later compress_blocks / compress_batch / compress_host /
@@ -306,6 +333,45 @@ int compress_host(bzg_ctx* ctx, const uint8_t* h_in, uint64_t n_bytes, uint32_t 
  */
 int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_out, uint64_t out_cap,
                uint64_t* d_out_bytes, void* stream);
+
+/*
+ * Light-weight field codecs (Sec. 2.1: per-field codes such as null
+ * suppression and Elias delta instead of a general-purpose compressor;
+ * Sec. 3.5: a GPU float compressor that subtracts a prediction and drops
+ * leading zero bytes), built on the same prefix sums as the bzip2 path:
+ * every value's code length, a scan to offsets, every code written at its
+ * offset (Figure 3).
+ *   BZG_FIELD_NS32     uint32 values: 2-bit byte count per value, then the
+ *                      significant bytes.
+ *   BZG_FIELD_EDELTA32 uint32 values v, coded as the Elias delta code of
+ *                      v + 1, with a bit-offset index every 1024 values so
+ *                      that decoding runs piece by piece in parallel.
+ *   BZG_FIELD_GFC64    doubles (any 64-bit patterns): residual against the
+ *                      previous value, sign and leading-zero-byte count in a
+ *                      4-bit code, then the remaining bytes; decoding adds
+ *                      the residuals up with a scan.
+ * The stream layouts are given in fields.hip.  Both calls enqueue on
+ * `stream` and take their scratch from the context's pool.
+ */
+enum { BZG_FIELD_NS32 = 1, BZG_FIELD_EDELTA32 = 2, BZG_FIELD_GFC64 = 3 };
+
+/* Largest stream field_encode can write for n_values values of `codec` (0
+ * for an unknown codec). */
+uint64_t bzg_field_bound(int codec, uint64_t n_values);
+
+/* d_values: n_values values (uint32, or 8-byte doubles for GFC64), 4- or
+ * 8-byte aligned.  d_out: out_cap bytes, 8-byte aligned, at least
+ * bzg_field_bound() (else BZG_ECAPACITY before anything is enqueued).
+ * d_out_bytes: device uint64 output, the stream length. */
+int field_encode(bzg_ctx* ctx, int codec, const void* d_values, uint64_t n_values, uint8_t* d_out, uint64_t out_cap,
+                 uint64_t* d_out_bytes, void* stream);
+
+/* d_in: a stream of in_bytes bytes (8-byte aligned) holding n_values values
+ * of `codec`; d_values receives them.  A stream whose count or lengths do
+ * not fit in_bytes is reported as BZG_EDATA by bzg_check (the output is then
+ * not meaningful). */
+int field_decode(bzg_ctx* ctx, int codec, const uint8_t* d_in, uint64_t in_bytes, void* d_values, uint64_t n_values,
+                 void* stream);
 
 /*
  * Diagnostics: per-kernel timing.  While enabled, every instrumented launch

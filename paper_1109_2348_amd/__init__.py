@@ -7,4 +7,5 @@ ABI in include/bzgpu.h.
 
 from . import native  # noqa: F401
 from .native import (BzgError, Compressor, Context, bwt, compress, compress_bound, compress_host, decompress,  # noqa: F401
-                     context, fixed_tables_from_sample, huffman, mtf, uniform_offsets)
+                     context, field_decode, field_encode, fixed_tables_from_sample, huffman, mtf,
+                     uniform_offsets)

@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libbzgpu.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["scan.hip", "plan.hip", "crc_rle1.hip", "bwt.hip", "mtf.hip", "huff.hip", "pack.hip", "decode.hip", "capi.hip"]
+SOURCES = ["scan.hip", "plan.hip", "crc_rle1.hip", "bwt.hip", "mtf.hip", "huff.hip", "pack.hip", "decode.hip", "fields.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

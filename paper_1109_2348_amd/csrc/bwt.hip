@@ -842,13 +842,13 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // costs its slowest wave at most this many steps per radix pass the tile
 // would otherwise run (a counting step of 64 rows and a radix pass over 64
 // rows cost about this much in issued instructions, measured as counters).
-constexpr uint32_t COUNT_STEPS_PER_PASS = 48;
+constexpr uint32_t COUNT_STEPS_PER_PASS = 48;  // (the built-in choice; a context may set another)
 
 __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec* __restrict__ segs,
                                 uint32_t* __restrict__ head, const uint32_t* __restrict__ blk_off,
                                 const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
                                 uint32_t* __restrict__ rank, uint32_t h_next, const uint8_t* __restrict__ text,
-                                const AppendCtx& app) {
+                                const AppendCtx& app, uint32_t count_steps) {
   const bool text_mode = text != nullptr;
   const uint32_t h = h_next / 2;
   __shared__ uint32_t mark[SMALL_CAP];
@@ -881,7 +881,7 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
     if (lane() == 0) atomicMax(&s_cost, steps);
   }
   __syncthreads();
-  const bool counting = s_cost <= COUNT_STEPS_PER_PASS * (uint32_t)npass_radix;
+  const bool counting = s_cost <= count_steps * (uint32_t)npass_radix;
   // load (segment start << 21 | key2, SA value).  Positions before the
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
@@ -1109,10 +1109,11 @@ __global__ __launch_bounds__(NT, 4) void k_small_sort(const SegRec* __restrict__
                                                    const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
                                                    uint32_t* __restrict__ rank, uint32_t h_next,
-                                                   const uint8_t* __restrict__ text, AppendCtx app) {
+                                                   const uint8_t* __restrict__ text, AppendCtx app,
+                                                   uint32_t count_steps) {
   const RoundSizes z = round_sizes(cnt, head_cap, owner_cap);
   for (TileLoop it = tile_loop(z.nsmall); it.t < it.end; it.t += it.step) {
-    small_sort_tile(it.t, z.small_total, segs, head, blk_off, key2, SA, rank, h_next, text, app);
+    small_sort_tile(it.t, z.small_total, segs, head, blk_off, key2, SA, rank, h_next, text, app, count_steps);
     __syncthreads();
   }
 }
@@ -1287,6 +1288,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
   const uint32_t Gs = resident_grid((const void*)k_small_sort, NT);
   const uint32_t Ga = resident_grid((const void*)k_rename_a, NT);
   const uint32_t Gb = resident_grid((const void*)k_rename_b, NT);
+  const uint32_t count_steps = g_tune && g_tune->count_steps ? g_tune->count_steps : COUNT_STEPS_PER_PASS;
   hipError_t e;
 #define BZG_TRY(x)                  \
   do {                              \
@@ -1361,7 +1363,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     {
       ProfScope ps("small_sort", st, 0, small_rows, 16.0);  // key2 and row in, row and rank out
       hipLaunchKernelGGL(k_small_sort, dim3(Gs), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cc], hcap, ocap,
-                         d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2);
+                         d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2, count_steps);
     }
     uint32_t *kin, *vin;
     BZG_TRY(radix_passes(w, ocap, big_tiles, big_rows, w.segs[cur], w.owner[cur], text_round ? 4 : rank_passes,

@@ -6,7 +6,10 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -49,6 +52,7 @@ hipError_t tables_export(uint32_t, const void*, uint8_t*, hipStream_t);
 namespace bzg {
 
 thread_local Profiler* g_prof = nullptr;
+thread_local const Tune* g_tune = nullptr;
 
 ProfScope::ProfScope(const char* name, hipStream_t s, double bytes, const uint32_t* count0, double per0,
                      const uint32_t* count1, double per1)
@@ -134,6 +138,12 @@ struct bzg_ctx {
   bool stage_used[2] = {false, false};
   int stage_next = 0;
   void* scratch = nullptr;  // this device's copy of `scratch`
+  // launch parameters: set explicitly (bzg_set_tune), or per size bucket
+  // from bzg_tune and the tune cache file
+  Tune tune;
+  bool tune_set = false;
+  std::map<uint32_t, Tune> tune_table;
+  std::string tune_path, tune_id;
   // precomputed Huffman tables (bzg_set_fixed_tables): MAXG x MAXA lengths
   uint8_t* fixed_tab = nullptr;
   int fixed_g = 0;
@@ -227,6 +237,27 @@ bool offsets_ok(const uint64_t* h, uint32_t nb) {
 struct ProfGuard {
   explicit ProfGuard(bzg_ctx* x) { g_prof = &x->prof; }
   ~ProfGuard() { g_prof = nullptr; }
+};
+
+// The launch parameters of a call over `total` bytes in `nb` blocks: the
+// explicit ones, else the tuned entry of its size bucket, else the built-in
+// choices (null).
+uint32_t tune_bucket(uint64_t total, uint32_t nb) {
+  uint32_t a = 0, b = 0;
+  while (a < 63 && (2ull << a) <= total) a++;
+  while (b < 31 && (2u << b) <= nb) b++;
+  return (a << 8) | b;
+}
+const Tune* pick_tune(bzg_ctx* c, uint64_t total, uint32_t nb) {
+  if (c->tune_set) return &c->tune;
+  auto it = c->tune_table.find(tune_bucket(total, nb));
+  return it == c->tune_table.end() ? nullptr : &it->second;
+}
+struct TuneGuard {
+  TuneGuard(bzg_ctx* c, const uint64_t* h_off, uint32_t nb) {
+    g_tune = pick_tune(c, nb && h_off ? h_off[nb] - h_off[0] : 0, nb);
+  }
+  ~TuneGuard() { g_tune = nullptr; }
 };
 
 // Workspace for a call: the caller's, or the context's pool (grown in
@@ -581,6 +612,7 @@ int compress_common(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offsets
                     uint8_t* d_out, const uint64_t* d_rout, const uint64_t* h_rout, uint64_t out_cap,
                     uint64_t* d_out_bytes, uint32_t* d_n_blocks, void* d_ws, size_t ws_bytes, hipStream_t st) {
   HIPX(hipSetDevice(ctx->device));
+  TuneGuard tg(ctx, h_offsets, n_blocks);
   const uint64_t zero_off = 0;
   const uint64_t* hoff = n_blocks ? h_offsets : &zero_off;
   const CBounds c = compress_bounds(hoff, n_blocks, level, h_rb, n_req);
@@ -637,6 +669,60 @@ int status_result(bzg_ctx* ctx) {
   return fail(ctx, BZG_ECAPACITY, "an output range was too small; nothing was packed");
 }
 
+// Tune cache: a JSON object, one entry per line,
+//   "<arch>|<HIP runtime version>|<bucket>": {"mtf_chunk": M, "assign_groups": A, "count_steps": C, "ms": T},
+// where bucket = floor(log2 bytes) * 256 + floor(log2 blocks).  Entries of
+// other devices and runtimes are kept in the file but not used.
+void load_tune_cache(bzg_ctx* ctx) {
+  std::ifstream f(ctx->tune_path);
+  std::string line;
+  while (std::getline(f, line)) {
+    char key[256];
+    unsigned m = 0, a = 0, c = 0;
+    if (sscanf(line.c_str(), " \"%255[^\"]\": {\"mtf_chunk\": %u, \"assign_groups\": %u, \"count_steps\": %u", key, &m,
+               &a, &c) != 4)
+      continue;
+    const std::string k = key;
+    const size_t bar = k.rfind('|');
+    if (bar == std::string::npos || k.substr(0, bar) != ctx->tune_id) continue;
+    Tune t;
+    t.mtf_chunk = m;
+    t.assign_groups = a;
+    t.count_steps = c;
+    ctx->tune_table[(uint32_t)std::stoul(k.substr(bar + 1))] = t;
+  }
+}
+
+int save_tune_entry(bzg_ctx* ctx, uint32_t bucket, const Tune& t, double ms) {
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(ctx->tune_path);
+    std::string line;
+    while (std::getline(f, line))
+      if (line.find("\"mtf_chunk\"") != std::string::npos) {
+        while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+        lines.push_back(line);
+      }
+  }
+  const std::string key = ctx->tune_id + "|" + std::to_string(bucket);
+  char buf[512];
+  snprintf(buf, sizeof(buf), "  \"%s\": {\"mtf_chunk\": %u, \"assign_groups\": %u, \"count_steps\": %u, \"ms\": %.4f}",
+           key.c_str(), t.mtf_chunk, t.assign_groups, t.count_steps, ms);
+  bool replaced = false;
+  for (std::string& l : lines)
+    if (l.find("\"" + key + "\"") != std::string::npos) {
+      l = buf;
+      replaced = true;
+    }
+  if (!replaced) lines.push_back(buf);
+  std::ofstream o(ctx->tune_path, std::ios::trunc);
+  if (!o) return fail(ctx, BZG_EINVAL, "cannot write the tune cache " + ctx->tune_path);
+  o << "{\n";
+  for (size_t i = 0; i < lines.size(); i++) o << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+  o << "}\n";
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -668,7 +754,20 @@ int bzg_create(bzg_ctx** out, int hip_device, const char* tune_cache_path) {
     bzg_destroy(ctx);
     return BZG_EHIP;
   }
-  (void)tune_cache_path;
+  {
+    hipDeviceProp_t prop{};
+    int rv = 0;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && hipRuntimeGetVersion(&rv) == hipSuccess) {
+      std::string arch = prop.gcnArchName;
+      arch = arch.substr(0, arch.find(':'));
+      ctx->tune_id = arch + "|" + std::to_string(rv);
+    }
+    (void)hipGetLastError();
+  }
+  if (tune_cache_path && *tune_cache_path) {
+    ctx->tune_path = tune_cache_path;
+    load_tune_cache(ctx);
+  }
   *out = ctx;
   return 0;
 }
@@ -836,7 +935,8 @@ size_t carve_stage(char* base, const SBounds& b, int call, SWork& w, size_t tota
   w.sort_tile0 = cv.take<uint32_t>(nb + 1);
   w.chunk0 = cv.take<uint32_t>(nb + 1);
   w.chunk_blk = cv.take<uint32_t>(call == BZG_CALL_MTF ? b.chunks + 1 : 1);
-  w.freq = cv.take<uint32_t>(call == BZG_CALL_HUFFMAN ? (size_t)nb * MAXA : 1);
+  // symbol counts per block: written by the MTF stage, read by the Huffman one
+  w.freq = cv.take<uint32_t>(call == BZG_CALL_HUFFMAN || call == BZG_CALL_MTF ? (size_t)nb * MAXA : 1);
   w.ns_eff = cv.take<uint32_t>(nb);
   w.selb = cv.take<uint64_t>(nb + 1);
   w.asg_tile0 = cv.take<uint32_t>(nb + 1);
@@ -894,6 +994,7 @@ int bzg_workspace_size(bzg_ctx* ctx, int call, const uint64_t* h_offsets, uint32
   if (!ctx || !bytes || !h_offsets) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
+  TuneGuard tg(ctx, h_offsets, n_blocks);
   if (n_blocks && !offsets_ok(h_offsets, n_blocks)) return fail(ctx, BZG_EINVAL, "offsets decrease");
   if (call == BZG_CALL_COMPRESS) {
     if (level < 1 || level > 9) return fail(ctx, BZG_EINVAL, "level must be 1..9");
@@ -918,6 +1019,7 @@ int bwt_forward_batch(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d_offse
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
+  TuneGuard tg(ctx, h_offsets, n_blocks);
   ProfGuard pg(ctx);
   if (!h_offsets || !d_bwt || !d_primary || (n_blocks && !d_in)) return fail(ctx, BZG_EINVAL, "null pointer");
   if (n_blocks == 0) return 0;
@@ -954,6 +1056,7 @@ int mtf_encode_batch(bzg_ctx* ctx, const uint8_t* d_bwt, const uint64_t* d_offse
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
+  TuneGuard tg(ctx, h_offsets, n_blocks);
   ProfGuard pg(ctx);
   if (!h_offsets || !d_syms || !d_nsyms || !d_inuse || (n_blocks && !d_bwt))
     return fail(ctx, BZG_EINVAL, "null pointer");
@@ -990,6 +1093,7 @@ int huffman_encode_batch(bzg_ctx* ctx, const uint16_t* d_syms, const uint32_t* d
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
+  TuneGuard tg(ctx, h_sym_offsets, n_blocks);
   ProfGuard pg(ctx);
   if (!h_sym_offsets || !h_out_offsets || !d_nbits || (n_blocks && (!d_syms || !d_nsyms || !d_inuse || !d_out)))
     return fail(ctx, BZG_EINVAL, "null pointer");
@@ -1111,6 +1215,7 @@ int compress_blocks_noalloc(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* d
   if (!ctx) return BZG_EINVAL;
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->err.clear();
+  TuneGuard tg(ctx, h_offsets, n_blocks);
   if (!d_out || !d_out_bytes || !d_offsets) return fail(ctx, BZG_EINVAL, "null pointer (d_offsets is required)");
   int rc = check_compress(ctx, d_in, h_offsets, n_blocks, level);
   if (rc) return rc;
@@ -1487,6 +1592,194 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   HIPX(rle1_blocks(nb, misc[2], d.out_off, ctx->crc_tab + CRC_POW_AT, misc[5], misc[6], misc[7], misc[8], misc[9], st));
   HIPX(dec_check(nb, misc[9], d.crc_want, ns, misc[0], misc[1], d.skip, ctx->status, st));
   return end_ws(ctx, nullptr, st);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ field codecs
+
+extern "C" {
+
+uint64_t bzg_field_bound(int codec, uint64_t n_values) {
+  if (codec < BZG_FIELD_NS32 || codec > BZG_FIELD_GFC64) return 0;
+  return field_bound(codec, n_values);
+}
+
+int field_encode(bzg_ctx* ctx, int codec, const void* d_values, uint64_t n_values, uint8_t* d_out, uint64_t out_cap,
+                 uint64_t* d_out_bytes, void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  ProfGuard pg(ctx);
+  if (codec < BZG_FIELD_NS32 || codec > BZG_FIELD_GFC64) return fail(ctx, BZG_EINVAL, "unknown codec");
+  if (!d_out || !d_out_bytes || (n_values && !d_values)) return fail(ctx, BZG_EINVAL, "null pointer");
+  if (((uintptr_t)d_out & 7) || ((uintptr_t)d_values & (codec == BZG_FIELD_GFC64 ? 7 : 3)))
+    return fail(ctx, BZG_EINVAL, "misaligned buffer");
+  if (n_values >= (1ull << 34)) return fail(ctx, BZG_EINVAL, "too many values");
+  if (out_cap < field_bound(codec, n_values))
+    return fail(ctx, BZG_ECAPACITY, "out_cap below bzg_field_bound(): " + std::to_string(field_bound(codec, n_values)));
+  HIPX(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t nt = field_tiles(n_values);
+  void* ws;
+  int rc = get_ws(ctx, nullptr, 0, 16 * (nt + 1) + 512, st, &ws);
+  if (rc) return rc;
+  Carve cv{(char*)ws};
+  uint64_t* tsum = cv.take<uint64_t>(nt + 1);
+  uint64_t* toff = cv.take<uint64_t>(nt + 1);
+  HIPX(field_encode_run(codec, d_values, n_values, d_out, d_out_bytes, tsum, toff, st));
+  return end_ws(ctx, nullptr, st);
+}
+
+int field_decode(bzg_ctx* ctx, int codec, const uint8_t* d_in, uint64_t in_bytes, void* d_values, uint64_t n_values,
+                 void* stream) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  ProfGuard pg(ctx);
+  if (codec < BZG_FIELD_NS32 || codec > BZG_FIELD_GFC64) return fail(ctx, BZG_EINVAL, "unknown codec");
+  if (!d_in || (n_values && !d_values)) return fail(ctx, BZG_EINVAL, "null pointer");
+  if (((uintptr_t)d_in & 7) || ((uintptr_t)d_values & (codec == BZG_FIELD_GFC64 ? 7 : 3)))
+    return fail(ctx, BZG_EINVAL, "misaligned buffer");
+  if (n_values >= (1ull << 34)) return fail(ctx, BZG_EINVAL, "too many values");
+  // the fixed-size parts must be there: header, codes or index
+  const uint64_t fixed = codec == BZG_FIELD_NS32 ? 8 + (n_values + 3) / 4
+                         : codec == BZG_FIELD_GFC64 ? 8 + (n_values + 1) / 2
+                                                    : 16 + 8 * ((n_values + 1023) / 1024);
+  if (in_bytes < fixed) return fail(ctx, BZG_EDATA, "stream shorter than its fixed part");
+  if (n_values == 0) return 0;
+  HIPX(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t nt = field_tiles(n_values);
+  void* ws;
+  int rc = get_ws(ctx, nullptr, 0, 32 * (nt + 1) + 1024, st, &ws);
+  if (rc) return rc;
+  Carve cv{(char*)ws};
+  uint64_t* tsum = cv.take<uint64_t>(nt + 1);
+  uint64_t* boff = cv.take<uint64_t>(nt + 1);
+  uint64_t* rsum = cv.take<uint64_t>(nt + 1);
+  uint64_t* roff = cv.take<uint64_t>(nt + 1);
+  HIPX(field_decode_run(codec, d_in, in_bytes, n_values, d_values, tsum, boff, rsum, roff, ctx->status, st));
+  return end_ws(ctx, nullptr, st);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ tuning
+
+extern "C" {
+
+int bzg_set_tune(bzg_ctx* ctx, uint32_t mtf_chunk, uint32_t assign_groups, uint32_t count_steps) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if ((mtf_chunk && mtf_chunk != 2048 && mtf_chunk != 4096) ||
+      (assign_groups && assign_groups != 128 && assign_groups != 512) || count_steps > 1024)
+    return fail(ctx, BZG_EINVAL, "mtf_chunk 0/2048/4096, assign_groups 0/128/512, count_steps 0..1024");
+  ctx->tune.mtf_chunk = mtf_chunk;
+  ctx->tune.assign_groups = assign_groups;
+  ctx->tune.count_steps = count_steps;
+  ctx->tune_set = mtf_chunk || assign_groups || count_steps;
+  return 0;
+}
+
+int bzg_tune(bzg_ctx* ctx, const uint8_t* d_in, const uint64_t* h_offsets, uint32_t n_blocks, int level, void* stream,
+             uint32_t* h_chosen) {
+  if (!ctx) return BZG_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!h_offsets || !n_blocks) return fail(ctx, BZG_EINVAL, "no blocks");
+  int rc = check_compress(ctx, d_in, h_offsets, n_blocks, level);
+  if (rc) return rc;
+  HIPX(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t total = h_offsets[n_blocks] - h_offsets[0];
+  const uint64_t cap = (compress_bound(total, n_blocks) + 255) & ~uint64_t(255);
+  uint8_t* out[2] = {nullptr, nullptr};
+  uint64_t* nbytes = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (uint8_t* p : out)
+      if (p) (void)hipFree(p);
+    if (nbytes) (void)hipFree(nbytes);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc((void**)&out[0], cap) != hipSuccess || hipMalloc((void**)&out[1], cap) != hipSuccess ||
+      hipMalloc((void**)&nbytes, 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(ctx, BZG_ENOMEM, "tuning buffers");
+  }
+  const Tune saved = ctx->tune;
+  const bool saved_set = ctx->tune_set;
+  std::vector<uint8_t> ref, got;
+  uint64_t ref_n = 0;
+  Tune best;
+  double best_ms = 1e30;
+  int points = 0;
+  rc = 0;
+  // every point must give the same bytes as the first (the built-in choices)
+  for (uint32_t cs : {48u, 24u, 96u})
+    for (uint32_t mc : {4096u, 2048u})
+      for (uint32_t ag : {512u, 128u}) {
+        if (rc) break;
+        ctx->tune = Tune{mc, ag, cs};
+        ctx->tune_set = true;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3 && !rc; rep++) {
+          (void)hipEventRecord(e0, st);
+          rc = compress_common(ctx, d_in, nullptr, h_offsets, n_blocks, nullptr, nullptr, 1, level, out[points ? 1 : 0],
+                               nullptr, nullptr, cap, nbytes + (points ? 1 : 0), nullptr, nullptr, 0, st);
+          (void)hipEventRecord(e1, st);
+          if (rc) break;
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = hip_fail(ctx, hipGetLastError(), "tune timing");
+            break;
+          }
+          float t = 0;
+          (void)hipEventElapsedTime(&t, e0, e1);
+          ms = std::min(ms, t);
+        }
+        if (rc) break;
+        if ((rc = status_result(ctx))) break;
+        uint64_t n = 0;
+        if (hipMemcpy(&n, nbytes + (points ? 1 : 0), 8, hipMemcpyDeviceToHost) != hipSuccess) {
+          rc = hip_fail(ctx, hipGetLastError(), "tune read-back");
+          break;
+        }
+        std::vector<uint8_t>& dst = points ? got : ref;
+        dst.resize(n);
+        if (n && hipMemcpy(dst.data(), out[points ? 1 : 0], n, hipMemcpyDeviceToHost) != hipSuccess) {
+          rc = hip_fail(ctx, hipGetLastError(), "tune read-back");
+          break;
+        }
+        if (points == 0) ref_n = n;
+        if (points && (n != ref_n || memcmp(got.data(), ref.data(), n) != 0)) {
+          rc = fail(ctx, BZG_EINTERNAL, "a tuning point changed the output bytes");
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = ctx->tune;
+        }
+        points++;
+      }
+  ctx->tune = saved;
+  ctx->tune_set = saved_set;
+  cleanup();
+  if (rc) return rc;
+  const uint32_t bucket = tune_bucket(total, n_blocks);
+  ctx->tune_table[bucket] = best;
+  if (h_chosen) {
+    h_chosen[0] = best.mtf_chunk;
+    h_chosen[1] = best.assign_groups;
+    h_chosen[2] = best.count_steps;
+  }
+  if (!ctx->tune_path.empty()) return save_tune_entry(ctx, bucket, best, best_ms);
+  return 0;
 }
 
 }  // extern "C"

@@ -702,6 +702,10 @@ hipError_t huff_run(const HuffArgs& a, hipStream_t st) {
 
 // Groups per assign tile for a call with ng groups in all: smaller tiles
 // when the large ones would leave most of the GPU idle.
-uint32_t huff_assign_groups(uint64_t ng) { return ng >= 1024ull * ASSIGN_GROUPS ? ASSIGN_GROUPS : ASSIGN_GROUPS_SMALL; }
+uint32_t huff_assign_groups(uint64_t ng) {
+  if (g_tune && (g_tune->assign_groups == ASSIGN_GROUPS || g_tune->assign_groups == ASSIGN_GROUPS_SMALL))
+    return g_tune->assign_groups;
+  return ng >= 1024ull * ASSIGN_GROUPS ? ASSIGN_GROUPS : ASSIGN_GROUPS_SMALL;
+}
 
 }  // namespace bzg

@@ -48,6 +48,16 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Launch parameters a context may set (bzg_set_tune, bzg_tune); every choice
+// gives identical output.  0 = the built-in choice.  The API calls point
+// g_tune at their context's values for the time they enqueue.
+struct Tune {
+  uint32_t mtf_chunk = 0;      // MTF rows per chunk: 2048 or 4096
+  uint32_t assign_groups = 0;  // Huffman selector groups per assign tile: 128 or 512
+  uint32_t count_steps = 0;    // small-segment sort: counting steps allowed per radix pass
+};
+extern thread_local const Tune* g_tune;
+
 // Tuning constants (fixed; every choice gives identical output).
 constexpr int NT = 256;                // threads per workgroup
 constexpr uint32_t RADIX_TILE = 4096;  // elements per tile of a segment radix pass
@@ -291,6 +301,14 @@ hipError_t dec_run(const DecRun& d, hipStream_t st);
 hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
                      const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
                      hipStream_t st);
+
+// Field codecs (fields.hip); codec ids as in the public header.
+uint64_t field_bound(int codec, uint64_t n);
+uint64_t field_tiles(uint64_t n);
+hipError_t field_encode_run(int codec, const void* vals, uint64_t n, uint8_t* out, uint64_t* out_bytes,
+                            uint64_t* tile_sum, uint64_t* tile_off, hipStream_t st);
+hipError_t field_decode_run(int codec, const uint8_t* z, uint64_t in_bytes, uint64_t n, void* vals, uint64_t* tile_sum,
+                            uint64_t* byte_off, uint64_t* res_sum, uint64_t* res_off, uint32_t* err, hipStream_t st);
 
 size_t bwt_workspace_bytes(uint32_t N, uint32_t nb);
 bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w);

@@ -745,6 +745,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_mtf_emit(const uint8_t* __restrict
 
 // Chunk rows for a call of at most `rows` rows in `nb` blocks.
 uint32_t mtf_chunk_rows(uint64_t rows, uint32_t nb) {
+  if (g_tune && (g_tune->mtf_chunk == MTF_CHUNK || g_tune->mtf_chunk == MTF_CHUNK_SMALL)) return g_tune->mtf_chunk;
   return (rows / MTF_CHUNK + nb) < MTF_FEW_CHUNKS ? MTF_CHUNK_SMALL : MTF_CHUNK;
 }
 static uint64_t chunk_bound(uint64_t rows, uint32_t nb, uint32_t ch) { return rows / ch + nb + 1; }

@@ -65,6 +65,16 @@ def lib() -> C.CDLL:
         L.compress_blocks_noalloc.argtypes = [vp, vp, vp, u64p, u32, i, vp, u64, vp, vp, vp]
         L.decompress.restype = i
         L.decompress.argtypes = [vp, vp, u64, vp, u64, vp, vp]
+        L.bzg_set_tune.restype = i
+        L.bzg_set_tune.argtypes = [vp, u32, u32, u32]
+        L.bzg_tune.restype = i
+        L.bzg_tune.argtypes = [vp, vp, u64p, u32, i, vp, u32p]
+        L.bzg_field_bound.restype = u64
+        L.bzg_field_bound.argtypes = [i, u64]
+        L.field_encode.restype = i
+        L.field_encode.argtypes = [vp, i, vp, u64, vp, u64, vp, vp]
+        L.field_decode.restype = i
+        L.field_decode.argtypes = [vp, i, vp, u64, vp, u64, vp]
         L.bzg_set_fixed_tables.restype = i
         L.bzg_set_fixed_tables.argtypes = [vp, vp, i]
         L.compress_host.restype = i
@@ -79,8 +89,8 @@ def lib() -> C.CDLL:
 
 EXPORTS = ("bzg_create", "bzg_destroy", "bzg_last_error", "bzg_check", "bzg_workspace_size", "bzg_compress_bound",
            "bwt_forward_batch", "mtf_encode_batch", "huffman_encode_batch", "compress_blocks", "compress_batch",
-           "compress_blocks_noalloc", "compress_host", "bzg_set_fixed_tables", "decompress", "bzg_profile",
-           "bzg_profile_read")
+           "compress_blocks_noalloc", "compress_host", "bzg_set_fixed_tables", "decompress", "bzg_field_bound",
+           "field_encode", "field_decode", "bzg_set_tune", "bzg_tune", "bzg_profile", "bzg_profile_read")
 
 
 class Profile:
@@ -133,6 +143,20 @@ class Context:
     def sync_check(self, stream: C.c_void_p):
         """Waits for the stream and raises the errors the kernels recorded."""
         self.check(lib().bzg_check(self.h, stream))
+
+    def set_tune(self, mtf_chunk: int = 0, assign_groups: int = 0, count_steps: int = 0):
+        """Fixes the launch parameters (0 = tuned or built-in choice)."""
+        self.check(lib().bzg_set_tune(self.h, mtf_chunk, assign_groups, count_steps))
+
+    def tune(self, x: torch.Tensor, offsets, level: int = 9) -> Tuple[int, int, int]:
+        """Times every launch-parameter point on this batch (outputs checked
+        byte for byte) and keeps the fastest for its size bucket (and in the
+        tune cache file, when the context has one)."""
+        x = _dev_u8(x)
+        o = _offs(offsets)
+        chosen = (C.c_uint32 * 3)()
+        self.check(lib().bzg_tune(self.h, _vp(x), _u64p(o), o.size - 1, level, _stream(x.device), chosen))
+        return tuple(int(v) for v in chosen)
 
     def set_fixed_tables(self, lens: Optional[np.ndarray]):
         """Precomputed Huffman tables (G x 258 code lengths, G = 2..6) for
@@ -468,4 +492,41 @@ def decompress(z: torch.Tensor, out_cap: Optional[int] = None, ctx: Optional[Con
             continue
         return out[: int(nbytes.item())]
     raise BzgError(BZG_ECAPACITY, "output size changed between attempts")
+
+
+FIELD_NS32, FIELD_EDELTA32, FIELD_GFC64 = 1, 2, 3
+
+
+def field_encode(values: torch.Tensor, codec: int, ctx: Optional[Context] = None) -> torch.Tensor:
+    """One field of values (uint32 / int32 for NS32 and EDELTA32, float64 for
+    GFC64) as a compressed stream (uint8 tensor on the same device)."""
+    if not values.is_cuda:
+        raise TypeError("values must be on the GPU")
+    want = torch.float64 if codec == FIELD_GFC64 else (torch.int32, torch.uint32)
+    if (values.dtype != want) if codec == FIELD_GFC64 else (values.dtype not in want):
+        raise TypeError("values of the wrong type for this codec")
+    v = values.contiguous()
+    n = v.numel()
+    ctx = ctx or context(v.device.index)
+    cap = int(lib().bzg_field_bound(codec, n))
+    out = torch.empty((cap + 7) // 8 * 8, dtype=torch.uint8, device=v.device)
+    nb = torch.zeros(1, dtype=torch.int64, device=v.device)
+    st = _stream(v.device)
+    ctx.check(lib().field_encode(ctx.h, codec, _vp(v) if n else None, n, _vp(out), out.numel(), _vp(nb), st))
+    ctx.sync_check(st)
+    return out[: int(nb.item())]
+
+
+def field_decode(z: torch.Tensor, codec: int, n: int, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Decodes n values of a field stream (int32 values, or float64 for GFC64)."""
+    z = _dev_u8(z)
+    zz = torch.empty((z.numel() + 7) // 8 * 8, dtype=torch.uint8, device=z.device)  # 8-byte aligned copy
+    zz[: z.numel()] = z
+    ctx = ctx or context(z.device.index)
+    dt = torch.float64 if codec == FIELD_GFC64 else torch.int32
+    out = torch.empty(max(n, 1), dtype=dt, device=z.device)
+    st = _stream(z.device)
+    ctx.check(lib().field_decode(ctx.h, codec, _vp(zz), z.numel(), _vp(out), n, st))
+    ctx.sync_check(st)
+    return out[:n]
 

@@ -147,6 +147,19 @@ def test_mtf_bwt_columns(bz):
     _check_mtf(bz, Ls, "BWT columns of uniform/text/sparse")
 
 
+def test_mtf_many_blocks_full_alphabet(bz):
+    # enough blocks and rows for 4096-row chunks; every byte in use in the
+    # first block (the symbol counts of all blocks are written by the stage)
+    g = np.random.default_rng(41)
+    Ls = []
+    for k in range(24):
+        n = int(g.integers(20_000, 200_000))
+        runs = g.geometric(0.3 if k % 3 else 0.02, size=n)
+        vals = g.integers(0, 256 if k % 2 == 0 else 27, size=n).astype(np.uint8)
+        Ls.append(np.repeat(vals, runs)[:n])
+    _check_mtf(bz, Ls, "24 blocks with runs, 4096-row chunks")
+
+
 def _check_huff(bz, sym_lists, used_list, name):
     import torch
     _say(f"huffman {name}: {len(sym_lists)} blocks")
