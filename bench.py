@@ -212,6 +212,8 @@ def bench_compress(args, batch, level):
         extra["fixed_tables"] = _fixed_tables(args, bz, batch, level, x)
     if args.decompress:
         extra["decompress"] = _decompress(args, bz, z.clone(), batch)
+    if args.graph:
+        extra["graph_replay"] = _graph(args, batch, level, x, z.cpu())
     return _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extra or None)
 
 
@@ -235,6 +237,44 @@ def _fixed_tables(args, bz, batch, level, x):
     return {"value": round(args.steps * n_in / wall / 1e6, 2), "unit": "MB/s", "ms_per_step": round(wall / args.steps * 1e3, 3),
             "output_bytes": int(z.numel()), "ratio": round(int(z.numel()) / n_in, 4),
             "huffman_ms_per_step": round(huff_ms, 3), "sample_blocks": k}
+
+
+def _graph(args, batch, level, x, z_eager):
+    """The same call captured once into a HIP graph (device offsets and a
+    caller workspace: kernels only) and replayed: launch cost gone."""
+    import torch
+    from paper_1109_2348_amd import native
+    ctx = native.Context()
+    comp = native.Compressor(ctx=ctx)
+    o = np.ascontiguousarray(batch.offsets, dtype=np.uint64)
+    ws = torch.empty(ctx.workspace_size(native.CALL_COMPRESS, o, level=level), dtype=torch.uint8, device=x.device)
+    d_o = native._dev_u64(o, x.device)
+    side = torch.cuda.Stream(x.device)
+    side.wait_stream(torch.cuda.current_stream(x.device))
+    with torch.cuda.stream(side):  # one eager call sizes the output buffers
+        comp.enqueue(x, o, level, d_offsets=d_o, ws=ws)
+    torch.cuda.current_stream(x.device).wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        comp.enqueue(x, o, level, d_offsets=d_o, ws=ws)
+    log("graph replay")
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync_check(native._stream(x.device))
+    n = int(comp.out_bytes.item())
+    ok = n == z_eager.numel() and torch.equal(comp.out[:n].cpu(), z_eager)
+    if not ok:
+        log("ERROR: graph replay stream differs from the eager stream")
+        sys.exit(1)
+    return {"value": round(args.steps * int(batch.data.size) / wall / 1e6, 2), "unit": "MB/s",
+            "ms_per_step": round(wall / args.steps * 1e3, 3), "checked": "stream identical to the eager call"}
 
 
 def _decompress(args, bz, z, batch):
@@ -418,6 +458,7 @@ def main():
     ap.add_argument("--host-chunk-blocks", type=int, default=128, help="blocks per chunk for --host-input")
     ap.add_argument("--fixed-tables", action="store_true", help="configs 1, 2, 4: also time precomputed tables")
     ap.add_argument("--decompress", action="store_true", help="configs 1, 2, 4: also time GPU decompression")
+    ap.add_argument("--graph", action="store_true", help="configs 1, 2, 4: also time the call replayed as a HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",

@@ -8,20 +8,21 @@
 // order is rotation order.
 //
 //  init   rows start in descending start order; stable LSD radix per
-//         block on the first 4 cyclic bytes (big-endian); name groups.  The
-//         first pass builds the (key, row) pairs from a sequential read of
-//         the block's text; the other three move them as plain pairs, so no
-//         pass gathers at random.
+//         block on the first INIT_BYTES cyclic bytes (big-endian); name
+//         groups.  The first pass builds the (key, row) pairs from a
+//         sequential read of the block's text; the others move them as plain
+//         pairs, so no pass gathers at random.
 //  round  for every unresolved group (a "segment"), key2 = rank of the
-//         rotation h positions on; stable sort of the segment by key2; a new
-//         group starts where key2 changes; rank = row of its head.  Groups of
-//         one row are done; groups whose block length is <= the next h hold
-//         equal rotations and are done too.  h doubles.
-//  round 0 (h = 4) takes key2 from the text instead: the 4 bytes h
-//         positions on order those rotations exactly as their ranks would,
-//         and they come from the block's L2-resident text.  So the init
-//         naming ranks only the rows already alone in their group, and round
-//         0 ranks the rest.
+//         rotation h positions on (h = the prefix length the rotations are
+//         ordered by); stable sort of the segment by key2; a new group
+//         starts where key2 changes; rank = row of its head.  Groups of one
+//         row are done; groups whose block length is <= the new prefix hold
+//         equal rotations and are done too.  The prefix doubles.
+//  round 0 (h = INIT_BYTES) takes key2 from the text instead: the 4 bytes
+//         h positions on order those rotations exactly as their ranks would,
+//         and they come from the block's L2-resident text (the prefix grows
+//         by 4).  So the init naming ranks only the rows already alone in
+//         their group, and round 0 ranks the rest.
 //
 // Stable sorts from a descending start order leave equal rotations in
 // descending start order.  Segments of at most SMALL_MAX rows are packed into
@@ -118,10 +119,19 @@ __device__ __forceinline__ BigTile big_tile(uint32_t j, const SegRec* segs, cons
 }
 
 // Per-tile digit counts of one LSD pass: digit = (kin >> shift) & 255.
+// The init sort orders rotations by their first INIT_BYTES bytes (one LSD
+// pass each); the first doubling round then compares the 4 bytes after them
+// in the text, so rotations are ordered by INIT_BYTES + 4 bytes after it.
+// Four: with three, the pass saved (4.7 ms on 8192 uneven blocks) went back
+// into the first round's larger groups (4.8 ms).
+constexpr uint32_t INIT_BYTES = 4;
+constexpr uint32_t INIT_MASK = 0xFFFFFFFFu << (8 * (4 - INIT_BYTES));  // the key bits the init sort orders
+
 // INIT instantiates the init sort's passes (a kernel of their own for
-// profiling); its first pass (text != null, shift 0) reads the digit, byte 3
-// of each row's first 4 bytes, from the text instead (rows are in descending
-// start order, so the read is sequential).  Init segments are whole blocks.
+// profiling); its first pass (text != null) reads the digit, byte
+// INIT_BYTES - 1 of each row's first bytes, from the text instead (rows are
+// in descending start order, so the read is sequential).  Init segments are
+// whole blocks.
 template <bool INIT>
 __device__ void radix_hist_tile(uint32_t jt, const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                 const uint32_t* __restrict__ kin, int shift, uint32_t* __restrict__ hist,
@@ -146,7 +156,7 @@ __device__ void radix_hist_tile(uint32_t jt, const SegRec* __restrict__ segs, co
 #pragma unroll
     for (int i = 0; i < RI; i++) {
       const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
-      dg[i] = text[o + cyc(n - 1u - (k - o) + 3u, n)];
+      dg[i] = text[o + cyc(n - 1u - (k - o) + (INIT_BYTES - 1u), n)];
     }
   } else {
 #pragma unroll
@@ -193,9 +203,9 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const SegRec* __restrict__ se
 }
 
 // One stable LSD pass: (key, row) pairs move.  INIT instantiates the init
-// sort's passes; in its first (text != null, shift 0) rows come from the row
-// index, in descending start order, and each key is its row's first 4 bytes
-// (big-endian), read sequentially from the text.
+// sort's passes; in its first (text != null) rows come from the row index,
+// in descending start order, and each key is its row's first INIT_BYTES
+// bytes (big-endian, in the high bytes), read sequentially from the text.
 template <bool INIT>
 __device__ void radix_scatter_tile(uint32_t jt, const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
                                    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
@@ -226,7 +236,7 @@ __device__ void radix_scatter_tile(uint32_t jt, const SegRec* __restrict__ segs,
       const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
       const uint32_t pos = n - 1u - (k - o);
       val[i] = o + pos;
-      key[i] = text_key_value(tw[i], text, o, n, pos);
+      key[i] = text_key_value(tw[i], text, o, n, pos) & INIT_MASK;
     }
   } else {
 #pragma unroll
@@ -687,9 +697,9 @@ __device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head
 }
 
 // key2 of every row of every segment: the rank of the rotation h positions
-// on, relative to the block start; or (text != null, the first round, h = 4)
-// that rotation's first 4 bytes, which order rotations exactly as their
-// ranks after the init sort do.
+// on, relative to the block start; or (text != null, the first round,
+// h = INIT_BYTES) that rotation's first 4 bytes, which order the rows of a
+// group (equal in their first h bytes) by their first h + 4.
 // key2 of M rows from their partner positions p[i], local to the block at
 // bo[i] with bn[i] rows (ONE_BLOCK: all in the block bo[0], bn[0]): the
 // partner's rank relative to the block start, or (text != null) its first 4
@@ -847,10 +857,9 @@ constexpr uint32_t COUNT_STEPS_PER_PASS = 48;  // (the built-in choice; a contex
 __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec* __restrict__ segs,
                                 uint32_t* __restrict__ head, const uint32_t* __restrict__ blk_off,
                                 const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
-                                uint32_t* __restrict__ rank, uint32_t h_next, const uint8_t* __restrict__ text,
-                                const AppendCtx& app, uint32_t count_steps) {
+                                uint32_t* __restrict__ rank, uint32_t h, uint32_t h_next,
+                                const uint8_t* __restrict__ text, const AppendCtx& app, uint32_t count_steps) {
   const bool text_mode = text != nullptr;
-  const uint32_t h = h_next / 2;
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint32_t sval[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
@@ -1108,12 +1117,12 @@ __global__ __launch_bounds__(NT, 4) void k_small_sort(const SegRec* __restrict__
                                                    const RoundCounters* cnt, uint32_t head_cap, uint32_t owner_cap,
                                                    const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
-                                                   uint32_t* __restrict__ rank, uint32_t h_next,
+                                                   uint32_t* __restrict__ rank, uint32_t h, uint32_t h_next,
                                                    const uint8_t* __restrict__ text, AppendCtx app,
                                                    uint32_t count_steps) {
   const RoundSizes z = round_sizes(cnt, head_cap, owner_cap);
   for (TileLoop it = tile_loop(z.nsmall); it.t < it.end; it.t += it.step) {
-    small_sort_tile(it.t, z.small_total, segs, head, blk_off, key2, SA, rank, h_next, text, app, count_steps);
+    small_sort_tile(it.t, z.small_total, segs, head, blk_off, key2, SA, rank, h, h_next, text, app, count_steps);
     __syncthreads();
   }
 }
@@ -1232,12 +1241,14 @@ bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w) {
   return bump.used <= ws_bytes;
 }
 
-// Doubling rounds after the first sort: one per h = 4, 8, ... below the
-// longest block (after the round at h, rotations are ordered by 2h bytes,
-// and groups in blocks of at most 2h rows are finished).
+// Doubling rounds after the first sort, while the ordered prefix P is
+// shorter than the longest block: P = INIT_BYTES after the init sort,
+// INIT_BYTES + 4 after the first round (text), then doubling (groups in
+// blocks of at most P rows are then finished).
 int bwt_rounds(uint32_t max_len) {
   int r = 0;
-  for (uint64_t h = 4; h < max_len; h *= 2) r++;
+  for (uint64_t P = INIT_BYTES; P < max_len; P = r ? 2 * P : P + 4, r++) {
+  }
   return r;
 }
 
@@ -1302,16 +1313,23 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
   const uint32_t icap = std::min<uint32_t>(bd.init_tiles, (uint32_t)z.owner_cap);
   const uint32_t Gi = persist_grid(icap, ONE_TILE_EACH);  // first sort: one tile per workgroup
   const uint32_t Gsi = persist_grid(scan_dev_tiles((uint64_t)icap * 256), ONE_TILE_EACH);
-  // init: 4 LSD passes on the first 4 bytes of every rotation
+  // init: INIT_BYTES LSD passes on the first bytes of every rotation (the
+  // last pass writes w.key / w.SA)
   {
-    uint32_t* kout[4] = {w.tmpK, w.key, w.tmpK, w.key};
-    uint32_t* vout[4] = {w.tmpV, w.SA, w.tmpV, w.SA};
-    for (int p = 0; p < 4; p++) {
+    uint32_t* kout[INIT_BYTES];
+    uint32_t* vout[INIT_BYTES];
+    for (int p = 0; p < (int)INIT_BYTES; p++) {
+      const bool last_parity = ((int)INIT_BYTES - 1 - p) % 2 == 0;
+      kout[p] = last_parity ? w.key : w.tmpK;
+      vout[p] = last_parity ? w.SA : w.tmpV;
+    }
+    for (int p = 0; p < (int)INIT_BYTES; p++) {
       const uint32_t* ka = p ? kout[p - 1] : nullptr;
       const uint32_t* va = p ? vout[p - 1] : nullptr;
+      const int shift = 8 * (p + 4 - (int)INIT_BYTES);
       {
         ProfScope ps("init_hist", st, 0, rows, p ? 4.0 : 1.0);  // key in (pass 0: one text byte)
-        hipLaunchKernelGGL(k_radix_hist<true>, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], ka, 8 * p, w.hist,
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], ka, shift, w.hist,
                            p ? nullptr : text, init_tiles, icap);
       }
       {
@@ -1321,7 +1339,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
       // key and row in and out (pass 0: one text byte in per row)
       ProfScope ps("init_scatter", st, 0, rows, p ? 16.0 : 9.0);
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], ka, va, kout[p],
-                         vout[p], 8 * p, w.hist, p ? nullptr : text, init_tiles, icap);
+                         vout[p], shift, w.hist, p ? nullptr : text, init_tiles, icap);
     }
   }
   const uint32_t hcap = (uint32_t)z.head_cap, ocap = (uint32_t)z.owner_cap;
@@ -1335,7 +1353,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     ProfScope ps("rename_b", st, 0, rows, 12.0);  // key and row in, rank out
     // only rows alone in their group are ranked here: round 0 compares text
     hipLaunchKernelGGL(k_rename_b, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.SA, w.agg, d_off, w.SA,
-                       w.rank, 4u, 0, 0, app, init_tiles, icap);
+                       w.rank, INIT_BYTES, 0, 0, app, init_tiles, icap);
   }
   BZG_TRY(hipGetLastError());
   int bits = 1;
@@ -1344,10 +1362,13 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
   const int R = bwt_rounds(bd.max_len);
   int cur = 1;  // segment lists and head arrays: double-buffered
   int cc = 1;   // counter records: three, so a round clears the one it does not touch
-  uint32_t h = 4;
-  for (int r = 0; r < R; r++, h *= 2) {
+  uint32_t P = INIT_BYTES;  // the ordered prefix
+  for (int r = 0; r < R; r++) {
     const int nxt = cur ^ 1, cn = (cc + 1) % 3, cz = (cc + 2) % 3;
-    const bool text_round = h == 4;
+    const bool text_round = r == 0;
+    // partners h rows on; after the round rotations are ordered by Pn bytes
+    const uint32_t h = P, Pn = text_round ? P + 4 : 2 * P;
+    P = Pn;
     const uint32_t* big_tiles = (const uint32_t*)&w.cnt[cc].tiles_big;         // low word
     const uint32_t* small_rows = (const uint32_t*)&w.cnt[cc].segs_small + 1;   // high word
     const uint32_t* big_rows = (const uint32_t*)&w.cnt[cc].tiles_big + 1;      // high word
@@ -1363,7 +1384,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     {
       ProfScope ps("small_sort", st, 0, small_rows, 16.0);  // key2 and row in, row and rank out
       hipLaunchKernelGGL(k_small_sort, dim3(Gs), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cc], hcap, ocap,
-                         d_off, w.key, w.SA, w.rank, 2 * h, text_round ? text : nullptr, app2, count_steps);
+                         d_off, w.key, w.SA, w.rank, h, Pn, text_round ? text : nullptr, app2, count_steps);
     }
     uint32_t *kin, *vin;
     BZG_TRY(radix_passes(w, ocap, big_tiles, big_rows, w.segs[cur], w.owner[cur], text_round ? 4 : rank_passes,
@@ -1375,7 +1396,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     }
     ProfScope ps("rename_b", st, 0, big_rows, 16.0);
     hipLaunchKernelGGL(k_rename_b, dim3(Gb), dim3(NT), 0, st, w.segs[cur], w.owner[cur], kin, vin, w.agg, d_off, w.SA,
-                       w.rank, 2 * h, text_round ? 0 : 1, 1, app2, big_tiles, ocap);
+                       w.rank, Pn, text_round ? 0 : 1, 1, app2, big_tiles, ocap);
     BZG_TRY(hipGetLastError());
     cur = nxt;
     cc = cn;

@@ -1523,6 +1523,7 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   auto carve = [&](char* base, DecRun& r, uint32_t** misc) -> size_t {
     Carve cv{base};
     r.blks = cv.take<DecBlk>(nb);
+    r.order = cv.take<uint32_t>(nb);
     r.walk0 = cv.take<uint64_t>(nb + 1);
     r.rle0 = cv.take<uint64_t>(nb + 1);
     misc[0] = cv.take<uint32_t>(ns + 1);  // stream first blocks
@@ -1530,7 +1531,6 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     r.L = cv.take<uint8_t>(lsum + 64);
     r.T = cv.take<uint8_t>(lsum + 64);
     r.FL = cv.take<uint32_t>(lsum + 16);
-    r.sel = cv.take<uint8_t>((size_t)nb * dec_sel_stride());
     r.n_rows = cv.take<uint32_t>(nb);
     r.orig = cv.take<uint32_t>(nb);
     r.crc_want = cv.take<uint32_t>(nb);
@@ -1560,8 +1560,14 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   void* ws;
   if ((rc = get_ws(ctx, nullptr, 0, need, st, &ws))) return rc;
   carve((char*)ws, d, misc);
+  std::vector<uint32_t> order(nb);
+  for (uint32_t b = 0; b < nb; b++) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    return blocks[x].end - blocks[x].start > blocks[y].end - blocks[y].start;
+  });
   if ((rc = upload(ctx,
                    {{(void*)d.blks, blocks.data(), nb * sizeof(DecBlk)},
+                    {(void*)d.order, order.data(), nb * 4},
                     {(void*)d.walk0, walk0.data(), (nb + 1) * 8},
                     {(void*)d.rle0, rle0.data(), (nb + 1) * 8},
                     {misc[0], sb0.data(), (ns + 1) * 4},

@@ -129,24 +129,61 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
 
 // ------------------------------------------------------- block decoding
 
+// A value every lane holds alike (a table entry at a wave-uniform index),
+// moved to a scalar register so that branches on it stay scalar.
+template <typename T>
+__device__ __forceinline__ uint32_t uni(T v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+}
+
+// The bit stream is read through a window of 64 dwords, one per lane
+// (256 bytes, most significant bit first); the next window is loaded while
+// the current one is decoded, so the loop waits for memory only when it
+// moves to the next window, 2048 bits after that load was issued.  Refills
+// take the word from its lane with a lane read.  Past the input's end the
+// last byte is read again: such bits are never part of a block.
 struct BitIn {
   const uint8_t* in;
   uint64_t n;
-  uint64_t fetch;  // next byte to load
+  uint64_t wnext;  // first dword of the window being loaded
+  uint32_t cur;    // this lane's dword of the current window
+  uint32_t pb[4];  // this lane's bytes of the next window, as loaded
+  uint32_t pos;    // next dword of the current window
   uint64_t buf;    // bits not yet used, from the top
   int nb;          // how many
   uint64_t used;   // bits consumed
-  __device__ __forceinline__ uint32_t word(uint64_t b) const {
-    uint32_t v = 0;
+  __device__ __forceinline__ void load_next() {
+    const uint64_t q = 4 * (wnext + lane());
 #pragma unroll
-    for (int i = 0; i < 4; i++) v = (v << 8) | (b + i < n ? in[b + i] : 0u);
-    return v;
+    for (int i = 0; i < 4; i++) pb[i] = in[min(q + i, n - 1)];
+    wnext += BZG_WAVE;
+  }
+  __device__ __forceinline__ uint32_t joined() const { return (pb[0] << 24) | (pb[1] << 16) | (pb[2] << 8) | pb[3]; }
+  // position the reader at bit `bit` of the input
+  __device__ __forceinline__ void start(uint64_t bit) {
+    wnext = bit >> 5;
+    load_next();
+    cur = joined();
+    load_next();
+    pos = 0;
+    buf = 0;
+    nb = 0;
+    refill();
+    const int drop = (int)(bit & 31);
+    buf <<= drop;
+    nb -= drop;
+    used = 0;
   }
   __device__ __forceinline__ void refill() {
     if (nb <= 32) {
-      buf |= (uint64_t)word(fetch) << (32 - nb);
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)cur, (int)pos);
+      buf |= (uint64_t)w << (32 - nb);
       nb += 32;
-      fetch += 4;
+      if (++pos == BZG_WAVE) {
+        cur = joined();
+        load_next();
+        pos = 0;
+      }
     }
   }
   __device__ __forceinline__ uint32_t peek(int k) const { return (uint32_t)(buf >> (64 - k)); }
@@ -164,17 +201,18 @@ struct BitIn {
 };
 
 constexpr uint32_t MAX_SEL = 18002;  // selectors kept per block (more are read and dropped)
-constexpr uint32_t SEL_STRIDE = 18048;
 constexpr int DEC_MAXLEN = 20;
+constexpr uint32_t OBUF = 4096;  // output bytes staged per block decoder
 
 // One wave per block: header, symbol map, selectors, code tables, then
 // every symbol: Huffman code (first-level table, then the canonical limits),
 // RUNA/RUNB runs, inverse move-to-front.  The move-to-front list is held
-// four entries per lane in one register and moved with lane shifts.  Writes
+// four bytes per lane in one register and moved with lane shifts.  Writes
 // the BWT column, its length, origPtr, the stored CRC and the byte counts.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restrict__ in, uint64_t n_in,
-                                                        const DecBlk* __restrict__ blks, uint8_t* __restrict__ L,
-                                                        uint8_t* __restrict__ selws, uint32_t* __restrict__ out_n,
+                                                        const DecBlk* __restrict__ blks,
+                                                        const uint32_t* __restrict__ order, uint8_t* __restrict__ L,
+                                                        uint32_t* __restrict__ out_n,
                                                         uint32_t* __restrict__ out_orig,
                                                         uint32_t* __restrict__ out_crc,
                                                         uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
@@ -184,22 +222,14 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   __shared__ uint32_t first[MAXG][DEC_MAXLEN + 2], start[MAXG][DEC_MAXLEN + 2];
   __shared__ uint8_t lens[MAXG][MAXA];
   __shared__ uint8_t unseq[256];
-  __shared__ uint32_t sh_hist[256];
+  __shared__ __align__(16) uint8_t obuf[OBUF];
   __shared__ uint32_t srun[DEC_MAXLEN + 2];
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = order[blockIdx.x];  // the longest blocks first
   const DecBlk B = blks[b];
-  uint8_t* sel = selws + (size_t)b * SEL_STRIDE;
   uint8_t* Lb = L + B.l_off;
   const uint32_t ln = lane();
-  for (uint32_t i = ln; i < 256; i += BZG_WAVE) sh_hist[i] = 0;
-  BitIn r{in, n_in, B.start >> 3, 0, 0, 0};
-  {
-    // start mid-byte: load the byte holding the first bit and drop the bits before it
-    const int drop = (int)(B.start & 7);
-    r.refill();
-    r.buf <<= drop;
-    r.nb -= drop;
-  }
+  BitIn r{in, n_in};
+  r.start(B.start);
   uint32_t bad = 0;
   const uint32_t crc_hi = r.get(16);
   const uint32_t crc = (crc_hi << 16) | r.get(16);
@@ -223,7 +253,10 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   const int G = (int)r.get(3);
   const uint32_t nsel = r.get(15);
   bad |= (G < 2) | (G > MAXG) | (nsel == 0);
-  uint32_t lst = 0x543210u;  // table list, 4 bits per entry, front in the low bits
+  // selectors: checked here and decoded again, one per group, in the symbol
+  // loop by a second reader (unary table positions, move-to-front over the
+  // tables)
+  const uint64_t sel_bit = B.start + r.used;
   for (uint32_t s = 0; s < nsel && !bad; s++) {
     uint32_t j = 0;
     while (r.get(1)) {
@@ -233,11 +266,6 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
         break;
       }
     }
-    if (bad) break;
-    const uint32_t t = (lst >> (4 * j)) & 15u;
-    const uint32_t below = lst & ((1u << (4 * j)) - 1u);
-    lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
-    if (s < MAX_SEL && ln == 0) sel[s] = (uint8_t)t;
   }
   const uint32_t nsel_kept = min(nsel, MAX_SEL);
   // code lengths, delta coded
@@ -305,45 +333,73 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
     }
   }
   __syncthreads();
-  // symbols
-  uint32_t stk = 0;  // move-to-front list entries 4*ln .. 4*ln+3, one byte each
+  // symbols.  The move-to-front list holds the bytes themselves (the
+  // in-use bytes, ascending, to start with), entries 4*ln .. 4*ln+3 in this
+  // lane; byte counts are kept by lane (byte & 63), four per lane.
+  uint32_t stk = 0;
 #pragma unroll
-  for (int j = 0; j < 4; j++) stk |= (uint32_t)((4 * ln + j) & 255u) << (8 * j);
+  for (int j = 0; j < 4; j++) stk |= (uint32_t)unseq[min(4 * ln + j, 255u)] << (8 * j);
+  uint32_t hc[4] = {0, 0, 0, 0};
+  auto count = [&](uint32_t by, uint32_t k) {
+    const bool mine = (by & 63u) == ln;
+#pragma unroll
+    for (int q = 0; q < 4; q++) hc[q] += (mine && (by >> 6) == (uint32_t)q) ? k : 0u;
+  };
+  // Output bytes are staged in LDS and stored OBUF at a time with wide
+  // stores: global stores in the loop would be waited for with the input
+  // loads (one memory counter covers both).
+  uint32_t cnt = 0, flushed = 0;
+  auto flush_full = [&]() {
+#pragma unroll
+    for (uint32_t i0 = 0; i0 < OBUF; i0 += BZG_WAVE * 16) {
+      const uint32_t i = i0 + ln * 16;
+      *(uint4*)(Lb + flushed + i) = *(const uint4*)(obuf + i);
+    }
+    flushed += OBUF;
+  };
   const uint32_t cap = B.cap;
-  uint32_t cnt = 0, zrun = 0, zN = 1, gsel = 0, gleft = 0, t = 0;
+  uint32_t zrun = 0, zN = 1, gsel = 0, gleft = 0, t = 0;
   const uint32_t eob = (uint32_t)a - 1;
+  BitIn rs{in, n_in};
+  rs.start(sel_bit);
+  uint32_t lst = 0x543210u;  // table list, 4 bits per entry, front in the low bits
+  bad = uni(bad);
   while (!bad) {
     if (gleft == 0) {
       if (gsel >= nsel_kept) {
         bad = 1;
         break;
       }
-      // read back by the lane that wrote it, then shared
-      const uint32_t tv = ln == 0 ? sel[gsel] : 0u;
-      t = (uint32_t)__builtin_amdgcn_readfirstlane((int)tv);
+      // j ones and a zero (j < G, checked above): table at list position j
+      rs.refill();
+      const uint32_t j = (uint32_t)__builtin_clz(~rs.peek(32) | 1u);
+      rs.skip((int)j + 1);
+      t = (lst >> (4 * j)) & 15u;
+      const uint32_t below = lst & ((1u << (4 * j)) - 1u);
+      lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
       gsel++;
       gleft = GROUP;
     }
     gleft--;
     r.refill();
-    const uint32_t e = lut[t][r.peek(DEC_LUT_BITS)];
+    const uint32_t e = uni(lut[t][r.peek(DEC_LUT_BITS)]);
     uint32_t sym;
     if (e >> 9) {
       sym = e & 511u;
       r.skip((int)(e >> 9));
     } else {
       int zn = DEC_LUT_BITS + 1;
-      while (zn <= DEC_MAXLEN && (int32_t)r.peek(zn) > limit[t][zn]) zn++;
+      while (zn <= DEC_MAXLEN && (int32_t)r.peek(zn) > (int32_t)uni(limit[t][zn])) zn++;
       if (zn > DEC_MAXLEN) {
         bad = 1;
         break;
       }
-      const uint32_t idx = start[t][zn] + r.peek(zn) - first[t][zn];
+      const uint32_t idx = uni(start[t][zn]) + r.peek(zn) - uni(first[t][zn]);
       if (idx >= (uint32_t)a) {
         bad = 1;
         break;
       }
-      sym = perm[t][idx];
+      sym = uni(perm[t][idx]);
       r.skip(zn);
     }
     if (sym <= 1) {  // RUNA / RUNB: a digit of the zero run, least significant first
@@ -360,12 +416,16 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
         bad = 1;
         break;
       }
-      const uint32_t front = (uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u;
-      const uint8_t by = unseq[front];
-      for (uint32_t j = ln; j < zrun; j += BZG_WAVE) Lb[cnt + j] = by;
-      if (ln == 0) sh_hist[by] += zrun;
-      cnt += zrun;
-      zrun = 0;
+      const uint8_t by = (uint8_t)((uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u);
+      count(by, zrun);
+      while (zrun) {
+        const uint32_t k = min(zrun, OBUF - (cnt - flushed));
+        for (uint32_t j0 = 0; j0 < k; j0 += BZG_WAVE)
+          if (j0 + ln < k) obuf[cnt - flushed + j0 + ln] = by;
+        cnt += k;
+        zrun -= k;
+        if (cnt - flushed == OBUF) flush_full();
+      }
       zN = 1;
     }
     if (sym == eob) break;
@@ -384,18 +444,18 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
     const uint32_t m = take == 4 ? 0xFFFFFFFFu : ((1u << (8 * take)) - 1u);
     stk = (up & m) | (stk & ~m);
     if (ln == 0) stk = (stk & ~255u) | uc;
-    const uint8_t by = unseq[uc];
-    if (ln == 0) {
-      Lb[cnt] = by;
-      sh_hist[by] += 1;
-    }
+    const uint8_t by = (uint8_t)uc;
+    if (ln == 0) obuf[cnt - flushed] = by;
+    count(by, 1);
     cnt++;
+    if (cnt - flushed == OBUF) flush_full();
   }
+  for (uint32_t j = ln; j < cnt - flushed; j += BZG_WAVE) Lb[flushed + j] = obuf[j];
   // the block's bits must end exactly where the next marker starts
   bad |= (B.start + r.used != B.end);
   bad |= (cnt == 0) | (orig >= cnt);
-  __syncthreads();
-  for (uint32_t i = ln; i < 256; i += BZG_WAVE) hist[(size_t)b * 256 + i] = bad ? 0u : sh_hist[i];
+#pragma unroll
+  for (int q = 0; q < 4; q++) hist[(size_t)b * 256 + 64 * q + ln] = bad ? 0u : hc[q];
   if (ln == 0) {
     out_n[b] = bad ? 0u : cnt;
     out_orig[b] = bad ? 0u : orig;
@@ -409,13 +469,14 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
 // FL of one block: the row that holds, in the last column, the k-th
 // occurrence of the byte that is first in row C[byte] + k -- a stable
 // counting sort of the column (one workgroup per block, 256 rows a step).
-__global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, const uint8_t* __restrict__ L,
+__global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, const uint32_t* __restrict__ order,
+                                               const uint8_t* __restrict__ L,
                                                const uint32_t* __restrict__ n_rows,
                                                const uint32_t* __restrict__ hist, uint32_t* __restrict__ FL) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wc[NT / BZG_WAVE][256];
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  const uint32_t b = blockIdx.x, tid = threadIdx.x, w = tid / BZG_WAVE;
+  const uint32_t b = order[blockIdx.x], tid = threadIdx.x, w = tid / BZG_WAVE;
   const uint32_t n = n_rows[b];
   const uint8_t* Lb = L + blks[b].l_off;
   uint32_t* F = FL + blks[b].l_off;
@@ -730,18 +791,17 @@ hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipSt
 
 uint32_t dec_walk_slots(uint32_t cap) { return cap / WALK_STRIDE + 2; }
 uint32_t dec_rle_slots(uint32_t cap) { return cap / RLE_SEG + 1; }
-size_t dec_sel_stride() { return SEL_STRIDE; }
 
 hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t nb = d.nb;
   {
     ProfScope ps("dec_block", st, 0.0);
-    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.L,
-                       d.sel, d.n_rows, d.orig, d.crc_want, d.hist, d.err);
+    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, d.L,
+                       d.n_rows, d.orig, d.crc_want, d.hist, d.err);
   }
   {
     ProfScope ps("dec_fl", st, 0.0);
-    hipLaunchKernelGGL(k_dec_fl, dim3(nb), dim3(NT), 0, st, d.blks, d.L, d.n_rows, d.hist, d.FL);
+    hipLaunchKernelGGL(k_dec_fl, dim3(nb), dim3(NT), 0, st, d.blks, d.order, d.L, d.n_rows, d.hist, d.FL);
   }
   const uint32_t gw = (uint32_t)((d.walk_total + NT - 1) / NT);
   {

@@ -278,7 +278,8 @@ struct DecRun {
   uint64_t n_in;
   uint32_t nb;
   const DecBlk* blks;
-  uint8_t *L, *T, *sel, *out;
+  const uint32_t* order;  // blocks by decreasing bit length (launch order)
+  uint8_t *L, *T, *out;
   uint32_t *n_rows, *orig, *crc_want, *hist, *err, *FL;
   const uint64_t* walk0;  // nb + 1 walker slot offsets
   uint64_t walk_total;
@@ -296,7 +297,6 @@ uint64_t dec_find_tiles(uint64_t n);
 hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipStream_t st);
 uint32_t dec_walk_slots(uint32_t cap);
 uint32_t dec_rle_slots(uint32_t cap);
-size_t dec_sel_stride();
 hipError_t dec_run(const DecRun& d, hipStream_t st);
 hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
                      const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
