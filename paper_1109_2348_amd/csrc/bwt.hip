@@ -337,27 +337,34 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const SegRec* __restrict__
 // --------------------------------------------------------- new segments
 
 struct AppendCtx {
-  SegRec* segs;
-  uint32_t* head;   // packed offset -> segment index + 1
-  uint32_t* owner;  // tile -> segment index
+  SegRec* segs;     // large segments
+  uint32_t* head;   // small segments, packed by block: first row + 1 at a segment's first position, else 0
+  uint32_t* bcnt;   // packed elements of each block's small segments
+  const uint32_t* blk_off;  // block row offsets: block b packs from head[blk_off[b]] on
+  uint32_t* owner;  // tile -> large segment index
   RoundCounters* cnt;
-  // capacities of segs, head and owner (every valid input stays below them;
-  // an append past one is dropped and flagged)
-  uint32_t seg_cap, head_cap, owner_cap;
+  // capacities of segs and owner (every valid input stays below them; an
+  // append past one is dropped and flagged)
+  uint32_t seg_cap, owner_cap;
   uint32_t* err;
 };
 
 // Workgroup-aggregated append of up to `m` groups held by this thread
-// (group g = (start[g], len[g], blk)).  All threads must call it.
+// (group g = rows [start[g], start[g] + len[g]) of block `blk`, the same
+// block for the whole workgroup).  All threads must call it.  Small groups
+// are packed into their block's range of the head array (a block's groups
+// never hold more elements than it has rows); large groups get a segment
+// record and their radix tiles.
 template <int M>
-__device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint32_t* gl, int m, uint32_t blk_of_thread,
-                              const uint32_t* gblk, uint32_t* wg_base /*LDS[4]*/) {
-  uint32_t nseg = (uint32_t)m, nsmall = 0, ntiles = 0, nbig = 0;
+__device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint32_t* gl, int m, uint32_t blk,
+                              uint32_t* wg_base /*LDS[4]*/) {
+  uint32_t nseg = 0, nsmall = 0, ntiles = 0, nbig = 0;
   // loops over the M slots with a mask: gs[] and gl[] stay in registers
 #pragma unroll
   for (int g = 0; g < M; g++) {
     const uint32_t len = g < m ? gl[g] : 0u;
     const bool big = len > SMALL_MAX;
+    nseg += big ? 1u : 0u;
     nsmall += big ? 0u : len;
     ntiles += big ? (len + RADIX_TILE - 1) / RADIX_TILE : 0u;
     nbig += big ? len : 0u;
@@ -373,20 +380,21 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
   const uint32_t t_seg = (uint32_t)tot & M13, t_small = (uint32_t)(tot >> 13) & M13;
   const uint32_t t_tiles = (uint32_t)(tot >> 26) & M13, t_big = (uint32_t)(tot >> 39) & ((1u << 22) - 1u);
   const uint32_t e_seg = (uint32_t)ex & M13, e_small = (uint32_t)(ex >> 13) & M13, e_tiles = (uint32_t)(ex >> 26) & M13;
+  const uint32_t area = a.blk_off[blk], rows = a.blk_off[blk + 1] - area;
   if (threadIdx.x == 0) {
-    // neither half of a word carries into the other: segments, packed
+    // neither half of a word carries into the other: large segments, packed
     // elements, tiles and large-segment elements of a round stay below 2^32
     const unsigned long long ss =
-        t_seg ? atomicAdd(&a.cnt->segs_small, (unsigned long long)t_seg | ((unsigned long long)t_small << 32)) : 0ull;
+        t_seg | t_small ? atomicAdd(&a.cnt->segs_small, (unsigned long long)t_seg | ((unsigned long long)t_small << 32))
+                        : 0ull;
     const unsigned long long tb =
         t_tiles ? atomicAdd(&a.cnt->tiles_big, (unsigned long long)t_tiles | ((unsigned long long)t_big << 32)) : 0ull;
     wg_base[0] = (uint32_t)ss;
-    wg_base[1] = (uint32_t)(ss >> 32);
+    wg_base[1] = t_small ? atomicAdd(&a.bcnt[blk], t_small) : 0u;
     wg_base[2] = (uint32_t)tb;
   }
   __syncthreads();
-  const bool fits = (uint64_t)wg_base[0] + t_seg <= a.seg_cap &&
-                    (uint64_t)wg_base[1] + t_small + SMALL_CAP <= a.head_cap &&
+  const bool fits = (uint64_t)wg_base[0] + t_seg <= a.seg_cap && (uint64_t)wg_base[1] + t_small <= rows &&
                     (uint64_t)wg_base[2] + t_tiles <= a.owner_cap;
   if (!fits) {
     if (threadIdx.x == 0) atomicOr(a.err, ERR_BOUND);
@@ -395,31 +403,28 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
   // The workgroup's packed range holds its segments back to back: every
   // position is written (0, then each segment's mark at its start), so a
   // head array needs no clearing before it is appended to.
-  {
-    const uint32_t lo = wg_base[1], hi = (uint32_t)min((uint64_t)lo + t_small, (uint64_t)a.head_cap);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += NT) a.head[i] = 0u;
-  }
+  if (fits)
+    for (uint32_t i = wg_base[1] + threadIdx.x; i < wg_base[1] + t_small; i += NT) a.head[area + i] = 0u;
   __syncthreads();
-  uint32_t si = wg_base[0] + e_seg, so = wg_base[1] + e_small, st = wg_base[2] + e_tiles;
+  uint32_t si = wg_base[0] + e_seg, so = area + wg_base[1] + e_small, st = wg_base[2] + e_tiles;
 #pragma unroll
   for (int g = 0; g < M; g++) {
     if (g >= m) break;
-    SegRec r;
-    r.start = gs[g];
-    r.len = gl[g];
-    r.blk = gblk ? gblk[g] : blk_of_thread;
     if (gl[g] <= SMALL_MAX) {
-      r.base = so;
-      a.head[so] = si + 1;
+      a.head[so] = gs[g] + 1;
       so += gl[g];
     } else {
-      uint32_t nt = (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
+      SegRec r;
+      r.start = gs[g];
+      r.len = gl[g];
+      r.blk = blk;
+      const uint32_t nt = (gl[g] + RADIX_TILE - 1) / RADIX_TILE;
       r.base = st;
       for (uint32_t q = 0; q < nt; q++) a.owner[st + q] = si;
       st += nt;
+      a.segs[si] = r;
+      si++;
     }
-    a.segs[si] = r;
-    si++;
   }
   __syncthreads();
 }
@@ -572,7 +577,7 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
       }
     }
   }
-  append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, nullptr, wg_base);
+  append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, wg_base);
 }
 
 __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
@@ -614,22 +619,50 @@ __device__ __forceinline__ uint32_t block_excl_suffix_min(uint32_t v, uint32_t* 
   return min(ex, later);
 }
 
-// Loads a small tile's segment map: mark[p] = segment index + 1 at each
-// segment's first position, segp[p] = first position of p's segment;
+// Small tiles.  Block b's small segments are packed from head[blk_off[b]]
+// on (bcnt[b] elements); its tiles are the SMALL_T-element windows of that
+// range, each taking the segments that start in it.  The tiles of all
+// blocks are numbered in block order (tile_pre[b] = the first of block b's,
+// tile_pre[nslot] = all), so that neighbouring tiles share a block's text
+// and ranks.
+struct SmallTile {
+  uint32_t blk, lo, avail;  // block, first packed position, packed elements in reach (<= SMALL_CAP)
+};
+__device__ __forceinline__ SmallTile small_tile_at(uint32_t t, const uint32_t* __restrict__ tile_pre, uint32_t nslot,
+                                                   const uint32_t* __restrict__ bcnt,
+                                                   const uint32_t* __restrict__ blk_off) {
+  // the block whose tiles hold t: tile_pre[b] <= t < tile_pre[b + 1]
+  uint32_t lo = 0, hi = nslot;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tile_pre[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  SmallTile st;
+  st.blk = lo;
+  const uint32_t k = (t - tile_pre[lo]) * SMALL_T, base = blk_off[lo];
+  const uint32_t used = min(bcnt[lo], blk_off[lo + 1] - base);
+  st.lo = base + k;
+  st.avail = min(used - k, SMALL_CAP);  // >= 1: the tile exists because k < used
+  return st;
+}
+
+// Loads a small tile's segment map: mark[p] = the segment's first row + 1 at
+// each segment's first position, segp[p] = first position of p's segment;
 // *s_maxlen gets the longest segment; send (optional) gets each segment's end
 // at its first position.  Packed small segments follow each other without
 // gaps, so a segment ends where the next one starts (or where the packed rows
 // end): one load of the head entries of the tile and of the SMALL_MAX
 // positions after it gives every length.
-__device__ uint32_t small_tile_map(uint32_t t, const uint32_t* __restrict__ head, uint32_t small_total,
-                                   uint32_t* mark, uint16_t* segp, uint32_t* sh, uint32_t* s_n, uint32_t* s_maxlen,
+__device__ uint32_t small_tile_map(const SmallTile& tl, const uint32_t* __restrict__ head, uint32_t* mark,
+                                   uint16_t* segp, uint32_t* sh, uint32_t* s_n, uint32_t* s_maxlen,
                                    uint16_t* send = nullptr) {
   if (threadIdx.x == 0) {
     *s_n = 0;
     *s_maxlen = 0;
   }
-  const uint32_t lo = t * SMALL_T;
-  const uint32_t avail = min(small_total - lo, SMALL_CAP);  // packed rows from lo on, in this tile's reach
+  const uint32_t lo = tl.lo;
+  const uint32_t avail = tl.avail;  // packed rows from lo on, in this tile's reach
   {
     constexpr int PH = SMALL_CAP / NT;
     uint32_t hd[PH];
@@ -727,72 +760,74 @@ __device__ __forceinline__ void gather_keys_impl(uint32_t* p, const uint32_t* bo
 // capacities (an append past a capacity was dropped and flagged, but its
 // counts went in).
 struct RoundSizes {
-  uint32_t small_total, nsmall, big_tiles;
+  uint32_t nsmall, big_tiles;
 };
-__device__ __forceinline__ RoundSizes round_sizes(const RoundCounters* c, uint32_t head_cap, uint32_t owner_cap) {
+__device__ __forceinline__ RoundSizes round_sizes(const RoundCounters* c, const uint32_t* tile_pre, uint32_t nslot,
+                                                  uint32_t owner_cap) {
   RoundSizes z;
-  const RoundCounters r = *c;
-  z.small_total = min(r.small_total(), head_cap - SMALL_CAP);
-  z.nsmall = (z.small_total + SMALL_T - 1) / SMALL_T;
-  z.big_tiles = min(r.big_tiles(), owner_cap);
+  z.nsmall = tile_pre[nslot];
+  z.big_tiles = min(c->big_tiles(), owner_cap);
   return z;
 }
 
-__device__ void gather_tile(uint32_t jt, uint32_t n_small_tiles, uint32_t small_total,
-                            const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
-                            const uint32_t* __restrict__ owner, const uint32_t* __restrict__ blk_off,
-                            const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
-                            const uint8_t* __restrict__ text, uint32_t h, uint32_t* __restrict__ key2) {
+// Tiles of each block's packed small segments and their exclusive prefix
+// over the blocks (tile_pre, nslot + 1 entries).  One workgroup.
+constexpr int TS_NT = 1024;
+__global__ __launch_bounds__(TS_NT) void k_small_tiles(const uint32_t* __restrict__ bcnt,
+                                                      const uint32_t* __restrict__ blk_off, uint32_t nslot,
+                                                      uint32_t* __restrict__ tile_pre) {
+  __shared__ uint32_t sh[TS_NT / BZG_WAVE + 1];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nslot; base += TS_NT) {
+    const uint32_t b = base + threadIdx.x;
+    const uint32_t c = b < nslot ? min(bcnt[b], blk_off[b + 1] - blk_off[b]) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum<uint32_t, TS_NT>((c + SMALL_T - 1) / SMALL_T, sh, &tot);
+    if (b < nslot) tile_pre[b] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tile_pre[nslot] = carry;
+}
+
+__device__ void gather_tile(uint32_t jt, uint32_t n_small_tiles, const uint32_t* __restrict__ tile_pre,
+                            uint32_t nslot, const uint32_t* __restrict__ bcnt, const SegRec* __restrict__ segs,
+                            const uint32_t* __restrict__ head, const uint32_t* __restrict__ owner,
+                            const uint32_t* __restrict__ blk_off, const uint32_t* __restrict__ SA,
+                            const uint32_t* __restrict__ rank, const uint8_t* __restrict__ text, uint32_t h,
+                            uint32_t* __restrict__ key2) {
   __shared__ uint32_t mark[SMALL_CAP];
   __shared__ uint16_t segp[SMALL_CAP];
   __shared__ uint32_t sh[NW + 1];
   __shared__ uint32_t s_n, s_maxlen;
   if (jt < n_small_tiles) {
-    uint32_t n = small_tile_map(jt, head, small_total, mark, segp, sh, &s_n, &s_maxlen);
-    // segment records, then block bounds and rows, then the gathers: each
-    // stage's loads are issued together, for half the tile at a time (which
-    // bounds the registers held across them)
+    const SmallTile tl = small_tile_at(jt, tile_pre, nslot, bcnt, blk_off);
+    uint32_t n = small_tile_map(tl, head, mark, segp, sh, &s_n, &s_maxlen);
+    const uint32_t o = blk_off[tl.blk], nbk = blk_off[tl.blk + 1] - o;
+    // rows (from the segment marks), then the rows' SA entries, then the
+    // gathers: each stage's loads are issued together, for half the tile at
+    // a time (which bounds the registers held across them)
     constexpr int PL = SMALL_CAP / NT / 2;
 #pragma unroll 1
     for (int half = 0; half < 2; half++) {
-      SegRec rr[PL];
-      uint32_t sa[PL], bo[PL], bn[PL], ps[PL], kv[PL];
-      // LDS reads unconditional (positions < SMALL_CAP), the record load from
-      // a clamped index: no read waits alone inside a branch
-      uint32_t spv[PL], mkv[PL];
-#pragma unroll
-      for (int j = 0; j < PL; j++) spv[j] = segp[(half * PL + j) * NT + threadIdx.x];
-#pragma unroll
-      for (int j = 0; j < PL; j++) mkv[j] = mark[spv[j] != NO_SEG ? spv[j] : 0u];
+      uint32_t row[PL], kv[PL];
+      bool has[PL];
 #pragma unroll
       for (int j = 0; j < PL; j++) {
         const uint32_t p = (half * PL + j) * NT + threadIdx.x;
-        const bool has = (p < n) & (spv[j] != NO_SEG);
-        const SegRec r = segs[has ? mkv[j] - 1u : 0u];
-        rr[j] = has ? r : SegRec{0, 0, 0, 0};
-      }
-      // positions without a row read row 0 of block 0 (loads stay unbranched)
-#pragma unroll
-      for (int j = 0; j < PL; j++) {
-        const uint32_t p = (half * PL + j) * NT + threadIdx.x;
-        ps[j] = rr[j].len ? p - spv[j] : 0u;
+        const uint32_t spv = segp[p];
+        const uint32_t mk = mark[spv != NO_SEG ? spv : 0u];
+        has[j] = (p < n) & (spv != NO_SEG);
+        row[j] = has[j] ? mk - 1u + (p - spv) : o;  // positions without a row read the block's first
       }
 #pragma unroll
-      for (int j = 0; j < PL; j++) {
-        sa[j] = SA[rr[j].start + ps[j]];
-        bo[j] = blk_off[rr[j].blk];
-        bn[j] = blk_off[rr[j].blk + 1];
-      }
+      for (int j = 0; j < PL; j++) kv[j] = SA[row[j]];
 #pragma unroll
-      for (int j = 0; j < PL; j++) {
-        bn[j] -= bo[j];
-        if (!rr[j].len) sa[j] = bo[j] = 0, bn[j] = 1;
-        kv[j] = cyc(sa[j] - bo[j] + (rr[j].len ? h : 0u), bn[j]);  // partner position
-      }
-      gather_keys_impl<PL, false>(kv, bo, bn, text, rank);
+      for (int j = 0; j < PL; j++) kv[j] = cyc(kv[j] - o + h, nbk);  // partner position
+      gather_keys_impl<PL, true>(kv, &o, &nbk, text, rank);
 #pragma unroll
       for (int j = 0; j < PL; j++)
-        if (rr[j].len) key2[rr[j].start + ps[j]] = kv[j];
+        if (has[j]) key2[row[j]] = kv[j];
     }
   } else {
     BigTile g = big_tile(jt - n_small_tiles, segs, owner);
@@ -821,22 +856,27 @@ __device__ void gather_tile(uint32_t jt, uint32_t n_small_tiles, uint32_t small_
 // (none in the text round, whose small segments gather their own keys) and
 // the large segments' tiles.  Workgroup 0 also clears the counter record
 // `clr`, the one that the round after the next appends to (nothing reads or
-// writes it meanwhile).
+// writes it meanwhile), and the workgroups clear the block counts
+// `bcnt_clr`, the ones this round's appends go to (last read by the round
+// before).
 __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, const uint32_t* __restrict__ head,
                                                const uint32_t* __restrict__ owner, const RoundCounters* cnt,
-                                               RoundCounters* clr, int with_small, uint32_t head_cap,
+                                               const uint32_t* __restrict__ tile_pre,
+                                               const uint32_t* __restrict__ bcnt, uint32_t nslot,
+                                               RoundCounters* clr, uint32_t* __restrict__ bcnt_clr, int with_small,
                                                uint32_t owner_cap, const uint32_t* __restrict__ blk_off,
                                                const uint32_t* __restrict__ SA, const uint32_t* __restrict__ rank,
                                                const uint8_t* __restrict__ text, uint32_t h,
                                                uint32_t* __restrict__ key2) {
-  const RoundSizes z = round_sizes(cnt, head_cap, owner_cap);
+  const RoundSizes z = round_sizes(cnt, tile_pre, nslot, owner_cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     clr->segs_small = 0ull;
     clr->tiles_big = 0ull;
   }
+  for (uint32_t b = blockIdx.x * NT + threadIdx.x; b < nslot; b += gridDim.x * NT) bcnt_clr[b] = 0u;
   const uint32_t nsmall = with_small ? z.nsmall : 0u;
   for (TileLoop it = tile_loop(nsmall + z.big_tiles); it.t < it.end; it.t += it.step) {
-    gather_tile(it.t, nsmall, z.small_total, segs, head, owner, blk_off, SA, rank, text, h, key2);
+    gather_tile(it.t, nsmall, tile_pre, nslot, bcnt, segs, head, owner, blk_off, SA, rank, text, h, key2);
     __syncthreads();
   }
 }
@@ -854,8 +894,9 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // rows cost about this much in issued instructions, measured as counters).
 constexpr uint32_t COUNT_STEPS_PER_PASS = 48;  // (the built-in choice; a context may set another)
 
-__device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec* __restrict__ segs,
-                                uint32_t* __restrict__ head, const uint32_t* __restrict__ blk_off,
+__device__ void small_sort_tile(uint32_t jt, const uint32_t* __restrict__ tile_pre, uint32_t nslot,
+                                const uint32_t* __restrict__ bcnt, uint32_t* __restrict__ head,
+                                const uint32_t* __restrict__ blk_off,
                                 const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
                                 uint32_t* __restrict__ rank, uint32_t h, uint32_t h_next,
                                 const uint8_t* __restrict__ text, const AppendCtx& app, uint32_t count_steps) {
@@ -871,7 +912,10 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
   __shared__ uint32_t s_n, s_maxlen, s_cost;
   __shared__ uint32_t wg_base[4];
   if (threadIdx.x == 0) s_cost = 0;
-  const uint32_t n = small_tile_map(jt, head, small_total, mark, segp, sh, &s_n, &s_maxlen, sseg);
+  const SmallTile tl = small_tile_at(jt, tile_pre, nslot, bcnt, blk_off);
+  const uint32_t n = small_tile_map(tl, head, mark, segp, sh, &s_n, &s_maxlen, sseg);
+  // the tile's block (one per tile)
+  const uint32_t bo = blk_off[tl.blk], nbk = blk_off[tl.blk + 1] - bo;
   constexpr int PI = SMALL_CAP / NT;  // 8
   const int npass_radix = text_mode ? 6 : 4;
   // Counting (below) ranks each row among its segment's rows in as many
@@ -895,42 +939,30 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
   // first segment take key 0 and stay in front (no segment starts at 0 then);
   // positions past the last take the largest key and stay behind.
   {
-    // all segment records first, then the rows' key2 and SA (independent
-    // loads, issued together)
-    // (positions without a row load from row 0 of segment 0: no load sits
-    // under a branch, so each stage's loads are all in flight together)
+    // rows from the segment marks, then their key2 and SA entries (independent
+    // loads, issued together); positions without a row load the block's first
+    // row, so that no load sits under a branch and each stage's loads are all
+    // in flight together
     constexpr int PL = SMALL_CAP / NT;
-    uint32_t sp[PL], kk[PL], k2[PL], vv[PL], kb[PL];
+    uint32_t sp[PL], kk[PL], k2[PL], vv[PL];
 #pragma unroll
     for (int j = 0; j < PL; j++) {
       const uint32_t p = j * NT + threadIdx.x;
       sp[j] = p < n ? segp[p] : NO_SEG;
-      const SegRec& r = segs[sp[j] != NO_SEG ? mark[sp[j]] - 1 : 0u];
-      kk[j] = r.start;
-      kb[j] = r.blk;
+      const uint32_t mk = mark[sp[j] != NO_SEG ? sp[j] : 0u];
+      kk[j] = sp[j] != NO_SEG ? mk - 1u + (p - sp[j]) : bo;
     }
 #pragma unroll
     for (int j = 0; j < PL; j++) {
-      const uint32_t p = j * NT + threadIdx.x;
-      kk[j] = sp[j] != NO_SEG ? kk[j] + (p - sp[j]) : kk[j];
       if (!text) k2[j] = key2[kk[j]];
       vv[j] = SA[kk[j]];
     }
     if (text) {
       // the text round gathers its own keys: the first 4 bytes of the
       // rotation h positions on (no k_gather pass for small segments)
-      uint32_t o[PL], nbk[PL];
 #pragma unroll
-      for (int j = 0; j < PL; j++) {
-        o[j] = blk_off[kb[j]];
-        nbk[j] = blk_off[kb[j] + 1];
-      }
-#pragma unroll
-      for (int j = 0; j < PL; j++) {
-        nbk[j] -= o[j];
-        k2[j] = cyc(vv[j] - o[j] + h, nbk[j]);
-      }
-      gather_keys_impl<PL, false>(k2, o, nbk, text, nullptr);
+      for (int j = 0; j < PL; j++) k2[j] = cyc(vv[j] - bo + h, nbk);
+      gather_keys_impl<PL, true>(k2, &bo, &nbk, text, nullptr);
     }
     // (selects, not branches: a load used only under a branch would be
     // moved into it and waited for there)
@@ -1047,23 +1079,12 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
     sg[i] = segp[p0 + i];
     sv[i] = sval[p0 + i];
   }
-  // segment records and block bounds of the thread's positions (loaded here,
-  // not before the sort, so that they hold no registers through it: that
-  // leaves room for a fourth workgroup per CU); record 0 where none
-  SegRec rr[PI];
-  uint32_t bo[PI], be[PI];
-  {
-    uint32_t ri[PI];
+  // each position's segment: its first row (the mark at its first
+  // position) and whether the segment ends there
+  uint32_t rs[PI];
 #pragma unroll
-    for (int i = 0; i < PI; i++) ri[i] = sg[i] != NO_SEG ? mark[sg[i]] : 0u;
-#pragma unroll
-    for (int i = 0; i < PI; i++) rr[i] = segs[ri[i] ? ri[i] - 1u : 0u];
-#pragma unroll
-    for (int i = 0; i < PI; i++) {
-      bo[i] = blk_off[rr[i].blk];
-      be[i] = blk_off[rr[i].blk + 1];
-    }
-  }
+  for (int i = 0; i < PI; i++) rs[i] = mark[sg[i] != NO_SEG ? sg[i] : 0u] - 1u;
+  const uint32_t sg_next = segp[min(p0 + PI, SMALL_CAP - 1u)];
   uint32_t lastb = 0;
 #pragma unroll
   for (int i = 0; i < PI; i++) {
@@ -1075,7 +1096,7 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
   sx[threadIdx.x] = incl;
   __syncthreads();
   uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
-  uint32_t gs[PI / 2 + 1], gl[PI / 2 + 1], gb[PI / 2 + 1];
+  uint32_t gs[PI / 2 + 1], gl[PI / 2 + 1];
   int m = 0;
 #pragma unroll
   for (int i = 0; i < PI; i++) {
@@ -1083,50 +1104,47 @@ __device__ void small_sort_tile(uint32_t jt, uint32_t small_total, const SegRec*
     if (p >= n) break;
     uint32_t sp = sg[i];
     if (sp == NO_SEG) continue;
-    const SegRec r = rr[i];
     if (p == sp || sk[i + 1] != sk[i]) hp = p + 1;
-    uint32_t k = r.start + (p - sp);
-    uint32_t headk = r.start + (hp - 1 - sp);
+    uint32_t k = rs[i] + (p - sp);
+    uint32_t headk = rs[i] + (hp - 1 - sp);
     uint32_t v = sv[i];
     SA[k] = v;
     // rank rounds: rows of the segment's first group keep the rank they have
     // (the segment's start), so only the other groups' rows are written
     if (text_mode || hp - 1 != sp) rank[v] = headk;
-    bool end = (p + 1 == sp + r.len) || sk[i + 2] != sk[i + 1];
+    const bool seg_end = (p + 1 == n) || (i + 1 < PI ? sg[i + 1] : sg_next) != sp;
+    const bool end = seg_end || sk[i + 2] != sk[i + 1];
     if (end) {
       uint32_t len = p + 1 - (hp - 1);
-      const uint32_t nbk = be[i] - bo[i];
       // closed group (see k_rename_b): equal rotations, final
-      const bool closed = !text_mode && len == r.len && (sk[i + 1] & ((1u << 21) - 1u)) == r.start - bo[i];
+      const bool closed = !text_mode && seg_end && hp - 1 == sp && (sk[i + 1] & ((1u << 21) - 1u)) == rs[i] - bo;
       if (len >= 2 && h_next < nbk && !closed) {
 #pragma unroll
         for (int q = 0; q < PI / 2 + 1; q++)  // register-resident append
           if (q == m) {
             gs[q] = headk;
             gl[q] = len;
-            gb[q] = r.blk;
           }
         m++;
       }
     }
   }
-  append_groups<PI / 2 + 1>(app, gs, gl, m, 0, gb, wg_base);
+  append_groups<PI / 2 + 1>(app, gs, gl, m, tl.blk, wg_base);
 }
 
-__global__ __launch_bounds__(NT, 4) void k_small_sort(const SegRec* __restrict__ segs, uint32_t* __restrict__ head,
-                                                   const RoundCounters* cnt, uint32_t head_cap, uint32_t owner_cap,
+__global__ __launch_bounds__(NT, 4) void k_small_sort(uint32_t* __restrict__ head, const uint32_t* __restrict__ tile_pre,
+                                                   const uint32_t* __restrict__ bcnt, uint32_t nslot,
                                                    const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
                                                    uint32_t* __restrict__ rank, uint32_t h, uint32_t h_next,
                                                    const uint8_t* __restrict__ text, AppendCtx app,
                                                    uint32_t count_steps) {
-  const RoundSizes z = round_sizes(cnt, head_cap, owner_cap);
-  for (TileLoop it = tile_loop(z.nsmall); it.t < it.end; it.t += it.step) {
-    small_sort_tile(it.t, z.small_total, segs, head, blk_off, key2, SA, rank, h, h_next, text, app, count_steps);
+  const uint32_t nsmall = tile_pre[nslot];
+  for (TileLoop it = tile_loop(nsmall); it.t < it.end; it.t += it.step) {
+    small_sort_tile(it.t, tile_pre, nslot, bcnt, head, blk_off, key2, SA, rank, h, h_next, text, app, count_steps);
     __syncthreads();
   }
 }
-
 // ------------------------------------------------------------- final BWT
 
 // L[k] = byte before rotation SA[k]; primary[b] = row of rotation 0; the
@@ -1193,7 +1211,7 @@ __global__ __launch_bounds__(NT) void k_bwt_out(const uint8_t* __restrict__ text
 static BwtSizes bwt_sizes(uint32_t N, uint32_t nb) {
   BwtSizes z;
   z.seg_cap = N / 2 + nb + 16;
-  z.head_cap = N + SMALL_CAP + 16;
+  z.head_cap = N + 16;  // block b packs its small segments from its first row on
   z.owner_cap = N / RADIX_TILE + N / (SMALL_MAX + 1) + nb + 16;
   z.hist_cap = (size_t)z.owner_cap * 256 + 16;
   z.state_cap = hist_scan_states((uint32_t)z.owner_cap) + 16;
@@ -1213,6 +1231,7 @@ size_t bwt_workspace_bytes(uint32_t N, uint32_t nb) {
     add(z.owner_cap * 4);
   }
   add(z.head_cap * 4 * 2);
+  for (int i = 0; i < 3; i++) add(((size_t)nb + 1) * 4);  // bcnt[2], tile_pre
   add(3 * sizeof(RoundCounters));
   return b + 4096;
 }
@@ -1237,6 +1256,10 @@ bool bwt_carve(void* ws, size_t ws_bytes, uint32_t N, uint32_t nb, BwtWork& w) {
   }
   w.head[0] = bump.take<uint32_t>(z.head_cap);
   w.head[1] = bump.take<uint32_t>(z.head_cap);
+  w.bcnt[0] = bump.take<uint32_t>((size_t)nb + 1);
+  w.bcnt[1] = bump.take<uint32_t>((size_t)nb + 1);
+  w.tile_pre = bump.take<uint32_t>((size_t)nb + 1);
+  w.nslot = nb;
   w.cnt = bump.take<RoundCounters>(3);
   return bump.used <= ws_bytes;
 }
@@ -1306,9 +1329,11 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     e = (x);                        \
     if (e != hipSuccess) return e;  \
   } while (0)
-  // the counter records start at zero; the head arrays need no clearing
-  // (each append writes its whole range)
+  // the counter records and the block counts of the first list start at
+  // zero (the second list's are cleared by the first round); the head arrays
+  // need no clearing (each append writes its whole range)
   BZG_TRY(fill32((uint32_t*)w.cnt, 3 * sizeof(RoundCounters) / 4, 0u, st));
+  BZG_TRY(fill32(w.bcnt[1], w.nslot, 0u, st));
   const uint32_t* rows = d_off + bd.nslot;  // the row count
   const uint32_t icap = std::min<uint32_t>(bd.init_tiles, (uint32_t)z.owner_cap);
   const uint32_t Gi = persist_grid(icap, ONE_TILE_EACH);  // first sort: one tile per workgroup
@@ -1342,9 +1367,9 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
                          vout[p], shift, w.hist, p ? nullptr : text, init_tiles, icap);
     }
   }
-  const uint32_t hcap = (uint32_t)z.head_cap, ocap = (uint32_t)z.owner_cap;
+  const uint32_t ocap = (uint32_t)z.owner_cap, nslot = std::min(bd.nslot, w.nslot);
   {
-    AppendCtx app{w.segs[1], w.head[1], w.owner[1], &w.cnt[1], (uint32_t)z.seg_cap, hcap, ocap, err};
+    AppendCtx app{w.segs[1], w.head[1], w.bcnt[1], d_off, w.owner[1], &w.cnt[1], (uint32_t)z.seg_cap, ocap, err};
     {
       ProfScope ps("rename_a", st, 0, rows, 4.0);
       hipLaunchKernelGGL(k_rename_a, dim3(Gi), dim3(NT), 0, st, w.segs[0], w.owner[0], w.key, w.agg, init_tiles,
@@ -1373,17 +1398,22 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     const uint32_t* small_rows = (const uint32_t*)&w.cnt[cc].segs_small + 1;   // high word
     const uint32_t* big_rows = (const uint32_t*)&w.cnt[cc].tiles_big + 1;      // high word
     {
+      ProfScope ps("scan", st, 0.0);
+      hipLaunchKernelGGL(k_small_tiles, dim3(1), dim3(TS_NT), 0, st, w.bcnt[cur], d_off, nslot, w.tile_pre);
+    }
+    {
       // row, partner rank, key2
       ProfScope ps("gather", st, 0, big_rows, 12.0, text_round ? nullptr : small_rows, 12.0);
       // the text round's small segments gather their keys in k_small_sort
       hipLaunchKernelGGL(k_gather, dim3(Gg), dim3(NT), 0, st, w.segs[cur], w.head[cur], w.owner[cur], &w.cnt[cc],
-                         &w.cnt[cz], text_round ? 0 : 1, hcap, ocap, d_off, w.SA, w.rank,
-                         text_round ? text : nullptr, h, w.key);
+                         w.tile_pre, w.bcnt[cur], nslot, &w.cnt[cz], w.bcnt[nxt], text_round ? 0 : 1, ocap, d_off,
+                         w.SA, w.rank, text_round ? text : nullptr, h, w.key);
     }
-    AppendCtx app2{w.segs[nxt], w.head[nxt], w.owner[nxt], &w.cnt[cn], (uint32_t)z.seg_cap, hcap, ocap, err};
+    AppendCtx app2{w.segs[nxt], w.head[nxt], w.bcnt[nxt], d_off, w.owner[nxt], &w.cnt[cn], (uint32_t)z.seg_cap,
+                   ocap, err};
     {
       ProfScope ps("small_sort", st, 0, small_rows, 16.0);  // key2 and row in, row and rank out
-      hipLaunchKernelGGL(k_small_sort, dim3(Gs), dim3(NT), 0, st, w.segs[cur], w.head[cur], &w.cnt[cc], hcap, ocap,
+      hipLaunchKernelGGL(k_small_sort, dim3(Gs), dim3(NT), 0, st, w.head[cur], w.tile_pre, w.bcnt[cur], nslot,
                          d_off, w.key, w.SA, w.rank, h, Pn, text_round ? text : nullptr, app2, count_steps);
     }
     uint32_t *kin, *vin;

@@ -122,9 +122,10 @@ constexpr uint32_t ONE_TILE_EACH = 0x7FFFFFF8u;  // cap for one tile per workgro
 // usually far below its bound.
 uint32_t resident_grid(const void* kernel, int threads);
 
-// A run of equal-prefix rotations still to be ordered: SA rows
-// [start, start+len) of block blk.  `base` is the segment's packed element
-// offset (small segments) or first tile index (large segments).
+// A run of equal-prefix rotations still to be ordered, too long for one
+// small tile: SA rows [start, start+len) of block blk, radix tiles from
+// `base` on.  (Small runs have no record: their first row is their mark in
+// the block's packed head range.)
 struct SegRec {
   uint32_t start, len, blk, base;
 };
@@ -134,7 +135,7 @@ struct SegRec {
 // that a workgroup takes its ranges with one atomic per word; the words sit
 // on different cache lines.
 struct RoundCounters {
-  unsigned long long segs_small;  // segments for the next round | packed elements of small segments << 32
+  unsigned long long segs_small;  // large segments for the next round | packed elements of small segments << 32
   uint32_t pad0[30];
   unsigned long long tiles_big;   // radix tiles of large segments | elements in large segments << 32
   uint32_t pad1[30];
@@ -146,8 +147,9 @@ struct RoundCounters {
 };
 
 // The sort's workspace: SA rows, ranks, keys, radix buffers, histograms
-// and scan state, segment lists, small-tile heads and three round-counter
-// records, carved from one range by bwt_carve.
+// and scan state, segment lists, small-segment heads with their per-block
+// counts and tile prefix, and three round-counter records, carved from one
+// range by bwt_carve.
 struct BwtSizes {
   size_t seg_cap, head_cap, owner_cap, hist_cap, state_cap;
 };
@@ -156,8 +158,11 @@ struct BwtWork {
   unsigned long long* state;
   SegRec* segs[2];
   uint32_t* head[2];
+  uint32_t* bcnt[2];   // per block: packed elements of its small segments
+  uint32_t* tile_pre;  // per block: first small tile; [nslot] = all small tiles
   uint32_t* owner[2];
   RoundCounters* cnt;
+  uint32_t nslot;
   BwtSizes z;
 };
 // Host bounds a sort is planned from: blocks (slots), rows, longest block,
