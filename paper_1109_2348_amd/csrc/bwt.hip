@@ -654,25 +654,27 @@ __device__ __forceinline__ SmallTile small_tile_at(uint32_t t, const uint32_t* _
 // gaps, so a segment ends where the next one starts (or where the packed rows
 // end): one load of the head entries of the tile and of the SMALL_MAX
 // positions after it gives every length.
-__device__ uint32_t small_tile_map(const SmallTile& tl, const uint32_t* __restrict__ head, uint32_t* mark,
-                                   uint16_t* segp, uint32_t* sh, uint32_t* s_n, uint32_t* s_maxlen,
-                                   uint16_t* send = nullptr) {
+constexpr int PH = SMALL_CAP / NT;  // head entries per thread
+
+// The head entries in a small tile's reach, PH per thread (clamped
+// positions: every load is unconditional).
+__device__ __forceinline__ void small_tile_heads(const SmallTile& tl, const uint32_t* __restrict__ head,
+                                                 uint32_t* hd) {
+#pragma unroll
+  for (int j = 0; j < PH; j++) hd[j] = head[tl.lo + min(j * NT + threadIdx.x, tl.avail - 1u)];
+}
+
+__device__ uint32_t small_tile_map(const SmallTile& tl, const uint32_t* hd, uint32_t* mark, uint16_t* segp,
+                                   uint32_t* sh, uint32_t* s_n, uint32_t* s_maxlen, uint16_t* send = nullptr) {
   if (threadIdx.x == 0) {
     *s_n = 0;
     *s_maxlen = 0;
   }
-  const uint32_t lo = tl.lo;
-  const uint32_t avail = tl.avail;  // packed rows from lo on, in this tile's reach
-  {
-    constexpr int PH = SMALL_CAP / NT;
-    uint32_t hd[PH];
+  const uint32_t avail = tl.avail;  // packed rows from the tile's first on, in its reach
 #pragma unroll
-    for (int j = 0; j < PH; j++) hd[j] = head[lo + min(j * NT + threadIdx.x, avail - 1u)];
-#pragma unroll
-    for (int j = 0; j < PH; j++) {
-      const uint32_t i = j * NT + threadIdx.x;
-      mark[i] = i < avail ? hd[j] : 0u;
-    }
+  for (int j = 0; j < PH; j++) {
+    const uint32_t i = j * NT + threadIdx.x;
+    mark[i] = i < avail ? hd[j] : 0u;
   }
   __syncthreads();
   constexpr int PER = SMALL_CAP / NT;  // 8 positions per thread, blocked
@@ -802,7 +804,9 @@ __device__ void gather_tile(uint32_t jt, uint32_t n_small_tiles, const uint32_t*
   __shared__ uint32_t s_n, s_maxlen;
   if (jt < n_small_tiles) {
     const SmallTile tl = small_tile_at(jt, tile_pre, nslot, bcnt, blk_off);
-    uint32_t n = small_tile_map(tl, head, mark, segp, sh, &s_n, &s_maxlen);
+    uint32_t hd[PH];
+    small_tile_heads(tl, head, hd);
+    uint32_t n = small_tile_map(tl, hd, mark, segp, sh, &s_n, &s_maxlen);
     const uint32_t o = blk_off[tl.blk], nbk = blk_off[tl.blk + 1] - o;
     // rows (from the segment marks), then the rows' SA entries, then the
     // gathers: each stage's loads are issued together, for half the tile at
@@ -894,8 +898,9 @@ __global__ __launch_bounds__(NT) void k_gather(const SegRec* __restrict__ segs, 
 // rows cost about this much in issued instructions, measured as counters).
 constexpr uint32_t COUNT_STEPS_PER_PASS = 48;  // (the built-in choice; a context may set another)
 
-__device__ void small_sort_tile(uint32_t jt, const uint32_t* __restrict__ tile_pre, uint32_t nslot,
-                                const uint32_t* __restrict__ bcnt, uint32_t* __restrict__ head,
+__device__ void small_sort_tile(const SmallTile& tl, const uint32_t* hd, uint32_t jt_next, SmallTile& tl_next,
+                                uint32_t* hd_next, const uint32_t* __restrict__ tile_pre, uint32_t nslot,
+                                const uint32_t* __restrict__ bcnt, const uint32_t* __restrict__ head,
                                 const uint32_t* __restrict__ blk_off,
                                 const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
                                 uint32_t* __restrict__ rank, uint32_t h, uint32_t h_next,
@@ -912,8 +917,7 @@ __device__ void small_sort_tile(uint32_t jt, const uint32_t* __restrict__ tile_p
   __shared__ uint32_t s_n, s_maxlen, s_cost;
   __shared__ uint32_t wg_base[4];
   if (threadIdx.x == 0) s_cost = 0;
-  const SmallTile tl = small_tile_at(jt, tile_pre, nslot, bcnt, blk_off);
-  const uint32_t n = small_tile_map(tl, head, mark, segp, sh, &s_n, &s_maxlen, sseg);
+  const uint32_t n = small_tile_map(tl, hd, mark, segp, sh, &s_n, &s_maxlen, sseg);
   // the tile's block (one per tile)
   const uint32_t bo = blk_off[tl.blk], nbk = blk_off[tl.blk + 1] - bo;
   constexpr int PI = SMALL_CAP / NT;  // 8
@@ -1067,6 +1071,13 @@ __device__ void small_sort_tile(uint32_t jt, const uint32_t* __restrict__ tile_p
     }
     __syncthreads();
   }
+  // the next tile's head entries, loaded now: before this tile's scattered
+  // stores, so that waiting for them later does not wait for the stores
+  // (one memory counter covers loads and stores, in issue order)
+  if (jt_next != 0xFFFFFFFFu) {
+    tl_next = small_tile_at(jt_next, tile_pre, nslot, bcnt, blk_off);
+    small_tile_heads(tl_next, head, hd_next);
+  }
   // naming: blocked, PI consecutive positions per thread.  The thread's
   // keys (with one neighbour on each side), segment starts and rows are read
   // from LDS first, all together (clamped positions).
@@ -1096,22 +1107,25 @@ __device__ void small_sort_tile(uint32_t jt, const uint32_t* __restrict__ tile_p
   sx[threadIdx.x] = incl;
   __syncthreads();
   uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
+  // Each position's SA row and the rank its rotation gets go to LDS (skey
+  // and mark, read above by every thread before the barriers of the scan),
+  // none = 0xFFFFFFFF, and are stored after the append.
   uint32_t gs[PI / 2 + 1], gl[PI / 2 + 1];
   int m = 0;
 #pragma unroll
   for (int i = 0; i < PI; i++) {
     uint32_t p = p0 + i;
-    if (p >= n) break;
+    skey[p] = 0xFFFFFFFFu;
+    mark[p] = 0xFFFFFFFFu;
+    if (p >= n) continue;
     uint32_t sp = sg[i];
     if (sp == NO_SEG) continue;
     if (p == sp || sk[i + 1] != sk[i]) hp = p + 1;
-    uint32_t k = rs[i] + (p - sp);
-    uint32_t headk = rs[i] + (hp - 1 - sp);
-    uint32_t v = sv[i];
-    SA[k] = v;
+    const uint32_t headk = rs[i] + (hp - 1 - sp);
+    skey[p] = rs[i] + (p - sp);
     // rank rounds: rows of the segment's first group keep the rank they have
     // (the segment's start), so only the other groups' rows are written
-    if (text_mode || hp - 1 != sp) rank[v] = headk;
+    if (text_mode || hp - 1 != sp) mark[p] = headk;
     const bool seg_end = (p + 1 == n) || (i + 1 < PI ? sg[i + 1] : sg_next) != sp;
     const bool end = seg_end || sk[i + 2] != sk[i + 1];
     if (end) {
@@ -1129,10 +1143,22 @@ __device__ void small_sort_tile(uint32_t jt, const uint32_t* __restrict__ tile_p
       }
     }
   }
+  // the append's reservation (atomics, waited for) before the scattered
+  // stores below, which it would otherwise wait for; its barriers also
+  // order the LDS writes above before the reads below
   append_groups<PI / 2 + 1>(app, gs, gl, m, tl.blk, wg_base);
+  // strided: neighbouring lanes store neighbouring rows of a segment
+#pragma unroll
+  for (int j = 0; j < PI; j++) {
+    const uint32_t p = j * NT + threadIdx.x;
+    const uint32_t k = skey[p], r = mark[p], v = sval[p];
+    if (k != 0xFFFFFFFFu) SA[k] = v;
+    if (r != 0xFFFFFFFFu) rank[v] = r;
+  }
 }
 
-__global__ __launch_bounds__(NT, 4) void k_small_sort(uint32_t* __restrict__ head, const uint32_t* __restrict__ tile_pre,
+__global__ __launch_bounds__(NT, 4) void k_small_sort(const uint32_t* __restrict__ head,
+                                                   const uint32_t* __restrict__ tile_pre,
                                                    const uint32_t* __restrict__ bcnt, uint32_t nslot,
                                                    const uint32_t* __restrict__ blk_off,
                                                    const uint32_t* __restrict__ key2, uint32_t* __restrict__ SA,
@@ -1140,11 +1166,25 @@ __global__ __launch_bounds__(NT, 4) void k_small_sort(uint32_t* __restrict__ hea
                                                    const uint8_t* __restrict__ text, AppendCtx app,
                                                    uint32_t count_steps) {
   const uint32_t nsmall = tile_pre[nslot];
-  for (TileLoop it = tile_loop(nsmall); it.t < it.end; it.t += it.step) {
-    small_sort_tile(it.t, tile_pre, nslot, bcnt, head, blk_off, key2, SA, rank, h, h_next, text, app, count_steps);
+  TileLoop it = tile_loop(nsmall);
+  if (it.t >= it.end) return;
+  // each tile's head entries are loaded by the tile before it
+  SmallTile tl = small_tile_at(it.t, tile_pre, nslot, bcnt, blk_off);
+  uint32_t hd[PH];
+  small_tile_heads(tl, head, hd);
+  for (; it.t < it.end; it.t += it.step) {
+    const uint32_t tn = it.t + it.step < it.end ? it.t + it.step : 0xFFFFFFFFu;
+    SmallTile tl_next = tl;
+    uint32_t hd_next[PH];
+    small_sort_tile(tl, hd, tn, tl_next, hd_next, tile_pre, nslot, bcnt, head, blk_off, key2, SA, rank, h, h_next,
+                    text, app, count_steps);
     __syncthreads();
+    tl = tl_next;
+#pragma unroll
+    for (int j = 0; j < PH; j++) hd[j] = hd_next[j];
   }
 }
+
 // ------------------------------------------------------------- final BWT
 
 // L[k] = byte before rotation SA[k]; primary[b] = row of rotation 0; the
