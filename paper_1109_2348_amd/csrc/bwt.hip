@@ -550,6 +550,9 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
   __syncthreads();
   uint32_t hp = threadIdx.x ? sx[threadIdx.x - 1] : 0u;
   hp = max(hp, s_carry);
+  // The rank each row's rotation gets (none = 0xFFFFFFFF) goes to tk (read
+  // above by every thread before the scan's barriers) and is stored, with
+  // the rows, after the append.
   uint32_t gs[RI / 2 + 1], gl[RI / 2 + 1];
   int m = 0;
 #pragma unroll
@@ -557,13 +560,11 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
     uint32_t k = k0 + i;
     if (k < g.hi) {
       if (k == g.r.start || t[i + 1] != t[i]) hp = k + 1;
-      const uint32_t v = vv[i];
-      if (vin != SA) SA[k] = v;
       const bool end = (k + 1 == segend) || t[i + 2] != t[i + 1];
       // rank rounds: rows of the segment's first group keep the rank they
       // have (the segment's start)
       const bool same_rank = key_is_rank && hp - 1 == g.r.start;
-      if (!same_rank && (rank_all || (end && hp == k + 1))) rank[v] = hp - 1;
+      tk[i0 + i] = !same_rank && (rank_all || (end && hp == k + 1)) ? hp - 1 : 0xFFFFFFFFu;
       if (end) {
         uint32_t len = k + 1 - (hp - 1);
         // closed group: the segment did not split and every partner lies in
@@ -577,7 +578,20 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
       }
     }
   }
+  // the append's reservation (atomics, waited for) before the scattered
+  // stores, which it would otherwise wait for; its barriers also order the
+  // LDS writes above before the reads below
   append_groups<RI / 2 + 1>(app, gs, gl, m, g.r.blk, wg_base);
+  // strided: neighbouring lanes store neighbouring rows
+#pragma unroll
+  for (int q = 0; q < RI; q++) {
+    const uint32_t i = q * NT + threadIdx.x;
+    if (i < tn) {
+      const uint32_t v = tv[i], r = tk[i];
+      if (vin != SA) SA[g.lo + i] = v;
+      if (r != 0xFFFFFFFFu) rank[v] = r;
+    }
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_rename_b(const SegRec* __restrict__ segs, const uint32_t* __restrict__ owner,
