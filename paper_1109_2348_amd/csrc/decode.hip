@@ -151,7 +151,8 @@ struct BitIn {
   uint32_t pos;    // next dword of the current window
   uint64_t buf;    // bits not yet used, from the top
   int nb;          // how many
-  uint64_t used;   // bits consumed
+  uint32_t taken;  // dwords moved into buf
+  uint32_t drop;   // bits of the first dword before the start
   __device__ __forceinline__ void load_next() {
     const uint64_t q = 4 * (wnext + lane());
 #pragma unroll
@@ -168,17 +169,20 @@ struct BitIn {
     pos = 0;
     buf = 0;
     nb = 0;
+    taken = 0;
     refill();
-    const int drop = (int)(bit & 31);
+    drop = (uint32_t)(bit & 31);
     buf <<= drop;
-    nb -= drop;
-    used = 0;
+    nb -= (int)drop;
   }
+  // bits consumed since the start
+  __device__ __forceinline__ uint64_t used() const { return 32ull * taken - (uint64_t)nb - drop; }
   __device__ __forceinline__ void refill() {
     if (nb <= 32) {
       const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)cur, (int)pos);
       buf |= (uint64_t)w << (32 - nb);
       nb += 32;
+      taken++;
       if (++pos == BZG_WAVE) {
         cur = joined();
         load_next();
@@ -190,7 +194,6 @@ struct BitIn {
   __device__ __forceinline__ void skip(int k) {
     buf <<= k;
     nb -= k;
-    used += k;
   }
   __device__ __forceinline__ uint32_t get(int k) {  // k <= 24
     refill();
@@ -202,31 +205,33 @@ struct BitIn {
 
 constexpr uint32_t MAX_SEL = 18002;  // selectors kept per block (more are read and dropped)
 constexpr int DEC_MAXLEN = 20;
-constexpr uint32_t OBUF = 4096;  // output bytes staged per block decoder
+constexpr uint32_t OBUF = 4096;    // output bytes staged per inverse-MTF chunk
+constexpr uint32_t MTF_CH = 4096;  // symbols per inverse-MTF chunk
 
 // One wave per block: header, symbol map, selectors, code tables, then
-// every symbol: Huffman code (first-level table, then the canonical limits),
-// RUNA/RUNB runs, inverse move-to-front.  The move-to-front list is held
-// four bytes per lane in one register and moved with lane shifts.  Writes
-// the BWT column, its length, origPtr, the stored CRC and the byte counts.
+// every Huffman code up to end-of-block (first-level table, then the
+// canonical limits).  Writes the block's symbols (RUNA/RUNB digits and
+// move-to-front positions + 1, uint16, in the block's range of `syms`),
+// their count, the move-to-front list it starts from (the in-use bytes,
+// ascending), origPtr and the stored CRC.  The move-to-front and run
+// decoding run afterwards, in parallel over chunks.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restrict__ in, uint64_t n_in,
                                                         const DecBlk* __restrict__ blks,
-                                                        const uint32_t* __restrict__ order, uint8_t* __restrict__ L,
-                                                        uint32_t* __restrict__ out_n,
+                                                        const uint32_t* __restrict__ order,
+                                                        uint16_t* __restrict__ syms, uint32_t* __restrict__ n_syms,
+                                                        uint8_t* __restrict__ mtf0,
                                                         uint32_t* __restrict__ out_orig,
-                                                        uint32_t* __restrict__ out_crc,
-                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ err) {
+                                                        uint32_t* __restrict__ out_crc, uint32_t* __restrict__ err) {
   __shared__ uint16_t lut[MAXG][1u << DEC_LUT_BITS];
   __shared__ uint16_t perm[MAXG][MAXA];
   __shared__ int32_t limit[MAXG][DEC_MAXLEN + 2];
   __shared__ uint32_t first[MAXG][DEC_MAXLEN + 2], start[MAXG][DEC_MAXLEN + 2];
   __shared__ uint8_t lens[MAXG][MAXA];
-  __shared__ uint8_t unseq[256];
-  __shared__ __align__(16) uint8_t obuf[OBUF];
+  __shared__ __align__(4) uint8_t unseq[256];
   __shared__ uint32_t srun[DEC_MAXLEN + 2];
   const uint32_t b = order[blockIdx.x];  // the longest blocks first
   const DecBlk B = blks[b];
-  uint8_t* Lb = L + B.l_off;
+  uint16_t* Sb = syms + (size_t)B.l_off;
   const uint32_t ln = lane();
   BitIn r{in, n_in};
   r.start(B.start);
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   // selectors: checked here and decoded again, one per group, in the symbol
   // loop by a second reader (unary table positions, move-to-front over the
   // tables)
-  const uint64_t sel_bit = B.start + r.used;
+  const uint64_t sel_bit = B.start + r.used();
   for (uint32_t s = 0; s < nsel && !bad; s++) {
     uint32_t j = 0;
     while (r.get(1)) {
@@ -285,6 +290,10 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
     }
   }
   __syncthreads();
+  // the list the block's move-to-front decoding starts from
+  for (uint32_t i = nin + ln; i < 256u; i += BZG_WAVE) unseq[i] = 0;
+  __syncthreads();
+  ((uint32_t*)(mtf0 + (size_t)b * 256))[ln] = ((const uint32_t*)unseq)[ln];
   // decoding tables: canonical first codes, limits, symbols by length
   if (!bad) {
     for (int t = 0; t < G; t++) {
@@ -333,134 +342,315 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
     }
   }
   __syncthreads();
-  // symbols.  The move-to-front list holds the bytes themselves (the
-  // in-use bytes, ascending, to start with), entries 4*ln .. 4*ln+3 in this
-  // lane; byte counts are kept by lane (byte & 63), four per lane.
-  uint32_t stk = 0;
-#pragma unroll
-  for (int j = 0; j < 4; j++) stk |= (uint32_t)unseq[min(4 * ln + j, 255u)] << (8 * j);
-  uint32_t hc[4] = {0, 0, 0, 0};
-  auto count = [&](uint32_t by, uint32_t k) {
-    const bool mine = (by & 63u) == ln;
-#pragma unroll
-    for (int q = 0; q < 4; q++) hc[q] += (mine && (by >> 6) == (uint32_t)q) ? k : 0u;
-  };
-  // Output bytes are staged in LDS and stored OBUF at a time with wide
-  // stores: global stores in the loop would be waited for with the input
-  // loads (one memory counter covers both).
-  uint32_t cnt = 0, flushed = 0;
-  auto flush_full = [&]() {
-#pragma unroll
-    for (uint32_t i0 = 0; i0 < OBUF; i0 += BZG_WAVE * 16) {
-      const uint32_t i = i0 + ln * 16;
-      *(uint4*)(Lb + flushed + i) = *(const uint4*)(obuf + i);
-    }
-    flushed += OBUF;
-  };
+  // symbols, a group of GROUP at a time with its table fixed: lane k holds
+  // the group's k-th symbol, and the
+  // group's symbols are stored together (coalesced).  A block has at most
+  // as many symbols as bytes.
   const uint32_t cap = B.cap;
-  uint32_t zrun = 0, zN = 1, gsel = 0, gleft = 0, t = 0;
+  uint32_t cnt = 0, gsel = 0;
   const uint32_t eob = (uint32_t)a - 1;
   BitIn rs{in, n_in};
   rs.start(sel_bit);
   uint32_t lst = 0x543210u;  // table list, 4 bits per entry, front in the low bits
+  bool ended = false;
   bad = uni(bad);
-  while (!bad) {
-    if (gleft == 0) {
-      if (gsel >= nsel_kept) {
-        bad = 1;
-        break;
-      }
-      // j ones and a zero (j < G, checked above): table at list position j
-      rs.refill();
-      const uint32_t j = (uint32_t)__builtin_clz(~rs.peek(32) | 1u);
-      rs.skip((int)j + 1);
-      t = (lst >> (4 * j)) & 15u;
-      const uint32_t below = lst & ((1u << (4 * j)) - 1u);
-      lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
-      gsel++;
-      gleft = GROUP;
-    }
-    gleft--;
-    r.refill();
-    const uint32_t e = uni(lut[t][r.peek(DEC_LUT_BITS)]);
-    uint32_t sym;
-    if (e >> 9) {
-      sym = e & 511u;
-      r.skip((int)(e >> 9));
-    } else {
-      int zn = DEC_LUT_BITS + 1;
-      while (zn <= DEC_MAXLEN && (int32_t)r.peek(zn) > (int32_t)uni(limit[t][zn])) zn++;
-      if (zn > DEC_MAXLEN) {
-        bad = 1;
-        break;
-      }
-      const uint32_t idx = uni(start[t][zn]) + r.peek(zn) - uni(first[t][zn]);
-      if (idx >= (uint32_t)a) {
-        bad = 1;
-        break;
-      }
-      sym = uni(perm[t][idx]);
-      r.skip(zn);
-    }
-    if (sym <= 1) {  // RUNA / RUNB: a digit of the zero run, least significant first
-      zrun += (sym + 1) * zN;
-      zN <<= 1;
-      if (zrun > cap || zN > (1u << 24)) {
-        bad = 1;
-        break;
-      }
-      continue;
-    }
-    if (zrun) {  // the run: copies of the list's front byte
-      if (cnt + zrun > cap) {
-        bad = 1;
-        break;
-      }
-      const uint8_t by = (uint8_t)((uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u);
-      count(by, zrun);
-      while (zrun) {
-        const uint32_t k = min(zrun, OBUF - (cnt - flushed));
-        for (uint32_t j0 = 0; j0 < k; j0 += BZG_WAVE)
-          if (j0 + ln < k) obuf[cnt - flushed + j0 + ln] = by;
-        cnt += k;
-        zrun -= k;
-        if (cnt - flushed == OBUF) flush_full();
-      }
-      zN = 1;
-    }
-    if (sym == eob) break;
-    const uint32_t i = sym - 1;  // list position, 1 .. nin-1
-    if (i >= nin || cnt >= cap) {
+  while (!bad && !ended) {
+    if (gsel >= nsel_kept) {
       bad = 1;
       break;
     }
-    const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)stk, (int)(i >> 2));
-    const uint32_t uc = (word >> (8 * (i & 3u))) & 255u;
-    // positions 0 .. i-1 move up one, uc goes to the front
-    const uint32_t prev = wave_shr1(0u, stk);
-    const uint32_t up = (stk << 8) | (prev >> 24);
-    const int q0 = 4 * (int)ln;
-    const int take = min(max((int)i - q0 + 1, 0), 4);  // bytes of this lane at positions <= i
-    const uint32_t m = take == 4 ? 0xFFFFFFFFu : ((1u << (8 * take)) - 1u);
-    stk = (up & m) | (stk & ~m);
-    if (ln == 0) stk = (stk & ~255u) | uc;
-    const uint8_t by = (uint8_t)uc;
-    if (ln == 0) obuf[cnt - flushed] = by;
-    count(by, 1);
-    cnt++;
-    if (cnt - flushed == OBUF) flush_full();
+    // j ones and a zero (j < G, checked above): table at list position j
+    rs.refill();
+    const uint32_t j = (uint32_t)__builtin_clz(~rs.peek(32) | 1u);
+    rs.skip((int)j + 1);
+    const uint32_t t = (lst >> (4 * j)) & 15u;
+    const uint32_t below = lst & ((1u << (4 * j)) - 1u);
+    lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
+    gsel++;
+    uint32_t sv = 0, k = 0;
+    for (; k < (uint32_t)GROUP; k++) {
+      r.refill();
+      const uint32_t e = uni(lut[t][r.peek(DEC_LUT_BITS)]);
+      uint32_t sym;
+      if (e >> 9) {
+        sym = e & 511u;
+        r.skip((int)(e >> 9));
+      } else {
+        int zn = DEC_LUT_BITS + 1;
+        while (zn <= DEC_MAXLEN && (int32_t)r.peek(zn) > (int32_t)uni(limit[t][zn])) zn++;
+        if (zn > DEC_MAXLEN) {
+          bad = 1;
+          break;
+        }
+        const uint32_t idx = uni(start[t][zn]) + r.peek(zn) - uni(first[t][zn]);
+        if (idx >= (uint32_t)a) {
+          bad = 1;
+          break;
+        }
+        sym = uni(perm[t][idx]);
+        r.skip(zn);
+      }
+      if (sym == eob) {
+        ended = true;
+        break;
+      }
+      // (symbols are < a: a literal's list position, sym - 1, is < nin)
+      sv = ln == k ? sym : sv;
+    }
+    if (bad) break;
+    if (cnt + k > cap) {
+      bad = 1;
+      break;
+    }
+    if (ln < k) Sb[cnt + ln] = (uint16_t)sv;
+    cnt += k;
   }
-  for (uint32_t j = ln; j < cnt - flushed; j += BZG_WAVE) Lb[flushed + j] = obuf[j];
   // the block's bits must end exactly where the next marker starts
-  bad |= (B.start + r.used != B.end);
-  bad |= (cnt == 0) | (orig >= cnt);
-#pragma unroll
-  for (int q = 0; q < 4; q++) hist[(size_t)b * 256 + 64 * q + ln] = bad ? 0u : hc[q];
+  bad |= !ended | (cnt == 0);  // a block holds at least one byte
+  bad |= (B.start + r.used() != B.end);
   if (ln == 0) {
-    out_n[b] = bad ? 0u : cnt;
-    out_orig[b] = bad ? 0u : orig;
+    n_syms[b] = bad ? 0u : cnt;
+    out_orig[b] = orig;
     out_crc[b] = crc;
     if (bad) atomicOr(err, ERR_STREAM);
+  }
+}
+
+// ------------------------------------------- move-to-front, run decoding
+
+// List entry i (i < 256) of a move-to-front list held four entries per lane
+// (entry 4*lane + k in byte k), moved to the front; returns it.
+__device__ __forceinline__ uint32_t mtf_take(uint32_t& stk, uint32_t i) {
+  const uint32_t ln = lane();
+  const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)stk, (int)(i >> 2));
+  const uint32_t uc = (word >> (8 * (i & 3u))) & 255u;
+  // positions 0 .. i-1 move up one, uc goes to the front
+  const uint32_t prev = wave_shr1(0u, stk);
+  const uint32_t up = (stk << 8) | (prev >> 24);
+  const int take = min(max((int)i - 4 * (int)ln + 1, 0), 4);  // bytes of this lane at positions <= i
+  const uint32_t m = take == 4 ? 0xFFFFFFFFu : ((1u << (8 * take)) - 1u);
+  stk = (up & m) | (stk & ~m);
+  if (ln == 0) stk = (stk & ~255u) | uc;
+  return uc;
+}
+
+// The first symbol at or after s that starts an item (a literal, or the
+// first digit of a run): s itself unless s continues a run begun before it.
+// Runs are at most a few dozen digits; a longer one is flagged.
+__device__ __forceinline__ uint32_t item_start(const uint16_t* __restrict__ S, uint32_t n, uint32_t s,
+                                               uint32_t* __restrict__ err) {
+  if (s == 0 || s >= n) return min(s, n);
+  // window lane w: symbol s - 1 + w (past the end: taken as a literal)
+  const uint32_t i = s - 1 + lane();
+  const uint64_t lit = __ballot(i >= n || S[i] >= 2u);
+  // symbol s + k starts an item when it, or the one before it, is a literal
+  const uint64_t st = (lit | (lit >> 1)) & ~(1ull << 63);
+  if (!st) {
+    if (lane() == 0) atomicOr(err, ERR_STREAM);
+    return n;
+  }
+  return min(s + (uint32_t)(__ffsll((long long)st) - 1), n);
+}
+
+// Chunk slot j of the per-block chunk layout: its block and index there.
+struct MtfChunk {
+  uint32_t b, c;
+};
+__device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, uint32_t nb, uint64_t j) {
+  MtfChunk k;
+  uint32_t lo = 0, hi = nb;  // ch0[lo] <= j < ch0[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (ch0[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  k.b = lo;
+  k.c = (uint32_t)(j - ch0[lo]);
+  return k;
+}
+
+__device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
+                               uint32_t nb, const uint16_t* __restrict__ syms, const uint32_t* __restrict__ n_syms,
+                               uint8_t* __restrict__ T, uint32_t* __restrict__ cs, uint32_t* __restrict__ ce,
+                               uint32_t* __restrict__ clen, uint32_t* __restrict__ err) {
+  const MtfChunk k = mtf_chunk(ch0, nb, j);
+  const uint32_t n = n_syms[k.b];
+  if ((uint64_t)k.c * MTF_CH >= n) return;
+  const DecBlk B = blks[k.b];
+  const uint16_t* S = syms + (size_t)B.l_off;
+  const uint32_t ln = lane();
+  const uint32_t s = item_start(S, n, k.c * MTF_CH, err);
+  const uint32_t e = item_start(S, n, (uint32_t)min((uint64_t)(k.c + 1) * MTF_CH, (uint64_t)n), err);
+  uint32_t stk = (4u * ln) | ((4u * ln + 1u) << 8) | ((4u * ln + 2u) << 16) | ((4u * ln + 3u) << 24);
+  uint64_t out = 0, run = 0;
+  uint32_t rk = 0;
+  for (uint32_t base = s; base < e; base += BZG_WAVE) {
+    const uint32_t m = min((uint32_t)BZG_WAVE, e - base);
+    const uint32_t v = ln < m ? S[base + ln] : 0u;
+    for (uint32_t q = 0; q < m; q++) {
+      const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)q);
+      if (x <= 1u) {  // RUNA / RUNB: a digit of the zero run, least significant first
+        run += (uint64_t)(x + 1u) << min(rk, 40u);
+        rk++;
+        continue;
+      }
+      out += run + 1u;
+      run = 0;
+      rk = 0;
+      (void)mtf_take(stk, x - 1u);
+    }
+  }
+  out += run;
+  const bool bad = rk > 40u || out > B.cap;
+  ((uint32_t*)(T + B.l_off + (size_t)k.c * 256))[ln] = stk;
+  if (ln == 0) {
+    cs[j] = s;
+    ce[j] = e;
+    clen[j] = bad ? B.cap + 1u : (uint32_t)out;
+  }
+}
+
+// A block's chunk c holds the items that start among its symbols
+// [c*MTF_CH, (c+1)*MTF_CH).  Move-to-front decoding of a chunk moves list
+// positions the same way whatever the list holds, so each chunk's effect is
+// a permutation of positions, found here by decoding it on the identity
+// list (one wave per chunk); chunks are then chained by composing them.
+// Also the chunk's item range and output length.  Per block, the
+// permutations sit in the first cap/MTF_CH + 1 256-byte slots of its T range
+// and the chunks' starting lists in the next as many.
+__global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_perm(const DecBlk* __restrict__ blks,
+                                                           const uint64_t* __restrict__ ch0, uint32_t nb,
+                                                           uint64_t ch_total, const uint16_t* __restrict__ syms,
+                                                           const uint32_t* __restrict__ n_syms,
+                                                           uint8_t* __restrict__ T, uint32_t* __restrict__ cs,
+                                                           uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
+                                                           uint32_t* __restrict__ err) {
+  for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x) mtf_perm_chunk(j, blks, ch0, nb, syms, n_syms, T, cs, ce,
+                                                                             clen, err);
+}
+// Per block (one wave): each chunk's starting list and output offset, by
+// composing the chunk permutations in order from the block's first list;
+// then the block's length and its checks (at least one byte, origPtr inside).
+__global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restrict__ blks,
+                                                           const uint64_t* __restrict__ ch0,
+                                                           const uint32_t* __restrict__ n_syms,
+                                                           const uint8_t* __restrict__ mtf0, uint8_t* __restrict__ T,
+                                                           const uint32_t* __restrict__ clen,
+                                                           uint32_t* __restrict__ coff, const uint32_t* __restrict__ orig,
+                                                           uint32_t* __restrict__ n_rows, uint32_t* __restrict__ err) {
+  __shared__ __align__(4) uint8_t lst[256];
+  const uint32_t b = blockIdx.x, ln = lane();
+  const DecBlk B = blks[b];
+  const uint32_t n = n_syms[b];
+  const uint32_t nch = (n + MTF_CH - 1) / MTF_CH, slots = B.cap / MTF_CH + 1;
+  const uint64_t j0 = ch0[b];
+  uint8_t* Tb = T + B.l_off;
+  ((uint32_t*)lst)[ln] = ((const uint32_t*)(mtf0 + (size_t)b * 256))[ln];
+  __syncthreads();
+  uint64_t acc = 0;
+  for (uint32_t c0 = 0; c0 < nch; c0 += BZG_WAVE) {
+    // output offsets of 64 chunks at once
+    const uint32_t c = c0 + ln;
+    const uint64_t len = c < nch ? clen[j0 + c] : 0u;
+    const uint64_t inc = wave_incl_sum(len);
+    if (c < nch) coff[j0 + c] = (uint32_t)min(acc + inc - len, (uint64_t)B.cap + 1u);
+    acc += wave_last(inc);
+    const uint32_t m = min((uint32_t)BZG_WAVE, nch - c0);
+    uint32_t pw = ((const uint32_t*)(Tb + (size_t)c0 * 256))[ln];
+    for (uint32_t q = 0; q < m; q++) {
+      const uint32_t cc = c0 + q;
+      // this chunk's permutation in hand, the next one's loaded
+      const uint32_t pn = q + 1 < m ? ((const uint32_t*)(Tb + (size_t)(cc + 1) * 256))[ln] : 0u;
+      const uint32_t cur = ((const uint32_t*)lst)[ln];
+      ((uint32_t*)(Tb + (size_t)(slots + cc) * 256))[ln] = cur;
+      const uint32_t nw = (uint32_t)lst[pw & 255u] | ((uint32_t)lst[(pw >> 8) & 255u] << 8) |
+                          ((uint32_t)lst[(pw >> 16) & 255u] << 16) | ((uint32_t)lst[pw >> 24] << 24);
+      __syncthreads();
+      ((uint32_t*)lst)[ln] = nw;
+      __syncthreads();
+      pw = pn;
+    }
+  }
+  const bool bad = n != 0 && (acc == 0 || acc > B.cap || orig[b] >= acc);
+  if (ln == 0) {
+    n_rows[b] = n == 0 || bad ? 0u : (uint32_t)acc;
+    if (bad) atomicOr(err, ERR_STREAM);
+  }
+}
+
+// One wave per chunk: move-to-front and run decoding from the chunk's
+// starting list, into the BWT column at the chunk's offset (staged in LDS,
+// stored OBUF bytes at a time).
+__device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
+                               uint32_t nb, const uint16_t* __restrict__ syms, const uint32_t* __restrict__ n_syms,
+                               const uint8_t* __restrict__ T, const uint32_t* __restrict__ cs,
+                               const uint32_t* __restrict__ ce, const uint32_t* __restrict__ coff,
+                               const uint32_t* __restrict__ n_rows, uint8_t* __restrict__ L, uint8_t* obuf) {
+  const MtfChunk k = mtf_chunk(ch0, nb, j);
+  const uint32_t n = n_syms[k.b], rows = n_rows[k.b];
+  if ((uint64_t)k.c * MTF_CH >= n || rows == 0) return;  // past the symbols, or a bad block
+  const DecBlk B = blks[k.b];
+  const uint16_t* S = syms + (size_t)B.l_off;
+  const uint32_t ln = lane(), slots = B.cap / MTF_CH + 1;
+  uint32_t stk = ((const uint32_t*)(T + B.l_off + (size_t)(slots + k.c) * 256))[ln];
+  const uint32_t s = cs[j], e = ce[j];
+  uint8_t* out = L + B.l_off + coff[j];  // the block's length checks bound every chunk inside it
+  uint32_t cnt = 0, flushed = 0;
+  auto flush = [&]() {
+    __syncthreads();
+    for (uint32_t i = ln; i < cnt - flushed; i += BZG_WAVE) out[flushed + i] = obuf[i];
+    __syncthreads();
+    flushed = cnt;
+  };
+  auto emit_run = [&](uint32_t by, uint64_t r) {
+    while (r) {
+      const uint32_t q = (uint32_t)min(r, (uint64_t)(OBUF - (cnt - flushed)));
+      for (uint32_t i0 = 0; i0 < q; i0 += BZG_WAVE)
+        if (i0 + ln < q) obuf[cnt - flushed + i0 + ln] = (uint8_t)by;
+      cnt += q;
+      r -= q;
+      if (cnt - flushed == OBUF) flush();
+    }
+  };
+  uint64_t run = 0;
+  uint32_t rk = 0;
+  for (uint32_t base = s; base < e; base += BZG_WAVE) {
+    const uint32_t m = min((uint32_t)BZG_WAVE, e - base);
+    const uint32_t v = ln < m ? S[base + ln] : 0u;
+    for (uint32_t q = 0; q < m; q++) {
+      const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)q);
+      if (x <= 1u) {
+        run += (uint64_t)(x + 1u) << min(rk, 40u);
+        rk++;
+        continue;
+      }
+      if (run) emit_run((uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u, run);
+      run = 0;
+      rk = 0;
+      const uint32_t uc = mtf_take(stk, x - 1u);
+      if (ln == 0) obuf[cnt - flushed] = (uint8_t)uc;
+      cnt++;
+      if (cnt - flushed == OBUF) flush();
+    }
+  }
+  if (run) emit_run((uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u, run);
+  flush();
+}
+
+__global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restrict__ blks,
+                                                           const uint64_t* __restrict__ ch0, uint32_t nb,
+                                                           uint64_t ch_total, const uint16_t* __restrict__ syms,
+                                                           const uint32_t* __restrict__ n_syms,
+                                                           const uint8_t* __restrict__ T,
+                                                           const uint32_t* __restrict__ cs,
+                                                           const uint32_t* __restrict__ ce,
+                                                           const uint32_t* __restrict__ coff,
+                                                           const uint32_t* __restrict__ n_rows,
+                                                           uint8_t* __restrict__ L) {
+  __shared__ uint8_t obuf[OBUF];
+  for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x) {
+    mtf_emit_chunk(j, blks, ch0, nb, syms, n_syms, T, cs, ce, coff, n_rows, L, obuf);
+    __syncthreads();
   }
 }
 
@@ -471,8 +661,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
 // counting sort of the column (one workgroup per block, 256 rows a step).
 __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, const uint32_t* __restrict__ order,
                                                const uint8_t* __restrict__ L,
-                                               const uint32_t* __restrict__ n_rows,
-                                               const uint32_t* __restrict__ hist, uint32_t* __restrict__ FL) {
+                                               const uint32_t* __restrict__ n_rows, uint32_t* __restrict__ FL) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wc[NT / BZG_WAVE][256];
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
@@ -480,9 +669,21 @@ __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, 
   const uint32_t n = n_rows[b];
   const uint8_t* Lb = L + blks[b].l_off;
   uint32_t* F = FL + blks[b].l_off;
+  // the column's byte counts (LDS atomics, a word of 4 bytes per thread a
+  // step; the range is 16-byte aligned and padded), then their offsets
+  base[tid] = 0;
+  __syncthreads();
+  for (uint32_t k = 4 * tid; k < n; k += 4 * NT) {
+    const uint32_t v = *(const uint32_t*)(Lb + k);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++)
+      if (k + q < n) atomicAdd(&base[(v >> (8 * q)) & 255u], 1u);
+  }
+  __syncthreads();
   {
     uint32_t tot;
-    const uint32_t c = hist[(size_t)b * 256 + tid];
+    const uint32_t c = base[tid];
+    __syncthreads();
     base[tid] = block_excl_sum<uint32_t, NT>(c, sh, &tot);
     for (int q = 0; q < NT / BZG_WAVE; q++) wc[q][tid] = 0;
   }
@@ -791,17 +992,29 @@ hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipSt
 
 uint32_t dec_walk_slots(uint32_t cap) { return cap / WALK_STRIDE + 2; }
 uint32_t dec_rle_slots(uint32_t cap) { return cap / RLE_SEG + 1; }
+uint32_t dec_mtf_chunks(uint32_t cap) { return cap / MTF_CH + 1; }
 
 hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t nb = d.nb;
+  uint16_t* syms = (uint16_t*)d.FL;  // free until the map is built
   {
     ProfScope ps("dec_block", st, 0.0);
-    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, d.L,
-                       d.n_rows, d.orig, d.crc_want, d.hist, d.err);
+    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, syms, d.n_syms,
+                       d.mtf0, d.orig, d.crc_want, d.err);
+  }
+  const uint32_t gc = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(d.ch_total, 1), 1u << 16);
+  {
+    ProfScope ps("dec_mtf", st, 0.0);
+    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, syms,
+                       d.n_syms, d.T, d.cs, d.ce, d.clen, d.err);
+    hipLaunchKernelGGL(k_dec_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, d.n_syms, d.mtf0, d.T,
+                       d.clen, d.coff, d.orig, d.n_rows, d.err);
+    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, syms,
+                       d.n_syms, d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
   }
   {
     ProfScope ps("dec_fl", st, 0.0);
-    hipLaunchKernelGGL(k_dec_fl, dim3(nb), dim3(NT), 0, st, d.blks, d.order, d.L, d.n_rows, d.hist, d.FL);
+    hipLaunchKernelGGL(k_dec_fl, dim3(nb), dim3(NT), 0, st, d.blks, d.order, d.L, d.n_rows, d.FL);
   }
   const uint32_t gw = (uint32_t)((d.walk_total + NT - 1) / NT);
   {

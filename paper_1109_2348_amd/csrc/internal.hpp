@@ -285,7 +285,12 @@ struct DecRun {
   const DecBlk* blks;
   const uint32_t* order;  // blocks by decreasing bit length (launch order)
   uint8_t *L, *T, *out;
-  uint32_t *n_rows, *orig, *crc_want, *hist, *err, *FL;
+  uint32_t *n_rows, *orig, *crc_want, *err, *FL;
+  uint32_t* n_syms;       // per block: Huffman symbols before end-of-block
+  uint8_t* mtf0;          // per block: the 256-byte list move-to-front decoding starts from
+  const uint64_t* ch0;    // nb + 1 move-to-front chunk slot offsets
+  uint64_t ch_total;
+  uint32_t *cs, *ce, *clen, *coff;  // per chunk slot: item range, output length and offset
   const uint64_t* walk0;  // nb + 1 walker slot offsets
   uint64_t walk_total;
   uint32_t *nxt, *steps, *pos, *period;
@@ -302,6 +307,7 @@ uint64_t dec_find_tiles(uint64_t n);
 hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipStream_t st);
 uint32_t dec_walk_slots(uint32_t cap);
 uint32_t dec_rle_slots(uint32_t cap);
+uint32_t dec_mtf_chunks(uint32_t cap);
 hipError_t dec_run(const DecRun& d, hipStream_t st);
 hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
                      const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
