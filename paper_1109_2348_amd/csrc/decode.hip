@@ -659,6 +659,8 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restr
 // FL of one block: the row that holds, in the last column, the k-th
 // occurrence of the byte that is first in row C[byte] + k -- a stable
 // counting sort of the column (one workgroup per block, 256 rows a step).
+// Each entry carries that byte in its top 8 bits (rows < 2^24), so the walks
+// read one array.
 __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, const uint32_t* __restrict__ order,
                                                const uint8_t* __restrict__ L,
                                                const uint32_t* __restrict__ n_rows, uint32_t* __restrict__ FL) {
@@ -698,7 +700,7 @@ __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, 
     __syncthreads();
     uint32_t before = 0;
     for (uint32_t q = 0; q < w; q++) before += wc[q][d];
-    if (ok) F[base[d] + before + rank] = k;
+    if (ok) F[base[d] + before + rank] = k | (d << 24);
     __syncthreads();
     uint32_t all = 0;
     for (int q = 0; q < NT / BZG_WAVE; q++) {
@@ -738,6 +740,14 @@ __device__ __forceinline__ uint32_t owner_of(const uint64_t* __restrict__ s0, ui
   }
   return lo;
 }
+// The same for a workgroup of consecutive slots: one search for its first
+// slot (workgroup-uniform), then each thread steps over the few blocks its
+// slot lies past.
+__device__ __forceinline__ uint32_t owner_of_wg(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
+  uint32_t b = owner_of(s0, nb, (uint64_t)blockIdx.x * blockDim.x);
+  while (b + 1 < nb && s0[b + 1] <= j) b++;
+  return b;
+}
 
 constexpr uint32_t UNVISITED = 0xFFFFFFFFu;
 
@@ -750,14 +760,14 @@ __global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks
                                                  uint32_t* __restrict__ pos) {
   const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
   if (j >= total) return;
-  const uint32_t b = owner_of(s0, nb, j);
+  const uint32_t b = owner_of_wg(s0, nb, j);
   const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b];
   pos[j] = UNVISITED;
   if (n == 0 || s >= samples_of(n, orig)) return;
   const uint32_t* F = FL + blks[b].l_off;
   uint32_t row = sample_row(s, n, orig), c = 0;
   do {
-    row = F[row];
+    row = F[row] & 0xFFFFFFu;
     c++;
   } while (!is_sample(row, orig) && c < n);
   nxt[j] = sample_index(row, n, orig);
@@ -795,25 +805,25 @@ __global__ void k_dec_chain(const uint64_t* __restrict__ s0, uint32_t nb, const 
 __global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
                                                  uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
                                                  const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
-                                                 const uint8_t* __restrict__ L, const uint32_t* __restrict__ steps,
+                                                 const uint32_t* __restrict__ steps,
                                                  const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
                                                  uint8_t* __restrict__ T) {
   const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
   if (j >= total) return;
   const uint32_t p0 = pos[j];
   if (p0 == UNVISITED) return;
-  const uint32_t b = owner_of(s0, nb, j);
+  const uint32_t b = owner_of_wg(s0, nb, j);
   const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b], per = period[b];
   if (per == 0) return;
   const uint64_t o = blks[b].l_off;
   const uint32_t* F = FL + o;
-  const uint8_t* Lb = L + o;
   uint8_t* Tb = T + o;
   uint32_t row = sample_row(s, n, orig);
   const uint32_t c = steps[j];
   for (uint32_t k = 0; k < c && p0 + k < per; k++) {
-    row = F[row];
-    Tb[p0 + k] = Lb[row];
+    const uint32_t v = F[row];
+    row = v & 0xFFFFFFu;
+    Tb[p0 + k] = (uint8_t)(v >> 24);
   }
 }
 
@@ -855,7 +865,7 @@ __global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks
                                                  uint64_t* __restrict__ summ) {
   const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
   if (j >= total) return;
-  const uint32_t b = owner_of(g0, nb, j);
+  const uint32_t b = owner_of_wg(g0, nb, j);
   const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
   if ((uint64_t)g * RLE_SEG >= n) return;
   const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
@@ -938,7 +948,7 @@ __global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks
                                                  const uint32_t* __restrict__ skip, uint8_t* __restrict__ out) {
   const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
   if (j >= total || *skip) return;
-  const uint32_t b = owner_of(g0, nb, j);
+  const uint32_t b = owner_of_wg(g0, nb, j);
   const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
   if ((uint64_t)g * RLE_SEG >= n) return;
   const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
@@ -1027,7 +1037,7 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   {
     ProfScope ps("dec_emit", st, 0.0);
     hipLaunchKernelGGL(k_dec_emit, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
-                       d.walk_total, d.n_rows, d.orig, d.FL, d.L, d.steps, d.pos, d.period, d.T);
+                       d.walk_total, d.n_rows, d.orig, d.FL, d.steps, d.pos, d.period, d.T);
   }
   hipLaunchKernelGGL(k_dec_repeat, dim3(nb), dim3(NT), 0, st, d.blks, d.n_rows, d.period, d.T);
   const uint32_t gr = (uint32_t)((d.rle_total + NT - 1) / NT);
