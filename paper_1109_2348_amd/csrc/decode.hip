@@ -470,9 +470,10 @@ __device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, 
 }
 
 __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, const uint16_t* __restrict__ syms, const uint32_t* __restrict__ n_syms,
-                               uint8_t* __restrict__ T, uint32_t* __restrict__ cs, uint32_t* __restrict__ ce,
-                               uint32_t* __restrict__ clen, uint32_t* __restrict__ err) {
+                               uint32_t nb, const uint16_t* __restrict__ syms, uint8_t* __restrict__ Q,
+                               const uint32_t* __restrict__ n_syms, uint8_t* __restrict__ T,
+                               uint32_t* __restrict__ cs, uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
+                               uint32_t* __restrict__ err) {
   const MtfChunk k = mtf_chunk(ch0, nb, j);
   const uint32_t n = n_syms[k.b];
   if ((uint64_t)k.c * MTF_CH >= n) return;
@@ -481,24 +482,30 @@ __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
   const uint32_t ln = lane();
   const uint32_t s = item_start(S, n, k.c * MTF_CH, err);
   const uint32_t e = item_start(S, n, (uint32_t)min((uint64_t)(k.c + 1) * MTF_CH, (uint64_t)n), err);
+  uint8_t* Qb = Q + B.l_off;
   uint32_t stk = (4u * ln) | ((4u * ln + 1u) << 8) | ((4u * ln + 2u) << 16) | ((4u * ln + 3u) << 24);
   uint64_t out = 0, run = 0;
   uint32_t rk = 0;
   for (uint32_t base = s; base < e; base += BZG_WAVE) {
     const uint32_t m = min((uint32_t)BZG_WAVE, e - base);
     const uint32_t v = ln < m ? S[base + ln] : 0u;
+    uint32_t qv = 0;  // lane q: the starting-list index of symbol base + q's byte
     for (uint32_t q = 0; q < m; q++) {
       const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)q);
+      uint32_t from;
       if (x <= 1u) {  // RUNA / RUNB: a digit of the zero run, least significant first
         run += (uint64_t)(x + 1u) << min(rk, 40u);
         rk++;
-        continue;
+        from = (uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u;  // the run repeats the front
+      } else {
+        out += run + 1u;
+        run = 0;
+        rk = 0;
+        from = mtf_take(stk, x - 1u);
       }
-      out += run + 1u;
-      run = 0;
-      rk = 0;
-      (void)mtf_take(stk, x - 1u);
+      qv = ln == q ? from : qv;
     }
+    if (ln < m) Qb[base + ln] = (uint8_t)qv;
   }
   out += run;
   const bool bad = rk > 40u || out > B.cap;
@@ -515,18 +522,21 @@ __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 // positions the same way whatever the list holds, so each chunk's effect is
 // a permutation of positions, found here by decoding it on the identity
 // list (one wave per chunk); chunks are then chained by composing them.
-// Also the chunk's item range and output length.  Per block, the
+// Also the chunk's item range and output length, and for every symbol the
+// index in the chunk's starting list of the byte it stands for (the front,
+// for a run digit), so that the bytes follow from that list without
+// decoding again.  Per block, the
 // permutations sit in the first cap/MTF_CH + 1 256-byte slots of its T range
 // and the chunks' starting lists in the next as many.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_perm(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
                                                            uint64_t ch_total, const uint16_t* __restrict__ syms,
-                                                           const uint32_t* __restrict__ n_syms,
+                                                           uint8_t* __restrict__ Q, const uint32_t* __restrict__ n_syms,
                                                            uint8_t* __restrict__ T, uint32_t* __restrict__ cs,
                                                            uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                                            uint32_t* __restrict__ err) {
-  for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x) mtf_perm_chunk(j, blks, ch0, nb, syms, n_syms, T, cs, ce,
-                                                                             clen, err);
+  for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x)
+    mtf_perm_chunk(j, blks, ch0, nb, syms, Q, n_syms, T, cs, ce, clen, err);
 }
 // Per block (one wave): each chunk's starting list and output offset, by
 // composing the chunk permutations in order from the block's first list;
@@ -578,68 +588,87 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restr
   }
 }
 
-// One wave per chunk: move-to-front and run decoding from the chunk's
-// starting list, into the BWT column at the chunk's offset (staged in LDS,
-// stored OBUF bytes at a time).
+// One wave per chunk, 64 symbols a step: every symbol's byte is its
+// starting-list entry, so a step finds each run's length (a segmented sum of
+// its digits' weights, a run carried across steps), each item's output
+// offset (a scan of the counts), and writes the bytes (literals one per
+// lane, runs by their last digit's lane, long runs by the whole wave).
 __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, const uint16_t* __restrict__ syms, const uint32_t* __restrict__ n_syms,
-                               const uint8_t* __restrict__ T, const uint32_t* __restrict__ cs,
-                               const uint32_t* __restrict__ ce, const uint32_t* __restrict__ coff,
-                               const uint32_t* __restrict__ n_rows, uint8_t* __restrict__ L, uint8_t* obuf) {
+                               uint32_t nb, const uint16_t* __restrict__ syms, const uint8_t* __restrict__ Q,
+                               const uint32_t* __restrict__ n_syms, const uint8_t* __restrict__ T,
+                               const uint32_t* __restrict__ cs, const uint32_t* __restrict__ ce,
+                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ n_rows,
+                               uint8_t* __restrict__ L, uint8_t* lst) {
   const MtfChunk k = mtf_chunk(ch0, nb, j);
   const uint32_t n = n_syms[k.b], rows = n_rows[k.b];
   if ((uint64_t)k.c * MTF_CH >= n || rows == 0) return;  // past the symbols, or a bad block
   const DecBlk B = blks[k.b];
   const uint16_t* S = syms + (size_t)B.l_off;
+  const uint8_t* Qb = Q + B.l_off;
   const uint32_t ln = lane(), slots = B.cap / MTF_CH + 1;
-  uint32_t stk = ((const uint32_t*)(T + B.l_off + (size_t)(slots + k.c) * 256))[ln];
+  ((uint32_t*)lst)[ln] = ((const uint32_t*)(T + B.l_off + (size_t)(slots + k.c) * 256))[ln];
+  __syncthreads();
   const uint32_t s = cs[j], e = ce[j];
   uint8_t* out = L + B.l_off + coff[j];  // the block's length checks bound every chunk inside it
-  uint32_t cnt = 0, flushed = 0;
-  auto flush = [&]() {
-    __syncthreads();
-    for (uint32_t i = ln; i < cnt - flushed; i += BZG_WAVE) out[flushed + i] = obuf[i];
-    __syncthreads();
-    flushed = cnt;
-  };
-  auto emit_run = [&](uint32_t by, uint64_t r) {
-    while (r) {
-      const uint32_t q = (uint32_t)min(r, (uint64_t)(OBUF - (cnt - flushed)));
-      for (uint32_t i0 = 0; i0 < q; i0 += BZG_WAVE)
-        if (i0 + ln < q) obuf[cnt - flushed + i0 + ln] = (uint8_t)by;
-      cnt += q;
-      r -= q;
-      if (cnt - flushed == OBUF) flush();
-    }
-  };
-  uint64_t run = 0;
-  uint32_t rk = 0;
+  uint64_t acc = 0;  // bytes written
+  // a run going on from the step before: its digits so far and their sum
+  uint32_t ck = 0;
+  uint64_t cv = 0;
+  bool cdig = false;
   for (uint32_t base = s; base < e; base += BZG_WAVE) {
     const uint32_t m = min((uint32_t)BZG_WAVE, e - base);
-    const uint32_t v = ln < m ? S[base + ln] : 0u;
-    for (uint32_t q = 0; q < m; q++) {
-      const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)q);
-      if (x <= 1u) {
-        run += (uint64_t)(x + 1u) << min(rk, 40u);
-        rk++;
-        continue;
-      }
-      if (run) emit_run((uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u, run);
-      run = 0;
-      rk = 0;
-      const uint32_t uc = mtf_take(stk, x - 1u);
-      if (ln == 0) obuf[cnt - flushed] = (uint8_t)uc;
-      cnt++;
-      if (cnt - flushed == OBUF) flush();
+    const bool valid = ln < m;
+    const uint32_t x = valid ? S[base + ln] : 2u;
+    const uint32_t q = valid ? Qb[base + ln] : 0u;
+    const uint32_t xn = base + BZG_WAVE < e ? S[base + BZG_WAVE] : 2u;  // the symbol after the step
+    const bool dig = valid && x <= 1u;
+    const uint64_t digm = __ballot(dig);
+    const bool prevdig = ln == 0 ? cdig : ((digm >> (ln - 1)) & 1ull) != 0;
+    const uint64_t startm = __ballot(dig && !prevdig);
+    const uint64_t le = startm & (ln == BZG_WAVE - 1 ? ~0ull : ((2ull << ln) - 1ull));
+    const int ls = le ? 63 - (int)__clzll((long long)le) : -1;  // the run's first digit in this step
+    const uint32_t kk = ls >= 0 ? ln - (uint32_t)ls : ln + ck;   // the digit's place in its run
+    const uint64_t v = dig ? (uint64_t)(x + 1u) << min(kk, 40u) : 0ull;
+    const uint64_t inc = wave_incl_sum(v);
+    const int src = ls > 0 ? ls - 1 : 0;
+    const uint64_t at = (uint64_t)(uint32_t)__shfl((int)(uint32_t)inc, src) |
+                        ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(inc >> 32), src) << 32);
+    const uint64_t part = ls > 0 ? inc - at : ls == 0 ? inc : inc + cv;  // the run's sum up to this digit
+    const bool nextdig = ln == BZG_WAVE - 1 ? xn <= 1u : ((digm >> (ln + 1)) & 1ull) != 0;
+    const bool run_end = dig && !nextdig;
+    const uint64_t cnt = !valid ? 0ull : dig ? (run_end ? part : 0ull) : 1ull;
+    // a run going on into the next step
+    const bool last_dig = ((digm >> (BZG_WAVE - 1)) & 1ull) != 0 && xn <= 1u;
+    const uint32_t ck_n = (uint32_t)__builtin_amdgcn_readlane((int)kk, BZG_WAVE - 1) + 1u;
+    const uint64_t cv_n = wave_last(part);
+    cdig = last_dig;
+    ck = last_dig ? ck_n : 0u;
+    cv = last_dig ? cv_n : 0ull;
+    const uint64_t ci = wave_incl_sum(cnt);
+    const uint64_t o = acc + ci - cnt;
+    acc += wave_last(ci);
+    const uint8_t by = lst[q];
+    if (valid && !dig) out[o] = by;
+    if (run_end && part <= BZG_WAVE)
+      for (uint32_t i = 0; i < (uint32_t)part; i++) out[o + i] = by;
+    uint64_t bigm = __ballot(run_end && part > BZG_WAVE);
+    while (bigm) {  // long runs: the whole wave writes each
+      const int l = (int)(__ffsll((long long)bigm) - 1);
+      bigm &= bigm - 1;
+      const uint64_t R = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)part, l) |
+                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(part >> 32), l) << 32);
+      const uint64_t oo = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)o, l) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(o >> 32), l) << 32);
+      const uint8_t b8 = (uint8_t)__builtin_amdgcn_readlane((int)by, l);
+      for (uint64_t i = ln; i < R; i += BZG_WAVE) out[oo + i] = b8;
     }
   }
-  if (run) emit_run((uint32_t)__builtin_amdgcn_readlane((int)stk, 0) & 255u, run);
-  flush();
 }
 
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
                                                            uint64_t ch_total, const uint16_t* __restrict__ syms,
+                                                           const uint8_t* __restrict__ Q,
                                                            const uint32_t* __restrict__ n_syms,
                                                            const uint8_t* __restrict__ T,
                                                            const uint32_t* __restrict__ cs,
@@ -647,9 +676,9 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restr
                                                            const uint32_t* __restrict__ coff,
                                                            const uint32_t* __restrict__ n_rows,
                                                            uint8_t* __restrict__ L) {
-  __shared__ uint8_t obuf[OBUF];
+  __shared__ __align__(4) uint8_t lst[256];
   for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x) {
-    mtf_emit_chunk(j, blks, ch0, nb, syms, n_syms, T, cs, ce, coff, n_rows, L, obuf);
+    mtf_emit_chunk(j, blks, ch0, nb, syms, Q, n_syms, T, cs, ce, coff, n_rows, L, lst);
     __syncthreads();
   }
 }
@@ -1006,7 +1035,7 @@ uint32_t dec_mtf_chunks(uint32_t cap) { return cap / MTF_CH + 1; }
 
 hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t nb = d.nb;
-  uint16_t* syms = (uint16_t*)d.FL;  // free until the map is built
+  uint16_t* syms = (uint16_t*)d.FL;  // the map's range is free until the map is built
   {
     ProfScope ps("dec_block", st, 0.0);
     hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, syms, d.n_syms,
@@ -1016,11 +1045,11 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   {
     ProfScope ps("dec_mtf", st, 0.0);
     hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, syms,
-                       d.n_syms, d.T, d.cs, d.ce, d.clen, d.err);
+                       d.mtfq, d.n_syms, d.T, d.cs, d.ce, d.clen, d.err);
     hipLaunchKernelGGL(k_dec_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, d.n_syms, d.mtf0, d.T,
                        d.clen, d.coff, d.orig, d.n_rows, d.err);
     hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, syms,
-                       d.n_syms, d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
+                       d.mtfq, d.n_syms, d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
   }
   {
     ProfScope ps("dec_fl", st, 0.0);
