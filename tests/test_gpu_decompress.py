@@ -105,3 +105,25 @@ def test_capacity_retry_and_bad_input(bz):
     assert ei.value.code == bz.native.BZG_EDATA
     # the context still works
     assert bz.decompress(_dev(z)).cpu().numpy().tobytes() == data
+
+
+def _straddles(syms, step):
+    """Whether some run of RUNA/RUNB digits (symbols 0 and 1) crosses a
+    multiple of `step` in the symbol sequence."""
+    d = np.asarray(syms) <= 1
+    k = np.arange(step, d.size, step)
+    return bool(np.any(d[k] & d[k - 1]))
+
+
+def test_runs_across_chunk_and_step_boundaries(bz):
+    # large sparse blocks: thousands of zero runs among the symbols, so runs
+    # cross the decoder's 4096-symbol chunks and its 64-symbol steps (pinned
+    # below on the oracle's own symbol sequence of each block)
+    data = np.concatenate(W.source_blocks("sparse", [900_000, 700_001], 91)).astype(np.uint8)
+    offs = [0, 900_000, data.size]
+    for lo, hi in zip(offs[:-1], offs[1:]):
+        _, last, _ = cref.bwt(cref.rle1(data[lo:hi]))
+        syms = cref.mtf_zrle(last)[0]
+        assert _straddles(syms, 4096) and _straddles(syms, 64), "the block should exercise run carries"
+    z = cref.compress(data, offs, 9, threads=16)
+    _roundtrip(bz, z, data.tobytes(), "sparse 900 KB blocks with runs across chunks")
