@@ -367,6 +367,8 @@ class Compressor:
         return d_offsets
 
     def __call__(self, x: torch.Tensor, offsets=None, level: int = 9, block_bytes: Optional[int] = None):
+        """Compresses and waits; returns a view of the kept output buffer,
+        valid until this compressor's next call (clone it to keep it)."""
         x = _dev_u8(x)
         if offsets is None:
             offsets = uniform_offsets(x.numel(), block_bytes or 100000 * level)
