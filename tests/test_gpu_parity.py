@@ -310,6 +310,16 @@ def test_compress_uneven_blocks(bz):
     assert bz2.decompress(z) == b.data.tobytes()
 
 
+def test_compress_one_block_of_many_pieces(bz):
+    # one caller block cut by the RLE1 limit into over 80 pieces (level 1:
+    # 100000 bytes after RLE1 each), uniform bytes then runs, against the
+    # oracle's unbounded cut
+    d = np.concatenate(W.source_blocks("uniform", [7_600_000], 31) + W.source_blocks("sparse", [1_400_001], 32))
+    d = d.astype(np.uint8)
+    z = _check_compress(bz, d, [0, d.size], 1, "one 9 MB caller block, level 1")
+    assert bz2.decompress(z) == d.tobytes()
+
+
 @pytest.mark.parametrize("level", [9, 5])
 def test_compress_empty_blocks_without_cuts(bz, level):
     # no block needs cutting at these levels, and empty blocks sit at the

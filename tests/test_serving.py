@@ -227,3 +227,32 @@ def test_gpu_serving_alone_equals_in_mix():
         if i % 5 == 0:
             assert z == cref.compress(p, native.uniform_offsets(p.size, 900000), level=9, threads=16)
         assert bz2.decompress(z) == p.tobytes()
+
+
+@pytest.mark.gpu
+def test_gpu_serving_device_tensors_wait_for_their_producer():
+    """Device-tensor requests submitted right after the kernels that write
+    them (queued behind a long one, no host wait): each stream equals the
+    oracle's stream of the bytes those kernels produce."""
+    import torch
+    from paper_1109_2348_amd import native
+    assert torch.cuda.is_available()
+    payloads = [W.source_blocks(k, [n], 41)[0] for k, n in (("text", 700_000), ("uniform", 250_001),
+                                                              ("sparse", 1_300_000))]
+    want = [((p.astype(np.int32) * 3 + 7) % 256).astype(np.uint8) for p in payloads]
+    srcs = [torch.from_numpy(p).cuda() for p in payloads]
+    big = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    print(f"[case] serving device tensors: {[p.size for p in payloads]}", flush=True)
+    backend = S.GpuBackend()
+    with S.Server(backend, hbm_budget=8 << 30, max_pass=8 << 20, workers=2, level=9) as srv:
+        futs = []
+        for s in srcs:
+            for _ in range(4):
+                big = torch.mm(big, big).clamp_(-1, 1)  # a long kernel ahead of the producer
+            y = ((s.to(torch.int32) * 3 + 7) % 256).to(torch.uint8)
+            futs.append(srv.submit(y))
+        outs = [bytes(f.result(120)) for f in futs]
+    for i, (w, z) in enumerate(zip(want, outs)):
+        assert z == cref.compress(w, native.uniform_offsets(w.size, 900000), level=9, threads=16), \
+            f"request {i}: stream differs from the oracle's stream of the produced bytes"
