@@ -1533,9 +1533,6 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     r.L = cv.take<uint8_t>(lsum + 64);
     r.T = cv.take<uint8_t>(lsum + 64);
     r.FL = cv.take<uint32_t>(lsum + 16);
-    // symbols (uint16) in the first half of the map's range, their list
-    // indices in the third quarter, until the map is built
-    r.mtfq = base ? (uint8_t*)r.FL + 2 * lsum : nullptr;
     r.n_rows = cv.take<uint32_t>(nb);
     r.orig = cv.take<uint32_t>(nb);
     r.crc_want = cv.take<uint32_t>(nb);

@@ -208,17 +208,26 @@ constexpr int DEC_MAXLEN = 20;
 constexpr uint32_t OBUF = 4096;    // output bytes staged per inverse-MTF chunk
 constexpr uint32_t MTF_CH = 4096;  // symbols per inverse-MTF chunk
 
+// Until a block's last-to-first map is built, its range of the map (4 bytes
+// per row of its capacity) holds its symbols (uint16, from the start) and
+// their starting-list indices (bytes, from 2 * cap on): each block's scratch
+// stays inside its own range.
+__device__ __forceinline__ uint16_t* blk_syms(uint32_t* FL, const DecBlk& B) { return (uint16_t*)(FL + B.l_off); }
+__device__ __forceinline__ uint8_t* blk_q(uint32_t* FL, const DecBlk& B) {
+  return (uint8_t*)(FL + B.l_off) + 2 * (size_t)B.cap;
+}
+
 // One wave per block: header, symbol map, selectors, code tables, then
 // every Huffman code up to end-of-block (first-level table, then the
 // canonical limits).  Writes the block's symbols (RUNA/RUNB digits and
-// move-to-front positions + 1, uint16, in the block's range of `syms`),
+// move-to-front positions + 1, uint16, at the start of the block's map range),
 // their count, the move-to-front list it starts from (the in-use bytes,
 // ascending), origPtr and the stored CRC.  The move-to-front and run
 // decoding run afterwards, in parallel over chunks.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restrict__ in, uint64_t n_in,
                                                         const DecBlk* __restrict__ blks,
                                                         const uint32_t* __restrict__ order,
-                                                        uint16_t* __restrict__ syms, uint32_t* __restrict__ n_syms,
+                                                        uint32_t* __restrict__ FL, uint32_t* __restrict__ n_syms,
                                                         uint8_t* __restrict__ mtf0,
                                                         uint32_t* __restrict__ out_orig,
                                                         uint32_t* __restrict__ out_crc, uint32_t* __restrict__ err) {
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   __shared__ uint32_t srun[DEC_MAXLEN + 2];
   const uint32_t b = order[blockIdx.x];  // the longest blocks first
   const DecBlk B = blks[b];
-  uint16_t* Sb = syms + (size_t)B.l_off;
+  uint16_t* Sb = blk_syms(FL, B);
   const uint32_t ln = lane();
   BitIn r{in, n_in};
   r.start(B.start);
@@ -470,19 +479,19 @@ __device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, 
 }
 
 __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, const uint16_t* __restrict__ syms, uint8_t* __restrict__ Q,
-                               const uint32_t* __restrict__ n_syms, uint8_t* __restrict__ T,
+                               uint32_t nb, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
+                               uint8_t* __restrict__ T,
                                uint32_t* __restrict__ cs, uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                uint32_t* __restrict__ err) {
   const MtfChunk k = mtf_chunk(ch0, nb, j);
   const uint32_t n = n_syms[k.b];
   if ((uint64_t)k.c * MTF_CH >= n) return;
   const DecBlk B = blks[k.b];
-  const uint16_t* S = syms + (size_t)B.l_off;
+  const uint16_t* S = blk_syms(FL, B);
   const uint32_t ln = lane();
   const uint32_t s = item_start(S, n, k.c * MTF_CH, err);
   const uint32_t e = item_start(S, n, (uint32_t)min((uint64_t)(k.c + 1) * MTF_CH, (uint64_t)n), err);
-  uint8_t* Qb = Q + B.l_off;
+  uint8_t* Qb = blk_q(FL, B);
   uint32_t stk = (4u * ln) | ((4u * ln + 1u) << 8) | ((4u * ln + 2u) << 16) | ((4u * ln + 3u) << 24);
   uint64_t out = 0, run = 0;
   uint32_t rk = 0;
@@ -530,13 +539,13 @@ __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 // and the chunks' starting lists in the next as many.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_perm(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
-                                                           uint64_t ch_total, const uint16_t* __restrict__ syms,
-                                                           uint8_t* __restrict__ Q, const uint32_t* __restrict__ n_syms,
+                                                           uint64_t ch_total, uint32_t* __restrict__ FL,
+                                                           const uint32_t* __restrict__ n_syms,
                                                            uint8_t* __restrict__ T, uint32_t* __restrict__ cs,
                                                            uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                                            uint32_t* __restrict__ err) {
   for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x)
-    mtf_perm_chunk(j, blks, ch0, nb, syms, Q, n_syms, T, cs, ce, clen, err);
+    mtf_perm_chunk(j, blks, ch0, nb, FL, n_syms, T, cs, ce, clen, err);
 }
 // Per block (one wave): each chunk's starting list and output offset, by
 // composing the chunk permutations in order from the block's first list;
@@ -594,8 +603,8 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restr
 // offset (a scan of the counts), and writes the bytes (literals one per
 // lane, runs by their last digit's lane, long runs by the whole wave).
 __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, const uint16_t* __restrict__ syms, const uint8_t* __restrict__ Q,
-                               const uint32_t* __restrict__ n_syms, const uint8_t* __restrict__ T,
+                               uint32_t nb, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
+                               const uint8_t* __restrict__ T,
                                const uint32_t* __restrict__ cs, const uint32_t* __restrict__ ce,
                                const uint32_t* __restrict__ coff, const uint32_t* __restrict__ n_rows,
                                uint8_t* __restrict__ L, uint8_t* lst) {
@@ -603,8 +612,8 @@ __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
   const uint32_t n = n_syms[k.b], rows = n_rows[k.b];
   if ((uint64_t)k.c * MTF_CH >= n || rows == 0) return;  // past the symbols, or a bad block
   const DecBlk B = blks[k.b];
-  const uint16_t* S = syms + (size_t)B.l_off;
-  const uint8_t* Qb = Q + B.l_off;
+  const uint16_t* S = blk_syms(FL, B);
+  const uint8_t* Qb = blk_q(FL, B);
   const uint32_t ln = lane(), slots = B.cap / MTF_CH + 1;
   ((uint32_t*)lst)[ln] = ((const uint32_t*)(T + B.l_off + (size_t)(slots + k.c) * 256))[ln];
   __syncthreads();
@@ -667,8 +676,7 @@ __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
-                                                           uint64_t ch_total, const uint16_t* __restrict__ syms,
-                                                           const uint8_t* __restrict__ Q,
+                                                           uint64_t ch_total, uint32_t* __restrict__ FL,
                                                            const uint32_t* __restrict__ n_syms,
                                                            const uint8_t* __restrict__ T,
                                                            const uint32_t* __restrict__ cs,
@@ -678,7 +686,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restr
                                                            uint8_t* __restrict__ L) {
   __shared__ __align__(4) uint8_t lst[256];
   for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x) {
-    mtf_emit_chunk(j, blks, ch0, nb, syms, Q, n_syms, T, cs, ce, coff, n_rows, L, lst);
+    mtf_emit_chunk(j, blks, ch0, nb, FL, n_syms, T, cs, ce, coff, n_rows, L, lst);
     __syncthreads();
   }
 }
@@ -1035,21 +1043,20 @@ uint32_t dec_mtf_chunks(uint32_t cap) { return cap / MTF_CH + 1; }
 
 hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t nb = d.nb;
-  uint16_t* syms = (uint16_t*)d.FL;  // the map's range is free until the map is built
   {
     ProfScope ps("dec_block", st, 0.0);
-    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, syms, d.n_syms,
+    hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, d.FL, d.n_syms,
                        d.mtf0, d.orig, d.crc_want, d.err);
   }
   const uint32_t gc = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(d.ch_total, 1), 1u << 16);
   {
     ProfScope ps("dec_mtf", st, 0.0);
-    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, syms,
-                       d.mtfq, d.n_syms, d.T, d.cs, d.ce, d.clen, d.err);
+    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, d.FL,
+                       d.n_syms, d.T, d.cs, d.ce, d.clen, d.err);
     hipLaunchKernelGGL(k_dec_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, d.n_syms, d.mtf0, d.T,
                        d.clen, d.coff, d.orig, d.n_rows, d.err);
-    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, syms,
-                       d.mtfq, d.n_syms, d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
+    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, d.FL,
+                       d.n_syms, d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
   }
   {
     ProfScope ps("dec_fl", st, 0.0);

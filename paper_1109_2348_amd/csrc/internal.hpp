@@ -288,7 +288,6 @@ struct DecRun {
   uint32_t *n_rows, *orig, *crc_want, *err, *FL;
   uint32_t* n_syms;       // per block: Huffman symbols before end-of-block
   uint8_t* mtf0;          // per block: the 256-byte list move-to-front decoding starts from
-  uint8_t* mtfq;          // per symbol (at the block's row offset): its byte's index in its chunk's starting list
   const uint64_t* ch0;    // nb + 1 move-to-front chunk slot offsets
   uint64_t ch_total;
   uint32_t *cs, *ce, *clen, *coff;  // per chunk slot: item range, output length and offset
