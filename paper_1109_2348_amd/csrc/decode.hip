@@ -922,31 +922,110 @@ __global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks
 
 // Per block, the segments in order: each one's incoming state (and last
 // byte) and output offset within the block; the block's output length.
-__global__ void k_rle_chain(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0, uint32_t nb,
-                            const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ period,
-                            const uint8_t* __restrict__ T, const uint64_t* __restrict__ summ,
-                            uint32_t* __restrict__ seg_in, uint32_t* __restrict__ seg_off,
-                            uint32_t* __restrict__ out_len) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+// A segment's effect on the decoding state (0..4): the state after it, for
+// each state before it, 3 bits per state.
+constexpr uint32_t MAP_ID = 0u | (1u << 3) | (2u << 6) | (3u << 9) | (4u << 12);
+__device__ __forceinline__ uint32_t map_at(uint32_t m, uint32_t st) { return (m >> (3 * st)) & 7u; }
+// first f, then g
+__device__ __forceinline__ uint32_t map_then(uint32_t f, uint32_t g) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t st = 0; st < 5; st++) r |= map_at(g, map_at(f, st)) << (3 * st);
+  return r;
+}
+
+// Per block (one workgroup): each segment's incoming state and last byte and
+// its output offset.  A segment's summary gives, per incoming state, the
+// state it leaves and its last byte; with the next segment's first byte that
+// makes a map of states, so the incoming states are an ordered scan of the
+// maps (composition), and the offsets a scan of the lengths those states
+// pick.  KS segments per thread, NT * KS a step.
+constexpr uint32_t KS = 4;
+constexpr uint32_t NWV = NT / BZG_WAVE;
+__global__ __launch_bounds__(NT) void k_rle_chain(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
+                                                  uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                  const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                                  const uint64_t* __restrict__ summ, uint32_t* __restrict__ seg_in,
+                                                  uint32_t* __restrict__ seg_off, uint32_t* __restrict__ out_len) {
+  __shared__ uint32_t wmap[NWV], wsum[NWV + 1], lastlo[NT];
+  const uint32_t b = blockIdx.x, tid = threadIdx.x, w = tid / BZG_WAVE, ln = lane();
   const uint32_t n = period[b] ? n_rows[b] : 0u;
   const uint32_t ns = (n + RLE_SEG - 1) / RLE_SEG;
   const uint8_t* Tb = T + blks[b].l_off;
   const uint64_t base = g0[b];
-  uint32_t st = 0, last = 0, off = 0;
-  for (uint32_t g = 0; g < ns; g++) {
-    seg_in[base + g] = st | (last << 8);
-    seg_off[base + g] = off;
-    const uint64_t v = summ[(base + g) * 5 + st];
-    off += (uint32_t)v;
-    const uint32_t so = (uint32_t)(v >> 32) & 255u, lo = (uint32_t)(v >> 40) & 255u;
-    if (g + 1 < ns) {
-      const uint32_t x0 = Tb[(g + 1) * RLE_SEG];
-      st = (so >= 1 && so <= 3) ? (lo == x0 ? so : 0u) : so;
-      last = lo;
+  uint32_t st0 = 0, last0 = 0, off0 = 0;  // entering the step (workgroup-uniform)
+  for (uint32_t t0 = 0; t0 < ns; t0 += NT * KS) {
+    const uint32_t gs = t0 + tid * KS;
+    uint64_t v[KS][5];
+    uint32_t fm[KS];
+#pragma unroll
+    for (uint32_t k = 0; k < KS; k++) {
+      const uint32_t g = min(gs + k, ns - 1u);
+#pragma unroll
+      for (uint32_t q = 0; q < 5; q++) v[k][q] = summ[(base + g) * 5 + q];
     }
+    uint32_t F = MAP_ID;
+#pragma unroll
+    for (uint32_t k = 0; k < KS; k++) {
+      const uint32_t g = gs + k;
+      const uint32_t x0 = g + 1 < ns ? Tb[(g + 1) * RLE_SEG] : 0u;
+      uint32_t m = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < 5; q++) {
+        const uint32_t so = (uint32_t)(v[k][q] >> 32) & 255u, lo = (uint32_t)(v[k][q] >> 40) & 255u;
+        m |= ((so >= 1 && so <= 3) ? (lo == x0 ? so : 0u) : so) << (3 * q);
+      }
+      fm[k] = g < ns ? m : MAP_ID;
+      F = map_then(F, fm[k]);
+    }
+    // ordered scan of the threads' maps: in the wave, then over the waves
+    const uint32_t inc = wave_incl_scan(F, MAP_ID, [](uint32_t cur, uint32_t lower) { return map_then(lower, cur); });
+    if (ln == BZG_WAVE - 1) wmap[w] = inc;
+    __syncthreads();
+    uint32_t pw = MAP_ID;
+    for (uint32_t q = 0; q < w; q++) pw = map_then(pw, wmap[q]);
+    const uint32_t lower = (uint32_t)__shfl_up((int)inc, 1, BZG_WAVE);
+    const uint32_t ex = map_then(pw, ln == 0 ? MAP_ID : lower);  // the step's threads before this one
+    uint32_t all = MAP_ID;
+    for (uint32_t q = 0; q < NWV; q++) all = map_then(all, wmap[q]);
+    // this thread's segments: states, lengths, last bytes
+    uint32_t st = map_at(ex, st0), len = 0, my_last = 0;
+    uint32_t sts[KS], lens[KS], los[KS];
+#pragma unroll
+    for (uint32_t k = 0; k < KS; k++) {
+      const uint64_t vv = v[k][min(st, 4u)];
+      sts[k] = st;
+      lens[k] = gs + k < ns ? (uint32_t)vv : 0u;
+      los[k] = (uint32_t)(vv >> 40) & 255u;
+      len += lens[k];
+      if (gs + k < ns) my_last = los[k];
+      st = map_at(fm[k], st);
+    }
+    lastlo[tid] = my_last;
+    uint32_t tot;
+    const uint32_t off = block_excl_sum<uint32_t, NT>(len, wsum, &tot);  // (its barriers also order lastlo)
+    uint32_t last_in = tid == 0 ? last0 : lastlo[tid - 1];
+    uint32_t o = off0 + off;
+#pragma unroll
+    for (uint32_t k = 0; k < KS; k++) {
+      const uint32_t g = gs + k;
+      if (g < ns) {
+        seg_in[base + g] = sts[k] | (last_in << 8);
+        seg_off[base + g] = o;
+      }
+      o += lens[k];
+      last_in = los[k];
+    }
+    // into the next step
+    const uint32_t last_t = min(ns - t0, NT * KS) - 1u;  // the step's last segment, relative
+    const uint32_t st_next = map_at(all, st0);
+    const uint32_t lo_next = lastlo[last_t / KS];
+    __syncthreads();
+    st0 = st_next;
+    last0 = lo_next;
+    off0 += tot;
   }
-  out_len[b] = off;
+  if (tid == 0) out_len[b] = off0;
 }
 
 // Block output offsets (one workgroup) and the total; when the total does
@@ -1081,7 +1160,7 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
     ProfScope ps("dec_rle", st, 0.0);
     hipLaunchKernelGGL(k_rle_summ, dim3(std::max(gr, 1u)), dim3(NT), 0, st, d.blks, d.rle0, nb,
                        d.rle_total, d.n_rows, d.period, d.T, d.summ);
-    hipLaunchKernelGGL(k_rle_chain, dim3((nb + 63) / 64), dim3(64), 0, st, d.blks, d.rle0, nb,
+    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb,
                        d.n_rows, d.period, d.T, d.summ, d.seg_in, d.seg_off, d.out_len);
     hipLaunchKernelGGL(k_rle_offsets, dim3(1), dim3(1024), 0, st, d.out_len, nb, d.out_cap, d.out_off, d.out_bytes,
                        d.skip, d.err);
