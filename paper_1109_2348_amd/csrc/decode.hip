@@ -208,6 +208,19 @@ constexpr int DEC_MAXLEN = 20;
 constexpr uint32_t OBUF = 4096;    // output bytes staged per inverse-MTF chunk
 constexpr uint32_t MTF_CH = 4096;  // symbols per inverse-MTF chunk
 
+// Huffman decoding a step at a time: a step decodes up to one group's
+// remaining codes inside a span of SPAN bits.  Lane l evaluates bit
+// positions PSTEP*l .. PSTEP*l + PSTEP-1 of the span as if a code started
+// there; the map position -> next code start is composed with itself
+// (pointer doubling), and lane l follows it l times from the step's start.
+constexpr uint32_t PSTEP = 8;
+constexpr uint32_t SPAN = PSTEP * BZG_WAVE;        // 512 bit positions
+constexpr uint32_t JSENT = SPAN + DEC_MAXLEN;      // beyond the span (a fixed point of the map)
+constexpr uint32_t JTAB = JSENT + 4;               // map entries, a multiple of 8
+constexpr uint32_t LUT_BAD = 0x8000u | (1u << 9) | 511u;  // no code here: length 1, symbol 0x81FF
+constexpr uint32_t SYM_BAD = LUT_BAD & 0x81FFu;
+constexpr uint32_t NLONG = DEC_MAXLEN - DEC_LUT_BITS;     // code lengths past the first-level table
+
 // Until a block's last-to-first map is built, its range of the map (4 bytes
 // per row of its capacity) holds its symbols (uint16, from the start) and
 // their starting-list indices (bytes, from 2 * cap on): each block's scratch
@@ -238,6 +251,11 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   __shared__ uint8_t lens[MAXG][MAXA];
   __shared__ __align__(4) uint8_t unseq[256];
   __shared__ uint32_t srun[DEC_MAXLEN + 2];
+  __shared__ int32_t lim20[MAXG][32];            // left-aligned limits, per length
+  __shared__ int32_t sbase[MAXG][DEC_MAXLEN + 2];  // start - first code, per length
+  __shared__ uint32_t ring[2 * BZG_WAVE];           // two 64-dword windows of the stream
+  __shared__ __align__(16) uint16_t jt[2][JTAB];   // next-code-start maps (ping-pong)
+  __shared__ __align__(16) uint16_t jsym[SPAN];    // symbol of the code at each position
   const uint32_t b = order[blockIdx.x];  // the longest blocks first
   const DecBlk B = blks[b];
   uint16_t* Sb = blk_syms(FL, B);
@@ -317,6 +335,10 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
           first[t][l] = code;
           start[t][l] = st;
           limit[t][l] = (int32_t)(code + c) - 1;
+          // a 20-bit prefix v holds a code of length <= l iff v <= lim20[l];
+          // these rise with l (any counts), so the length is found by counting
+          lim20[t][l] = (int32_t)((code + c) << (DEC_MAXLEN - l)) - 1;
+          sbase[t][l] = (int32_t)st - (int32_t)code;
           code = (code + c) << 1;
           st += c;
         }
@@ -342,7 +364,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
           const int32_t v = (int32_t)(x >> (DEC_LUT_BITS - l));
           if (v <= limit[t][l]) {
             const uint32_t idx = start[t][l] + (uint32_t)v - first[t][l];
-            e = idx < (uint32_t)a ? (uint16_t)(perm[t][idx] | (l << 9)) : 0;
+            e = (uint16_t)(idx < (uint32_t)a ? (perm[t][idx] | (l << 9)) : LUT_BAD);
             break;
           }
         }
@@ -351,72 +373,137 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
     }
   }
   __syncthreads();
-  // symbols, a group of GROUP at a time with its table fixed: lane k holds
-  // the group's k-th symbol, and the
-  // group's symbols are stored together (coalesced).  A block has at most
-  // as many symbols as bytes.
+  // symbols.  Each group of GROUP codes uses the table its selector names;
+  // a step decodes the group's remaining codes that start inside the next
+  // SPAN bits (all of them unless the codes average over SPAN/GROUP bits).
+  // Lane k of a step holds its k-th code; the step's symbols are stored
+  // together (coalesced).  A block has at most as many symbols as bytes.
   const uint32_t cap = B.cap;
-  uint32_t cnt = 0, gsel = 0;
+  uint32_t cnt = 0, gsel = 0, rem = 0, t = 0;
   const uint32_t eob = (uint32_t)a - 1;
+  uint64_t bit = B.start + r.used();  // the first code
   BitIn rs{in, n_in};
   rs.start(sel_bit);
   uint32_t lst = 0x543210u;  // table list, 4 bits per entry, front in the low bits
   bool ended = false;
+  int32_t lim[NLONG];
+  for (uint32_t i = SPAN + ln; i < JTAB; i += BZG_WAVE) {
+    jt[0][i] = (uint16_t)JSENT;
+    jt[1][i] = (uint16_t)JSENT;
+  }
+  // the stream as 64-dword windows: ring slot (w & 1) holds window w; the
+  // ring holds the windows of `bit` and the next, pb the one after
+  uint32_t wr = (uint32_t)(bit >> 11);
+  uint32_t pb[4];
+  auto win_load = [&](uint64_t w) {
+    const uint64_t q = 4 * (BZG_WAVE * w + ln);
+#pragma unroll
+    for (int i = 0; i < 4; i++) pb[i] = in[min(q + i, n_in - 1)];
+  };
+  auto win_put = [&](uint64_t w) {
+    ring[BZG_WAVE * (uint32_t)(w & 1) + ln] = (pb[0] << 24) | (pb[1] << 16) | (pb[2] << 8) | pb[3];
+  };
+  win_load(wr);
+  win_put(wr);
+  win_load(wr + 1ull);
+  win_put(wr + 1ull);
+  win_load(wr + 2ull);
   bad = uni(bad);
+  __syncthreads();
   while (!bad && !ended) {
-    if (gsel >= nsel_kept) {
-      bad = 1;
-      break;
-    }
-    // j ones and a zero (j < G, checked above): table at list position j
-    rs.refill();
-    const uint32_t j = (uint32_t)__builtin_clz(~rs.peek(32) | 1u);
-    rs.skip((int)j + 1);
-    const uint32_t t = (lst >> (4 * j)) & 15u;
-    const uint32_t below = lst & ((1u << (4 * j)) - 1u);
-    lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
-    gsel++;
-    uint32_t sv = 0, k = 0;
-    for (; k < (uint32_t)GROUP; k++) {
-      r.refill();
-      const uint32_t e = uni(lut[t][r.peek(DEC_LUT_BITS)]);
-      uint32_t sym;
-      if (e >> 9) {
-        sym = e & 511u;
-        r.skip((int)(e >> 9));
-      } else {
-        int zn = DEC_LUT_BITS + 1;
-        while (zn <= DEC_MAXLEN && (int32_t)r.peek(zn) > (int32_t)uni(limit[t][zn])) zn++;
-        if (zn > DEC_MAXLEN) {
-          bad = 1;
-          break;
-        }
-        const uint32_t idx = uni(start[t][zn]) + r.peek(zn) - uni(first[t][zn]);
-        if (idx >= (uint32_t)a) {
-          bad = 1;
-          break;
-        }
-        sym = uni(perm[t][idx]);
-        r.skip(zn);
-      }
-      if (sym == eob) {
-        ended = true;
+    if (rem == 0) {
+      if (gsel >= nsel_kept) {
+        bad = 1;
         break;
       }
-      // (symbols are < a: a literal's list position, sym - 1, is < nin)
-      sv = ln == k ? sym : sv;
+      // j ones and a zero (j < G, checked above): table at list position j
+      rs.refill();
+      const uint32_t j = (uint32_t)__builtin_clz(~rs.peek(32) | 1u);
+      rs.skip((int)j + 1);
+      t = (lst >> (4 * j)) & 15u;
+      const uint32_t below = lst & ((1u << (4 * j)) - 1u);
+      lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
+      gsel++;
+      rem = GROUP;
+      const int32_t lv = lim20[t][ln & 31u];
+#pragma unroll
+      for (uint32_t l = 0; l < NLONG; l++) lim[l] = __builtin_amdgcn_readlane(lv, (int)(DEC_LUT_BITS + 1 + l));
     }
-    if (bad) break;
-    if (cnt + k > cap) {
+    // this lane's 32 bits from span position PSTEP*ln
+    const uint64_t q = bit + PSTEP * ln;
+    const uint32_t dq = (uint32_t)(q >> 5);
+    const uint64_t hl = ((uint64_t)ring[dq & (2 * BZG_WAVE - 1)] << 32) | ring[(dq + 1) & (2 * BZG_WAVE - 1)];
+    const uint32_t w = (uint32_t)(hl >> (32 - ((uint32_t)q & 31u)));
+    uint32_t jv[PSTEP], sv[PSTEP];
+#pragma unroll
+    for (uint32_t i = 0; i < PSTEP; i++) {
+      const uint32_t v = (w >> (32 - DEC_MAXLEN - i)) & ((1u << DEC_MAXLEN) - 1u);
+      uint32_t e = lut[t][v >> (DEC_MAXLEN - DEC_LUT_BITS)];
+      if (e == 0) {
+        // longer than the first-level table: the first length whose limit admits v
+        uint32_t zn = DEC_LUT_BITS + 1;
+#pragma unroll
+        for (uint32_t l = 0; l + 1 < NLONG; l++) zn += (int32_t)v > lim[l] ? 1u : 0u;
+        const uint32_t idx = (uint32_t)(sbase[t][zn] + (int32_t)(v >> (DEC_MAXLEN - zn)));
+        e = (int32_t)v <= lim[NLONG - 1] && idx < (uint32_t)a ? (perm[t][idx] | (zn << 9)) : LUT_BAD;
+      }
+      jv[i] = PSTEP * ln + i + ((e >> 9) & 31u);
+      sv[i] = e & 0x81FFu;
+    }
+    uint4* jrow = (uint4*)&jt[0][PSTEP * ln];
+    *jrow = make_uint4(jv[0] | (jv[1] << 16), jv[2] | (jv[3] << 16), jv[4] | (jv[5] << 16), jv[6] | (jv[7] << 16));
+    *(uint4*)&jsym[PSTEP * ln] =
+        make_uint4(sv[0] | (sv[1] << 16), sv[2] | (sv[3] << 16), sv[4] | (sv[5] << 16), sv[6] | (sv[7] << 16));
+    __syncthreads();
+    // doubling: table k maps a position to the start 2^k codes on; lane ln
+    // takes table k when bit k of ln is set, landing on its code's start
+    uint32_t x = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 6; k++) {
+      const uint16_t* A = jt[k & 1];
+      const uint32_t xa = A[x];
+      if (k < 5) {
+#pragma unroll
+        for (uint32_t i = 0; i < PSTEP; i++) jv[i] = A[jv[i]];
+      }
+      x = (ln >> k) & 1u ? xa : x;
+      if (k < 5) {
+        *(uint4*)&jt[(k + 1) & 1][PSTEP * ln] =
+            make_uint4(jv[0] | (jv[1] << 16), jv[2] | (jv[3] << 16), jv[4] | (jv[5] << 16), jv[6] | (jv[7] << 16));
+        __syncthreads();
+      }
+    }
+    // codes that start inside the span are exact (the map saturates past it)
+    const bool ok = ln < rem && x < SPAN;
+    const uint32_t sym = ok ? jsym[x] : 0u;
+    const uint64_t vm = __ballot(ok);
+    const uint64_t em = __ballot(ok && sym == eob);
+    const uint64_t im = __ballot(ok && sym == SYM_BAD);
+    uint32_t m = (uint32_t)__popcll(vm);  // a prefix of the lanes
+    if (em) {
+      m = (uint32_t)__builtin_ctzll(em);
+      ended = true;
+    }
+    const uint32_t nx = (uint32_t)__builtin_amdgcn_readlane((int)x, (int)(ended ? m + 1 : m));
+    if ((im & ((1ull << m) - 1ull)) | (cnt + m > cap)) {
       bad = 1;
       break;
     }
-    if (ln < k) Sb[cnt + ln] = (uint16_t)sv;
-    cnt += k;
+    // (symbols are < a: a literal's list position, sym - 1, is < nin)
+    if (ln < m) Sb[cnt + ln] = (uint16_t)sym;
+    cnt += m;
+    rem -= m;
+    bit += nx;
+    if ((uint32_t)(bit >> 11) != wr) {  // at most one window per step
+      wr++;
+      win_put(wr + 1ull);
+      win_load(wr + 2ull);
+    }
+    __syncthreads();
   }
   // the block's bits must end exactly where the next marker starts
   bad |= !ended | (cnt == 0);  // a block holds at least one byte
-  bad |= (B.start + r.used() != B.end);
+  bad |= (bit != B.end);
   if (ln == 0) {
     n_syms[b] = bad ? 0u : cnt;
     out_orig[b] = orig;
