@@ -211,14 +211,18 @@ constexpr uint32_t MTF_CH = 4096;  // symbols per inverse-MTF chunk
 // Huffman decoding a step at a time: a step decodes up to one group's
 // remaining codes inside a span of SPAN bits.  Lane l evaluates bit
 // positions PSTEP*l .. PSTEP*l + PSTEP-1 of the span as if a code started
-// there; the map position -> next code start is composed with itself
+// there.  The map position -> next code start is composed with itself
 // (pointer doubling), and lane l follows it l times from the step's start.
+// A map entry holds 4 * the target position (high half) and the symbol of
+// the code it passed last (low half), which composition carries along: lane
+// l ends with code l's start and code l-1's symbol.
 constexpr uint32_t PSTEP = 8;
 constexpr uint32_t SPAN = PSTEP * BZG_WAVE;        // 512 bit positions
 constexpr uint32_t JSENT = SPAN + DEC_MAXLEN;      // beyond the span (a fixed point of the map)
 constexpr uint32_t JTAB = JSENT + 4;               // map entries, a multiple of 8
 constexpr uint32_t LUT_BAD = 0x8000u | (1u << 9) | 511u;  // no code here: length 1, symbol 0x81FF
 constexpr uint32_t SYM_BAD = LUT_BAD & 0x81FFu;
+constexpr uint32_t SYM_BEYOND = 0x7FFFu;           // the code passed started past the span
 constexpr uint32_t NLONG = DEC_MAXLEN - DEC_LUT_BITS;     // code lengths past the first-level table
 
 // Until a block's last-to-first map is built, its range of the map (4 bytes
@@ -254,8 +258,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   __shared__ int32_t lim20[MAXG][32];            // left-aligned limits, per length
   __shared__ int32_t sbase[MAXG][DEC_MAXLEN + 2];  // start - first code, per length
   __shared__ uint32_t ring[2 * BZG_WAVE];           // two 64-dword windows of the stream
-  __shared__ __align__(16) uint16_t jt[2][JTAB];   // next-code-start maps (ping-pong)
-  __shared__ __align__(16) uint16_t jsym[SPAN];    // symbol of the code at each position
+  __shared__ __align__(16) uint32_t jt[2][JTAB];   // next-code-start maps (ping-pong)
   const uint32_t b = order[blockIdx.x];  // the longest blocks first
   const DecBlk B = blks[b];
   uint16_t* Sb = blk_syms(FL, B);
@@ -376,8 +379,10 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   // symbols.  Each group of GROUP codes uses the table its selector names;
   // a step decodes the group's remaining codes that start inside the next
   // SPAN bits (all of them unless the codes average over SPAN/GROUP bits).
-  // Lane k of a step holds its k-th code; the step's symbols are stored
+  // Lane k+1 of a step holds its k-th code; the step's symbols are stored
   // together (coalesced).  A block has at most as many symbols as bytes.
+  // The workgroup is one wave, whose LDS accesses take effect in program
+  // order: the step's phases need compiler fences only.
   const uint32_t cap = B.cap;
   uint32_t cnt = 0, gsel = 0, rem = 0, t = 0;
   const uint32_t eob = (uint32_t)a - 1;
@@ -386,10 +391,10 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   rs.start(sel_bit);
   uint32_t lst = 0x543210u;  // table list, 4 bits per entry, front in the low bits
   bool ended = false;
-  int32_t lim[NLONG];
+  int32_t lv = 0;  // lane l: left-aligned limit of length l of the group's table
   for (uint32_t i = SPAN + ln; i < JTAB; i += BZG_WAVE) {
-    jt[0][i] = (uint16_t)JSENT;
-    jt[1][i] = (uint16_t)JSENT;
+    jt[0][i] = (4 * JSENT << 16) | SYM_BEYOND;
+    jt[1][i] = (4 * JSENT << 16) | SYM_BEYOND;
   }
   // the stream as 64-dword windows: ring slot (w & 1) holds window w; the
   // ring holds the windows of `bit` and the next, pb the one after
@@ -402,6 +407,14 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
   };
   auto win_put = [&](uint64_t w) {
     ring[BZG_WAVE * (uint32_t)(w & 1) + ln] = (pb[0] << 24) | (pb[1] << 16) | (pb[2] << 8) | pb[3];
+  };
+  auto put_row = [&](uint32_t* row, const uint32_t (&v)[PSTEP]) {
+    ((uint4*)row)[0] = make_uint4(v[0], v[1], v[2], v[3]);
+    ((uint4*)row)[1] = make_uint4(v[4], v[5], v[6], v[7]);
+  };
+  auto lds_order = [] {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   };
   win_load(wr);
   win_put(wr);
@@ -425,72 +438,92 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
       lst = (lst & ~((1u << (4 * j + 4)) - 1u)) | (below << 4) | t;
       gsel++;
       rem = GROUP;
-      const int32_t lv = lim20[t][ln & 31u];
-#pragma unroll
-      for (uint32_t l = 0; l < NLONG; l++) lim[l] = __builtin_amdgcn_readlane(lv, (int)(DEC_LUT_BITS + 1 + l));
+      lv = lim20[t][ln & 31u];
     }
     // this lane's 32 bits from span position PSTEP*ln
     const uint64_t q = bit + PSTEP * ln;
     const uint32_t dq = (uint32_t)(q >> 5);
     const uint64_t hl = ((uint64_t)ring[dq & (2 * BZG_WAVE - 1)] << 32) | ring[(dq + 1) & (2 * BZG_WAVE - 1)];
     const uint32_t w = (uint32_t)(hl >> (32 - ((uint32_t)q & 31u)));
-    uint32_t jv[PSTEP], sv[PSTEP];
+    uint32_t jv[PSTEP];
+#pragma unroll
+    for (uint32_t i = 0; i < PSTEP; i++) jv[i] = lut[t][(w >> (32 - DEC_LUT_BITS - i)) & ((1u << DEC_LUT_BITS) - 1u)];
+    uint32_t slow = 0;
 #pragma unroll
     for (uint32_t i = 0; i < PSTEP; i++) {
-      const uint32_t v = (w >> (32 - DEC_MAXLEN - i)) & ((1u << DEC_MAXLEN) - 1u);
-      uint32_t e = lut[t][v >> (DEC_MAXLEN - DEC_LUT_BITS)];
-      if (e == 0) {
-        // longer than the first-level table: the first length whose limit admits v
+      slow |= (jv[i] == 0 ? 1u : 0u) << i;
+      jv[i] = ((4 * (PSTEP * ln + i + ((jv[i] >> 9) & 31u))) << 16) | (jv[i] & 0x81FFu);
+    }
+    uint32_t* jrow = &jt[0][PSTEP * ln];
+    put_row(jrow, jv);
+    if (__ballot(slow != 0)) {
+      // codes longer than the first-level table: the first length whose
+      // limit admits the 20-bit prefix; the entries are rewritten in place
+      int32_t lim[DEC_MAXLEN - DEC_LUT_BITS];
+#pragma unroll
+      for (uint32_t l = 0; l < DEC_MAXLEN - DEC_LUT_BITS; l++)
+        lim[l] = __builtin_amdgcn_readlane(lv, (int)(DEC_LUT_BITS + 1 + l));
+      while (slow) {
+        const uint32_t i = (uint32_t)__builtin_ctz(slow);
+        slow &= slow - 1u;
+        const uint32_t v = (w >> (32 - DEC_MAXLEN - i)) & ((1u << DEC_MAXLEN) - 1u);
         uint32_t zn = DEC_LUT_BITS + 1;
 #pragma unroll
-        for (uint32_t l = 0; l + 1 < NLONG; l++) zn += (int32_t)v > lim[l] ? 1u : 0u;
+        for (uint32_t l = 0; l + 1 < DEC_MAXLEN - DEC_LUT_BITS; l++) zn += (int32_t)v > lim[l] ? 1u : 0u;
         const uint32_t idx = (uint32_t)(sbase[t][zn] + (int32_t)(v >> (DEC_MAXLEN - zn)));
-        e = (int32_t)v <= lim[NLONG - 1] && idx < (uint32_t)a ? (perm[t][idx] | (zn << 9)) : LUT_BAD;
+        const uint32_t ee = (int32_t)v <= lim[DEC_MAXLEN - DEC_LUT_BITS - 1] && idx < (uint32_t)a
+                                ? (perm[t][idx] | (zn << 9))
+                                : LUT_BAD;
+        jrow[i] = ((4 * (PSTEP * ln + i + ((ee >> 9) & 31u))) << 16) | (ee & 0x81FFu);
       }
-      jv[i] = PSTEP * ln + i + ((e >> 9) & 31u);
-      sv[i] = e & 0x81FFu;
+      const uint4 r0 = ((const uint4*)jrow)[0], r1 = ((const uint4*)jrow)[1];
+      jv[0] = r0.x;
+      jv[1] = r0.y;
+      jv[2] = r0.z;
+      jv[3] = r0.w;
+      jv[4] = r1.x;
+      jv[5] = r1.y;
+      jv[6] = r1.z;
+      jv[7] = r1.w;
     }
-    uint4* jrow = (uint4*)&jt[0][PSTEP * ln];
-    *jrow = make_uint4(jv[0] | (jv[1] << 16), jv[2] | (jv[3] << 16), jv[4] | (jv[5] << 16), jv[6] | (jv[7] << 16));
-    *(uint4*)&jsym[PSTEP * ln] =
-        make_uint4(sv[0] | (sv[1] << 16), sv[2] | (sv[3] << 16), sv[4] | (sv[5] << 16), sv[6] | (sv[7] << 16));
-    __syncthreads();
+    lds_order();
     // doubling: table k maps a position to the start 2^k codes on; lane ln
-    // takes table k when bit k of ln is set, landing on its code's start
-    uint32_t x = 0;
+    // takes table k when bit k of ln is set
+    uint32_t x = 0;  // 4 * code ln's start (high half), code ln-1's symbol
 #pragma unroll
     for (uint32_t k = 0; k < 6; k++) {
-      const uint16_t* A = jt[k & 1];
-      const uint32_t xa = A[x];
+      const char* A = (const char*)jt[k & 1];
+      const uint32_t xa = *(const uint32_t*)(A + (x >> 16));
       if (k < 5) {
 #pragma unroll
-        for (uint32_t i = 0; i < PSTEP; i++) jv[i] = A[jv[i]];
+        for (uint32_t i = 0; i < PSTEP; i++) jv[i] = *(const uint32_t*)(A + (jv[i] >> 16));
       }
       x = (ln >> k) & 1u ? xa : x;
       if (k < 5) {
-        *(uint4*)&jt[(k + 1) & 1][PSTEP * ln] =
-            make_uint4(jv[0] | (jv[1] << 16), jv[2] | (jv[3] << 16), jv[4] | (jv[5] << 16), jv[6] | (jv[7] << 16));
-        __syncthreads();
+        put_row(&jt[(k + 1) & 1][PSTEP * ln], jv);
+        lds_order();
       }
     }
     // codes that start inside the span are exact (the map saturates past it)
-    const bool ok = ln < rem && x < SPAN;
-    const uint32_t sym = ok ? jsym[x] : 0u;
+    const uint32_t sym = x & 0xFFFFu, xs = x >> 18;
+    const bool ok = ln >= 1 && ln <= rem && sym != SYM_BEYOND;
     const uint64_t vm = __ballot(ok);
     const uint64_t em = __ballot(ok && sym == eob);
     const uint64_t im = __ballot(ok && sym == SYM_BAD);
-    uint32_t m = (uint32_t)__popcll(vm);  // a prefix of the lanes
+    uint32_t m = (uint32_t)__popcll(vm);  // lanes 1 .. m
+    uint32_t nl = m;                      // the lane holding the next start
     if (em) {
-      m = (uint32_t)__builtin_ctzll(em);
+      nl = (uint32_t)__builtin_ctzll(em);
+      m = nl - 1;
       ended = true;
     }
-    const uint32_t nx = (uint32_t)__builtin_amdgcn_readlane((int)x, (int)(ended ? m + 1 : m));
-    if ((im & ((1ull << m) - 1ull)) | (cnt + m > cap)) {
+    const uint32_t nx = (uint32_t)__builtin_amdgcn_readlane((int)xs, (int)nl);
+    if ((im & ((2ull << m) - 2ull)) | (cnt + m > cap)) {
       bad = 1;
       break;
     }
     // (symbols are < a: a literal's list position, sym - 1, is < nin)
-    if (ln < m) Sb[cnt + ln] = (uint16_t)sym;
+    if (ln >= 1 && ln <= m) Sb[cnt + ln - 1] = (uint16_t)sym;
     cnt += m;
     rem -= m;
     bit += nx;
@@ -499,7 +532,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
       win_put(wr + 1ull);
       win_load(wr + 2ull);
     }
-    __syncthreads();
+    lds_order();
   }
   // the block's bits must end exactly where the next marker starts
   bad |= !ended | (cnt == 0);  // a block holds at least one byte
