@@ -23,7 +23,7 @@ constexpr uint64_t MAGIC_EOS = 0x177245385090ull;
 constexpr uint32_t FIND_BYTES = 16;                 // input bytes per thread of the marker search
 constexpr uint32_t FIND_TILE = NT * FIND_BYTES;     // per workgroup
 constexpr uint32_t DEC_LUT_BITS = 10;               // first-level decoding table
-constexpr uint32_t WALK_STRIDE = 128;               // one sampled row per this many rows
+constexpr uint32_t WALK_STRIDE = 64;                // one sampled row per this many rows
 constexpr uint32_t RLE_SEG = 64;                    // bytes per run-length decoding segment
 
 // --------------------------------------------------------- marker search
@@ -901,7 +901,7 @@ __device__ __forceinline__ uint32_t owner_of(const uint64_t* __restrict__ s0, ui
 // slot (workgroup-uniform), then each thread steps over the few blocks its
 // slot lies past.
 __device__ __forceinline__ uint32_t owner_of_wg(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
-  uint32_t b = owner_of(s0, nb, (uint64_t)blockIdx.x * blockDim.x);
+  uint32_t b = owner_of(s0, nb, j - threadIdx.x);
   while (b + 1 < nb && s0[b + 1] <= j) b++;
   return b;
 }
@@ -915,7 +915,9 @@ __global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks
                                                  const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
                                                  uint32_t* __restrict__ nxt, uint32_t* __restrict__ steps,
                                                  uint32_t* __restrict__ pos) {
-  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  // each XCD walks a contiguous range of walkers, so a block's map is read
+  // through one L2
+  const uint64_t j = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   if (j >= total) return;
   const uint32_t b = owner_of_wg(s0, nb, j);
   const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b];
@@ -933,29 +935,83 @@ __global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks
 
 // Per block: the chain of samples from origPtr gives every walker on it its
 // output position; its length is the period of the text (the whole block
-// unless the block repeats a shorter string).
-__global__ void k_dec_chain(const uint64_t* __restrict__ s0, uint32_t nb, const uint32_t* __restrict__ n_rows,
-                            const uint32_t* __restrict__ origs, const uint32_t* __restrict__ nxt,
-                            const uint32_t* __restrict__ steps, uint32_t* __restrict__ pos,
-                            uint32_t* __restrict__ period, uint32_t* __restrict__ err) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+// unless the block repeats a shorter string).  The chain is cut where it
+// returns to origPtr's sample and ranked by pointer jumping in LDS: each
+// sample's count of text bytes from itself to the cut, doubled along the
+// chain each round; a walker's position is the total minus its own count.
+// Samples off the chain (other cycles of a periodic block) never reach the
+// cut and stay unvisited.
+constexpr uint32_t CHAIN_NT = 1024;
+constexpr uint32_t CHAIN_CAP = 900000 / WALK_STRIDE + 3;  // samples of the largest block, and the cut
+constexpr uint32_t CHAIN_PER = (CHAIN_CAP + CHAIN_NT - 1) / CHAIN_NT;
+constexpr uint32_t CHAIN_BIG = 0x40000000u;  // a count past any block (two of them sum without wrapping)
+__global__ __launch_bounds__(CHAIN_NT) void k_dec_chain(const uint64_t* __restrict__ s0, uint32_t nb,
+                                                        const uint32_t* __restrict__ n_rows,
+                                                        const uint32_t* __restrict__ origs,
+                                                        const uint32_t* __restrict__ nxt,
+                                                        const uint32_t* __restrict__ steps, uint32_t* __restrict__ pos,
+                                                        uint32_t* __restrict__ period, uint32_t* __restrict__ err) {
+  __shared__ uint32_t succ[CHAIN_CAP], cnt[CHAIN_CAP];
+  const uint32_t b = blockIdx.x, tid = threadIdx.x;
   const uint32_t n = n_rows[b], orig = origs[b];
   if (n == 0) {
-    period[b] = 0;
+    if (tid == 0) period[b] = 0;
+    return;
+  }
+  const uint32_t ns = samples_of(n, orig), s_start = sample_index(orig, n, orig);
+  if (ns + 1 > CHAIN_CAP) {  // a block longer than any level allows
+    if (tid == 0) {
+      period[b] = 0;
+      atomicOr(err, ERR_STREAM);
+    }
     return;
   }
   const uint64_t base = s0[b];
-  const uint32_t ns = samples_of(n, orig), s_start = sample_index(orig, n, orig);
-  uint32_t s = s_start, p = 0, it = 0;
-  do {
-    pos[base + s] = p;
-    p += steps[base + s];
-    s = nxt[base + s];
-  } while (s != s_start && p < n && ++it <= ns && s < ns);
-  const bool ok = s == s_start && p <= n && p > 0 && n % p == 0;
-  period[b] = ok ? p : 0u;
-  if (!ok) atomicOr(err, ERR_STREAM);
+  const uint32_t cut = ns;  // the node after the chain's last sample
+  for (uint32_t i = tid; i <= ns; i += CHAIN_NT) {
+    if (i == cut) {
+      succ[i] = cut;
+      cnt[i] = 0;
+    } else {
+      const uint32_t x = nxt[base + i];
+      // a walker that found no sample ends the chain with an impossible count
+      succ[i] = x == s_start || x >= ns ? cut : x;
+      cnt[i] = x >= ns ? CHAIN_BIG : min(steps[base + i], CHAIN_BIG);
+    }
+  }
+  __syncthreads();
+  uint32_t rounds = 0;
+  while ((1u << rounds) < ns + 1) rounds++;
+  for (uint32_t r = 0; r < rounds; r++) {
+    uint32_t su[CHAIN_PER], cu[CHAIN_PER];
+#pragma unroll
+    for (uint32_t k = 0; k < CHAIN_PER; k++) {
+      const uint32_t i = tid + k * CHAIN_NT;
+      if (i <= ns) {
+        const uint32_t u = succ[i];
+        su[k] = succ[u];
+        cu[k] = min(cnt[i] + cnt[u], CHAIN_BIG);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < CHAIN_PER; k++) {
+      const uint32_t i = tid + k * CHAIN_NT;
+      if (i <= ns) {
+        succ[i] = su[k];
+        cnt[i] = cu[k];
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t P = cnt[s_start];
+  const bool ok = succ[s_start] == cut && P > 0 && P <= n && n % P == 0;
+  for (uint32_t i = tid; i < ns; i += CHAIN_NT)
+    if (succ[i] == cut) pos[base + i] = ok ? P - cnt[i] : UNVISITED;
+  if (tid == 0) {
+    period[b] = ok ? P : 0u;
+    if (!ok) atomicOr(err, ERR_STREAM);
+  }
 }
 
 // Walkers on the chain write their pieces of the text (the RLE1 bytes).
@@ -965,22 +1021,40 @@ __global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks
                                                  const uint32_t* __restrict__ steps,
                                                  const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
                                                  uint8_t* __restrict__ T) {
-  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t j = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;  // as in k_dec_walk
   if (j >= total) return;
   const uint32_t p0 = pos[j];
   if (p0 == UNVISITED) return;
   const uint32_t b = owner_of_wg(s0, nb, j);
   const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b], per = period[b];
-  if (per == 0) return;
+  if (per == 0 || p0 >= per) return;
   const uint64_t o = blks[b].l_off;
   const uint32_t* F = FL + o;
-  uint8_t* Tb = T + o;
+  uint8_t* Tb = T + o + p0;
   uint32_t row = sample_row(s, n, orig);
-  const uint32_t c = steps[j];
-  for (uint32_t k = 0; k < c && p0 + k < per; k++) {
+  const uint32_t c = min(steps[j], per - p0);
+  // the piece's bytes in order: single bytes up to a 4-byte boundary, then
+  // whole words, then the rest
+  uint32_t k = 0;
+  for (; k < c && ((uintptr_t)(Tb + k) & 3u); k++) {
     const uint32_t v = F[row];
     row = v & 0xFFFFFFu;
-    Tb[p0 + k] = (uint8_t)(v >> 24);
+    Tb[k] = (uint8_t)(v >> 24);
+  }
+  for (; k + 4 <= c; k += 4) {
+    uint32_t w = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; i++) {
+      const uint32_t v = F[row];
+      row = v & 0xFFFFFFu;
+      w |= (v >> 24) << (8 * i);
+    }
+    *(uint32_t*)(Tb + k) = w;
+  }
+  for (; k < c; k++) {
+    const uint32_t v = F[row];
+    row = v & 0xFFFFFFu;
+    Tb[k] = (uint8_t)(v >> 24);
   }
 }
 
@@ -1267,8 +1341,8 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
     hipLaunchKernelGGL(k_dec_walk, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
                        d.walk_total, d.n_rows, d.orig, d.FL, d.nxt, d.steps, d.pos);
   }
-  hipLaunchKernelGGL(k_dec_chain, dim3((nb + 63) / 64), dim3(64), 0, st, d.walk0, nb, d.n_rows, d.orig, d.nxt,
-                     d.steps, d.pos, d.period, d.err);
+  hipLaunchKernelGGL(k_dec_chain, dim3(nb), dim3(CHAIN_NT), 0, st, d.walk0, nb, d.n_rows, d.orig, d.nxt, d.steps,
+                     d.pos, d.period, d.err);
   {
     ProfScope ps("dec_emit", st, 0.0);
     hipLaunchKernelGGL(k_dec_emit, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
