@@ -1495,16 +1495,19 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   if (rc) return rc;
   const uint32_t nb = (uint32_t)blocks.size(), ns = (uint32_t)streams.size();
   if (nb >= (1u << 24)) return fail(ctx, BZG_EINVAL, "too many blocks");
-  // per block: BWT column, text and map ranges, walker and segment slots
-  std::vector<uint64_t> walk0(nb + 1, 0), rle0(nb + 1, 0), ch0(nb + 1, 0);
+  // per block: BWT column, text and map ranges; bounds on the work items the
+  // device plans from the decoded lengths (walkers, run-length segments,
+  // move-to-front and FL chunks)
+  uint64_t wt = 0, rt = 0, ct = 0, ft = 0;
   std::vector<uint32_t> sb0(ns + 1, 0), scrc(ns, 0);
   uint64_t lsum = 0;
   for (uint32_t b = 0; b < nb; b++) {
     blocks[b].l_off = lsum;
     lsum += blocks[b].cap;
-    walk0[b + 1] = walk0[b] + dec_walk_slots(blocks[b].cap);
-    rle0[b + 1] = rle0[b] + dec_rle_slots(blocks[b].cap);
-    ch0[b + 1] = ch0[b] + dec_mtf_chunks(blocks[b].cap);
+    wt += dec_walk_slots(blocks[b].cap);
+    rt += dec_rle_slots(blocks[b].cap);
+    ct += dec_mtf_chunks(blocks[b].cap);
+    ft += dec_fl_chunks(blocks[b].cap);
   }
   for (uint32_t k = 0; k < ns; k++) {
     sb0[k] = streams[k].b0;
@@ -1517,7 +1520,6 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     const uint64_t zero = 0;
     return upload(ctx, {{d_out_bytes, &zero, 8}}, st);
   }
-  const uint64_t wt = walk0[nb], rt = rle0[nb], ct = ch0[nb];
   const uint64_t tcap = out_cap / RLE_TILE + nb + 1;
   if (tcap >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "out_cap too large");
   DecRun d{};
@@ -1528,6 +1530,8 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     r.walk0 = cv.take<uint64_t>(nb + 1);
     r.rle0 = cv.take<uint64_t>(nb + 1);
     r.ch0 = cv.take<uint64_t>(nb + 1);
+    r.plan_cnt = cv.take<uint32_t>(nb);
+    r.fl_off = cv.take<uint64_t>(nb + 1);
     misc[0] = cv.take<uint32_t>(ns + 1);  // stream first blocks
     misc[1] = cv.take<uint32_t>(ns + 1);  // stream CRCs
     r.L = cv.take<uint8_t>(lsum + 64);
@@ -1544,6 +1548,8 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     r.ce = cv.take<uint32_t>(ct);
     r.clen = cv.take<uint32_t>(ct);
     r.coff = cv.take<uint32_t>(ct);
+    r.fl_cnt = cv.take<uint32_t>(ft * 256);
+    r.fl_owner = cv.take<uint32_t>(ft);
     r.nxt = cv.take<uint32_t>(wt);
     r.steps = cv.take<uint32_t>(wt);
     r.pos = cv.take<uint32_t>(wt);
@@ -1575,9 +1581,6 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   if ((rc = upload(ctx,
                    {{(void*)d.blks, blocks.data(), nb * sizeof(DecBlk)},
                     {(void*)d.order, order.data(), nb * 4},
-                    {(void*)d.walk0, walk0.data(), (nb + 1) * 8},
-                    {(void*)d.rle0, rle0.data(), (nb + 1) * 8},
-                    {(void*)d.ch0, ch0.data(), (nb + 1) * 8},
                     {misc[0], sb0.data(), (ns + 1) * 4},
                     {misc[1], scrc.data(), ns * 4}},
                    st)))
@@ -1590,6 +1593,7 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   d.walk_total = wt;
   d.rle_total = rt;
   d.ch_total = ct;
+  d.fl_total = ft;
   d.out_cap = out_cap;
   d.out_bytes = d_out_bytes;
   HIPX(dec_run(d, st));

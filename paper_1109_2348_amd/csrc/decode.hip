@@ -28,35 +28,69 @@ constexpr uint32_t RLE_SEG = 64;                    // bytes per run-length deco
 
 // --------------------------------------------------------- marker search
 
+// A marker that starts at bit r (0..7) of a byte covers the whole two bytes
+// after it, which then hold bits 8-r .. 23-r of the magic: 8 possible 16-bit
+// values per kind.  A bitmap over the top 12 bits of those values is the
+// filter; positions it passes get the full 48-bit comparison.
+constexpr uint32_t FIND_MAP_WORDS = 4096 / 32;
+__device__ __forceinline__ void find_filter_init(uint32_t* map) {
+  for (uint32_t i = threadIdx.x; i < FIND_MAP_WORDS; i += blockDim.x) map[i] = 0;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const uint64_t M = threadIdx.x < 8 ? MAGIC_BLOCK : MAGIC_EOS;
+    const uint32_t r = threadIdx.x & 7u;
+    const uint32_t v = (uint32_t)(M >> (28 + r)) & 0xFFFu;
+    atomicOr(&map[v >> 5], 1u << (v & 31u));
+  }
+  __syncthreads();
+}
+
 // Marker candidates of the 16 bytes at b0 (bit positions 8*b0 .. +127 whose
 // 48 bits lie inside the input): a bit mask per 64 positions for each kind.
 __device__ __forceinline__ void find_markers(const uint8_t* __restrict__ in, uint64_t n, uint64_t b0,
-                                             uint64_t m[2][2]) {
-  uint64_t W[3];
+                                             const uint32_t* __restrict__ map, uint64_t m[2][2]) {
+  uint64_t W[3];  // the 24 bytes from b0, most significant first
+  if (b0 + 24 <= n && ((uintptr_t)(in + b0) & 7u) == 0) {
 #pragma unroll
-  for (int w = 0; w < 3; w++) {
-    uint64_t v = 0;
+    for (int w = 0; w < 3; w++) W[w] = __builtin_bswap64(((const uint64_t*)(in + b0))[w]);
+  } else {
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const uint64_t q = b0 + 8 * w + i;
-      v = (v << 8) | (q < n ? in[q] : 0u);
+    for (int w = 0; w < 3; w++) {
+      uint64_t v = 0;
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const uint64_t q = b0 + 8 * w + i;
+        v = (v << 8) | (q < n ? in[q] : 0u);
+      }
+      W[w] = v;
     }
-    W[w] = v;
   }
-  const uint64_t nbits = 8 * n;
+  m[0][0] = m[0][1] = m[1][0] = m[1][1] = 0;
+  // bytes q+1, q+2 of the 24 loaded, for the 16 byte positions q
+  uint32_t hit = 0;
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
-    uint64_t mb = 0, me = 0;
-#pragma unroll 8
-    for (int p = 0; p < 64; p++) {
-      const uint64_t hi = p ? (W[h] << p) | (W[h + 1] >> (64 - p)) : W[h];
-      const uint64_t v = hi >> 16;
-      const bool inside = 8 * b0 + 64 * h + p + 48 <= nbits;
-      mb |= (uint64_t)(inside && v == MAGIC_BLOCK) << p;
-      me |= (uint64_t)(inside && v == MAGIC_EOS) << p;
+  for (int q = 0; q < 16; q++) {
+    const int j = q + 1;  // first of the two bytes
+    const uint64_t hi = W[j / 8], lo = j / 8 + 1 < 3 ? W[j / 8 + 1] : 0ull;
+    const int sh = 8 * (j % 8);  // bits of hi before byte j
+    const uint64_t win = sh ? (hi << sh) | (lo >> (64 - sh)) : hi;
+    const uint32_t v = (uint32_t)(win >> 52);
+    hit |= ((map[v >> 5] >> (v & 31u)) & 1u) << q;
+  }
+  if (!hit) return;
+  const uint64_t nbits = 8 * n;
+  while (hit) {
+    const int q = __ffs(hit) - 1;
+    hit &= hit - 1;
+    for (int r = 0; r < 8; r++) {
+      const int p = 8 * q + r;  // bit position in the 16 bytes
+      const int h = p >> 6, pp = p & 63;
+      const uint64_t win = pp ? (W[h] << pp) | (W[h + 1] >> (64 - pp)) : W[h];
+      const uint64_t v = win >> 16;
+      const bool inside = 8 * b0 + (uint64_t)p + 48 <= nbits;
+      if (inside && v == MAGIC_BLOCK) m[0][h] |= 1ull << pp;
+      if (inside && v == MAGIC_EOS) m[1][h] |= 1ull << pp;
     }
-    m[0][h] = mb;
-    m[1][h] = me;
   }
 }
 
@@ -78,9 +112,11 @@ __global__ __launch_bounds__(NT) void k_find_markers(const uint8_t* __restrict__
                                                      const uint64_t* __restrict__ tile_off,
                                                      uint64_t* __restrict__ cand, uint64_t cand_cap) {
   __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  __shared__ uint32_t map[FIND_MAP_WORDS];
+  find_filter_init(map);
   const uint64_t b0 = ((uint64_t)blockIdx.x * NT + threadIdx.x) * FIND_BYTES;
   uint64_t m[2][2] = {{0, 0}, {0, 0}};
-  if (b0 < n) find_markers(in, n, b0, m);
+  if (b0 < n) find_markers(in, n, b0, map, m);
   const uint32_t c = __popcll(m[0][0]) + __popcll(m[0][1]) + __popcll(m[1][0]) + __popcll(m[1][1]);
   uint32_t tot;
   const uint32_t ex = block_excl_sum<uint32_t, NT>(c, sh, &tot);
@@ -659,12 +695,13 @@ __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 // and the chunks' starting lists in the next as many.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_perm(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
-                                                           uint64_t ch_total, uint32_t* __restrict__ FL,
+                                                           uint32_t* __restrict__ FL,
                                                            const uint32_t* __restrict__ n_syms,
                                                            uint8_t* __restrict__ T, uint32_t* __restrict__ cs,
                                                            uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                                            uint32_t* __restrict__ err) {
-  for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x)
+  const uint64_t total = ch0[nb];
+  for (uint64_t j = blockIdx.x; j < total; j += gridDim.x)
     mtf_perm_chunk(j, blks, ch0, nb, FL, n_syms, T, cs, ce, clen, err);
 }
 // Per block (one wave): each chunk's starting list and output offset, by
@@ -796,7 +833,7 @@ __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
-                                                           uint64_t ch_total, uint32_t* __restrict__ FL,
+                                                           uint32_t* __restrict__ FL,
                                                            const uint32_t* __restrict__ n_syms,
                                                            const uint8_t* __restrict__ T,
                                                            const uint32_t* __restrict__ cs,
@@ -805,7 +842,8 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restr
                                                            const uint32_t* __restrict__ n_rows,
                                                            uint8_t* __restrict__ L) {
   __shared__ __align__(4) uint8_t lst[256];
-  for (uint64_t j = blockIdx.x; j < ch_total; j += gridDim.x) {
+  const uint64_t total = ch0[nb];
+  for (uint64_t j = blockIdx.x; j < total; j += gridDim.x) {
     mtf_emit_chunk(j, blks, ch0, nb, FL, n_syms, T, cs, ce, coff, n_rows, L, lst);
     __syncthreads();
   }
@@ -813,58 +851,149 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restr
 
 // ------------------------------------------------------ inverse BWT map
 
+// The block owning flat slot j of a per-block slot layout (offsets s0[0..nb]).
+__device__ __forceinline__ uint32_t owner_of(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
+  uint32_t lo = 0, hi = nb;  // s0[lo] <= j < s0[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (s0[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+// The same for a workgroup of consecutive slots: one search for its first
+// slot (workgroup-uniform), then each thread steps over the few blocks its
+// slot lies past.
+__device__ __forceinline__ uint32_t owner_of_wg(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
+  uint32_t b = owner_of(s0, nb, j - threadIdx.x);
+  while (b + 1 < nb && s0[b + 1] <= j) b++;
+  return b;
+}
+
 // FL of one block: the row that holds, in the last column, the k-th
 // occurrence of the byte that is first in row C[byte] + k -- a stable
-// counting sort of the column (one workgroup per block, 256 rows a step).
-// Each entry carries that byte in its top 8 bits (rows < 2^24), so the walks
-// read one array.
-__global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, const uint32_t* __restrict__ order,
-                                               const uint8_t* __restrict__ L,
-                                               const uint32_t* __restrict__ n_rows, uint32_t* __restrict__ FL) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wc[NT / BZG_WAVE][256];
-  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
-  const uint32_t b = order[blockIdx.x], tid = threadIdx.x, w = tid / BZG_WAVE;
-  const uint32_t n = n_rows[b];
-  const uint8_t* Lb = L + blks[b].l_off;
-  uint32_t* F = FL + blks[b].l_off;
-  // the column's byte counts (LDS atomics, a word of 4 bytes per thread a
-  // step; the range is 16-byte aligned and padded), then their offsets
-  base[tid] = 0;
-  __syncthreads();
-  for (uint32_t k = 4 * tid; k < n; k += 4 * NT) {
-    const uint32_t v = *(const uint32_t*)(Lb + k);
+// counting sort of the column.  Each entry carries that byte in its top 8
+// bits (rows < 2^24), so the walks read one array.  The column is cut into
+// chunks of FL_CH rows (a workgroup each; slots planned from the block's
+// capacity, those past its length idle): byte counts per chunk, then per
+// block their offsets, then every chunk writes its rows, each wave its own
+// FL_SUB rows 64 at a time.
+constexpr uint32_t FL_CH = 65536;
+constexpr uint32_t FL_NW = NT / BZG_WAVE;
+constexpr uint32_t FL_SUB = FL_CH / FL_NW;
+constexpr uint32_t FL_BATCH = 16 * BZG_WAVE;  // column bytes a wave stages at a time
+
+// The block of every FL chunk (a thread per block): the chunk kernels are
+// persistent over the chunks that exist.
+__global__ void k_dec_fl_owner(const uint64_t* __restrict__ off, uint32_t nb, uint32_t* __restrict__ owner) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  for (uint64_t j = off[b]; j < off[b + 1]; j++) owner[j] = b;
+}
+
+// Byte counts of rows [lo, hi) of a block's column into h (LDS atomics, 16
+// bytes per thread a step; block ranges are 16-byte aligned and padded).
+__device__ __forceinline__ void fl_count(const uint8_t* __restrict__ Lb, uint32_t lo, uint32_t hi, uint32_t t,
+                                         uint32_t nt, uint32_t* h) {
+  for (uint32_t k = lo + 16 * t; k < hi; k += 16 * nt) {
+    const uint4 v = *(const uint4*)(Lb + k);
+    const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (uint32_t q = 0; q < 4; q++)
-      if (k + q < n) atomicAdd(&base[(v >> (8 * q)) & 255u], 1u);
+    for (uint32_t q = 0; q < 16; q++)
+      if (k + q < hi) atomicAdd(&h[(wv[q / 4] >> (8 * (q % 4))) & 255u], 1u);
   }
-  __syncthreads();
-  {
-    uint32_t tot;
-    const uint32_t c = base[tid];
+}
+
+__global__ __launch_bounds__(NT) void k_dec_fl_count(const DecBlk* __restrict__ blks, uint32_t nb,
+                                                     const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ owner, const uint8_t* __restrict__ L,
+                                                     const uint32_t* __restrict__ n_rows, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t h[FL_NW][256];
+  const uint32_t tid = threadIdx.x, w = tid / BZG_WAVE;
+  const uint64_t total = off[nb];
+  for (uint64_t j = blockIdx.x; j < total; j += gridDim.x) {
+    const uint32_t b = owner[j], c = (uint32_t)(j - off[b]), n = n_rows[b];
+    for (uint32_t q = 0; q < FL_NW; q++) h[q][tid] = 0;
     __syncthreads();
-    base[tid] = block_excl_sum<uint32_t, NT>(c, sh, &tot);
-    for (int q = 0; q < NT / BZG_WAVE; q++) wc[q][tid] = 0;
+    const uint32_t lo = c * FL_CH, hi = min(n, lo + FL_CH);
+    fl_count(L + blks[b].l_off, lo, hi, tid, NT, h[w]);
+    __syncthreads();
+    uint32_t t = 0;
+    for (uint32_t q = 0; q < FL_NW; q++) t += h[q][tid];
+    cnt[j * 256 + tid] = t;
+    __syncthreads();
   }
-  __syncthreads();
-  for (uint32_t k0 = 0; k0 < n; k0 += NT) {
-    const uint32_t k = k0 + tid;
-    const bool ok = k < n;
-    const uint32_t d = ok ? Lb[k] : 0u;
-    const uint64_t peers = match_digit8(d, __ballot(ok));
-    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-    if (ok && (uint32_t)(__ffsll((long long)peers) - 1) == lane()) wc[w][d] = (uint32_t)__popcll(peers);
+}
+
+// Per block (a workgroup, a thread per byte): each chunk's first row per
+// byte -- the byte's start in the first column plus the chunks before.
+__global__ __launch_bounds__(NT) void k_dec_fl_scan(const uint64_t* __restrict__ off, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t sh[NT / BZG_WAVE + 1];
+  const uint32_t b = blockIdx.x, d = threadIdx.x;
+  const uint32_t nch = (uint32_t)(off[b + 1] - off[b]);
+  uint32_t* cb = cnt + off[b] * 256;
+  uint32_t acc = 0;
+  for (uint32_t c = 0; c < nch; c++) {
+    const uint32_t v = cb[c * 256 + d];
+    cb[c * 256 + d] = acc;
+    acc += v;
+  }
+  uint32_t tot;
+  const uint32_t C = block_excl_sum<uint32_t, NT>(acc, sh, &tot);
+  for (uint32_t c = 0; c < nch; c++) cb[c * 256 + d] += C;
+}
+
+__global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, uint32_t nb,
+                                               const uint64_t* __restrict__ off, const uint32_t* __restrict__ owner,
+                                               const uint8_t* __restrict__ L, const uint32_t* __restrict__ n_rows,
+                                               const uint32_t* __restrict__ cnt, uint32_t* __restrict__ FL) {
+  __shared__ uint32_t wb[FL_NW][256];  // per wave: the next row of each byte
+  __shared__ __align__(16) uint8_t stage[FL_NW][FL_BATCH];
+  const uint32_t tid = threadIdx.x, w = tid / BZG_WAVE, ln = lane();
+  const uint64_t total = off[nb];
+  for (uint64_t j = blockIdx.x; j < total; j += gridDim.x) {
+    const uint32_t b = owner[j], c = (uint32_t)(j - off[b]), n = n_rows[b];
+    const uint8_t* Lb = L + blks[b].l_off;
+    uint32_t* F = FL + blks[b].l_off;
+    const uint32_t lo = min(n, c * FL_CH + w * FL_SUB), hi = min(n, lo + FL_SUB);
+    for (uint32_t q = 0; q < FL_NW; q++) wb[q][tid] = 0;
     __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t q = 0; q < w; q++) before += wc[q][d];
-    if (ok) F[base[d] + before + rank] = k | (d << 24);
+    fl_count(Lb, lo, hi, ln, BZG_WAVE, wb[w]);
     __syncthreads();
-    uint32_t all = 0;
-    for (int q = 0; q < NT / BZG_WAVE; q++) {
-      all += wc[q][tid];
-      wc[q][tid] = 0;
+    {
+      uint32_t run = cnt[j * 256 + tid];
+      for (uint32_t q = 0; q < FL_NW; q++) {
+        const uint32_t x = wb[q][tid];
+        wb[q][tid] = run;
+        run += x;
+      }
     }
-    base[tid] += all;
+    __syncthreads();
+    // this wave alone until the next barrier (its LDS rows are used in
+    // program order): the column FL_BATCH bytes at a time, the next batch
+    // loading while this one is ranked 64 rows a step
+    uint32_t* nx = wb[w];
+    uint8_t* sg = stage[w];
+    uint4 ahead = lo + 16 * ln < hi ? *(const uint4*)(Lb + lo + 16 * ln) : make_uint4(0, 0, 0, 0);
+    for (uint32_t k0 = lo; k0 < hi; k0 += FL_BATCH) {
+      ((uint4*)sg)[ln] = ahead;
+      const uint32_t k1 = k0 + FL_BATCH;
+      if (k1 + 16 * ln < hi) ahead = *(const uint4*)(Lb + k1 + 16 * ln);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t steps = min(FL_BATCH, hi - k0);
+      for (uint32_t s = 0; s < steps; s += BZG_WAVE) {
+        const uint32_t k = k0 + s + ln;
+        const bool ok = k < hi;
+        const uint32_t d = ok ? sg[s + ln] : 0u;
+        const uint64_t peers = match_digit8(d, __ballot(ok));
+        const uint32_t base = nx[d];
+        if (ok) F[base + (uint32_t)__popcll(peers & lanemask_lt())] = k | (d << 24);
+        if (ok && (uint32_t)(__ffsll((long long)peers) - 1) == ln) nx[d] = base + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
     __syncthreads();
   }
 }
@@ -887,37 +1016,15 @@ __device__ __forceinline__ uint32_t sample_index(uint32_t row, uint32_t n, uint3
   return row % WALK_STRIDE == 0 ? row / WALK_STRIDE : (n + WALK_STRIDE - 1) / WALK_STRIDE;
 }
 
-// The block owning flat slot j of a per-block slot layout (offsets s0[0..nb]).
-__device__ __forceinline__ uint32_t owner_of(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
-  uint32_t lo = 0, hi = nb;  // s0[lo] <= j < s0[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (s0[mid] <= j) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-// The same for a workgroup of consecutive slots: one search for its first
-// slot (workgroup-uniform), then each thread steps over the few blocks its
-// slot lies past.
-__device__ __forceinline__ uint32_t owner_of_wg(const uint64_t* __restrict__ s0, uint32_t nb, uint64_t j) {
-  uint32_t b = owner_of(s0, nb, j - threadIdx.x);
-  while (b + 1 < nb && s0[b + 1] <= j) b++;
-  return b;
-}
-
 constexpr uint32_t UNVISITED = 0xFFFFFFFFu;
 
 // Walker per sampled row: follows FL until the next sampled row; records
 // the steps and which sample it reached.
-__global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
-                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
-                                                 const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
-                                                 uint32_t* __restrict__ nxt, uint32_t* __restrict__ steps,
-                                                 uint32_t* __restrict__ pos) {
-  // each XCD walks a contiguous range of walkers, so a block's map is read
-  // through one L2
-  const uint64_t j = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+__device__ __forceinline__ void walk_item(uint64_t j, const DecBlk* __restrict__ blks,
+                                          const uint64_t* __restrict__ s0, uint32_t nb, uint64_t total,
+                                          const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ origs,
+                                          const uint32_t* __restrict__ FL, uint32_t* __restrict__ nxt,
+                                          uint32_t* __restrict__ steps, uint32_t* __restrict__ pos) {
   if (j >= total) return;
   const uint32_t b = owner_of_wg(s0, nb, j);
   const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b];
@@ -931,6 +1038,17 @@ __global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks
   } while (!is_sample(row, orig) && c < n);
   nxt[j] = sample_index(row, n, orig);
   steps[j] = c;
+}
+// Walkers in tiles of NT, persistent; each XCD walks a contiguous range of
+// walkers, so a block's map is read through one L2.
+__global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
+                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
+                                                 uint32_t* __restrict__ nxt, uint32_t* __restrict__ steps,
+                                                 uint32_t* __restrict__ pos) {
+  const uint64_t total = s0[nb];
+  for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
+    walk_item((uint64_t)it.t * NT + threadIdx.x, blks, s0, nb, total, n_rows, origs, FL, nxt, steps, pos);
 }
 
 // Per block: the chain of samples from origPtr gives every walker on it its
@@ -1015,13 +1133,12 @@ __global__ __launch_bounds__(CHAIN_NT) void k_dec_chain(const uint64_t* __restri
 }
 
 // Walkers on the chain write their pieces of the text (the RLE1 bytes).
-__global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
-                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
-                                                 const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
-                                                 const uint32_t* __restrict__ steps,
-                                                 const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
-                                                 uint8_t* __restrict__ T) {
-  const uint64_t j = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x;  // as in k_dec_walk
+__device__ __forceinline__ void emit_item(uint64_t j, const DecBlk* __restrict__ blks,
+                                          const uint64_t* __restrict__ s0, uint32_t nb, uint64_t total,
+                                          const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ origs,
+                                          const uint32_t* __restrict__ FL, const uint32_t* __restrict__ steps,
+                                          const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
+                                          uint8_t* __restrict__ T) {
   if (j >= total) return;
   const uint32_t p0 = pos[j];
   if (p0 == UNVISITED) return;
@@ -1058,6 +1175,18 @@ __global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks
   }
 }
 
+// The walkers as in k_dec_walk.
+__global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
+                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
+                                                 const uint32_t* __restrict__ steps,
+                                                 const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
+                                                 uint8_t* __restrict__ T) {
+  const uint64_t total = s0[nb];
+  for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
+    emit_item((uint64_t)it.t * NT + threadIdx.x, blks, s0, nb, total, n_rows, origs, FL, steps, pos, period, T);
+}
+
 // A block that repeats a string of the period: the rest is copies.
 __global__ __launch_bounds__(NT) void k_dec_repeat(const DecBlk* __restrict__ blks,
                                                    const uint32_t* __restrict__ n_rows,
@@ -1090,11 +1219,11 @@ __device__ __forceinline__ uint32_t rle_step(uint32_t& st, uint32_t& last, uint3
 // Per segment of RLE_SEG text bytes, for each incoming state s (with `last`
 // = the segment's first byte for s = 1..3): output bytes, outgoing state and
 // last byte, packed as len | st << 32 | last << 40.
-__global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
-                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
-                                                 const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
-                                                 uint64_t* __restrict__ summ) {
-  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
+__device__ __forceinline__ void rle_summ_item(uint64_t j, const DecBlk* __restrict__ blks,
+                                              const uint64_t* __restrict__ g0, uint32_t nb, uint64_t total,
+                                              const uint32_t* __restrict__ n_rows,
+                                              const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                              uint64_t* __restrict__ summ) {
   if (j >= total) return;
   const uint32_t b = owner_of_wg(g0, nb, j);
   const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
@@ -1126,6 +1255,16 @@ __device__ __forceinline__ uint32_t map_then(uint32_t f, uint32_t g) {
 #pragma unroll
   for (uint32_t st = 0; st < 5; st++) r |= map_at(g, map_at(f, st)) << (3 * st);
   return r;
+}
+
+// Segments in tiles of NT, persistent.
+__global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
+                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                                 uint64_t* __restrict__ summ) {
+  const uint64_t total = g0[nb];
+  for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
+    rle_summ_item((uint64_t)it.t * NT + threadIdx.x, blks, g0, nb, total, n_rows, period, T, summ);
 }
 
 // Per block (one workgroup): each segment's incoming state and last byte and
@@ -1249,15 +1388,14 @@ __global__ __launch_bounds__(1024) void k_rle_offsets(const uint32_t* __restrict
 }
 
 // Every segment expands its bytes at its offset (Figure 2's scatter).
-__global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
-                                                 uint32_t nb, uint64_t total, const uint32_t* __restrict__ n_rows,
-                                                 const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
-                                                 const uint32_t* __restrict__ seg_in,
-                                                 const uint32_t* __restrict__ seg_off,
-                                                 const uint64_t* __restrict__ out_off,
-                                                 const uint32_t* __restrict__ skip, uint8_t* __restrict__ out) {
-  const uint64_t j = (uint64_t)blockIdx.x * NT + threadIdx.x;
-  if (j >= total || *skip) return;
+__device__ __forceinline__ void rle_emit_item(uint64_t j, const DecBlk* __restrict__ blks,
+                                              const uint64_t* __restrict__ g0, uint32_t nb, uint64_t total,
+                                              const uint32_t* __restrict__ n_rows,
+                                              const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                              const uint32_t* __restrict__ seg_in,
+                                              const uint32_t* __restrict__ seg_off,
+                                              const uint64_t* __restrict__ out_off, uint8_t* __restrict__ out) {
+  if (j >= total) return;
   const uint32_t b = owner_of_wg(g0, nb, j);
   const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
   if ((uint64_t)g * RLE_SEG >= n) return;
@@ -1276,6 +1414,44 @@ __global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks
     }
     (void)rle_step(st, last, x);
   }
+}
+
+// Segments as in k_rle_summ (nothing when the output did not fit).
+__global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
+                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
+                                                 const uint32_t* __restrict__ seg_in,
+                                                 const uint32_t* __restrict__ seg_off,
+                                                 const uint64_t* __restrict__ out_off,
+                                                 const uint32_t* __restrict__ skip, uint8_t* __restrict__ out) {
+  if (*skip) return;
+  const uint64_t total = g0[nb];
+  for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
+    rle_emit_item((uint64_t)it.t * NT + threadIdx.x, blks, g0, nb, total, n_rows, period, T, seg_in, seg_off,
+                  out_off, out);
+}
+
+// Work items per block of each kind, planned on the device once the blocks'
+// lengths are known (their offsets are then a scan, k_scan_counts).  None
+// exceeds the bound the host sized its arrays for from the block's capacity.
+enum DecPlan : int { PLAN_MTF = 0, PLAN_FL = 1, PLAN_WALK = 2, PLAN_RLE = 3 };
+__global__ void k_dec_plan(int kind, uint32_t nb, const uint32_t* __restrict__ n_syms,
+                           const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ origs,
+                           const uint32_t* __restrict__ period, uint32_t* __restrict__ cnt) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  uint32_t c;
+  if (kind == PLAN_MTF) {
+    c = (n_syms[b] + MTF_CH - 1) / MTF_CH;
+  } else if (kind == PLAN_FL) {
+    c = (n_rows[b] + FL_CH - 1) / FL_CH;
+  } else if (kind == PLAN_WALK) {
+    c = n_rows[b] ? samples_of(n_rows[b], origs[b]) : 0u;
+  } else {
+    const uint32_t n = period[b] ? n_rows[b] : 0u;
+    c = (n + RLE_SEG - 1) / RLE_SEG;
+  }
+  cnt[b] = c;
 }
 
 // Block CRCs against the stored ones, and every stream's combined CRC.
@@ -1313,9 +1489,21 @@ hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipSt
 uint32_t dec_walk_slots(uint32_t cap) { return cap / WALK_STRIDE + 2; }
 uint32_t dec_rle_slots(uint32_t cap) { return cap / RLE_SEG + 1; }
 uint32_t dec_mtf_chunks(uint32_t cap) { return cap / MTF_CH + 1; }
+uint32_t dec_fl_chunks(uint32_t cap) { return cap / FL_CH + 1; }
 
 hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t nb = d.nb;
+  // per-block work items of a kind, from the lengths decoded so far
+  auto plan = [&](int kind, uint64_t* off) {
+    hipLaunchKernelGGL(k_dec_plan, dim3((nb + 255) / 256), dim3(256), 0, st, kind, nb, d.n_syms, d.n_rows, d.orig,
+                       d.period, d.plan_cnt);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, d.plan_cnt, nb, off);
+  };
+  // one tile of NT items per workgroup, over the items' bound: the items
+  // that exist come first in every XCD's range (the hardware hands tiles out
+  // as workgroups finish, which balances walks of uneven length), and
+  // workgroups past them end at once
+  auto grid = [](uint64_t bound_items) { return persist_grid((bound_items + NT - 1) / NT, ONE_TILE_EACH); };
   {
     ProfScope ps("dec_block", st, 0.0);
     hipLaunchKernelGGL(k_dec_block, dim3(nb), dim3(BZG_WAVE), 0, st, d.in, d.n_in, d.blks, d.order, d.FL, d.n_syms,
@@ -1324,42 +1512,54 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t gc = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(d.ch_total, 1), 1u << 16);
   {
     ProfScope ps("dec_mtf", st, 0.0);
-    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, d.FL,
-                       d.n_syms, d.T, d.cs, d.ce, d.clen, d.err);
+    plan(PLAN_MTF, d.ch0);
+    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.FL, d.n_syms, d.T,
+                       d.cs, d.ce, d.clen, d.err);
     hipLaunchKernelGGL(k_dec_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, d.n_syms, d.mtf0, d.T,
                        d.clen, d.coff, d.orig, d.n_rows, d.err);
-    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.ch_total, d.FL,
-                       d.n_syms, d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
+    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.FL, d.n_syms, d.T,
+                       d.cs, d.ce, d.coff, d.n_rows, d.L);
   }
   {
     ProfScope ps("dec_fl", st, 0.0);
-    hipLaunchKernelGGL(k_dec_fl, dim3(nb), dim3(NT), 0, st, d.blks, d.order, d.L, d.n_rows, d.FL);
+    plan(PLAN_FL, d.fl_off);
+    hipLaunchKernelGGL(k_dec_fl_owner, dim3((nb + 255) / 256), dim3(256), 0, st, d.fl_off, nb, d.fl_owner);
+    const uint32_t gf = std::min<uint32_t>((uint32_t)std::max<uint64_t>(d.fl_total, 1),
+                                           resident_grid((const void*)k_dec_fl, NT));
+    hipLaunchKernelGGL(k_dec_fl_count, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.fl_off, d.fl_owner, d.L, d.n_rows,
+                       d.fl_cnt);
+    hipLaunchKernelGGL(k_dec_fl_scan, dim3(nb), dim3(NT), 0, st, d.fl_off, d.fl_cnt);
+    hipLaunchKernelGGL(k_dec_fl, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.fl_off, d.fl_owner, d.L, d.n_rows,
+                       d.fl_cnt, d.FL);
   }
-  const uint32_t gw = (uint32_t)((d.walk_total + NT - 1) / NT);
+  const uint32_t gw = grid(d.walk_total);
+  const uint32_t ge = grid(d.walk_total);
   {
     ProfScope ps("dec_walk", st, 0.0);
-    hipLaunchKernelGGL(k_dec_walk, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
-                       d.walk_total, d.n_rows, d.orig, d.FL, d.nxt, d.steps, d.pos);
+    plan(PLAN_WALK, d.walk0);
+    hipLaunchKernelGGL(k_dec_walk, dim3(gw), dim3(NT), 0, st, d.blks, d.walk0, nb, d.n_rows, d.orig, d.FL, d.nxt,
+                       d.steps, d.pos);
   }
   hipLaunchKernelGGL(k_dec_chain, dim3(nb), dim3(CHAIN_NT), 0, st, d.walk0, nb, d.n_rows, d.orig, d.nxt, d.steps,
                      d.pos, d.period, d.err);
   {
     ProfScope ps("dec_emit", st, 0.0);
-    hipLaunchKernelGGL(k_dec_emit, dim3(std::max(gw, 1u)), dim3(NT), 0, st, d.blks, d.walk0, nb,
-                       d.walk_total, d.n_rows, d.orig, d.FL, d.steps, d.pos, d.period, d.T);
+    hipLaunchKernelGGL(k_dec_emit, dim3(ge), dim3(NT), 0, st, d.blks, d.walk0, nb, d.n_rows, d.orig, d.FL, d.steps,
+                       d.pos, d.period, d.T);
   }
   hipLaunchKernelGGL(k_dec_repeat, dim3(nb), dim3(NT), 0, st, d.blks, d.n_rows, d.period, d.T);
-  const uint32_t gr = (uint32_t)((d.rle_total + NT - 1) / NT);
+  const uint32_t gs = grid(d.rle_total);
+  const uint32_t gr = grid(d.rle_total);
   {
     ProfScope ps("dec_rle", st, 0.0);
-    hipLaunchKernelGGL(k_rle_summ, dim3(std::max(gr, 1u)), dim3(NT), 0, st, d.blks, d.rle0, nb,
-                       d.rle_total, d.n_rows, d.period, d.T, d.summ);
-    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb,
-                       d.n_rows, d.period, d.T, d.summ, d.seg_in, d.seg_off, d.out_len);
+    plan(PLAN_RLE, d.rle0);
+    hipLaunchKernelGGL(k_rle_summ, dim3(gs), dim3(NT), 0, st, d.blks, d.rle0, nb, d.n_rows, d.period, d.T, d.summ);
+    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb, d.n_rows, d.period, d.T, d.summ,
+                       d.seg_in, d.seg_off, d.out_len);
     hipLaunchKernelGGL(k_rle_offsets, dim3(1), dim3(1024), 0, st, d.out_len, nb, d.out_cap, d.out_off, d.out_bytes,
                        d.skip, d.err);
-    hipLaunchKernelGGL(k_rle_emit, dim3(std::max(gr, 1u)), dim3(NT), 0, st, d.blks, d.rle0, nb,
-                       d.rle_total, d.n_rows, d.period, d.T, d.seg_in, d.seg_off, d.out_off, d.skip, d.out);
+    hipLaunchKernelGGL(k_rle_emit, dim3(gr), dim3(NT), 0, st, d.blks, d.rle0, nb, d.n_rows, d.period, d.T,
+                       d.seg_in, d.seg_off, d.out_off, d.skip, d.out);
   }
   return hipGetLastError();
 }

@@ -288,14 +288,19 @@ struct DecRun {
   uint32_t *n_rows, *orig, *crc_want, *err, *FL;
   uint32_t* n_syms;       // per block: Huffman symbols before end-of-block
   uint8_t* mtf0;          // per block: the 256-byte list move-to-front decoding starts from
-  const uint64_t* ch0;    // nb + 1 move-to-front chunk slot offsets
-  uint64_t ch_total;
+  uint64_t* ch0;          // nb + 1 move-to-front chunk offsets (device-planned)
+  uint64_t ch_total;      // move-to-front chunks at most (from the blocks' capacities)
   uint32_t *cs, *ce, *clen, *coff;  // per chunk slot: item range, output length and offset
-  const uint64_t* walk0;  // nb + 1 walker slot offsets
-  uint64_t walk_total;
+  uint64_t fl_total;     // FL chunks at most (from the blocks' capacities)
+  uint32_t* plan_cnt;    // per block: work items of the kind being planned
+  uint64_t* fl_off;      // nb + 1 FL chunk offsets (device-planned)
+  uint32_t* fl_cnt;      // 256 per FL chunk
+  uint32_t* fl_owner;    // block of each FL chunk
+  uint64_t* walk0;        // nb + 1 walker offsets (device-planned)
+  uint64_t walk_total;    // walkers at most
   uint32_t *nxt, *steps, *pos, *period;
-  const uint64_t* rle0;  // nb + 1 segment slot offsets
-  uint64_t rle_total;
+  uint64_t* rle0;         // nb + 1 segment offsets (device-planned)
+  uint64_t rle_total;     // segments at most
   uint64_t* summ;  // 5 per segment slot
   uint32_t *seg_in, *seg_off, *out_len, *skip;
   uint64_t out_cap;
@@ -308,6 +313,7 @@ hipError_t dec_scan_counts(const uint32_t* cnt, uint32_t n, uint64_t* off, hipSt
 uint32_t dec_walk_slots(uint32_t cap);
 uint32_t dec_rle_slots(uint32_t cap);
 uint32_t dec_mtf_chunks(uint32_t cap);
+uint32_t dec_fl_chunks(uint32_t cap);
 hipError_t dec_run(const DecRun& d, hipStream_t st);
 hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
                      const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
