@@ -158,6 +158,10 @@ struct bzg_ctx {
     hipStream_t up = nullptr, down = nullptr;
     hipEvent_t in_ev[2] = {nullptr, nullptr}, comp_ev[2] = {nullptr, nullptr}, out_ev[2] = {nullptr, nullptr};
   } hio;
+  // decompress: the streams the longer blocks are decoded on, and the
+  // events that fork them from the call's stream and join them back
+  hipStream_t dec_side[2] = {nullptr, nullptr};
+  hipEvent_t dec_fork = nullptr, dec_join[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -804,6 +808,10 @@ void bzg_destroy(bzg_ctx* ctx) {
   if (h.hsize) (void)hipHostFree(h.hsize);
   if (h.up) (void)hipStreamDestroy(h.up);
   if (h.down) (void)hipStreamDestroy(h.down);
+  for (hipStream_t q : ctx->dec_side)
+    if (q) (void)hipStreamDestroy(q);
+  for (hipEvent_t e : {ctx->dec_fork, ctx->dec_join[0], ctx->dec_join[1]})
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -1495,19 +1503,12 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   if (rc) return rc;
   const uint32_t nb = (uint32_t)blocks.size(), ns = (uint32_t)streams.size();
   if (nb >= (1u << 24)) return fail(ctx, BZG_EINVAL, "too many blocks");
-  // per block: BWT column, text and map ranges; bounds on the work items the
-  // device plans from the decoded lengths (walkers, run-length segments,
-  // move-to-front and FL chunks)
-  uint64_t wt = 0, rt = 0, ct = 0, ft = 0;
+  // per block: BWT column, text and map ranges
   std::vector<uint32_t> sb0(ns + 1, 0), scrc(ns, 0);
   uint64_t lsum = 0;
   for (uint32_t b = 0; b < nb; b++) {
     blocks[b].l_off = lsum;
     lsum += blocks[b].cap;
-    wt += dec_walk_slots(blocks[b].cap);
-    rt += dec_rle_slots(blocks[b].cap);
-    ct += dec_mtf_chunks(blocks[b].cap);
-    ft += dec_fl_chunks(blocks[b].cap);
   }
   for (uint32_t k = 0; k < ns; k++) {
     sb0[k] = streams[k].b0;
@@ -1520,6 +1521,51 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     const uint64_t zero = 0;
     return upload(ctx, {{d_out_bytes, &zero, 8}}, st);
   }
+  // the blocks by decreasing bit length, in classes decoded on streams of
+  // their own: class k down to the longest block's bits >> DEC_CUT_SHIFT[k],
+  // the last class the rest; the longer classes' serial Huffman decoding
+  // then overlaps the shorter ones' later stages (batches of at least
+  // DEC_SPLIT_MIN blocks)
+  std::vector<uint32_t> order(nb);
+  for (uint32_t b = 0; b < nb; b++) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    return blocks[x].end - blocks[x].start > blocks[y].end - blocks[y].start;
+  });
+  struct Cls {
+    uint32_t first, nb;
+    uint64_t wt, rt, ct, ft;
+  } cls[DEC_CLASSES] = {};
+  uint32_t ncls = 0;
+  {
+    const uint64_t top = nb ? blocks[order[0]].end - blocks[order[0]].start : 0;
+    uint32_t q = 0;
+    for (uint32_t k = 0; k < DEC_CLASSES && q < nb; k++) {
+      const uint32_t first = q;
+      if (k + 1 == DEC_CLASSES || nb < DEC_SPLIT_MIN) {
+        q = nb;
+      } else {
+        const uint64_t cut = top >> DEC_CUT_SHIFT[k];
+        while (q < nb && blocks[order[q]].end - blocks[order[q]].start >= cut) q++;
+      }
+      if (q > first) cls[ncls++] = Cls{first, q - first, 0, 0, 0, 0};
+    }
+  }
+  // per class: bounds on the work items the device plans from the decoded
+  // lengths (walkers, run-length segments, move-to-front and FL chunks)
+  uint64_t wt = 0, rt = 0, ct = 0, ft = 0;
+  for (uint32_t k = 0; k < ncls; k++) {
+    for (uint32_t q = cls[k].first; q < cls[k].first + cls[k].nb; q++) {
+      const uint32_t cap = blocks[order[q]].cap;
+      cls[k].wt += dec_walk_slots(cap);
+      cls[k].rt += dec_rle_slots(cap);
+      cls[k].ct += dec_mtf_chunks(cap);
+      cls[k].ft += dec_fl_chunks(cap);
+    }
+    wt += cls[k].wt;
+    rt += cls[k].rt;
+    ct += cls[k].ct;
+    ft += cls[k].ft;
+  }
   const uint64_t tcap = out_cap / RLE_TILE + nb + 1;
   if (tcap >= (1ull << 31)) return fail(ctx, BZG_EINVAL, "out_cap too large");
   DecRun d{};
@@ -1527,11 +1573,11 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
     Carve cv{base};
     r.blks = cv.take<DecBlk>(nb);
     r.order = cv.take<uint32_t>(nb);
-    r.walk0 = cv.take<uint64_t>(nb + 1);
-    r.rle0 = cv.take<uint64_t>(nb + 1);
-    r.ch0 = cv.take<uint64_t>(nb + 1);
+    r.walk0 = cv.take<uint64_t>(nb + DEC_CLASSES);  // per class: its blocks + 1
+    r.rle0 = cv.take<uint64_t>(nb + DEC_CLASSES);
+    r.ch0 = cv.take<uint64_t>(nb + DEC_CLASSES);
     r.plan_cnt = cv.take<uint32_t>(nb);
-    r.fl_off = cv.take<uint64_t>(nb + 1);
+    r.fl_off = cv.take<uint64_t>(nb + DEC_CLASSES);
     misc[0] = cv.take<uint32_t>(ns + 1);  // stream first blocks
     misc[1] = cv.take<uint32_t>(ns + 1);  // stream CRCs
     r.L = cv.take<uint8_t>(lsum + 64);
@@ -1573,11 +1619,6 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   void* ws;
   if ((rc = get_ws(ctx, nullptr, 0, need, st, &ws))) return rc;
   carve((char*)ws, d, misc);
-  std::vector<uint32_t> order(nb);
-  for (uint32_t b = 0; b < nb; b++) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-    return blocks[x].end - blocks[x].start > blocks[y].end - blocks[y].start;
-  });
   if ((rc = upload(ctx,
                    {{(void*)d.blks, blocks.data(), nb * sizeof(DecBlk)},
                     {(void*)d.order, order.data(), nb * 4},
@@ -1590,13 +1631,63 @@ int decompress(bzg_ctx* ctx, const uint8_t* d_in, uint64_t n_bytes, uint8_t* d_o
   d.nb = nb;
   d.out = d_out;
   d.err = ctx->status;
-  d.walk_total = wt;
-  d.rle_total = rt;
-  d.ch_total = ct;
-  d.fl_total = ft;
   d.out_cap = out_cap;
   d.out_bytes = d_out_bytes;
-  HIPX(dec_run(d, st));
+  // the classes' runs: each its own range of every planned array
+  DecRun dc[DEC_CLASSES];
+  {
+    uint32_t lo = 0;
+    uint64_t w0 = 0, r0 = 0, c0 = 0, f0 = 0;
+    for (uint32_t k = 0; k < ncls; k++) {
+      DecRun& r = dc[k];
+      r = d;
+      r.nb = cls[k].nb;
+      r.order = d.order + cls[k].first;
+      r.plan_cnt = d.plan_cnt + cls[k].first;
+      r.ch0 = d.ch0 + lo;  // offset arrays: nb + 1 entries per class
+      r.fl_off = d.fl_off + lo;
+      r.walk0 = d.walk0 + lo;
+      r.rle0 = d.rle0 + lo;
+      r.cs = d.cs + c0;
+      r.ce = d.ce + c0;
+      r.clen = d.clen + c0;
+      r.coff = d.coff + c0;
+      r.fl_cnt = d.fl_cnt + f0 * 256;
+      r.fl_owner = d.fl_owner + f0;
+      r.nxt = d.nxt + w0;
+      r.steps = d.steps + w0;
+      r.pos = d.pos + w0;
+      r.summ = d.summ + r0 * 5;
+      r.seg_in = d.seg_in + r0;
+      r.seg_off = d.seg_off + r0;
+      r.walk_total = cls[k].wt;
+      r.rle_total = cls[k].rt;
+      r.ch_total = cls[k].ct;
+      r.fl_total = cls[k].ft;
+      lo += cls[k].nb + 1;
+      w0 += cls[k].wt;
+      r0 += cls[k].rt;
+      c0 += cls[k].ct;
+      f0 += cls[k].ft;
+    }
+  }
+  // the longer classes on the side streams (forked after this call's
+  // uploads), the shortest on the call's stream, joined before the offsets
+  if (ncls > 1 && !ctx->dec_fork) {
+    for (hipStream_t& q : ctx->dec_side) HIPX(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&ctx->dec_fork, hipEventDisableTiming));
+    for (hipEvent_t& e : ctx->dec_join) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  if (ncls > 1) HIPX(hipEventRecord(ctx->dec_fork, st));
+  for (uint32_t k = 0; k + 1 < ncls; k++) {
+    HIPX(hipStreamWaitEvent(ctx->dec_side[k], ctx->dec_fork, 0));
+    HIPX(dec_run(dc[k], ctx->dec_side[k]));
+    HIPX(hipEventRecord(ctx->dec_join[k], ctx->dec_side[k]));
+  }
+  HIPX(dec_run(dc[ncls - 1], st));
+  for (uint32_t k = 0; k + 1 < ncls; k++) HIPX(hipStreamWaitEvent(st, ctx->dec_join[k], 0));
+  HIPX(dec_offsets(d, nb, st));
+  for (uint32_t k = 0; k < ncls; k++) HIPX(dec_output(dc[k], st));
   // block CRCs of the output (the compressor's tile CRC and its combination)
   HIPX(plan_slot_tiles(d.out_off, nb, misc[2], misc[3], st));
   {

@@ -621,7 +621,8 @@ __device__ __forceinline__ uint32_t item_start(const uint16_t* __restrict__ S, u
 struct MtfChunk {
   uint32_t b, c;
 };
-__device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, uint32_t nb, uint64_t j) {
+__device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, uint32_t nb, uint64_t j,
+                                              const uint32_t* __restrict__ bl) {
   MtfChunk k;
   uint32_t lo = 0, hi = nb;  // ch0[lo] <= j < ch0[hi]
   while (hi - lo > 1) {
@@ -629,17 +630,17 @@ __device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, 
     if (ch0[mid] <= j) lo = mid;
     else hi = mid;
   }
-  k.b = lo;
+  k.b = bl[lo];
   k.c = (uint32_t)(j - ch0[lo]);
   return k;
 }
 
 __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
+                               uint32_t nb, const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
                                uint8_t* __restrict__ T,
                                uint32_t* __restrict__ cs, uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                uint32_t* __restrict__ err) {
-  const MtfChunk k = mtf_chunk(ch0, nb, j);
+  const MtfChunk k = mtf_chunk(ch0, nb, j, bl);
   const uint32_t n = n_syms[k.b];
   if ((uint64_t)k.c * MTF_CH >= n) return;
   const DecBlk B = blks[k.b];
@@ -695,31 +696,32 @@ __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 // and the chunks' starting lists in the next as many.
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_perm(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
-                                                           uint32_t* __restrict__ FL,
+                                                           const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL,
                                                            const uint32_t* __restrict__ n_syms,
                                                            uint8_t* __restrict__ T, uint32_t* __restrict__ cs,
                                                            uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                                            uint32_t* __restrict__ err) {
   const uint64_t total = ch0[nb];
   for (uint64_t j = blockIdx.x; j < total; j += gridDim.x)
-    mtf_perm_chunk(j, blks, ch0, nb, FL, n_syms, T, cs, ce, clen, err);
+    mtf_perm_chunk(j, blks, ch0, nb, bl, FL, n_syms, T, cs, ce, clen, err);
 }
 // Per block (one wave): each chunk's starting list and output offset, by
 // composing the chunk permutations in order from the block's first list;
 // then the block's length and its checks (at least one byte, origPtr inside).
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0,
+                                                           const uint32_t* __restrict__ bl,
                                                            const uint32_t* __restrict__ n_syms,
                                                            const uint8_t* __restrict__ mtf0, uint8_t* __restrict__ T,
                                                            const uint32_t* __restrict__ clen,
                                                            uint32_t* __restrict__ coff, const uint32_t* __restrict__ orig,
                                                            uint32_t* __restrict__ n_rows, uint32_t* __restrict__ err) {
   __shared__ __align__(4) uint8_t lst[256];
-  const uint32_t b = blockIdx.x, ln = lane();
+  const uint32_t bi = blockIdx.x, b = bl[bi], ln = lane();
   const DecBlk B = blks[b];
   const uint32_t n = n_syms[b];
   const uint32_t nch = (n + MTF_CH - 1) / MTF_CH, slots = B.cap / MTF_CH + 1;
-  const uint64_t j0 = ch0[b];
+  const uint64_t j0 = ch0[bi];
   uint8_t* Tb = T + B.l_off;
   ((uint32_t*)lst)[ln] = ((const uint32_t*)(mtf0 + (size_t)b * 256))[ln];
   __syncthreads();
@@ -760,12 +762,12 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restr
 // offset (a scan of the counts), and writes the bytes (literals one per
 // lane, runs by their last digit's lane, long runs by the whole wave).
 __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
+                               uint32_t nb, const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
                                const uint8_t* __restrict__ T,
                                const uint32_t* __restrict__ cs, const uint32_t* __restrict__ ce,
                                const uint32_t* __restrict__ coff, const uint32_t* __restrict__ n_rows,
                                uint8_t* __restrict__ L, uint8_t* lst) {
-  const MtfChunk k = mtf_chunk(ch0, nb, j);
+  const MtfChunk k = mtf_chunk(ch0, nb, j, bl);
   const uint32_t n = n_syms[k.b], rows = n_rows[k.b];
   if ((uint64_t)k.c * MTF_CH >= n || rows == 0) return;  // past the symbols, or a bad block
   const DecBlk B = blks[k.b];
@@ -833,7 +835,7 @@ __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, cons
 
 __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restrict__ blks,
                                                            const uint64_t* __restrict__ ch0, uint32_t nb,
-                                                           uint32_t* __restrict__ FL,
+                                                           const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL,
                                                            const uint32_t* __restrict__ n_syms,
                                                            const uint8_t* __restrict__ T,
                                                            const uint32_t* __restrict__ cs,
@@ -844,7 +846,7 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_emit(const DecBlk* __restr
   __shared__ __align__(4) uint8_t lst[256];
   const uint64_t total = ch0[nb];
   for (uint64_t j = blockIdx.x; j < total; j += gridDim.x) {
-    mtf_emit_chunk(j, blks, ch0, nb, FL, n_syms, T, cs, ce, coff, n_rows, L, lst);
+    mtf_emit_chunk(j, blks, ch0, nb, bl, FL, n_syms, T, cs, ce, coff, n_rows, L, lst);
     __syncthreads();
   }
 }
@@ -905,14 +907,14 @@ __device__ __forceinline__ void fl_count(const uint8_t* __restrict__ Lb, uint32_
 }
 
 __global__ __launch_bounds__(NT) void k_dec_fl_count(const DecBlk* __restrict__ blks, uint32_t nb,
-                                                     const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ bl, const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ owner, const uint8_t* __restrict__ L,
                                                      const uint32_t* __restrict__ n_rows, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t h[FL_NW][256];
   const uint32_t tid = threadIdx.x, w = tid / BZG_WAVE;
   const uint64_t total = off[nb];
   for (uint64_t j = blockIdx.x; j < total; j += gridDim.x) {
-    const uint32_t b = owner[j], c = (uint32_t)(j - off[b]), n = n_rows[b];
+    const uint32_t bi = owner[j], b = bl[bi], c = (uint32_t)(j - off[bi]), n = n_rows[b];
     for (uint32_t q = 0; q < FL_NW; q++) h[q][tid] = 0;
     __syncthreads();
     const uint32_t lo = c * FL_CH, hi = min(n, lo + FL_CH);
@@ -944,7 +946,7 @@ __global__ __launch_bounds__(NT) void k_dec_fl_scan(const uint64_t* __restrict__
 }
 
 __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, uint32_t nb,
-                                               const uint64_t* __restrict__ off, const uint32_t* __restrict__ owner,
+                                               const uint32_t* __restrict__ bl, const uint64_t* __restrict__ off, const uint32_t* __restrict__ owner,
                                                const uint8_t* __restrict__ L, const uint32_t* __restrict__ n_rows,
                                                const uint32_t* __restrict__ cnt, uint32_t* __restrict__ FL) {
   __shared__ uint32_t wb[FL_NW][256];  // per wave: the next row of each byte
@@ -952,7 +954,7 @@ __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, 
   const uint32_t tid = threadIdx.x, w = tid / BZG_WAVE, ln = lane();
   const uint64_t total = off[nb];
   for (uint64_t j = blockIdx.x; j < total; j += gridDim.x) {
-    const uint32_t b = owner[j], c = (uint32_t)(j - off[b]), n = n_rows[b];
+    const uint32_t bi = owner[j], b = bl[bi], c = (uint32_t)(j - off[bi]), n = n_rows[b];
     const uint8_t* Lb = L + blks[b].l_off;
     uint32_t* F = FL + blks[b].l_off;
     const uint32_t lo = min(n, c * FL_CH + w * FL_SUB), hi = min(n, lo + FL_SUB);
@@ -1021,13 +1023,14 @@ constexpr uint32_t UNVISITED = 0xFFFFFFFFu;
 // Walker per sampled row: follows FL until the next sampled row; records
 // the steps and which sample it reached.
 __device__ __forceinline__ void walk_item(uint64_t j, const DecBlk* __restrict__ blks,
-                                          const uint64_t* __restrict__ s0, uint32_t nb, uint64_t total,
+                                          const uint64_t* __restrict__ s0, uint32_t nb,
+                                          const uint32_t* __restrict__ bl, uint64_t total,
                                           const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ origs,
                                           const uint32_t* __restrict__ FL, uint32_t* __restrict__ nxt,
                                           uint32_t* __restrict__ steps, uint32_t* __restrict__ pos) {
   if (j >= total) return;
-  const uint32_t b = owner_of_wg(s0, nb, j);
-  const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b];
+  const uint32_t bi = owner_of_wg(s0, nb, j), b = bl[bi];
+  const uint32_t s = (uint32_t)(j - s0[bi]), n = n_rows[b], orig = origs[b];
   pos[j] = UNVISITED;
   if (n == 0 || s >= samples_of(n, orig)) return;
   const uint32_t* F = FL + blks[b].l_off;
@@ -1042,13 +1045,14 @@ __device__ __forceinline__ void walk_item(uint64_t j, const DecBlk* __restrict__
 // Walkers in tiles of NT, persistent; each XCD walks a contiguous range of
 // walkers, so a block's map is read through one L2.
 __global__ __launch_bounds__(NT) void k_dec_walk(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
-                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 uint32_t nb, const uint32_t* __restrict__ bl,
+                                                 const uint32_t* __restrict__ n_rows,
                                                  const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
                                                  uint32_t* __restrict__ nxt, uint32_t* __restrict__ steps,
                                                  uint32_t* __restrict__ pos) {
   const uint64_t total = s0[nb];
   for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
-    walk_item((uint64_t)it.t * NT + threadIdx.x, blks, s0, nb, total, n_rows, origs, FL, nxt, steps, pos);
+    walk_item((uint64_t)it.t * NT + threadIdx.x, blks, s0, nb, bl, total, n_rows, origs, FL, nxt, steps, pos);
 }
 
 // Per block: the chain of samples from origPtr gives every walker on it its
@@ -1064,13 +1068,14 @@ constexpr uint32_t CHAIN_CAP = 900000 / WALK_STRIDE + 3;  // samples of the larg
 constexpr uint32_t CHAIN_PER = (CHAIN_CAP + CHAIN_NT - 1) / CHAIN_NT;
 constexpr uint32_t CHAIN_BIG = 0x40000000u;  // a count past any block (two of them sum without wrapping)
 __global__ __launch_bounds__(CHAIN_NT) void k_dec_chain(const uint64_t* __restrict__ s0, uint32_t nb,
+                                                        const uint32_t* __restrict__ bl,
                                                         const uint32_t* __restrict__ n_rows,
                                                         const uint32_t* __restrict__ origs,
                                                         const uint32_t* __restrict__ nxt,
                                                         const uint32_t* __restrict__ steps, uint32_t* __restrict__ pos,
                                                         uint32_t* __restrict__ period, uint32_t* __restrict__ err) {
   __shared__ uint32_t succ[CHAIN_CAP], cnt[CHAIN_CAP];
-  const uint32_t b = blockIdx.x, tid = threadIdx.x;
+  const uint32_t bi = blockIdx.x, b = bl[bi], tid = threadIdx.x;
   const uint32_t n = n_rows[b], orig = origs[b];
   if (n == 0) {
     if (tid == 0) period[b] = 0;
@@ -1084,7 +1089,7 @@ __global__ __launch_bounds__(CHAIN_NT) void k_dec_chain(const uint64_t* __restri
     }
     return;
   }
-  const uint64_t base = s0[b];
+  const uint64_t base = s0[bi];
   const uint32_t cut = ns;  // the node after the chain's last sample
   for (uint32_t i = tid; i <= ns; i += CHAIN_NT) {
     if (i == cut) {
@@ -1134,7 +1139,8 @@ __global__ __launch_bounds__(CHAIN_NT) void k_dec_chain(const uint64_t* __restri
 
 // Walkers on the chain write their pieces of the text (the RLE1 bytes).
 __device__ __forceinline__ void emit_item(uint64_t j, const DecBlk* __restrict__ blks,
-                                          const uint64_t* __restrict__ s0, uint32_t nb, uint64_t total,
+                                          const uint64_t* __restrict__ s0, uint32_t nb,
+                                          const uint32_t* __restrict__ bl, uint64_t total,
                                           const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ origs,
                                           const uint32_t* __restrict__ FL, const uint32_t* __restrict__ steps,
                                           const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
@@ -1142,8 +1148,8 @@ __device__ __forceinline__ void emit_item(uint64_t j, const DecBlk* __restrict__
   if (j >= total) return;
   const uint32_t p0 = pos[j];
   if (p0 == UNVISITED) return;
-  const uint32_t b = owner_of_wg(s0, nb, j);
-  const uint32_t s = (uint32_t)(j - s0[b]), n = n_rows[b], orig = origs[b], per = period[b];
+  const uint32_t bi = owner_of_wg(s0, nb, j), b = bl[bi];
+  const uint32_t s = (uint32_t)(j - s0[bi]), n = n_rows[b], orig = origs[b], per = period[b];
   if (per == 0 || p0 >= per) return;
   const uint64_t o = blks[b].l_off;
   const uint32_t* F = FL + o;
@@ -1177,21 +1183,22 @@ __device__ __forceinline__ void emit_item(uint64_t j, const DecBlk* __restrict__
 
 // The walkers as in k_dec_walk.
 __global__ __launch_bounds__(NT) void k_dec_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ s0,
-                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 uint32_t nb, const uint32_t* __restrict__ bl,
+                                                 const uint32_t* __restrict__ n_rows,
                                                  const uint32_t* __restrict__ origs, const uint32_t* __restrict__ FL,
                                                  const uint32_t* __restrict__ steps,
                                                  const uint32_t* __restrict__ pos, const uint32_t* __restrict__ period,
                                                  uint8_t* __restrict__ T) {
   const uint64_t total = s0[nb];
   for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
-    emit_item((uint64_t)it.t * NT + threadIdx.x, blks, s0, nb, total, n_rows, origs, FL, steps, pos, period, T);
+    emit_item((uint64_t)it.t * NT + threadIdx.x, blks, s0, nb, bl, total, n_rows, origs, FL, steps, pos, period, T);
 }
 
 // A block that repeats a string of the period: the rest is copies.
-__global__ __launch_bounds__(NT) void k_dec_repeat(const DecBlk* __restrict__ blks,
+__global__ __launch_bounds__(NT) void k_dec_repeat(const DecBlk* __restrict__ blks, const uint32_t* __restrict__ bl,
                                                    const uint32_t* __restrict__ n_rows,
                                                    const uint32_t* __restrict__ period, uint8_t* __restrict__ T) {
-  const uint32_t b = blockIdx.x, n = n_rows[b], p = period[b];
+  const uint32_t b = bl[blockIdx.x], n = n_rows[b], p = period[b];
   if (p == 0 || p >= n) return;
   uint8_t* Tb = T + blks[b].l_off;
   for (uint32_t i = p + threadIdx.x; i < n; i += NT) Tb[i] = Tb[i % p];
@@ -1220,13 +1227,14 @@ __device__ __forceinline__ uint32_t rle_step(uint32_t& st, uint32_t& last, uint3
 // = the segment's first byte for s = 1..3): output bytes, outgoing state and
 // last byte, packed as len | st << 32 | last << 40.
 __device__ __forceinline__ void rle_summ_item(uint64_t j, const DecBlk* __restrict__ blks,
-                                              const uint64_t* __restrict__ g0, uint32_t nb, uint64_t total,
+                                              const uint64_t* __restrict__ g0, uint32_t nb,
+                                              const uint32_t* __restrict__ bl, uint64_t total,
                                               const uint32_t* __restrict__ n_rows,
                                               const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
                                               uint64_t* __restrict__ summ) {
   if (j >= total) return;
-  const uint32_t b = owner_of_wg(g0, nb, j);
-  const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
+  const uint32_t bi = owner_of_wg(g0, nb, j), b = bl[bi];
+  const uint32_t g = (uint32_t)(j - g0[bi]), n = period[b] ? n_rows[b] : 0u;
   if ((uint64_t)g * RLE_SEG >= n) return;
   const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
   const uint32_t m = min(RLE_SEG, n - g * RLE_SEG);
@@ -1259,12 +1267,13 @@ __device__ __forceinline__ uint32_t map_then(uint32_t f, uint32_t g) {
 
 // Segments in tiles of NT, persistent.
 __global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
-                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 uint32_t nb, const uint32_t* __restrict__ bl,
+                                                 const uint32_t* __restrict__ n_rows,
                                                  const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
                                                  uint64_t* __restrict__ summ) {
   const uint64_t total = g0[nb];
   for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
-    rle_summ_item((uint64_t)it.t * NT + threadIdx.x, blks, g0, nb, total, n_rows, period, T, summ);
+    rle_summ_item((uint64_t)it.t * NT + threadIdx.x, blks, g0, nb, bl, total, n_rows, period, T, summ);
 }
 
 // Per block (one workgroup): each segment's incoming state and last byte and
@@ -1276,16 +1285,17 @@ __global__ __launch_bounds__(NT) void k_rle_summ(const DecBlk* __restrict__ blks
 constexpr uint32_t KS = 4;
 constexpr uint32_t NWV = NT / BZG_WAVE;
 __global__ __launch_bounds__(NT) void k_rle_chain(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
-                                                  uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                  uint32_t nb, const uint32_t* __restrict__ bl,
+                                                  const uint32_t* __restrict__ n_rows,
                                                   const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
                                                   const uint64_t* __restrict__ summ, uint32_t* __restrict__ seg_in,
                                                   uint32_t* __restrict__ seg_off, uint32_t* __restrict__ out_len) {
   __shared__ uint32_t wmap[NWV], wsum[NWV + 1], lastlo[NT];
-  const uint32_t b = blockIdx.x, tid = threadIdx.x, w = tid / BZG_WAVE, ln = lane();
+  const uint32_t bi = blockIdx.x, b = bl[bi], tid = threadIdx.x, w = tid / BZG_WAVE, ln = lane();
   const uint32_t n = period[b] ? n_rows[b] : 0u;
   const uint32_t ns = (n + RLE_SEG - 1) / RLE_SEG;
   const uint8_t* Tb = T + blks[b].l_off;
-  const uint64_t base = g0[b];
+  const uint64_t base = g0[bi];
   uint32_t st0 = 0, last0 = 0, off0 = 0;  // entering the step (workgroup-uniform)
   for (uint32_t t0 = 0; t0 < ns; t0 += NT * KS) {
     const uint32_t gs = t0 + tid * KS;
@@ -1389,15 +1399,16 @@ __global__ __launch_bounds__(1024) void k_rle_offsets(const uint32_t* __restrict
 
 // Every segment expands its bytes at its offset (Figure 2's scatter).
 __device__ __forceinline__ void rle_emit_item(uint64_t j, const DecBlk* __restrict__ blks,
-                                              const uint64_t* __restrict__ g0, uint32_t nb, uint64_t total,
+                                              const uint64_t* __restrict__ g0, uint32_t nb,
+                                              const uint32_t* __restrict__ bl, uint64_t total,
                                               const uint32_t* __restrict__ n_rows,
                                               const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
                                               const uint32_t* __restrict__ seg_in,
                                               const uint32_t* __restrict__ seg_off,
                                               const uint64_t* __restrict__ out_off, uint8_t* __restrict__ out) {
   if (j >= total) return;
-  const uint32_t b = owner_of_wg(g0, nb, j);
-  const uint32_t g = (uint32_t)(j - g0[b]), n = period[b] ? n_rows[b] : 0u;
+  const uint32_t bi = owner_of_wg(g0, nb, j), b = bl[bi];
+  const uint32_t g = (uint32_t)(j - g0[bi]), n = period[b] ? n_rows[b] : 0u;
   if ((uint64_t)g * RLE_SEG >= n) return;
   const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
   const uint32_t m = min(RLE_SEG, n - g * RLE_SEG);
@@ -1418,7 +1429,8 @@ __device__ __forceinline__ void rle_emit_item(uint64_t j, const DecBlk* __restri
 
 // Segments as in k_rle_summ (nothing when the output did not fit).
 __global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks, const uint64_t* __restrict__ g0,
-                                                 uint32_t nb, const uint32_t* __restrict__ n_rows,
+                                                 uint32_t nb, const uint32_t* __restrict__ bl,
+                                                 const uint32_t* __restrict__ n_rows,
                                                  const uint32_t* __restrict__ period, const uint8_t* __restrict__ T,
                                                  const uint32_t* __restrict__ seg_in,
                                                  const uint32_t* __restrict__ seg_off,
@@ -1427,7 +1439,7 @@ __global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks
   if (*skip) return;
   const uint64_t total = g0[nb];
   for (TileLoop it = tile_loop((uint32_t)((total + NT - 1) / NT)); it.t < it.end; it.t += it.step)
-    rle_emit_item((uint64_t)it.t * NT + threadIdx.x, blks, g0, nb, total, n_rows, period, T, seg_in, seg_off,
+    rle_emit_item((uint64_t)it.t * NT + threadIdx.x, blks, g0, nb, bl, total, n_rows, period, T, seg_in, seg_off,
                   out_off, out);
 }
 
@@ -1435,11 +1447,12 @@ __global__ __launch_bounds__(NT) void k_rle_emit(const DecBlk* __restrict__ blks
 // lengths are known (their offsets are then a scan, k_scan_counts).  None
 // exceeds the bound the host sized its arrays for from the block's capacity.
 enum DecPlan : int { PLAN_MTF = 0, PLAN_FL = 1, PLAN_WALK = 2, PLAN_RLE = 3 };
-__global__ void k_dec_plan(int kind, uint32_t nb, const uint32_t* __restrict__ n_syms,
+__global__ void k_dec_plan(int kind, uint32_t nb, const uint32_t* __restrict__ bl, const uint32_t* __restrict__ n_syms,
                            const uint32_t* __restrict__ n_rows, const uint32_t* __restrict__ origs,
                            const uint32_t* __restrict__ period, uint32_t* __restrict__ cnt) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+  const uint32_t bi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bi >= nb) return;
+  const uint32_t b = bl[bi];
   uint32_t c;
   if (kind == PLAN_MTF) {
     c = (n_syms[b] + MTF_CH - 1) / MTF_CH;
@@ -1451,7 +1464,7 @@ __global__ void k_dec_plan(int kind, uint32_t nb, const uint32_t* __restrict__ n
     const uint32_t n = period[b] ? n_rows[b] : 0u;
     c = (n + RLE_SEG - 1) / RLE_SEG;
   }
-  cnt[b] = c;
+  cnt[bi] = c;
 }
 
 // Block CRCs against the stored ones, and every stream's combined CRC.
@@ -1495,8 +1508,8 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   const uint32_t nb = d.nb;
   // per-block work items of a kind, from the lengths decoded so far
   auto plan = [&](int kind, uint64_t* off) {
-    hipLaunchKernelGGL(k_dec_plan, dim3((nb + 255) / 256), dim3(256), 0, st, kind, nb, d.n_syms, d.n_rows, d.orig,
-                       d.period, d.plan_cnt);
+    hipLaunchKernelGGL(k_dec_plan, dim3((nb + 255) / 256), dim3(256), 0, st, kind, nb, d.order, d.n_syms, d.n_rows,
+                       d.orig, d.period, d.plan_cnt);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, d.plan_cnt, nb, off);
   };
   // one tile of NT items per workgroup, over the items' bound: the items
@@ -1513,12 +1526,12 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   {
     ProfScope ps("dec_mtf", st, 0.0);
     plan(PLAN_MTF, d.ch0);
-    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.FL, d.n_syms, d.T,
-                       d.cs, d.ce, d.clen, d.err);
-    hipLaunchKernelGGL(k_dec_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, d.n_syms, d.mtf0, d.T,
+    hipLaunchKernelGGL(k_dec_mtf_perm, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.order, d.FL, d.n_syms,
+                       d.T, d.cs, d.ce, d.clen, d.err);
+    hipLaunchKernelGGL(k_dec_mtf_scan, dim3(nb), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, d.order, d.n_syms, d.mtf0, d.T,
                        d.clen, d.coff, d.orig, d.n_rows, d.err);
-    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.FL, d.n_syms, d.T,
-                       d.cs, d.ce, d.coff, d.n_rows, d.L);
+    hipLaunchKernelGGL(k_dec_mtf_emit, dim3(gc), dim3(BZG_WAVE), 0, st, d.blks, d.ch0, nb, d.order, d.FL, d.n_syms,
+                       d.T, d.cs, d.ce, d.coff, d.n_rows, d.L);
   }
   {
     ProfScope ps("dec_fl", st, 0.0);
@@ -1526,10 +1539,10 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
     hipLaunchKernelGGL(k_dec_fl_owner, dim3((nb + 255) / 256), dim3(256), 0, st, d.fl_off, nb, d.fl_owner);
     const uint32_t gf = std::min<uint32_t>((uint32_t)std::max<uint64_t>(d.fl_total, 1),
                                            resident_grid((const void*)k_dec_fl, NT));
-    hipLaunchKernelGGL(k_dec_fl_count, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.fl_off, d.fl_owner, d.L, d.n_rows,
+    hipLaunchKernelGGL(k_dec_fl_count, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.order, d.fl_off, d.fl_owner, d.L, d.n_rows,
                        d.fl_cnt);
     hipLaunchKernelGGL(k_dec_fl_scan, dim3(nb), dim3(NT), 0, st, d.fl_off, d.fl_cnt);
-    hipLaunchKernelGGL(k_dec_fl, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.fl_off, d.fl_owner, d.L, d.n_rows,
+    hipLaunchKernelGGL(k_dec_fl, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.order, d.fl_off, d.fl_owner, d.L, d.n_rows,
                        d.fl_cnt, d.FL);
   }
   const uint32_t gw = grid(d.walk_total);
@@ -1537,30 +1550,44 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   {
     ProfScope ps("dec_walk", st, 0.0);
     plan(PLAN_WALK, d.walk0);
-    hipLaunchKernelGGL(k_dec_walk, dim3(gw), dim3(NT), 0, st, d.blks, d.walk0, nb, d.n_rows, d.orig, d.FL, d.nxt,
+    hipLaunchKernelGGL(k_dec_walk, dim3(gw), dim3(NT), 0, st, d.blks, d.walk0, nb, d.order, d.n_rows, d.orig, d.FL, d.nxt,
                        d.steps, d.pos);
   }
-  hipLaunchKernelGGL(k_dec_chain, dim3(nb), dim3(CHAIN_NT), 0, st, d.walk0, nb, d.n_rows, d.orig, d.nxt, d.steps,
+  hipLaunchKernelGGL(k_dec_chain, dim3(nb), dim3(CHAIN_NT), 0, st, d.walk0, nb, d.order, d.n_rows, d.orig, d.nxt, d.steps,
                      d.pos, d.period, d.err);
   {
     ProfScope ps("dec_emit", st, 0.0);
-    hipLaunchKernelGGL(k_dec_emit, dim3(ge), dim3(NT), 0, st, d.blks, d.walk0, nb, d.n_rows, d.orig, d.FL, d.steps,
+    hipLaunchKernelGGL(k_dec_emit, dim3(ge), dim3(NT), 0, st, d.blks, d.walk0, nb, d.order, d.n_rows, d.orig, d.FL, d.steps,
                        d.pos, d.period, d.T);
   }
-  hipLaunchKernelGGL(k_dec_repeat, dim3(nb), dim3(NT), 0, st, d.blks, d.n_rows, d.period, d.T);
+  hipLaunchKernelGGL(k_dec_repeat, dim3(nb), dim3(NT), 0, st, d.blks, d.order, d.n_rows, d.period, d.T);
   const uint32_t gs = grid(d.rle_total);
-  const uint32_t gr = grid(d.rle_total);
   {
     ProfScope ps("dec_rle", st, 0.0);
     plan(PLAN_RLE, d.rle0);
-    hipLaunchKernelGGL(k_rle_summ, dim3(gs), dim3(NT), 0, st, d.blks, d.rle0, nb, d.n_rows, d.period, d.T, d.summ);
-    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb, d.n_rows, d.period, d.T, d.summ,
+    hipLaunchKernelGGL(k_rle_summ, dim3(gs), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T, d.summ);
+    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T, d.summ,
                        d.seg_in, d.seg_off, d.out_len);
-    hipLaunchKernelGGL(k_rle_offsets, dim3(1), dim3(1024), 0, st, d.out_len, nb, d.out_cap, d.out_off, d.out_bytes,
-                       d.skip, d.err);
-    hipLaunchKernelGGL(k_rle_emit, dim3(gr), dim3(NT), 0, st, d.blks, d.rle0, nb, d.n_rows, d.period, d.T,
-                       d.seg_in, d.seg_off, d.out_off, d.skip, d.out);
   }
+  return hipGetLastError();
+}
+
+// The output offsets of all blocks, in stream order (once every class has
+// its blocks' lengths).
+hipError_t dec_offsets(const DecRun& d, uint32_t nb, hipStream_t st) {
+  ProfScope ps("dec_rle", st, 0.0);
+  hipLaunchKernelGGL(k_rle_offsets, dim3(1), dim3(1024), 0, st, d.out_len, nb, d.out_cap, d.out_off, d.out_bytes,
+                     d.skip, d.err);
+  return hipGetLastError();
+}
+
+// A class's output: its run-length segments expanded at their offsets.
+hipError_t dec_output(const DecRun& d, hipStream_t st) {
+  const uint32_t nb = d.nb;
+  const uint32_t gr = persist_grid((d.rle_total + NT - 1) / NT, ONE_TILE_EACH);
+  ProfScope ps("dec_rle", st, 0.0);
+  hipLaunchKernelGGL(k_rle_emit, dim3(gr), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T,
+                     d.seg_in, d.seg_off, d.out_off, d.skip, d.out);
   return hipGetLastError();
 }
 

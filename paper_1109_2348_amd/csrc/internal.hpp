@@ -278,12 +278,17 @@ struct DecBlk {
   uint32_t cap, pad;
 };
 // The arrays of one call, carved by the host.
+// Decompression of a batch of at least DEC_SPLIT_MIN blocks decodes it in
+// up to DEC_CLASSES classes of block length, each on a stream of its own.
+constexpr uint32_t DEC_SPLIT_MIN = 64;
+constexpr uint32_t DEC_CLASSES = 2;
+constexpr int DEC_CUT_SHIFT[DEC_CLASSES - 1] = {2};  // class bounds: the longest block's bits >> these
 struct DecRun {
   const uint8_t* in;
   uint64_t n_in;
   uint32_t nb;
   const DecBlk* blks;
-  const uint32_t* order;  // blocks by decreasing bit length (launch order)
+  const uint32_t* order;  // the blocks decoded (global ids), by decreasing bit length
   uint8_t *L, *T, *out;
   uint32_t *n_rows, *orig, *crc_want, *err, *FL;
   uint32_t* n_syms;       // per block: Huffman symbols before end-of-block
@@ -314,7 +319,11 @@ uint32_t dec_walk_slots(uint32_t cap);
 uint32_t dec_rle_slots(uint32_t cap);
 uint32_t dec_mtf_chunks(uint32_t cap);
 uint32_t dec_fl_chunks(uint32_t cap);
+// A class of blocks (d.order, d.nb of them) decoded through the run-length
+// chain; then the offsets of every block; then each class's output.
 hipError_t dec_run(const DecRun& d, hipStream_t st);
+hipError_t dec_offsets(const DecRun& d, uint32_t nb, hipStream_t st);
+hipError_t dec_output(const DecRun& d, hipStream_t st);
 hipError_t dec_check(uint32_t nb, const uint32_t* crc_got, const uint32_t* crc_want, uint32_t n_streams,
                      const uint32_t* stream_b0, const uint32_t* stream_crc, const uint32_t* skip, uint32_t* err,
                      hipStream_t st);

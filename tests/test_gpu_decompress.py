@@ -127,3 +127,16 @@ def test_runs_across_chunk_and_step_boundaries(bz):
         assert _straddles(syms, 4096) and _straddles(syms, 64), "the block should exercise run carries"
     z = cref.compress(data, offs, 9, threads=16)
     _roundtrip(bz, z, data.tobytes(), "sparse 900 KB blocks with runs across chunks")
+
+
+def test_long_and_short_blocks_decoded_as_two_classes(bz):
+    # 96 blocks of log-uniform length 2 KB .. 300 KB: the long ones (a
+    # quarter of the longest block's bits or more) are decoded on a second
+    # stream, the rest on the call's, and every block's bytes land at its
+    # place in the output
+    b = W.config4(nb=96, lo=2000, hi=300_000, seed=91)
+    z = cref.compress(b.data, [int(o) for o in b.offsets], 9, threads=16)
+    _roundtrip(bz, z, b.data.tobytes(), "96 blocks of 2 KB .. 300 KB in two length classes")
+    # the same blocks as 96 streams of one block each, concatenated
+    parts = [cref.compress(b.data[int(b.offsets[k]):int(b.offsets[k + 1])], None, 9) for k in range(96)]
+    _roundtrip(bz, b"".join(bytes(p) for p in parts), b.data.tobytes(), "96 one-block streams")
