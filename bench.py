@@ -95,6 +95,26 @@ def _roofline(kern, steps, step_ms_total, config=None):
             "share_of_step": round(rec["ms"] / step_ms_total, 3) if step_ms_total > 0 else None}
 
 
+# The BWT sort's kernels by the library profiler's names: the LSD passes of
+# the first bytes, the per-round gathers, small-segment sorts, radix passes
+# and namings, and the tile-count scans between them.
+SORT_KERNELS = ("init_hist", "init_scatter", "rename_a", "rename_b", "gather", "small_sort", "radix_hist",
+                "radix_scatter", "sort_scan")
+
+
+def _sort_roofline(kern, steps):
+    """The sort kernels together: their algorithmic bytes over their time."""
+    rec = [kern[k] for k in SORT_KERNELS if k in kern]
+    if not rec:
+        return None
+    ms = sum(r["ms"] for r in rec) / steps
+    gb = sum(r["bytes"] for r in rec) / steps / 1e9
+    achieved = gb / (ms * 1e-3) if ms > 0 else 0.0
+    return {"kernels": list(SORT_KERNELS), "ms_per_step": round(ms, 3), "algorithmic_GB_per_step": round(gb, 2),
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+
 def _kernels(kern, steps):
     return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches": v["launches"] // steps,
                 "algorithmic_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
@@ -149,6 +169,7 @@ def _result(args, value, wall, step_ms, n_in, config, kern, cpu, per_block, extr
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": config,
         "p50_ms": round(float(np.percentile(step_ms, 50)), 3), "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
         "per_block": per_block, "roofline": _roofline(kern, args.steps, float(step_ms.sum()), args.config),
+        "sort_kernels": _sort_roofline(kern, args.steps),
         "cpu_baseline": cpu,
         "profiled_steps": args.steps,
         "kernels": _kernels(kern, args.steps),

@@ -1346,7 +1346,7 @@ static hipError_t radix_passes(BwtWork& w, uint32_t cap, const uint32_t* ntiles,
                          ntiles, cap);
     }
     {
-      ProfScope ps("scan", st, 0, ntiles, 8.0 * 256);
+      ProfScope ps("sort_scan", st, 0, ntiles, 8.0 * 256);
       hipError_t e = scan_lb_u32(w.hist, ntiles, cap, 256, w.state, err, gq, st);
       if (e != hipSuccess) return e;
     }
@@ -1412,7 +1412,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
                            p ? nullptr : text, init_tiles, icap);
       }
       {
-        ProfScope ps("scan", st, 0, init_tiles, 8.0 * 256);
+        ProfScope ps("sort_scan", st, 0, init_tiles, 8.0 * 256);
         BZG_TRY(scan_lb_u32(w.hist, init_tiles, icap, 256, w.state, err, Gsi, st));
       }
       // key and row in and out (pass 0: one text byte in per row)
@@ -1452,7 +1452,7 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     const uint32_t* small_rows = (const uint32_t*)&w.cnt[cc].segs_small + 1;   // high word
     const uint32_t* big_rows = (const uint32_t*)&w.cnt[cc].tiles_big + 1;      // high word
     {
-      ProfScope ps("scan", st, 0.0);
+      ProfScope ps("sort_scan", st, 0.0);
       hipLaunchKernelGGL(k_small_tiles, dim3(1), dim3(TS_NT), 0, st, w.bcnt[cur], d_off, nslot, w.tile_pre);
     }
     {

@@ -1,8 +1,14 @@
 // Decompression of bzip2 streams on the GPU: the decoding half the paper
 // discusses stage by stage --
 //   variable-length decoding (Sec. 3.4: code boundaries are only known
-//     serially; blocks are decoded in parallel, one wave each, with the
-//     RUNA/RUNB runs and the inverse move-to-front (Sec. 3.3) fused in);
+//     serially): one wave per block finds each group's 50 code starts at
+//     once by pointer doubling over the next 512 bits, the groups chained
+//     in order;
+//   the inverse move-to-front (Sec. 3.3) in parallel over chunks: a chunk's
+//     effect on list positions is found on the identity list, the chunks'
+//     permutations composed in order per block, and every symbol's byte
+//     taken from its chunk's starting list, with RUNA/RUNB run lengths as
+//     segmented sums;
 //   the inverse BWT started from many points (Sec. 3.1): walkers start at
 //     sampled rows of the last-to-first map, each stops at the next sampled
 //     row, a pass along the chain of samples places every walker's piece,
@@ -11,8 +17,11 @@
 //     output length and outgoing state for every incoming state; a scan
 //     gives each segment its state and output offset; then every segment
 //     expands its runs at its offset.
-// Blocks are found by a bit-parallel search for the block and end-of-stream
-// markers; the host reads back the marker list to lay the blocks out.
+// Blocks are found by a filtered search for the block and end-of-stream
+// markers; the host reads back the marker list to lay the blocks out.  The
+// work items of the later stages (chunks, walkers, segments) are planned on
+// the device from the decoded lengths; long blocks can be decoded as a class
+// of their own on a second stream.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -271,8 +280,8 @@ __device__ __forceinline__ uint8_t* blk_q(uint32_t* FL, const DecBlk& B) {
 }
 
 // One wave per block: header, symbol map, selectors, code tables, then
-// every Huffman code up to end-of-block (first-level table, then the
-// canonical limits).  Writes the block's symbols (RUNA/RUNB digits and
+// every Huffman code up to end-of-block, a group per step (first-level
+// table, then the canonical limits for longer codes).  Writes the block's symbols (RUNA/RUNB digits and
 // move-to-front positions + 1, uint16, at the start of the block's map range),
 // their count, the move-to-front list it starts from (the in-use bytes,
 // ascending), origPtr and the stored CRC.  The move-to-front and run
@@ -636,7 +645,8 @@ __device__ __forceinline__ MtfChunk mtf_chunk(const uint64_t* __restrict__ ch0, 
 }
 
 __device__ void mtf_perm_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
+                               uint32_t nb, const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL,
+                               const uint32_t* __restrict__ n_syms,
                                uint8_t* __restrict__ T,
                                uint32_t* __restrict__ cs, uint32_t* __restrict__ ce, uint32_t* __restrict__ clen,
                                uint32_t* __restrict__ err) {
@@ -714,7 +724,8 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restr
                                                            const uint32_t* __restrict__ n_syms,
                                                            const uint8_t* __restrict__ mtf0, uint8_t* __restrict__ T,
                                                            const uint32_t* __restrict__ clen,
-                                                           uint32_t* __restrict__ coff, const uint32_t* __restrict__ orig,
+                                                           uint32_t* __restrict__ coff,
+                                                           const uint32_t* __restrict__ orig,
                                                            uint32_t* __restrict__ n_rows, uint32_t* __restrict__ err) {
   __shared__ __align__(4) uint8_t lst[256];
   const uint32_t bi = blockIdx.x, b = bl[bi], ln = lane();
@@ -762,7 +773,8 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_mtf_scan(const DecBlk* __restr
 // offset (a scan of the counts), and writes the bytes (literals one per
 // lane, runs by their last digit's lane, long runs by the whole wave).
 __device__ void mtf_emit_chunk(uint64_t j, const DecBlk* __restrict__ blks, const uint64_t* __restrict__ ch0,
-                               uint32_t nb, const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL, const uint32_t* __restrict__ n_syms,
+                               uint32_t nb, const uint32_t* __restrict__ bl, uint32_t* __restrict__ FL,
+                               const uint32_t* __restrict__ n_syms,
                                const uint8_t* __restrict__ T,
                                const uint32_t* __restrict__ cs, const uint32_t* __restrict__ ce,
                                const uint32_t* __restrict__ coff, const uint32_t* __restrict__ n_rows,
@@ -946,7 +958,8 @@ __global__ __launch_bounds__(NT) void k_dec_fl_scan(const uint64_t* __restrict__
 }
 
 __global__ __launch_bounds__(NT) void k_dec_fl(const DecBlk* __restrict__ blks, uint32_t nb,
-                                               const uint32_t* __restrict__ bl, const uint64_t* __restrict__ off, const uint32_t* __restrict__ owner,
+                                               const uint32_t* __restrict__ bl, const uint64_t* __restrict__ off,
+                                               const uint32_t* __restrict__ owner,
                                                const uint8_t* __restrict__ L, const uint32_t* __restrict__ n_rows,
                                                const uint32_t* __restrict__ cnt, uint32_t* __restrict__ FL) {
   __shared__ uint32_t wb[FL_NW][256];  // per wave: the next row of each byte
@@ -1539,8 +1552,8 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
     hipLaunchKernelGGL(k_dec_fl_owner, dim3((nb + 255) / 256), dim3(256), 0, st, d.fl_off, nb, d.fl_owner);
     const uint32_t gf = std::min<uint32_t>((uint32_t)std::max<uint64_t>(d.fl_total, 1),
                                            resident_grid((const void*)k_dec_fl, NT));
-    hipLaunchKernelGGL(k_dec_fl_count, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.order, d.fl_off, d.fl_owner, d.L, d.n_rows,
-                       d.fl_cnt);
+    hipLaunchKernelGGL(k_dec_fl_count, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.order, d.fl_off, d.fl_owner, d.L,
+                       d.n_rows, d.fl_cnt);
     hipLaunchKernelGGL(k_dec_fl_scan, dim3(nb), dim3(NT), 0, st, d.fl_off, d.fl_cnt);
     hipLaunchKernelGGL(k_dec_fl, dim3(gf), dim3(NT), 0, st, d.blks, nb, d.order, d.fl_off, d.fl_owner, d.L, d.n_rows,
                        d.fl_cnt, d.FL);
@@ -1550,24 +1563,25 @@ hipError_t dec_run(const DecRun& d, hipStream_t st) {
   {
     ProfScope ps("dec_walk", st, 0.0);
     plan(PLAN_WALK, d.walk0);
-    hipLaunchKernelGGL(k_dec_walk, dim3(gw), dim3(NT), 0, st, d.blks, d.walk0, nb, d.order, d.n_rows, d.orig, d.FL, d.nxt,
-                       d.steps, d.pos);
+    hipLaunchKernelGGL(k_dec_walk, dim3(gw), dim3(NT), 0, st, d.blks, d.walk0, nb, d.order, d.n_rows, d.orig, d.FL,
+                       d.nxt, d.steps, d.pos);
   }
-  hipLaunchKernelGGL(k_dec_chain, dim3(nb), dim3(CHAIN_NT), 0, st, d.walk0, nb, d.order, d.n_rows, d.orig, d.nxt, d.steps,
-                     d.pos, d.period, d.err);
+  hipLaunchKernelGGL(k_dec_chain, dim3(nb), dim3(CHAIN_NT), 0, st, d.walk0, nb, d.order, d.n_rows, d.orig, d.nxt,
+                     d.steps, d.pos, d.period, d.err);
   {
     ProfScope ps("dec_emit", st, 0.0);
-    hipLaunchKernelGGL(k_dec_emit, dim3(ge), dim3(NT), 0, st, d.blks, d.walk0, nb, d.order, d.n_rows, d.orig, d.FL, d.steps,
-                       d.pos, d.period, d.T);
+    hipLaunchKernelGGL(k_dec_emit, dim3(ge), dim3(NT), 0, st, d.blks, d.walk0, nb, d.order, d.n_rows, d.orig, d.FL,
+                       d.steps, d.pos, d.period, d.T);
   }
   hipLaunchKernelGGL(k_dec_repeat, dim3(nb), dim3(NT), 0, st, d.blks, d.order, d.n_rows, d.period, d.T);
   const uint32_t gs = grid(d.rle_total);
   {
     ProfScope ps("dec_rle", st, 0.0);
     plan(PLAN_RLE, d.rle0);
-    hipLaunchKernelGGL(k_rle_summ, dim3(gs), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T, d.summ);
-    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T, d.summ,
-                       d.seg_in, d.seg_off, d.out_len);
+    hipLaunchKernelGGL(k_rle_summ, dim3(gs), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T,
+                       d.summ);
+    hipLaunchKernelGGL(k_rle_chain, dim3(nb), dim3(NT), 0, st, d.blks, d.rle0, nb, d.order, d.n_rows, d.period, d.T,
+                       d.summ, d.seg_in, d.seg_off, d.out_len);
   }
   return hipGetLastError();
 }
