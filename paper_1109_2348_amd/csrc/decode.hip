@@ -295,15 +295,30 @@ __global__ __launch_bounds__(BZG_WAVE) void k_dec_block(const uint8_t* __restric
                                                         uint32_t* __restrict__ out_crc, uint32_t* __restrict__ err) {
   __shared__ uint16_t lut[MAXG][1u << DEC_LUT_BITS];
   __shared__ uint16_t perm[MAXG][MAXA];
-  __shared__ int32_t limit[MAXG][DEC_MAXLEN + 2];
-  __shared__ uint32_t first[MAXG][DEC_MAXLEN + 2], start[MAXG][DEC_MAXLEN + 2];
-  __shared__ uint8_t lens[MAXG][MAXA];
   __shared__ __align__(4) uint8_t unseq[256];
-  __shared__ uint32_t srun[DEC_MAXLEN + 2];
   __shared__ int32_t lim20[MAXG][32];            // left-aligned limits, per length
   __shared__ int32_t sbase[MAXG][DEC_MAXLEN + 2];  // start - first code, per length
-  __shared__ uint32_t ring[2 * BZG_WAVE];           // two 64-dword windows of the stream
-  __shared__ __align__(16) uint32_t jt[2][JTAB];   // next-code-start maps (ping-pong)
+  // what only the table building uses shares its LDS with what only the
+  // symbol steps use (fewer bytes per workgroup, more workgroups per CU)
+  __shared__ union {
+    struct {
+      int32_t limit[MAXG][DEC_MAXLEN + 2];
+      uint32_t first[MAXG][DEC_MAXLEN + 2], start[MAXG][DEC_MAXLEN + 2];
+      uint8_t lens[MAXG][MAXA];
+      uint32_t srun[DEC_MAXLEN + 2];
+    } build;
+    struct {
+      uint32_t ring[2 * BZG_WAVE];                 // two 64-dword windows of the stream
+      __align__(16) uint32_t jt[2][JTAB];          // next-code-start maps (ping-pong)
+    } step;
+  } ls;
+  auto& limit = ls.build.limit;
+  auto& first = ls.build.first;
+  auto& start = ls.build.start;
+  auto& lens = ls.build.lens;
+  auto& srun = ls.build.srun;
+  auto& ring = ls.step.ring;
+  auto& jt = ls.step.jt;
   const uint32_t b = order[blockIdx.x];  // the longest blocks first
   const DecBlk B = blks[b];
   uint16_t* Sb = blk_syms(FL, B);
