@@ -1251,6 +1251,64 @@ __device__ __forceinline__ uint32_t rle_step(uint32_t& st, uint32_t& last, uint3
   return 1;
 }
 
+// A segment's RLE_SEG bytes as words, byte i in bits 8*(i%4) of word i/4.
+// Segments start 16-byte aligned (block ranges are multiples of 32 bytes)
+// and the text array is padded, so all RLE_SEG bytes are read, the ones past
+// the block's end unused.
+__device__ __forceinline__ void seg_words(const uint8_t* __restrict__ Tb, uint32_t (&xw)[RLE_SEG / 4]) {
+#pragma unroll
+  for (uint32_t q = 0; q < RLE_SEG / 16; q++) {
+    const uint4 v = ((const uint4*)Tb)[q];
+    xw[4 * q] = v.x;
+    xw[4 * q + 1] = v.y;
+    xw[4 * q + 2] = v.z;
+    xw[4 * q + 3] = v.w;
+  }
+}
+
+// Bytes written in order from `base` through a pending aligned word: a word
+// whose bytes are all this writer's is stored whole, the partial words at
+// either end byte by byte (their other bytes belong to the neighbouring
+// segments' writers).
+struct ByteOut {
+  uint8_t* base;
+  uint64_t pos = 0;
+  uint32_t word = 0;
+  __device__ __forceinline__ void store(uint64_t wa) {
+    const uint64_t lo = (uint64_t)(uintptr_t)base;
+    if (wa >= lo) {
+      *(uint32_t*)(uintptr_t)wa = word;
+    } else {
+      for (uint64_t q = lo; q < wa + 4; q++) *(uint8_t*)(uintptr_t)q = (uint8_t)(word >> (8 * (q - wa)));
+    }
+    word = 0;
+  }
+  __device__ __forceinline__ void put(uint32_t x) {
+    const uint64_t ad = (uint64_t)(uintptr_t)base + pos;
+    word |= x << (8 * (ad & 3u));
+    pos++;
+    if (((ad + 1) & 3u) == 0) store(ad & ~3ull);
+  }
+  __device__ __forceinline__ void fill(uint32_t x, uint32_t k) {  // k copies of x
+    while (k && (((uint64_t)(uintptr_t)base + pos) & 3u)) {
+      put(x);
+      k--;
+    }
+    const uint32_t w4 = x * 0x01010101u;
+    for (; k >= 4; k -= 4) {
+      *(uint32_t*)(base + pos) = w4;
+      pos += 4;
+    }
+    for (; k; k--) put(x);
+  }
+  __device__ __forceinline__ void finish() {
+    const uint64_t ad = (uint64_t)(uintptr_t)base + pos;
+    if (!(ad & 3u)) return;
+    const uint64_t wa = ad & ~3ull, lo = (uint64_t)(uintptr_t)base;
+    for (uint64_t q = wa > lo ? wa : lo; q < ad; q++) *(uint8_t*)(uintptr_t)q = (uint8_t)(word >> (8 * (q - wa)));
+  }
+};
+
 // Per segment of RLE_SEG text bytes, for each incoming state s (with `last`
 // = the segment's first byte for s = 1..3): output bytes, outgoing state and
 // last byte, packed as len | st << 32 | last << 40.
@@ -1266,15 +1324,14 @@ __device__ __forceinline__ void rle_summ_item(uint64_t j, const DecBlk* __restri
   if ((uint64_t)g * RLE_SEG >= n) return;
   const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
   const uint32_t m = min(RLE_SEG, n - g * RLE_SEG);
-  uint8_t x[RLE_SEG];
-#pragma unroll
-  for (uint32_t i = 0; i < RLE_SEG; i++) x[i] = Tb[min(i, m - 1)];
+  uint32_t xw[RLE_SEG / 4];
+  seg_words(Tb, xw);
 #pragma unroll
   for (uint32_t s = 0; s < 5; s++) {
-    uint32_t st = s, last = x[0], len = 0;
+    uint32_t st = s, last = xw[0] & 255u, len = 0;
 #pragma unroll
     for (uint32_t i = 0; i < RLE_SEG; i++)
-      if (i < m) len += rle_step(st, last, x[i]);
+      if (i < m) len += rle_step(st, last, (xw[i / 4] >> (8 * (i % 4))) & 255u);
     summ[j * 5 + s] = (uint64_t)len | ((uint64_t)st << 32) | ((uint64_t)last << 40);
   }
 }
@@ -1440,19 +1497,19 @@ __device__ __forceinline__ void rle_emit_item(uint64_t j, const DecBlk* __restri
   if ((uint64_t)g * RLE_SEG >= n) return;
   const uint8_t* Tb = T + blks[b].l_off + (uint64_t)g * RLE_SEG;
   const uint32_t m = min(RLE_SEG, n - g * RLE_SEG);
-  uint8_t* o = out + out_off[b] + seg_off[j];
+  uint32_t xw[RLE_SEG / 4];
+  seg_words(Tb, xw);
+  ByteOut o{out + out_off[b] + seg_off[j]};
   uint32_t st = seg_in[j] & 255u, last = seg_in[j] >> 8;
-  uint32_t w = 0;
-  for (uint32_t i = 0; i < m; i++) {
-    const uint32_t x = Tb[i];
-    if (st == 4) {
-      for (uint32_t k = 0; k < x; k++) o[w + k] = (uint8_t)last;
-      w += x;
-    } else {
-      o[w++] = (uint8_t)x;
-    }
+#pragma unroll
+  for (uint32_t i = 0; i < RLE_SEG; i++) {
+    if (i >= m) break;
+    const uint32_t x = (xw[i / 4] >> (8 * (i % 4))) & 255u;
+    if (st == 4) o.fill(last, x);
+    else o.put(x);
     (void)rle_step(st, last, x);
   }
+  o.finish();
 }
 
 // Segments as in k_rle_summ (nothing when the output did not fit).
