@@ -382,11 +382,12 @@ __device__ void append_groups(const AppendCtx& a, const uint32_t* gs, const uint
   const uint32_t e_seg = (uint32_t)ex & M13, e_small = (uint32_t)(ex >> 13) & M13, e_tiles = (uint32_t)(ex >> 26) & M13;
   const uint32_t area = a.blk_off[blk], rows = a.blk_off[blk + 1] - area;
   if (threadIdx.x == 0) {
-    // neither half of a word carries into the other: large segments, packed
-    // elements, tiles and large-segment elements of a round stay below 2^32
-    const unsigned long long ss =
-        t_seg | t_small ? atomicAdd(&a.cnt->segs_small, (unsigned long long)t_seg | ((unsigned long long)t_small << 32))
-                        : 0ull;
+    // neither half of a word carries into the other: tiles and large-segment
+    // elements of a round stay below 2^32.  The round's packed-element total
+    // is summed from the blocks' counts (k_small_tiles), so the word every
+    // workgroup would add to is touched only by those that append a large
+    // segment.
+    const unsigned long long ss = t_seg ? atomicAdd(&a.cnt->segs_small, (unsigned long long)t_seg) : 0ull;
     const unsigned long long tb =
         t_tiles ? atomicAdd(&a.cnt->tiles_big, (unsigned long long)t_tiles | ((unsigned long long)t_big << 32)) : 0ull;
     wg_base[0] = (uint32_t)ss;
@@ -787,23 +788,32 @@ __device__ __forceinline__ RoundSizes round_sizes(const RoundCounters* c, const 
 }
 
 // Tiles of each block's packed small segments and their exclusive prefix
-// over the blocks (tile_pre, nslot + 1 entries).  One workgroup.
+// over the blocks (tile_pre, nslot + 1 entries), and the packed elements of
+// all blocks (*small_rows).  One workgroup; each thread takes a run of
+// consecutive blocks.
 constexpr int TS_NT = 1024;
 __global__ __launch_bounds__(TS_NT) void k_small_tiles(const uint32_t* __restrict__ bcnt,
                                                       const uint32_t* __restrict__ blk_off, uint32_t nslot,
-                                                      uint32_t* __restrict__ tile_pre) {
-  __shared__ uint32_t sh[TS_NT / BZG_WAVE + 1];
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < nslot; base += TS_NT) {
-    const uint32_t b = base + threadIdx.x;
-    const uint32_t c = b < nslot ? min(bcnt[b], blk_off[b + 1] - blk_off[b]) : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_sum<uint32_t, TS_NT>((c + SMALL_T - 1) / SMALL_T, sh, &tot);
-    if (b < nslot) tile_pre[b] = carry + ex;
-    carry += tot;
-    __syncthreads();
+                                                      uint32_t* __restrict__ tile_pre,
+                                                      uint32_t* __restrict__ small_rows) {
+  __shared__ uint64_t sh[TS_NT / BZG_WAVE + 1];
+  const uint32_t per = (nslot + TS_NT - 1) / TS_NT;
+  const uint32_t lo = min(threadIdx.x * per, nslot), hi = min(lo + per, nslot);
+  uint64_t acc = 0;  // tiles | elements << 32
+  for (uint32_t b = lo; b < hi; b++) {
+    const uint32_t c = min(bcnt[b], blk_off[b + 1] - blk_off[b]);
+    acc += (uint64_t)((c + SMALL_T - 1) / SMALL_T) | ((uint64_t)c << 32);
   }
-  if (threadIdx.x == 0) tile_pre[nslot] = carry;
+  uint64_t tot;
+  uint32_t run = (uint32_t)block_excl_sum<uint64_t, TS_NT>(acc, sh, &tot);
+  for (uint32_t b = lo; b < hi; b++) {
+    tile_pre[b] = run;
+    run += (min(bcnt[b], blk_off[b + 1] - blk_off[b]) + SMALL_T - 1) / SMALL_T;
+  }
+  if (threadIdx.x == 0) {
+    tile_pre[nslot] = (uint32_t)tot;
+    *small_rows = (uint32_t)(tot >> 32);
+  }
 }
 
 __device__ void gather_tile(uint32_t jt, uint32_t n_small_tiles, const uint32_t* __restrict__ tile_pre,
@@ -1453,7 +1463,8 @@ hipError_t bwt_sort(BwtWork& w, const uint8_t* text, const uint32_t* d_off, cons
     const uint32_t* big_rows = (const uint32_t*)&w.cnt[cc].tiles_big + 1;      // high word
     {
       ProfScope ps("sort_scan", st, 0.0);
-      hipLaunchKernelGGL(k_small_tiles, dim3(1), dim3(TS_NT), 0, st, w.bcnt[cur], d_off, nslot, w.tile_pre);
+      hipLaunchKernelGGL(k_small_tiles, dim3(1), dim3(TS_NT), 0, st, w.bcnt[cur], d_off, nslot, w.tile_pre,
+                         (uint32_t*)small_rows);
     }
     {
       // row, partner rank, key2

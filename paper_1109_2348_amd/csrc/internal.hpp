@@ -136,6 +136,7 @@ struct SegRec {
 // on different cache lines.
 struct RoundCounters {
   unsigned long long segs_small;  // large segments for the next round | packed elements of small segments << 32
+                                  // (the high word: the round's total, written by the round's first kernel)
   uint32_t pad0[30];
   unsigned long long tiles_big;   // radix tiles of large segments | elements in large segments << 32
   uint32_t pad1[30];

@@ -113,25 +113,49 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_scan_down_dev(T* data, const uint32_t* __restrict__ count_ptr, uint32_t cap,
                                                       uint32_t mult, const T* __restrict__ sums) {
   __shared__ T sh[NT / BZG_WAVE + 1];
+  constexpr int PV = 16 / sizeof(T);  // elements per 16-byte vector
+  static_assert(SCAN_ITEMS % PV == 0, "whole vectors per thread");
   const uint64_t n = (uint64_t)min(*count_ptr, cap) * mult;
   const uint32_t ntiles = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
+  const bool aligned = ((uintptr_t)data & 15u) == 0;
   for (TileLoop it = tile_loop(ntiles); it.t < it.end; it.t += it.step) {
     const uint64_t base = (uint64_t)it.t * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    // a thread's run of SCAN_ITEMS elements moves as whole 16-byte vectors
+    // where it lies inside the count (every thread but the last one's)
+    const bool whole = aligned && base + SCAN_ITEMS <= n;
     T v[SCAN_ITEMS];
+    if (whole) {
+#pragma unroll
+      for (int j = 0; j < SCAN_ITEMS / PV; j++) {
+        const uint4 q = *reinterpret_cast<const uint4*>(data + base + j * PV);
+        __builtin_memcpy(&v[j * PV], &q, 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SCAN_ITEMS; i++) v[i] = base + i < n ? data[base + i] : T(0);
+    }
     T acc = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) v[i] = data[min(base + i, n - 1)];
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-      v[i] = base + i < n ? v[i] : T(0);
-      acc += v[i];
-    }
+    for (int i = 0; i < SCAN_ITEMS; i++) acc += v[i];
     T tot;
     T run = block_excl_sum<T, NT>(acc, sh, &tot) + sums[it.t];
+    T o[SCAN_ITEMS];
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-      if (base + i < n) data[base + i] = run;
+      o[i] = run;
       run += v[i];
+    }
+    if (whole) {
+#pragma unroll
+      for (int j = 0; j < SCAN_ITEMS / PV; j++) {
+        uint4 q;
+        __builtin_memcpy(&q, &o[j * PV], 16);
+        *reinterpret_cast<uint4*>(data + base + j * PV) = q;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SCAN_ITEMS; i++)
+        if (base + i < n) data[base + i] = o[i];
     }
     __syncthreads();
   }
