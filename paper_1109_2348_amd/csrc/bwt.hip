@@ -242,8 +242,10 @@ __device__ void radix_scatter_tile(uint32_t jt, const SegRec* __restrict__ segs,
 #pragma unroll
     for (int i = 0; i < RI; i++) {
       const uint32_t k = min(wbase + i * BZG_WAVE + lane(), g.hi - 1u);
-      key[i] = kin[k];
-      val[i] = vin[k];
+      // streamed once: non-temporal, so the L2 keeps the output runs that
+      // neighbouring tiles complete
+      key[i] = __builtin_nontemporal_load(&kin[k]);
+      val[i] = __builtin_nontemporal_load(&vin[k]);
     }
   }
 #pragma unroll
