@@ -503,26 +503,25 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
   const bool keep_blk = h_next < nblk;
   const uint32_t segend = g.r.start + g.r.len;
   // the tile's keys (with the neighbours on both sides, where they are in
-  // the segment) and rows, loaded coalesced into LDS and read blocked
-  __shared__ uint32_t tk[RADIX_TILE + 2], tv[RADIX_TILE];
+  // the segment), loaded coalesced into LDS and read blocked; the rows stay
+  // in registers, strided, as the stores at the end take them
+  __shared__ uint32_t tk[RADIX_TILE + 2];
   const uint32_t tn = g.hi - g.lo;
+  uint32_t rows[RI];  // row g.lo + q * NT + threadIdx.x
   {
-    uint32_t a[RI], b[RI];  // loads first (clamped rows, unbranched), then LDS
+    uint32_t a[RI];  // loads first (clamped rows, unbranched), then LDS
 #pragma unroll
     for (int q = 0; q < RI; q++) {
       const uint32_t i = min(q * NT + threadIdx.x, tn - 1u);
       // streamed once: non-temporal, so the L2 keeps the rank lines that
       // this kernel's scattered writes land in
       a[q] = __builtin_nontemporal_load(&kin[g.lo + i]);
-      b[q] = __builtin_nontemporal_load(&vin[g.lo + i]);
+      rows[q] = __builtin_nontemporal_load(&vin[g.lo + i]);
     }
 #pragma unroll
     for (int q = 0; q < RI; q++) {
       const uint32_t i = q * NT + threadIdx.x;
-      if (i < tn) {
-        tk[i + 1] = a[q];
-        tv[i] = b[q];
-      }
+      if (i < tn) tk[i + 1] = a[q];
     }
   }
   if (threadIdx.x == 0) {
@@ -533,13 +532,11 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
   const uint32_t k0 = g.lo + threadIdx.x * RI;  // blocked: RI consecutive rows per thread
   const uint32_t i0 = threadIdx.x * RI;         // its first position in tk (minus the halo)
   // the thread's keys with one neighbour on each side (t[i + 1] is row
-  // k0 + i's key) and its rows, read from LDS all together; tk holds the
-  // tile's keys at 1.. with the keys before and after the tile around them
-  uint32_t t[RI + 2], vv[RI];
+  // k0 + i's key), read from LDS all together; tk holds the tile's keys at
+  // 1.. with the keys before and after the tile around them
+  uint32_t t[RI + 2];
 #pragma unroll
   for (int i = 0; i < RI + 2; i++) t[i] = tk[i0 + i];
-#pragma unroll
-  for (int i = 0; i < RI; i++) vv[i] = tv[i0 + i];
   uint32_t lastb = 0;
 #pragma unroll
   for (int i = 0; i < RI; i++) {
@@ -590,7 +587,7 @@ __device__ void rename_b_tile(uint32_t jt, const SegRec* __restrict__ segs, cons
   for (int q = 0; q < RI; q++) {
     const uint32_t i = q * NT + threadIdx.x;
     if (i < tn) {
-      const uint32_t v = tv[i], r = tk[i];
+      const uint32_t v = rows[q], r = tk[i];
       if (vin != SA) SA[g.lo + i] = v;
       if (r != 0xFFFFFFFFu) rank[v] = r;
     }
